@@ -1,0 +1,179 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module holds none of the method's arithmetic: it only places bodies
+(random orientations, random sequential addition of bounding spheres, affine
+rescaling of a periodic box) so that the GPU library and the CPU oracle can
+be fed the same states.  Both sides import it; it imports neither.
+
+Workload shapes (Sec. 5 of Palmer, Aktulga, Gao, arXiv 2506.14097):
+  * two ellipsoids meeting head-on (inertial);
+  * periodic packings of ellipsoids with semiaxes uniform in [0.5, 1.0] at a
+    prescribed volume fraction (compacting suspension, Sec. 5.2);
+  * monolayers of spherocylinders of diameter 1 (colony, Sec. 5.3).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+ELLIPSOID = 0
+SPHEROCYLINDER = 1
+
+
+def rng_for(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def shoemake_quaternions(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Uniform random unit quaternions, scalar first (Shoemake 1992)."""
+    u1, u2, u3 = rng.random(n), rng.random(n), rng.random(n)
+    a, b = np.sqrt(1.0 - u1), np.sqrt(u1)
+    q = np.stack([b * np.cos(2 * np.pi * u3), a * np.sin(2 * np.pi * u2), a * np.cos(2 * np.pi * u2),
+                  b * np.sin(2 * np.pi * u3)], axis=1)
+    return q / np.linalg.norm(q, axis=1, keepdims=True)
+
+
+def planar_quaternions(theta: np.ndarray) -> np.ndarray:
+    """Rotations about z by theta (body x axis -> (cos, sin, 0))."""
+    return np.stack([np.cos(theta / 2), np.zeros_like(theta), np.zeros_like(theta), np.sin(theta / 2)], axis=1)
+
+
+def ellipsoid_volume(shape: np.ndarray) -> np.ndarray:
+    return 4.0 / 3.0 * np.pi * shape[:, 0] * shape[:, 1] * shape[:, 2]
+
+
+def bounding_radius(kind: np.ndarray, shape: np.ndarray) -> np.ndarray:
+    return np.where(kind == ELLIPSOID, shape.max(axis=1), 0.5 * shape[:, 1] + shape[:, 0])
+
+
+def two_ellipsoids(seed: int = 0, separation: float = 3.0, closing_speed: float = 1.0, spin_sd: float = 0.05,
+                   semiaxes=(1.0, 0.5, 0.5), density: float = 1.0):
+    """Two ellipsoids approaching head-on along x with random orientations
+    and small random spins (inertial two-body collision)."""
+    rng = rng_for(seed)
+    q = shoemake_quaternions(rng, 2)
+    x = np.array([[-separation / 2, 0.0, 0.0], [separation / 2, 0.0, 0.0]])
+    u = np.zeros((2, 6))
+    u[0, 0], u[1, 0] = 0.5 * closing_speed, -0.5 * closing_speed
+    u[:, 3:] = rng.normal(0.0, spin_sd, size=(2, 3))
+    shape = np.array([semiaxes, semiaxes], dtype=np.float64)
+    return dict(x=x, q=q, u=u, kind=np.zeros(2, np.int32), shape=shape, rho_xi=np.full(2, density),
+                box=np.zeros(3))
+
+
+def rsa_spheres(rng: np.random.Generator, radii: np.ndarray, box: np.ndarray, max_attempts: int = 2000,
+                planar: bool = False) -> np.ndarray:
+    """Random sequential addition of non-overlapping spheres (largest first)
+    in a periodic box (z fixed at 0 when planar).  Raises if a sphere cannot
+    be placed within max_attempts."""
+    n = radii.size
+    order = np.argsort(-radii, kind="stable")
+    rmax = float(radii.max())
+    cell = 2.0 * rmax
+    dims = 2 if planar else 3
+    nc = np.maximum(1, np.floor(box[:dims] / cell).astype(int))
+    csize = box[:dims] / nc
+    grid: dict = {}
+    pos = np.zeros((n, 3))
+    placed_r = np.zeros(n)
+    for i in order:
+        r = radii[i]
+        for _ in range(max_attempts):
+            p = np.zeros(3)
+            p[:dims] = rng.random(dims) * box[:dims]
+            c = np.floor(p[:dims] / csize).astype(int) % nc
+            ok = True
+            rng3 = range(-1, 2)
+            offs = [(a, b, 0) for a in rng3 for b in rng3] if planar else \
+                [(a, b, e) for a in rng3 for b in rng3 for e in rng3]
+            seen = set()
+            for o in offs:
+                key = tuple((c + np.array(o[:dims])) % nc)
+                if key in seen:
+                    continue
+                seen.add(key)
+                for j in grid.get(key, ()):
+                    d = pos[j, :dims] - p[:dims]
+                    d -= box[:dims] * np.round(d / box[:dims])
+                    if d @ d < (r + placed_r[j]) ** 2:
+                        ok = False
+                        break
+                if not ok:
+                    break
+            if ok:
+                pos[i] = p
+                placed_r[i] = r
+                grid.setdefault(tuple(c), []).append(i)
+                break
+        else:
+            raise RuntimeError("random sequential addition jammed; lower the density")
+    return pos
+
+
+def ellipsoid_packing(seed: int, n: int, phi: float | None = None, sphere_phi: float = 0.25,
+                      semiaxis_lo: float = 0.5, semiaxis_hi: float = 1.0, xi: float = 1.0, compress: float = 1.0):
+    """Periodic packing of n ellipsoids (semiaxes i.i.d. uniform) at volume
+    fraction phi.  Bounding spheres are placed by random sequential addition
+    at sphere volume fraction `sphere_phi`; the box and positions are then
+    rescaled affinely to reach phi.  When phi is above the fraction of that
+    sphere packing, the rescale creates overlaps (as an isotropic
+    compression step does), which the time-step resolves.  With phi=None
+    the rescale factor is `compress` instead."""
+    rng = rng_for(seed)
+    shape = rng.uniform(semiaxis_lo, semiaxis_hi, size=(n, 3))
+    q = shoemake_quaternions(rng, n)
+    R = shape.max(axis=1)
+    vs = float(np.sum(4.0 / 3.0 * np.pi * R ** 3))
+    L0 = (vs / sphere_phi) ** (1.0 / 3.0)
+    box0 = np.full(3, L0)
+    x = rsa_spheres(rng, R, box0)
+    ve = float(np.sum(ellipsoid_volume(shape)))
+    L = (ve / phi) ** (1.0 / 3.0) if phi is not None else L0 * compress
+    s = L / L0
+    return dict(x=x * s, q=q, kind=np.zeros(n, np.int32), shape=shape, rho_xi=np.full(n, xi), box=np.full(3, L),
+                scale=s, phi=ve / L ** 3)
+
+
+def spherocylinder_monolayer(seed: int, n: int, area_fraction: float | None = None, length_lo: float = 1.0,
+                             length_hi: float = 2.0, radius: float = 0.5, disk_fraction: float = 0.3,
+                             xi: float = 1.0, compress: float = 1.0):
+    """Planar periodic layer of spherocylinders (radius 0.5, cylinder length
+    uniform in [length_lo, length_hi], random in-plane orientations): bounding
+    disks by random sequential addition at area fraction `disk_fraction`,
+    then an affine rescale of the box to the requested capsule area
+    fraction (overlaps appear when it exceeds the disk packing's), or by the
+    factor `compress` when area_fraction is None."""
+    rng = rng_for(seed)
+    ell = rng.uniform(length_lo, length_hi, size=n)
+    shape = np.stack([np.full(n, radius), ell, np.zeros(n)], axis=1)
+    theta = rng.uniform(0.0, 2 * np.pi, size=n)
+    q = planar_quaternions(theta)
+    R = 0.5 * ell + radius
+    a_disk = float(np.sum(np.pi * R ** 2))
+    L0 = math.sqrt(a_disk / disk_fraction)
+    box0 = np.array([L0, L0, 0.0])
+    x = rsa_spheres(rng, R, box0, planar=True)
+    a_caps = float(np.sum(np.pi * radius ** 2 + 2 * radius * ell))
+    L = math.sqrt(a_caps / area_fraction) if area_fraction is not None else L0 * compress
+    s = L / L0
+    return dict(x=x * s, q=q, kind=np.full(n, SPHEROCYLINDER, np.int32), shape=shape, rho_xi=np.full(n, xi),
+                box=np.array([L, L, 0.0]), scale=s, area_fraction=a_caps / L ** 2)
+
+
+def batch_of_packings(seed: int, count: int, n_lo: int, n_hi: int, phi_lo: float, phi_hi: float,
+                      sphere_phi: float = 0.25):
+    """`count` independent periodic ellipsoid packings with body counts
+    log-uniform in [n_lo, n_hi] and volume fractions uniform in
+    [phi_lo, phi_hi], concatenated with batch offsets."""
+    rng = rng_for(seed)
+    ns = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), size=count)).astype(int)
+    phis = rng.uniform(phi_lo, phi_hi, size=count)
+    parts = [ellipsoid_packing(int(rng.integers(1 << 30)), int(k), float(p), sphere_phi=sphere_phi)
+             for k, p in zip(ns, phis)]
+    off = np.zeros(count + 1, np.int32)
+    off[1:] = np.cumsum(ns)
+    return dict(x=np.concatenate([p["x"] for p in parts]), q=np.concatenate([p["q"] for p in parts]),
+                kind=np.concatenate([p["kind"] for p in parts]), shape=np.concatenate([p["shape"] for p in parts]),
+                rho_xi=np.concatenate([p["rho_xi"] for p in parts]), box=np.stack([p["box"] for p in parts]),
+                batch_off=off, phi=phis)
