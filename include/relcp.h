@@ -1,0 +1,193 @@
+/*
+ * relcp.h -- C ABI of the MI355X ReLCP time-step library (librelcp.so).
+ *
+ * One ReLCP time-step for frictionless contact between smooth rigid bodies
+ * (ellipsoids, spherocylinders), after Palmer, Aktulga, Gao, "Smooth-Rigid-
+ * Body Contact as a ReLCP" (arXiv 2506.14097): Alg. 1 (overdamped) and Eq.
+ * relcp_inertial (inertial).  Each call states the passage it implements.
+ *
+ * Conventions
+ *  - Every call returns an int status: RELCP_OK (0) or a negative RELCP_E_*.
+ *    Nothing is thrown across the ABI; relcp_last_error() gives a message.
+ *  - The library owns the context and all of its device buffers.  Inputs
+ *    are copied at create / set time; the caller may free them afterwards.
+ *  - Host arrays are array-of-structs per body in double precision: x[3i+k],
+ *    q[4i+k] with the scalar part first (q = [s, w]), velocities u[3i+k]
+ *    (translation) and w[3i+k] (world-frame angular velocity).  Functions
+ *    with the _device suffix take device pointers of the same layout and work
+ *    on the context's stream.
+ *  - One context per stream; calls on one context are not thread-safe.
+ *  - Units are the caller's; all lengths, times and forces consistent.
+ *  - Errors leave the state untouched: a step commits only on acceptance.
+ */
+#ifndef RELCP_H
+#define RELCP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#ifndef RELCP_API
+#define RELCP_API __attribute__((visibility("default")))
+#endif
+
+typedef struct relcp_ctx relcp_ctx;
+
+enum {
+    RELCP_OK = 0,
+    RELCP_E_INVALID = -1,       /* bad argument: NaN, non-unit quaternion, bad shape, box too small */
+    RELCP_E_OOM = -2,           /* device allocation failed */
+    RELCP_E_DEVICE = -3,        /* HIP runtime error */
+    RELCP_E_LCP_MAXITER = -4,   /* projected gradient did not reach lcp_tol within lcp_max_iters */
+    RELCP_E_RECURSION_CAP = -5, /* more than max_recursions augmentations (Alg. 1 while-loop) */
+    RELCP_E_SKIN = -6,          /* a trial moved a surface point by more than skin/2 */
+    RELCP_E_NAN = -7,           /* non-finite value produced during the step */
+    RELCP_E_CAPACITY = -8       /* contact or pair buffer would exceed the configured maximum */
+};
+
+enum { RELCP_ELLIPSOID = 0, RELCP_SPHEROCYLINDER = 1 };
+enum { RELCP_OVERDAMPED = 0, RELCP_INERTIAL = 1 };
+enum { RELCP_WS_COLD = 0, RELCP_WS_PREV = 1, RELCP_WS_LEARNED = 2 };
+
+/* Bodies (generalized configuration C, Sec. 2.1.1): n bodies in n_batch
+ * independent systems ("packings").  Bodies of packing p are
+ * [batch_off[p], batch_off[p+1]).  box[3p+k] is the periodic box edge of
+ * packing p along k, 0 for an open direction.  u, w may be NULL (at rest).
+ * batch_off may be NULL when n_batch == 1. */
+typedef struct {
+    int32_t n;
+    const double *x, *q, *u, *w;
+    int32_t n_batch;
+    const int32_t *batch_off;
+    const double *box;
+} relcp_bodies;
+
+/* Shapes: kind[i] = RELCP_ELLIPSOID with p[3i..] = semiaxes (a, b, c) along
+ * the body x, y, z axes; or RELCP_SPHEROCYLINDER with p[3i..] = (r, l, 0):
+ * cap radius r and cylinder length l, axis along body x (Sec. 5.3).
+ * rho_or_xi[i] = density (inertial) or drag coefficient xi (overdamped, Eq.
+ * ellipsoid_mobility).  One packing holds one kind only. */
+typedef struct {
+    const int32_t *kind;
+    const double *p;
+    const double *rho_or_xi;
+} relcp_shapes;
+
+/* Parameters.  precision: 64 = FP64 LCP iterations; 32 = FP32 products and
+ * projection with an FP64 residual, FP64 polish and FP64 acceptance.
+ * max_recursions: cap on Alg. 1 augmentations (0 = the plain single-
+ * constraint SNSD LCP, first trial always accepted).  lcp_max_iters: cap on
+ * projected-gradient iterations per LCP (0 = 100000).  skin: near-contact
+ * distance delta_c; pairs whose bounding spheres are within skin are
+ * candidates and pairs with Phi_0 <= skin start in A_0.  stream: a
+ * hipStream_t, NULL = the library creates its own. */
+typedef struct {
+    int32_t dynamics, precision, warm_start, planar;
+    int32_t max_recursions, lcp_max_iters, lcp_fixed_iters;
+    double skin;
+    void *stream;
+} relcp_params;
+
+#define RELCP_MAX_RECORDED 65
+
+/* Statistics of one step.  For batched contexts the counts are totals over
+ * packings and recursions/iterations are maxima over packings. */
+typedef struct {
+    int32_t recursions;          /* augmentations before acceptance */
+    int32_t lcp_iters_total;     /* projected-gradient iterations over all recursions */
+    int32_t n_pairs;             /* candidate pairs */
+    int32_t n_contacts_final;    /* rows at acceptance */
+    int32_t n_contacts[RELCP_MAX_RECORDED];
+    int32_t lcp_iters[RELCP_MAX_RECORDED];   /* iterations per recursion (all precisions) */
+    int32_t lcp_iters64[RELCP_MAX_RECORDED]; /* of which FP64 (the FP32 path's polish) */
+    double W[RELCP_MAX_RECORDED];        /* gamma_n^T A_n gamma_n (work, non-decreasing) */
+    double margin[RELCP_MAX_RECORDED];   /* min |Phi(C_{n+1}) + overlap_tol| over pairs */
+    double residual_fp64;        /* scaled natural residual max|min(A_aa g_a, w_a)| of the accepted LCP */
+    double residual_lowp;        /* the same in the iteration precision before the FP64 polish */
+    double max_overlap;          /* max over pairs of -Phi at the accepted configuration (>= 0) */
+    double max_disp;             /* largest surface-point displacement bound of the accepted trial */
+    double t_narrow, t_lcp, t_other; /* milliseconds (host clock, stream-synchronised) */
+} relcp_step_stats;
+
+/* Create a context (Sec. 2.1.1 state, Sec. 2.1.2 laws of motion).  Validates
+ * the inputs (RELCP_E_INVALID), allocates device buffers (RELCP_E_OOM) and
+ * uploads the state once.  *out is set on success only. */
+RELCP_API int relcp_create(const relcp_bodies *bodies, const relcp_shapes *shapes, const relcp_params *params,
+                 relcp_ctx **out);
+RELCP_API void relcp_destroy(relcp_ctx *ctx);
+RELCP_API const char *relcp_last_error(const relcp_ctx *ctx);
+
+/* External wrench F_ext (6n host doubles: force then torque per body, world
+ * frame), or NULL for none (Alg. 1 input F_ext). */
+RELCP_API int relcp_set_external(relcp_ctx *ctx, const double *f);
+
+/* One time-step: Alg. 1 (overdamped) or Eq. relcp_inertial (inertial) with
+ * overlap tolerance eps_NCP = overlap_tol (Eq. gap_stopping_rule) and LCP
+ * tolerance lcp_tol on the scaled natural residual.  stats may be NULL. */
+RELCP_API int relcp_step(relcp_ctx *ctx, double dt, double overlap_tol, double lcp_tol, relcp_step_stats *stats);
+
+/* State read-back into caller buffers (x 3n, q 4n, u 3n, w 3n; any may be
+ * NULL).  u, w are the last accepted velocity V_n = U_free + K D gamma. */
+RELCP_API int relcp_get_state(const relcp_ctx *ctx, double *x, double *q, double *u, double *w);
+RELCP_API int relcp_get_state_device(const relcp_ctx *ctx, double *x, double *q, double *u, double *w);
+
+/* Replace the state (same n, n_batch and shapes as at create, or new body
+ * counts: the context is then re-sized).  Clears the warm-start history. */
+RELCP_API int relcp_set_state(relcp_ctx *ctx, const relcp_bodies *bodies, const relcp_shapes *shapes);
+
+/* Isotropic affine compression x <- s x, box <- s box (all packings). */
+RELCP_API int relcp_affine_rescale(relcp_ctx *ctx, double s);
+
+/* Rows of the last accepted step (caller buffers of n_contacts_final
+ * entries; any may be NULL): body pair, recursion at which the row was
+ * generated, multiplier gamma, true Phi where generated, normal (3 each). */
+RELCP_API int relcp_get_contacts(const relcp_ctx *ctx, int32_t *ia, int32_t *ib, int32_t *recursion_added, double *gamma,
+                       double *phi_at_discovery, double *normal);
+
+/* Kernel timing with HIP events recorded on the context's stream around
+ * each launch of the step (off by default; costs one event pair per
+ * launch).  Classes: 0 = LCP scatter pass (D gamma -> K), 1 = LCP gather
+ * pass (D^T V, projection, step-size reductions), 2 = SNSD narrowphase,
+ * 3 = candidate pairs, 4 = trial integration.  relcp_get_timing fills
+ * count[5] (launches) and ms[5] (summed durations) since the last reset,
+ * and resets when reset != 0. */
+RELCP_API int relcp_set_timing(relcp_ctx *ctx, int32_t enable);
+RELCP_API int relcp_get_timing(relcp_ctx *ctx, int32_t *count, double *ms, int32_t reset);
+
+/* ---- stand-alone operations on device arrays (parity tests, tools) ---- */
+
+/* Shared-normal signed distance (Sec. 2.1.4; Lemma uniform interior tangent
+ * ball) of m pairs, FP64.  Device SoA inputs for the bodies: x (3 arrays of
+ * nb), q (4 arrays of nb), kind, p (3 arrays of nb); pairs pa, pb (m);
+ * box[3] host.  Output out (10 arrays of m): Phi, n (3), r_a = p_a - x_a (3),
+ * r_b = p_b - x_b (3).  Runs on `stream` (hipStream_t, NULL = default) and
+ * synchronises before returning. */
+RELCP_API int relcp_snsd_device(int32_t nb, const double *x, const double *q, const int32_t *kind, const double *p, int32_t m,
+                      const int32_t *pa, const int32_t *pb, const double *box, int32_t planar, double *out,
+                      void *stream);
+
+/* Candidate pairs of one packing: all a < b with bounding-sphere gap <= skin
+ * (the near-contacting pairs of Alg. 1), sorted by (a, b).  Device SoA x
+ * (3 arrays of nb), kind, p (3 arrays).  Writes up to cap pairs to pa, pb
+ * (device) and the total count to *m (host). */
+RELCP_API int relcp_broadphase_device(int32_t nb, const double *x, const int32_t *kind, const double *p, const double *box,
+                            double skin, int32_t cap, int32_t *pa, int32_t *pb, int32_t *m, void *stream);
+
+/* The LCP of one recursion (Eq. relcp; Eq. cqpp), 0 <= g = qv + dt D^T K D
+ * gamma _|_ gamma >= 0, solved by the library's Jacobi-scaled BB projected
+ * gradient (precision 64 or 32) from the warm start in gamma.  Device arrays:
+ * rows ia, ib (m), n, ta = r_a x n, tb = r_b x n (3 arrays of m each), qv (m),
+ * body operator kt (nb), Kr (6 arrays of nb: xx, yy, zz, xy, xz, yz), gamma
+ * (m, in/out).  *iters and *residual (FP64 residual) are host outputs. */
+RELCP_API int relcp_lcp_solve_device(int32_t nb, int32_t m, const int32_t *ia, const int32_t *ib, const double *n,
+                           const double *ta, const double *tb, const double *qv, const double *kt, const double *Kr,
+                           double dt, int32_t planar, int32_t precision, double tol, int32_t max_iters,
+                           double *gamma, int32_t *iters, double *residual, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RELCP_H */

@@ -1,0 +1,143 @@
+// common.h -- internal declarations of librelcp (gfx950).
+//
+// Layout: every per-body and per-contact quantity is structure-of-arrays
+// (component k of item i at ptr[k * ld + i]) so that a wavefront of 64 lanes
+// reads 64 consecutive values of one component.  Symmetric 3x3 matrices are
+// stored as 6 components (xx, yy, zz, xy, xz, yz).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#define RELCP_WAVE 64
+
+namespace relcp {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+struct Error {
+    int code;
+    std::string msg;
+};
+
+#define HIP_OK(expr)                                                                                  \
+    do {                                                                                              \
+        hipError_t _e = (expr);                                                                       \
+        if (_e != hipSuccess)                                                                         \
+            throw ::relcp::Error{-3, std::string(#expr) + ": " + hipGetErrorString(_e)};              \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+template <typename T>
+struct DBuf {
+    T *p = nullptr;
+    size_t cap = 0;  // elements
+    void ensure(size_t n) {
+        if (n <= cap) return;
+        size_t nc = cap ? cap : 256;
+        while (nc < n) nc *= 2;
+        if (p) HIP_OK(hipFree(p));
+        p = nullptr;
+        cap = 0;
+        if (hipMalloc(&p, nc * sizeof(T)) != hipSuccess) {
+            p = nullptr;
+            throw Error{-2, "device allocation failed"};
+        }
+        cap = nc;
+    }
+    // grow keeping the first `keep` elements of each of `comps` components
+    // laid out with leading dimension cap
+    void grow_soa(size_t n, int comps, size_t keep, hipStream_t s) {
+        if (n * comps <= cap) return;
+        size_t oldld = cap / (comps ? comps : 1);
+        size_t nld = oldld ? oldld : 256;
+        while (nld < n) nld *= 2;
+        T *np_ = nullptr;
+        if (hipMalloc(&np_, nld * comps * sizeof(T)) != hipSuccess) throw Error{-2, "device allocation failed"};
+        if (p && keep) {
+            for (int k = 0; k < comps; ++k)
+                HIP_OK(hipMemcpyAsync(np_ + k * nld, p + k * oldld, keep * sizeof(T), hipMemcpyDeviceToDevice, s));
+        }
+        HIP_OK(hipStreamSynchronize(s));
+        if (p) HIP_OK(hipFree(p));
+        p = np_;
+        cap = nld * comps;
+    }
+    size_t ld(int comps) const { return cap / comps; }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// small device vector helpers (FP64 geometry)
+// ---------------------------------------------------------------------------
+struct d3 {
+    double x, y, z;
+};
+__host__ __device__ inline d3 mk(double x, double y, double z) { return d3{x, y, z}; }
+__host__ __device__ inline d3 operator+(d3 a, d3 b) { return d3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__host__ __device__ inline d3 operator-(d3 a, d3 b) { return d3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__host__ __device__ inline d3 operator*(double s, d3 a) { return d3{s * a.x, s * a.y, s * a.z}; }
+__host__ __device__ inline double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__host__ __device__ inline d3 cross(d3 a, d3 b) {
+    return d3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__host__ __device__ inline double len(d3 a) { return sqrt(dot(a, a)); }
+
+struct sym3 {
+    double xx, yy, zz, xy, xz, yz;
+};
+__host__ __device__ inline d3 mul(const sym3 &S, d3 v) {
+    return d3{S.xx * v.x + S.xy * v.y + S.xz * v.z, S.xy * v.x + S.yy * v.y + S.yz * v.z,
+              S.xz * v.x + S.yz * v.y + S.zz * v.z};
+}
+
+// rotation matrix columns of a unit quaternion [s, w]
+__host__ __device__ inline void quat_axes(double s, double x, double y, double z, d3 &c0, d3 &c1, d3 &c2) {
+    c0 = d3{1 - 2 * (y * y + z * z), 2 * (x * y + s * z), 2 * (x * z - s * y)};
+    c1 = d3{2 * (x * y - s * z), 1 - 2 * (x * x + z * z), 2 * (y * z + s * x)};
+    c2 = d3{2 * (x * z + s * y), 2 * (y * z - s * x), 1 - 2 * (x * x + y * y)};
+}
+
+// ---------------------------------------------------------------------------
+// per-packing broadphase grid
+// ---------------------------------------------------------------------------
+struct PackGrid {
+    int nc[3];
+    int periodic[3];
+    double cs[3];      // cell size
+    double org[3];     // origin (open directions)
+    double box[3];     // periodic edge (0 = open)
+    long long cell_off;
+};
+
+// ---------------------------------------------------------------------------
+// LCP iteration state (device, one per solve)
+// ---------------------------------------------------------------------------
+struct PgdState {
+    double alpha;     // current step (Jacobi-scaled variables)
+    double res;       // scaled natural residual of the current iterate
+    double ss, sy, yy;
+    int iter;         // iterations taken
+    int conv;         // 1 once res <= tol
+    unsigned ticket;  // last-block counter
+    int pad;
+};
+
+// ---------------------------------------------------------------------------
+// host launchers (each defined in the .hip file that owns the kernels)
+// ---------------------------------------------------------------------------
+// scan.hip: exclusive prefix sum of n ints (out may alias in); the total is
+// written to total_dev[0] when total_dev is not null.  scratch grows as needed.
+void exclusive_scan(const int *in, int *out, int n, int *total_dev, DBuf<int> &scratch, hipStream_t s);
+
+}  // namespace relcp

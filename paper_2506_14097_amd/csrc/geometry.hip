@@ -1,0 +1,658 @@
+// geometry.hip -- body set-up, trial integration, candidate pairs and the
+// shared-normal signed distance (SNSD) narrowphase, all FP64.
+//
+// Paper: Palmer, Aktulga, Gao (arXiv 2506.14097).  SNSD: Sec. 2.1.4 and
+// Fig. surface representation (a); stationarity p_b - p_a = Phi n: Lemma
+// uniform interior tangent ball; ellipsoids Sec. 5.2, spherocylinders Sec.
+// 5.3.  Laws of motion: Sec. 2.1.2 (Eq. law_inertia, Eq. law_overdamped, Eq.
+// ellipsoid_mobility).
+#include "geometry.h"
+
+namespace relcp {
+
+// ===========================================================================
+// SNSD of two ellipsoids
+// ===========================================================================
+// The shared-normal pair is read as the maximiser of the support gap
+//   f(n) = n.d - h_a(n) - h_b(n),  h(n) = sqrt(n^T Sigma n),  |n| = 1,
+// d = x_b - x_a: the Euclidean distance when apart, minus the minimum
+// translation depth when overlapping.  f is 1-homogeneous, so its gradient
+// is p_b - p_a and a stationary point on the sphere is a shared normal.
+// Maximised by a Riemannian Newton ascent with a gradient-ascent fallback
+// where the projected Hessian is not negative definite.
+
+__device__ inline double support_gap(d3 n, d3 d, const sym3 &A, const sym3 &B) {
+    return dot(n, d) - sqrt(dot(n, mul(A, n))) - sqrt(dot(n, mul(B, n)));
+}
+
+__device__ inline void tangent_frame(d3 n, d3 &e1, d3 &e2) {
+    // cross with the coordinate axis least aligned with n
+    double ax = fabs(n.x), ay = fabs(n.y), az = fabs(n.z);
+    d3 a = (ax <= ay && ax <= az) ? mk(1, 0, 0) : ((ay <= az) ? mk(0, 1, 0) : mk(0, 0, 1));
+    e1 = cross(n, a);
+    e1 = (1.0 / len(e1)) * e1;
+    e2 = cross(n, e1);
+}
+
+__device__ double gap_newton(d3 &n, d3 d, const sym3 &A, const sym3 &B, int maxit) {
+    double F = support_gap(n, d, A, B);
+    const double dl = len(d);
+    for (int it = 0; it < maxit; ++it) {
+        d3 an = mul(A, n), bn = mul(B, n);
+        double ha = sqrt(dot(n, an)), hb = sqrt(dot(n, bn));
+        d3 grad = d - (1.0 / ha) * an - (1.0 / hb) * bn;  // p_b - p_a
+        double fn = dot(n, grad);
+        d3 e1, e2;
+        tangent_frame(n, e1, e2);
+        double g1 = dot(e1, grad), g2 = dot(e2, grad);
+        double scale = dl + ha + hb;
+        double gnorm = sqrt(g1 * g1 + g2 * g2);
+        if (gnorm <= 1e-14 * scale) break;
+        // projected Hessian of f on the sphere: P (Hess f) P - (n.grad f) P
+        d3 Ae1 = mul(A, e1), Ae2 = mul(A, e2), Be1 = mul(B, e1), Be2 = mul(B, e2);
+        double ia = 1.0 / ha, ib = 1.0 / hb, ia3 = ia * ia * ia, ib3 = ib * ib * ib;
+        double a1 = dot(e1, an), a2 = dot(e2, an), b1 = dot(e1, bn), b2 = dot(e2, bn);
+        double h11 = -(dot(e1, Ae1) * ia - a1 * a1 * ia3) - (dot(e1, Be1) * ib - b1 * b1 * ib3) - fn;
+        double h12 = -(dot(e1, Ae2) * ia - a1 * a2 * ia3) - (dot(e1, Be2) * ib - b1 * b2 * ib3);
+        double h22 = -(dot(e2, Ae2) * ia - a2 * a2 * ia3) - (dot(e2, Be2) * ib - b2 * b2 * ib3) - fn;
+        double det = h11 * h22 - h12 * h12;
+        double v1, v2;
+        if (h11 < 0.0 && det > 0.0) {
+            v1 = (-h22 * g1 + h12 * g2) / det;
+            v2 = (h12 * g1 - h11 * g2) / det;
+        } else {
+            double curv = fabs(h11) + fabs(h22) + 2.0 * fabs(h12) + 1e-300;
+            double t = 1.0 / curv;
+            if (t * gnorm > 0.5) t = 0.5 / gnorm;
+            v1 = t * g1;
+            v2 = t * g2;
+        }
+        double vl = sqrt(v1 * v1 + v2 * v2);
+        if (vl > 0.5) {
+            v1 *= 0.5 / vl;
+            v2 *= 0.5 / vl;
+            vl = 0.5;
+        }
+        double t = 1.0, Fn = F;
+        d3 nn = n;
+        bool ok = false;
+        for (int ls = 0; ls < 40; ++ls) {
+            d3 c = n + t * (v1 * e1 + v2 * e2);
+            c = (1.0 / len(c)) * c;
+            double Fc = support_gap(c, d, A, B);
+            if (Fc >= F - 1e-15 * scale) {
+                nn = c;
+                Fn = Fc;
+                ok = true;
+                break;
+            }
+            t *= 0.5;
+        }
+        if (!ok) break;
+        n = nn;
+        F = Fn;
+        if (t * vl < 1e-15) break;
+    }
+    return F;
+}
+
+// Result: Phi, n (a -> b), r_a = p_a - x_a, r_b = p_b - x_b.
+struct Snsd {
+    double phi;
+    d3 n, ra, rb;
+};
+
+__device__ Snsd snsd_ellipsoid(d3 d, const sym3 &A, const sym3 &B, d3 hint, bool has_hint) {
+    double dl = len(d);
+    d3 n0 = dl > 0.0 ? (1.0 / dl) * d : mk(1, 0, 0);
+    d3 best_n = n0;
+    double best = gap_newton(best_n, d, A, B, 60);
+    if (has_hint) {
+        d3 n1 = hint;
+        double F1 = gap_newton(n1, d, A, B, 60);
+        if (F1 > best) {
+            best = F1;
+            best_n = n1;
+        }
+    }
+    // deep overlap: several local maxima are possible; seed from a coarse
+    // Fibonacci sphere and keep the best converged value
+    double ha = sqrt(dot(best_n, mul(A, best_n))), hb = sqrt(dot(best_n, mul(B, best_n)));
+    if (best < -0.05 * (ha + hb) || dl == 0.0) {
+        const int ns = 64;
+        double bs = -1e300;
+        d3 bsn = n0;
+        for (int i = 0; i < ns; ++i) {
+            double z = 1.0 - (2.0 * i + 1.0) / ns;
+            double r = sqrt(fmax(0.0, 1.0 - z * z));
+            double ph = 2.399963229728653 * i;
+            d3 c = mk(r * cos(ph), r * sin(ph), z);
+            double Fc = support_gap(c, d, A, B);
+            if (Fc > bs) {
+                bs = Fc;
+                bsn = c;
+            }
+        }
+        double F2 = gap_newton(bsn, d, A, B, 60);
+        if (F2 > best) {
+            best = F2;
+            best_n = bsn;
+        }
+    }
+    d3 an = mul(A, best_n), bn = mul(B, best_n);
+    Snsd o;
+    o.phi = best;
+    o.n = best_n;
+    o.ra = (1.0 / sqrt(dot(best_n, an))) * an;
+    o.rb = (-1.0 / sqrt(dot(best_n, bn))) * bn;
+    return o;
+}
+
+// ===========================================================================
+// SNSD of two spherocylinders: closest points of the axis segments minus
+// the cap radii (Sec. 5.3).  Readings for non-unique closest pairs:
+// parallel axes (|t_a x t_b|^2 < 1e-12): midpoint of the overlap of B's
+// projection onto A, else the nearer end of A; coincident axis points
+// (|q - p| < 1e-12): normal t_a x t_b (in a monolayer: the in-plane normal
+// of t_a), with parallel axes the part of d normal to t_a, signed n.d >= 0.
+// ===========================================================================
+__device__ inline double clampd(double v, double lo, double hi) { return fmin(fmax(v, lo), hi); }
+
+__device__ Snsd snsd_spherocyl(d3 d, d3 ta, double la, double ra, d3 tb, double lb, double rb, bool planar) {
+    const double ha = 0.5 * la, hb = 0.5 * lb;
+    const d3 c = cross(ta, tb);
+    const double b = dot(ta, tb), ea = dot(ta, d), eb = dot(tb, d);
+    double s, u;
+    if (dot(c, c) < 1e-12) {
+        double p0 = ea - hb * b, p1 = ea + hb * b;
+        double lo = fmin(p0, p1), hi = fmax(p0, p1);
+        double olo = fmax(lo, -ha), ohi = fmin(hi, ha);
+        if (olo <= ohi)
+            s = 0.5 * (olo + ohi);
+        else
+            s = (hi < -ha) ? -ha : ha;
+        u = clampd(s * b - eb, -hb, hb);
+    } else {
+        // convex quadratic over a rectangle: interior stationary point, else
+        // the best of the four clamped edge minimisers
+        auto dist2 = [&](double ss, double uu) {
+            d3 w = d + uu * tb - ss * ta;
+            return dot(w, w);
+        };
+        double den = 1.0 - b * b;
+        double s0 = (ea - b * eb) / den, u0 = (b * ea - eb) / den;
+        double best = 1e300;
+        s = 0.0;
+        u = 0.0;
+        if (s0 >= -ha && s0 <= ha && u0 >= -hb && u0 <= hb) {
+            best = dist2(s0, u0);
+            s = s0;
+            u = u0;
+        }
+        for (int k = 0; k < 2; ++k) {
+            double ss = k ? ha : -ha;
+            double uu = clampd(ss * b - eb, -hb, hb);
+            double v = dist2(ss, uu);
+            if (v < best) {
+                best = v;
+                s = ss;
+                u = uu;
+            }
+        }
+        for (int k = 0; k < 2; ++k) {
+            double uu = k ? hb : -hb;
+            double ss = clampd(ea + uu * b, -ha, ha);
+            double v = dist2(ss, uu);
+            if (v < best) {
+                best = v;
+                s = ss;
+                u = uu;
+            }
+        }
+    }
+    d3 p = s * ta;
+    d3 qb = d + u * tb;
+    d3 w = qb - p;
+    double dist = len(w);
+    d3 n;
+    if (dist >= 1e-12) {
+        n = (1.0 / dist) * w;
+    } else {
+        if (planar) {
+            n = mk(-ta.y, ta.x, 0.0);
+            n = (1.0 / len(n)) * n;
+        } else if (dot(c, c) >= 1e-12) {
+            n = (1.0 / len(c)) * c;
+        } else {
+            n = d - ea * ta;
+            double l = len(n);
+            if (l < 1e-12) {
+                n = mk(-ta.y, ta.x, 0.0);
+                l = len(n);
+            }
+            if (l < 1e-12) {
+                n = mk(0.0, -ta.z, ta.y);
+                l = len(n);
+            }
+            n = (1.0 / l) * n;
+        }
+        if (dot(n, d) < 0.0) n = -1.0 * n;
+    }
+    Snsd o;
+    o.phi = dist - ra - rb;
+    o.n = n;
+    o.ra = p + ra * n;
+    o.rb = (qb - d) - rb * n;
+    return o;
+}
+
+// ===========================================================================
+// per-body set-up at C^k: geometry (Sigma or axis), bounding radius,
+// operator K, free velocity U_free
+// ===========================================================================
+// K per body (9 comps): translational diagonal (3) and rotational symmetric
+// (6), already projected for a monolayer (z translation, x/y rotation off).
+//  overdamped: K = M = (1/xi) diag(I/L, 12 I/L^3), L = 2 max semiaxis
+//              (ellipsoid) or l + 2 r (spherocylinder, tip to tip)
+//  inertial:   K = dt M^-1, M^-1 = diag(I/m, R diag(1/I_body) R^T), solid
+//              ellipsoid of density rho
+__global__ void k_body_setup(int nb, const double *__restrict__ q, int ldq, const int *__restrict__ kind,
+                             const double *__restrict__ p, int ldp, const double *__restrict__ rho_xi,
+                             const double *__restrict__ u, int ldu, const double *__restrict__ fext, int ldf,
+                             int dynamics, int planar, double dt, double *__restrict__ geo, int ldg,
+                             double *__restrict__ Rb, double *__restrict__ K, int ldk, float *__restrict__ K32,
+                             double *__restrict__ vfree, int ldv) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    double qs = q[i], qx = q[ldq + i], qy = q[2 * ldq + i], qz = q[3 * ldq + i];
+    d3 c0, c1, c2;
+    quat_axes(qs, qx, qy, qz, c0, c1, c2);
+    double a = p[i], b = p[ldp + i], c = p[2 * ldp + i];
+    int kd = kind[i];
+    if (kd == 0) {
+        // Sigma = R diag(a^2, b^2, c^2) R^T
+        double a2 = a * a, b2 = b * b, c2s = c * c;
+        geo[0 * ldg + i] = a2 * c0.x * c0.x + b2 * c1.x * c1.x + c2s * c2.x * c2.x;
+        geo[1 * ldg + i] = a2 * c0.y * c0.y + b2 * c1.y * c1.y + c2s * c2.y * c2.y;
+        geo[2 * ldg + i] = a2 * c0.z * c0.z + b2 * c1.z * c1.z + c2s * c2.z * c2.z;
+        geo[3 * ldg + i] = a2 * c0.x * c0.y + b2 * c1.x * c1.y + c2s * c2.x * c2.y;
+        geo[4 * ldg + i] = a2 * c0.x * c0.z + b2 * c1.x * c1.z + c2s * c2.x * c2.z;
+        geo[5 * ldg + i] = a2 * c0.y * c0.z + b2 * c1.y * c1.z + c2s * c2.y * c2.z;
+        Rb[i] = fmax(a, fmax(b, c));
+    } else {
+        geo[0 * ldg + i] = c0.x;
+        geo[1 * ldg + i] = c0.y;
+        geo[2 * ldg + i] = c0.z;
+        geo[3 * ldg + i] = 0.0;
+        geo[4 * ldg + i] = 0.0;
+        geo[5 * ldg + i] = 0.0;
+        Rb[i] = 0.5 * b + a;
+    }
+    if (!K) return;
+    double kt[3], kr[6];
+    if (dynamics == 0) {
+        double L = (kd == 0) ? 2.0 * fmax(a, fmax(b, c)) : b + 2.0 * a;
+        double xi = rho_xi[i];
+        double t = 1.0 / (xi * L), r = 12.0 / (xi * L * L * L);
+        kt[0] = kt[1] = kt[2] = t;
+        kr[0] = kr[1] = kr[2] = r;
+        kr[3] = kr[4] = kr[5] = 0.0;
+    } else {
+        double m = rho_xi[i] * (4.0 / 3.0) * M_PI * a * b * c;
+        double I0 = m * (b * b + c * c) / 5.0, I1 = m * (a * a + c * c) / 5.0, I2 = m * (a * a + b * b) / 5.0;
+        double w0 = dt / I0, w1 = dt / I1, w2 = dt / I2;
+        kt[0] = kt[1] = kt[2] = dt / m;
+        kr[0] = w0 * c0.x * c0.x + w1 * c1.x * c1.x + w2 * c2.x * c2.x;
+        kr[1] = w0 * c0.y * c0.y + w1 * c1.y * c1.y + w2 * c2.y * c2.y;
+        kr[2] = w0 * c0.z * c0.z + w1 * c1.z * c1.z + w2 * c2.z * c2.z;
+        kr[3] = w0 * c0.x * c0.y + w1 * c1.x * c1.y + w2 * c2.x * c2.y;
+        kr[4] = w0 * c0.x * c0.z + w1 * c1.x * c1.z + w2 * c2.x * c2.z;
+        kr[5] = w0 * c0.y * c0.z + w1 * c1.y * c1.z + w2 * c2.y * c2.z;
+    }
+    if (planar) {
+        kt[2] = 0.0;
+        kr[0] = kr[1] = kr[3] = kr[4] = kr[5] = 0.0;
+    }
+    for (int k = 0; k < 3; ++k) {
+        K[k * ldk + i] = kt[k];
+        K32[k * ldk + i] = (float)kt[k];
+    }
+    for (int k = 0; k < 6; ++k) {
+        K[(3 + k) * ldk + i] = kr[k];
+        K32[(3 + k) * ldk + i] = (float)kr[k];
+    }
+    // U_free = U^k (inertial) + K F_ext
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (dynamics == 1 && u)
+        for (int k = 0; k < 6; ++k) v[k] = u[k * ldu + i];
+    if (fext) {
+        double f[6];
+        for (int k = 0; k < 6; ++k) f[k] = fext[k * ldf + i];
+        v[0] += kt[0] * f[0];
+        v[1] += kt[1] * f[1];
+        v[2] += kt[2] * f[2];
+        v[3] += kr[0] * f[3] + kr[3] * f[4] + kr[4] * f[5];
+        v[4] += kr[3] * f[3] + kr[1] * f[4] + kr[5] * f[5];
+        v[5] += kr[4] * f[3] + kr[5] * f[4] + kr[2] * f[5];
+    }
+    if (planar) {
+        v[2] = 0.0;
+        v[3] = 0.0;
+        v[4] = 0.0;
+    }
+    for (int k = 0; k < 6; ++k) vfree[k * ldv + i] = v[k];
+}
+
+// ===========================================================================
+// trial configuration C_{n+1} = C^k (+) dt V_n   (Alg. 1; Eq. relcp)
+// ===========================================================================
+// Reading of the configuration map: positions x + dt v exactly; orientation
+// exp(dt w) (x) q with world-frame w, renormalised (agrees with the linear
+// G^k to first order in dt).
+__device__ inline unsigned long long dbl_bits(double v) { return (unsigned long long)__double_as_longlong(v); }
+
+__global__ void k_trial(int nb, const double *__restrict__ x, int ldx, const double *__restrict__ q, int ldq,
+                        const double *__restrict__ vfree, const double *__restrict__ vc, int ldv, double dt,
+                        const int *__restrict__ kind, const double *__restrict__ p, int ldp,
+                        const double *__restrict__ Rb, double *__restrict__ xt, double *__restrict__ qt,
+                        double *__restrict__ geo, int ldg, double *__restrict__ vout,
+                        unsigned long long *__restrict__ maxdisp) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double disp = 0.0;
+    if (i < nb) {
+        double v[6];
+        for (int k = 0; k < 6; ++k) v[k] = vfree[k * ldv + i] + vc[k * ldv + i];
+        if (vout)
+            for (int k = 0; k < 6; ++k) vout[k * ldv + i] = v[k];
+        for (int k = 0; k < 3; ++k) xt[k * ldx + i] = x[k * ldx + i] + dt * v[k];
+        d3 th = mk(dt * v[3], dt * v[4], dt * v[5]);
+        double ang = len(th);
+        double es, ek;
+        if (ang < 1e-8) {
+            es = 1.0 - ang * ang / 8.0;
+            ek = 0.5 - ang * ang / 48.0;
+        } else {
+            es = cos(0.5 * ang);
+            ek = sin(0.5 * ang) / ang;
+        }
+        d3 ew = ek * th;
+        double s0 = q[i];
+        d3 w0 = mk(q[ldq + i], q[2 * ldq + i], q[3 * ldq + i]);
+        double rs = es * s0 - dot(ew, w0);
+        d3 rw = es * w0 + s0 * ew + cross(ew, w0);
+        double nr = sqrt(rs * rs + dot(rw, rw));
+        rs /= nr;
+        rw = (1.0 / nr) * rw;
+        qt[i] = rs;
+        qt[ldq + i] = rw.x;
+        qt[2 * ldq + i] = rw.y;
+        qt[3 * ldq + i] = rw.z;
+        // geometry at the trial orientation
+        d3 c0, c1, c2;
+        quat_axes(rs, rw.x, rw.y, rw.z, c0, c1, c2);
+        if (kind[i] == 0) {
+            double a2 = p[i] * p[i], b2 = p[ldp + i] * p[ldp + i], cc = p[2 * ldp + i] * p[2 * ldp + i];
+            geo[0 * ldg + i] = a2 * c0.x * c0.x + b2 * c1.x * c1.x + cc * c2.x * c2.x;
+            geo[1 * ldg + i] = a2 * c0.y * c0.y + b2 * c1.y * c1.y + cc * c2.y * c2.y;
+            geo[2 * ldg + i] = a2 * c0.z * c0.z + b2 * c1.z * c1.z + cc * c2.z * c2.z;
+            geo[3 * ldg + i] = a2 * c0.x * c0.y + b2 * c1.x * c1.y + cc * c2.x * c2.y;
+            geo[4 * ldg + i] = a2 * c0.x * c0.z + b2 * c1.x * c1.z + cc * c2.x * c2.z;
+            geo[5 * ldg + i] = a2 * c0.y * c0.z + b2 * c1.y * c1.z + cc * c2.y * c2.z;
+        } else {
+            geo[0 * ldg + i] = c0.x;
+            geo[1 * ldg + i] = c0.y;
+            geo[2 * ldg + i] = c0.z;
+            geo[3 * ldg + i] = 0.0;
+            geo[4 * ldg + i] = 0.0;
+            geo[5 * ldg + i] = 0.0;
+        }
+        // bound on the displacement of any surface point
+        disp = dt * sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) + Rb[i] * ang;
+    }
+    // wave max, then one atomic per wave (non-negative doubles order like
+    // their bit patterns)
+    for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) disp = fmax(disp, __shfl_xor(disp, o, RELCP_WAVE));
+    if ((threadIdx.x & (RELCP_WAVE - 1)) == 0 && disp > 0.0) atomicMax(maxdisp, dbl_bits(disp));
+}
+
+// ===========================================================================
+// SNSD over a pair list
+// ===========================================================================
+// Sortable key of a double (monotone map to unsigned 64-bit).
+__device__ inline unsigned long long order_key(double v) {
+    unsigned long long b = dbl_bits(v);
+    return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__global__ void __launch_bounds__(256) k_snsd_pairs(SnsdArgs A) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    double phi = 1e300, marg = 1e300;
+    if (k < A.m) {
+        int a = A.pa[k], b = A.pb[k];
+        int pk = A.body_batch ? A.body_batch[a] : 0;
+        d3 d = mk(A.x[b] - A.x[a], A.x[A.ldx + b] - A.x[A.ldx + a], A.x[2 * A.ldx + b] - A.x[2 * A.ldx + a]);
+        const double *bx = A.boxes + 3 * pk;
+        if (bx[0] > 0.0) d.x -= bx[0] * rint(d.x / bx[0]);
+        if (bx[1] > 0.0) d.y -= bx[1] * rint(d.y / bx[1]);
+        if (bx[2] > 0.0) d.z -= bx[2] * rint(d.z / bx[2]);
+        Snsd s;
+        if (A.kind[a] == 0) {
+            sym3 Sa{A.geo[a], A.geo[A.ldg + a], A.geo[2 * A.ldg + a], A.geo[3 * A.ldg + a], A.geo[4 * A.ldg + a],
+                    A.geo[5 * A.ldg + a]};
+            sym3 Sb{A.geo[b], A.geo[A.ldg + b], A.geo[2 * A.ldg + b], A.geo[3 * A.ldg + b], A.geo[4 * A.ldg + b],
+                    A.geo[5 * A.ldg + b]};
+            d3 hint = mk(1, 0, 0);
+            bool has = false;
+            if (A.hint) {
+                hint = mk(A.hint[k], A.hint[A.ldo + k], A.hint[2 * A.ldo + k]);
+                double hl = len(hint);
+                has = hl > 0.5;
+                if (has) hint = (1.0 / hl) * hint;
+            }
+            s = snsd_ellipsoid(d, Sa, Sb, hint, has);
+        } else {
+            d3 ta = mk(A.geo[a], A.geo[A.ldg + a], A.geo[2 * A.ldg + a]);
+            d3 tb = mk(A.geo[b], A.geo[A.ldg + b], A.geo[2 * A.ldg + b]);
+            s = snsd_spherocyl(d, ta, A.p[A.ldp + a], A.p[a], tb, A.p[A.ldp + b], A.p[b], A.planar != 0);
+        }
+        A.out[k] = s.phi;
+        A.out[1 * A.ldo + k] = s.n.x;
+        A.out[2 * A.ldo + k] = s.n.y;
+        A.out[3 * A.ldo + k] = s.n.z;
+        A.out[4 * A.ldo + k] = s.ra.x;
+        A.out[5 * A.ldo + k] = s.ra.y;
+        A.out[6 * A.ldo + k] = s.ra.z;
+        A.out[7 * A.ldo + k] = s.rb.x;
+        A.out[8 * A.ldo + k] = s.rb.y;
+        A.out[9 * A.ldo + k] = s.rb.z;
+        phi = s.phi;
+        marg = fabs(s.phi + A.eps);
+        if (A.flag) A.flag[k] = (A.mode == 0) ? (s.phi <= A.thresh ? 1 : 0) : (s.phi < -A.eps ? 1 : 0);
+    }
+    if (A.minphi) {
+        for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) {
+            phi = fmin(phi, __shfl_xor(phi, o, RELCP_WAVE));
+            marg = fmin(marg, __shfl_xor(marg, o, RELCP_WAVE));
+        }
+        if ((threadIdx.x & (RELCP_WAVE - 1)) == 0 && phi < 1e300) {
+            atomicMin(A.minphi, order_key(phi));
+            atomicMin(A.minmarg, order_key(marg));
+        }
+    }
+}
+
+// ===========================================================================
+// candidate pairs by a per-packing cell list
+// ===========================================================================
+__device__ inline int cell_coord(double v, int k, const PackGrid &g) {
+    if (g.periodic[k]) {
+        double t = v / g.box[k];
+        t -= floor(t);
+        int c = (int)(t * g.nc[k]);
+        return c >= g.nc[k] ? g.nc[k] - 1 : (c < 0 ? 0 : c);
+    }
+    int c = (int)floor((v - g.org[k]) / g.cs[k]);
+    return c < 0 ? 0 : (c >= g.nc[k] ? g.nc[k] - 1 : c);
+}
+
+__global__ void k_cell_assign(int nb, const double *__restrict__ x, int ldx, const int *__restrict__ body_batch,
+                              const PackGrid *__restrict__ grids, int *__restrict__ body_cell,
+                              int *__restrict__ cell_count) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    int pk = body_batch ? body_batch[i] : 0;
+    PackGrid g = grids[pk];
+    int cx = cell_coord(x[i], 0, g), cy = cell_coord(x[ldx + i], 1, g), cz = cell_coord(x[2 * ldx + i], 2, g);
+    long long c = g.cell_off + ((long long)cz * g.nc[1] + cy) * g.nc[0] + cx;
+    body_cell[i] = (int)c;
+    atomicAdd(cell_count + c, 1);
+}
+
+__global__ void k_cell_fill(int nb, const int *__restrict__ body_cell, const int *__restrict__ cell_start,
+                            int *__restrict__ cursor, int *__restrict__ items) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    int c = body_cell[i];
+    int pos = cell_start[c] + atomicAdd(cursor + c, 1);
+    items[pos] = i;
+}
+
+// neighbour offsets of one direction: unique cells among c-1, c, c+1
+__device__ inline int nbr_cells(int c, int k, const PackGrid &g, int out[3]) {
+    int n = g.nc[k];
+    if (g.periodic[k]) {
+        if (n == 1) {
+            out[0] = 0;
+            return 1;
+        }
+        if (n == 2) {
+            out[0] = 0;
+            out[1] = 1;
+            return 2;
+        }
+        out[0] = (c + n - 1) % n;
+        out[1] = c;
+        out[2] = (c + 1) % n;
+        return 3;
+    }
+    int m = 0;
+    for (int o = -1; o <= 1; ++o) {
+        int cc = c + o;
+        if (cc >= 0 && cc < n) out[m++] = cc;
+    }
+    return m;
+}
+
+template <bool kFill>
+__global__ void __launch_bounds__(256) k_pairs(int nb, const double *__restrict__ x, int ldx,
+                                               const double *__restrict__ Rb, const int *__restrict__ body_batch,
+                                               const PackGrid *__restrict__ grids, const int *__restrict__ body_cell,
+                                               const int *__restrict__ cell_start, const int *__restrict__ cell_count,
+                                               const int *__restrict__ items, double skin,
+                                               int *__restrict__ pair_count, const int *__restrict__ pair_off,
+                                               int *__restrict__ pa, int *__restrict__ pb, int cap) {
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nb) return;
+    int pk = body_batch ? body_batch[a] : 0;
+    PackGrid g = grids[pk];
+    double xa = x[a], ya = x[ldx + a], za = x[2 * ldx + a], ra = Rb[a];
+    long long local = body_cell[a] - g.cell_off;
+    int cx = (int)(local % g.nc[0]);
+    int cy = (int)((local / g.nc[0]) % g.nc[1]);
+    int cz = (int)(local / ((long long)g.nc[0] * g.nc[1]));
+    int ox[3], oy[3], oz[3];
+    int nx = nbr_cells(cx, 0, g, ox), ny = nbr_cells(cy, 1, g, oy), nz = nbr_cells(cz, 2, g, oz);
+    int cnt = 0;
+    int base = kFill ? pair_off[a] : 0;
+    for (int iz = 0; iz < nz; ++iz)
+        for (int iy = 0; iy < ny; ++iy)
+            for (int ix = 0; ix < nx; ++ix) {
+                long long c = g.cell_off + ((long long)oz[iz] * g.nc[1] + oy[iy]) * g.nc[0] + ox[ix];
+                int s0 = cell_start[c], s1 = s0 + cell_count[c];
+                for (int t = s0; t < s1; ++t) {
+                    int b = items[t];
+                    if (b <= a) continue;
+                    double dx = x[b] - xa, dy = x[ldx + b] - ya, dz = x[2 * ldx + b] - za;
+                    if (g.periodic[0]) dx -= g.box[0] * rint(dx / g.box[0]);
+                    if (g.periodic[1]) dy -= g.box[1] * rint(dy / g.box[1]);
+                    if (g.periodic[2]) dz -= g.box[2] * rint(dz / g.box[2]);
+                    if (sqrt(dx * dx + dy * dy + dz * dz) - ra - Rb[b] <= skin) {
+                        if (kFill) {
+                            int pos = base + cnt;
+                            if (pos < cap) {
+                                pa[pos] = a;
+                                pb[pos] = b;
+                            }
+                        }
+                        ++cnt;
+                    }
+                }
+            }
+    if (!kFill) {
+        pair_count[a] = cnt;
+    } else {
+        // order the partners of a by index (insertion sort of a short list)
+        int lo = base, hi = min(base + cnt, cap);
+        for (int i = lo + 1; i < hi; ++i) {
+            int v = pb[i];
+            int j = i - 1;
+            while (j >= lo && pb[j] > v) {
+                pb[j + 1] = pb[j];
+                --j;
+            }
+            pb[j + 1] = v;
+        }
+    }
+}
+
+// ===========================================================================
+// host launchers
+// ===========================================================================
+static inline int nblk(long long n, int t) { return (int)((n + t - 1) / t); }
+
+void launch_body_setup(const BodySetupArgs &a, hipStream_t s) {
+    if (a.nb <= 0) return;
+    hipLaunchKernelGGL(k_body_setup, dim3(nblk(a.nb, 256)), dim3(256), 0, s, a.nb, a.q, a.ldq, a.kind, a.p, a.ldp,
+                       a.rho_xi, a.u, a.ldu, a.fext, a.ldf, a.dynamics, a.planar, a.dt, a.geo, a.ldg, a.Rb, a.K, a.ldk,
+                       a.K32, a.vfree, a.ldv);
+}
+
+void launch_trial(int nb, const double *x, int ldx, const double *q, int ldq, const double *vfree, const double *vc,
+                  int ldv, double dt, const int *kind, const double *p, int ldp, const double *Rb, double *xt,
+                  double *qt, double *geo, int ldg, double *vout, unsigned long long *maxdisp, hipStream_t s) {
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_trial, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, x, ldx, q, ldq, vfree, vc, ldv, dt, kind, p,
+                       ldp, Rb, xt, qt, geo, ldg, vout, maxdisp);
+}
+
+void launch_snsd_pairs(const SnsdArgs &a, hipStream_t s) {
+    if (a.m <= 0) return;
+    hipLaunchKernelGGL(k_snsd_pairs, dim3(nblk(a.m, 256)), dim3(256), 0, s, a);
+}
+
+void launch_cell_assign(int nb, const double *x, int ldx, const int *body_batch, const PackGrid *grids,
+                        int *body_cell, int *cell_count, hipStream_t s) {
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_cell_assign, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, x, ldx, body_batch, grids, body_cell,
+                       cell_count);
+}
+
+void launch_cell_fill(int nb, const int *body_cell, const int *cell_start, int *cursor, int *items, hipStream_t s) {
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_cell_fill, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, body_cell, cell_start, cursor, items);
+}
+
+void launch_pairs(bool fill, int nb, const double *x, int ldx, const double *Rb, const int *body_batch,
+                  const PackGrid *grids, const int *body_cell, const int *cell_start, const int *cell_count,
+                  const int *items, double skin, int *pair_count, const int *pair_off, int *pa, int *pb, int cap,
+                  hipStream_t s) {
+    if (nb <= 0) return;
+    if (fill)
+        hipLaunchKernelGGL(k_pairs<true>, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, x, ldx, Rb, body_batch, grids,
+                           body_cell, cell_start, cell_count, items, skin, pair_count, pair_off, pa, pb, cap);
+    else
+        hipLaunchKernelGGL(k_pairs<false>, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, x, ldx, Rb, body_batch, grids,
+                           body_cell, cell_start, cell_count, items, skin, pair_count, pair_off, pa, pb, cap);
+}
+
+}  // namespace relcp

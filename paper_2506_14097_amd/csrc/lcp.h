@@ -1,0 +1,87 @@
+// lcp.h -- launch arguments of the contact-row and LCP kernels (lcp.hip).
+#pragma once
+
+#include "common.h"
+
+namespace relcp {
+
+// Rows (constraints) of the LCP in one precision.  SoA with leading
+// dimension ld: n, ta = r_a x n, tb = r_b x n have 3 comps each.
+template <typename T>
+struct RowsT {
+    int m, ld;
+    const int *ia, *ib;
+    const T *n, *ta, *tb;
+    const T *qv;  // constant term of g = qv + dt D^T K D gamma
+    const T *dA;  // diagonal of A = dt D^T K D
+    T *gam, *g;
+};
+
+// Bodies for the LCP: operator K (9 comps: kt xyz, Kr xx yy zz xy xz yz),
+// contact-induced velocity vc = K D gamma (6 comps), CSR of incident rows
+// (entry = row << 1 | side, side 0 = body a, 1 = body b).
+template <typename T>
+struct BodiesT {
+    int nb, ld;
+    const T *K;
+    T *vc;
+    const int *off, *ent;
+};
+
+struct RowBuildArgs {
+    int nsel;
+    const int *sel;  // selected pair indices
+    const int *pa, *pb;
+    const double *snsd;  // 10 comps, ld = ldp
+    int ldp;
+    int m0;              // first row written
+    int rec;             // recursion at which the rows are generated
+    double dt;
+    const double *K;     // 9 comps, ld = ldb
+    const double *vfree; // 6 comps
+    const double *vc;    // 6 comps (new rows: V_n - U_free) or null (iteration-0 rows)
+    int ldb;
+    // warm start from the previous step (sorted pair list) or null
+    int nprev;
+    const int *prev_a, *prev_b;
+    const double *prev_lam;
+    // outputs, ld = ldr
+    int ldr;
+    int *ia, *ib, *pair, *rec_out;
+    double *n64, *ta64, *tb64, *qv64, *dA64, *gam64, *phi64;
+    float *n32, *ta32, *tb32, *qv32, *dA32, *gam32;
+};
+
+void launch_rows_build(const RowBuildArgs &a, hipStream_t s);
+void launch_compact(int n, const int *flags, const int *scanned, int *out, hipStream_t s);
+void launch_csr(int nb, int m, const int *ia, const int *ib, int *cnt, int *off, int *cursor, int *ent,
+                DBuf<int> &scan_scratch, hipStream_t s);
+
+// One projected-gradient iteration pass.  mode 0 = evaluate g at max(0,
+// gamma) (start of a solve); mode 1 = project with the current step, then
+// evaluate (one BB-PGD iteration).  Both passes skip when st->conv is set
+// (mode 1).
+template <typename T>
+void launch_lcp_iteration(int mode, const RowsT<T> &r, const BodiesT<T> &b, double dt, double tol, PgdState *st,
+                          double *partials, hipStream_t s);
+template <typename T>
+void launch_lcp_scatter(int mode, const RowsT<T> &r, const BodiesT<T> &b, const PgdState *st, hipStream_t s);
+template <typename T>
+void launch_lcp_gather(int mode, const RowsT<T> &r, const BodiesT<T> &b, double dt, double tol, PgdState *st,
+                       double *partials, hipStream_t s);
+
+// gamma64 <- gamma32 ; gamma32 <- gamma64
+void launch_promote(int m, const float *g32, double *g64, hipStream_t s);
+void launch_demote(int m, const double *g64, float *g32, hipStream_t s);
+
+// sum over rows of gamma (g - qv) = gamma^T A gamma, FP64, into out[0]
+void launch_work(int m, const double *gam, const double *g, const double *qv, double *partials, unsigned *ticket,
+                 double *out, hipStream_t s);
+
+// lam[pair[r]] += gamma[r] for the rows generated at recursion `level`
+void launch_pair_lambda(int m, const int *rec, const int *pair, const double *gam, int level, double *lam,
+                        hipStream_t s);
+
+int lcp_partials_needed(int m);
+
+}  // namespace relcp

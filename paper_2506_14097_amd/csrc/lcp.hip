@@ -1,0 +1,444 @@
+// lcp.hip -- contact rows, per-body incidence (CSR) and the matrix-free
+// projected-gradient LCP loop on A = dt D^T K D.
+//
+// Paper: Palmer, Aktulga, Gao (arXiv 2506.14097).  Rows: Eq. collision_ft
+// and the rigid wrench form [-n, -(r_a x n), n, (r_b x n)] (proof of Thm.
+// is_a_relcp).  LCP of one recursion: Eq. relcp (overdamped) and Eq.
+// relcp_inertial; CQP form Eq. cqpp, solved by projected gradient (one of
+// the solvers named after Eq. cqpp; the paper does not say which it used).
+// Per-row constants of the pulled-back rows: Sec. 3.1 (iteration 1,
+// "linearizing and pulling back new constraints").
+//
+// Iteration (Jacobi-scaled Barzilai-Borwein projected gradient):
+//   gamma' = max(0, gamma - alpha g / A_aa)
+//   g'     = qv + dt D^T (K D gamma')
+//   s = gamma' - gamma, y = g' - g
+//   even k: alpha = s^T D s / s^T y ; odd k: alpha = s^T y / y^T D^-1 y
+//   (kept when s^T y <= 0, clamped to [1e-10, 1e10]), stop when
+//   max_a |min(A_aa gamma_a, g_a)| <= tol.
+// Each iteration is two passes: a per-body scatter D gamma' -> K -> vc (no
+// atomics: each body walks its incidence list) and a per-row gather
+// D^T vc -> g' with the step-size reductions.  The last block of the gather
+// finishes the reductions in a fixed order, so the result does not depend
+// on block scheduling.
+#include "lcp.h"
+
+namespace relcp {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / RELCP_WAVE;
+
+inline int nblk(long long n, int t) { return (int)((n + t - 1) / t); }
+
+// The projection must round identically in the scatter and the gather.
+__device__ inline double project(double gm, double g, double dA, double al) {
+    double v = __dsub_rn(gm, __ddiv_rn(__dmul_rn(al, g), dA));
+    return v > 0.0 ? v : 0.0;
+}
+__device__ inline float project(float gm, float g, float dA, float al) {
+    float v = __fsub_rn(gm, __fdiv_rn(__fmul_rn(al, g), dA));
+    return v > 0.0f ? v : 0.0f;
+}
+template <typename T>
+__device__ inline T clamp0(T v) {
+    return v > T(0) ? v : T(0);
+}
+
+// ---------------------------------------------------------------------------
+// rows
+// ---------------------------------------------------------------------------
+__global__ void k_rows_build(RowBuildArgs A) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= A.nsel) return;
+    int pr = A.sel[k];
+    int a = A.pa[pr], b = A.pb[pr];
+    int r = A.m0 + k;
+    const int lp = A.ldp;
+    double phi = A.snsd[pr];
+    d3 n = mk(A.snsd[1 * lp + pr], A.snsd[2 * lp + pr], A.snsd[3 * lp + pr]);
+    d3 ra = mk(A.snsd[4 * lp + pr], A.snsd[5 * lp + pr], A.snsd[6 * lp + pr]);
+    d3 rb = mk(A.snsd[7 * lp + pr], A.snsd[8 * lp + pr], A.snsd[9 * lp + pr]);
+    d3 ta = cross(ra, n), tb = cross(rb, n);
+    const int lb = A.ldb;
+    auto rate = [&](const double *V) {  // D_r^T V
+        d3 va = mk(V[a], V[lb + a], V[2 * lb + a]), wa = mk(V[3 * lb + a], V[4 * lb + a], V[5 * lb + a]);
+        d3 vb = mk(V[b], V[lb + b], V[2 * lb + b]), wb = mk(V[3 * lb + b], V[4 * lb + b], V[5 * lb + b]);
+        return -dot(n, va) - dot(ta, wa) + dot(n, vb) + dot(tb, wb);
+    };
+    // qv = c + dt D^T U_free, with c = Phi at C^k for iteration-0 rows and
+    // c = Phi(C_{n+1}) - dt D^T V_n for rows pulled back from a trial, so
+    // that for those qv = Phi(C_{n+1}) - dt D^T (V_n - U_free).
+    double qv = A.vc ? phi - A.dt * rate(A.vc) : phi + A.dt * rate(A.vfree);
+    // A_rr = dt (n.kt_a n + ta.Kr_a ta + n.kt_b n + tb.Kr_b tb)
+    auto quad = [&](int i, d3 t) {
+        const double *K = A.K;
+        double tr = n.x * n.x * K[i] + n.y * n.y * K[lb + i] + n.z * n.z * K[2 * lb + i];
+        sym3 R{K[3 * lb + i], K[4 * lb + i], K[5 * lb + i], K[6 * lb + i], K[7 * lb + i], K[8 * lb + i]};
+        return tr + dot(t, mul(R, t));
+    };
+    double dA = A.dt * (quad(a, ta) + quad(b, tb));
+    if (!(dA > 0.0)) dA = 1.0;
+    double g0 = 0.0;
+    if (A.prev_lam && A.nprev > 0) {
+        int lo = 0, hi = A.nprev - 1;
+        while (lo <= hi) {
+            int mid = (lo + hi) >> 1;
+            int pa_ = A.prev_a[mid], pb_ = A.prev_b[mid];
+            if (pa_ == a && pb_ == b) {
+                g0 = A.prev_lam[mid];
+                break;
+            }
+            if (pa_ < a || (pa_ == a && pb_ < b))
+                lo = mid + 1;
+            else
+                hi = mid - 1;
+        }
+    }
+    const int L = A.ldr;
+    A.ia[r] = a;
+    A.ib[r] = b;
+    A.pair[r] = pr;
+    A.rec_out[r] = A.rec;
+    double nn[3] = {n.x, n.y, n.z}, tt[3] = {ta.x, ta.y, ta.z}, uu[3] = {tb.x, tb.y, tb.z};
+    for (int c = 0; c < 3; ++c) {
+        A.n64[c * L + r] = nn[c];
+        A.ta64[c * L + r] = tt[c];
+        A.tb64[c * L + r] = uu[c];
+        A.n32[c * L + r] = (float)nn[c];
+        A.ta32[c * L + r] = (float)tt[c];
+        A.tb32[c * L + r] = (float)uu[c];
+    }
+    A.qv64[r] = qv;
+    A.qv32[r] = (float)qv;
+    A.dA64[r] = dA;
+    A.dA32[r] = (float)dA;
+    A.gam64[r] = g0;
+    A.gam32[r] = (float)g0;
+    A.phi64[r] = phi;
+}
+
+__global__ void k_compact(int n, const int *__restrict__ flags, const int *__restrict__ scanned,
+                          int *__restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && flags[i]) out[scanned[i]] = i;
+}
+
+// ---------------------------------------------------------------------------
+// incidence lists (CSR by body)
+// ---------------------------------------------------------------------------
+__global__ void k_csr_count(int m, const int *__restrict__ ia, const int *__restrict__ ib, int *__restrict__ cnt) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    atomicAdd(cnt + ia[r], 1);
+    atomicAdd(cnt + ib[r], 1);
+}
+
+__global__ void k_csr_fill(int m, const int *__restrict__ ia, const int *__restrict__ ib, const int *__restrict__ off,
+                           int *__restrict__ cursor, int *__restrict__ ent) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    int a = ia[r], b = ib[r];
+    ent[off[a] + atomicAdd(cursor + a, 1)] = r << 1;
+    ent[off[b] + atomicAdd(cursor + b, 1)] = (r << 1) | 1;
+}
+
+// order each body's list by entry (row index) so summation order is fixed
+__global__ void k_csr_sort(int nb, const int *__restrict__ off, int *__restrict__ ent) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    int lo = off[i], hi = off[i + 1];
+    for (int k = lo + 1; k < hi; ++k) {
+        int v = ent[k], j = k - 1;
+        while (j >= lo && ent[j] > v) {
+            ent[j + 1] = ent[j];
+            --j;
+        }
+        ent[j + 1] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the two passes of one iteration
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kThreads) k_scatter(RowsT<T> R, BodiesT<T> B, const PgdState *__restrict__ st) {
+    if (MODE == 1 && st->conv) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B.nb) return;
+    const T al = (T)st->alpha;
+    T f0 = 0, f1 = 0, f2 = 0, t0 = 0, t1 = 0, t2 = 0;
+    const int e0 = B.off[i], e1 = B.off[i + 1];
+    const int L = R.ld;
+    for (int e = e0; e < e1; ++e) {
+        int en = B.ent[e];
+        int c = en >> 1;
+        T gm = R.gam[c];
+        T gv = MODE == 1 ? project(gm, R.g[c], R.dA[c], al) : clamp0(gm);
+        const T *tau = (en & 1) ? R.tb : R.ta;
+        T sg = (en & 1) ? gv : -gv;
+        f0 += sg * R.n[c];
+        f1 += sg * R.n[L + c];
+        f2 += sg * R.n[2 * L + c];
+        t0 += sg * tau[c];
+        t1 += sg * tau[L + c];
+        t2 += sg * tau[2 * L + c];
+    }
+    const int lb = B.ld;
+    const T *K = B.K;
+    B.vc[i] = K[i] * f0;
+    B.vc[lb + i] = K[lb + i] * f1;
+    B.vc[2 * lb + i] = K[2 * lb + i] * f2;
+    T kxx = K[3 * lb + i], kyy = K[4 * lb + i], kzz = K[5 * lb + i];
+    T kxy = K[6 * lb + i], kxz = K[7 * lb + i], kyz = K[8 * lb + i];
+    B.vc[3 * lb + i] = kxx * t0 + kxy * t1 + kxz * t2;
+    B.vc[4 * lb + i] = kxy * t0 + kyy * t1 + kyz * t2;
+    B.vc[5 * lb + i] = kxz * t0 + kyz * t1 + kzz * t2;
+}
+
+__device__ inline double wave_sum(double v) {
+    for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, RELCP_WAVE);
+    return v;
+}
+__device__ inline double wave_max(double v) {
+    for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, RELCP_WAVE));
+    return v;
+}
+
+// Block reduction of 3 sums and 1 max in a fixed order; result in lane 0
+// of thread 0.
+__device__ inline void block_reduce4(double &a, double &b, double &c, double &mx, double (*sh)[kWaves]) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    mx = wave_max(mx);
+    const int lane = threadIdx.x & (RELCP_WAVE - 1), w = threadIdx.x / RELCP_WAVE;
+    if (lane == 0) {
+        sh[0][w] = a;
+        sh[1][w] = b;
+        sh[2][w] = c;
+        sh[3][w] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = b = c = 0.0;
+        mx = 0.0;
+        for (int k = 0; k < kWaves; ++k) {
+            a += sh[0][k];
+            b += sh[1][k];
+            c += sh[2][k];
+            mx = fmax(mx, sh[3][k]);
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kThreads) k_gather(RowsT<T> R, BodiesT<T> B, double dt, double tol,
+                                                     PgdState *__restrict__ st, double *__restrict__ partials) {
+    if (MODE == 1 && st->conv) return;
+    __shared__ double sh[4][kWaves];
+    __shared__ bool last;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    double ss = 0.0, sy = 0.0, yy = 0.0, res = 0.0;
+    if (c < R.m) {
+        const T al = (T)st->alpha;
+        const int L = R.ld, lb = B.ld;
+        T gm = R.gam[c], gold = R.g[c], dA = R.dA[c];
+        T gv = MODE == 1 ? project(gm, gold, dA, al) : clamp0(gm);
+        int a = R.ia[c], b = R.ib[c];
+        T nx = R.n[c], ny = R.n[L + c], nz = R.n[2 * L + c];
+        const T *V = B.vc;
+        T rate = -(nx * V[a] + ny * V[lb + a] + nz * V[2 * lb + a]) -
+                 (R.ta[c] * V[3 * lb + a] + R.ta[L + c] * V[4 * lb + a] + R.ta[2 * L + c] * V[5 * lb + a]) +
+                 (nx * V[b] + ny * V[lb + b] + nz * V[2 * lb + b]) +
+                 (R.tb[c] * V[3 * lb + b] + R.tb[L + c] * V[4 * lb + b] + R.tb[2 * L + c] * V[5 * lb + b]);
+        T gn = R.qv[c] + (T)dt * rate;
+        T dg = dA * gv;
+        res = fabs((double)(dg < gn ? dg : gn));
+        if (MODE == 1) {
+            double s = (double)gv - (double)gm, y = (double)gn - (double)gold;
+            ss = (double)dA * s * s;
+            sy = s * y;
+            yy = y * y / (double)dA;
+        }
+        R.gam[c] = gv;
+        R.g[c] = gn;
+    }
+    block_reduce4(ss, sy, yy, res, sh);
+    if (threadIdx.x == 0) {
+        double *p = partials + 4 * blockIdx.x;
+        p[0] = ss;
+        p[1] = sy;
+        p[2] = yy;
+        p[3] = res;
+        __threadfence();
+        unsigned t = atomicAdd(&st->ticket, 1u);
+        last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // last block: reduce the per-block partials in a fixed order
+    ss = sy = yy = res = 0.0;
+    for (int k = threadIdx.x; k < (int)gridDim.x; k += kThreads) {
+        const double *p = partials + 4 * k;
+        ss += __builtin_nontemporal_load(p + 0);
+        sy += __builtin_nontemporal_load(p + 1);
+        yy += __builtin_nontemporal_load(p + 2);
+        res = fmax(res, __builtin_nontemporal_load(p + 3));
+    }
+    block_reduce4(ss, sy, yy, res, sh);
+    if (threadIdx.x == 0) {
+        st->ticket = 0;
+        st->res = res;
+        st->ss = ss;
+        st->sy = sy;
+        st->yy = yy;
+        if (MODE == 0) {
+            st->iter = 0;
+            st->alpha = 1.0;
+            st->conv = (res <= tol) ? 1 : 0;
+        } else {
+            int k = st->iter;
+            st->iter = k + 1;
+            if (res <= tol) st->conv = 1;
+            if (sy > 0.0) {
+                double a = (k % 2 == 0) ? ss / sy : sy / yy;
+                st->alpha = a < 1e-10 ? 1e-10 : (a > 1e10 ? 1e10 : a);
+            }
+        }
+    }
+}
+
+__global__ void k_promote(int m, const float *__restrict__ a, double *__restrict__ b) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) b[i] = (double)a[i];
+}
+__global__ void k_demote(int m, const double *__restrict__ a, float *__restrict__ b) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) b[i] = (float)a[i];
+}
+
+__global__ void __launch_bounds__(kThreads) k_work(int m, const double *__restrict__ gam, const double *__restrict__ g,
+                                                   const double *__restrict__ qv, double *__restrict__ partials,
+                                                   unsigned *__restrict__ ticket, double *__restrict__ out) {
+    __shared__ double sh[4][kWaves];
+    __shared__ bool last;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    double w = 0.0, z0 = 0.0, z1 = 0.0, z2 = 0.0;
+    if (c < m) w = gam[c] * (g[c] - qv[c]);
+    block_reduce4(w, z0, z1, z2, sh);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = w;
+        __threadfence();
+        unsigned t = atomicAdd(ticket, 1u);
+        last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    w = 0.0;
+    z0 = z1 = z2 = 0.0;
+    for (int k = threadIdx.x; k < (int)gridDim.x; k += kThreads) w += __builtin_nontemporal_load(partials + k);
+    block_reduce4(w, z0, z1, z2, sh);
+    if (threadIdx.x == 0) {
+        out[0] = w;
+        ticket[0] = 0;
+    }
+}
+
+__global__ void k_pair_lambda(int m, const int *__restrict__ rec, const int *__restrict__ pair,
+                              const double *__restrict__ gam, int level, double *__restrict__ lam) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < m && rec[r] == level) lam[pair[r]] += gam[r];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+int lcp_partials_needed(int m) { return 4 * (nblk(m > 0 ? m : 1, kThreads) + 1); }
+
+void launch_rows_build(const RowBuildArgs &a, hipStream_t s) {
+    if (a.nsel <= 0) return;
+    hipLaunchKernelGGL(k_rows_build, dim3(nblk(a.nsel, 256)), dim3(256), 0, s, a);
+}
+
+void launch_compact(int n, const int *flags, const int *scanned, int *out, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_compact, dim3(nblk(n, 256)), dim3(256), 0, s, n, flags, scanned, out);
+}
+
+void launch_csr(int nb, int m, const int *ia, const int *ib, int *cnt, int *off, int *cursor, int *ent,
+                DBuf<int> &scan_scratch, hipStream_t s) {
+    HIP_OK(hipMemsetAsync(cnt, 0, sizeof(int) * (nb + 1), s));
+    HIP_OK(hipMemsetAsync(cursor, 0, sizeof(int) * (nb + 1), s));
+    if (m > 0) hipLaunchKernelGGL(k_csr_count, dim3(nblk(m, 256)), dim3(256), 0, s, m, ia, ib, cnt);
+    exclusive_scan(cnt, off, nb + 1, nullptr, scan_scratch, s);
+    if (m > 0) {
+        hipLaunchKernelGGL(k_csr_fill, dim3(nblk(m, 256)), dim3(256), 0, s, m, ia, ib, off, cursor, ent);
+        hipLaunchKernelGGL(k_csr_sort, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, off, ent);
+    }
+}
+
+template <typename T>
+void launch_lcp_scatter(int mode, const RowsT<T> &r, const BodiesT<T> &b, const PgdState *st, hipStream_t s) {
+    if (b.nb <= 0) return;
+    if (mode == 0)
+        hipLaunchKernelGGL((k_scatter<T, 0>), dim3(nblk(b.nb, kThreads)), dim3(kThreads), 0, s, r, b, st);
+    else
+        hipLaunchKernelGGL((k_scatter<T, 1>), dim3(nblk(b.nb, kThreads)), dim3(kThreads), 0, s, r, b, st);
+}
+
+template <typename T>
+void launch_lcp_gather(int mode, const RowsT<T> &r, const BodiesT<T> &b, double dt, double tol, PgdState *st,
+                       double *partials, hipStream_t s) {
+    int nbk = nblk(r.m > 0 ? r.m : 1, kThreads);
+    if (mode == 0)
+        hipLaunchKernelGGL((k_gather<T, 0>), dim3(nbk), dim3(kThreads), 0, s, r, b, dt, tol, st, partials);
+    else
+        hipLaunchKernelGGL((k_gather<T, 1>), dim3(nbk), dim3(kThreads), 0, s, r, b, dt, tol, st, partials);
+}
+
+template <typename T>
+void launch_lcp_iteration(int mode, const RowsT<T> &r, const BodiesT<T> &b, double dt, double tol, PgdState *st,
+                          double *partials, hipStream_t s) {
+    launch_lcp_scatter<T>(mode, r, b, st, s);
+    launch_lcp_gather<T>(mode, r, b, dt, tol, st, partials, s);
+}
+
+template void launch_lcp_iteration<double>(int, const RowsT<double> &, const BodiesT<double> &, double, double,
+                                           PgdState *, double *, hipStream_t);
+template void launch_lcp_iteration<float>(int, const RowsT<float> &, const BodiesT<float> &, double, double,
+                                          PgdState *, double *, hipStream_t);
+template void launch_lcp_gather<double>(int, const RowsT<double> &, const BodiesT<double> &, double, double,
+                                        PgdState *, double *, hipStream_t);
+template void launch_lcp_gather<float>(int, const RowsT<float> &, const BodiesT<float> &, double, double, PgdState *,
+                                       double *, hipStream_t);
+template void launch_lcp_scatter<double>(int, const RowsT<double> &, const BodiesT<double> &, const PgdState *,
+                                         hipStream_t);
+template void launch_lcp_scatter<float>(int, const RowsT<float> &, const BodiesT<float> &, const PgdState *,
+                                        hipStream_t);
+
+void launch_promote(int m, const float *g32, double *g64, hipStream_t s) {
+    if (m > 0) hipLaunchKernelGGL(k_promote, dim3(nblk(m, 256)), dim3(256), 0, s, m, g32, g64);
+}
+void launch_demote(int m, const double *g64, float *g32, hipStream_t s) {
+    if (m > 0) hipLaunchKernelGGL(k_demote, dim3(nblk(m, 256)), dim3(256), 0, s, m, g64, g32);
+}
+
+void launch_work(int m, const double *gam, const double *g, const double *qv, double *partials, unsigned *ticket,
+                 double *out, hipStream_t s) {
+    int nbk = nblk(m > 0 ? m : 1, kThreads);
+    hipLaunchKernelGGL(k_work, dim3(nbk), dim3(kThreads), 0, s, m, gam, g, qv, partials, ticket, out);
+}
+
+void launch_pair_lambda(int m, const int *rec, const int *pair, const double *gam, int level, double *lam,
+                        hipStream_t s) {
+    if (m > 0) hipLaunchKernelGGL(k_pair_lambda, dim3(nblk(m, 256)), dim3(256), 0, s, m, rec, pair, gam, level, lam);
+}
+
+}  // namespace relcp

@@ -1,0 +1,1165 @@
+// relcp.hip -- context, step orchestration and the C ABI of librelcp.
+//
+// One call of relcp_step runs Alg. 1 of Palmer, Aktulga, Gao (arXiv
+// 2506.14097) -- or its inertial form, Eq. relcp_inertial -- on the GPU:
+//   candidate pairs at C^k -> SNSD at C^k -> rows of A_0 -> LCP (BB-PGD)
+//   -> trial C_{n+1} = C^k (+) dt V_n -> SNSD at C_{n+1} -> violators
+//   Phi < -eps -> append pulled-back rows -> LCP ... -> accept.
+// The host only launches kernels and reads back a few counters per
+// recursion (pair count, violator count, convergence flag of the LCP).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "../../include/relcp.h"
+#include "geometry.h"
+#include "lcp.h"
+
+using namespace relcp;
+
+namespace {
+
+inline int nblk(long long n, int t) { return (int)((n + t - 1) / t); }
+
+// (re)allocate an SoA buffer of `comps` components with leading dimension
+// new_ld, keeping the first `keep` items of each component
+template <typename T>
+void realloc_soa(DBuf<T> &b, int comps, size_t old_ld, size_t new_ld, size_t keep, hipStream_t s) {
+    T *np_ = nullptr;
+    if (hipMalloc(&np_, std::max<size_t>(1, new_ld * comps) * sizeof(T)) != hipSuccess)
+        throw Error{RELCP_E_OOM, "device allocation failed"};
+    if (b.p && keep) {
+        for (int k = 0; k < comps; ++k)
+            HIP_OK(hipMemcpyAsync(np_ + k * new_ld, b.p + k * old_ld, keep * sizeof(T), hipMemcpyDeviceToDevice, s));
+        HIP_OK(hipStreamSynchronize(s));
+    }
+    if (b.p) HIP_OK(hipFree(b.p));
+    b.p = np_;
+    b.cap = new_ld * comps;
+}
+
+__global__ void k_bbox(int nb, const double *__restrict__ x, int ldx, const int *__restrict__ body_batch,
+                       unsigned long long *__restrict__ keys) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    int pk = body_batch ? body_batch[i] : 0;
+    for (int k = 0; k < 3; ++k) {
+        double v = x[k * ldx + i];
+        unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        unsigned long long key = (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+        atomicMin(keys + 6 * pk + k, key);
+        atomicMax(keys + 6 * pk + 3 + k, key);
+    }
+}
+
+__global__ void k_aos_to_soa(int n, int comps, const double *__restrict__ in, double *__restrict__ out, int ld) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < comps; ++k) out[k * ld + i] = in[(size_t)comps * i + k];
+}
+__global__ void k_soa_to_aos(int n, int comps, const double *__restrict__ in, int ld, int c0, double *__restrict__ out,
+                             int ocomps) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < ocomps; ++k) out[(size_t)ocomps * i + k] = in[(c0 + k) * ld + i];
+}
+__global__ void k_scale(int n, double *__restrict__ x, double s) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] *= s;
+}
+
+struct Timer {
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    double ms() {
+        auto now = std::chrono::steady_clock::now();
+        double v = std::chrono::duration<double, std::milli>(now - t).count();
+        t = now;
+        return v;
+    }
+};
+
+}  // namespace
+
+// ===========================================================================
+// context
+// ===========================================================================
+struct relcp_ctx {
+    // configuration
+    int n = 0, nbatch = 1;
+    int dynamics = 0, precision = 64, warm_start = 1, planar = 0, max_rec = 64, lcp_max_iters = 100000,
+        lcp_fixed = 0;
+    double skin = 0.05;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    std::vector<int> boff;      // nbatch + 1
+    std::vector<double> box;    // 3 nbatch
+    std::vector<double> rmax;   // nbatch
+    bool has_fext = false;
+
+    // bodies (SoA, ld = n)
+    DBuf<double> x, q, u, p, rho, fext, xt, qt, geo, geot, Rb, K, vfree, vc64, vout, boxes;
+    DBuf<float> K32, vc32;
+    DBuf<int> kind, body_batch;
+
+    // broadphase
+    DBuf<PackGrid> grids;
+    DBuf<int> body_cell, cell_count, cell_start, cell_cursor, cell_items, pair_count, pair_off;
+    DBuf<unsigned long long> keys;
+    std::vector<PackGrid> grids_h;
+
+    // pairs (ld = ldp)
+    int np = 0, ldp = 0;
+    DBuf<int> pa, pb, pflag, pscan, sel;
+    DBuf<double> snsd0, snsdt, lam;
+    // previous step (warm start): sorted pairs and multiplier sums
+    int nprev = 0, ldprev = 0;
+    DBuf<int> prev_a, prev_b;
+    DBuf<double> prev_lam;
+
+    // rows (ld = ldr)
+    int m = 0, ldr = 0, m_acc = 0;
+    DBuf<int> ria, rib, rpair, rrec;
+    DBuf<double> rn64, rta64, rtb64, rqv64, rdA64, rgam64, rg64, rphi64;
+    DBuf<float> rn32, rta32, rtb32, rqv32, rdA32, rgam32, rg32;
+    DBuf<int> csr_cnt, csr_off, csr_cur, csr_ent;
+
+    // LCP state and reductions
+    DBuf<PgdState> pst;
+    DBuf<double> partials, work_out;
+    DBuf<unsigned> ticket;
+    DBuf<unsigned long long> red;  // [0] max displacement bits, [1] min Phi key, [2] min margin key
+    DBuf<int> scan_scratch, dtotal;
+    // optional kernel timing (HIP events on the stream)
+    static constexpr int kClasses = 5;
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_class;
+    size_t ev_used = 0;
+    long long t_count[kClasses] = {0, 0, 0, 0, 0};
+    double t_ms[kClasses] = {0, 0, 0, 0, 0};
+    // record a start/stop event pair around launch `f` when timing is on
+    template <typename F>
+    void timed(int cls, F &&f) {
+        if (!timing) {
+            f();
+            return;
+        }
+        if (ev_used + 2 > ev_pool.size()) {
+            for (int k = 0; k < 256; ++k) {
+                hipEvent_t e;
+                HIP_OK(hipEventCreate(&e));
+                ev_pool.push_back(e);
+            }
+            ev_class.resize(ev_pool.size() / 2);
+        }
+        HIP_OK(hipEventRecord(ev_pool[ev_used], stream));
+        f();
+        HIP_OK(hipEventRecord(ev_pool[ev_used + 1], stream));
+        ev_class[ev_used / 2] = cls;
+        ev_used += 2;
+    }
+    // fold the recorded pairs into the totals (stream must be idle)
+    void collect_timing() {
+        for (size_t k = 0; k + 1 < ev_used; k += 2) {
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, ev_pool[k], ev_pool[k + 1]));
+            int c = ev_class[k / 2];
+            t_count[c] += 1;
+            t_ms[c] += ms;
+        }
+        ev_used = 0;
+    }
+
+    // pinned host mirrors
+    PgdState *pst_h = nullptr;
+    int *int_h = nullptr;
+    unsigned long long *red_h = nullptr;
+    double *dbl_h = nullptr;
+
+    ~relcp_ctx() {
+        DBuf<double> *ds[] = {&x, &q, &u, &p, &rho, &fext, &xt, &qt, &geo, &geot, &Rb, &K, &vfree, &vc64, &vout,
+                              &boxes, &snsd0, &snsdt, &lam, &prev_lam, &rn64, &rta64, &rtb64, &rqv64, &rdA64,
+                              &rgam64, &rg64, &rphi64, &partials, &work_out};
+        for (auto *b : ds) b->release();
+        DBuf<float> *fs[] = {&K32, &vc32, &rn32, &rta32, &rtb32, &rqv32, &rdA32, &rgam32, &rg32};
+        for (auto *b : fs) b->release();
+        DBuf<int> *is[] = {&kind, &body_batch, &body_cell, &cell_count, &cell_start, &cell_cursor, &cell_items,
+                           &pair_count, &pair_off, &pa, &pb, &pflag, &pscan, &sel, &prev_a, &prev_b, &ria, &rib,
+                           &rpair, &rrec, &csr_cnt, &csr_off, &csr_cur, &csr_ent, &scan_scratch, &dtotal};
+        for (auto *b : is) b->release();
+        grids.release();
+        keys.release();
+        pst.release();
+        ticket.release();
+        red.release();
+        if (pst_h) (void)hipHostFree(pst_h);
+        if (int_h) (void)hipHostFree(int_h);
+        if (red_h) (void)hipHostFree(red_h);
+        if (dbl_h) (void)hipHostFree(dbl_h);
+        for (auto e : ev_pool) (void)hipEventDestroy(e);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+
+    // ---------------------------------------------------------------------
+    void upload_bodies(const relcp_bodies *B, const relcp_shapes *S);
+    void ensure_pairs(int need);
+    void ensure_rows(int need);
+    void broadphase(const double *xs, double skin_);
+    void build_rows(int nsel, int rec, const double *snsd, const double *vc, bool warm, double dt);
+    void rebuild_csr();
+    template <typename T>
+    int solve(double dt, double tol, int &iters, double &res);
+    int step(double dt, double eps, double tol, relcp_step_stats *st);
+    void sync() { HIP_OK(hipStreamSynchronize(stream)); }
+};
+
+// ---------------------------------------------------------------------------
+// validation and upload
+// ---------------------------------------------------------------------------
+static void validate(const relcp_bodies *B, const relcp_shapes *S, const relcp_params *P, double skin) {
+    if (!B || !S || !B->x || !B->q || !S->kind || !S->p || !S->rho_or_xi) throw Error{RELCP_E_INVALID, "null input"};
+    if (B->n <= 0) throw Error{RELCP_E_INVALID, "need at least one body"};
+    int nbt = B->n_batch <= 0 ? 1 : B->n_batch;
+    if (nbt > 1 && !B->batch_off) throw Error{RELCP_E_INVALID, "batch_off required for n_batch > 1"};
+    if (B->batch_off) {
+        if (B->batch_off[0] != 0 || B->batch_off[nbt] != B->n) throw Error{RELCP_E_INVALID, "bad batch offsets"};
+        for (int k = 0; k < nbt; ++k)
+            if (B->batch_off[k + 1] <= B->batch_off[k]) throw Error{RELCP_E_INVALID, "empty or unordered packing"};
+    }
+    for (int i = 0; i < B->n; ++i) {
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(B->x[3 * i + k])) throw Error{RELCP_E_INVALID, "non-finite position"};
+        double qn = 0;
+        for (int k = 0; k < 4; ++k) {
+            if (!std::isfinite(B->q[4 * i + k])) throw Error{RELCP_E_INVALID, "non-finite quaternion"};
+            qn += B->q[4 * i + k] * B->q[4 * i + k];
+        }
+        if (std::fabs(std::sqrt(qn) - 1.0) > 1e-10) throw Error{RELCP_E_INVALID, "quaternion not of unit norm"};
+        int kd = S->kind[i];
+        const double *pp = S->p + 3 * i;
+        if (kd == RELCP_ELLIPSOID) {
+            if (!(pp[0] > 0 && pp[1] > 0 && pp[2] > 0)) throw Error{RELCP_E_INVALID, "semiaxes must be positive"};
+        } else if (kd == RELCP_SPHEROCYLINDER) {
+            if (!(pp[0] > 0 && pp[1] >= 0)) throw Error{RELCP_E_INVALID, "bad spherocylinder radius or length"};
+            if (P && P->dynamics == RELCP_INERTIAL)
+                throw Error{RELCP_E_INVALID, "inertial dynamics needs ellipsoids (mass properties)"};
+        } else {
+            throw Error{RELCP_E_INVALID, "unknown shape kind"};
+        }
+        if (!(S->rho_or_xi[i] > 0) || !std::isfinite(S->rho_or_xi[i]))
+            throw Error{RELCP_E_INVALID, "density / drag must be positive"};
+        if (B->u)
+            for (int k = 0; k < 3; ++k)
+                if (!std::isfinite(B->u[3 * i + k])) throw Error{RELCP_E_INVALID, "non-finite velocity"};
+        if (B->w)
+            for (int k = 0; k < 3; ++k)
+                if (!std::isfinite(B->w[3 * i + k])) throw Error{RELCP_E_INVALID, "non-finite angular velocity"};
+    }
+    for (int pk = 0; pk < nbt; ++pk) {
+        int b0 = B->batch_off ? B->batch_off[pk] : 0, b1 = B->batch_off ? B->batch_off[pk + 1] : B->n;
+        double R = 0;
+        for (int i = b0; i < b1; ++i) {
+            if (S->kind[i] != S->kind[b0]) throw Error{RELCP_E_INVALID, "one shape kind per packing"};
+            const double *pp = S->p + 3 * i;
+            R = std::max(R, S->kind[i] == 0 ? std::max(pp[0], std::max(pp[1], pp[2])) : 0.5 * pp[1] + pp[0]);
+        }
+        for (int k = 0; k < 3; ++k) {
+            double L = B->box ? B->box[3 * pk + k] : 0.0;
+            if (!(L >= 0) || !std::isfinite(L)) throw Error{RELCP_E_INVALID, "bad box"};
+            if (L > 0 && L < 2.0 * (R + skin))
+                throw Error{RELCP_E_INVALID, "periodic box smaller than 2 (R_max + skin)"};
+        }
+    }
+}
+
+void relcp_ctx::upload_bodies(const relcp_bodies *B, const relcp_shapes *S) {
+    n = B->n;
+    nbatch = B->n_batch <= 0 ? 1 : B->n_batch;
+    boff.assign(nbatch + 1, 0);
+    for (int k = 0; k <= nbatch; ++k) boff[k] = B->batch_off ? B->batch_off[k] : (k ? n : 0);
+    box.assign(3 * nbatch, 0.0);
+    if (B->box)
+        for (int k = 0; k < 3 * nbatch; ++k) box[k] = B->box[k];
+    rmax.assign(nbatch, 0.0);
+    std::vector<int> bb(n);
+    for (int pk = 0; pk < nbatch; ++pk)
+        for (int i = boff[pk]; i < boff[pk + 1]; ++i) {
+            bb[i] = pk;
+            const double *pp = S->p + 3 * i;
+            double R = S->kind[i] == 0 ? std::max(pp[0], std::max(pp[1], pp[2])) : 0.5 * pp[1] + pp[0];
+            rmax[pk] = std::max(rmax[pk], R);
+        }
+    size_t N = (size_t)n;
+    auto alloc = [&](auto &b, int comps) {
+        b.release();
+        b.ensure(N * comps);
+        b.cap = N * comps;  // ld = n exactly
+    };
+    alloc(x, 3); alloc(q, 4); alloc(u, 6); alloc(p, 3); alloc(rho, 1); alloc(fext, 6); alloc(xt, 3); alloc(qt, 4);
+    alloc(geo, 6); alloc(geot, 6); alloc(Rb, 1); alloc(K, 9); alloc(vfree, 6); alloc(vc64, 6); alloc(vout, 6);
+    alloc(K32, 9); alloc(vc32, 6); alloc(kind, 1); alloc(body_batch, 1);
+    // host transposes to SoA
+    std::vector<double> t(6 * N, 0.0);
+    auto up = [&](DBuf<double> &dst, const double *src, int comps, int c0, int stride) {
+        for (size_t i = 0; i < N; ++i)
+            for (int k = 0; k < comps; ++k) t[(c0 + k) * N + i] = src ? src[stride * i + k] : 0.0;
+        (void)dst;
+    };
+    up(x, B->x, 3, 0, 3);
+    HIP_OK(hipMemcpyAsync(x.p, t.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, stream));
+    sync();
+    up(q, B->q, 4, 0, 4);
+    HIP_OK(hipMemcpyAsync(q.p, t.data(), 4 * N * sizeof(double), hipMemcpyHostToDevice, stream));
+    sync();
+    up(u, B->u, 3, 0, 3);
+    up(u, B->w, 3, 3, 3);
+    HIP_OK(hipMemcpyAsync(u.p, t.data(), 6 * N * sizeof(double), hipMemcpyHostToDevice, stream));
+    HIP_OK(hipMemcpyAsync(vout.p, t.data(), 6 * N * sizeof(double), hipMemcpyHostToDevice, stream));
+    sync();
+    up(p, S->p, 3, 0, 3);
+    HIP_OK(hipMemcpyAsync(p.p, t.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, stream));
+    sync();
+    HIP_OK(hipMemcpyAsync(rho.p, S->rho_or_xi, N * sizeof(double), hipMemcpyHostToDevice, stream));
+    HIP_OK(hipMemcpyAsync(kind.p, S->kind, N * sizeof(int), hipMemcpyHostToDevice, stream));
+    HIP_OK(hipMemcpyAsync(body_batch.p, bb.data(), N * sizeof(int), hipMemcpyHostToDevice, stream));
+    boxes.ensure(3 * nbatch);
+    HIP_OK(hipMemcpyAsync(boxes.p, box.data(), 3 * nbatch * sizeof(double), hipMemcpyHostToDevice, stream));
+    HIP_OK(hipMemsetAsync(fext.p, 0, 6 * N * sizeof(double), stream));
+    has_fext = false;
+    nprev = 0;
+    m = 0;
+    m_acc = 0;
+    sync();
+}
+
+void relcp_ctx::ensure_pairs(int need) {
+    if (need <= ldp) return;
+    size_t nld = std::max<size_t>((size_t)need + need / 4 + 1024, 2 * (size_t)ldp);
+    pa.release(); pb.release(); pflag.release(); pscan.release(); sel.release();
+    snsd0.release(); snsdt.release(); lam.release();
+    pa.ensure(nld); pb.ensure(nld); pflag.ensure(nld + 1); pscan.ensure(nld + 1); sel.ensure(nld);
+    snsd0.ensure(10 * nld); snsdt.ensure(10 * nld); lam.ensure(nld);
+    ldp = (int)nld;
+}
+
+void relcp_ctx::ensure_rows(int need) {
+    if (need <= ldr) return;
+    size_t old = ldr, nld = std::max<size_t>((size_t)need + need / 2 + 1024, 2 * (size_t)ldr);
+    realloc_soa(ria, 1, old, nld, m, stream);
+    realloc_soa(rib, 1, old, nld, m, stream);
+    realloc_soa(rpair, 1, old, nld, m, stream);
+    realloc_soa(rrec, 1, old, nld, m, stream);
+    realloc_soa(rn64, 3, old, nld, m, stream);
+    realloc_soa(rta64, 3, old, nld, m, stream);
+    realloc_soa(rtb64, 3, old, nld, m, stream);
+    realloc_soa(rqv64, 1, old, nld, m, stream);
+    realloc_soa(rdA64, 1, old, nld, m, stream);
+    realloc_soa(rgam64, 1, old, nld, m, stream);
+    realloc_soa(rg64, 1, old, nld, m, stream);
+    realloc_soa(rphi64, 1, old, nld, m, stream);
+    realloc_soa(rn32, 3, old, nld, m, stream);
+    realloc_soa(rta32, 3, old, nld, m, stream);
+    realloc_soa(rtb32, 3, old, nld, m, stream);
+    realloc_soa(rqv32, 1, old, nld, m, stream);
+    realloc_soa(rdA32, 1, old, nld, m, stream);
+    realloc_soa(rgam32, 1, old, nld, m, stream);
+    realloc_soa(rg32, 1, old, nld, m, stream);
+    csr_ent.release();
+    csr_ent.ensure(2 * nld);
+    ldr = (int)nld;
+}
+
+// ---------------------------------------------------------------------------
+// candidate pairs (all a < b of one packing with bounding gap <= skin)
+// ---------------------------------------------------------------------------
+void relcp_ctx::broadphase(const double *xs, double skin_) {
+    const int N = n;
+    keys.ensure(6 * nbatch + 1);
+    bool any_open = false;
+    for (int pk = 0; pk < nbatch; ++pk)
+        for (int k = 0; k < 3; ++k) any_open |= !(box[3 * pk + k] > 0);
+    std::vector<unsigned long long> kh(6 * nbatch);
+    if (any_open) {
+        std::vector<unsigned long long> init(6 * nbatch);
+        for (int pk = 0; pk < nbatch; ++pk)
+            for (int k = 0; k < 3; ++k) {
+                init[6 * pk + k] = ~0ull;
+                init[6 * pk + 3 + k] = 0ull;
+            }
+        HIP_OK(hipMemcpyAsync(keys.p, init.data(), 6 * nbatch * sizeof(unsigned long long), hipMemcpyHostToDevice,
+                              stream));
+        hipLaunchKernelGGL(k_bbox, dim3(nblk(N, 256)), dim3(256), 0, stream, N, xs, N, body_batch.p, keys.p);
+        HIP_OK(hipMemcpyAsync(kh.data(), keys.p, 6 * nbatch * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                              stream));
+        sync();
+    }
+    grids_h.resize(nbatch);
+    long long total = 0;
+    for (int pk = 0; pk < nbatch; ++pk) {
+        PackGrid &g = grids_h[pk];
+        double csmin = 2.0 * rmax[pk] + skin_;
+        int nbody = boff[pk + 1] - boff[pk];
+        long long cap_cells = std::max<long long>(64, 8LL * nbody);
+        for (int k = 0; k < 3; ++k) {
+            double L = box[3 * pk + k];
+            g.box[k] = L;
+            if (L > 0) {
+                g.periodic[k] = 1;
+                g.nc[k] = std::max(1, (int)std::floor(L / csmin));
+                g.cs[k] = L / g.nc[k];
+                g.org[k] = 0.0;
+            } else {
+                g.periodic[k] = 0;
+                double lo = order_key_value(kh[6 * pk + k]), hi = order_key_value(kh[6 * pk + 3 + k]);
+                double ext = std::max(0.0, hi - lo);
+                g.org[k] = lo;
+                g.cs[k] = csmin;
+                g.nc[k] = std::max(1, (int)std::ceil(ext / csmin + 1e-9));
+            }
+        }
+        // keep the cell count bounded for sparse open domains
+        while ((long long)g.nc[0] * g.nc[1] * g.nc[2] > cap_cells) {
+            for (int k = 0; k < 3; ++k)
+                if (!g.periodic[k] && g.nc[k] > 1) {
+                    g.cs[k] *= 2.0;
+                    g.nc[k] = std::max(1, (g.nc[k] + 1) / 2);
+                }
+            bool shrinkable = false;
+            for (int k = 0; k < 3; ++k) shrinkable |= (!g.periodic[k] && g.nc[k] > 1);
+            if (!shrinkable) break;
+        }
+        g.cell_off = total;
+        total += (long long)g.nc[0] * g.nc[1] * g.nc[2];
+    }
+    if (total > (1LL << 30)) throw Error{RELCP_E_CAPACITY, "too many broadphase cells"};
+    int nc = (int)total;
+    grids.ensure(nbatch);
+    HIP_OK(hipMemcpyAsync(grids.p, grids_h.data(), nbatch * sizeof(PackGrid), hipMemcpyHostToDevice, stream));
+    body_cell.ensure(N);
+    cell_count.ensure(nc + 1);
+    cell_start.ensure(nc + 1);
+    cell_cursor.ensure(nc + 1);
+    cell_items.ensure(N);
+    pair_count.ensure(N + 1);
+    pair_off.ensure(N + 1);
+    dtotal.ensure(4);
+    HIP_OK(hipMemsetAsync(cell_count.p, 0, (nc + 1) * sizeof(int), stream));
+    HIP_OK(hipMemsetAsync(cell_cursor.p, 0, (nc + 1) * sizeof(int), stream));
+    launch_cell_assign(N, xs, N, body_batch.p, grids.p, body_cell.p, cell_count.p, stream);
+    exclusive_scan(cell_count.p, cell_start.p, nc, nullptr, scan_scratch, stream);
+    launch_cell_fill(N, body_cell.p, cell_start.p, cell_cursor.p, cell_items.p, stream);
+    timed(3, [&] {
+        launch_pairs(false, N, xs, N, Rb.p, body_batch.p, grids.p, body_cell.p, cell_start.p, cell_count.p,
+                     cell_items.p, skin_, pair_count.p, nullptr, nullptr, nullptr, 0, stream);
+    });
+    exclusive_scan(pair_count.p, pair_off.p, N, dtotal.p, scan_scratch, stream);
+    HIP_OK(hipMemcpyAsync(int_h, dtotal.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+    sync();
+    np = int_h[0];
+    if (np < 0) throw Error{RELCP_E_CAPACITY, "pair count overflow"};
+    ensure_pairs(std::max(np, 1));
+    timed(3, [&] {
+        launch_pairs(true, N, xs, N, Rb.p, body_batch.p, grids.p, body_cell.p, cell_start.p, cell_count.p,
+                     cell_items.p, skin_, pair_count.p, pair_off.p, pa.p, pb.p, ldp, stream);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// rows and incidence
+// ---------------------------------------------------------------------------
+void relcp_ctx::build_rows(int nsel, int rec, const double *snsd, const double *vc, bool warm, double dt) {
+    RowBuildArgs a{};
+    a.nsel = nsel;
+    a.sel = sel.p;
+    a.pa = pa.p;
+    a.pb = pb.p;
+    a.snsd = snsd;
+    a.ldp = ldp;
+    a.m0 = m;
+    a.rec = rec;
+    a.dt = dt;
+    a.K = K.p;
+    a.vfree = vfree.p;
+    a.vc = vc;
+    a.ldb = n;
+    a.nprev = warm ? nprev : 0;
+    a.prev_a = prev_a.p;
+    a.prev_b = prev_b.p;
+    a.prev_lam = warm ? prev_lam.p : nullptr;
+    a.ldr = ldr;
+    a.ia = ria.p; a.ib = rib.p; a.pair = rpair.p; a.rec_out = rrec.p;
+    a.n64 = rn64.p; a.ta64 = rta64.p; a.tb64 = rtb64.p; a.qv64 = rqv64.p; a.dA64 = rdA64.p; a.gam64 = rgam64.p;
+    a.phi64 = rphi64.p;
+    a.n32 = rn32.p; a.ta32 = rta32.p; a.tb32 = rtb32.p; a.qv32 = rqv32.p; a.dA32 = rdA32.p; a.gam32 = rgam32.p;
+    launch_rows_build(a, stream);
+    m += nsel;
+}
+
+void relcp_ctx::rebuild_csr() {
+    csr_cnt.ensure(n + 1);
+    csr_off.ensure(n + 1);
+    csr_cur.ensure(n + 1);
+    csr_ent.ensure(2 * (size_t)std::max(m, 1));
+    launch_csr(n, m, ria.p, rib.p, csr_cnt.p, csr_off.p, csr_cur.p, csr_ent.p, scan_scratch, stream);
+}
+
+// ---------------------------------------------------------------------------
+// LCP of one recursion
+// ---------------------------------------------------------------------------
+template <typename T>
+int relcp_ctx::solve(double dt, double tol, int &iters, double &res) {
+    RowsT<T> R{};
+    BodiesT<T> Bd{};
+    R.m = m;
+    R.ld = ldr;
+    R.ia = ria.p;
+    R.ib = rib.p;
+    if constexpr (sizeof(T) == 8) {
+        R.n = rn64.p; R.ta = rta64.p; R.tb = rtb64.p; R.qv = rqv64.p; R.dA = rdA64.p; R.gam = rgam64.p; R.g = rg64.p;
+        Bd.K = K.p; Bd.vc = vc64.p;
+    } else {
+        R.n = rn32.p; R.ta = rta32.p; R.tb = rtb32.p; R.qv = rqv32.p; R.dA = rdA32.p; R.gam = rgam32.p; R.g = rg32.p;
+        Bd.K = K32.p; Bd.vc = vc32.p;
+    }
+    Bd.nb = n;
+    Bd.ld = n;
+    Bd.off = csr_off.p;
+    Bd.ent = csr_ent.p;
+    partials.ensure(lcp_partials_needed(m));
+    pst.ensure(1);
+    HIP_OK(hipMemsetAsync(pst.p, 0, sizeof(PgdState), stream));
+    const double tol_run = lcp_fixed > 0 ? -1.0 : tol;
+    const int cap = lcp_fixed > 0 ? lcp_fixed : lcp_max_iters;
+    timed(0, [&] { launch_lcp_scatter<T>(0, R, Bd, pst.p, stream); });
+    timed(1, [&] { launch_lcp_gather<T>(0, R, Bd, dt, tol_run, pst.p, partials.p, stream); });
+    HIP_OK(hipMemcpyAsync(pst_h, pst.p, sizeof(PgdState), hipMemcpyDeviceToHost, stream));
+    sync();
+    int chunk = 8;
+    while (!pst_h->conv && pst_h->iter < cap) {
+        int k = std::min(chunk, cap - pst_h->iter);
+        for (int j = 0; j < k; ++j) {
+            timed(0, [&] { launch_lcp_scatter<T>(1, R, Bd, pst.p, stream); });
+            timed(1, [&] { launch_lcp_gather<T>(1, R, Bd, dt, tol_run, pst.p, partials.p, stream); });
+        }
+        HIP_OK(hipMemcpyAsync(pst_h, pst.p, sizeof(PgdState), hipMemcpyDeviceToHost, stream));
+        sync();
+        chunk = std::min(64, chunk * 2);
+    }
+    iters = pst_h->iter;
+    res = pst_h->res;
+    if (!std::isfinite(res)) return RELCP_E_NAN;
+    if (lcp_fixed > 0) return RELCP_OK;
+    return pst_h->conv ? RELCP_OK : RELCP_E_LCP_MAXITER;
+}
+
+// ---------------------------------------------------------------------------
+// one time-step (Alg. 1 / Eq. relcp_inertial)
+// ---------------------------------------------------------------------------
+int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
+    relcp_step_stats S;
+    std::memset(&S, 0, sizeof(S));
+    Timer tm;
+    double t_narrow = 0, t_lcp = 0, t_other = 0;
+    const int N = n;
+
+    // set-up at C^k: geometry, K, U_free
+    BodySetupArgs ba{};
+    ba.nb = N; ba.q = q.p; ba.ldq = N; ba.kind = kind.p; ba.p = p.p; ba.ldp = N; ba.rho_xi = rho.p;
+    ba.u = u.p; ba.ldu = N; ba.fext = has_fext ? fext.p : nullptr; ba.ldf = N;
+    ba.dynamics = dynamics; ba.planar = planar; ba.dt = dt;
+    ba.geo = geo.p; ba.ldg = N; ba.Rb = Rb.p; ba.K = K.p; ba.ldk = N; ba.K32 = K32.p; ba.vfree = vfree.p; ba.ldv = N;
+    launch_body_setup(ba, stream);
+
+    // candidate pairs at C^k
+    broadphase(x.p, skin);
+    S.n_pairs = np;
+    t_other += tm.ms();
+
+    // SNSD at C^k, iteration-0 set A_0 = {Phi_0 <= skin}
+    red.ensure(4);
+    SnsdArgs sa{};
+    sa.m = np; sa.pa = pa.p; sa.pb = pb.p; sa.body_batch = body_batch.p; sa.x = x.p; sa.ldx = N; sa.geo = geo.p;
+    sa.ldg = N; sa.kind = kind.p; sa.p = p.p; sa.ldp = N; sa.boxes = boxes.p; sa.planar = planar; sa.hint = nullptr;
+    sa.out = snsd0.p; sa.ldo = ldp; sa.mode = 0; sa.thresh = skin; sa.eps = eps; sa.flag = pflag.p;
+    sa.minphi = nullptr; sa.minmarg = nullptr;
+    timed(2, [&] { launch_snsd_pairs(sa, stream); });
+    exclusive_scan(pflag.p, pscan.p, np, dtotal.p, scan_scratch, stream);
+    launch_compact(np, pflag.p, pscan.p, sel.p, stream);
+    HIP_OK(hipMemcpyAsync(int_h, dtotal.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+    sync();
+    int m0 = np > 0 ? int_h[0] : 0;
+    t_narrow += tm.ms();
+    m = 0;
+    ensure_rows(m0);
+    build_rows(m0, 0, snsd0.p, nullptr, warm_start == RELCP_WS_PREV, dt);
+    rebuild_csr();
+    t_other += tm.ms();
+
+    int status = RELCP_OK;
+    int rec = 0;
+    int iters_total = 0;
+    double minphi = 0.0;
+    for (;; ++rec) {
+        // LCP of recursion rec
+        int it = 0, it64 = 0;
+        double res = 0, res64 = 0;
+        if (precision == 32) {
+            launch_demote(m, rgam64.p, rgam32.p, stream);
+            status = solve<float>(dt, tol, it, res);
+            if (status == RELCP_OK || status == RELCP_E_LCP_MAXITER) {
+                // FP64 residual of the FP32 iterate, polished in FP64 if needed
+                launch_promote(m, rgam32.p, rgam64.p, stream);
+                status = solve<double>(dt, tol, it64, res64);
+            }
+        } else {
+            status = solve<double>(dt, tol, it, res64);
+            res = res64;
+        }
+        iters_total += it + it64;
+        if (rec < RELCP_MAX_RECORDED) {
+            S.n_contacts[rec] = m;
+            S.lcp_iters[rec] = it + it64;
+            S.lcp_iters64[rec] = precision == 32 ? it64 : it;
+        }
+        S.residual_fp64 = res64;
+        S.residual_lowp = res;
+        if (status != RELCP_OK) break;
+        // W_n = gamma^T A gamma
+        work_out.ensure(1);
+        ticket.ensure(1);
+        HIP_OK(hipMemsetAsync(ticket.p, 0, sizeof(unsigned), stream));
+        launch_work(m, rgam64.p, rg64.p, rqv64.p, partials.p, ticket.p, work_out.p, stream);
+        t_lcp += tm.ms();
+
+        // trial configuration C_{n+1} = C^k (+) dt V_n
+        unsigned long long init[3] = {0ull, ~0ull, ~0ull};
+        HIP_OK(hipMemcpyAsync(red.p, init, sizeof(init), hipMemcpyHostToDevice, stream));
+        timed(4, [&] {
+            launch_trial(N, x.p, N, q.p, N, vfree.p, vc64.p, N, dt, kind.p, p.p, N, Rb.p, xt.p, qt.p, geot.p, N,
+                         vout.p, red.p, stream);
+        });
+        // SNSD of every candidate pair at the trial configuration
+        SnsdArgs sb = sa;
+        sb.x = xt.p; sb.geo = geot.p; sb.hint = snsd0.p + ldp; sb.out = snsdt.p; sb.mode = 1; sb.flag = pflag.p;
+        sb.minphi = red.p + 1; sb.minmarg = red.p + 2;
+        timed(2, [&] { launch_snsd_pairs(sb, stream); });
+        exclusive_scan(pflag.p, pscan.p, np, dtotal.p, scan_scratch, stream);
+        launch_compact(np, pflag.p, pscan.p, sel.p, stream);
+        HIP_OK(hipMemcpyAsync(red_h, red.p, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipMemcpyAsync(int_h, dtotal.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipMemcpyAsync(dbl_h, work_out.p, sizeof(double), hipMemcpyDeviceToHost, stream));
+        sync();
+        t_narrow += tm.ms();
+        int nv = np > 0 ? int_h[0] : 0;
+        double maxdisp;
+        {
+            unsigned long long b = red_h[0];
+            std::memcpy(&maxdisp, &b, sizeof(double));
+        }
+        minphi = np > 0 ? order_key_value(red_h[1]) : 0.0;
+        if (rec < RELCP_MAX_RECORDED) {
+            S.W[rec] = dbl_h[0];
+            S.margin[rec] = np > 0 ? order_key_value(red_h[2]) : 0.0;
+        }
+        S.max_disp = maxdisp;
+        if (!std::isfinite(maxdisp) || !std::isfinite(dbl_h[0])) {
+            status = RELCP_E_NAN;
+            break;
+        }
+        if (maxdisp > 0.5 * skin) {
+            status = RELCP_E_SKIN;
+            break;
+        }
+        if (nv == 0) break;
+        if (rec >= max_rec) {
+            if (max_rec == 0) break;  // plain SNSD LCP: accept the first trial
+            status = RELCP_E_RECURSION_CAP;
+            break;
+        }
+        // augment: rows generated at C_{n+1}, pulled back (per-row constant)
+        ensure_rows(m + nv);
+        build_rows(nv, rec + 1, snsdt.p, vc64.p, false, dt);
+        rebuild_csr();
+        t_other += tm.ms();
+    }
+    S.recursions = rec;
+    S.lcp_iters_total = iters_total;
+    S.n_contacts_final = m;
+    if (status == RELCP_OK) {
+        S.max_overlap = minphi < 0 ? -minphi : 0.0;
+        // accept: C^{k+1} = C_{n+1}; U^{k+1} = V_n
+        std::swap(x.p, xt.p);
+        std::swap(q.p, qt.p);
+        std::swap(u.p, vout.p);
+        HIP_OK(hipMemcpyAsync(vout.p, u.p, 6 * (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        // multiplier sum per pair, for the next warm start
+        HIP_OK(hipMemsetAsync(lam.p, 0, std::max(np, 1) * sizeof(double), stream));
+        for (int lv = 0; lv <= rec; ++lv) launch_pair_lambda(m, rrec.p, rpair.p, rgam64.p, lv, lam.p, stream);
+        std::swap(prev_a.p, pa.p);
+        std::swap(prev_a.cap, pa.cap);
+        std::swap(prev_b.p, pb.p);
+        std::swap(prev_b.cap, pb.cap);
+        std::swap(prev_lam.p, lam.p);
+        std::swap(prev_lam.cap, lam.cap);
+        // keep pair-buffer capacities consistent with ldp
+        if ((int)pa.cap < ldp || (int)pb.cap < ldp || (int)lam.cap < ldp) {
+            pa.release(); pb.release(); lam.release();
+            pa.ensure(ldp); pb.ensure(ldp); lam.ensure(ldp);
+        }
+        nprev = np;
+        m_acc = m;
+        sync();
+    }
+    if (timing) {
+        sync();
+        collect_timing();
+    }
+    t_other += tm.ms();
+    S.t_narrow = t_narrow;
+    S.t_lcp = t_lcp;
+    S.t_other = t_other;
+    if (st) *st = S;
+    return status;
+}
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+template <typename F>
+static int guarded(relcp_ctx *ctx, F &&f) {
+    try {
+        return f();
+    } catch (const Error &e) {
+        if (ctx) ctx->err = e.msg;
+        return e.code;
+    } catch (const std::exception &e) {
+        if (ctx) ctx->err = e.what();
+        return RELCP_E_DEVICE;
+    }
+}
+
+extern "C" {
+
+int relcp_create(const relcp_bodies *bodies, const relcp_shapes *shapes, const relcp_params *params,
+                 relcp_ctx **out) {
+    if (!out) return RELCP_E_INVALID;
+    *out = nullptr;
+    relcp_ctx *c = new (std::nothrow) relcp_ctx();
+    if (!c) return RELCP_E_OOM;
+    try {
+        relcp_params P{};
+        P.dynamics = RELCP_OVERDAMPED;
+        P.precision = 64;
+        P.warm_start = RELCP_WS_PREV;
+        P.max_recursions = 64;
+        P.skin = 0.05;
+        if (params) P = *params;
+        if (P.dynamics != 0 && P.dynamics != 1) throw Error{RELCP_E_INVALID, "bad dynamics"};
+        if (P.precision != 64 && P.precision != 32) throw Error{RELCP_E_INVALID, "precision must be 64 or 32"};
+        if (P.warm_start < 0 || P.warm_start > 2) throw Error{RELCP_E_INVALID, "bad warm start"};
+        if (P.warm_start == RELCP_WS_LEARNED) throw Error{RELCP_E_INVALID, "learned warm start needs a model"};
+        if (P.max_recursions < 0 || P.max_recursions >= RELCP_MAX_RECORDED)
+            throw Error{RELCP_E_INVALID, "max_recursions must be in [0, 64]"};
+        if (!(P.skin > 0) || !std::isfinite(P.skin)) throw Error{RELCP_E_INVALID, "skin must be positive"};
+        validate(bodies, shapes, &P, P.skin);
+        c->dynamics = P.dynamics;
+        c->precision = P.precision;
+        c->warm_start = P.warm_start;
+        c->planar = P.planar ? 1 : 0;
+        c->max_rec = P.max_recursions;
+        c->lcp_max_iters = P.lcp_max_iters > 0 ? P.lcp_max_iters : 100000;
+        c->lcp_fixed = P.lcp_fixed_iters > 0 ? P.lcp_fixed_iters : 0;
+        c->skin = P.skin;
+        if (P.stream) {
+            c->stream = (hipStream_t)P.stream;
+        } else {
+            HIP_OK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+            c->own_stream = true;
+        }
+        HIP_OK(hipHostMalloc((void **)&c->pst_h, sizeof(PgdState), hipHostMallocDefault));
+        HIP_OK(hipHostMalloc((void **)&c->int_h, 16 * sizeof(int), hipHostMallocDefault));
+        HIP_OK(hipHostMalloc((void **)&c->red_h, 8 * sizeof(unsigned long long), hipHostMallocDefault));
+        HIP_OK(hipHostMalloc((void **)&c->dbl_h, 8 * sizeof(double), hipHostMallocDefault));
+        c->upload_bodies(bodies, shapes);
+        *out = c;
+        return RELCP_OK;
+    } catch (const Error &e) {
+        delete c;
+        return e.code;
+    } catch (...) {
+        delete c;
+        return RELCP_E_DEVICE;
+    }
+}
+
+void relcp_destroy(relcp_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    delete ctx;
+}
+
+const char *relcp_last_error(const relcp_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int relcp_set_external(relcp_ctx *ctx, const double *f) {
+    if (!ctx) return RELCP_E_INVALID;
+    return guarded(ctx, [&]() -> int {
+        if (!f) {
+            ctx->has_fext = false;
+            return RELCP_OK;
+        }
+        size_t N = ctx->n;
+        std::vector<double> t(6 * N);
+        for (size_t i = 0; i < N; ++i)
+            for (int k = 0; k < 6; ++k) {
+                double v = f[6 * i + k];
+                if (!std::isfinite(v)) throw Error{RELCP_E_INVALID, "non-finite external wrench"};
+                t[k * N + i] = v;
+            }
+        HIP_OK(hipMemcpyAsync(ctx->fext.p, t.data(), 6 * N * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        ctx->sync();
+        ctx->has_fext = true;
+        return RELCP_OK;
+    });
+}
+
+int relcp_step(relcp_ctx *ctx, double dt, double overlap_tol, double lcp_tol, relcp_step_stats *stats) {
+    if (!ctx) return RELCP_E_INVALID;
+    if (!(dt > 0) || !(overlap_tol > 0) || !(lcp_tol > 0) || !std::isfinite(dt)) {
+        ctx->err = "dt, overlap_tol and lcp_tol must be positive";
+        return RELCP_E_INVALID;
+    }
+    return guarded(ctx, [&]() -> int {
+        int rc = ctx->step(dt, overlap_tol, lcp_tol, stats);
+        if (rc != RELCP_OK) {
+            static const char *names[] = {"ok", "invalid", "out of memory", "device", "LCP iteration cap",
+                                          "recursion cap", "skin exceeded", "non-finite value", "capacity"};
+            ctx->err = std::string("step failed: ") + names[-rc];
+        }
+        return rc;
+    });
+}
+
+static int get_state_impl(const relcp_ctx *cc, double *x, double *q, double *u, double *w, bool device) {
+    relcp_ctx *ctx = const_cast<relcp_ctx *>(cc);
+    return guarded(ctx, [&]() -> int {
+        size_t N = ctx->n;
+        if (device) {
+            auto conv = [&](const double *src, int c0, int comps, double *dst) {
+                if (!dst) return;
+                hipLaunchKernelGGL(k_soa_to_aos, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (int)N, comps, src,
+                                   (int)N, c0, dst, comps);
+            };
+            conv(ctx->x.p, 0, 3, x);
+            conv(ctx->q.p, 0, 4, q);
+            conv(ctx->u.p, 0, 3, u);
+            conv(ctx->u.p, 3, 3, w);
+            ctx->sync();
+            return RELCP_OK;
+        }
+        std::vector<double> t(6 * N);
+        auto down = [&](const double *src, int c0, int comps, double *dst) {
+            if (!dst) return;
+            HIP_OK(hipMemcpyAsync(t.data(), src + c0 * N, comps * N * sizeof(double), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+            ctx->sync();
+            for (size_t i = 0; i < N; ++i)
+                for (int k = 0; k < comps; ++k) dst[comps * i + k] = t[k * N + i];
+        };
+        down(ctx->x.p, 0, 3, x);
+        down(ctx->q.p, 0, 4, q);
+        down(ctx->u.p, 0, 3, u);
+        down(ctx->u.p, 3, 3, w);
+        return RELCP_OK;
+    });
+}
+
+int relcp_get_state(const relcp_ctx *ctx, double *x, double *q, double *u, double *w) {
+    if (!ctx) return RELCP_E_INVALID;
+    return get_state_impl(ctx, x, q, u, w, false);
+}
+
+int relcp_get_state_device(const relcp_ctx *ctx, double *x, double *q, double *u, double *w) {
+    if (!ctx) return RELCP_E_INVALID;
+    return get_state_impl(ctx, x, q, u, w, true);
+}
+
+int relcp_set_state(relcp_ctx *ctx, const relcp_bodies *bodies, const relcp_shapes *shapes) {
+    if (!ctx) return RELCP_E_INVALID;
+    return guarded(ctx, [&]() -> int {
+        validate(bodies, shapes, nullptr, ctx->skin);
+        if (ctx->dynamics == RELCP_INERTIAL)
+            for (int i = 0; i < bodies->n; ++i)
+                if (shapes->kind[i] != RELCP_ELLIPSOID) throw Error{RELCP_E_INVALID, "inertial needs ellipsoids"};
+        ctx->upload_bodies(bodies, shapes);
+        return RELCP_OK;
+    });
+}
+
+int relcp_affine_rescale(relcp_ctx *ctx, double s) {
+    if (!ctx) return RELCP_E_INVALID;
+    if (!(s > 0) || !std::isfinite(s)) return RELCP_E_INVALID;
+    return guarded(ctx, [&]() -> int {
+        for (int pk = 0; pk < ctx->nbatch; ++pk)
+            for (int k = 0; k < 3; ++k) {
+                double L = ctx->box[3 * pk + k] * s;
+                if (L > 0 && L < 2.0 * (ctx->rmax[pk] + ctx->skin))
+                    throw Error{RELCP_E_INVALID, "box would become smaller than 2 (R_max + skin)"};
+            }
+        for (auto &v : ctx->box) v *= s;
+        HIP_OK(hipMemcpyAsync(ctx->boxes.p, ctx->box.data(), ctx->box.size() * sizeof(double),
+                              hipMemcpyHostToDevice, ctx->stream));
+        hipLaunchKernelGGL(k_scale, dim3(nblk(3LL * ctx->n, 256)), dim3(256), 0, ctx->stream, 3 * ctx->n, ctx->x.p,
+                           s);
+        ctx->sync();
+        return RELCP_OK;
+    });
+}
+
+int relcp_get_contacts(const relcp_ctx *cc, int32_t *ia, int32_t *ib, int32_t *recursion_added, double *gamma,
+                       double *phi_at_discovery, double *normal) {
+    relcp_ctx *ctx = const_cast<relcp_ctx *>(cc);
+    if (!ctx) return RELCP_E_INVALID;
+    return guarded(ctx, [&]() -> int {
+        size_t M = ctx->m_acc;
+        if (M == 0) return RELCP_OK;
+        auto cp = [&](void *dst, const void *src, size_t bytes) {
+            if (dst) HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->stream));
+        };
+        cp(ia, ctx->ria.p, M * 4);
+        cp(ib, ctx->rib.p, M * 4);
+        cp(recursion_added, ctx->rrec.p, M * 4);
+        cp(gamma, ctx->rgam64.p, M * 8);
+        cp(phi_at_discovery, ctx->rphi64.p, M * 8);
+        std::vector<double> t;
+        if (normal) {
+            t.resize(3 * M);
+            for (int k = 0; k < 3; ++k) cp(t.data() + k * M, ctx->rn64.p + (size_t)k * ctx->ldr, M * 8);
+        }
+        ctx->sync();
+        if (normal)
+            for (size_t i = 0; i < M; ++i)
+                for (int k = 0; k < 3; ++k) normal[3 * i + k] = t[k * M + i];
+        return RELCP_OK;
+    });
+}
+
+int relcp_set_timing(relcp_ctx *ctx, int32_t enable) {
+    if (!ctx) return RELCP_E_INVALID;
+    return guarded(ctx, [&]() -> int {
+        ctx->sync();
+        ctx->collect_timing();
+        ctx->timing = enable != 0;
+        return RELCP_OK;
+    });
+}
+
+int relcp_get_timing(relcp_ctx *ctx, int32_t *count, double *ms, int32_t reset) {
+    if (!ctx) return RELCP_E_INVALID;
+    return guarded(ctx, [&]() -> int {
+        ctx->sync();
+        ctx->collect_timing();
+        for (int k = 0; k < relcp_ctx::kClasses; ++k) {
+            if (count) count[k] = (int32_t)ctx->t_count[k];
+            if (ms) ms[k] = ctx->t_ms[k];
+            if (reset) {
+                ctx->t_count[k] = 0;
+                ctx->t_ms[k] = 0.0;
+            }
+        }
+        return RELCP_OK;
+    });
+}
+
+// ---------------------------------------------------------------------------
+// stand-alone operations
+// ---------------------------------------------------------------------------
+int relcp_snsd_device(int32_t nb, const double *x, const double *q, const int32_t *kind, const double *p, int32_t m,
+                      const int32_t *pa, const int32_t *pb, const double *box, int32_t planar, double *out,
+                      void *stream) {
+    if (nb <= 0 || m < 0 || !x || !q || !kind || !p || (m > 0 && (!pa || !pb || !out)) || !box)
+        return RELCP_E_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        DBuf<double> geo, Rb, boxes;
+        geo.ensure(6 * (size_t)nb);
+        Rb.ensure(nb);
+        boxes.ensure(3);
+        HIP_OK(hipMemcpyAsync(boxes.p, box, 3 * sizeof(double), hipMemcpyHostToDevice, s));
+        BodySetupArgs ba{};
+        ba.nb = nb; ba.q = q; ba.ldq = nb; ba.kind = kind; ba.p = p; ba.ldp = nb; ba.geo = geo.p; ba.ldg = nb;
+        ba.Rb = Rb.p; ba.K = nullptr;
+        launch_body_setup(ba, s);
+        SnsdArgs sa{};
+        sa.m = m; sa.pa = pa; sa.pb = pb; sa.body_batch = nullptr; sa.x = x; sa.ldx = nb; sa.geo = geo.p; sa.ldg = nb;
+        sa.kind = kind; sa.p = p; sa.ldp = nb; sa.boxes = boxes.p; sa.planar = planar; sa.hint = nullptr; sa.out = out;
+        sa.ldo = m; sa.mode = 0; sa.thresh = 0; sa.eps = 0; sa.flag = nullptr; sa.minphi = nullptr;
+        launch_snsd_pairs(sa, s);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipStreamSynchronize(s));
+        geo.release(); Rb.release(); boxes.release();
+        return RELCP_OK;
+    } catch (const Error &e) {
+        return e.code;
+    }
+}
+
+int relcp_broadphase_device(int32_t nb, const double *x, const int32_t *kind, const double *p, const double *box,
+                            double skin, int32_t cap, int32_t *pa, int32_t *pb, int32_t *m, void *stream) {
+    if (nb <= 0 || !x || !kind || !p || !box || !m || !(skin >= 0)) return RELCP_E_INVALID;
+    relcp_ctx c;
+    c.stream = (hipStream_t)stream;
+    try {
+        HIP_OK(hipHostMalloc((void **)&c.int_h, 16 * sizeof(int), hipHostMallocDefault));
+        c.n = nb;
+        c.nbatch = 1;
+        c.boff = {0, nb};
+        c.box.assign(box, box + 3);
+        c.body_batch.ensure(nb);
+        HIP_OK(hipMemsetAsync(c.body_batch.p, 0, nb * sizeof(int), c.stream));
+        c.Rb.ensure(nb);
+        DBuf<double> geo;
+        geo.ensure(6 * (size_t)nb);
+        DBuf<double> qd;
+        qd.ensure(4 * (size_t)nb);
+        // bounding radii do not depend on orientation: any unit quaternion
+        std::vector<double> qh(4 * (size_t)nb, 0.0);
+        for (int i = 0; i < nb; ++i) qh[i] = 1.0;
+        HIP_OK(hipMemcpyAsync(qd.p, qh.data(), qh.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        BodySetupArgs ba{};
+        ba.nb = nb; ba.q = qd.p; ba.ldq = nb; ba.kind = kind; ba.p = p; ba.ldp = nb; ba.geo = geo.p; ba.ldg = nb;
+        ba.Rb = c.Rb.p; ba.K = nullptr;
+        launch_body_setup(ba, c.stream);
+        std::vector<double> ph(3 * (size_t)nb);
+        std::vector<int> kh(nb);
+        HIP_OK(hipMemcpyAsync(ph.data(), p, ph.size() * 8, hipMemcpyDeviceToHost, c.stream));
+        HIP_OK(hipMemcpyAsync(kh.data(), kind, kh.size() * 4, hipMemcpyDeviceToHost, c.stream));
+        c.sync();
+        double R = 0;
+        for (int i = 0; i < nb; ++i)
+            R = std::max(R, kh[i] == 0 ? std::max(ph[i], std::max(ph[nb + i], ph[2 * nb + i]))
+                                       : 0.5 * ph[nb + i] + ph[i]);
+        c.rmax = {R};
+        for (int k = 0; k < 3; ++k)
+            if (box[k] > 0 && box[k] < 2.0 * (R + skin)) throw Error{RELCP_E_INVALID, "box too small"};
+        c.broadphase(x, skin);
+        *m = c.np;
+        int k = std::min(c.np, cap);
+        if (k > 0 && pa && pb) {
+            HIP_OK(hipMemcpyAsync(pa, c.pa.p, k * sizeof(int), hipMemcpyDeviceToDevice, c.stream));
+            HIP_OK(hipMemcpyAsync(pb, c.pb.p, k * sizeof(int), hipMemcpyDeviceToDevice, c.stream));
+        }
+        c.sync();
+        geo.release();
+        qd.release();
+        c.stream = nullptr;
+        return RELCP_OK;
+    } catch (const Error &e) {
+        c.stream = nullptr;
+        return e.code;
+    }
+}
+
+__global__ void k_rows_from_user(int m, int ld, const double *__restrict__ n, const double *__restrict__ ta,
+                                 const double *__restrict__ tb, const double *__restrict__ qv,
+                                 const int *__restrict__ ia, const int *__restrict__ ib, const double *__restrict__ K,
+                                 int ldb, double dt, double *n64, double *ta64, double *tb64, double *qv64,
+                                 double *dA64, float *n32, float *ta32, float *tb32, float *qv32, float *dA32) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    d3 nn = mk(n[r], n[m + r], n[2 * m + r]);
+    d3 a = mk(ta[r], ta[m + r], ta[2 * m + r]);
+    d3 b = mk(tb[r], tb[m + r], tb[2 * m + r]);
+    auto quad = [&](int i, d3 t) {
+        double tr = nn.x * nn.x * K[i] + nn.y * nn.y * K[ldb + i] + nn.z * nn.z * K[2 * ldb + i];
+        sym3 R{K[3 * ldb + i], K[4 * ldb + i], K[5 * ldb + i], K[6 * ldb + i], K[7 * ldb + i], K[8 * ldb + i]};
+        return tr + dot(t, mul(R, t));
+    };
+    double dA = dt * (quad(ia[r], a) + quad(ib[r], b));
+    if (!(dA > 0.0)) dA = 1.0;
+    double nv[3] = {nn.x, nn.y, nn.z}, av[3] = {a.x, a.y, a.z}, bv[3] = {b.x, b.y, b.z};
+    for (int k = 0; k < 3; ++k) {
+        n64[k * ld + r] = nv[k];
+        ta64[k * ld + r] = av[k];
+        tb64[k * ld + r] = bv[k];
+        n32[k * ld + r] = (float)nv[k];
+        ta32[k * ld + r] = (float)av[k];
+        tb32[k * ld + r] = (float)bv[k];
+    }
+    qv64[r] = qv[r];
+    qv32[r] = (float)qv[r];
+    dA64[r] = dA;
+    dA32[r] = (float)dA;
+}
+
+__global__ void k_K_from_user(int nb, const double *__restrict__ kt, const double *__restrict__ Kr, int planar,
+                              double *K, float *K32) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    double v[9];
+    for (int k = 0; k < 3; ++k) v[k] = kt[i];
+    for (int k = 0; k < 6; ++k) v[3 + k] = Kr[k * nb + i];
+    if (planar) {
+        v[2] = 0.0;
+        v[3] = v[4] = v[6] = v[7] = v[8] = 0.0;
+    }
+    for (int k = 0; k < 9; ++k) {
+        K[k * nb + i] = v[k];
+        K32[k * nb + i] = (float)v[k];
+    }
+}
+
+int relcp_lcp_solve_device(int32_t nb, int32_t m, const int32_t *ia, const int32_t *ib, const double *n,
+                           const double *ta, const double *tb, const double *qv, const double *kt, const double *Kr,
+                           double dt, int32_t planar, int32_t precision, double tol, int32_t max_iters,
+                           double *gamma, int32_t *iters, double *residual, void *stream) {
+    if (nb <= 0 || m < 0 || !(dt > 0) || (precision != 32 && precision != 64) || !gamma || !kt || !Kr)
+        return RELCP_E_INVALID;
+    relcp_ctx c;
+    c.stream = (hipStream_t)stream;
+    try {
+        HIP_OK(hipHostMalloc((void **)&c.pst_h, sizeof(PgdState), hipHostMallocDefault));
+        c.n = nb;
+        c.lcp_max_iters = max_iters > 0 ? max_iters : 100000;
+        c.K.ensure(9 * (size_t)nb);
+        c.K32.ensure(9 * (size_t)nb);
+        c.vc64.ensure(6 * (size_t)nb);
+        c.vc32.ensure(6 * (size_t)nb);
+        hipLaunchKernelGGL(k_K_from_user, dim3(nblk(nb, 256)), dim3(256), 0, c.stream, nb, kt, Kr, planar, c.K.p,
+                           c.K32.p);
+        c.ensure_rows(std::max(m, 1));
+        c.m = m;
+        if (m > 0) {
+            HIP_OK(hipMemcpyAsync(c.ria.p, ia, m * 4, hipMemcpyDeviceToDevice, c.stream));
+            HIP_OK(hipMemcpyAsync(c.rib.p, ib, m * 4, hipMemcpyDeviceToDevice, c.stream));
+            HIP_OK(hipMemcpyAsync(c.rgam64.p, gamma, m * 8, hipMemcpyDeviceToDevice, c.stream));
+            hipLaunchKernelGGL(k_rows_from_user, dim3(nblk(m, 256)), dim3(256), 0, c.stream, m, c.ldr, n, ta, tb, qv,
+                               ia, ib, c.K.p, nb, dt, c.rn64.p, c.rta64.p, c.rtb64.p, c.rqv64.p, c.rdA64.p, c.rn32.p,
+                               c.rta32.p, c.rtb32.p, c.rqv32.p, c.rdA32.p);
+        }
+        c.rebuild_csr();
+        int it = 0, it64 = 0, rc;
+        double res = 0, res64 = 0;
+        if (precision == 32) {
+            launch_demote(m, c.rgam64.p, c.rgam32.p, c.stream);
+            rc = c.solve<float>(dt, tol, it, res);
+            launch_promote(m, c.rgam32.p, c.rgam64.p, c.stream);
+            if (rc == RELCP_OK || rc == RELCP_E_LCP_MAXITER) rc = c.solve<double>(dt, tol, it64, res64);
+        } else {
+            rc = c.solve<double>(dt, tol, it, res64);
+        }
+        if (m > 0) HIP_OK(hipMemcpyAsync(gamma, c.rgam64.p, m * 8, hipMemcpyDeviceToDevice, c.stream));
+        c.sync();
+        if (iters) *iters = it + it64;
+        if (residual) *residual = res64;
+        c.stream = nullptr;
+        return rc;
+    } catch (const Error &e) {
+        c.stream = nullptr;
+        return e.code;
+    }
+}
+
+}  // extern "C"

@@ -13,7 +13,10 @@ Workload shapes (Sec. 5 of Palmer, Aktulga, Gao, arXiv 2506.14097):
 """
 from __future__ import annotations
 
+import ctypes
 import math
+import os
+import subprocess
 
 import numpy as np
 
@@ -62,52 +65,46 @@ def two_ellipsoids(seed: int = 0, separation: float = 3.0, closing_speed: float 
                 box=np.zeros(3))
 
 
-def rsa_spheres(rng: np.random.Generator, radii: np.ndarray, box: np.ndarray, max_attempts: int = 2000,
+_RSA_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "inputs_rsa.c")
+_RSA_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_librsa.so")
+_rsa = None
+
+
+def build_rsa(force: bool = False) -> str:
+    """Compile the placement helper (plain C, gcc)."""
+    if force or not os.path.exists(_RSA_LIB) or os.path.getmtime(_RSA_LIB) < os.path.getmtime(_RSA_SRC):
+        tmp = _RSA_LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, _RSA_SRC, "-lm"])
+        os.replace(tmp, _RSA_LIB)
+    return _RSA_LIB
+
+
+def _rsa_lib():
+    global _rsa
+    if _rsa is None:
+        build_rsa()
+        _rsa = ctypes.CDLL(_RSA_LIB)
+        _rsa.rsa_spheres.restype = ctypes.c_int
+        _rsa.rsa_spheres.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                     ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p]
+    return _rsa
+
+
+def rsa_spheres(rng: np.random.Generator, radii: np.ndarray, box: np.ndarray, max_attempts: int = 20000,
                 planar: bool = False) -> np.ndarray:
     """Random sequential addition of non-overlapping spheres (largest first)
     in a periodic box (z fixed at 0 when planar).  Raises if a sphere cannot
     be placed within max_attempts."""
+    radii = np.ascontiguousarray(radii, dtype=np.float64)
     n = radii.size
-    order = np.argsort(-radii, kind="stable")
-    rmax = float(radii.max())
-    cell = 2.0 * rmax
-    dims = 2 if planar else 3
-    nc = np.maximum(1, np.floor(box[:dims] / cell).astype(int))
-    csize = box[:dims] / nc
-    grid: dict = {}
+    order = np.ascontiguousarray(np.argsort(-radii, kind="stable"), dtype=np.int32)
+    box = np.ascontiguousarray(box, dtype=np.float64)
     pos = np.zeros((n, 3))
-    placed_r = np.zeros(n)
-    for i in order:
-        r = radii[i]
-        for _ in range(max_attempts):
-            p = np.zeros(3)
-            p[:dims] = rng.random(dims) * box[:dims]
-            c = np.floor(p[:dims] / csize).astype(int) % nc
-            ok = True
-            rng3 = range(-1, 2)
-            offs = [(a, b, 0) for a in rng3 for b in rng3] if planar else \
-                [(a, b, e) for a in rng3 for b in rng3 for e in rng3]
-            seen = set()
-            for o in offs:
-                key = tuple((c + np.array(o[:dims])) % nc)
-                if key in seen:
-                    continue
-                seen.add(key)
-                for j in grid.get(key, ()):
-                    d = pos[j, :dims] - p[:dims]
-                    d -= box[:dims] * np.round(d / box[:dims])
-                    if d @ d < (r + placed_r[j]) ** 2:
-                        ok = False
-                        break
-                if not ok:
-                    break
-            if ok:
-                pos[i] = p
-                placed_r[i] = r
-                grid.setdefault(tuple(c), []).append(i)
-                break
-        else:
-            raise RuntimeError("random sequential addition jammed; lower the density")
+    seed = int(rng.integers(0, 1 << 62))
+    got = _rsa_lib().rsa_spheres(n, radii.ctypes.data, order.ctypes.data, box.ctypes.data, 1 if planar else 0, seed,
+                                 max_attempts, pos.ctypes.data)
+    if got != n:
+        raise RuntimeError("random sequential addition jammed; lower the density")
     return pos
 
 

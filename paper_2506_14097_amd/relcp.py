@@ -1,0 +1,301 @@
+"""Thin ctypes binding of librelcp.so (the C ABI in include/relcp.h).
+
+Argument marshalling only: every step of the time-step runs in the HIP
+kernels of librelcp.so.  There is no fallback: if the library is missing the
+import of this module's functions raises.
+
+Host arrays are numpy (array-of-structs per body, FP64); the ``*_device``
+helpers take torch tensors on the GPU and pass their data pointers.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "librelcp.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "relcp.h")
+
+OK = 0
+E_INVALID, E_OOM, E_DEVICE, E_LCP_MAXITER, E_RECURSION_CAP, E_SKIN, E_NAN, E_CAPACITY = (-1, -2, -3, -4, -5, -6,
+                                                                                       -7, -8)
+ELLIPSOID, SPHEROCYLINDER = 0, 1
+OVERDAMPED, INERTIAL = 0, 1
+WS_COLD, WS_PREV, WS_LEARNED = 0, 1, 2
+MAX_RECORDED = 65
+
+STATUS_NAMES = {0: "ok", -1: "invalid", -2: "out of memory", -3: "device error", -4: "LCP iteration cap",
+                -5: "recursion cap", -6: "skin exceeded", -7: "non-finite value", -8: "capacity"}
+
+
+class RelcpError(RuntimeError):
+    def __init__(self, status, msg=""):
+        super().__init__("relcp status %d (%s): %s" % (status, STATUS_NAMES.get(status, "?"), msg))
+        self.status = status
+
+
+class Bodies(C.Structure):
+    _fields_ = [("n", C.c_int32), ("x", C.c_void_p), ("q", C.c_void_p), ("u", C.c_void_p), ("w", C.c_void_p),
+                ("n_batch", C.c_int32), ("batch_off", C.c_void_p), ("box", C.c_void_p)]
+
+
+class Shapes(C.Structure):
+    _fields_ = [("kind", C.c_void_p), ("p", C.c_void_p), ("rho_or_xi", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("dynamics", C.c_int32), ("precision", C.c_int32), ("warm_start", C.c_int32), ("planar", C.c_int32),
+                ("max_recursions", C.c_int32), ("lcp_max_iters", C.c_int32), ("lcp_fixed_iters", C.c_int32),
+                ("skin", C.c_double), ("stream", C.c_void_p)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("recursions", C.c_int32), ("lcp_iters_total", C.c_int32), ("n_pairs", C.c_int32),
+                ("n_contacts_final", C.c_int32), ("n_contacts", C.c_int32 * MAX_RECORDED),
+                ("lcp_iters", C.c_int32 * MAX_RECORDED), ("lcp_iters64", C.c_int32 * MAX_RECORDED),
+                ("W", C.c_double * MAX_RECORDED),
+                ("margin", C.c_double * MAX_RECORDED), ("residual_fp64", C.c_double),
+                ("residual_lowp", C.c_double), ("max_overlap", C.c_double), ("max_disp", C.c_double),
+                ("t_narrow", C.c_double), ("t_lcp", C.c_double), ("t_other", C.c_double)]
+
+    def as_dict(self):
+        R = self.recursions
+        k = min(R + 1, MAX_RECORDED)
+        return dict(recursions=R, lcp_iters_total=self.lcp_iters_total, n_pairs=self.n_pairs,
+                    n_contacts_final=self.n_contacts_final, n_contacts=np.array(self.n_contacts[:k]),
+                    lcp_iters=np.array(self.lcp_iters[:k]), lcp_iters64=np.array(self.lcp_iters64[:k]),
+                    W=np.array(self.W[:k]), margin=np.array(self.margin[:k]),
+                    residual_fp64=self.residual_fp64, residual_lowp=self.residual_lowp,
+                    max_overlap=self.max_overlap, max_disp=self.max_disp, t_narrow=self.t_narrow, t_lcp=self.t_lcp,
+                    t_other=self.t_other)
+
+
+_lib = None
+
+# every entry point of include/relcp.h with its ctypes signature
+_SIGS = {
+    "relcp_create": (C.c_int, [C.POINTER(Bodies), C.POINTER(Shapes), C.POINTER(Params), C.POINTER(C.c_void_p)]),
+    "relcp_destroy": (None, [C.c_void_p]),
+    "relcp_last_error": (C.c_char_p, [C.c_void_p]),
+    "relcp_set_external": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "relcp_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.POINTER(StepStats)]),
+    "relcp_get_state": (C.c_int, [C.c_void_p] + [C.c_void_p] * 4),
+    "relcp_get_state_device": (C.c_int, [C.c_void_p] + [C.c_void_p] * 4),
+    "relcp_set_state": (C.c_int, [C.c_void_p, C.POINTER(Bodies), C.POINTER(Shapes)]),
+    "relcp_affine_rescale": (C.c_int, [C.c_void_p, C.c_double]),
+    "relcp_get_contacts": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6),
+    "relcp_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
+    "relcp_get_timing": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "relcp_snsd_device": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "relcp_broadphase_device": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                          C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.c_void_p]),
+    "relcp_lcp_solve_device": (C.c_int, [C.c_int32, C.c_int32] + [C.c_void_p] * 8 + [C.c_double, C.c_int32, C.c_int32,
+                                         C.c_double, C.c_int32, C.c_void_p, C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_double), C.c_void_p]),
+}
+
+
+def lib():
+    """Load librelcp.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise ImportError("librelcp.so is not built: run `python -m paper_2506_14097_amd.build`")
+        L = C.CDLL(LIBPATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _d(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.size != n:
+        raise ValueError("expected %d values, got %d" % (n, a.size))
+    return a
+
+
+def _i(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _tptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else t.data_ptr()
+
+
+class Simulation:
+    """A ReLCP context: one or several independent packings on one GPU."""
+
+    def __init__(self, x, q, kind, shape, rho_xi, box, u=None, w=None, batch_off=None, *, dynamics=OVERDAMPED,
+                 precision=64, warm_start=WS_PREV, planar=False, max_recursions=64, lcp_max_iters=0,
+                 lcp_fixed_iters=0, skin=0.05, stream=None):
+        L = lib()
+        self._keep = []
+        self.ctx = C.c_void_p()
+        B, S = self._structs(x, q, kind, shape, rho_xi, box, u, w, batch_off)
+        P = Params(dynamics, precision, warm_start, 1 if planar else 0, max_recursions, lcp_max_iters,
+                   lcp_fixed_iters, skin, stream)
+        rc = L.relcp_create(C.byref(B), C.byref(S), C.byref(P), C.byref(self.ctx))
+        self._keep = []
+        if rc != OK:
+            self.ctx = None
+            raise RelcpError(rc, "relcp_create")
+
+    def _structs(self, x, q, kind, shape, rho_xi, box, u, w, batch_off):
+        x = _d(x)
+        n = x.size // 3
+        q = _d(q, 4 * n)
+        kind = _i(kind)
+        shape = _d(shape, 3 * n)
+        rho_xi = _d(rho_xi, n)
+        box = _d(box)
+        nb = box.size // 3
+        boff = None if batch_off is None else _i(batch_off)
+        uu = None if u is None else _d(u, 3 * n)
+        ww = None if w is None else _d(w, 3 * n)
+        self._keep = [x, q, kind, shape, rho_xi, box, boff, uu, ww]
+        self.n = n
+        self.n_batch = nb
+        B = Bodies(n, _ptr(x), _ptr(q), _ptr(uu), _ptr(ww), nb, _ptr(boff), _ptr(box))
+        S = Shapes(_ptr(kind), _ptr(shape), _ptr(rho_xi))
+        return B, S
+
+    def close(self):
+        if self.ctx:
+            lib().relcp_destroy(self.ctx)
+            self.ctx = None
+
+    __del__ = close
+
+    def _err(self):
+        return lib().relcp_last_error(self.ctx).decode()
+
+    def set_external(self, f):
+        f = None if f is None else _d(f, 6 * self.n)
+        rc = lib().relcp_set_external(self.ctx, _ptr(f))
+        if rc != OK:
+            raise RelcpError(rc, self._err())
+
+    def step(self, dt, overlap_tol, lcp_tol, raise_on_error=True):
+        st = StepStats()
+        rc = lib().relcp_step(self.ctx, dt, overlap_tol, lcp_tol, C.byref(st))
+        d = st.as_dict()
+        d["status"] = rc
+        if rc != OK and raise_on_error:
+            raise RelcpError(rc, self._err())
+        return d
+
+    def get_state(self):
+        n = self.n
+        x, q, u, w = np.zeros(3 * n), np.zeros(4 * n), np.zeros(3 * n), np.zeros(3 * n)
+        rc = lib().relcp_get_state(self.ctx, _ptr(x), _ptr(q), _ptr(u), _ptr(w))
+        if rc != OK:
+            raise RelcpError(rc, self._err())
+        return x.reshape(n, 3), q.reshape(n, 4), np.concatenate([u.reshape(n, 3), w.reshape(n, 3)], 1)
+
+    def get_state_device(self, x, q, u, w):
+        rc = lib().relcp_get_state_device(self.ctx, _tptr(x), _tptr(q), _tptr(u), _tptr(w))
+        if rc != OK:
+            raise RelcpError(rc, self._err())
+
+    def set_state(self, x, q, kind, shape, rho_xi, box, u=None, w=None, batch_off=None):
+        B, S = self._structs(x, q, kind, shape, rho_xi, box, u, w, batch_off)
+        rc = lib().relcp_set_state(self.ctx, C.byref(B), C.byref(S))
+        self._keep = []
+        if rc != OK:
+            raise RelcpError(rc, self._err())
+
+    def affine_rescale(self, s):
+        rc = lib().relcp_affine_rescale(self.ctx, s)
+        if rc != OK:
+            raise RelcpError(rc, self._err())
+
+    TIMING_CLASSES = ("lcp_scatter", "lcp_gather", "snsd", "pairs", "trial")
+
+    def set_timing(self, on):
+        rc = lib().relcp_set_timing(self.ctx, 1 if on else 0)
+        if rc != OK:
+            raise RelcpError(rc, self._err())
+
+    def get_timing(self, reset=True):
+        cnt = np.zeros(5, np.int32)
+        ms = np.zeros(5)
+        rc = lib().relcp_get_timing(self.ctx, _ptr(cnt), _ptr(ms), 1 if reset else 0)
+        if rc != OK:
+            raise RelcpError(rc, self._err())
+        return {k: (int(c), float(t)) for k, c, t in zip(self.TIMING_CLASSES, cnt, ms)}
+
+    def get_contacts(self, m):
+        ia, ib, rec = np.zeros(m, np.int32), np.zeros(m, np.int32), np.zeros(m, np.int32)
+        gam, phi, nrm = np.zeros(m), np.zeros(m), np.zeros(3 * m)
+        rc = lib().relcp_get_contacts(self.ctx, _ptr(ia), _ptr(ib), _ptr(rec), _ptr(gam), _ptr(phi), _ptr(nrm))
+        if rc != OK:
+            raise RelcpError(rc, self._err())
+        return dict(ia=ia, ib=ib, rec=rec, gamma=gam, phi=phi, n=nrm.reshape(m, 3))
+
+
+# --------------------------------------------------------------------------
+# stand-alone device operations (torch tensors in, torch tensors out)
+# --------------------------------------------------------------------------
+def snsd_device(x_soa, q_soa, kind, p_soa, pa, pb, box, planar=False, out=None, stream=None):
+    """SNSD of pairs on the GPU: x_soa (3, nb), q_soa (4, nb), p_soa (3, nb)
+    float64 cuda tensors; kind, pa, pb int32 cuda tensors.  Returns out (10, m)."""
+    import torch
+    nb = x_soa.shape[1]
+    m = pa.numel()
+    if out is None:
+        out = torch.empty((10, max(m, 1)), dtype=torch.float64, device=x_soa.device)
+    boxh = _d(box, 3)
+    rc = lib().relcp_snsd_device(nb, _tptr(x_soa), _tptr(q_soa), _tptr(kind), _tptr(p_soa), m, _tptr(pa), _tptr(pb),
+                                 boxh.ctypes.data, 1 if planar else 0, _tptr(out), stream)
+    if rc != OK:
+        raise RelcpError(rc, "relcp_snsd_device")
+    return out[:, :m]
+
+
+def broadphase_device(x_soa, kind, p_soa, box, skin, cap=None, stream=None):
+    import torch
+    nb = x_soa.shape[1]
+    if cap is None:
+        cap = 64 * nb
+    pa = torch.empty(max(cap, 1), dtype=torch.int32, device=x_soa.device)
+    pb = torch.empty(max(cap, 1), dtype=torch.int32, device=x_soa.device)
+    m = C.c_int32(0)
+    boxh = _d(box, 3)
+    rc = lib().relcp_broadphase_device(nb, _tptr(x_soa), _tptr(kind), _tptr(p_soa), boxh.ctypes.data, skin, cap,
+                                       _tptr(pa), _tptr(pb), C.byref(m), stream)
+    if rc != OK:
+        raise RelcpError(rc, "relcp_broadphase_device")
+    k = min(m.value, cap)
+    return pa[:k], pb[:k], m.value
+
+
+def lcp_solve_device(nb, ia, ib, n_soa, ta_soa, tb_soa, qv, kt, Kr_soa, dt, gamma, *, planar=False, precision=64,
+                     tol=1e-12, max_iters=0, stream=None):
+    """Solve 0 <= qv + dt D^T K D gamma _|_ gamma >= 0 on the GPU (gamma
+    in/out).  Returns (iterations, FP64 residual, status)."""
+    m = ia.numel()
+    it = C.c_int32(0)
+    res = C.c_double(0.0)
+    rc = lib().relcp_lcp_solve_device(nb, m, _tptr(ia), _tptr(ib), _tptr(n_soa), _tptr(ta_soa), _tptr(tb_soa),
+                                      _tptr(qv), _tptr(kt), _tptr(Kr_soa), dt, 1 if planar else 0, precision, tol,
+                                      max_iters, _tptr(gamma), C.byref(it), C.byref(res), stream)
+    return it.value, res.value, rc
+
+
+def header_symbols():
+    """Names of the functions declared in include/relcp.h."""
+    import re
+    with open(HEADER) as f:
+        txt = f.read()
+    return sorted(set(re.findall(r"RELCP_API\s+[\w\s\*]*?\b(relcp_\w+)\s*\(", txt)))

@@ -1,0 +1,85 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point declared in include/relcp.h, the ctypes mirrors of the
+structs match the C layout, and argument validation rejects bad input before
+any device work."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2506_14097_amd import relcp as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_header_symbol():
+    L = R.lib()
+    names = R.header_symbols()
+    assert len(names) >= 13
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(R._SIGS)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "relcp.h"\nint main(void){'
+                   'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(relcp_bodies), sizeof(relcp_shapes),'
+                   'sizeof(relcp_params), sizeof(relcp_step_stats), offsetof(relcp_step_stats, residual_fp64),'
+                   'offsetof(relcp_params, skin)); return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [C.sizeof(R.Bodies), C.sizeof(R.Shapes), C.sizeof(R.Params), C.sizeof(R.StepStats),
+            R.StepStats.residual_fp64.offset, R.Params.skin.offset]
+    assert got == want
+
+
+def _two():
+    x = np.array([[0.0, 0, 0], [3.0, 0, 0]])
+    q = np.array([[1.0, 0, 0, 0]] * 2)
+    return dict(x=x, q=q, kind=np.zeros(2, np.int32), shape=np.array([[1.0, 0.5, 0.5]] * 2), rho_xi=np.ones(2),
+                box=np.zeros(3))
+
+
+@pytest.mark.parametrize("bad", ["nan_x", "quat", "semiaxis", "box", "precision", "xi", "kinds", "inertial_rod",
+                                 "skin", "recursions"])
+def test_create_rejects_invalid_input(bad):
+    a = _two()
+    kw = {}
+    if bad == "nan_x":
+        a["x"][0, 0] = np.nan
+    elif bad == "quat":
+        a["q"][0] = [1.0, 0.1, 0, 0]
+    elif bad == "semiaxis":
+        a["shape"][1, 2] = -0.1
+    elif bad == "box":
+        a["box"] = np.array([2.0, 2.0, 2.0])
+    elif bad == "precision":
+        kw["precision"] = 16
+    elif bad == "xi":
+        a["rho_xi"][0] = 0.0
+    elif bad == "kinds":
+        a["kind"][1] = 1
+        a["shape"][1] = [0.5, 1.0, 0.0]
+    elif bad == "inertial_rod":
+        a["kind"][:] = 1
+        a["shape"][:] = [0.5, 1.0, 0.0]
+        kw["dynamics"] = R.INERTIAL
+    elif bad == "skin":
+        kw["skin"] = -1.0
+    elif bad == "recursions":
+        kw["max_recursions"] = 100
+    with pytest.raises(R.RelcpError) as ei:
+        R.Simulation(a["x"], a["q"], a["kind"], a["shape"], a["rho_xi"], a["box"], **kw)
+    assert ei.value.status == R.E_INVALID
+
+
+def test_null_context_calls_fail_cleanly():
+    L = R.lib()
+    assert L.relcp_step(None, 0.1, 1e-3, 1e-6, None) == R.E_INVALID
+    assert L.relcp_get_state(None, None, None, None, None) == R.E_INVALID
+    assert L.relcp_affine_rescale(None, 0.9) == R.E_INVALID
+    L.relcp_destroy(None)
