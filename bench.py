@@ -144,6 +144,8 @@ def main():
     ap.add_argument("--roofline-steps", type=int, default=5)
     ap.add_argument("--cpu-n", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=float, default=0.0,
+                    help="only run a device-to-device copy of this many MB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -152,6 +154,15 @@ def main():
     import torch
     from paper_2506_14097_amd import relcp as R
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe_mb > 0:
+        nel = int(args.copy_probe_mb * 1e6 / 4)
+        a = torch.ones(nel, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: 5 copies of %d bytes" % (4 * nel))
+        return
     R.lib()
 
     sim, P, box, phi = setup(args)

@@ -141,8 +141,9 @@ RELCP_API int relcp_set_state(relcp_ctx *ctx, const relcp_bodies *bodies, const 
 RELCP_API int relcp_affine_rescale(relcp_ctx *ctx, double s);
 
 /* Rows of the last accepted step (caller buffers of n_contacts_final
- * entries; any may be NULL): body pair, recursion at which the row was
- * generated, multiplier gamma, true Phi where generated, normal (3 each). */
+ * entries; any may be NULL): body pair (caller's indices, ia < ib),
+ * recursion at which the row was generated, multiplier gamma, true Phi
+ * where generated, unit normal from ia towards ib (3 each). */
 RELCP_API int relcp_get_contacts(const relcp_ctx *ctx, int32_t *ia, int32_t *ib, int32_t *recursion_added, double *gamma,
                        double *phi_at_discovery, double *normal);
 

@@ -551,8 +551,11 @@ __global__ void __launch_bounds__(256) k_pairs(int nb, const double *__restrict_
                                                const int *__restrict__ items, double skin,
                                                int *__restrict__ pair_count, const int *__restrict__ pair_off,
                                                int *__restrict__ pa, int *__restrict__ pb, int cap) {
-    int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= nb) return;
+    // threads walk the bodies in cell order, so neighbouring lanes scan the
+    // same neighbour cells
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb) return;
+    int a = items[t];
     int pk = body_batch ? body_batch[a] : 0;
     PackGrid g = grids[pk];
     double xa = x[a], ya = x[ldx + a], za = x[2 * ldx + a], ra = Rb[a];

@@ -57,18 +57,29 @@ void launch_compact(int n, const int *flags, const int *scanned, int *out, hipSt
 void launch_csr(int nb, int m, const int *ia, const int *ib, int *cnt, int *off, int *cursor, int *ent,
                 DBuf<int> &scan_scratch, hipStream_t s);
 
-// One projected-gradient iteration pass.  mode 0 = evaluate g at max(0,
-// gamma) (start of a solve); mode 1 = project with the current step, then
-// evaluate (one BB-PGD iteration).  Both passes skip when st->conv is set
-// (mode 1).
+// Device control block of one solve: ping-pong states S[0], S[1], the
+// final state, the done flag and the gather's per-block partial sums.
+struct PgdCtl {
+    PgdState *S;
+    PgdState *fin;
+    int *done;
+    double *partials;
+    int nbg;
+    double tol;
+};
+
+// Passes of the projected-gradient loop.  Iteration j (j = 1, 2, ...) is
+// scatter(mode 1, par = j & 1) then gather(mode 1, par = j & 1); a solve
+// starts with pgd_init, scatter(mode 0), gather(mode 0).  All mode-1
+// passes return at once after convergence (done flag).
 template <typename T>
-void launch_lcp_iteration(int mode, const RowsT<T> &r, const BodiesT<T> &b, double dt, double tol, PgdState *st,
-                          double *partials, hipStream_t s);
+void launch_lcp_scatter(int mode, const RowsT<T> &r, const BodiesT<T> &b, const PgdCtl &C, int par, hipStream_t s);
 template <typename T>
-void launch_lcp_scatter(int mode, const RowsT<T> &r, const BodiesT<T> &b, const PgdState *st, hipStream_t s);
-template <typename T>
-void launch_lcp_gather(int mode, const RowsT<T> &r, const BodiesT<T> &b, double dt, double tol, PgdState *st,
-                       double *partials, hipStream_t s);
+void launch_lcp_gather(int mode, const RowsT<T> &r, const BodiesT<T> &b, double dt, const PgdCtl &C, int par,
+                       hipStream_t s);
+void launch_pgd_init(const PgdCtl &C, hipStream_t s);
+void launch_pgd_finalize(const PgdCtl &C, int par, hipStream_t s);
+int lcp_gather_blocks(int m);
 
 // gamma64 <- gamma32 ; gamma32 <- gamma64
 void launch_promote(int m, const float *g32, double *g64, hipStream_t s);

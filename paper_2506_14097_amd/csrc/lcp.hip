@@ -162,41 +162,6 @@ __global__ void k_csr_sort(int nb, const int *__restrict__ off, int *__restrict_
 // ---------------------------------------------------------------------------
 // the two passes of one iteration
 // ---------------------------------------------------------------------------
-template <typename T, int MODE>
-__global__ void __launch_bounds__(kThreads) k_scatter(RowsT<T> R, BodiesT<T> B, const PgdState *__restrict__ st) {
-    if (MODE == 1 && st->conv) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= B.nb) return;
-    const T al = (T)st->alpha;
-    T f0 = 0, f1 = 0, f2 = 0, t0 = 0, t1 = 0, t2 = 0;
-    const int e0 = B.off[i], e1 = B.off[i + 1];
-    const int L = R.ld;
-    for (int e = e0; e < e1; ++e) {
-        int en = B.ent[e];
-        int c = en >> 1;
-        T gm = R.gam[c];
-        T gv = MODE == 1 ? project(gm, R.g[c], R.dA[c], al) : clamp0(gm);
-        const T *tau = (en & 1) ? R.tb : R.ta;
-        T sg = (en & 1) ? gv : -gv;
-        f0 += sg * R.n[c];
-        f1 += sg * R.n[L + c];
-        f2 += sg * R.n[2 * L + c];
-        t0 += sg * tau[c];
-        t1 += sg * tau[L + c];
-        t2 += sg * tau[2 * L + c];
-    }
-    const int lb = B.ld;
-    const T *K = B.K;
-    B.vc[i] = K[i] * f0;
-    B.vc[lb + i] = K[lb + i] * f1;
-    B.vc[2 * lb + i] = K[2 * lb + i] * f2;
-    T kxx = K[3 * lb + i], kyy = K[4 * lb + i], kzz = K[5 * lb + i];
-    T kxy = K[6 * lb + i], kxz = K[7 * lb + i], kyz = K[8 * lb + i];
-    B.vc[3 * lb + i] = kxx * t0 + kxy * t1 + kxz * t2;
-    B.vc[4 * lb + i] = kxy * t0 + kyy * t1 + kyz * t2;
-    B.vc[5 * lb + i] = kxz * t0 + kyz * t1 + kzz * t2;
-}
-
 __device__ inline double wave_sum(double v) {
     for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, RELCP_WAVE);
     return v;
@@ -206,8 +171,8 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
-// Block reduction of 3 sums and 1 max in a fixed order; result in lane 0
-// of thread 0.
+// Block reduction of 3 sums and 1 max in a fixed order; the result is
+// valid in thread 0.
 __device__ inline void block_reduce4(double &a, double &b, double &c, double &mx, double (*sh)[kWaves]) {
     a = wave_sum(a);
     b = wave_sum(b);
@@ -234,16 +199,145 @@ __device__ inline void block_reduce4(double &a, double &b, double &c, double &mx
     __syncthreads();
 }
 
+// State after one gather: iteration count, residual, convergence and the
+// Barzilai-Borwein step (BB1 after even iterations, BB2 after odd ones).
+__device__ inline PgdState pgd_next(const PgdState &s, double ss, double sy, double yy, double res, double tol) {
+    PgdState n = s;
+    const int k = s.iter;
+    n.iter = k + 1;
+    n.res = res;
+    n.ss = ss;
+    n.sy = sy;
+    n.yy = yy;
+    n.conv = (res <= tol) ? 1 : 0;
+    if (sy > 0.0) {
+        double a = (k % 2 == 0) ? ss / sy : sy / yy;
+        n.alpha = a < 1e-10 ? 1e-10 : (a > 1e10 ? 1e10 : a);
+    }
+    return n;
+}
+
+// Reduce the gather partials (same fixed order in every block) and advance
+// the state; thread 0 of every block ends with the new state in `out`.
+__device__ inline void reduce_partials(const PgdCtl &C, int par, PgdState *out, double (*sh)[kWaves]) {
+    double ss = 0.0, sy = 0.0, yy = 0.0, res = 0.0;
+    for (int k = threadIdx.x; k < C.nbg; k += kThreads) {
+        const double *p = C.partials + 4 * k;
+        ss += p[0];
+        sy += p[1];
+        yy += p[2];
+        res = fmax(res, p[3]);
+    }
+    block_reduce4(ss, sy, yy, res, sh);
+    if (threadIdx.x == 0) *out = pgd_next(C.S[par ^ 1], ss, sy, yy, res, C.tol);
+    __syncthreads();
+}
+
+__global__ void k_pgd_init(PgdCtl C) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        PgdState s{};
+        s.alpha = 1.0;
+        s.iter = -1;
+        C.S[0] = s;
+        C.S[1] = s;
+        *C.fin = s;
+        *C.done = 0;
+    }
+}
+
+// MODE 0: V = K D max(0, gamma) (start of a solve).
+// MODE 1: reduce the previous gather, advance the state (S[par^1] ->
+// S[par]); stop if converged; else V = K D gamma' with gamma' the projected
+// step.  The projection is recomputed per incident row, bit-identical to
+// the gather's.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(kThreads) k_gather(RowsT<T> R, BodiesT<T> B, double dt, double tol,
-                                                     PgdState *__restrict__ st, double *__restrict__ partials) {
-    if (MODE == 1 && st->conv) return;
+__global__ void __launch_bounds__(kThreads) k_scatter(RowsT<T> R, BodiesT<T> B, PgdCtl C, int par) {
     __shared__ double sh[4][kWaves];
-    __shared__ bool last;
+    __shared__ PgdState ns;
+    T al = T(0);
+    if (MODE == 1) {
+        if (*C.done) return;
+        reduce_partials(C, par, &ns, sh);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            C.S[par] = ns;
+            if (ns.conv) {
+                *C.fin = ns;
+                *C.done = 1;
+            }
+        }
+        if (ns.conv) return;
+        al = (T)ns.alpha;
+    }
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B.nb) return;
+    T f0 = 0, f1 = 0, f2 = 0, t0 = 0, t1 = 0, t2 = 0;
+    const int e0 = B.off[i], e1 = B.off[i + 1];
+    const int L = R.ld;
+    // four incident rows per round: all their loads are issued before any
+    // is consumed (a body has 2-3 rows on average)
+    constexpr int U = 4;
+    for (int e = e0; e < e1; e += U) {
+        int cc[U], sd[U];
+        T gm[U], gg[U], da[U], n0[U], n1[U], n2[U], u0[U], u1[U], u2[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            int en = (e + k < e1) ? B.ent[e + k] : -1;
+            cc[k] = en >= 0 ? (en >> 1) : -1;
+            sd[k] = en & 1;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (cc[k] < 0) continue;
+            const int c = cc[k];
+            const T *tau = sd[k] ? R.tb : R.ta;
+            gm[k] = R.gam[c];
+            if (MODE == 1) {
+                gg[k] = R.g[c];
+                da[k] = R.dA[c];
+            }
+            n0[k] = R.n[c];
+            n1[k] = R.n[L + c];
+            n2[k] = R.n[2 * L + c];
+            u0[k] = tau[c];
+            u1[k] = tau[L + c];
+            u2[k] = tau[2 * L + c];
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (cc[k] < 0) continue;
+            T gv = MODE == 1 ? project(gm[k], gg[k], da[k], al) : clamp0(gm[k]);
+            T sg = sd[k] ? gv : -gv;
+            f0 += sg * n0[k];
+            f1 += sg * n1[k];
+            f2 += sg * n2[k];
+            t0 += sg * u0[k];
+            t1 += sg * u1[k];
+            t2 += sg * u2[k];
+        }
+    }
+    const int lb = B.ld;
+    const T *K = B.K;
+    B.vc[i] = K[i] * f0;
+    B.vc[lb + i] = K[lb + i] * f1;
+    B.vc[2 * lb + i] = K[2 * lb + i] * f2;
+    T kxx = K[3 * lb + i], kyy = K[4 * lb + i], kzz = K[5 * lb + i];
+    T kxy = K[6 * lb + i], kxz = K[7 * lb + i], kyz = K[8 * lb + i];
+    B.vc[3 * lb + i] = kxx * t0 + kxy * t1 + kxz * t2;
+    B.vc[4 * lb + i] = kxy * t0 + kyy * t1 + kyz * t2;
+    B.vc[5 * lb + i] = kxz * t0 + kyz * t1 + kzz * t2;
+}
+
+// MODE 0: g = qv + dt D^T V at max(0, gamma); MODE 1: the same at the
+// projected step, plus the step-size sums.  Each block writes its partial
+// sums (s^T D s, s^T y, y^T D^-1 y, max residual) for the next scatter.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kThreads) k_gather(RowsT<T> R, BodiesT<T> B, double dt, PgdCtl C, int par) {
+    if (MODE == 1 && *C.done) return;
+    __shared__ double sh[4][kWaves];
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     double ss = 0.0, sy = 0.0, yy = 0.0, res = 0.0;
     if (c < R.m) {
-        const T al = (T)st->alpha;
+        const T al = MODE == 1 ? (T)C.S[par].alpha : T(0);
         const int L = R.ld, lb = B.ld;
         T gm = R.gam[c], gold = R.g[c], dA = R.dA[c];
         T gv = MODE == 1 ? project(gm, gold, dA, al) : clamp0(gm);
@@ -268,47 +362,25 @@ __global__ void __launch_bounds__(kThreads) k_gather(RowsT<T> R, BodiesT<T> B, d
     }
     block_reduce4(ss, sy, yy, res, sh);
     if (threadIdx.x == 0) {
-        double *p = partials + 4 * blockIdx.x;
+        double *p = C.partials + 4 * blockIdx.x;
         p[0] = ss;
         p[1] = sy;
         p[2] = yy;
         p[3] = res;
-        __threadfence();
-        unsigned t = atomicAdd(&st->ticket, 1u);
-        last = (t == gridDim.x - 1);
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // last block: reduce the per-block partials in a fixed order
-    ss = sy = yy = res = 0.0;
-    for (int k = threadIdx.x; k < (int)gridDim.x; k += kThreads) {
-        const double *p = partials + 4 * k;
-        ss += __builtin_nontemporal_load(p + 0);
-        sy += __builtin_nontemporal_load(p + 1);
-        yy += __builtin_nontemporal_load(p + 2);
-        res = fmax(res, __builtin_nontemporal_load(p + 3));
-    }
-    block_reduce4(ss, sy, yy, res, sh);
+}
+
+// Advance the state from the last gather without another scatter (end of a
+// solve that hit its iteration cap, or a fixed-iteration run).
+__global__ void __launch_bounds__(kThreads) k_pgd_finalize(PgdCtl C, int par) {
+    __shared__ double sh[4][kWaves];
+    __shared__ PgdState ns;
+    if (*C.done) return;
+    reduce_partials(C, par, &ns, sh);
     if (threadIdx.x == 0) {
-        st->ticket = 0;
-        st->res = res;
-        st->ss = ss;
-        st->sy = sy;
-        st->yy = yy;
-        if (MODE == 0) {
-            st->iter = 0;
-            st->alpha = 1.0;
-            st->conv = (res <= tol) ? 1 : 0;
-        } else {
-            int k = st->iter;
-            st->iter = k + 1;
-            if (res <= tol) st->conv = 1;
-            if (sy > 0.0) {
-                double a = (k % 2 == 0) ? ss / sy : sy / yy;
-                st->alpha = a < 1e-10 ? 1e-10 : (a > 1e10 ? 1e10 : a);
-            }
-        }
+        C.S[par] = ns;
+        *C.fin = ns;
+        if (ns.conv) *C.done = 1;
     }
 }
 
@@ -374,8 +446,8 @@ void launch_compact(int n, const int *flags, const int *scanned, int *out, hipSt
 
 void launch_csr(int nb, int m, const int *ia, const int *ib, int *cnt, int *off, int *cursor, int *ent,
                 DBuf<int> &scan_scratch, hipStream_t s) {
-    HIP_OK(hipMemsetAsync(cnt, 0, sizeof(int) * (nb + 1), s));
-    HIP_OK(hipMemsetAsync(cursor, 0, sizeof(int) * (nb + 1), s));
+    // cnt and cursor are adjacent (cursor = cnt + nb + 1): one clear
+    HIP_OK(hipMemsetAsync(cnt, 0, sizeof(int) * 2 * (nb + 1), s));
     if (m > 0) hipLaunchKernelGGL(k_csr_count, dim3(nblk(m, 256)), dim3(256), 0, s, m, ia, ib, cnt);
     exclusive_scan(cnt, off, nb + 1, nullptr, scan_scratch, s);
     if (m > 0) {
@@ -385,43 +457,42 @@ void launch_csr(int nb, int m, const int *ia, const int *ib, int *cnt, int *off,
 }
 
 template <typename T>
-void launch_lcp_scatter(int mode, const RowsT<T> &r, const BodiesT<T> &b, const PgdState *st, hipStream_t s) {
-    if (b.nb <= 0) return;
+void launch_lcp_scatter(int mode, const RowsT<T> &r, const BodiesT<T> &b, const PgdCtl &C, int par, hipStream_t s) {
+    int nbk = nblk(b.nb > 0 ? b.nb : 1, kThreads);
     if (mode == 0)
-        hipLaunchKernelGGL((k_scatter<T, 0>), dim3(nblk(b.nb, kThreads)), dim3(kThreads), 0, s, r, b, st);
+        hipLaunchKernelGGL((k_scatter<T, 0>), dim3(nbk), dim3(kThreads), 0, s, r, b, C, par);
     else
-        hipLaunchKernelGGL((k_scatter<T, 1>), dim3(nblk(b.nb, kThreads)), dim3(kThreads), 0, s, r, b, st);
+        hipLaunchKernelGGL((k_scatter<T, 1>), dim3(nbk), dim3(kThreads), 0, s, r, b, C, par);
 }
 
 template <typename T>
-void launch_lcp_gather(int mode, const RowsT<T> &r, const BodiesT<T> &b, double dt, double tol, PgdState *st,
-                       double *partials, hipStream_t s) {
+void launch_lcp_gather(int mode, const RowsT<T> &r, const BodiesT<T> &b, double dt, const PgdCtl &C, int par,
+                       hipStream_t s) {
     int nbk = nblk(r.m > 0 ? r.m : 1, kThreads);
     if (mode == 0)
-        hipLaunchKernelGGL((k_gather<T, 0>), dim3(nbk), dim3(kThreads), 0, s, r, b, dt, tol, st, partials);
+        hipLaunchKernelGGL((k_gather<T, 0>), dim3(nbk), dim3(kThreads), 0, s, r, b, dt, C, par);
     else
-        hipLaunchKernelGGL((k_gather<T, 1>), dim3(nbk), dim3(kThreads), 0, s, r, b, dt, tol, st, partials);
+        hipLaunchKernelGGL((k_gather<T, 1>), dim3(nbk), dim3(kThreads), 0, s, r, b, dt, C, par);
 }
 
-template <typename T>
-void launch_lcp_iteration(int mode, const RowsT<T> &r, const BodiesT<T> &b, double dt, double tol, PgdState *st,
-                          double *partials, hipStream_t s) {
-    launch_lcp_scatter<T>(mode, r, b, st, s);
-    launch_lcp_gather<T>(mode, r, b, dt, tol, st, partials, s);
+int lcp_gather_blocks(int m) { return nblk(m > 0 ? m : 1, kThreads); }
+
+void launch_pgd_init(const PgdCtl &C, hipStream_t s) {
+    hipLaunchKernelGGL(k_pgd_init, dim3(1), dim3(64), 0, s, C);
 }
 
-template void launch_lcp_iteration<double>(int, const RowsT<double> &, const BodiesT<double> &, double, double,
-                                           PgdState *, double *, hipStream_t);
-template void launch_lcp_iteration<float>(int, const RowsT<float> &, const BodiesT<float> &, double, double,
-                                          PgdState *, double *, hipStream_t);
-template void launch_lcp_gather<double>(int, const RowsT<double> &, const BodiesT<double> &, double, double,
-                                        PgdState *, double *, hipStream_t);
-template void launch_lcp_gather<float>(int, const RowsT<float> &, const BodiesT<float> &, double, double, PgdState *,
-                                       double *, hipStream_t);
-template void launch_lcp_scatter<double>(int, const RowsT<double> &, const BodiesT<double> &, const PgdState *,
-                                         hipStream_t);
-template void launch_lcp_scatter<float>(int, const RowsT<float> &, const BodiesT<float> &, const PgdState *,
-                                        hipStream_t);
+void launch_pgd_finalize(const PgdCtl &C, int par, hipStream_t s) {
+    hipLaunchKernelGGL(k_pgd_finalize, dim3(1), dim3(kThreads), 0, s, C, par);
+}
+
+#define RELCP_INST(T)                                                                                              \
+    template void launch_lcp_scatter<T>(int, const RowsT<T> &, const BodiesT<T> &, const PgdCtl &, int,           \
+                                        hipStream_t);                                                             \
+    template void launch_lcp_gather<T>(int, const RowsT<T> &, const BodiesT<T> &, double, const PgdCtl &, int,    \
+                                       hipStream_t);
+RELCP_INST(double)
+RELCP_INST(float)
+#undef RELCP_INST
 
 void launch_promote(int m, const float *g32, double *g64, hipStream_t s) {
     if (m > 0) hipLaunchKernelGGL(k_promote, dim3(nblk(m, 256)), dim3(256), 0, s, m, g32, g64);

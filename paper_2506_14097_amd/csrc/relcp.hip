@@ -60,10 +60,11 @@ __global__ void k_aos_to_soa(int n, int comps, const double *__restrict__ in, do
     for (int k = 0; k < comps; ++k) out[k * ld + i] = in[(size_t)comps * i + k];
 }
 __global__ void k_soa_to_aos(int n, int comps, const double *__restrict__ in, int ld, int c0, double *__restrict__ out,
-                             int ocomps) {
+                             int ocomps, const int *__restrict__ perm) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    for (int k = 0; k < ocomps; ++k) out[(size_t)ocomps * i + k] = in[(c0 + k) * ld + i];
+    size_t o = (size_t)ocomps * perm[i];
+    for (int k = 0; k < ocomps; ++k) out[o + k] = in[(c0 + k) * ld + i];
 }
 __global__ void k_scale(int n, double *__restrict__ x, double s) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -102,7 +103,8 @@ struct relcp_ctx {
     // bodies (SoA, ld = n)
     DBuf<double> x, q, u, p, rho, fext, xt, qt, geo, geot, Rb, K, vfree, vc64, vout, boxes;
     DBuf<float> K32, vc32;
-    DBuf<int> kind, body_batch;
+    DBuf<int> kind, body_batch, perm_d;
+    std::vector<int> perm, inv;  // internal -> caller index, caller -> internal
 
     // broadphase
     DBuf<PackGrid> grids;
@@ -174,7 +176,8 @@ struct relcp_ctx {
     }
 
     // pinned host mirrors
-    PgdState *pst_h = nullptr;
+    PgdState *pst_h = nullptr;  // fin and the done slot
+    int last_iters[2] = {8, 8};  // previous solve's iteration count (FP32, FP64)
     int *int_h = nullptr;
     unsigned long long *red_h = nullptr;
     double *dbl_h = nullptr;
@@ -186,7 +189,7 @@ struct relcp_ctx {
         for (auto *b : ds) b->release();
         DBuf<float> *fs[] = {&K32, &vc32, &rn32, &rta32, &rtb32, &rqv32, &rdA32, &rgam32, &rg32};
         for (auto *b : fs) b->release();
-        DBuf<int> *is[] = {&kind, &body_batch, &body_cell, &cell_count, &cell_start, &cell_cursor, &cell_items,
+        DBuf<int> *is[] = {&kind, &body_batch, &perm_d, &body_cell, &cell_count, &cell_start, &cell_cursor, &cell_items,
                            &pair_count, &pair_off, &pa, &pb, &pflag, &pscan, &sel, &prev_a, &prev_b, &ria, &rib,
                            &rpair, &rrec, &csr_cnt, &csr_off, &csr_cur, &csr_ent, &scan_scratch, &dtotal};
         for (auto *b : is) b->release();
@@ -275,6 +278,21 @@ static void validate(const relcp_bodies *B, const relcp_shapes *S, const relcp_p
     }
 }
 
+// Bodies are stored in the order of a Morton (Z-order) curve over a grid
+// of their positions, packing by packing, so that bodies close in space are
+// close in memory: neighbouring lanes then touch neighbouring cache lines in
+// every pass (pairs, SNSD, LCP scatter and gather).  perm[i] is the caller's
+// index of internal body i.
+static uint64_t spread3(uint64_t v) {
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffull;
+    v = (v | v << 16) & 0x1f0000ff0000ffull;
+    v = (v | v << 8) & 0x100f00f00f00f00full;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+    v = (v | v << 2) & 0x1249249249249249ull;
+    return v;
+}
+
 void relcp_ctx::upload_bodies(const relcp_bodies *B, const relcp_shapes *S) {
     n = B->n;
     nbatch = B->n_batch <= 0 ? 1 : B->n_batch;
@@ -292,6 +310,43 @@ void relcp_ctx::upload_bodies(const relcp_bodies *B, const relcp_shapes *S) {
             double R = S->kind[i] == 0 ? std::max(pp[0], std::max(pp[1], pp[2])) : 0.5 * pp[1] + pp[0];
             rmax[pk] = std::max(rmax[pk], R);
         }
+    // spatial order inside each packing
+    perm.resize(n);
+    for (int pk = 0; pk < nbatch; ++pk) {
+        int b0 = boff[pk], b1 = boff[pk + 1];
+        double lo[3], hi[3];
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = 1e300;
+            hi[k] = -1e300;
+        }
+        for (int i = b0; i < b1; ++i)
+            for (int k = 0; k < 3; ++k) {
+                double v = B->x[3 * i + k];
+                if (box[3 * pk + k] > 0) v -= box[3 * pk + k] * std::floor(v / box[3 * pk + k]);
+                lo[k] = std::min(lo[k], v);
+                hi[k] = std::max(hi[k], v);
+            }
+        double cell = std::max(1e-12, rmax[pk]);
+        std::vector<std::pair<uint64_t, int>> key(b1 - b0);
+        for (int i = b0; i < b1; ++i) {
+            uint64_t code = 0;
+            for (int k = 0; k < 3; ++k) {
+                double v = B->x[3 * i + k];
+                if (box[3 * pk + k] > 0) v -= box[3 * pk + k] * std::floor(v / box[3 * pk + k]);
+                double c = std::floor((v - lo[k]) / cell);
+                uint64_t ci = (uint64_t)std::min(std::max(c, 0.0), 2097151.0);
+                code |= spread3(ci) << k;
+            }
+            key[i - b0] = {code, i};
+        }
+        std::stable_sort(key.begin(), key.end(),
+                         [](const std::pair<uint64_t, int> &a, const std::pair<uint64_t, int> &b) {
+                             return a.first < b.first;
+                         });
+        for (int i = b0; i < b1; ++i) perm[i] = key[i - b0].second;
+    }
+    inv.resize(n);
+    for (int i = 0; i < n; ++i) inv[perm[i]] = i;
     size_t N = (size_t)n;
     auto alloc = [&](auto &b, int comps) {
         b.release();
@@ -300,31 +355,38 @@ void relcp_ctx::upload_bodies(const relcp_bodies *B, const relcp_shapes *S) {
     };
     alloc(x, 3); alloc(q, 4); alloc(u, 6); alloc(p, 3); alloc(rho, 1); alloc(fext, 6); alloc(xt, 3); alloc(qt, 4);
     alloc(geo, 6); alloc(geot, 6); alloc(Rb, 1); alloc(K, 9); alloc(vfree, 6); alloc(vc64, 6); alloc(vout, 6);
-    alloc(K32, 9); alloc(vc32, 6); alloc(kind, 1); alloc(body_batch, 1);
-    // host transposes to SoA
+    alloc(K32, 9); alloc(vc32, 6); alloc(kind, 1); alloc(body_batch, 1); alloc(perm_d, 1);
+    // host transposes to SoA in internal order
     std::vector<double> t(6 * N, 0.0);
-    auto up = [&](DBuf<double> &dst, const double *src, int comps, int c0, int stride) {
+    auto up = [&](const double *src, int comps, int c0, int stride) {
         for (size_t i = 0; i < N; ++i)
-            for (int k = 0; k < comps; ++k) t[(c0 + k) * N + i] = src ? src[stride * i + k] : 0.0;
-        (void)dst;
+            for (int k = 0; k < comps; ++k) t[(c0 + k) * N + i] = src ? src[(size_t)stride * perm[i] + k] : 0.0;
     };
-    up(x, B->x, 3, 0, 3);
+    up(B->x, 3, 0, 3);
     HIP_OK(hipMemcpyAsync(x.p, t.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, stream));
     sync();
-    up(q, B->q, 4, 0, 4);
+    up(B->q, 4, 0, 4);
     HIP_OK(hipMemcpyAsync(q.p, t.data(), 4 * N * sizeof(double), hipMemcpyHostToDevice, stream));
     sync();
-    up(u, B->u, 3, 0, 3);
-    up(u, B->w, 3, 3, 3);
+    up(B->u, 3, 0, 3);
+    up(B->w, 3, 3, 3);
     HIP_OK(hipMemcpyAsync(u.p, t.data(), 6 * N * sizeof(double), hipMemcpyHostToDevice, stream));
     HIP_OK(hipMemcpyAsync(vout.p, t.data(), 6 * N * sizeof(double), hipMemcpyHostToDevice, stream));
     sync();
-    up(p, S->p, 3, 0, 3);
+    up(S->p, 3, 0, 3);
     HIP_OK(hipMemcpyAsync(p.p, t.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, stream));
     sync();
-    HIP_OK(hipMemcpyAsync(rho.p, S->rho_or_xi, N * sizeof(double), hipMemcpyHostToDevice, stream));
-    HIP_OK(hipMemcpyAsync(kind.p, S->kind, N * sizeof(int), hipMemcpyHostToDevice, stream));
-    HIP_OK(hipMemcpyAsync(body_batch.p, bb.data(), N * sizeof(int), hipMemcpyHostToDevice, stream));
+    std::vector<double> rh(N);
+    std::vector<int> kh(N), bh(N);
+    for (size_t i = 0; i < N; ++i) {
+        rh[i] = S->rho_or_xi[perm[i]];
+        kh[i] = S->kind[perm[i]];
+        bh[i] = bb[perm[i]];
+    }
+    HIP_OK(hipMemcpyAsync(rho.p, rh.data(), N * sizeof(double), hipMemcpyHostToDevice, stream));
+    HIP_OK(hipMemcpyAsync(kind.p, kh.data(), N * sizeof(int), hipMemcpyHostToDevice, stream));
+    HIP_OK(hipMemcpyAsync(body_batch.p, bh.data(), N * sizeof(int), hipMemcpyHostToDevice, stream));
+    HIP_OK(hipMemcpyAsync(perm_d.p, perm.data(), N * sizeof(int), hipMemcpyHostToDevice, stream));
     boxes.ensure(3 * nbatch);
     HIP_OK(hipMemcpyAsync(boxes.p, box.data(), 3 * nbatch * sizeof(double), hipMemcpyHostToDevice, stream));
     HIP_OK(hipMemsetAsync(fext.p, 0, 6 * N * sizeof(double), stream));
@@ -439,18 +501,17 @@ void relcp_ctx::broadphase(const double *xs, double skin_) {
     grids.ensure(nbatch);
     HIP_OK(hipMemcpyAsync(grids.p, grids_h.data(), nbatch * sizeof(PackGrid), hipMemcpyHostToDevice, stream));
     body_cell.ensure(N);
-    cell_count.ensure(nc + 1);
+    cell_count.ensure(2 * (size_t)(nc + 1));  // counts, then cursors
     cell_start.ensure(nc + 1);
-    cell_cursor.ensure(nc + 1);
     cell_items.ensure(N);
     pair_count.ensure(N + 1);
     pair_off.ensure(N + 1);
     dtotal.ensure(4);
-    HIP_OK(hipMemsetAsync(cell_count.p, 0, (nc + 1) * sizeof(int), stream));
-    HIP_OK(hipMemsetAsync(cell_cursor.p, 0, (nc + 1) * sizeof(int), stream));
+    HIP_OK(hipMemsetAsync(cell_count.p, 0, 2 * (nc + 1) * sizeof(int), stream));
+    int *cell_cur = cell_count.p + (nc + 1);
     launch_cell_assign(N, xs, N, body_batch.p, grids.p, body_cell.p, cell_count.p, stream);
     exclusive_scan(cell_count.p, cell_start.p, nc, nullptr, scan_scratch, stream);
-    launch_cell_fill(N, body_cell.p, cell_start.p, cell_cursor.p, cell_items.p, stream);
+    launch_cell_fill(N, body_cell.p, cell_start.p, cell_cur, cell_items.p, stream);
     timed(3, [&] {
         launch_pairs(false, N, xs, N, Rb.p, body_batch.p, grids.p, body_cell.p, cell_start.p, cell_count.p,
                      cell_items.p, skin_, pair_count.p, nullptr, nullptr, nullptr, 0, stream);
@@ -499,11 +560,10 @@ void relcp_ctx::build_rows(int nsel, int rec, const double *snsd, const double *
 }
 
 void relcp_ctx::rebuild_csr() {
-    csr_cnt.ensure(n + 1);
+    csr_cnt.ensure(2 * (size_t)(n + 1));
     csr_off.ensure(n + 1);
-    csr_cur.ensure(n + 1);
     csr_ent.ensure(2 * (size_t)std::max(m, 1));
-    launch_csr(n, m, ria.p, rib.p, csr_cnt.p, csr_off.p, csr_cur.p, csr_ent.p, scan_scratch, stream);
+    launch_csr(n, m, ria.p, rib.p, csr_cnt.p, csr_off.p, csr_cnt.p + (n + 1), csr_ent.p, scan_scratch, stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -529,30 +589,49 @@ int relcp_ctx::solve(double dt, double tol, int &iters, double &res) {
     Bd.off = csr_off.p;
     Bd.ent = csr_ent.p;
     partials.ensure(lcp_partials_needed(m));
-    pst.ensure(1);
-    HIP_OK(hipMemsetAsync(pst.p, 0, sizeof(PgdState), stream));
-    const double tol_run = lcp_fixed > 0 ? -1.0 : tol;
+    // pst: S[0], S[1], fin, then a slot whose first int is the done flag
+    pst.ensure(4);
+    PgdCtl C{pst.p, pst.p + 2, reinterpret_cast<int *>(pst.p + 3), partials.p, lcp_gather_blocks(m),
+             lcp_fixed > 0 ? -1.0 : tol};
     const int cap = lcp_fixed > 0 ? lcp_fixed : lcp_max_iters;
-    timed(0, [&] { launch_lcp_scatter<T>(0, R, Bd, pst.p, stream); });
-    timed(1, [&] { launch_lcp_gather<T>(0, R, Bd, dt, tol_run, pst.p, partials.p, stream); });
-    HIP_OK(hipMemcpyAsync(pst_h, pst.p, sizeof(PgdState), hipMemcpyDeviceToHost, stream));
-    sync();
-    int chunk = 8;
-    while (!pst_h->conv && pst_h->iter < cap) {
-        int k = std::min(chunk, cap - pst_h->iter);
-        for (int j = 0; j < k; ++j) {
-            timed(0, [&] { launch_lcp_scatter<T>(1, R, Bd, pst.p, stream); });
-            timed(1, [&] { launch_lcp_gather<T>(1, R, Bd, dt, tol_run, pst.p, partials.p, stream); });
+    const int pk = sizeof(T) == 8 ? 1 : 0;
+    launch_pgd_init(C, stream);
+    timed(0, [&] { launch_lcp_scatter<T>(0, R, Bd, C, 0, stream); });
+    timed(1, [&] { launch_lcp_gather<T>(0, R, Bd, dt, C, 0, stream); });
+    // iterations are launched in chunks; passes after convergence return at
+    // once, so a chunk only over-runs by empty launches
+    int j = 1;
+    int chunk = std::max(2, std::min(64, (last_iters[pk] + 3) & ~1));
+    bool done = false;
+    for (;;) {
+        int k = std::min(chunk, cap - (j - 1));
+        if (k <= 0) break;
+        for (int t = 0; t < k; ++t, ++j) {
+            const int par = j & 1;
+            timed(0, [&] { launch_lcp_scatter<T>(1, R, Bd, C, par, stream); });
+            timed(1, [&] { launch_lcp_gather<T>(1, R, Bd, dt, C, par, stream); });
         }
-        HIP_OK(hipMemcpyAsync(pst_h, pst.p, sizeof(PgdState), hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipMemcpyAsync(pst_h, pst.p + 2, 2 * sizeof(PgdState), hipMemcpyDeviceToHost, stream));
         sync();
-        chunk = std::min(64, chunk * 2);
+        if (*reinterpret_cast<int *>(pst_h + 1)) {
+            done = true;
+            break;
+        }
+        chunk = std::min(64, std::max(8, 2 * chunk));
     }
-    iters = pst_h->iter;
-    res = pst_h->res;
+    if (!done) {
+        // account for the last gather (iteration cap or fixed-iteration run)
+        launch_pgd_finalize(C, (j - 1) & 1, stream);
+        HIP_OK(hipMemcpyAsync(pst_h, pst.p + 2, 2 * sizeof(PgdState), hipMemcpyDeviceToHost, stream));
+        sync();
+    }
+    const bool conv = *reinterpret_cast<int *>(pst_h + 1) != 0;
+    iters = pst_h[0].iter;
+    res = pst_h[0].res;
+    last_iters[pk] = iters;
     if (!std::isfinite(res)) return RELCP_E_NAN;
     if (lcp_fixed > 0) return RELCP_OK;
-    return pst_h->conv ? RELCP_OK : RELCP_E_LCP_MAXITER;
+    return conv ? RELCP_OK : RELCP_E_LCP_MAXITER;
 }
 
 // ---------------------------------------------------------------------------
@@ -779,7 +858,7 @@ int relcp_create(const relcp_bodies *bodies, const relcp_shapes *shapes, const r
             HIP_OK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
             c->own_stream = true;
         }
-        HIP_OK(hipHostMalloc((void **)&c->pst_h, sizeof(PgdState), hipHostMallocDefault));
+        HIP_OK(hipHostMalloc((void **)&c->pst_h, 2 * sizeof(PgdState), hipHostMallocDefault));
         HIP_OK(hipHostMalloc((void **)&c->int_h, 16 * sizeof(int), hipHostMallocDefault));
         HIP_OK(hipHostMalloc((void **)&c->red_h, 8 * sizeof(unsigned long long), hipHostMallocDefault));
         HIP_OK(hipHostMalloc((void **)&c->dbl_h, 8 * sizeof(double), hipHostMallocDefault));
@@ -814,7 +893,7 @@ int relcp_set_external(relcp_ctx *ctx, const double *f) {
         std::vector<double> t(6 * N);
         for (size_t i = 0; i < N; ++i)
             for (int k = 0; k < 6; ++k) {
-                double v = f[6 * i + k];
+                double v = f[6 * (size_t)ctx->perm[i] + k];
                 if (!std::isfinite(v)) throw Error{RELCP_E_INVALID, "non-finite external wrench"};
                 t[k * N + i] = v;
             }
@@ -850,7 +929,7 @@ static int get_state_impl(const relcp_ctx *cc, double *x, double *q, double *u, 
             auto conv = [&](const double *src, int c0, int comps, double *dst) {
                 if (!dst) return;
                 hipLaunchKernelGGL(k_soa_to_aos, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (int)N, comps, src,
-                                   (int)N, c0, dst, comps);
+                                   (int)N, c0, dst, comps, ctx->perm_d.p);
             };
             conv(ctx->x.p, 0, 3, x);
             conv(ctx->q.p, 0, 4, q);
@@ -866,7 +945,7 @@ static int get_state_impl(const relcp_ctx *cc, double *x, double *q, double *u, 
                                   ctx->stream));
             ctx->sync();
             for (size_t i = 0; i < N; ++i)
-                for (int k = 0; k < comps; ++k) dst[comps * i + k] = t[k * N + i];
+                for (int k = 0; k < comps; ++k) dst[comps * (size_t)ctx->perm[i] + k] = t[k * N + i];
         };
         down(ctx->x.p, 0, 3, x);
         down(ctx->q.p, 0, 4, q);
@@ -928,8 +1007,6 @@ int relcp_get_contacts(const relcp_ctx *cc, int32_t *ia, int32_t *ib, int32_t *r
         auto cp = [&](void *dst, const void *src, size_t bytes) {
             if (dst) HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->stream));
         };
-        cp(ia, ctx->ria.p, M * 4);
-        cp(ib, ctx->rib.p, M * 4);
         cp(recursion_added, ctx->rrec.p, M * 4);
         cp(gamma, ctx->rgam64.p, M * 8);
         cp(phi_at_discovery, ctx->rphi64.p, M * 8);
@@ -938,10 +1015,20 @@ int relcp_get_contacts(const relcp_ctx *cc, int32_t *ia, int32_t *ib, int32_t *r
             t.resize(3 * M);
             for (int k = 0; k < 3; ++k) cp(t.data() + k * M, ctx->rn64.p + (size_t)k * ctx->ldr, M * 8);
         }
+        std::vector<int> ha(M), hb(M);
+        HIP_OK(hipMemcpyAsync(ha.data(), ctx->ria.p, M * 4, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(hipMemcpyAsync(hb.data(), ctx->rib.p, M * 4, hipMemcpyDeviceToHost, ctx->stream));
         ctx->sync();
-        if (normal)
-            for (size_t i = 0; i < M; ++i)
-                for (int k = 0; k < 3; ++k) normal[3 * i + k] = t[k * M + i];
+        // caller's indices, first body the smaller index, normal from the
+        // first body to the second
+        for (size_t i = 0; i < M; ++i) {
+            int a = ctx->perm[ha[i]], b = ctx->perm[hb[i]];
+            double sg = a < b ? 1.0 : -1.0;
+            if (ia) ia[i] = a < b ? a : b;
+            if (ib) ib[i] = a < b ? b : a;
+            if (normal)
+                for (int k = 0; k < 3; ++k) normal[3 * i + k] = sg * t[k * M + i];
+        }
         return RELCP_OK;
     });
 }
@@ -1120,7 +1207,7 @@ int relcp_lcp_solve_device(int32_t nb, int32_t m, const int32_t *ia, const int32
     relcp_ctx c;
     c.stream = (hipStream_t)stream;
     try {
-        HIP_OK(hipHostMalloc((void **)&c.pst_h, sizeof(PgdState), hipHostMallocDefault));
+        HIP_OK(hipHostMalloc((void **)&c.pst_h, 2 * sizeof(PgdState), hipHostMallocDefault));
         c.n = nb;
         c.lcp_max_iters = max_iters > 0 ? max_iters : 100000;
         c.K.ensure(9 * (size_t)nb);

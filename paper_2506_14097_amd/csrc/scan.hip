@@ -60,18 +60,19 @@ __global__ void __launch_bounds__(kThreads) k_scan_add(int *__restrict__ out, in
     }
 }
 
-__global__ void k_scan_total(const int *in_last, const int *out_last, int *total, int n) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) total[0] = n > 0 ? (out_last[0] + in_last[0]) : 0;
-}
-
-void scan_rec(const int *in, int *out, int n, int *scratch, hipStream_t s) {
+// Scan of one level; the total of the whole input ends in `total` (the top
+// level is a single tile whose block sum is the total).
+void scan_rec(const int *in, int *out, int n, int *scratch, int *total, hipStream_t s) {
     int nt = (n + kTile - 1) / kTile;
+    if (nt == 1) {
+        int *sums = total ? total : scratch;
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kThreads), 0, s, in, out, n, sums);
+        return;
+    }
     int *sums = scratch;
     hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kThreads), 0, s, in, out, n, sums);
-    if (nt > 1) {
-        scan_rec(sums, sums, nt, scratch + nt, s);
-        hipLaunchKernelGGL(k_scan_add, dim3(nt), dim3(kThreads), 0, s, out, n, sums);
-    }
+    scan_rec(sums, sums, nt, scratch + nt, total, s);
+    hipLaunchKernelGGL(k_scan_add, dim3(nt), dim3(kThreads), 0, s, out, n, sums);
 }
 
 }  // namespace
@@ -81,15 +82,10 @@ void exclusive_scan(const int *in, int *out, int n, int *total_dev, DBuf<int> &s
         if (total_dev) HIP_OK(hipMemsetAsync(total_dev, 0, sizeof(int), s));
         return;
     }
-    // scratch: tile sums of every level plus one slot for the last input
     size_t need = 1;
     for (long long m = n; m > 1; m = (m + kTile - 1) / kTile) need += (m + kTile - 1) / kTile;
     scratch.ensure(need + 2);
-    int *last_in = scratch.p + need;
-    // keep the last input before an in-place scan overwrites it
-    HIP_OK(hipMemcpyAsync(last_in, in + (n - 1), sizeof(int), hipMemcpyDeviceToDevice, s));
-    scan_rec(in, out, n, scratch.p, s);
-    if (total_dev) hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, s, last_in, out + (n - 1), total_dev, n);
+    scan_rec(in, out, n, scratch.p, total_dev, s);
 }
 
 }  // namespace relcp

@@ -180,9 +180,10 @@ def test_lcp_solver(dev, precision, seed):
     W1 = _wrench(n, ia, ib, nrm, ta, tb, g)
     W0 = _wrench(n, ia, ib, nrm, ta, tb, g_or)
     assert rel(W1, W0) < (1e-8 if precision == 64 else 1e-4)
-    if precision == 64 and seed == 0:
-        # same algorithm, same start: same iteration count up to rounding
-        assert abs(it - it_or) <= max(5, it_or // 10)
+    if precision == 64:
+        # same algorithm from the same start; Barzilai-Borwein steps amplify
+        # rounding differences, so only the scale of the count is compared
+        assert abs(it - it_or) <= max(10, it_or // 2)
 
 
 def test_lcp_empty_and_trivial(dev):
