@@ -147,13 +147,28 @@ RELCP_API int relcp_affine_rescale(relcp_ctx *ctx, double s);
 RELCP_API int relcp_get_contacts(const relcp_ctx *ctx, int32_t *ia, int32_t *ib, int32_t *recursion_added, double *gamma,
                        double *phi_at_discovery, double *normal);
 
+/* Execution of the LCP loop (the same Jacobi-scaled projected gradient in
+ * every mode).  mode 0 = automatic, 1 = grid (two passes per iteration over
+ * all rows, launched in chunks), 2 = resident (one workgroup per packing
+ * runs its whole solve in one launch; block = workgroup size 256, 512 or
+ * 1024; lds = stage the packing's velocities in LDS when they fit). */
+RELCP_API int relcp_set_lcp_config(relcp_ctx *ctx, int32_t mode, int32_t block, int32_t lds);
+
+/* Autotuner: times every LCP configuration (grid; resident x {256, 512,
+ * 1024} x {LDS, global}) on the rows of the last accepted step, from the
+ * same start, reps times each, keeps the fastest for this context and
+ * writes it to config[3] = {mode, block, lds} and the average milliseconds
+ * per configuration to ms[7] (either may be NULL; a configuration that
+ * does not fit reports 0).  The multipliers of the last step are restored. */
+RELCP_API int relcp_autotune(relcp_ctx *ctx, double dt, double lcp_tol, int32_t reps, int32_t *config, double *ms);
+
 /* Kernel timing with HIP events recorded on the context's stream around
  * each launch of the step (off by default; costs one event pair per
  * launch).  Classes: 0 = LCP scatter pass (D gamma -> K), 1 = LCP gather
  * pass (D^T V, projection, step-size reductions), 2 = SNSD narrowphase,
- * 3 = candidate pairs, 4 = trial integration.  relcp_get_timing fills
- * count[5] (launches) and ms[5] (summed durations) since the last reset,
- * and resets when reset != 0. */
+ * 3 = candidate pairs, 4 = trial integration, 5 = resident LCP solve.
+ * relcp_get_timing fills count[6] (launches) and ms[6] (summed durations)
+ * since the last reset, and resets when reset != 0. */
 RELCP_API int relcp_set_timing(relcp_ctx *ctx, int32_t enable);
 RELCP_API int relcp_get_timing(relcp_ctx *ctx, int32_t *count, double *ms, int32_t reset);
 

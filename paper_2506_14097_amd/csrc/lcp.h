@@ -81,6 +81,30 @@ void launch_pgd_init(const PgdCtl &C, hipStream_t s);
 void launch_pgd_finalize(const PgdCtl &C, int par, hipStream_t s);
 int lcp_gather_blocks(int m);
 
+// Resident mode: one workgroup per packing solves that packing's LCP in one
+// launch.  Rows of packing p are rlist[roff[p] .. roff[p+1]).  out[p]
+// receives the packing's final state.  block in {256, 512, 1024}; lds
+// stages the velocities of a packing (6 lds_ld values) in LDS.  Returns 0,
+// or -1 if the launch configuration is not available.
+template <typename T>
+struct ResidentArgs {
+    RowsT<T> R;
+    BodiesT<T> B;
+    int npk;
+    const int *boff, *roff, *rlist;
+    double dt, tol;
+    int cap;
+    PgdState *out;
+    int lds_ld;
+};
+template <typename T>
+int launch_lcp_resident(const ResidentArgs<T> &a, int block, bool lds, hipStream_t s);
+void launch_rows_per_packing(int m0, int m1, const int *ia, const int *body_batch, int *cnt, hipStream_t s);
+void launch_rlist_merge(int m_old, int nv, const int *rlist_old, const int *ia, const int *body_batch,
+                        const int *roff_old, const int *E, int *rlist_new, hipStream_t s);
+void launch_add_arrays(int n, const int *a, const int *b, int *c, hipStream_t s);
+void launch_iota(int n, int *v, hipStream_t s);
+
 // gamma64 <- gamma32 ; gamma32 <- gamma64
 void launch_promote(int m, const float *g32, double *g64, hipStream_t s);
 void launch_demote(int m, const double *g64, float *g32, hipStream_t s);

@@ -171,8 +171,35 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
-// Block reduction of 3 sums and 1 max in a fixed order; the result is
-// valid in thread 0.
+// Block reduction of 3 sums and 1 max in a fixed order over NW waves; the
+// result is valid in thread 0.
+template <int NW>
+__device__ inline void block_reduce4n(double &a, double &b, double &c, double &mx, double (*sh)[NW]) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    mx = wave_max(mx);
+    const int lane = threadIdx.x & (RELCP_WAVE - 1), w = threadIdx.x / RELCP_WAVE;
+    if (lane == 0) {
+        sh[0][w] = a;
+        sh[1][w] = b;
+        sh[2][w] = c;
+        sh[3][w] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = b = c = 0.0;
+        mx = 0.0;
+        for (int k = 0; k < NW; ++k) {
+            a += sh[0][k];
+            b += sh[1][k];
+            c += sh[2][k];
+            mx = fmax(mx, sh[3][k]);
+        }
+    }
+    __syncthreads();
+}
+
 __device__ inline void block_reduce4(double &a, double &b, double &c, double &mx, double (*sh)[kWaves]) {
     a = wave_sum(a);
     b = wave_sum(b);
@@ -245,36 +272,30 @@ __global__ void k_pgd_init(PgdCtl C) {
     }
 }
 
-// MODE 0: V = K D max(0, gamma) (start of a solve).
-// MODE 1: reduce the previous gather, advance the state (S[par^1] ->
-// S[par]); stop if converged; else V = K D gamma' with gamma' the projected
-// step.  The projection is recomputed per incident row, bit-identical to
-// the gather's.
-template <typename T, int MODE>
-__global__ void __launch_bounds__(kThreads) k_scatter(RowsT<T> R, BodiesT<T> B, PgdCtl C, int par) {
-    __shared__ double sh[4][kWaves];
-    __shared__ PgdState ns;
-    T al = T(0);
-    if (MODE == 1) {
-        if (*C.done) return;
-        reduce_partials(C, par, &ns, sh);
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            C.S[par] = ns;
-            if (ns.conv) {
-                *C.fin = ns;
-                *C.done = 1;
-            }
-        }
-        if (ns.conv) return;
-        al = (T)ns.alpha;
-    }
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= B.nb) return;
+// Velocity storage of the LCP loop: the global array (ld, body index) or a
+// packing's slice staged in LDS (ld = packing size, index minus first body).
+template <typename T>
+struct VGlobal {
+    T *v;
+    int ld;
+    __device__ T &operator()(int comp, int i) const { return v[comp * ld + i]; }
+};
+template <typename T>
+struct VLocal {
+    T *v;
+    int ld, b0;
+    __device__ T &operator()(int comp, int i) const { return v[comp * ld + (i - b0)]; }
+};
+
+// V_i = K_i (D gamma)_i over the incident rows of body i, walking its
+// incidence list in a fixed order.  MODE 0 uses max(0, gamma); MODE 1 the
+// projected step with step length al.  Four rows per round so that all their
+// loads are in flight together (a body has 2-3 rows on average).
+template <typename T, int MODE, class VS>
+__device__ inline void scatter_body(const RowsT<T> &R, const BodiesT<T> &B, int i, T al, const VS &V) {
     T f0 = 0, f1 = 0, f2 = 0, t0 = 0, t1 = 0, t2 = 0;
     const int e0 = B.off[i], e1 = B.off[i + 1];
     const int L = R.ld;
-    // four incident rows per round: all their loads are issued before any
-    // is consumed (a body has 2-3 rows on average)
     constexpr int U = 4;
     for (int e = e0; e < e1; e += U) {
         int cc[U], sd[U];
@@ -317,19 +338,75 @@ __global__ void __launch_bounds__(kThreads) k_scatter(RowsT<T> R, BodiesT<T> B, 
     }
     const int lb = B.ld;
     const T *K = B.K;
-    B.vc[i] = K[i] * f0;
-    B.vc[lb + i] = K[lb + i] * f1;
-    B.vc[2 * lb + i] = K[2 * lb + i] * f2;
+    V(0, i) = K[i] * f0;
+    V(1, i) = K[lb + i] * f1;
+    V(2, i) = K[2 * lb + i] * f2;
     T kxx = K[3 * lb + i], kyy = K[4 * lb + i], kzz = K[5 * lb + i];
     T kxy = K[6 * lb + i], kxz = K[7 * lb + i], kyz = K[8 * lb + i];
-    B.vc[3 * lb + i] = kxx * t0 + kxy * t1 + kxz * t2;
-    B.vc[4 * lb + i] = kxy * t0 + kyy * t1 + kyz * t2;
-    B.vc[5 * lb + i] = kxz * t0 + kyz * t1 + kzz * t2;
+    V(3, i) = kxx * t0 + kxy * t1 + kxz * t2;
+    V(4, i) = kxy * t0 + kyy * t1 + kyz * t2;
+    V(5, i) = kxz * t0 + kyz * t1 + kzz * t2;
 }
 
-// MODE 0: g = qv + dt D^T V at max(0, gamma); MODE 1: the same at the
-// projected step, plus the step-size sums.  Each block writes its partial
-// sums (s^T D s, s^T y, y^T D^-1 y, max residual) for the next scatter.
+// Row c: gamma' (MODE 0: max(0, gamma); MODE 1: projected step), then
+// g' = qv + dt D_c^T V, the step-size sums and the scaled natural residual.
+template <typename T, int MODE, class VS>
+__device__ inline void gather_row(const RowsT<T> &R, int c, T al, T dtT, const VS &V, double &ss, double &sy,
+                                  double &yy, double &res) {
+    const int L = R.ld;
+    T gm = R.gam[c], gold = R.g[c], dA = R.dA[c];
+    T gv = MODE == 1 ? project(gm, gold, dA, al) : clamp0(gm);
+    int a = R.ia[c], b = R.ib[c];
+    T nx = R.n[c], ny = R.n[L + c], nz = R.n[2 * L + c];
+    T rate = -(nx * V(0, a) + ny * V(1, a) + nz * V(2, a)) -
+             (R.ta[c] * V(3, a) + R.ta[L + c] * V(4, a) + R.ta[2 * L + c] * V(5, a)) +
+             (nx * V(0, b) + ny * V(1, b) + nz * V(2, b)) +
+             (R.tb[c] * V(3, b) + R.tb[L + c] * V(4, b) + R.tb[2 * L + c] * V(5, b));
+    T gn = R.qv[c] + dtT * rate;
+    T dg = dA * gv;
+    res = fmax(res, fabs((double)(dg < gn ? dg : gn)));
+    if (MODE == 1) {
+        double s = (double)gv - (double)gm, y = (double)gn - (double)gold;
+        ss += (double)dA * s * s;
+        sy += s * y;
+        yy += y * y / (double)dA;
+    }
+    R.gam[c] = gv;
+    R.g[c] = gn;
+}
+
+// Grid mode, MODE 0: V = K D max(0, gamma) (start of a solve).
+// MODE 1: reduce the previous gather, advance the state (S[par^1] ->
+// S[par]); stop if converged; else V = K D gamma' with gamma' the projected
+// step.  The projection is recomputed per incident row, bit-identical to
+// the gather's.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kThreads) k_scatter(RowsT<T> R, BodiesT<T> B, PgdCtl C, int par) {
+    __shared__ double sh[4][kWaves];
+    __shared__ PgdState ns;
+    T al = T(0);
+    if (MODE == 1) {
+        if (*C.done) return;
+        reduce_partials(C, par, &ns, sh);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            C.S[par] = ns;
+            if (ns.conv) {
+                *C.fin = ns;
+                *C.done = 1;
+            }
+        }
+        if (ns.conv) return;
+        al = (T)ns.alpha;
+    }
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B.nb) return;
+    scatter_body<T, MODE>(R, B, i, al, VGlobal<T>{B.vc, B.ld});
+}
+
+// Grid mode, MODE 0: g = qv + dt D^T V at max(0, gamma); MODE 1: the same at
+// the projected step, plus the step-size sums.  Each block writes its
+// partial sums (s^T D s, s^T y, y^T D^-1 y, max residual) for the next
+// scatter.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads) k_gather(RowsT<T> R, BodiesT<T> B, double dt, PgdCtl C, int par) {
     if (MODE == 1 && *C.done) return;
@@ -338,27 +415,7 @@ __global__ void __launch_bounds__(kThreads) k_gather(RowsT<T> R, BodiesT<T> B, d
     double ss = 0.0, sy = 0.0, yy = 0.0, res = 0.0;
     if (c < R.m) {
         const T al = MODE == 1 ? (T)C.S[par].alpha : T(0);
-        const int L = R.ld, lb = B.ld;
-        T gm = R.gam[c], gold = R.g[c], dA = R.dA[c];
-        T gv = MODE == 1 ? project(gm, gold, dA, al) : clamp0(gm);
-        int a = R.ia[c], b = R.ib[c];
-        T nx = R.n[c], ny = R.n[L + c], nz = R.n[2 * L + c];
-        const T *V = B.vc;
-        T rate = -(nx * V[a] + ny * V[lb + a] + nz * V[2 * lb + a]) -
-                 (R.ta[c] * V[3 * lb + a] + R.ta[L + c] * V[4 * lb + a] + R.ta[2 * L + c] * V[5 * lb + a]) +
-                 (nx * V[b] + ny * V[lb + b] + nz * V[2 * lb + b]) +
-                 (R.tb[c] * V[3 * lb + b] + R.tb[L + c] * V[4 * lb + b] + R.tb[2 * L + c] * V[5 * lb + b]);
-        T gn = R.qv[c] + (T)dt * rate;
-        T dg = dA * gv;
-        res = fabs((double)(dg < gn ? dg : gn));
-        if (MODE == 1) {
-            double s = (double)gv - (double)gm, y = (double)gn - (double)gold;
-            ss = (double)dA * s * s;
-            sy = s * y;
-            yy = y * y / (double)dA;
-        }
-        R.gam[c] = gv;
-        R.g[c] = gn;
+        gather_row<T, MODE>(R, c, al, (T)dt, VGlobal<T>{B.vc, B.ld}, ss, sy, yy, res);
     }
     block_reduce4(ss, sy, yy, res, sh);
     if (threadIdx.x == 0) {
@@ -368,6 +425,93 @@ __global__ void __launch_bounds__(kThreads) k_gather(RowsT<T> R, BodiesT<T> B, d
         p[2] = yy;
         p[3] = res;
     }
+}
+
+// Resident mode: one workgroup owns one packing (bodies [boff[p],
+// boff[p+1]), rows rlist[roff[p] .. roff[p+1])) and runs its whole solve:
+// the same two passes per iteration separated by workgroup barriers, with
+// the packing's own step length and convergence.  With LDSV the packing's
+// velocities live in LDS during the solve and are written back at the end.
+template <typename T, int BS, bool LDSV>
+__global__ void __launch_bounds__(BS) k_lcp_resident(RowsT<T> R, BodiesT<T> B, const int *__restrict__ boff,
+                                                     const int *__restrict__ roff, const int *__restrict__ rlist,
+                                                     double dt, double tol, int cap, PgdState *__restrict__ out,
+                                                     int lds_ld) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double sh[4][BS / RELCP_WAVE];
+    __shared__ PgdState st;
+    const int p = blockIdx.x;
+    const int b0 = boff[p], b1 = boff[p + 1], r0 = roff[p], r1 = roff[p + 1];
+    const T dtT = (T)dt;
+    auto run = [&](const auto &V) {
+        for (int i = b0 + threadIdx.x; i < b1; i += BS) scatter_body<T, 0>(R, B, i, T(0), V);
+        __syncthreads();
+        double ss = 0.0, sy = 0.0, yy = 0.0, res = 0.0;
+        for (int k = r0 + threadIdx.x; k < r1; k += BS) gather_row<T, 0>(R, rlist[k], T(0), dtT, V, ss, sy, yy, res);
+        block_reduce4n<BS / RELCP_WAVE>(ss, sy, yy, res, sh);
+        if (threadIdx.x == 0) {
+            PgdState s0{};
+            s0.alpha = 1.0;
+            s0.iter = -1;
+            st = pgd_next(s0, ss, sy, yy, res, tol);
+        }
+        __syncthreads();
+        while (!st.conv && st.iter < cap) {
+            const T al = (T)st.alpha;
+            for (int i = b0 + threadIdx.x; i < b1; i += BS) scatter_body<T, 1>(R, B, i, al, V);
+            __syncthreads();
+            ss = sy = yy = res = 0.0;
+            for (int k = r0 + threadIdx.x; k < r1; k += BS)
+                gather_row<T, 1>(R, rlist[k], al, dtT, V, ss, sy, yy, res);
+            block_reduce4n<BS / RELCP_WAVE>(ss, sy, yy, res, sh);
+            if (threadIdx.x == 0) st = pgd_next(st, ss, sy, yy, res, tol);
+            __syncthreads();
+        }
+    };
+    if (LDSV) {
+        VLocal<T> V{reinterpret_cast<T *>(smem_raw), lds_ld, b0};
+        run(V);
+        for (int i = b0 + threadIdx.x; i < b1; i += BS)
+            for (int k = 0; k < 6; ++k) B.vc[k * B.ld + i] = V(k, i);
+    } else {
+        run(VGlobal<T>{B.vc, B.ld});
+    }
+    if (threadIdx.x == 0) out[p] = st;
+}
+
+// rows grouped by packing: count the rows of each packing in [m0, m1)
+__global__ void k_rows_per_packing(int m0, int m1, const int *__restrict__ ia, const int *__restrict__ body_batch,
+                                   int *__restrict__ cnt) {
+    int r = m0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < m1) atomicAdd(cnt + body_batch[ia[r]], 1);
+}
+
+// New row list after appending rows [m_old, m_old + nv) (themselves grouped
+// by packing): old position t of packing p moves to t + E[p]; the k-th new
+// row goes to roff_old[p + 1] + k, where E = exclusive scan of the new
+// rows' per-packing counts.
+__global__ void k_rlist_merge(int m_old, int nv, const int *__restrict__ rlist_old, const int *__restrict__ ia,
+                              const int *__restrict__ body_batch, const int *__restrict__ roff_old,
+                              const int *__restrict__ E, int *__restrict__ rlist_new) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < m_old) {
+        int r = rlist_old[t];
+        rlist_new[t + E[body_batch[ia[r]]]] = r;
+    } else if (t < m_old + nv) {
+        int k = t - m_old;
+        int r = m_old + k;
+        rlist_new[roff_old[body_batch[ia[r]] + 1] + k] = r;
+    }
+}
+
+__global__ void k_add_arrays(int n, const int *__restrict__ a, const int *__restrict__ b, int *__restrict__ c) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) c[i] = a[i] + b[i];
+}
+
+__global__ void k_iota(int n, int *__restrict__ v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = i;
 }
 
 // Advance the state from the last gather without another scatter (end of a
@@ -476,6 +620,49 @@ void launch_lcp_gather(int mode, const RowsT<T> &r, const BodiesT<T> &b, double 
 }
 
 int lcp_gather_blocks(int m) { return nblk(m > 0 ? m : 1, kThreads); }
+
+template <typename T, int BS, bool LDSV>
+static int launch_res(const ResidentArgs<T> &a, hipStream_t s) {
+    size_t lds = LDSV ? (size_t)6 * a.lds_ld * sizeof(T) : 0;
+    auto fn = k_lcp_resident<T, BS, LDSV>;
+    if (lds > 0) {
+        if (hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+            hipSuccess)
+            return -1;
+    }
+    hipLaunchKernelGGL(fn, dim3(a.npk), dim3(BS), lds, s, a.R, a.B, a.boff, a.roff, a.rlist, a.dt, a.tol, a.cap,
+                       a.out, a.lds_ld);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T>
+int launch_lcp_resident(const ResidentArgs<T> &a, int block, bool lds, hipStream_t s) {
+    if (a.npk <= 0) return 0;
+    switch (block) {
+        case 256: return lds ? launch_res<T, 256, true>(a, s) : launch_res<T, 256, false>(a, s);
+        case 512: return lds ? launch_res<T, 512, true>(a, s) : launch_res<T, 512, false>(a, s);
+        default: return lds ? launch_res<T, 1024, true>(a, s) : launch_res<T, 1024, false>(a, s);
+    }
+}
+template int launch_lcp_resident<double>(const ResidentArgs<double> &, int, bool, hipStream_t);
+template int launch_lcp_resident<float>(const ResidentArgs<float> &, int, bool, hipStream_t);
+
+void launch_rows_per_packing(int m0, int m1, const int *ia, const int *body_batch, int *cnt, hipStream_t s) {
+    if (m1 > m0) hipLaunchKernelGGL(k_rows_per_packing, dim3(nblk(m1 - m0, 256)), dim3(256), 0, s, m0, m1, ia,
+                                    body_batch, cnt);
+}
+void launch_rlist_merge(int m_old, int nv, const int *rlist_old, const int *ia, const int *body_batch,
+                        const int *roff_old, const int *E, int *rlist_new, hipStream_t s) {
+    if (m_old + nv > 0)
+        hipLaunchKernelGGL(k_rlist_merge, dim3(nblk(m_old + nv, 256)), dim3(256), 0, s, m_old, nv, rlist_old, ia,
+                           body_batch, roff_old, E, rlist_new);
+}
+void launch_add_arrays(int n, const int *a, const int *b, int *c, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_add_arrays, dim3(nblk(n, 256)), dim3(256), 0, s, n, a, b, c);
+}
+void launch_iota(int n, int *v, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_iota, dim3(nblk(n, 256)), dim3(256), 0, s, n, v);
+}
 
 void launch_pgd_init(const PgdCtl &C, hipStream_t s) {
     hipLaunchKernelGGL(k_pgd_init, dim3(1), dim3(64), 0, s, C);

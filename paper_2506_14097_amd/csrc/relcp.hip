@@ -135,13 +135,13 @@ struct relcp_ctx {
     DBuf<unsigned long long> red;  // [0] max displacement bits, [1] min Phi key, [2] min margin key
     DBuf<int> scan_scratch, dtotal;
     // optional kernel timing (HIP events on the stream)
-    static constexpr int kClasses = 5;
+    static constexpr int kClasses = 6;
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_class;
     size_t ev_used = 0;
-    long long t_count[kClasses] = {0, 0, 0, 0, 0};
-    double t_ms[kClasses] = {0, 0, 0, 0, 0};
+    long long t_count[kClasses] = {0, 0, 0, 0, 0, 0};
+    double t_ms[kClasses] = {0, 0, 0, 0, 0, 0};
     // record a start/stop event pair around launch `f` when timing is on
     template <typename F>
     void timed(int cls, F &&f) {
@@ -178,6 +178,20 @@ struct relcp_ctx {
     // pinned host mirrors
     PgdState *pst_h = nullptr;  // fin and the done slot
     int last_iters[2] = {8, 8};  // previous solve's iteration count (FP32, FP64)
+    // LCP execution: mode 0 = automatic, 1 = grid (two passes per iteration
+    // over all rows), 2 = resident (one workgroup per packing, one launch)
+    int lcp_mode = 0, res_block = 256, res_lds = 1;
+    int maxpk = 0;                       // bodies of the largest packing
+    DBuf<int> boff_d, roff, rlist, rlist2, rcnt, rE;
+    DBuf<PgdState> pk_state;
+    PgdState *pk_state_h = nullptr;
+    bool resident_mode() const {
+        if (lcp_mode == 1) return false;
+        if (lcp_mode == 2) return true;
+        return maxpk <= 8192;
+    }
+    void rows_by_packing_init(int m0);
+    void rows_by_packing_append(int m_old, int nv);
     int *int_h = nullptr;
     unsigned long long *red_h = nullptr;
     double *dbl_h = nullptr;
@@ -202,6 +216,9 @@ struct relcp_ctx {
         if (int_h) (void)hipHostFree(int_h);
         if (red_h) (void)hipHostFree(red_h);
         if (dbl_h) (void)hipHostFree(dbl_h);
+        if (pk_state_h) (void)hipHostFree(pk_state_h);
+        boff_d.release(); roff.release(); rlist.release(); rlist2.release(); rcnt.release(); rE.release();
+        pk_state.release();
         for (auto e : ev_pool) (void)hipEventDestroy(e);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
@@ -390,6 +407,16 @@ void relcp_ctx::upload_bodies(const relcp_bodies *B, const relcp_shapes *S) {
     boxes.ensure(3 * nbatch);
     HIP_OK(hipMemcpyAsync(boxes.p, box.data(), 3 * nbatch * sizeof(double), hipMemcpyHostToDevice, stream));
     HIP_OK(hipMemsetAsync(fext.p, 0, 6 * N * sizeof(double), stream));
+    boff_d.ensure(nbatch + 1);
+    HIP_OK(hipMemcpyAsync(boff_d.p, boff.data(), (nbatch + 1) * sizeof(int), hipMemcpyHostToDevice, stream));
+    maxpk = 0;
+    for (int pk = 0; pk < nbatch; ++pk) maxpk = std::max(maxpk, boff[pk + 1] - boff[pk]);
+    roff.ensure(nbatch + 2);
+    rcnt.ensure(nbatch + 2);
+    rE.ensure(nbatch + 2);
+    pk_state.ensure(nbatch);
+    if (pk_state_h) HIP_OK(hipHostFree(pk_state_h));
+    HIP_OK(hipHostMalloc((void **)&pk_state_h, nbatch * sizeof(PgdState), hipHostMallocDefault));
     has_fext = false;
     nprev = 0;
     m = 0;
@@ -431,6 +458,9 @@ void relcp_ctx::ensure_rows(int need) {
     realloc_soa(rg32, 1, old, nld, m, stream);
     csr_ent.release();
     csr_ent.ensure(2 * nld);
+    realloc_soa(rlist, 1, old, nld, m, stream);
+    rlist2.release();
+    rlist2.ensure(nld);
     ldr = (int)nld;
 }
 
@@ -559,6 +589,25 @@ void relcp_ctx::build_rows(int nsel, int rec, const double *snsd, const double *
     m += nsel;
 }
 
+// Rows grouped by packing for the resident LCP kernel: rlist holds row
+// indices packing by packing, roff the packing offsets into rlist.
+void relcp_ctx::rows_by_packing_init(int m0) {
+    HIP_OK(hipMemsetAsync(rcnt.p, 0, (nbatch + 1) * sizeof(int), stream));
+    launch_rows_per_packing(0, m0, ria.p, body_batch.p, rcnt.p, stream);
+    exclusive_scan(rcnt.p, roff.p, nbatch + 1, nullptr, scan_scratch, stream);
+    launch_iota(m0, rlist.p, stream);
+}
+
+void relcp_ctx::rows_by_packing_append(int m_old, int nv) {
+    HIP_OK(hipMemsetAsync(rcnt.p, 0, (nbatch + 1) * sizeof(int), stream));
+    launch_rows_per_packing(m_old, m_old + nv, ria.p, body_batch.p, rcnt.p, stream);
+    exclusive_scan(rcnt.p, rE.p, nbatch + 1, nullptr, scan_scratch, stream);
+    launch_rlist_merge(m_old, nv, rlist.p, ria.p, body_batch.p, roff.p, rE.p, rlist2.p, stream);
+    launch_add_arrays(nbatch + 1, roff.p, rE.p, roff.p, stream);
+    std::swap(rlist.p, rlist2.p);
+    std::swap(rlist.cap, rlist2.cap);
+}
+
 void relcp_ctx::rebuild_csr() {
     csr_cnt.ensure(2 * (size_t)(n + 1));
     csr_off.ensure(n + 1);
@@ -588,6 +637,28 @@ int relcp_ctx::solve(double dt, double tol, int &iters, double &res) {
     Bd.ld = n;
     Bd.off = csr_off.p;
     Bd.ent = csr_ent.p;
+    if (resident_mode()) {
+        ResidentArgs<T> a{R, Bd, nbatch, boff_d.p, roff.p, rlist.p, dt, lcp_fixed > 0 ? -1.0 : tol,
+                          lcp_fixed > 0 ? lcp_fixed : lcp_max_iters, pk_state.p, maxpk};
+        const bool lds = res_lds && (size_t)6 * maxpk * sizeof(T) <= 150 * 1024;
+        int rc = 0;
+        timed(5, [&] { rc = launch_lcp_resident<T>(a, res_block, lds, stream); });
+        if (rc != 0 && lds) timed(5, [&] { rc = launch_lcp_resident<T>(a, res_block, false, stream); });
+        if (rc != 0) throw Error{RELCP_E_DEVICE, "resident LCP launch failed"};
+        HIP_OK(hipMemcpyAsync(pk_state_h, pk_state.p, nbatch * sizeof(PgdState), hipMemcpyDeviceToHost, stream));
+        sync();
+        bool conv = true;
+        iters = 0;
+        res = 0.0;
+        for (int k = 0; k < nbatch; ++k) {
+            iters = std::max(iters, pk_state_h[k].iter);
+            res = std::max(res, pk_state_h[k].res);
+            conv = conv && pk_state_h[k].conv;
+        }
+        if (!std::isfinite(res)) return RELCP_E_NAN;
+        if (lcp_fixed > 0) return RELCP_OK;
+        return conv ? RELCP_OK : RELCP_E_LCP_MAXITER;
+    }
     partials.ensure(lcp_partials_needed(m));
     // pst: S[0], S[1], fin, then a slot whose first int is the done flag
     pst.ensure(4);
@@ -675,6 +746,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     ensure_rows(m0);
     build_rows(m0, 0, snsd0.p, nullptr, warm_start == RELCP_WS_PREV, dt);
     rebuild_csr();
+    if (resident_mode()) rows_by_packing_init(m0);
     t_other += tm.ms();
 
     int status = RELCP_OK;
@@ -706,7 +778,9 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         S.residual_fp64 = res64;
         S.residual_lowp = res;
         if (status != RELCP_OK) break;
-        // W_n = gamma^T A gamma
+        // W_n = gamma^T A gamma (its block partials need their own sizing:
+        // the resident LCP mode never touches the grid-mode partials)
+        partials.ensure(lcp_partials_needed(m));
         work_out.ensure(1);
         ticket.ensure(1);
         HIP_OK(hipMemsetAsync(ticket.p, 0, sizeof(unsigned), stream));
@@ -760,8 +834,12 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         }
         // augment: rows generated at C_{n+1}, pulled back (per-row constant)
         ensure_rows(m + nv);
-        build_rows(nv, rec + 1, snsdt.p, vc64.p, false, dt);
-        rebuild_csr();
+        {
+            const int m_old = m;
+            build_rows(nv, rec + 1, snsdt.p, vc64.p, false, dt);
+            rebuild_csr();
+            if (resident_mode()) rows_by_packing_append(m_old, nv);
+        }
         t_other += tm.ms();
     }
     S.recursions = rec;
@@ -1033,6 +1111,120 @@ int relcp_get_contacts(const relcp_ctx *cc, int32_t *ia, int32_t *ib, int32_t *r
     });
 }
 
+int relcp_set_lcp_config(relcp_ctx *ctx, int32_t mode, int32_t block, int32_t lds) {
+    if (!ctx) return RELCP_E_INVALID;
+    if (mode < 0 || mode > 2 || (block != 256 && block != 512 && block != 1024)) {
+        ctx->err = "mode must be 0..2 and block 256, 512 or 1024";
+        return RELCP_E_INVALID;
+    }
+    ctx->lcp_mode = mode;
+    ctx->res_block = block;
+    ctx->res_lds = lds ? 1 : 0;
+    return RELCP_OK;
+}
+
+// Time every LCP configuration on the rows of the last accepted step (the
+// same start, restored before each trial) and keep the fastest.
+int relcp_autotune(relcp_ctx *ctx, double dt, double lcp_tol, int32_t reps, int32_t *config, double *ms) {
+    if (!ctx) return RELCP_E_INVALID;
+    return guarded(ctx, [&]() -> int {
+        if (ctx->m_acc <= 0 || ctx->m != ctx->m_acc) throw Error{RELCP_E_INVALID, "autotune needs an accepted step"};
+        if (reps < 1) reps = 1;
+        const int M = ctx->m;
+        DBuf<double> s64;
+        DBuf<float> s32;
+        s64.ensure(2 * (size_t)M);
+        s32.ensure(2 * (size_t)M);
+        auto cp = [&](void *dst, const void *src, size_t b) {
+            HIP_OK(hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToDevice, ctx->stream));
+        };
+        cp(s64.p, ctx->rgam64.p, M * 8);
+        cp(s64.p + M, ctx->rg64.p, M * 8);
+        cp(s32.p, ctx->rgam32.p, M * 4);
+        cp(s32.p + M, ctx->rg32.p, M * 4);
+        {
+            // group the rows by packing (the list is not kept in grid mode)
+            std::vector<int> ia(M), bb(ctx->n), order(M);
+            HIP_OK(hipMemcpyAsync(ia.data(), ctx->ria.p, M * 4, hipMemcpyDeviceToHost, ctx->stream));
+            HIP_OK(hipMemcpyAsync(bb.data(), ctx->body_batch.p, ctx->n * 4, hipMemcpyDeviceToHost, ctx->stream));
+            ctx->sync();
+            std::vector<int> cnt(ctx->nbatch + 1, 0);
+            for (int r = 0; r < M; ++r) cnt[bb[ia[r]] + 1]++;
+            for (int k = 0; k < ctx->nbatch; ++k) cnt[k + 1] += cnt[k];
+            std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+            for (int r = 0; r < M; ++r) order[pos[bb[ia[r]]]++] = r;
+            HIP_OK(hipMemcpyAsync(ctx->rlist.p, order.data(), M * 4, hipMemcpyHostToDevice, ctx->stream));
+            HIP_OK(hipMemcpyAsync(ctx->roff.p, cnt.data(), (ctx->nbatch + 1) * 4, hipMemcpyHostToDevice,
+                                  ctx->stream));
+            ctx->sync();
+        }
+        struct Cfg {
+            int mode, block, lds;
+        };
+        std::vector<Cfg> cfgs = {{1, 256, 0}};
+        for (int b : {256, 512, 1024})
+            for (int l : {0, 1}) cfgs.push_back({2, b, l});
+        const int save_mode = ctx->lcp_mode, save_block = ctx->res_block, save_lds = ctx->res_lds;
+        hipEvent_t e0, e1;
+        HIP_OK(hipEventCreate(&e0));
+        HIP_OK(hipEventCreate(&e1));
+        double best = 1e300;
+        Cfg bestc = cfgs[0];
+        for (const Cfg &c : cfgs) {
+            if (c.lds && (size_t)6 * ctx->maxpk * (ctx->precision == 32 ? 4 : 8) > 150 * 1024) continue;
+            ctx->lcp_mode = c.mode;
+            ctx->res_block = c.block;
+            ctx->res_lds = c.lds;
+            double tot = 0.0;
+            for (int r = 0; r < reps; ++r) {
+                cp(ctx->rgam64.p, s64.p, M * 8);
+                cp(ctx->rg64.p, s64.p + M, M * 8);
+                cp(ctx->rgam32.p, s32.p, M * 4);
+                cp(ctx->rg32.p, s32.p + M, M * 4);
+                int it = 0;
+                double res = 0;
+                HIP_OK(hipEventRecord(e0, ctx->stream));
+                int rc = ctx->precision == 32 ? ctx->solve<float>(dt, lcp_tol, it, res)
+                                              : ctx->solve<double>(dt, lcp_tol, it, res);
+                HIP_OK(hipEventRecord(e1, ctx->stream));
+                HIP_OK(hipEventSynchronize(e1));
+                if (rc != RELCP_OK) {
+                    tot = 1e300;
+                    break;
+                }
+                float t = 0.f;
+                HIP_OK(hipEventElapsedTime(&t, e0, e1));
+                tot += t;
+            }
+            double avg = tot / reps;
+            if (ms) ms[&c - &cfgs[0]] = avg;
+            if (avg < best) {
+                best = avg;
+                bestc = c;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        cp(ctx->rgam64.p, s64.p, M * 8);
+        cp(ctx->rg64.p, s64.p + M, M * 8);
+        cp(ctx->rgam32.p, s32.p, M * 4);
+        cp(ctx->rg32.p, s32.p + M, M * 4);
+        ctx->sync();
+        s64.release();
+        s32.release();
+        (void)save_mode; (void)save_block; (void)save_lds;
+        ctx->lcp_mode = bestc.mode;
+        ctx->res_block = bestc.block;
+        ctx->res_lds = bestc.lds;
+        if (config) {
+            config[0] = bestc.mode;
+            config[1] = bestc.block;
+            config[2] = bestc.lds;
+        }
+        return RELCP_OK;
+    });
+}
+
 int relcp_set_timing(relcp_ctx *ctx, int32_t enable) {
     if (!ctx) return RELCP_E_INVALID;
     return guarded(ctx, [&]() -> int {
@@ -1209,6 +1401,7 @@ int relcp_lcp_solve_device(int32_t nb, int32_t m, const int32_t *ia, const int32
     try {
         HIP_OK(hipHostMalloc((void **)&c.pst_h, 2 * sizeof(PgdState), hipHostMallocDefault));
         c.n = nb;
+        c.lcp_mode = 1;
         c.lcp_max_iters = max_iters > 0 ? max_iters : 100000;
         c.K.ensure(9 * (size_t)nb);
         c.K32.ensure(9 * (size_t)nb);

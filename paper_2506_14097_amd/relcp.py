@@ -86,6 +86,8 @@ _SIGS = {
     "relcp_set_state": (C.c_int, [C.c_void_p, C.POINTER(Bodies), C.POINTER(Shapes)]),
     "relcp_affine_rescale": (C.c_int, [C.c_void_p, C.c_double]),
     "relcp_get_contacts": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6),
+    "relcp_set_lcp_config": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
+    "relcp_autotune": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_void_p]),
     "relcp_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "relcp_get_timing": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "relcp_snsd_device": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
@@ -220,7 +222,24 @@ class Simulation:
         if rc != OK:
             raise RelcpError(rc, self._err())
 
-    TIMING_CLASSES = ("lcp_scatter", "lcp_gather", "snsd", "pairs", "trial")
+    TIMING_CLASSES = ("lcp_scatter", "lcp_gather", "snsd", "pairs", "trial", "lcp_resident")
+    LCP_CONFIGS = ("grid", "resident-256", "resident-256-lds", "resident-512", "resident-512-lds",
+                   "resident-1024", "resident-1024-lds")
+
+    def set_lcp_config(self, mode, block=256, lds=True):
+        """mode: 0 automatic, 1 grid, 2 resident (one workgroup per packing)."""
+        rc = lib().relcp_set_lcp_config(self.ctx, mode, block, 1 if lds else 0)
+        if rc != OK:
+            raise RelcpError(rc, self._err())
+
+    def autotune(self, dt, lcp_tol, reps=3):
+        cfg = np.zeros(3, np.int32)
+        ms = np.zeros(7)
+        rc = lib().relcp_autotune(self.ctx, dt, lcp_tol, reps, _ptr(cfg), _ptr(ms))
+        if rc != OK:
+            raise RelcpError(rc, self._err())
+        return dict(mode=int(cfg[0]), block=int(cfg[1]), lds=bool(cfg[2]),
+                    ms={k: float(v) for k, v in zip(self.LCP_CONFIGS, ms)})
 
     def set_timing(self, on):
         rc = lib().relcp_set_timing(self.ctx, 1 if on else 0)
@@ -228,8 +247,8 @@ class Simulation:
             raise RelcpError(rc, self._err())
 
     def get_timing(self, reset=True):
-        cnt = np.zeros(5, np.int32)
-        ms = np.zeros(5)
+        cnt = np.zeros(6, np.int32)
+        ms = np.zeros(6)
         rc = lib().relcp_get_timing(self.ctx, _ptr(cnt), _ptr(ms), 1 if reset else 0)
         if rc != OK:
             raise RelcpError(rc, self._err())

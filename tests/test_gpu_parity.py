@@ -232,16 +232,18 @@ def _compare_step(res_gpu, sim, ref, tol_u):
     return True
 
 
+@pytest.mark.parametrize("mode", [1, 2], ids=["grid", "resident"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("precision", [64, 32])
-def test_step_overdamped_packing(dev, seed, precision):
+def test_step_overdamped_packing(dev, seed, precision, mode):
     S = compressed_packing(seed, 150, 26)
     S = dict(S, x=S["x"] * 0.99, box=S["box"] * 0.99)
     kw = dict(dt=5e-3, eps=1e-5, skin=0.2)
-    print("step packing seed", seed, "precision", precision, flush=True)
+    print("step packing seed", seed, "precision", precision, "mode", mode, flush=True)
     ref = O.relcp_step(S["x"], S["q"], S["kind"], S["shape"], S["rho_xi"], S["box"], tol=1e-12, lcp_mode=1,
                        dt=kw["dt"], eps=kw["eps"], skin=kw["skin"])
     sim = sim_from(S, precision=precision, skin=kw["skin"], warm_start=R.WS_COLD)
+    sim.set_lcp_config(mode, 256, True)
     res = sim.step(kw["dt"], kw["eps"], 1e-12 if precision == 64 else 1e-9)
     print("  gpu recursions", res["recursions"], "contacts", list(res["n_contacts"]), "iters",
           list(res["lcp_iters"]), "oracle", list(ref["n_contacts"]), list(ref["lcp_iters"]), flush=True)
@@ -305,7 +307,9 @@ def test_inertial_two_ellipsoids_trajectory(dev):
     assert contacts > 0
 
 
-def test_batched_packings_match_per_packing_oracle(dev):
+@pytest.mark.parametrize("cfg", [(1, 256, False), (2, 256, True), (2, 512, False), (2, 1024, True)],
+                         ids=["grid", "res256lds", "res512", "res1024lds"])
+def test_batched_packings_match_per_packing_oracle(dev, cfg):
     parts = [compressed_packing(s, 120, 24) for s in (3, 4, 5)]
     x = np.concatenate([p["x"] * 0.99 for p in parts])
     off = np.cumsum([0] + [len(p["x"]) for p in parts]).astype(np.int32)
@@ -314,6 +318,7 @@ def test_batched_packings_match_per_packing_oracle(dev):
              box=np.stack([p["box"] * 0.99 for p in parts]))
     sim = R.Simulation(B["x"], B["q"], B["kind"], B["shape"], B["rho_xi"], B["box"], batch_off=off, skin=0.2,
                        warm_start=R.WS_COLD)
+    sim.set_lcp_config(*cfg)
     res = sim.step(5e-3, 1e-5, 1e-12)
     assert res["status"] == 0
     xg, qg, Ug = sim.get_state()
@@ -353,3 +358,31 @@ def test_error_paths_leave_state_untouched(dev):
     assert np.array_equal(x0, x1) and np.array_equal(q0, q1)
     sim2 = sim_from(S, skin=0.2, lcp_max_iters=1)
     assert sim2.step(5e-3, 1e-5, 1e-12, raise_on_error=False)["status"] == R.E_LCP_MAXITER
+
+
+def test_batch_of_uneven_packings_and_autotune(dev):
+    """Many independent packings of uneven size (log-uniform body counts,
+    uneven densities) in one context: every packing matches its own oracle
+    step; the autotuner then picks a configuration and the next step still
+    matches."""
+    B = I.batch_of_packings(11, 12, 30, 200, 0.12, 0.17, sphere_phi=0.3)
+    x = B["x"] * 0.985
+    box = B["box"] * 0.985
+    off = B["batch_off"]
+    sim = R.Simulation(x, B["q"], B["kind"], B["shape"], B["rho_xi"], box, batch_off=off, skin=0.2)
+    res = sim.step(5e-3, 1e-5, 1e-12)
+    assert res["status"] == 0
+    xg, qg, Ug = sim.get_state()
+    for k in range(len(off) - 1):
+        sl = slice(off[k], off[k + 1])
+        ref = O.relcp_step(x[sl], B["q"][sl], B["kind"][sl], B["shape"][sl], B["rho_xi"][sl], box[k], dt=5e-3,
+                           eps=1e-5, tol=1e-12, skin=0.2, lcp_mode=1)
+        assert ref["status"] == 0
+        if ref["n_rows"]:
+            assert rel(Ug[sl], ref["U"]) < 1e-7
+        assert np.abs(xg[sl] - ref["x"]).max() < 1e-8
+    choice = sim.autotune(5e-3, 1e-12, reps=2)
+    assert choice["mode"] in (1, 2)
+    x2, q2 = xg.copy(), qg.copy()
+    res2 = sim.step(5e-3, 1e-5, 1e-12)
+    assert res2["status"] == 0
