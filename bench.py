@@ -29,6 +29,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
+# HBM bytes per non-empty launch of the LCP passes at this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, the scales a plain
+# copy of known size reads), recorded in profiles/lcp_passes_100k_hbm_traffic.md
+# for the kernel source with the given sha256 prefix (stale once it changes).
+MEASURED_TRAFFIC = {"sha256_prefix": "05a6215d8c110f99", "lcp_scatter": 2.4678e7, "lcp_gather": 1.7280e7}
+
+
+def kernel_source_sha():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2506_14097_amd", "csrc", "lcp.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -98,6 +110,83 @@ def run_steps(sim, shape, box, phi, nsteps, args, stats=None):
     return box, phi
 
 
+def packings_workload(args):
+    """Batched workload: 512 independent periodic packings (body counts
+    log-uniform in [200, 5000], target volume fractions uniform in [0.3,
+    0.5]) in one context; set-up compresses each packing to its own target,
+    then every timed step compresses each packing by dphi and steps all of
+    them together (resident LCP: one workgroup per packing, one launch)."""
+    import torch
+    from paper_2506_14097_amd import inputs as I
+    from paper_2506_14097_amd import relcp as R
+    t0 = time.time()
+    B = I.batch_of_packings(3, args.packings, 200, 5000, 0.3, 0.5, sphere_phi=0.3, rescale=False)
+    off = B["batch_off"]
+    npk = len(off) - 1
+    log("placed %d packings, %d bodies in %.1fs" % (npk, off[-1], time.time() - t0))
+    sim = R.Simulation(B["x"], B["q"], B["kind"], B["shape"], B["rho_xi"], B["box"], batch_off=off,
+                       precision=args.precision, skin=args.skin, warm_start=R.WS_PREV)
+    phi = B["phi"].copy()
+    target = B["phi_target"]
+    rate = 0.015
+    k = 0
+    t0 = time.time()
+    while np.any(phi < target - 1e-12):
+        nxt = np.minimum(target, phi * (1 + rate))
+        s = (phi / nxt) ** (1.0 / 3.0)
+        sim.affine_rescale_packings(s)
+        res = sim.step(args.dt, args.eps, args.tol, raise_on_error=False)
+        if res["status"] != 0:
+            sim.affine_rescale_packings(1.0 / s)
+            rate *= 0.5
+            if rate < 1e-5:
+                raise RuntimeError("set-up compression stalled (status %d)" % res["status"])
+            continue
+        phi = nxt
+        k += 1
+        if k % 10 == 0:
+            log("set-up compression: step %d mean phi %.4f contacts %d (%.1fs)" % (k, phi.mean(),
+                                                                                 res["n_contacts_final"],
+                                                                                 time.time() - t0))
+    log("set-up done after %d steps (%.1fs)" % (k, time.time() - t0))
+
+    def advance(nsteps, stats=None):
+        nonlocal phi
+        for _ in range(nsteps):
+            nxt = phi + args.dphi
+            sim.affine_rescale_packings((phi / nxt) ** (1.0 / 3.0))
+            phi = nxt
+            r = sim.step(args.dt, args.eps, args.tol)
+            if stats is not None:
+                stats.append(r)
+
+    advance(1)
+    tune = sim.autotune(args.dt, args.tol, reps=2)
+    log("autotuned LCP configuration: %s" % tune)
+    advance(args.warmup)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    advance(args.steps, stats)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sim.set_timing(True)
+    sim.get_timing(reset=True)
+    advance(args.roofline_steps)
+    tm = sim.get_timing(reset=True)
+    out = {"metric": "packing-steps/s, %d independent periodic ellipsoid packings in one context" % npk,
+           "value": npk * args.steps / el, "unit": "packing-steps/s", "steps": args.steps,
+           "ms_per_step": 1e3 * el / args.steps, "bodies": int(off[-1]), "packings": npk,
+           "dtype": "f32+f64" if args.precision == 32 else "f64",
+           "pgd_iters_per_step_max_over_packings": float(np.mean([r["lcp_iters_total"] for r in stats])),
+           "contacts_final": int(stats[-1]["n_contacts_final"]),
+           "recursions_per_step": float(np.mean([r["recursions"] for r in stats])),
+           "max_overlap": float(max(r["max_overlap"] for r in stats)), "autotune": tune,
+           "kernel_ms": {k2: round(v[1], 3) for k2, v in tm.items()},
+           "kernel_launches": {k2: v[0] for k2, v in tm.items()}}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(args, bench_pairs, bench_rec):
     """The CPU oracle (FP64, single thread) on a bounded sample of the same
     workload: one step of a periodic packing from the same generator.  The
@@ -144,6 +233,8 @@ def main():
     ap.add_argument("--roofline-steps", type=int, default=5)
     ap.add_argument("--cpu-n", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="compaction100k", choices=("compaction100k", "packings512"))
+    ap.add_argument("--packings", type=int, default=512)
     ap.add_argument("--copy-probe-mb", type=float, default=0.0,
                     help="only run a device-to-device copy of this many MB (reference for HBM counters)")
     args = ap.parse_args()
@@ -162,6 +253,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log("copy probe: 5 copies of %d bytes" % (4 * nel))
+        return
+    if args.workload == "packings512":
+        packings_workload(args)
         return
     R.lib()
 
@@ -189,9 +283,9 @@ def main():
     box, phi = run_steps(sim, shape, box, phi, args.roofline_steps, args, rstats)
     tm = sim.get_timing(reset=True)
     sim.set_timing(False)
-    w_lo = 4 if args.precision == 32 else 8
     nb = args.n
     tot_bytes = {"lcp_gather": 0.0, "lcp_scatter": 0.0}
+    busy = 0  # launches that did work (the rest return at once after convergence)
     for s in rstats:
         for m, it, it64 in zip(s["n_contacts"], s["lcp_iters"], s["lcp_iters64"]):
             itlo = it - it64
@@ -200,13 +294,17 @@ def main():
                     tot_bytes[cls] += (itlo + 1) * lcp_bytes(cls, m, nb, 4) + (it64 + 1) * lcp_bytes(cls, m, nb, 8)
                 else:
                     tot_bytes[cls] += (it + 1) * lcp_bytes(cls, m, nb, 8)
+            busy += (itlo + 1 + it64 + 1) if args.precision == 32 else (it + 1)
     dom = max(tm, key=lambda k: tm[k][1])
     cnt, ms = tm[dom]
     if dom in tot_bytes:
         achieved = tot_bytes[dom] / (ms * 1e-3) / 1e9
+        traffic = None
+        if kernel_source_sha() == MEASURED_TRAFFIC["sha256_prefix"] and args.n == 100000 and args.precision == 32:
+            traffic = MEASURED_TRAFFIC[dom]
         roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launches": cnt, "avg_us": 1e3 * ms / max(cnt, 1),
-                "bytes_per_launch": tot_bytes[dom] / max(cnt, 1)}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "launches": cnt, "busy_launches": busy,
+                "avg_us": 1e3 * ms / max(busy, 1), "bytes_per_launch": tot_bytes[dom] / max(busy, 1)}
     else:
         roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": None, "traffic": None, "launches": cnt, "avg_us": 1e3 * ms / max(cnt, 1)}

@@ -139,6 +139,8 @@ RELCP_API int relcp_set_state(relcp_ctx *ctx, const relcp_bodies *bodies, const 
 
 /* Isotropic affine compression x <- s x, box <- s box (all packings). */
 RELCP_API int relcp_affine_rescale(relcp_ctx *ctx, double s);
+/* The same with one factor per packing (host array of n_batch values). */
+RELCP_API int relcp_affine_rescale_packings(relcp_ctx *ctx, const double *s);
 
 /* Rows of the last accepted step (caller buffers of n_contacts_final
  * entries; any may be NULL): body pair (caller's indices, ia < ib),

@@ -1075,6 +1075,43 @@ int relcp_affine_rescale(relcp_ctx *ctx, double s) {
     });
 }
 
+__global__ void k_scale_packings(int n, double *__restrict__ x, const int *__restrict__ body_batch,
+                                 const double *__restrict__ s) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        double f = s[body_batch[i]];
+        x[i] *= f;
+        x[n + i] *= f;
+        x[2 * n + i] *= f;
+    }
+}
+
+int relcp_affine_rescale_packings(relcp_ctx *ctx, const double *s) {
+    if (!ctx || !s) return RELCP_E_INVALID;
+    return guarded(ctx, [&]() -> int {
+        for (int pk = 0; pk < ctx->nbatch; ++pk) {
+            if (!(s[pk] > 0) || !std::isfinite(s[pk])) throw Error{RELCP_E_INVALID, "scale factors must be positive"};
+            for (int k = 0; k < 3; ++k) {
+                double L = ctx->box[3 * pk + k] * s[pk];
+                if (L > 0 && L < 2.0 * (ctx->rmax[pk] + ctx->skin))
+                    throw Error{RELCP_E_INVALID, "box would become smaller than 2 (R_max + skin)"};
+            }
+        }
+        for (int pk = 0; pk < ctx->nbatch; ++pk)
+            for (int k = 0; k < 3; ++k) ctx->box[3 * pk + k] *= s[pk];
+        DBuf<double> sd;
+        sd.ensure(ctx->nbatch);
+        HIP_OK(hipMemcpyAsync(sd.p, s, ctx->nbatch * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        HIP_OK(hipMemcpyAsync(ctx->boxes.p, ctx->box.data(), ctx->box.size() * sizeof(double),
+                              hipMemcpyHostToDevice, ctx->stream));
+        hipLaunchKernelGGL(k_scale_packings, dim3(nblk(ctx->n, 256)), dim3(256), 0, ctx->stream, ctx->n, ctx->x.p,
+                           ctx->body_batch.p, sd.p);
+        ctx->sync();
+        sd.release();
+        return RELCP_OK;
+    });
+}
+
 int relcp_get_contacts(const relcp_ctx *cc, int32_t *ia, int32_t *ib, int32_t *recursion_added, double *gamma,
                        double *phi_at_discovery, double *normal) {
     relcp_ctx *ctx = const_cast<relcp_ctx *>(cc);

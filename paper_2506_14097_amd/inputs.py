@@ -159,18 +159,20 @@ def spherocylinder_monolayer(seed: int, n: int, area_fraction: float | None = No
 
 
 def batch_of_packings(seed: int, count: int, n_lo: int, n_hi: int, phi_lo: float, phi_hi: float,
-                      sphere_phi: float = 0.25):
+                      sphere_phi: float = 0.25, rescale: bool = True):
     """`count` independent periodic ellipsoid packings with body counts
     log-uniform in [n_lo, n_hi] and volume fractions uniform in
-    [phi_lo, phi_hi], concatenated with batch offsets."""
+    [phi_lo, phi_hi], concatenated with batch offsets.  With rescale=False
+    every packing keeps the fraction of its sphere placement and the drawn
+    fractions are only returned (as targets for a compression run)."""
     rng = rng_for(seed)
     ns = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), size=count)).astype(int)
     phis = rng.uniform(phi_lo, phi_hi, size=count)
-    parts = [ellipsoid_packing(int(rng.integers(1 << 30)), int(k), float(p), sphere_phi=sphere_phi)
-             for k, p in zip(ns, phis)]
+    parts = [ellipsoid_packing(int(rng.integers(1 << 30)), int(k), float(p) if rescale else None,
+                               sphere_phi=sphere_phi) for k, p in zip(ns, phis)]
     off = np.zeros(count + 1, np.int32)
     off[1:] = np.cumsum(ns)
     return dict(x=np.concatenate([p["x"] for p in parts]), q=np.concatenate([p["q"] for p in parts]),
                 kind=np.concatenate([p["kind"] for p in parts]), shape=np.concatenate([p["shape"] for p in parts]),
                 rho_xi=np.concatenate([p["rho_xi"] for p in parts]), box=np.stack([p["box"] for p in parts]),
-                batch_off=off, phi=phis)
+                batch_off=off, phi=np.array([p["phi"] for p in parts]), phi_target=phis)

@@ -85,6 +85,7 @@ _SIGS = {
     "relcp_get_state_device": (C.c_int, [C.c_void_p] + [C.c_void_p] * 4),
     "relcp_set_state": (C.c_int, [C.c_void_p, C.POINTER(Bodies), C.POINTER(Shapes)]),
     "relcp_affine_rescale": (C.c_int, [C.c_void_p, C.c_double]),
+    "relcp_affine_rescale_packings": (C.c_int, [C.c_void_p, C.c_void_p]),
     "relcp_get_contacts": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6),
     "relcp_set_lcp_config": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
     "relcp_autotune": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_void_p]),
@@ -253,6 +254,12 @@ class Simulation:
         if rc != OK:
             raise RelcpError(rc, self._err())
         return {k: (int(c), float(t)) for k, c, t in zip(self.TIMING_CLASSES, cnt, ms)}
+
+    def affine_rescale_packings(self, s):
+        s = _d(s, self.n_batch)
+        rc = lib().relcp_affine_rescale_packings(self.ctx, _ptr(s))
+        if rc != OK:
+            raise RelcpError(rc, self._err())
 
     def get_contacts(self, m):
         ia, ib, rec = np.zeros(m, np.int32), np.zeros(m, np.int32), np.zeros(m, np.int32)
