@@ -294,7 +294,7 @@ def main():
                     tot_bytes[cls] += (itlo + 1) * lcp_bytes(cls, m, nb, 4) + (it64 + 1) * lcp_bytes(cls, m, nb, 8)
                 else:
                     tot_bytes[cls] += (it + 1) * lcp_bytes(cls, m, nb, 8)
-            busy += (itlo + 1 + it64 + 1) if args.precision == 32 else (it + 1)
+            busy += int((itlo + 1 + it64 + 1) if args.precision == 32 else (it + 1))
     dom = max(tm, key=lambda k: tm[k][1])
     cnt, ms = tm[dom]
     if dom in tot_bytes:
@@ -303,7 +303,7 @@ def main():
         if kernel_source_sha() == MEASURED_TRAFFIC["sha256_prefix"] and args.n == 100000 and args.precision == 32:
             traffic = MEASURED_TRAFFIC[dom]
         roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "launches": cnt, "busy_launches": busy,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "launches": int(cnt), "busy_launches": int(busy),
                 "avg_us": 1e3 * ms / max(busy, 1), "bytes_per_launch": tot_bytes[dom] / max(busy, 1)}
     else:
         roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
