@@ -10,8 +10,10 @@ ReLCP step (dt = 5e-3, overlap_tol = 1e-3, lcp_tol = 1e-6, previous-step
 warm start, FP32 products with FP64 residual and acceptance by default).
 
 Prints one JSON line with steps/s, the roofline of the dominant kernel
-(measured with HIP events inside the library on its own stream) and the CPU
-oracle timed on a bounded sample.
+(measured with HIP events inside the library on its own stream), the
+learned warm start against the previous-step one on the same workload
+(projected-gradient iterations and time per step; the model is trained on
+the GPU first, untimed) and the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -46,10 +48,6 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def phi_of(shape, box):
-    return float(np.sum(4.0 / 3.0 * np.pi * shape[:, 0] * shape[:, 1] * shape[:, 2]) / np.prod(box))
-
-
 def lcp_bytes(kind, m, nb, w):
     """Algorithmic bytes of one launch of an LCP pass over m rows, nb bodies,
     word size w (4 = FP32, 8 = FP64).
@@ -63,51 +61,55 @@ def lcp_bytes(kind, m, nb, w):
     return m * (8 + 12 * w) + nb * (4 + 15 * w)
 
 
-def setup(args):
-    from paper_2506_14097_amd import inputs as I
+def learned_comparison(args, state):
+    """Learned against previous-step warm start on the same workload.  The
+    model is trained on the GPU (library kernels) on about a million rows of
+    A_0 logged from a 10,000-ellipsoid compaction (seed 1) at volume
+    fractions 0.40 to 0.55; then two contexts start from the benchmark's
+    state, take three previous-step warm-up steps and `learned_steps` timed
+    steps each, one per warm start."""
+    import torch
+    from paper_2506_14097_amd import learned as L
     from paper_2506_14097_amd import relcp as R
+    from paper_2506_14097_amd.compaction import Compaction
     t0 = time.time()
-    P = I.ellipsoid_packing(args.seed, args.n, sphere_phi=0.3)
-    log("placed %d bodies at phi %.3f in %.1fs" % (args.n, P["phi"], time.time() - t0))
-    sim = R.Simulation(P["x"], P["q"], P["kind"], P["shape"], P["rho_xi"], P["box"], precision=args.precision,
-                       skin=args.skin, warm_start=R.WS_PREV)
-    box = P["box"].copy()
-    phi = phi_of(P["shape"], box)
-    rate = 0.015
-    k = 0
-    t0 = time.time()
-    while phi < args.phi0 - 1e-12:
-        target = min(args.phi0, phi * (1 + rate))
-        s = (phi / target) ** (1.0 / 3.0)
-        sim.affine_rescale(s)
-        res = sim.step(args.dt, args.eps, args.tol, raise_on_error=False)
-        if res["status"] != 0:
-            sim.affine_rescale(1.0 / s)
-            rate *= 0.5
-            if rate < 1e-5:
-                raise RuntimeError("set-up compression stalled at phi %.4f (status %d)" % (phi, res["status"]))
-            continue
-        box *= s
-        phi = target
-        k += 1
-        if k % 20 == 0:
-            log("set-up compression: step %d phi %.4f contacts %d recursions %d (%.1fs)" %
-                (k, phi, res["n_contacts_final"], res["recursions"], time.time() - t0))
-    log("set-up done: phi %.4f after %d steps (%.1fs)" % (phi, k, time.time() - t0))
-    return sim, P, box, phi
-
-
-def run_steps(sim, shape, box, phi, nsteps, args, stats=None):
-    for _ in range(nsteps):
-        target = phi + args.dphi
-        s = (phi / target) ** (1.0 / 3.0)
-        sim.affine_rescale(s)
-        box *= s
-        phi = target
-        res = sim.step(args.dt, args.eps, args.tol)
-        if stats is not None:
-            stats.append(res)
-    return box, phi
+    C = Compaction(1, 10000, 0.40, dt=args.dt, eps=args.eps, tol=args.tol, precision=args.precision, skin=args.skin)
+    C.sim.enable_contact_log(True)
+    rows = L.ContactLog()
+    for level in (0.40, 0.45, 0.50, 0.55):
+        C.compress_to(level)
+        C.steps(5, args.dphi)
+        C.steps(15, args.dphi, on_step=lambda s, r: rows.record(s))
+    C.sim.close()
+    feat, gam = rows.tensors()
+    norm = L.normalisation(feat, gam)
+    tr = L.Trainer(norm, seed=0)
+    t1 = time.time()
+    hist = tr.fit(feat, gam, epochs=20)
+    torch.cuda.synchronize()
+    t_train = time.time() - t1
+    W = tr.weights()
+    log("learned warm start: %d training rows, loss %.2e -> %.2e, %.1fs training (%.1fs with logging)" %
+        (feat.shape[0], hist[0], hist[-1], t_train, time.time() - t0))
+    out = {"training_rows": int(feat.shape[0]), "epochs": 20, "train_s": t_train,
+           "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
+    for name, mode in (("plain", R.WS_PREV), ("learned", R.WS_LEARNED)):
+        D = Compaction(None, None, None, state=state, dt=args.dt, eps=args.eps, tol=args.tol,
+                       precision=args.precision, skin=args.skin)
+        D.sim.set_warmstart_model(W, norm)
+        D.steps(3, args.dphi)
+        D.sim.set_warm_start(mode)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = D.steps(args.learned_steps, args.dphi)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        out[name] = {"pgd_iters_per_step": float(np.mean([s["lcp_iters_total"] for s in st])),
+                     "ms_per_step": 1e3 * el / args.learned_steps,
+                     "lcp_ms_per_step": float(np.mean([s["t_lcp"] for s in st]))}
+        log("  %s: %s" % (name, out[name]))
+        D.sim.close()
+    return out
 
 
 def packings_workload(args):
@@ -233,6 +235,8 @@ def main():
     ap.add_argument("--roofline-steps", type=int, default=5)
     ap.add_argument("--cpu-n", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start comparison")
+    ap.add_argument("--learned-steps", type=int, default=20)
     ap.add_argument("--workload", default="compaction100k", choices=("compaction100k", "packings512"))
     ap.add_argument("--packings", type=int, default=512)
     ap.add_argument("--copy-probe-mb", type=float, default=0.0,
@@ -259,14 +263,18 @@ def main():
         return
     R.lib()
 
-    sim, P, box, phi = setup(args)
-    shape = P["shape"]
-    box, phi = run_steps(sim, shape, box, phi, args.warmup, args)
+    from paper_2506_14097_amd.compaction import Compaction
+    t0 = time.time()
+    C = Compaction(args.seed, args.n, args.phi0, dt=args.dt, eps=args.eps, tol=args.tol, precision=args.precision,
+                   skin=args.skin, log=log)
+    sim = C.sim
+    log("set-up done: phi %.4f (%.1fs)" % (C.phi, time.time() - t0))
+    start_state = C.state()
+    C.steps(args.warmup, args.dphi)
     log("warm-up done, timing %d steps" % args.steps)
-    stats = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    box, phi = run_steps(sim, shape, box, phi, args.steps, args, stats)
+    stats = C.steps(args.steps, args.dphi)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
@@ -279,8 +287,7 @@ def main():
     # its stream, over further steps of the same protocol
     sim.set_timing(True)
     sim.get_timing(reset=True)
-    rstats = []
-    box, phi = run_steps(sim, shape, box, phi, args.roofline_steps, args, rstats)
+    rstats = C.steps(args.roofline_steps, args.dphi)
     tm = sim.get_timing(reset=True)
     sim.set_timing(False)
     nb = args.n
@@ -311,6 +318,10 @@ def main():
     roof["kernel_ms"] = {k: round(v[1], 3) for k, v in tm.items()}
     roof["kernel_launches"] = {k: v[0] for k, v in tm.items()}
 
+    learned = None
+    if not args.no_learned:
+        learned = learned_comparison(args, start_state)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -324,9 +335,11 @@ def main():
         "vs_baseline": None, "dtype": "f32+f64" if args.precision == 32 else "f64", "data": "synthetic",
         "config": {"workload": "compaction of %d periodic ellipsoids (semiaxes U[0.5,1]), phi %.2f -> %.5f at "
                                "dphi %.0e/step, overdamped, dt %.0e, overlap_tol %.0e, lcp_tol %.0e, previous-step "
-                               "warm start" % (args.n, args.phi0, phi, args.dphi, args.dt, args.eps, args.tol),
+                               "warm start" % (args.n, args.phi0, C.phi, args.dphi, args.dt, args.eps, args.tol),
                    "bodies": args.n, "precision": args.precision, "skin": args.skin},
-        "pgd_iters_per_step": {"plain": float(np.mean(pgd)), "learned": None},
+        "pgd_iters_per_step": {"plain": float(np.mean(pgd)),
+                               "learned": learned["learned"]["pgd_iters_per_step"] if learned else None},
+        "learned_warm_start": learned,
         "contact_iters_per_s": citers / elapsed,
         "recursions_per_step": float(np.mean([s["recursions"] for s in stats])),
         "contacts_final": int(stats[-1]["n_contacts_final"]),

@@ -23,6 +23,7 @@
 #ifndef RELCP_H
 #define RELCP_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -81,7 +82,10 @@ typedef struct {
  * constraint SNSD LCP, first trial always accepted).  lcp_max_iters: cap on
  * projected-gradient iterations per LCP (0 = 100000).  skin: near-contact
  * distance delta_c; pairs whose bounding spheres are within skin are
- * candidates and pairs with Phi_0 <= skin start in A_0.  stream: a
+ * candidates and pairs with Phi_0 <= skin start in A_0.  warm_start: start
+ * of the iteration-0 LCP, RELCP_WS_COLD (zero) or RELCP_WS_PREV (the pair's
+ * previous-step multiplier sum, the default); RELCP_WS_LEARNED is selected
+ * with relcp_set_warm_start once a model is installed.  stream: a
  * hipStream_t, NULL = the library creates its own. */
 typedef struct {
     int32_t dynamics, precision, warm_start, planar;
@@ -168,11 +172,78 @@ RELCP_API int relcp_autotune(relcp_ctx *ctx, double dt, double lcp_tol, int32_t 
  * each launch of the step (off by default; costs one event pair per
  * launch).  Classes: 0 = LCP scatter pass (D gamma -> K), 1 = LCP gather
  * pass (D^T V, projection, step-size reductions), 2 = SNSD narrowphase,
- * 3 = candidate pairs, 4 = trial integration, 5 = resident LCP solve.
- * relcp_get_timing fills count[6] (launches) and ms[6] (summed durations)
- * since the last reset, and resets when reset != 0. */
+ * 3 = candidate pairs, 4 = trial integration, 5 = resident LCP solve,
+ * 6 = warm-start features and MLP inference.  relcp_get_timing fills
+ * count[7] (launches) and ms[7] (summed durations) since the last reset,
+ * and resets when reset != 0. */
 RELCP_API int relcp_set_timing(relcp_ctx *ctx, int32_t enable);
 RELCP_API int relcp_get_timing(relcp_ctx *ctx, int32_t *count, double *ms, int32_t reset);
+
+/* ---- learned warm start of the iteration-0 LCP ----
+ *
+ * The paper leaves the start of the LCP iteration open (the projected
+ * gradient solve of Eq. cqpp converges from any nonnegative start); these
+ * calls only change the start, never the converged multipliers, the
+ * contact sets or the acceptance test.  Per row of A_0 (pairs with
+ * Phi_0 <= skin) the library computes 8 features, oriented so that body a
+ * has the smaller caller index:
+ *   0 Phi_0 / abar (abar: mean of the two bodies' mean semi-extents),
+ *   1 dt (D^T U_prev) / abar (previous-step velocity along the row),
+ *   2 previous-step multiplier of the pair (the RELCP_WS_PREV start),
+ *   3, 4 rows of A_0 at body a, at body b,
+ *   5, 6 min / max semi-extent of a, of b,
+ *   7 h_a(n) / h_b(n) (support functions along the normal).
+ * Model: z = w3 . GELU(W2 GELU(W1 x + b1) + b2) + b3, GELU exact (erf,
+ * evaluated to 5e-7), x = (feature - mean) / std; the start corrects the
+ * previous-step multiplier: y0 = max(0, f_2 + scale z) in length units
+ * (f_2 = raw feature 2), gamma0 = y0 abar / A_aa.  Weights are a flat fp32
+ * vector of RELCP_MLP_NPARAM values in the order W1 (128 x 8, row = hidden
+ * unit), b1 (128), W2 (128 x 128), b2 (128), w3 (128), b3 (1); norm holds
+ * mean (8), std (8), scale (1).  The matrix products run on the matrix
+ * cores with bf16 operands (x, W1, the first hidden layer, W2) and fp32
+ * accumulation; the rest is fp32. */
+#define RELCP_MLP_NPARAM 17793
+#define RELCP_MLP_NORM 17
+
+/* Select the warm start (RELCP_WS_COLD, _PREV or _LEARNED; _LEARNED needs an
+ * installed model, else RELCP_E_INVALID). */
+RELCP_API int relcp_set_warm_start(relcp_ctx *ctx, int32_t mode);
+/* Install a model: params (RELCP_MLP_NPARAM host floats), norm (17 host
+ * floats, std and scale > 0).  Copied; RELCP_E_INVALID on non-finite input. */
+RELCP_API int relcp_set_warmstart_model(relcp_ctx *ctx, const float *params, const float *norm);
+/* Record the rows of A_0 of every accepted step (features and final
+ * multipliers: the training data of the model).  Off by default. */
+RELCP_API int relcp_enable_contact_log(relcp_ctx *ctx, int32_t on);
+/* Copy out the log of the last accepted step into caller device buffers of
+ * cap rows (any may be NULL): feat (cap x 8 floats, row-major), gamma (the
+ * row's multiplier after the step's last recursion, in the features' length
+ * units A_aa gamma / abar: the training target), ia < ib (caller indices).
+ * *count = rows (0 when logging is off or the last step failed); returns
+ * RELCP_E_CAPACITY, writing nothing, when *count > cap. */
+RELCP_API int relcp_log_contacts(relcp_ctx *ctx, float *feat, float *gamma, int32_t *ia, int32_t *ib, int32_t cap,
+                                 int32_t *count);
+
+/* Training and inference on device arrays (stream = hipStream_t or NULL).
+ * params: RELCP_MLP_NPARAM device floats, 16-byte aligned; feat: rows of 8
+ * raw features; idx (may be NULL): row k of the batch is entry idx[k];
+ * norm: host array as above.  Asynchronous on the stream. */
+/* out[idx[k]] (or out[k]) = max(0, f_2 + scale z) (length units) for the n
+ * rows. */
+RELCP_API int relcp_mlp_forward(const float *params, const float *norm, int32_t n, const float *feat,
+                                const int32_t *idx, float *out, void *stream);
+/* Bytes of device workspace that relcp_mlp_grad needs for a batch of n. */
+RELCP_API size_t relcp_mlp_workspace_bytes(int32_t n);
+/* Gradient of the batch loss mean_k (z_k - (target_k - f_2k) / scale)^2
+ * (targets in length units, as logged) into grad (RELCP_MLP_NPARAM device
+ * floats) and the loss into *loss (one device float, may be NULL).
+ * Deterministic: per-32-row partial gradients in the caller's workspace,
+ * summed in a fixed order. */
+RELCP_API int relcp_mlp_grad(const float *params, const float *norm, int32_t n, const float *feat, const float *target,
+                             const int32_t *idx, float *grad, float *loss, void *work, size_t work_bytes,
+                             void *stream);
+/* One Adam update (beta1 0.9, beta2 0.999, eps 1e-8; step count t >= 1) of
+ * params with moment buffers m, v (RELCP_MLP_NPARAM device floats each). */
+RELCP_API int relcp_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t t, float lr, void *stream);
 
 /* ---- stand-alone operations on device arrays (parity tests, tools) ---- */
 

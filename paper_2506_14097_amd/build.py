@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librelcp.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["scan.hip", "geometry.hip", "lcp.hip", "relcp.hip"]
+SOURCES = ["scan.hip", "geometry.hip", "lcp.hip", "mlp.hip", "relcp.hip"]
 
 
 def hipcc() -> str:

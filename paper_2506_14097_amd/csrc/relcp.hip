@@ -16,6 +16,9 @@
 #include "../../include/relcp.h"
 #include "geometry.h"
 #include "lcp.h"
+#include "mlp.h"
+
+static_assert(RELCP_MLP_NPARAM == relcp::MLP_NPARAM && RELCP_MLP_NORM == relcp::MLP_NORM, "model layout");
 
 using namespace relcp;
 
@@ -135,13 +138,13 @@ struct relcp_ctx {
     DBuf<unsigned long long> red;  // [0] max displacement bits, [1] min Phi key, [2] min margin key
     DBuf<int> scan_scratch, dtotal;
     // optional kernel timing (HIP events on the stream)
-    static constexpr int kClasses = 6;
+    static constexpr int kClasses = 7;
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_class;
     size_t ev_used = 0;
-    long long t_count[kClasses] = {0, 0, 0, 0, 0, 0};
-    double t_ms[kClasses] = {0, 0, 0, 0, 0, 0};
+    long long t_count[kClasses] = {0, 0, 0, 0, 0, 0, 0};
+    double t_ms[kClasses] = {0, 0, 0, 0, 0, 0, 0};
     // record a start/stop event pair around launch `f` when timing is on
     template <typename F>
     void timed(int cls, F &&f) {
@@ -192,6 +195,13 @@ struct relcp_ctx {
     }
     void rows_by_packing_init(int m0);
     void rows_by_packing_append(int m_old, int nv);
+    // learned warm start: model (fp32 master weights + standardisation),
+    // features of the iteration-0 rows, contact log of the last accepted step
+    bool has_model = false, log_on = false, log_valid = false;
+    float mlp_norm[MLP_NORM] = {};
+    DBuf<float> mlp_w, feat;
+    DBuf<double> rowscale;
+    int m0_last = 0;
     int *int_h = nullptr;
     unsigned long long *red_h = nullptr;
     double *dbl_h = nullptr;
@@ -219,6 +229,7 @@ struct relcp_ctx {
         if (pk_state_h) (void)hipHostFree(pk_state_h);
         boff_d.release(); roff.release(); rlist.release(); rlist2.release(); rcnt.release(); rE.release();
         pk_state.release();
+        mlp_w.release(); feat.release(); rowscale.release();
         for (auto e : ev_pool) (void)hipEventDestroy(e);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
@@ -230,6 +241,7 @@ struct relcp_ctx {
     void broadphase(const double *xs, double skin_);
     void build_rows(int nsel, int rec, const double *snsd, const double *vc, bool warm, double dt);
     void rebuild_csr();
+    void warm_start_rows(int m0, double dt);
     template <typename T>
     int solve(double dt, double tol, int &iters, double &res);
     int step(double dt, double eps, double tol, relcp_step_stats *st);
@@ -312,6 +324,7 @@ static uint64_t spread3(uint64_t v) {
 
 void relcp_ctx::upload_bodies(const relcp_bodies *B, const relcp_shapes *S) {
     n = B->n;
+    log_valid = false;
     nbatch = B->n_batch <= 0 ? 1 : B->n_batch;
     boff.assign(nbatch + 1, 0);
     for (int k = 0; k <= nbatch; ++k) boff[k] = B->batch_off ? B->batch_off[k] : (k ? n : 0);
@@ -615,6 +628,31 @@ void relcp_ctx::rebuild_csr() {
     launch_csr(n, m, ria.p, rib.p, csr_cnt.p, csr_off.p, csr_cnt.p + (n + 1), csr_ent.p, scan_scratch, stream);
 }
 
+// Features of the iteration-0 rows (their multipliers hold the previous
+// step's pair sums) and, for the learned start, the MLP's prediction in
+// their place; a cold start clears them again.
+void relcp_ctx::warm_start_rows(int m0, double dt) {
+    feat.ensure(8 * (size_t)std::max(m0, 1));
+    rowscale.ensure(std::max(m0, 1));
+    FeatureArgs fa{};
+    fa.m0 = m0; fa.ldr = ldr; fa.ia = ria.p; fa.ib = rib.p;
+    fa.n = rn64.p; fa.ta = rta64.p; fa.tb = rtb64.p; fa.phi = rphi64.p; fa.lam = rgam64.p; fa.dA = rdA64.p;
+    fa.ldb = n; fa.kind = kind.p; fa.p = p.p; fa.u = u.p; fa.off = csr_off.p; fa.ent = csr_ent.p;
+    fa.perm = perm_d.p;
+    fa.dt = dt; fa.feat = feat.p; fa.rowscale = rowscale.p;
+    launch_features(fa, stream);
+    if (warm_start == RELCP_WS_LEARNED) {
+        MlpArgs ma{};
+        ma.n = m0; ma.X = feat.p; ma.params = mlp_w.p;
+        std::memcpy(ma.norm, mlp_norm, sizeof(mlp_norm));
+        ma.rowscale = rowscale.p;
+        ma.out64 = rgam64.p;
+        launch_mlp_forward(ma, stream);
+    } else if (warm_start == RELCP_WS_COLD && m0 > 0) {
+        HIP_OK(hipMemsetAsync(rgam64.p, 0, (size_t)m0 * sizeof(double), stream));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // LCP of one recursion
 // ---------------------------------------------------------------------------
@@ -744,8 +782,12 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     t_narrow += tm.ms();
     m = 0;
     ensure_rows(m0);
-    build_rows(m0, 0, snsd0.p, nullptr, warm_start == RELCP_WS_PREV, dt);
+    const bool learned = warm_start == RELCP_WS_LEARNED;
+    const bool need_feat = learned || log_on;
+    log_valid = false;
+    build_rows(m0, 0, snsd0.p, nullptr, warm_start == RELCP_WS_PREV || need_feat, dt);
     rebuild_csr();
+    if (need_feat) timed(6, [&] { warm_start_rows(m0, dt); });
     if (resident_mode()) rows_by_packing_init(m0);
     t_other += tm.ms();
 
@@ -868,6 +910,8 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         }
         nprev = np;
         m_acc = m;
+        m0_last = m0;
+        log_valid = log_on;
         sync();
     }
     if (timing) {
@@ -917,7 +961,8 @@ int relcp_create(const relcp_bodies *bodies, const relcp_shapes *shapes, const r
         if (P.dynamics != 0 && P.dynamics != 1) throw Error{RELCP_E_INVALID, "bad dynamics"};
         if (P.precision != 64 && P.precision != 32) throw Error{RELCP_E_INVALID, "precision must be 64 or 32"};
         if (P.warm_start < 0 || P.warm_start > 2) throw Error{RELCP_E_INVALID, "bad warm start"};
-        if (P.warm_start == RELCP_WS_LEARNED) throw Error{RELCP_E_INVALID, "learned warm start needs a model"};
+        if (P.warm_start == RELCP_WS_LEARNED)
+            throw Error{RELCP_E_INVALID, "learned warm start needs a model (relcp_set_warmstart_model)"};
         if (P.max_recursions < 0 || P.max_recursions >= RELCP_MAX_RECORDED)
             throw Error{RELCP_E_INVALID, "max_recursions must be in [0, 64]"};
         if (!(P.skin > 0) || !std::isfinite(P.skin)) throw Error{RELCP_E_INVALID, "skin must be positive"};
@@ -1287,6 +1332,119 @@ int relcp_get_timing(relcp_ctx *ctx, int32_t *count, double *ms, int32_t reset) 
         }
         return RELCP_OK;
     });
+}
+
+// ---------------------------------------------------------------------------
+// learned warm start
+// ---------------------------------------------------------------------------
+int relcp_set_warm_start(relcp_ctx *ctx, int32_t mode) {
+    if (!ctx) return RELCP_E_INVALID;
+    return guarded(ctx, [&]() -> int {
+        if (mode < RELCP_WS_COLD || mode > RELCP_WS_LEARNED) throw Error{RELCP_E_INVALID, "bad warm start"};
+        if (mode == RELCP_WS_LEARNED && !ctx->has_model)
+            throw Error{RELCP_E_INVALID, "learned warm start needs a model (relcp_set_warmstart_model)"};
+        ctx->warm_start = mode;
+        return RELCP_OK;
+    });
+}
+
+int relcp_set_warmstart_model(relcp_ctx *ctx, const float *params, const float *norm) {
+    if (!ctx) return RELCP_E_INVALID;
+    return guarded(ctx, [&]() -> int {
+        if (!params || !norm) throw Error{RELCP_E_INVALID, "null model"};
+        for (int k = 0; k < MLP_NPARAM; ++k)
+            if (!std::isfinite(params[k])) throw Error{RELCP_E_INVALID, "non-finite model weight"};
+        for (int k = 0; k < MLP_NORM; ++k)
+            if (!std::isfinite(norm[k]) || (k >= 8 && !(norm[k] > 0)))
+                throw Error{RELCP_E_INVALID, "feature std and multiplier scale must be positive"};
+        ctx->mlp_w.ensure(MLP_NPARAM);
+        HIP_OK(hipMemcpyAsync(ctx->mlp_w.p, params, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice,
+                              ctx->stream));
+        ctx->sync();
+        std::memcpy(ctx->mlp_norm, norm, sizeof(ctx->mlp_norm));
+        ctx->has_model = true;
+        return RELCP_OK;
+    });
+}
+
+int relcp_enable_contact_log(relcp_ctx *ctx, int32_t on) {
+    if (!ctx) return RELCP_E_INVALID;
+    ctx->log_on = on != 0;
+    if (!ctx->log_on) ctx->log_valid = false;
+    return RELCP_OK;
+}
+
+int relcp_log_contacts(relcp_ctx *ctx, float *feat, float *gamma, int32_t *ia, int32_t *ib, int32_t cap,
+                       int32_t *count) {
+    if (!ctx || !count || cap < 0) return RELCP_E_INVALID;
+    return guarded(ctx, [&]() -> int {
+        const int m0 = ctx->log_valid ? ctx->m0_last : 0;
+        *count = m0;
+        if (m0 > cap) return RELCP_E_CAPACITY;
+        launch_log_rows(m0, ctx->feat.p, ctx->rgam64.p, ctx->rowscale.p, ctx->ria.p, ctx->rib.p, ctx->perm_d.p, feat,
+                        gamma, ia, ib, ctx->stream);
+        HIP_OK(hipGetLastError());
+        ctx->sync();
+        return RELCP_OK;
+    });
+}
+
+size_t relcp_mlp_workspace_bytes(int32_t n) {
+    return n < 0 ? 0 : (size_t)mlp_slots(n) * MLP_SLOT * sizeof(float);
+}
+
+static bool mlp_norm_ok(const float *norm) {
+    if (!norm) return false;
+    for (int k = 0; k < MLP_NORM; ++k)
+        if (!std::isfinite(norm[k]) || (k >= 8 && !(norm[k] > 0))) return false;
+    return true;
+}
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+int relcp_mlp_forward(const float *params, const float *norm, int32_t n, const float *feat, const int32_t *idx,
+                      float *out, void *stream) {
+    if (n < 0 || (n > 0 && (!params || !feat || !out)) || !mlp_norm_ok(norm)) return RELCP_E_INVALID;
+    if (n > 0 && !aligned16(params)) return RELCP_E_INVALID;
+    try {
+        MlpArgs a{};
+        a.n = n; a.idx = idx; a.X = feat; a.params = params; a.out32 = out;
+        std::memcpy(a.norm, norm, sizeof(a.norm));
+        launch_mlp_forward(a, (hipStream_t)stream);
+        HIP_OK(hipGetLastError());
+        return RELCP_OK;
+    } catch (const Error &e) {
+        return e.code;
+    }
+}
+
+int relcp_mlp_grad(const float *params, const float *norm, int32_t n, const float *feat, const float *target,
+                   const int32_t *idx, float *grad, float *loss, void *work, size_t work_bytes, void *stream) {
+    if (n < 0 || !params || !grad || (n > 0 && (!feat || !target)) || !mlp_norm_ok(norm)) return RELCP_E_INVALID;
+    if (n > 0 && (!work || work_bytes < relcp_mlp_workspace_bytes(n) || !aligned16(params))) return RELCP_E_INVALID;
+    try {
+        MlpArgs a{};
+        a.n = n; a.idx = idx; a.X = feat; a.params = params; a.y = target;
+        a.scale2 = n > 0 ? 2.0f / (float)n : 0.0f;
+        a.partial = (float *)work;
+        std::memcpy(a.norm, norm, sizeof(a.norm));
+        launch_mlp_grad(a, grad, loss, (hipStream_t)stream);
+        HIP_OK(hipGetLastError());
+        return RELCP_OK;
+    } catch (const Error &e) {
+        return e.code;
+    }
+}
+
+int relcp_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t t, float lr, void *stream) {
+    if (!params || !grad || !m || !v || t < 1 || !(lr > 0) || !std::isfinite(lr)) return RELCP_E_INVALID;
+    try {
+        launch_adam(params, grad, m, v, lr, t, (hipStream_t)stream);
+        HIP_OK(hipGetLastError());
+        return RELCP_OK;
+    } catch (const Error &e) {
+        return e.code;
+    }
 }
 
 // ---------------------------------------------------------------------------

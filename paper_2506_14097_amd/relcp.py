@@ -91,6 +91,15 @@ _SIGS = {
     "relcp_autotune": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_void_p]),
     "relcp_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "relcp_get_timing": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "relcp_set_warm_start": (C.c_int, [C.c_void_p, C.c_int32]),
+    "relcp_set_warmstart_model": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "relcp_enable_contact_log": (C.c_int, [C.c_void_p, C.c_int32]),
+    "relcp_log_contacts": (C.c_int, [C.c_void_p] + [C.c_void_p] * 4 + [C.c_int32, C.POINTER(C.c_int32)]),
+    "relcp_mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]),
+    "relcp_mlp_workspace_bytes": (C.c_size_t, [C.c_int32]),
+    "relcp_mlp_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32] + [C.c_void_p] * 6 + [C.c_size_t, C.c_void_p]),
+    "relcp_mlp_adam": (C.c_int, [C.c_void_p] * 4 + [C.c_int32, C.c_float, C.c_void_p]),
     "relcp_snsd_device": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "relcp_broadphase_device": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
@@ -174,9 +183,9 @@ class Simulation:
         return B, S
 
     def close(self):
-        if self.ctx:
-            lib().relcp_destroy(self.ctx)
-            self.ctx = None
+        ctx, self.ctx = getattr(self, "ctx", None), None
+        if ctx and _lib is not None:
+            _lib.relcp_destroy(ctx)
 
     __del__ = close
 
@@ -223,7 +232,7 @@ class Simulation:
         if rc != OK:
             raise RelcpError(rc, self._err())
 
-    TIMING_CLASSES = ("lcp_scatter", "lcp_gather", "snsd", "pairs", "trial", "lcp_resident")
+    TIMING_CLASSES = ("lcp_scatter", "lcp_gather", "snsd", "pairs", "trial", "lcp_resident", "warm_start")
     LCP_CONFIGS = ("grid", "resident-256", "resident-256-lds", "resident-512", "resident-512-lds",
                    "resident-1024", "resident-1024-lds")
 
@@ -248,8 +257,8 @@ class Simulation:
             raise RelcpError(rc, self._err())
 
     def get_timing(self, reset=True):
-        cnt = np.zeros(6, np.int32)
-        ms = np.zeros(6)
+        cnt = np.zeros(len(self.TIMING_CLASSES), np.int32)
+        ms = np.zeros(len(self.TIMING_CLASSES))
         rc = lib().relcp_get_timing(self.ctx, _ptr(cnt), _ptr(ms), 1 if reset else 0)
         if rc != OK:
             raise RelcpError(rc, self._err())
@@ -268,6 +277,101 @@ class Simulation:
         if rc != OK:
             raise RelcpError(rc, self._err())
         return dict(ia=ia, ib=ib, rec=rec, gamma=gam, phi=phi, n=nrm.reshape(m, 3))
+
+
+    # ---- learned warm start ----
+    def set_warm_start(self, mode):
+        rc = lib().relcp_set_warm_start(self.ctx, int(mode))
+        if rc != OK:
+            raise RelcpError(rc, self._err())
+
+    def set_warmstart_model(self, params, norm):
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        norm = np.ascontiguousarray(norm, dtype=np.float32)
+        if params.size != MLP_NPARAM or norm.size != MLP_NORM:
+            raise ValueError("model needs %d weights and %d normalisation values" % (MLP_NPARAM, MLP_NORM))
+        rc = lib().relcp_set_warmstart_model(self.ctx, _ptr(params), _ptr(norm))
+        if rc != OK:
+            raise RelcpError(rc, self._err())
+
+    def enable_contact_log(self, on=True):
+        rc = lib().relcp_enable_contact_log(self.ctx, 1 if on else 0)
+        if rc != OK:
+            raise RelcpError(rc, self._err())
+
+    def log_contacts(self, device="cuda:0"):
+        """Rows of A_0 of the last accepted step: (feat (m, 8) float32,
+        gamma (m,) float32, ia (m,), ib (m,) int32), torch tensors on the GPU."""
+        import torch
+        cnt = C.c_int32(0)
+        rc = lib().relcp_log_contacts(self.ctx, None, None, None, None, 0, C.byref(cnt))
+        if rc not in (OK, E_CAPACITY):
+            raise RelcpError(rc, self._err())
+        m = cnt.value
+        feat = torch.empty((max(m, 1), MLP_NFEAT), dtype=torch.float32, device=device)
+        gam = torch.empty(max(m, 1), dtype=torch.float32, device=device)
+        ia = torch.empty(max(m, 1), dtype=torch.int32, device=device)
+        ib = torch.empty(max(m, 1), dtype=torch.int32, device=device)
+        if m > 0:
+            rc = lib().relcp_log_contacts(self.ctx, _tptr(feat), _tptr(gam), _tptr(ia), _tptr(ib), m, C.byref(cnt))
+            if rc != OK:
+                raise RelcpError(rc, self._err())
+        return feat[:m], gam[:m], ia[:m], ib[:m]
+
+
+# --------------------------------------------------------------------------
+# learned warm start: device training and inference kernels
+# --------------------------------------------------------------------------
+MLP_NPARAM = 17793
+MLP_NORM = 17
+MLP_NFEAT = 8
+
+
+def mlp_forward(params, norm, feat, idx=None, out=None, stream=None):
+    """Warm start max(0, f_2 + scale z) (length units) for the rows of feat
+    (n, 8) (or feat[idx]);
+    params: float32 cuda tensor of MLP_NPARAM values; norm: 17 host floats."""
+    import torch
+    n = feat.shape[0] if idx is None else idx.numel()
+    if out is None:
+        out = torch.empty(max(feat.shape[0], 1), dtype=torch.float32, device=feat.device)
+    nh = np.ascontiguousarray(norm, dtype=np.float32)
+    rc = lib().relcp_mlp_forward(_tptr(params), _ptr(nh), n, _tptr(feat), _tptr(idx), _tptr(out), stream)
+    if rc != OK:
+        raise RelcpError(rc, "relcp_mlp_forward")
+    return out
+
+
+def mlp_workspace(n, device):
+    import torch
+    nbytes = int(lib().relcp_mlp_workspace_bytes(int(n)))
+    return torch.empty(max(nbytes // 4, 1), dtype=torch.float32, device=device)
+
+
+def mlp_grad(params, norm, feat, target, idx=None, grad=None, loss=None, work=None, stream=None):
+    """Gradient of mean (z - (target - f_2) / scale)^2 over the batch.
+    Returns (grad, loss) as cuda tensors."""
+    import torch
+    n = feat.shape[0] if idx is None else idx.numel()
+    dev = params.device
+    if grad is None:
+        grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device=dev)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+    if work is None:
+        work = mlp_workspace(n, dev)
+    nh = np.ascontiguousarray(norm, dtype=np.float32)
+    rc = lib().relcp_mlp_grad(_tptr(params), _ptr(nh), n, _tptr(feat), _tptr(target), _tptr(idx), _tptr(grad),
+                              _tptr(loss), _tptr(work), work.numel() * 4, stream)
+    if rc != OK:
+        raise RelcpError(rc, "relcp_mlp_grad")
+    return grad, loss
+
+
+def mlp_adam(params, grad, m, v, t, lr, stream=None):
+    rc = lib().relcp_mlp_adam(_tptr(params), _tptr(grad), _tptr(m), _tptr(v), int(t), float(lr), stream)
+    if rc != OK:
+        raise RelcpError(rc, "relcp_mlp_adam")
 
 
 # --------------------------------------------------------------------------

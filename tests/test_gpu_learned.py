@@ -1,0 +1,282 @@
+"""GPU parity of the learned warm start against the FP64 oracle (oracle.mlp),
+through the C ABI.
+
+Bars:
+ * forward: the start max(0, f_2 + scale z) within 5e-4 scale of the
+   oracle run with the same bf16 operand rounding, median
+   within 1e-5.  Both sides round the same operands to bf16; they differ by
+   fp32 against fp64 accumulation and by the rare operand that fp32 rounding
+   sends to the other bf16 neighbour (one bf16 step, 2^-8 relative, in one
+   of 8 + 128 inputs of a unit);
+ * gradient: within 2e-3 of the oracle's norm, element by element within
+   1e-2 of its largest entry, bit-identical on repetition (fixed-order sum);
+ * Adam: 1e-6 relative (fp32 update of the same formula);
+ * features of A_0 and the logged final multipliers: the oracle's rows
+   (same pairs), features to fp32 rounding plus the FP64 path's 1e-8;
+ * a step with the learned start: the plain step's bars (contact sets,
+   velocities and positions against the oracle step).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import mlp as M
+from paper_2506_14097_amd import learned as L
+from paper_2506_14097_amd import relcp as R
+
+from states import compressed_packing
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _model(seed):
+    rng = np.random.default_rng(seed)
+    return f32(M.init_params(seed) + 0.05 * rng.normal(size=M.NPARAM))
+
+
+def _data(seed, n):
+    """Raw features shaped like those of a compaction run, their
+    normalisation, and positive targets."""
+    rng = np.random.default_rng(100 + seed)
+    X = rng.normal(size=(n, 8)) * [0.02, 0.002, 0.3, 1.5, 1.5, 0.15, 0.15, 0.3] + [0.0, -0.001, 0.3, 3, 3, 0.7,
+                                                                                   0.7, 1.0]
+    X = f32(X)
+    mean = X.mean(0) if n > 1 else np.zeros(8)
+    std = X.std(0) if n > 1 else np.ones(8)
+    norm = f32(np.concatenate([mean, np.where(std > 0, std, 1.0), [0.05]]))
+    y = f32(np.abs(X[:, 2] + rng.normal(0.0, 0.3, n)))
+    return X, norm, y
+
+
+def T(a, dev, dtype=torch.float32):
+    return torch.tensor(np.asarray(a), dtype=dtype, device=dev)
+
+
+@pytest.mark.parametrize("n", [1, 31, 32, 33, 1000, 4099])
+def test_mlp_forward_matches_oracle(dev, n):
+    flat = _model(n)
+    X, norm, _ = _data(n, n)
+    print("mlp forward n", n, flush=True)
+    out = R.mlp_forward(T(flat, dev), norm, T(X, dev)).cpu().numpy()[:n]
+    ref = M.predict(flat, X, norm, emulate=True)
+    s = norm[16]
+    err = np.abs(out - ref) / s
+    assert err.max() < 5e-4 and np.median(err) < 1e-5, (err.max(), np.median(err))
+    assert (ref > 0).any() and (ref == 0).any() or n < 32
+    # the same rows through an index list in another order: bit-identical per row
+    perm = np.random.default_rng(n).permutation(n).astype(np.int32)
+    out2 = R.mlp_forward(T(flat, dev), norm, T(X, dev), idx=T(perm, dev, torch.int32)).cpu().numpy()[:n]
+    assert np.array_equal(out2, out)
+
+
+def test_mlp_forward_empty(dev):
+    X, norm, _ = _data(0, 4)
+    out = torch.full((4,), -1.0, device=dev)
+    R.mlp_forward(T(_model(0), dev), norm, T(X, dev)[:0], out=out)
+    assert torch.all(out == -1.0)
+
+
+@pytest.mark.parametrize("n", [1, 45, 777, 4096])
+def test_mlp_grad_matches_oracle(dev, n):
+    flat = _model(7 + n)
+    X, norm, y = _data(7 + n, n)
+    print("mlp grad n", n, flush=True)
+    g, loss = R.mlp_grad(T(flat, dev), norm, T(X, dev), T(y, dev))
+    g = g.cpu().numpy().astype(np.float64)
+    Xs = M.standardise(X, norm)
+    t = M.correction_target(X, y, norm)
+    ref = M.grad(flat, Xs, t, emulate=True)
+    lref = M.loss(flat, Xs, t, emulate=True)
+    assert np.linalg.norm(g - ref) <= 2e-3 * np.linalg.norm(ref)
+    assert np.abs(g - ref).max() <= 1e-2 * np.abs(ref).max()
+    assert abs(float(loss.item()) - lref) <= 1e-4 * max(lref, 1e-3)
+    # every parameter block is pinned (no slot left unwritten)
+    for o, k in ((0, 1024), (1024, 128), (1152, 16384), (17536, 128), (17664, 128), (17792, 1)):
+        blk = slice(o, o + k)
+        assert np.linalg.norm(g[blk] - ref[blk]) <= 5e-3 * max(np.linalg.norm(ref[blk]), 1e-6)
+    # deterministic
+    g2, _ = R.mlp_grad(T(flat, dev), norm, T(X, dev), T(y, dev))
+    assert np.array_equal(g2.cpu().numpy(), g.astype(np.float32))
+
+
+def test_mlp_grad_with_index_batch(dev):
+    """A minibatch given as an index list equals the gathered batch."""
+    flat = _model(3)
+    X, norm, y = _data(3, 600)
+    idx = np.random.default_rng(3).choice(600, 250, replace=False).astype(np.int32)
+    g1, l1 = R.mlp_grad(T(flat, dev), norm, T(X, dev), T(y, dev), idx=T(idx, dev, torch.int32))
+    g2, l2 = R.mlp_grad(T(flat, dev), norm, T(X[idx], dev), T(y[idx], dev))
+    assert np.array_equal(g1.cpu().numpy(), g2.cpu().numpy())
+    assert float(l1.item()) == float(l2.item())
+
+
+def test_adam_matches_oracle(dev):
+    rng = np.random.default_rng(5)
+    p = f32(rng.normal(size=M.NPARAM))
+    m = np.zeros(M.NPARAM)
+    v = np.zeros(M.NPARAM)
+    pt, mt, vt = T(p, dev), T(m, dev), T(v, dev)
+    for t in range(1, 4):
+        g = f32(rng.normal(size=M.NPARAM) * 10.0 ** rng.uniform(-6, 1, M.NPARAM))
+        R.mlp_adam(pt, T(g, dev), mt, vt, t, 1e-3)
+        p, m, v = M.adam(p, g, m, v, t, 1e-3)
+    np.testing.assert_allclose(pt.cpu().numpy(), p, rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(vt.cpu().numpy(), v, rtol=1e-5, atol=1e-30)
+
+
+# --------------------------------------------------------------------------
+# features, contact log and the learned start inside a step
+# --------------------------------------------------------------------------
+def _two_steps(seed, n=150, steps=26):
+    S = compressed_packing(seed, n, steps)
+    S = dict(S, x=S["x"] * 0.99, box=S["box"] * 0.99)
+    kw = dict(dt=5e-3, eps=1e-5, tol=1e-12, skin=0.2)
+    r1 = O.relcp_step(S["x"], S["q"], S["kind"], S["shape"], S["rho_xi"], S["box"], lcp_mode=1, prev=S["prev"], **kw)
+    x1 = r1["x"] * 0.995
+    box1 = S["box"] * 0.995
+    prev1 = O.pair_lambda(r1)
+    r2 = O.relcp_step(x1, r1["q"], S["kind"], S["shape"], S["rho_xi"], box1, lcp_mode=1, prev=prev1, **kw)
+    return S, kw, r1, prev1, r2
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_features_and_log_match_oracle(dev, seed):
+    S, kw, r1, prev1, r2 = _two_steps(seed)
+    print("features seed", seed, "rows", int((r2["rec"] == 0).sum()), flush=True)
+    # warm starts move only the start: the GPU's first step (no history) and
+    # the oracle's (with the compression history) reach the same solution
+    sim = R.Simulation(S["x"], S["q"], S["kind"], S["shape"], S["rho_xi"], S["box"], skin=kw["skin"],
+                       warm_start=R.WS_PREV)
+    res1 = sim.step(kw["dt"], kw["eps"], kw["tol"])
+    assert res1["status"] == 0
+    sim.enable_contact_log(True)
+    sim.affine_rescale(0.995)
+    res2 = sim.step(kw["dt"], kw["eps"], kw["tol"])
+    assert res2["status"] == 0
+    feat, gam, ia, ib = [t.cpu().numpy() for t in sim.log_contacts()]
+    oa, ob, OX, ors = M.features(r1["q"], S["kind"], S["shape"], S["rho_xi"], r1["U"], prev1, r2, kw["dt"])
+    assert np.all(ia < ib) and np.all(oa < ob)
+    key_g = {(int(a), int(b)): k for k, (a, b) in enumerate(zip(ia, ib))}
+    key_o = {(int(a), int(b)): k for k, (a, b) in enumerate(zip(oa, ob))}
+    assert set(key_g) == set(key_o)
+    kg = np.array([key_g[k] for k in key_o])
+    ko = np.array([key_o[k] for k in key_o])
+    G, X = feat[kg].astype(np.float64), OX[ko]
+    assert np.array_equal(G[:, 3:5], X[:, 3:5])                       # coordination: exact
+    np.testing.assert_allclose(G[:, [0, 1, 5, 6, 7]], X[:, [0, 1, 5, 6, 7]], rtol=2e-6, atol=1e-7)
+    lam_scale = max(np.abs(X[:, 2]).max(), 1e-12)
+    assert np.abs(G[:, 2] - X[:, 2]).max() <= 1e-6 * lam_scale        # previous multipliers
+    assert np.abs(X[:, 2]).max() > 0
+    # logged targets: final multipliers of the iteration-0 rows, length units
+    yref = M.targets(r2, ors)[ko]
+    assert np.abs(yref).max() > 0
+    assert np.abs(gam[kg] - yref).max() <= 1e-5 * np.abs(yref).max()
+
+
+def test_log_capacity_and_off(dev):
+    S, kw, *_ = _two_steps(2)
+    sim = R.Simulation(S["x"], S["q"], S["kind"], S["shape"], S["rho_xi"], S["box"], skin=kw["skin"])
+    sim.step(kw["dt"], kw["eps"], kw["tol"])
+    f, g, a, b = sim.log_contacts()
+    assert f.shape[0] == 0            # logging is off by default
+    sim.enable_contact_log(True)
+    sim.step(kw["dt"], kw["eps"], kw["tol"])
+    f, g, a, b = sim.log_contacts()
+    assert f.shape[0] > 0
+    import ctypes as C
+    cnt = C.c_int32(0)
+    rc = R.lib().relcp_log_contacts(sim.ctx, None, None, None, None, f.shape[0] - 1, C.byref(cnt))
+    assert rc == R.E_CAPACITY and cnt.value == f.shape[0]
+
+
+def test_learned_needs_model(dev):
+    S, kw, *_ = _two_steps(2)
+    sim = R.Simulation(S["x"], S["q"], S["kind"], S["shape"], S["rho_xi"], S["box"], skin=kw["skin"])
+    with pytest.raises(R.RelcpError):
+        sim.set_warm_start(R.WS_LEARNED)
+    bad = np.full(17, 1.0, np.float32)
+    bad[8] = 0.0
+    with pytest.raises(R.RelcpError):
+        sim.set_warmstart_model(np.zeros(R.MLP_NPARAM, np.float32), bad)
+    with pytest.raises(R.RelcpError):
+        R.Simulation(S["x"], S["q"], S["kind"], S["shape"], S["rho_xi"], S["box"], skin=kw["skin"],
+                     warm_start=R.WS_LEARNED)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_learned_step_matches_oracle(dev, seed, precision):
+    """Any start gives the same step: an untrained model's start against the
+    oracle's step (previous-step start)."""
+    from test_gpu_parity import _compare_step
+    S, kw, r1, prev1, r2 = _two_steps(seed)
+    x1, box1 = r1["x"] * 0.995, S["box"] * 0.995
+    sim = R.Simulation(x1, r1["q"], S["kind"], S["shape"], S["rho_xi"], box1, u=r1["U"][:, :3], w=r1["U"][:, 3:],
+                       skin=kw["skin"], precision=precision)
+    X, norm, _ = _data(seed, 64)
+    sim.set_warmstart_model(_model(seed).astype(np.float32), norm)
+    sim.set_warm_start(R.WS_LEARNED)
+    res = sim.step(kw["dt"], kw["eps"], kw["tol"] if precision == 64 else 1e-9)
+    print("learned step seed", seed, "precision", precision, "iters", list(res["lcp_iters"]), flush=True)
+    _compare_step(res, sim, r2, 1e-8 if precision == 64 else 1e-4)
+
+
+def test_trained_network_gains_over_previous_step_start(dev):
+    """Train on the rows of A_0 logged from one compaction (10,000
+    ellipsoids, seed 1, 60 steps each at volume fractions 0.40 and 0.50),
+    evaluate on another (seed 7, from 0.45): the learned start is closer to
+    the converged multipliers than the previous-step start, in rms and in
+    the largest row error (length units), and the steps need fewer
+    projected-gradient iterations."""
+    from paper_2506_14097_amd.compaction import Compaction
+    C = Compaction(1, 10000, 0.40)
+    C.sim.enable_contact_log(True)
+    log = L.ContactLog()
+    for level in (0.40, 0.50):
+        C.compress_to(level)
+        C.steps(5)
+        C.steps(60, on_step=lambda s, r: log.record(s))
+    feat, gam = log.tensors()
+    print("training rows", feat.shape[0], flush=True)
+    norm = L.normalisation(feat, gam)
+    tr = L.Trainer(norm, seed=0)
+    hist = tr.fit(feat, gam, epochs=40)
+    print("loss", hist[0], "->", hist[-1], flush=True)
+    assert hist[-1] < 0.8 * hist[0]
+    W = tr.weights()
+    E = Compaction(7, 10000, 0.45)
+    start = E.state()
+    iters = {}
+    for mode in (R.WS_PREV, R.WS_LEARNED):
+        D = Compaction(None, None, None, state=start)
+        D.sim.set_warmstart_model(W, norm)
+        D.steps(3)
+        D.sim.set_warm_start(mode)
+        st = D.steps(30)
+        assert all(s["status"] == 0 for s in st)
+        iters[mode] = np.mean([s["lcp_iters_total"] for s in st])
+        if mode == R.WS_PREV:
+            D.sim.enable_contact_log(True)
+            D.steps(1)
+            f, g, _, _ = D.sim.log_contacts()
+            err = tr.start_error(f, g)
+            print("start error (rms, max):", err, flush=True)
+            assert err["learned"][0] < 0.9 * err["previous"][0]
+            assert err["learned"][1] < err["previous"][1]
+        D.sim.close()
+    print("PGD iterations per step: previous-step start %.2f, learned %.2f" % (iters[R.WS_PREV],
+                                                                             iters[R.WS_LEARNED]), flush=True)
+    assert iters[R.WS_LEARNED] < iters[R.WS_PREV]
