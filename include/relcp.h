@@ -101,7 +101,7 @@ typedef struct {
 typedef struct {
     int32_t recursions;          /* augmentations before acceptance */
     int32_t lcp_iters_total;     /* projected-gradient iterations over all recursions */
-    int32_t n_pairs;             /* candidate pairs */
+    int32_t n_pairs;             /* pairs of the candidate list (bounding-sphere gap <= 1.5 skin when built) */
     int32_t n_contacts_final;    /* rows at acceptance */
     int32_t n_contacts[RELCP_MAX_RECORDED];
     int32_t lcp_iters[RELCP_MAX_RECORDED];   /* iterations per recursion (all precisions) */
@@ -113,6 +113,8 @@ typedef struct {
     double max_overlap;          /* max over pairs of -Phi at the accepted configuration (>= 0) */
     double max_disp;             /* largest surface-point displacement bound of the accepted trial */
     double t_narrow, t_lcp, t_other; /* milliseconds (host clock, stream-synchronised) */
+    int32_t rowgraph_entries[RELCP_MAX_RECORDED]; /* entries of A over rows per recursion (row-graph LCP mode; 0 otherwise) */
+    int32_t pairs_rebuilt;       /* 1 if the candidate list was rebuilt at this step (it is kept while valid) */
 } relcp_step_stats;
 
 /* Create a context (Sec. 2.1.1 state, Sec. 2.1.2 laws of motion).  Validates
@@ -154,18 +156,22 @@ RELCP_API int relcp_get_contacts(const relcp_ctx *ctx, int32_t *ia, int32_t *ib,
                        double *phi_at_discovery, double *normal);
 
 /* Execution of the LCP loop (the same Jacobi-scaled projected gradient in
- * every mode).  mode 0 = automatic, 1 = grid (two passes per iteration over
- * all rows, launched in chunks), 2 = resident (one workgroup per packing
- * runs its whole solve in one launch; block = workgroup size 256, 512 or
- * 1024; lds = stage the packing's velocities in LDS when they fit). */
+ * every mode).  mode 0 = automatic (resident when every packing has at
+ * most 8192 bodies, else row graph), 1 = grid (two passes per iteration
+ * over all rows and bodies, through the velocities K D gamma, launched in
+ * chunks), 2 = resident (one workgroup per packing runs its whole solve in
+ * one launch; block = workgroup size 256, 512 or 1024; lds = stage the
+ * packing's velocities in LDS when they fit), 3 = row graph (A = dt D^T K D
+ * assembled over rows once per recursion, one pass per iteration). */
 RELCP_API int relcp_set_lcp_config(relcp_ctx *ctx, int32_t mode, int32_t block, int32_t lds);
 
 /* Autotuner: times every LCP configuration (grid; resident x {256, 512,
- * 1024} x {LDS, global}) on the rows of the last accepted step, from the
- * same start, reps times each, keeps the fastest for this context and
- * writes it to config[3] = {mode, block, lds} and the average milliseconds
- * per configuration to ms[7] (either may be NULL; a configuration that
- * does not fit reports 0).  The multipliers of the last step are restored. */
+ * 1024} x {global, LDS}; row graph) on the rows of the last accepted step,
+ * from the same start, reps times each, keeps the fastest for this context
+ * and writes it to config[3] = {mode, block, lds} and the average
+ * milliseconds per configuration to ms[8] in that order (either may be
+ * NULL; a configuration that does not fit reports 0).  The multipliers of
+ * the last step are restored. */
 RELCP_API int relcp_autotune(relcp_ctx *ctx, double dt, double lcp_tol, int32_t reps, int32_t *config, double *ms);
 
 /* Kernel timing with HIP events recorded on the context's stream around
@@ -173,9 +179,10 @@ RELCP_API int relcp_autotune(relcp_ctx *ctx, double dt, double lcp_tol, int32_t 
  * launch).  Classes: 0 = LCP scatter pass (D gamma -> K), 1 = LCP gather
  * pass (D^T V, projection, step-size reductions), 2 = SNSD narrowphase,
  * 3 = candidate pairs, 4 = trial integration, 5 = resident LCP solve,
- * 6 = warm-start features and MLP inference.  relcp_get_timing fills
- * count[7] (launches) and ms[7] (summed durations) since the last reset,
- * and resets when reset != 0. */
+ * 6 = warm-start features and MLP inference, 7 = row-graph LCP pass,
+ * 8 = row-graph assembly.  relcp_get_timing fills count[9] (launches) and
+ * ms[9] (summed durations) since the last reset, and resets when
+ * reset != 0. */
 RELCP_API int relcp_set_timing(relcp_ctx *ctx, int32_t enable);
 RELCP_API int relcp_get_timing(relcp_ctx *ctx, int32_t *count, double *ms, int32_t reset);
 
@@ -269,10 +276,12 @@ RELCP_API int relcp_broadphase_device(int32_t nb, const double *x, const int32_t
  * gradient (precision 64 or 32) from the warm start in gamma.  Device arrays:
  * rows ia, ib (m), n, ta = r_a x n, tb = r_b x n (3 arrays of m each), qv (m),
  * body operator kt (nb), Kr (6 arrays of nb: xx, yy, zz, xy, xz, yz), gamma
- * (m, in/out).  *iters and *residual (FP64 residual) are host outputs. */
+ * (m, in/out).  mode: LCP execution as in relcp_set_lcp_config, 1 = grid,
+ * 3 = row graph (0 = row graph).  *iters and *residual (FP64 residual) are
+ * host outputs. */
 RELCP_API int relcp_lcp_solve_device(int32_t nb, int32_t m, const int32_t *ia, const int32_t *ib, const double *n,
                            const double *ta, const double *tb, const double *qv, const double *kt, const double *Kr,
-                           double dt, int32_t planar, int32_t precision, double tol, int32_t max_iters,
+                           double dt, int32_t planar, int32_t precision, int32_t mode, double tol, int32_t max_iters,
                            double *gamma, int32_t *iters, double *residual, void *stream);
 
 #ifdef __cplusplus

@@ -23,6 +23,11 @@ struct SnsdArgs {
     int ldo;
     int mode;                    // 0: flag = Phi <= thresh;  1: flag = Phi < -eps
     double thresh, eps;
+    // bounding radii or null: a pair whose bounding spheres are more than
+    // thresh (mode 0) or 0 (mode 1) apart cannot be flagged and skips the
+    // Newton solve; it reports the sphere gap (a lower bound of Phi) and
+    // the centre-to-centre normal
+    const double *Rb;
     int *flag;                   // per pair, or null
     unsigned long long *minphi;  // order keys of min Phi and min |Phi + eps|, or null
     unsigned long long *minmarg;

@@ -436,7 +436,14 @@ __global__ void __launch_bounds__(256) k_snsd_pairs(SnsdArgs A) {
         if (bx[1] > 0.0) d.y -= bx[1] * rint(d.y / bx[1]);
         if (bx[2] > 0.0) d.z -= bx[2] * rint(d.z / bx[2]);
         Snsd s;
-        if (A.kind[a] == 0) {
+        const double dl = len(d);
+        const double sgap = A.Rb ? dl - A.Rb[a] - A.Rb[b] : -1e300;
+        if (sgap > (A.mode == 0 ? A.thresh : 0.0) && dl > 0.0) {
+            s.phi = sgap;
+            s.n = (1.0 / dl) * d;
+            s.ra = A.Rb[a] * s.n;
+            s.rb = (-A.Rb[b]) * s.n;
+        } else if (A.kind[a] == 0) {
             sym3 Sa{A.geo[a], A.geo[A.ldg + a], A.geo[2 * A.ldg + a], A.geo[3 * A.ldg + a], A.geo[4 * A.ldg + a],
                     A.geo[5 * A.ldg + a]};
             sym3 Sb{A.geo[b], A.geo[A.ldg + b], A.geo[2 * A.ldg + b], A.geo[3 * A.ldg + b], A.geo[4 * A.ldg + b],

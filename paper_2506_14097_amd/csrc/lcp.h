@@ -58,7 +58,9 @@ void launch_csr(int nb, int m, const int *ia, const int *ib, int *cnt, int *off,
                 DBuf<int> &scan_scratch, hipStream_t s);
 
 // Device control block of one solve: ping-pong states S[0], S[1], the
-// final state, the done flag and the gather's per-block partial sums.
+// final state, the done flag and the per-block partial sums of the last
+// pass (read by the next pass; the row-graph pass writes its own partials
+// to a second buffer, `pout` of its launch).
 struct PgdCtl {
     PgdState *S;
     PgdState *fin;
@@ -67,6 +69,67 @@ struct PgdCtl {
     int nbg;
     double tol;
 };
+
+// Row-graph form of the LCP matrix A = dt D^T K D: one entry per (row,
+// row) pair sharing a body and per shared body (a pair of rows sharing both
+// bodies has two entries; the diagonal is split into its two body parts).
+// Sliced ELL: slice s holds rows [64 s, 64 s + 64) with width w_s, entry k
+// of row r at 64 base[s] + 64 k + r % 64 (base = exclusive scan of the
+// widths); padding entries point at the row itself with value 0.
+template <typename T>
+struct RowGraphT {
+    int m;
+    const int *base, *col;
+    const T *val;
+    size_t cap;  // entry slots allocated: a slice past them was not filled and is skipped
+};
+
+// Iteration state of a row seen by the rows it couples to: multiplier and
+// scaled gradient h = g / A_rr (its projected step is max(0, gam - alpha h)).
+template <typename T>
+struct alignas(2 * sizeof(T)) RowStep {
+    T gam, h;
+};
+
+struct RowGraphFill {
+    int m, ldr;
+    const int *ia, *ib;
+    const double *n, *ta, *tb;
+    int ldb;
+    const double *K;   // 9 comps, ld = ldb
+    const int *off, *ent;
+    const double *jb;  // per incidence entry e: s (n, tau) of its row at that body (6 values, ent order)
+    const int *base;
+    double dt;
+    size_t cap;        // entry slots allocated
+    int *overflow;     // set when the slots do not suffice (nothing is written past cap)
+    int *col;
+    double *val64;
+    float *val32;
+};
+
+int rowgraph_slices(int m);
+// width[s] = largest row degree (rows at body a + rows at body b) in slice s;
+// *count += the sum of the row degrees (the entries without padding)
+void launch_rowgraph_width(int m, const int *ia, const int *ib, const int *off, int *width, int *count,
+                           hipStream_t s);
+// jb[6 e ..] = s (n, tau) of the row of incidence entry e (s = -1, tau = r_a x n
+// at body a; s = +1, tau = r_b x n at body b): the column of D at that body
+void launch_incidence_jacobian(int m, const int *ent, const double *n, const double *ta, const double *tb, int ldr,
+                               double *jb, hipStream_t s);
+void launch_rowgraph_fill(const RowGraphFill &a, hipStream_t s);
+// One pass of the row-graph LCP loop over m rows with A in G and the
+// diagonal dA.  mode 0: start, gamma0 = max(0, gam0), g at gamma0; mode 1:
+// iteration with parity par, reading the previous pass's state (zin, gin)
+// and partials, writing (zout, gout) and its own partials pout.
+template <typename T>
+void launch_lcp_spmv(int mode, const RowGraphT<T> &G, const T *qv, const T *dA, const T *gam0,
+                     const RowStep<T> *zin, const T *gin, RowStep<T> *zout, T *gout, const PgdCtl &C, double *pout,
+                     int par, hipStream_t s);
+// gamma, g <- the state of the pass that holds the final iterate (fin.iter & 1)
+template <typename T>
+void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, const T *g0, const T *g1,
+                            const PgdState *fin, T *gam, T *g, hipStream_t s);
 
 // Passes of the projected-gradient loop.  Iteration j (j = 1, 2, ...) is
 // scatter(mode 1, par = j & 1) then gather(mode 1, par = j & 1); a solve

@@ -528,6 +528,221 @@ __global__ void __launch_bounds__(kThreads) k_pgd_finalize(PgdCtl C, int par) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// row-graph LCP: A = dt D^T K D assembled over rows, one pass per iteration
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_rowgraph_width(int m, const int *__restrict__ ia,
+                                                             const int *__restrict__ ib, const int *__restrict__ off,
+                                                             int *__restrict__ width, int *__restrict__ count) {
+    const int r = blockIdx.x * kThreads + threadIdx.x;
+    int w = 0;
+    if (r < m) {
+        const int a = ia[r], b = ib[r];
+        w = off[a + 1] - off[a] + off[b + 1] - off[b];
+    }
+    int sum = w;
+    for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) {
+        w = max(w, __shfl_xor(w, o, RELCP_WAVE));
+        sum += __shfl_xor(sum, o, RELCP_WAVE);
+    }
+    const int ns = (m + RELCP_WAVE - 1) / RELCP_WAVE;
+    if ((threadIdx.x & (RELCP_WAVE - 1)) == 0 && r / RELCP_WAVE < ns) {
+        width[r / RELCP_WAVE] = w;
+        atomicAdd(count, sum);
+    }
+    if (r == 0) width[ns] = 0;
+}
+
+__global__ void __launch_bounds__(kThreads) k_incidence_jacobian(int m2, const int *__restrict__ ent,
+                                                                 const double *__restrict__ n,
+                                                                 const double *__restrict__ ta,
+                                                                 const double *__restrict__ tb, int L,
+                                                                 double *__restrict__ jb) {
+    const int e = blockIdx.x * kThreads + threadIdx.x;
+    if (e >= m2) return;
+    const int en = ent[e], j = en >> 1;
+    const double s = (en & 1) ? 1.0 : -1.0;
+    const double *t = (en & 1) ? tb : ta;
+    double *o = jb + 6 * (size_t)e;
+    o[0] = s * n[j];
+    o[1] = s * n[L + j];
+    o[2] = s * n[2 * L + j];
+    o[3] = s * t[j];
+    o[4] = s * t[L + j];
+    o[5] = s * t[2 * L + j];
+}
+
+// Entries of row r: for each of its bodies c (a, then b) and each row j at
+// c (incidence order), dt J_r^c . (K_c J_j^c) with J the column of D at c,
+// then padding entries (the row itself, value 0).
+__global__ void __launch_bounds__(kThreads) k_rowgraph_fill(RowGraphFill A) {
+    const int r = blockIdx.x * kThreads + threadIdx.x;
+    if (r >= A.m) return;
+    const int lane = r & (RELCP_WAVE - 1), sl = r / RELCP_WAVE;
+    const int b0 = A.base[sl], w = A.base[sl + 1] - b0;
+    const int L = A.ldr, lb = A.ldb;
+    const d3 nr = mk(A.n[r], A.n[L + r], A.n[2 * L + r]);
+    if ((size_t)RELCP_WAVE * (b0 + w) > A.cap) {
+        *A.overflow = 1;
+        return;
+    }
+    int k = 0;
+    for (int side = 0; side < 2; ++side) {
+        const int c = side ? A.ib[r] : A.ia[r];
+        const double *tr = side ? A.tb : A.ta;
+        const double sr = side ? 1.0 : -1.0;
+        const d3 ur = mk(tr[r], tr[L + r], tr[2 * L + r]);
+        const double *K = A.K;
+        // K_c applied to this row's column (sign included)
+        const d3 Kn = mk(sr * K[c] * nr.x, sr * K[lb + c] * nr.y, sr * K[2 * lb + c] * nr.z);
+        const sym3 Kr{K[3 * lb + c], K[4 * lb + c], K[5 * lb + c], K[6 * lb + c], K[7 * lb + c], K[8 * lb + c]};
+        const d3 Ku = sr * mul(Kr, ur);
+        for (int e = A.off[c]; e < A.off[c + 1]; ++e, ++k) {
+            const double *J = A.jb + 6 * (size_t)e;
+            const double v = A.dt * (J[0] * Kn.x + J[1] * Kn.y + J[2] * Kn.z + J[3] * Ku.x + J[4] * Ku.y + J[5] * Ku.z);
+            const size_t at = (size_t)RELCP_WAVE * (b0 + k) + lane;
+            A.col[at] = A.ent[e] >> 1;
+            A.val64[at] = v;
+            A.val32[at] = (float)v;
+        }
+    }
+    for (; k < w; ++k) {
+        const size_t at = (size_t)RELCP_WAVE * (b0 + k) + lane;
+        A.col[at] = r;
+        A.val64[at] = 0.0;
+        A.val32[at] = 0.0f;
+    }
+}
+
+// max(0, gamma - alpha h); the same rounding wherever a row's step is formed
+__device__ inline double step_h(double gm, double h, double al) {
+    const double v = __dsub_rn(gm, __dmul_rn(al, h));
+    return v > 0.0 ? v : 0.0;
+}
+__device__ inline float step_h(float gm, float h, float al) {
+    const float v = __fsub_rn(gm, __fmul_rn(al, h));
+    return v > 0.0f ? v : 0.0f;
+}
+
+// One pass per iteration.  Each thread takes one row.  Everything that does
+// not depend on the step length is loaded first (its own state, up to KP
+// matrix entries and the previous state of the rows they point at), so that
+// the reduction of the previous pass's partial sums (fixed order, every
+// block) overlaps those loads; then the projected steps, g' = qv + A gamma',
+// the row's new state and its share of the step-size sums and residual.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kThreads)
+    k_spmv(RowGraphT<T> G, const T *__restrict__ qv, const T *__restrict__ dA0, const T *__restrict__ gam0,
+           const RowStep<T> *__restrict__ zin, const T *__restrict__ gin, RowStep<T> *__restrict__ zout,
+           T *__restrict__ gout, PgdCtl C, double *__restrict__ pout, int par) {
+    constexpr int KP = 16;
+    __shared__ double sh[4][kWaves];
+    __shared__ PgdState ns;
+    if (MODE == 1 && *C.done) return;
+    const int r = blockIdx.x * kThreads + threadIdx.x;
+    const bool act = r < G.m;
+    int w = 0;
+    const int *col = nullptr;
+    const T *val = nullptr;
+    T gm = T(0), hm = T(0), gold = T(0), dA = T(1), q = T(0);
+    int cj[KP];
+    T vj[KP], gj[KP], hj[KP];
+    if (act) {
+        const int lane = r & (RELCP_WAVE - 1), sl = r / RELCP_WAVE;
+        const int b0 = G.base[sl];
+        w = G.base[sl + 1] - b0;
+        // an overflowed assembly left this slice unwritten: no entries (the
+        // caller sees the overflow flag, re-sizes and starts the solve over)
+        if ((size_t)RELCP_WAVE * (b0 + w) > G.cap) w = 0;
+        col = G.col + (size_t)RELCP_WAVE * b0 + lane;
+        val = G.val + (size_t)RELCP_WAVE * b0 + lane;
+        dA = dA0[r];
+        q = qv[r];
+        if (MODE == 1) {
+            const RowStep<T> z = zin[r];
+            gm = z.gam;
+            hm = z.h;
+            gold = gin[r];
+        } else {
+            gm = gam0[r];
+        }
+#pragma unroll
+        for (int k = 0; k < KP; ++k) cj[k] = k < w ? col[RELCP_WAVE * k] : r;
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            vj[k] = k < w ? val[RELCP_WAVE * k] : T(0);
+            if (MODE == 1) {
+                const RowStep<T> z = zin[cj[k]];
+                gj[k] = z.gam;
+                hj[k] = z.h;
+            } else {
+                gj[k] = gam0[cj[k]];
+                hj[k] = T(0);
+            }
+        }
+    }
+    T al = T(0);
+    if (MODE == 1) {
+        reduce_partials(C, par, &ns, sh);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            C.S[par] = ns;
+            if (ns.conv) {
+                *C.fin = ns;
+                *C.done = 1;
+            }
+        }
+        if (ns.conv) return;
+        al = (T)ns.alpha;
+    }
+    double ss = 0.0, sy = 0.0, yy = 0.0, res = 0.0;
+    if (act) {
+        T acc = T(0);
+#pragma unroll
+        for (int k = 0; k < KP; ++k) acc += vj[k] * (MODE == 1 ? step_h(gj[k], hj[k], al) : clamp0(gj[k]));
+        for (int k = KP; k < w; ++k) {
+            const int j = col[RELCP_WAVE * k];
+            const T v = val[RELCP_WAVE * k];
+            if (MODE == 1) {
+                const RowStep<T> z = zin[j];
+                acc += v * step_h(z.gam, z.h, al);
+            } else {
+                acc += v * clamp0(gam0[j]);
+            }
+        }
+        const T gv = MODE == 1 ? step_h(gm, hm, al) : clamp0(gm);
+        const T gn = q + acc;
+        zout[r] = RowStep<T>{gv, gn / dA};
+        gout[r] = gn;
+        const T dg = dA * gv;
+        res = fabs((double)(dg < gn ? dg : gn));
+        if (MODE == 1) {
+            const double sd = (double)gv - (double)gm, yd = (double)gn - (double)gold;
+            ss = (double)dA * sd * sd;
+            sy = sd * yd;
+            yy = yd * yd / (double)dA;
+        }
+    }
+    block_reduce4(ss, sy, yy, res, sh);
+    if (threadIdx.x == 0) {
+        double *p = pout + 4 * blockIdx.x;
+        p[0] = ss;
+        p[1] = sy;
+        p[2] = yy;
+        p[3] = res;
+    }
+}
+
+template <typename T>
+__global__ void k_rowstate_unpack(int m, const RowStep<T> *__restrict__ z0, const RowStep<T> *__restrict__ z1,
+                                  const T *__restrict__ g0, const T *__restrict__ g1,
+                                  const PgdState *__restrict__ fin, T *__restrict__ gam, T *__restrict__ g) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const bool odd = fin->iter & 1;
+    gam[r] = (odd ? z1 : z0)[r].gam;
+    g[r] = (odd ? g1 : g0)[r];
+}
+
 __global__ void k_promote(int m, const float *__restrict__ a, double *__restrict__ b) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < m) b[i] = (double)a[i];
@@ -672,11 +887,56 @@ void launch_pgd_finalize(const PgdCtl &C, int par, hipStream_t s) {
     hipLaunchKernelGGL(k_pgd_finalize, dim3(1), dim3(kThreads), 0, s, C, par);
 }
 
+int rowgraph_slices(int m) { return (m + RELCP_WAVE - 1) / RELCP_WAVE; }
+
+void launch_rowgraph_width(int m, const int *ia, const int *ib, const int *off, int *width, int *count,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_rowgraph_width, dim3(nblk(m > 0 ? m : 1, kThreads)), dim3(kThreads), 0, s, m, ia, ib, off,
+                       width, count);
+}
+
+void launch_incidence_jacobian(int m, const int *ent, const double *n, const double *ta, const double *tb, int ldr,
+                               double *jb, hipStream_t s) {
+    if (m > 0)
+        hipLaunchKernelGGL(k_incidence_jacobian, dim3(nblk(2 * (long long)m, kThreads)), dim3(kThreads), 0, s, 2 * m,
+                           ent, n, ta, tb, ldr, jb);
+}
+
+void launch_rowgraph_fill(const RowGraphFill &a, hipStream_t s) {
+    if (a.m > 0) hipLaunchKernelGGL(k_rowgraph_fill, dim3(nblk(a.m, kThreads)), dim3(kThreads), 0, s, a);
+}
+
+template <typename T>
+void launch_lcp_spmv(int mode, const RowGraphT<T> &G, const T *qv, const T *dA, const T *gam0,
+                     const RowStep<T> *zin, const T *gin, RowStep<T> *zout, T *gout, const PgdCtl &C, double *pout,
+                     int par, hipStream_t s) {
+    const int nb = nblk(G.m > 0 ? G.m : 1, kThreads);
+    if (mode == 0)
+        hipLaunchKernelGGL((k_spmv<T, 0>), dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C,
+                           pout, par);
+    else
+        hipLaunchKernelGGL((k_spmv<T, 1>), dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C,
+                           pout, par);
+}
+
+template <typename T>
+void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, const T *g0, const T *g1,
+                            const PgdState *fin, T *gam, T *g, hipStream_t s) {
+    if (m > 0)
+        hipLaunchKernelGGL((k_rowstate_unpack<T>), dim3(nblk(m, 256)), dim3(256), 0, s, m, z0, z1, g0, g1, fin, gam,
+                           g);
+}
+
 #define RELCP_INST(T)                                                                                              \
     template void launch_lcp_scatter<T>(int, const RowsT<T> &, const BodiesT<T> &, const PgdCtl &, int,           \
                                         hipStream_t);                                                             \
     template void launch_lcp_gather<T>(int, const RowsT<T> &, const BodiesT<T> &, double, const PgdCtl &, int,    \
-                                       hipStream_t);
+                                       hipStream_t);                                                              \
+    template void launch_lcp_spmv<T>(int, const RowGraphT<T> &, const T *, const T *, const T *,                  \
+                                     const RowStep<T> *, const T *, RowStep<T> *, T *, const PgdCtl &, double *,  \
+                                     int, hipStream_t);                                                           \
+    template void launch_rowstate_unpack<T>(int, const RowStep<T> *, const RowStep<T> *, const T *, const T *,    \
+                                            const PgdState *, T *, T *, hipStream_t);
 RELCP_INST(double)
 RELCP_INST(float)
 #undef RELCP_INST

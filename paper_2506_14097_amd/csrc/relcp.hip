@@ -122,6 +122,16 @@ struct relcp_ctx {
     // previous step (warm start): sorted pairs and multiplier sums
     int nprev = 0, ldprev = 0;
     DBuf<int> prev_a, prev_b;
+    // the candidate list pa, pb is kept across steps (a Verlet list): built
+    // with bounding-sphere gap <= skin + 2 margin, it holds every pair within
+    // skin as long as the accumulated bound on how much any gap has shrunk
+    // since the build (vl_used) stays below 2 margin; pairs of the list
+    // beyond skin are cut by a bounding-sphere test in the narrowphase
+    bool vl_valid = false, prev_is_list = false;
+    double vl_used = 0.0;
+    double vl_margin() const { return 0.25 * skin; }
+    double vl_radius() const { return skin + 2.0 * vl_margin(); }
+    void candidate_pairs(relcp_step_stats &S);
     DBuf<double> prev_lam;
 
     // rows (ld = ldr)
@@ -138,13 +148,13 @@ struct relcp_ctx {
     DBuf<unsigned long long> red;  // [0] max displacement bits, [1] min Phi key, [2] min margin key
     DBuf<int> scan_scratch, dtotal;
     // optional kernel timing (HIP events on the stream)
-    static constexpr int kClasses = 7;
+    static constexpr int kClasses = 9;
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_class;
     size_t ev_used = 0;
-    long long t_count[kClasses] = {0, 0, 0, 0, 0, 0, 0};
-    double t_ms[kClasses] = {0, 0, 0, 0, 0, 0, 0};
+    long long t_count[kClasses] = {};
+    double t_ms[kClasses] = {};
     // record a start/stop event pair around launch `f` when timing is on
     template <typename F>
     void timed(int cls, F &&f) {
@@ -182,14 +192,28 @@ struct relcp_ctx {
     PgdState *pst_h = nullptr;  // fin and the done slot
     int last_iters[2] = {8, 8};  // previous solve's iteration count (FP32, FP64)
     // LCP execution: mode 0 = automatic, 1 = grid (two passes per iteration
-    // over all rows), 2 = resident (one workgroup per packing, one launch)
+    // over all rows), 2 = resident (one workgroup per packing, one launch),
+    // 3 = row graph (A assembled over rows, one pass per iteration)
     int lcp_mode = 0, res_block = 256, res_lds = 1;
+    DBuf<int> rg_width, rg_base, rg_col, rg_flags;  // flags: [0] entry count, [1] overflow
+    DBuf<double> rg_val64, rg_jb;
+    DBuf<float> rg_val32;
+    DBuf<RowStep<double>> z64;
+    DBuf<RowStep<float>> z32;
+    DBuf<double> zg64;
+    DBuf<float> zg32;
+    bool rg_valid = false;
+    double rg_dt = 0.0;
+    size_t rg_cap = 0;     // entry slots allocated
+    int rg_entries = 0;    // entries of the current graph (known after the solve's first read-back)
+    bool rowgraph_mode() const { return !resident_mode() && lcp_mode != 1; }
+    void build_rowgraph(double dt);
     int maxpk = 0;                       // bodies of the largest packing
     DBuf<int> boff_d, roff, rlist, rlist2, rcnt, rE;
     DBuf<PgdState> pk_state;
     PgdState *pk_state_h = nullptr;
     bool resident_mode() const {
-        if (lcp_mode == 1) return false;
+        if (lcp_mode == 1 || lcp_mode == 3) return false;
         if (lcp_mode == 2) return true;
         return maxpk <= 8192;
     }
@@ -230,6 +254,8 @@ struct relcp_ctx {
         boff_d.release(); roff.release(); rlist.release(); rlist2.release(); rcnt.release(); rE.release();
         pk_state.release();
         mlp_w.release(); feat.release(); rowscale.release();
+        rg_width.release(); rg_base.release(); rg_col.release(); rg_flags.release(); rg_val64.release();
+        rg_jb.release(); rg_val32.release(); z64.release(); z32.release(); zg64.release(); zg32.release();
         for (auto e : ev_pool) (void)hipEventDestroy(e);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
@@ -244,6 +270,8 @@ struct relcp_ctx {
     void warm_start_rows(int m0, double dt);
     template <typename T>
     int solve(double dt, double tol, int &iters, double &res);
+    template <typename T>
+    int solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt, double tol, int &iters, double &res);
     int step(double dt, double eps, double tol, relcp_step_stats *st);
     void sync() { HIP_OK(hipStreamSynchronize(stream)); }
 };
@@ -325,6 +353,8 @@ static uint64_t spread3(uint64_t v) {
 void relcp_ctx::upload_bodies(const relcp_bodies *B, const relcp_shapes *S) {
     n = B->n;
     log_valid = false;
+    vl_valid = false;
+    prev_is_list = false;
     nbatch = B->n_batch <= 0 ? 1 : B->n_batch;
     boff.assign(nbatch + 1, 0);
     for (int k = 0; k <= nbatch; ++k) boff[k] = B->batch_off ? B->batch_off[k] : (k ? n : 0);
@@ -571,6 +601,17 @@ void relcp_ctx::broadphase(const double *xs, double skin_) {
     });
 }
 
+void relcp_ctx::candidate_pairs(relcp_step_stats &S) {
+    if (!vl_valid || vl_used >= 2.0 * vl_margin()) {
+        broadphase(x.p, vl_radius());
+        vl_valid = true;
+        vl_used = 0.0;
+        prev_is_list = false;
+        S.pairs_rebuilt = 1;
+    }
+    S.n_pairs = np;
+}
+
 // ---------------------------------------------------------------------------
 // rows and incidence
 // ---------------------------------------------------------------------------
@@ -622,6 +663,7 @@ void relcp_ctx::rows_by_packing_append(int m_old, int nv) {
 }
 
 void relcp_ctx::rebuild_csr() {
+    rg_valid = false;
     csr_cnt.ensure(2 * (size_t)(n + 1));
     csr_off.ensure(n + 1);
     csr_ent.ensure(2 * (size_t)std::max(m, 1));
@@ -651,6 +693,42 @@ void relcp_ctx::warm_start_rows(int m0, double dt) {
     } else if (warm_start == RELCP_WS_COLD && m0 > 0) {
         HIP_OK(hipMemsetAsync(rgam64.p, 0, (size_t)m0 * sizeof(double), stream));
     }
+}
+
+// Row graph of the current rows: slice widths and their scan, the columns of
+// D in incidence order, then the entries.  Nothing is read back here: the
+// entry slots are sized from an estimate (twice the current need seen so
+// far, at least 16 per row) and the fill flags an overflow, which the solve
+// checks at its first read-back (then re-sizes, rebuilds and restarts).
+void relcp_ctx::build_rowgraph(double dt) {
+    const int ns = rowgraph_slices(m);
+    rg_width.ensure(ns + 1);
+    rg_base.ensure(ns + 1);
+    rg_flags.ensure(2);
+    rg_jb.ensure(12 * (size_t)std::max(m, 1));
+    const size_t want = std::max<size_t>((size_t)RELCP_WAVE * ns * 16, 64);
+    if (rg_cap < want) {
+        rg_cap = std::max(want, rg_cap);
+        rg_col.release(); rg_val64.release(); rg_val32.release();
+        rg_col.ensure(rg_cap);
+        rg_val64.ensure(rg_cap);
+        rg_val32.ensure(rg_cap);
+    }
+    HIP_OK(hipMemsetAsync(rg_flags.p, 0, 2 * sizeof(int), stream));
+    launch_rowgraph_width(m, ria.p, rib.p, csr_off.p, rg_width.p, rg_flags.p, stream);
+    exclusive_scan(rg_width.p, rg_base.p, ns + 1, nullptr, scan_scratch, stream);
+    launch_incidence_jacobian(m, csr_ent.p, rn64.p, rta64.p, rtb64.p, ldr, rg_jb.p, stream);
+    RowGraphFill f{};
+    f.m = m; f.ldr = ldr; f.ia = ria.p; f.ib = rib.p; f.n = rn64.p; f.ta = rta64.p; f.tb = rtb64.p;
+    f.ldb = n; f.K = K.p; f.off = csr_off.p; f.ent = csr_ent.p; f.jb = rg_jb.p; f.base = rg_base.p; f.dt = dt;
+    f.cap = rg_cap; f.overflow = rg_flags.p + 1;
+    f.col = rg_col.p; f.val64 = rg_val64.p; f.val32 = rg_val32.p;
+    launch_rowgraph_fill(f, stream);
+    // slots needed, entry count and overflow flag, read with the solve's first read-back
+    HIP_OK(hipMemcpyAsync(int_h + 4, rg_base.p + ns, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipMemcpyAsync(int_h + 5, rg_flags.p, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
+    rg_valid = true;
+    rg_dt = dt;
 }
 
 // ---------------------------------------------------------------------------
@@ -697,6 +775,7 @@ int relcp_ctx::solve(double dt, double tol, int &iters, double &res) {
         if (lcp_fixed > 0) return RELCP_OK;
         return conv ? RELCP_OK : RELCP_E_LCP_MAXITER;
     }
+    if (rowgraph_mode()) return solve_rowgraph<T>(R, Bd, dt, tol, iters, res);
     partials.ensure(lcp_partials_needed(m));
     // pst: S[0], S[1], fin, then a slot whose first int is the done flag
     pst.ensure(4);
@@ -729,11 +808,118 @@ int relcp_ctx::solve(double dt, double tol, int &iters, double &res) {
         chunk = std::min(64, std::max(8, 2 * chunk));
     }
     if (!done) {
-        // account for the last gather (iteration cap or fixed-iteration run)
-        launch_pgd_finalize(C, (j - 1) & 1, stream);
+        // account for the last gather (iteration cap or fixed-iteration run):
+        // the state after it follows S[(j - 1) & 1] into slot j & 1
+        launch_pgd_finalize(C, j & 1, stream);
         HIP_OK(hipMemcpyAsync(pst_h, pst.p + 2, 2 * sizeof(PgdState), hipMemcpyDeviceToHost, stream));
         sync();
     }
+    const bool conv = *reinterpret_cast<int *>(pst_h + 1) != 0;
+    iters = pst_h[0].iter;
+    res = pst_h[0].res;
+    last_iters[pk] = iters;
+    if (!std::isfinite(res)) return RELCP_E_NAN;
+    if (lcp_fixed > 0) return RELCP_OK;
+    return conv ? RELCP_OK : RELCP_E_LCP_MAXITER;
+}
+
+// Row-graph LCP loop: pass 0 forms g at the start, pass j (parity j & 1)
+// reads state buffer z[(j - 1) & 1] and the partials of pass j - 1 and
+// writes z[j & 1] and its own partials; the final iterate is unpacked into
+// the rows' gamma and g, and (FP64) the contact velocities K D gamma that
+// the trial integration needs are formed once.
+template <typename T>
+int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt, double tol, int &iters,
+                              double &res) {
+    const size_t mz = std::max(m, 1);
+    RowStep<T> *z0, *z1;
+    T *g0, *g1;
+    if constexpr (sizeof(T) == 8) {
+        z64.ensure(2 * mz);
+        zg64.ensure(2 * mz);
+        z0 = z64.p; z1 = z64.p + mz; g0 = zg64.p; g1 = zg64.p + mz;
+    } else {
+        z32.ensure(2 * mz);
+        zg32.ensure(2 * mz);
+        z0 = z32.p; z1 = z32.p + mz; g0 = zg32.p; g1 = zg32.p + mz;
+    }
+    const size_t stride = lcp_partials_needed(m);
+    partials.ensure(2 * stride);
+    pst.ensure(4);
+    const int cap = lcp_fixed > 0 ? lcp_fixed : lcp_max_iters;
+    const int pk = sizeof(T) == 8 ? 1 : 0;
+    PgdCtl C{pst.p, pst.p + 2, reinterpret_cast<int *>(pst.p + 3), partials.p, lcp_gather_blocks(m),
+             lcp_fixed > 0 ? -1.0 : tol};
+    auto ctl = [&](int par) {  // control block of a pass with parity par: reads the other partials buffer
+        PgdCtl c = C;
+        c.partials = partials.p + (size_t)(par ^ 1) * stride;
+        return c;
+    };
+    for (int attempt = 0;; ++attempt) {
+        bool fresh = false;
+        if (!rg_valid || rg_dt != dt) {
+            timed(8, [&] { build_rowgraph(dt); });
+            fresh = true;
+        }
+        RowGraphT<T> G{m, rg_base.p, rg_col.p, nullptr, rg_cap};
+        if constexpr (sizeof(T) == 8)
+            G.val = rg_val64.p;
+        else
+            G.val = rg_val32.p;
+        launch_pgd_init(C, stream);
+        timed(7, [&] {
+            launch_lcp_spmv<T>(0, G, R.qv, R.dA, R.gam, nullptr, nullptr, z0, g0, C, partials.p, 0, stream);
+        });
+        int j = 1;
+        int chunk = std::max(2, std::min(64, (last_iters[pk] + 3) & ~1));
+        bool done = false, first = true;
+        for (;;) {
+            int k = std::min(chunk, cap - (j - 1));
+            if (k <= 0) break;
+            for (int t = 0; t < k; ++t, ++j) {
+                const int par = j & 1;
+                timed(7, [&] {
+                    launch_lcp_spmv<T>(1, G, R.qv, R.dA, nullptr, par ? z0 : z1, par ? g0 : g1, par ? z1 : z0,
+                                       par ? g1 : g0, ctl(par), partials.p + (size_t)par * stride, par, stream);
+                });
+            }
+            HIP_OK(hipMemcpyAsync(pst_h, pst.p + 2, 2 * sizeof(PgdState), hipMemcpyDeviceToHost, stream));
+            sync();
+            if (first && fresh) {
+                first = false;
+                rg_entries = int_h[5];
+                const size_t need = (size_t)RELCP_WAVE * int_h[4];
+                if (int_h[6] || need > rg_cap) break;
+            }
+            if (*reinterpret_cast<int *>(pst_h + 1)) {
+                done = true;
+                break;
+            }
+            chunk = std::min(64, std::max(8, 2 * chunk));
+        }
+        if (fresh && (int_h[6] || (size_t)RELCP_WAVE * int_h[4] > rg_cap)) {
+            // the entry slots did not suffice: re-size to twice the need and start over
+            if (attempt > 0) throw Error{RELCP_E_DEVICE, "row graph sizing failed"};
+            rg_cap = 2 * (size_t)RELCP_WAVE * int_h[4];
+            rg_col.release(); rg_val64.release(); rg_val32.release();
+            rg_col.ensure(rg_cap);
+            rg_val64.ensure(rg_cap);
+            rg_val32.ensure(rg_cap);
+            rg_valid = false;
+            continue;
+        }
+        if (!done) {
+            // the state after the last pass (iteration cap or fixed iterations)
+            PgdCtl cf = C;
+            cf.partials = partials.p + (size_t)((j - 1) & 1) * stride;
+            launch_pgd_finalize(cf, j & 1, stream);
+            HIP_OK(hipMemcpyAsync(pst_h, pst.p + 2, 2 * sizeof(PgdState), hipMemcpyDeviceToHost, stream));
+        }
+        break;
+    }
+    launch_rowstate_unpack<T>(m, z0, z1, g0, g1, C.fin, R.gam, R.g, stream);
+    if constexpr (sizeof(T) == 8) timed(0, [&] { launch_lcp_scatter<T>(0, R, Bd, C, 0, stream); });
+    sync();
     const bool conv = *reinterpret_cast<int *>(pst_h + 1) != 0;
     iters = pst_h[0].iter;
     res = pst_h[0].res;
@@ -762,8 +948,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     launch_body_setup(ba, stream);
 
     // candidate pairs at C^k
-    broadphase(x.p, skin);
-    S.n_pairs = np;
+    candidate_pairs(S);
     t_other += tm.ms();
 
     // SNSD at C^k, iteration-0 set A_0 = {Phi_0 <= skin}
@@ -772,7 +957,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     sa.m = np; sa.pa = pa.p; sa.pb = pb.p; sa.body_batch = body_batch.p; sa.x = x.p; sa.ldx = N; sa.geo = geo.p;
     sa.ldg = N; sa.kind = kind.p; sa.p = p.p; sa.ldp = N; sa.boxes = boxes.p; sa.planar = planar; sa.hint = nullptr;
     sa.out = snsd0.p; sa.ldo = ldp; sa.mode = 0; sa.thresh = skin; sa.eps = eps; sa.flag = pflag.p;
-    sa.minphi = nullptr; sa.minmarg = nullptr;
+    sa.minphi = nullptr; sa.minmarg = nullptr; sa.Rb = Rb.p;
     timed(2, [&] { launch_snsd_pairs(sa, stream); });
     exclusive_scan(pflag.p, pscan.p, np, dtotal.p, scan_scratch, stream);
     launch_compact(np, pflag.p, pscan.p, sel.p, stream);
@@ -816,6 +1001,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
             S.n_contacts[rec] = m;
             S.lcp_iters[rec] = it + it64;
             S.lcp_iters64[rec] = precision == 32 ? it64 : it;
+            S.rowgraph_entries[rec] = rowgraph_mode() && rg_valid ? rg_entries : 0;
         }
         S.residual_fp64 = res64;
         S.residual_lowp = res;
@@ -897,16 +1083,23 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         // multiplier sum per pair, for the next warm start
         HIP_OK(hipMemsetAsync(lam.p, 0, std::max(np, 1) * sizeof(double), stream));
         for (int lv = 0; lv <= rec; ++lv) launch_pair_lambda(m, rrec.p, rpair.p, rgam64.p, lv, lam.p, stream);
-        std::swap(prev_a.p, pa.p);
-        std::swap(prev_a.cap, pa.cap);
-        std::swap(prev_b.p, pb.p);
-        std::swap(prev_b.cap, pb.cap);
+        if (!prev_is_list) {
+            // the previous-step pairs are the candidate list itself until it is rebuilt
+            prev_a.ensure(std::max(np, 1));
+            prev_b.ensure(std::max(np, 1));
+            if (np > 0) {
+                HIP_OK(hipMemcpyAsync(prev_a.p, pa.p, np * sizeof(int), hipMemcpyDeviceToDevice, stream));
+                HIP_OK(hipMemcpyAsync(prev_b.p, pb.p, np * sizeof(int), hipMemcpyDeviceToDevice, stream));
+            }
+            prev_is_list = true;
+        }
         std::swap(prev_lam.p, lam.p);
         std::swap(prev_lam.cap, lam.cap);
-        // keep pair-buffer capacities consistent with ldp
-        if ((int)pa.cap < ldp || (int)pb.cap < ldp || (int)lam.cap < ldp) {
-            pa.release(); pb.release(); lam.release();
-            pa.ensure(ldp); pb.ensure(ldp); lam.ensure(ldp);
+        vl_used += 2.0 * S.max_disp;
+        // keep the multiplier buffer's capacity consistent with ldp
+        if ((int)lam.cap < ldp) {
+            lam.release();
+            lam.ensure(ldp);
         }
         nprev = np;
         m_acc = m;
@@ -1115,6 +1308,10 @@ int relcp_affine_rescale(relcp_ctx *ctx, double s) {
                               hipMemcpyHostToDevice, ctx->stream));
         hipLaunchKernelGGL(k_scale, dim3(nblk(3LL * ctx->n, 256)), dim3(256), 0, ctx->stream, 3 * ctx->n, ctx->x.p,
                            s);
+        // a pair of the list is at most 2 R_max + radius apart: its gap shrinks by at most (1 - s) times that
+        double rm = 0.0;
+        for (double r : ctx->rmax) rm = std::max(rm, r);
+        ctx->vl_used += std::max(0.0, 1.0 - s) * (2.0 * rm + ctx->vl_radius());
         ctx->sync();
         return RELCP_OK;
     });
@@ -1153,6 +1350,10 @@ int relcp_affine_rescale_packings(relcp_ctx *ctx, const double *s) {
                            ctx->body_batch.p, sd.p);
         ctx->sync();
         sd.release();
+        double shrink = 0.0;
+        for (int pk = 0; pk < ctx->nbatch; ++pk)
+            shrink = std::max(shrink, std::max(0.0, 1.0 - s[pk]) * (2.0 * ctx->rmax[pk] + ctx->vl_radius()));
+        ctx->vl_used += shrink;
         return RELCP_OK;
     });
 }
@@ -1195,8 +1396,8 @@ int relcp_get_contacts(const relcp_ctx *cc, int32_t *ia, int32_t *ib, int32_t *r
 
 int relcp_set_lcp_config(relcp_ctx *ctx, int32_t mode, int32_t block, int32_t lds) {
     if (!ctx) return RELCP_E_INVALID;
-    if (mode < 0 || mode > 2 || (block != 256 && block != 512 && block != 1024)) {
-        ctx->err = "mode must be 0..2 and block 256, 512 or 1024";
+    if (mode < 0 || mode > 3 || (block != 256 && block != 512 && block != 1024)) {
+        ctx->err = "mode must be 0..3 and block 256, 512 or 1024";
         return RELCP_E_INVALID;
     }
     ctx->lcp_mode = mode;
@@ -1246,6 +1447,7 @@ int relcp_autotune(relcp_ctx *ctx, double dt, double lcp_tol, int32_t reps, int3
         std::vector<Cfg> cfgs = {{1, 256, 0}};
         for (int b : {256, 512, 1024})
             for (int l : {0, 1}) cfgs.push_back({2, b, l});
+        cfgs.push_back({3, 256, 0});
         const int save_mode = ctx->lcp_mode, save_block = ctx->res_block, save_lds = ctx->res_lds;
         hipEvent_t e0, e1;
         HIP_OK(hipEventCreate(&e0));
@@ -1587,16 +1789,18 @@ __global__ void k_K_from_user(int nb, const double *__restrict__ kt, const doubl
 
 int relcp_lcp_solve_device(int32_t nb, int32_t m, const int32_t *ia, const int32_t *ib, const double *n,
                            const double *ta, const double *tb, const double *qv, const double *kt, const double *Kr,
-                           double dt, int32_t planar, int32_t precision, double tol, int32_t max_iters,
+                           double dt, int32_t planar, int32_t precision, int32_t mode, double tol, int32_t max_iters,
                            double *gamma, int32_t *iters, double *residual, void *stream) {
-    if (nb <= 0 || m < 0 || !(dt > 0) || (precision != 32 && precision != 64) || !gamma || !kt || !Kr)
+    if (nb <= 0 || m < 0 || !(dt > 0) || (precision != 32 && precision != 64) || !gamma || !kt || !Kr ||
+        (mode != 0 && mode != 1 && mode != 3))
         return RELCP_E_INVALID;
     relcp_ctx c;
     c.stream = (hipStream_t)stream;
     try {
         HIP_OK(hipHostMalloc((void **)&c.pst_h, 2 * sizeof(PgdState), hipHostMallocDefault));
+        HIP_OK(hipHostMalloc((void **)&c.int_h, 16 * sizeof(int), hipHostMallocDefault));
         c.n = nb;
-        c.lcp_mode = 1;
+        c.lcp_mode = mode == 1 ? 1 : 3;
         c.lcp_max_iters = max_iters > 0 ? max_iters : 100000;
         c.K.ensure(9 * (size_t)nb);
         c.K32.ensure(9 * (size_t)nb);

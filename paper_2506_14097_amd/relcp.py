@@ -58,7 +58,8 @@ class StepStats(C.Structure):
                 ("W", C.c_double * MAX_RECORDED),
                 ("margin", C.c_double * MAX_RECORDED), ("residual_fp64", C.c_double),
                 ("residual_lowp", C.c_double), ("max_overlap", C.c_double), ("max_disp", C.c_double),
-                ("t_narrow", C.c_double), ("t_lcp", C.c_double), ("t_other", C.c_double)]
+                ("t_narrow", C.c_double), ("t_lcp", C.c_double), ("t_other", C.c_double),
+                ("rowgraph_entries", C.c_int32 * MAX_RECORDED), ("pairs_rebuilt", C.c_int32)]
 
     def as_dict(self):
         R = self.recursions
@@ -69,7 +70,8 @@ class StepStats(C.Structure):
                     W=np.array(self.W[:k]), margin=np.array(self.margin[:k]),
                     residual_fp64=self.residual_fp64, residual_lowp=self.residual_lowp,
                     max_overlap=self.max_overlap, max_disp=self.max_disp, t_narrow=self.t_narrow, t_lcp=self.t_lcp,
-                    t_other=self.t_other)
+                    t_other=self.t_other, rowgraph_entries=np.array(self.rowgraph_entries[:k]),
+                    pairs_rebuilt=self.pairs_rebuilt)
 
 
 _lib = None
@@ -105,7 +107,7 @@ _SIGS = {
     "relcp_broadphase_device": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                           C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.c_void_p]),
     "relcp_lcp_solve_device": (C.c_int, [C.c_int32, C.c_int32] + [C.c_void_p] * 8 + [C.c_double, C.c_int32, C.c_int32,
-                                         C.c_double, C.c_int32, C.c_void_p, C.POINTER(C.c_int32),
+                                         C.c_int32, C.c_double, C.c_int32, C.c_void_p, C.POINTER(C.c_int32),
                                          C.POINTER(C.c_double), C.c_void_p]),
 }
 
@@ -232,19 +234,21 @@ class Simulation:
         if rc != OK:
             raise RelcpError(rc, self._err())
 
-    TIMING_CLASSES = ("lcp_scatter", "lcp_gather", "snsd", "pairs", "trial", "lcp_resident", "warm_start")
+    TIMING_CLASSES = ("lcp_scatter", "lcp_gather", "snsd", "pairs", "trial", "lcp_resident", "warm_start",
+                      "lcp_rowgraph", "rowgraph_build")
     LCP_CONFIGS = ("grid", "resident-256", "resident-256-lds", "resident-512", "resident-512-lds",
-                   "resident-1024", "resident-1024-lds")
+                   "resident-1024", "resident-1024-lds", "rowgraph")
 
     def set_lcp_config(self, mode, block=256, lds=True):
-        """mode: 0 automatic, 1 grid, 2 resident (one workgroup per packing)."""
+        """mode: 0 automatic, 1 grid, 2 resident (one workgroup per packing),
+        3 row graph (A assembled over rows, one pass per iteration)."""
         rc = lib().relcp_set_lcp_config(self.ctx, mode, block, 1 if lds else 0)
         if rc != OK:
             raise RelcpError(rc, self._err())
 
     def autotune(self, dt, lcp_tol, reps=3):
         cfg = np.zeros(3, np.int32)
-        ms = np.zeros(7)
+        ms = np.zeros(len(self.LCP_CONFIGS))
         rc = lib().relcp_autotune(self.ctx, dt, lcp_tol, reps, _ptr(cfg), _ptr(ms))
         if rc != OK:
             raise RelcpError(rc, self._err())
@@ -411,15 +415,15 @@ def broadphase_device(x_soa, kind, p_soa, box, skin, cap=None, stream=None):
 
 
 def lcp_solve_device(nb, ia, ib, n_soa, ta_soa, tb_soa, qv, kt, Kr_soa, dt, gamma, *, planar=False, precision=64,
-                     tol=1e-12, max_iters=0, stream=None):
+                     mode=3, tol=1e-12, max_iters=0, stream=None):
     """Solve 0 <= qv + dt D^T K D gamma _|_ gamma >= 0 on the GPU (gamma
     in/out).  Returns (iterations, FP64 residual, status)."""
     m = ia.numel()
     it = C.c_int32(0)
     res = C.c_double(0.0)
     rc = lib().relcp_lcp_solve_device(nb, m, _tptr(ia), _tptr(ib), _tptr(n_soa), _tptr(ta_soa), _tptr(tb_soa),
-                                      _tptr(qv), _tptr(kt), _tptr(Kr_soa), dt, 1 if planar else 0, precision, tol,
-                                      max_iters, _tptr(gamma), C.byref(it), C.byref(res), stream)
+                                      _tptr(qv), _tptr(kt), _tptr(Kr_soa), dt, 1 if planar else 0, precision, mode,
+                                      tol, max_iters, _tptr(gamma), C.byref(it), C.byref(res), stream)
     return it.value, res.value, rc
 
 

@@ -159,9 +159,10 @@ def _wrench(n, ia, ib, nrm, ta, tb, g):
     return W
 
 
+@pytest.mark.parametrize("mode", [1, 3], ids=["grid", "rowgraph"])
 @pytest.mark.parametrize("precision", [64, 32])
 @pytest.mark.parametrize("seed", [0, 1])
-def test_lcp_solver(dev, precision, seed):
+def test_lcp_solver(dev, precision, seed, mode):
     n, m = 120, 600
     ia, ib, nrm, ta, tb, kt, Kr, qv = _random_lcp(seed, n, m)
     dt = 0.05
@@ -173,8 +174,8 @@ def test_lcp_solver(dev, precision, seed):
     it, res, rc = R.lcp_solve_device(n, tens(ia, dev, torch.int32), tens(ib, dev, torch.int32), soa(nrm, dev),
                                      soa(ta, dev), soa(tb, dev), tens(qv, dev, torch.float64),
                                      tens(kt, dev, torch.float64), tens(Kr6, dev, torch.float64), dt, gam,
-                                     precision=precision, tol=tol)
-    print("LCP", precision, seed, "oracle iters", it_or, "gpu iters", it, "res", res, flush=True)
+                                     precision=precision, mode=mode, tol=tol)
+    print("LCP", precision, seed, mode, "oracle iters", it_or, "gpu iters", it, "res", res, flush=True)
     assert rc == 0 and res <= tol
     g = gam.cpu().numpy()
     W1 = _wrench(n, ia, ib, nrm, ta, tb, g)
@@ -186,7 +187,8 @@ def test_lcp_solver(dev, precision, seed):
         assert abs(it - it_or) <= max(10, it_or // 2)
 
 
-def test_lcp_empty_and_trivial(dev):
+@pytest.mark.parametrize("mode", [1, 3], ids=["grid", "rowgraph"])
+def test_lcp_empty_and_trivial(dev, mode):
     n = 4
     kt = torch.ones(n, dtype=torch.float64, device=dev)
     Kr6 = torch.zeros((6, n), dtype=torch.float64, device=dev)
@@ -195,14 +197,15 @@ def test_lcp_empty_and_trivial(dev):
     z = torch.zeros((3, 0), dtype=torch.float64, device=dev)
     gam = torch.zeros(1, dtype=torch.float64, device=dev)
     it, res, rc = R.lcp_solve_device(n, e, e, z, z, z, torch.zeros(0, dtype=torch.float64, device=dev), kt, Kr6, 0.1,
-                                     gam)
+                                     gam, mode=mode)
     assert rc == 0 and it == 0 and res == 0.0
     # one row, closed form gamma = max(0, -qv / A)
     ia, ib = tens([0], dev, torch.int32), tens([1], dev, torch.int32)
     nrm = soa([[1.0, 0, 0]], dev)
     zero3 = soa([[0.0, 0, 0]], dev)
     gam = torch.zeros(1, dtype=torch.float64, device=dev)
-    it, res, rc = R.lcp_solve_device(n, ia, ib, nrm, zero3, zero3, tens([-0.3], dev, torch.float64), kt, Kr6, 0.1, gam)
+    it, res, rc = R.lcp_solve_device(n, ia, ib, nrm, zero3, zero3, tens([-0.3], dev, torch.float64), kt, Kr6, 0.1, gam,
+                                     mode=mode)
     assert rc == 0
     assert abs(gam.item() - 0.3 / (0.1 * 2.0)) < 1e-13
 
@@ -232,7 +235,7 @@ def _compare_step(res_gpu, sim, ref, tol_u):
     return True
 
 
-@pytest.mark.parametrize("mode", [1, 2], ids=["grid", "resident"])
+@pytest.mark.parametrize("mode", [1, 2, 3], ids=["grid", "resident", "rowgraph"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("precision", [64, 32])
 def test_step_overdamped_packing(dev, seed, precision, mode):
@@ -307,8 +310,8 @@ def test_inertial_two_ellipsoids_trajectory(dev):
     assert contacts > 0
 
 
-@pytest.mark.parametrize("cfg", [(1, 256, False), (2, 256, True), (2, 512, False), (2, 1024, True)],
-                         ids=["grid", "res256lds", "res512", "res1024lds"])
+@pytest.mark.parametrize("cfg", [(1, 256, False), (2, 256, True), (2, 512, False), (2, 1024, True), (3, 256, False)],
+                         ids=["grid", "res256lds", "res512", "res1024lds", "rowgraph"])
 def test_batched_packings_match_per_packing_oracle(dev, cfg):
     parts = [compressed_packing(s, 120, 24) for s in (3, 4, 5)]
     x = np.concatenate([p["x"] * 0.99 for p in parts])
@@ -386,3 +389,28 @@ def test_batch_of_uneven_packings_and_autotune(dev):
     x2, q2 = xg.copy(), qg.copy()
     res2 = sim.step(5e-3, 1e-5, 1e-12)
     assert res2["status"] == 0
+
+
+@pytest.mark.parametrize("mode", [2, 3], ids=["resident", "rowgraph"])
+def test_candidate_list_kept_across_steps(dev, mode):
+    """The candidate list is built once and kept over a compaction run while
+    the displacement bound allows; every step still matches the oracle's
+    step (full candidate search) from the same state."""
+    S = compressed_packing(4, 150, 26)
+    box = S["box"].copy()
+    sim = sim_from(dict(S, box=box), skin=0.2, warm_start=R.WS_COLD)
+    sim.set_lcp_config(mode, 256, True)
+    rebuilt = []
+    for k in range(8):
+        x, q, _ = sim.get_state()
+        sim.affine_rescale(0.998)
+        box = box * 0.998
+        ref = O.relcp_step(x * 0.998, q, S["kind"], S["shape"], S["rho_xi"], box, tol=1e-12, lcp_mode=1, dt=5e-3,
+                           eps=1e-5, skin=0.2)
+        res = sim.step(5e-3, 1e-5, 1e-12)
+        rebuilt.append(res["pairs_rebuilt"])
+        print("step", k, "rebuilt", res["pairs_rebuilt"], "pairs", res["n_pairs"], "oracle pairs", ref["n_pairs"],
+              flush=True)
+        assert res["n_pairs"] >= ref["n_pairs"]
+        _compare_step(res, sim, ref, 1e-8)
+    assert rebuilt[0] == 1 and sum(rebuilt) < len(rebuilt)
