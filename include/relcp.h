@@ -19,6 +19,9 @@
  *  - One context per stream; calls on one context are not thread-safe.
  *  - Units are the caller's; all lengths, times and forces consistent.
  *  - Errors leave the state untouched: a step commits only on acceptance.
+ *  - relcp_step and relcp_affine_rescale may return before the last of
+ *    their device work has run (it is ordered on the context's stream);
+ *    every call that reads results back waits for it.
  */
 #ifndef RELCP_H
 #define RELCP_H

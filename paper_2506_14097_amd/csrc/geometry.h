@@ -29,7 +29,9 @@ struct SnsdArgs {
     // the centre-to-centre normal
     const double *Rb;
     int *flag;                   // per pair, or null
-    unsigned long long *minphi;  // order keys of min Phi and min |Phi + eps|, or null
+    // per-block order keys of min Phi and min |Phi + eps| (snsd_blocks(m)
+    // slots each), or null
+    unsigned long long *minphi;
     unsigned long long *minmarg;
 };
 
@@ -58,6 +60,10 @@ struct BodySetupArgs {
 };
 
 void launch_body_setup(const BodySetupArgs &a, hipStream_t s);
+int snsd_blocks(int m);
+// maxdisp: trial_blocks(nb) slots, each the bits of its block's largest
+// surface-point displacement bound
+int trial_blocks(int nb);
 void launch_trial(int nb, const double *x, int ldx, const double *q, int ldq, const double *vfree, const double *vc,
                   int ldv, double dt, const int *kind, const double *p, int ldp, const double *Rb, double *xt,
                   double *qt, double *geo, int ldg, double *vout, unsigned long long *maxdisp, hipStream_t s);

@@ -105,19 +105,24 @@ struct Snsd {
 __device__ Snsd snsd_ellipsoid(d3 d, const sym3 &A, const sym3 &B, d3 hint, bool has_hint) {
     double dl = len(d);
     d3 n0 = dl > 0.0 ? (1.0 / dl) * d : mk(1, 0, 0);
-    d3 best_n = n0;
+    // A hint (the normal of the same pair a moment earlier) is tried first;
+    // if it converges to a separated or shallow configuration, where the
+    // maximiser is unique, the centre-line start would reach the same point.
+    d3 best_n = has_hint ? hint : n0;
     double best = gap_newton(best_n, d, A, B, 60);
-    if (has_hint) {
-        d3 n1 = hint;
+    double ha = sqrt(dot(best_n, mul(A, best_n))), hb = sqrt(dot(best_n, mul(B, best_n)));
+    if (has_hint && best < -0.05 * (ha + hb)) {
+        d3 n1 = n0;
         double F1 = gap_newton(n1, d, A, B, 60);
         if (F1 > best) {
             best = F1;
             best_n = n1;
         }
+        ha = sqrt(dot(best_n, mul(A, best_n)));
+        hb = sqrt(dot(best_n, mul(B, best_n)));
     }
     // deep overlap: several local maxima are possible; seed from a coarse
     // Fibonacci sphere and keep the best converged value
-    double ha = sqrt(dot(best_n, mul(A, best_n))), hb = sqrt(dot(best_n, mul(B, best_n)));
     if (best < -0.05 * (ha + hb) || dl == 0.0) {
         const int ns = 64;
         double bs = -1e300;
@@ -409,10 +414,16 @@ __global__ void k_trial(int nb, const double *__restrict__ x, int ldx, const dou
         // bound on the displacement of any surface point
         disp = dt * sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) + Rb[i] * ang;
     }
-    // wave max, then one atomic per wave (non-negative doubles order like
-    // their bit patterns)
+    // block max into this block's slot (reduced in a fixed order later)
+    __shared__ double wmax[4];
     for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) disp = fmax(disp, __shfl_xor(disp, o, RELCP_WAVE));
-    if ((threadIdx.x & (RELCP_WAVE - 1)) == 0 && disp > 0.0) atomicMax(maxdisp, dbl_bits(disp));
+    if ((threadIdx.x & (RELCP_WAVE - 1)) == 0) wmax[threadIdx.x / RELCP_WAVE] = disp;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double mx = 0.0;
+        for (int k = 0; k < (int)(blockDim.x / RELCP_WAVE); ++k) mx = fmax(mx, wmax[k]);
+        maxdisp[blockIdx.x] = dbl_bits(mx);  // non-negative doubles order like their bit patterns
+    }
 }
 
 // ===========================================================================
@@ -477,13 +488,25 @@ __global__ void __launch_bounds__(256) k_snsd_pairs(SnsdArgs A) {
         if (A.flag) A.flag[k] = (A.mode == 0) ? (s.phi <= A.thresh ? 1 : 0) : (s.phi < -A.eps ? 1 : 0);
     }
     if (A.minphi) {
+        // block minima into this block's slots (reduced in a fixed order later)
+        __shared__ double wphi[4], wmarg[4];
         for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) {
             phi = fmin(phi, __shfl_xor(phi, o, RELCP_WAVE));
             marg = fmin(marg, __shfl_xor(marg, o, RELCP_WAVE));
         }
-        if ((threadIdx.x & (RELCP_WAVE - 1)) == 0 && phi < 1e300) {
-            atomicMin(A.minphi, order_key(phi));
-            atomicMin(A.minmarg, order_key(marg));
+        if ((threadIdx.x & (RELCP_WAVE - 1)) == 0) {
+            wphi[threadIdx.x / RELCP_WAVE] = phi;
+            wmarg[threadIdx.x / RELCP_WAVE] = marg;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double mp = 1e300, mm = 1e300;
+            for (int k = 0; k < (int)(blockDim.x / RELCP_WAVE); ++k) {
+                mp = fmin(mp, wphi[k]);
+                mm = fmin(mm, wmarg[k]);
+            }
+            A.minphi[blockIdx.x] = mp < 1e300 ? order_key(mp) : ~0ull;
+            A.minmarg[blockIdx.x] = mm < 1e300 ? order_key(mm) : ~0ull;
         }
     }
 }
@@ -634,6 +657,9 @@ void launch_trial(int nb, const double *x, int ldx, const double *q, int ldq, co
     hipLaunchKernelGGL(k_trial, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, x, ldx, q, ldq, vfree, vc, ldv, dt, kind, p,
                        ldp, Rb, xt, qt, geo, ldg, vout, maxdisp);
 }
+
+int snsd_blocks(int m) { return nblk(m > 0 ? m : 1, 256); }
+int trial_blocks(int nb) { return nblk(nb > 0 ? nb : 1, 256); }
 
 void launch_snsd_pairs(const SnsdArgs &a, hipStream_t s) {
     if (a.m <= 0) return;

@@ -68,6 +68,9 @@ struct PgdCtl {
     double *partials;
     int nbg;
     double tol;
+    // host-mapped mirrors of fin and done (or null), written with them
+    PgdState *fin_h;
+    int *done_h;
 };
 
 // Row-graph form of the LCP matrix A = dt D^T K D: one entry per (row,
@@ -102,7 +105,8 @@ struct RowGraphFill {
     const int *base;
     double dt;
     size_t cap;        // entry slots allocated
-    int *overflow;     // set when the slots do not suffice (nothing is written past cap)
+    int *count;        // device entry counter of the width pass (read here, then cleared for the next build)
+    int *report;       // host-mapped: [0] slots needed / 64, [1] entries, [2] set to 1 on overflow
     int *col;
     double *val64;
     float *val32;
@@ -172,9 +176,10 @@ void launch_iota(int n, int *v, hipStream_t s);
 void launch_promote(int m, const float *g32, double *g64, hipStream_t s);
 void launch_demote(int m, const double *g64, float *g32, hipStream_t s);
 
-// sum over rows of gamma (g - qv) = gamma^T A gamma, FP64, into out[0]
-void launch_work(int m, const double *gam, const double *g, const double *qv, double *partials, unsigned *ticket,
-                 double *out, hipStream_t s);
+// gamma^T A gamma = sum over rows of gamma (g - qv), FP64, as work_blocks(m)
+// per-block partial sums
+int work_blocks(int m);
+void launch_work(int m, const double *gam, const double *g, const double *qv, double *partials, hipStream_t s);
 
 // lam[pair[r]] += gamma[r] for the rows generated at recursion `level`
 void launch_pair_lambda(int m, const int *rec, const int *pair, const double *gam, int level, double *lam,

@@ -269,6 +269,8 @@ __global__ void k_pgd_init(PgdCtl C) {
         C.S[1] = s;
         *C.fin = s;
         *C.done = 0;
+        if (C.fin_h) *C.fin_h = s;
+        if (C.done_h) *C.done_h = 0;
     }
 }
 
@@ -393,6 +395,8 @@ __global__ void __launch_bounds__(kThreads) k_scatter(RowsT<T> R, BodiesT<T> B, 
             if (ns.conv) {
                 *C.fin = ns;
                 *C.done = 1;
+                if (C.fin_h) *C.fin_h = ns;
+                if (C.done_h) *C.done_h = 1;
             }
         }
         if (ns.conv) return;
@@ -524,7 +528,11 @@ __global__ void __launch_bounds__(kThreads) k_pgd_finalize(PgdCtl C, int par) {
     if (threadIdx.x == 0) {
         C.S[par] = ns;
         *C.fin = ns;
-        if (ns.conv) *C.done = 1;
+        if (C.fin_h) *C.fin_h = ns;
+        if (ns.conv) {
+            *C.done = 1;
+            if (C.done_h) *C.done_h = 1;
+        }
     }
 }
 
@@ -540,17 +548,25 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_width(int m, const int *_
         const int a = ia[r], b = ib[r];
         w = off[a + 1] - off[a] + off[b + 1] - off[b];
     }
+    __shared__ int bsum[kWaves];
     int sum = w;
     for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) {
         w = max(w, __shfl_xor(w, o, RELCP_WAVE));
         sum += __shfl_xor(sum, o, RELCP_WAVE);
     }
     const int ns = (m + RELCP_WAVE - 1) / RELCP_WAVE;
-    if ((threadIdx.x & (RELCP_WAVE - 1)) == 0 && r / RELCP_WAVE < ns) {
-        width[r / RELCP_WAVE] = w;
-        atomicAdd(count, sum);
+    const int lane = threadIdx.x & (RELCP_WAVE - 1), wv = threadIdx.x / RELCP_WAVE;
+    if (lane == 0) {
+        if (r / RELCP_WAVE < ns) width[r / RELCP_WAVE] = w;
+        bsum[wv] = sum;
     }
     if (r == 0) width[ns] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int k = 0; k < kWaves; ++k) t += bsum[k];
+        if (t) atomicAdd(count, t);
+    }
 }
 
 __global__ void __launch_bounds__(kThreads) k_incidence_jacobian(int m2, const int *__restrict__ ent,
@@ -582,8 +598,14 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_fill(RowGraphFill A) {
     const int b0 = A.base[sl], w = A.base[sl + 1] - b0;
     const int L = A.ldr, lb = A.ldb;
     const d3 nr = mk(A.n[r], A.n[L + r], A.n[2 * L + r]);
+    if (r == 0) {
+        // the width pass and the scan are complete: report and clear its counter
+        A.report[0] = A.base[(A.m + RELCP_WAVE - 1) / RELCP_WAVE];
+        A.report[1] = *A.count;
+        *A.count = 0;
+    }
     if ((size_t)RELCP_WAVE * (b0 + w) > A.cap) {
-        *A.overflow = 1;
+        A.report[2] = 1;
         return;
     }
     int k = 0;
@@ -689,6 +711,8 @@ __global__ void __launch_bounds__(kThreads)
             if (ns.conv) {
                 *C.fin = ns;
                 *C.done = 1;
+                if (C.fin_h) *C.fin_h = ns;
+                if (C.done_h) *C.done_h = 1;
             }
         }
         if (ns.conv) return;
@@ -752,32 +776,16 @@ __global__ void k_demote(int m, const double *__restrict__ a, float *__restrict_
     if (i < m) b[i] = (float)a[i];
 }
 
+// per-block sums of gamma (g - qv) into partials[block] (summed in a fixed
+// order by the caller's report)
 __global__ void __launch_bounds__(kThreads) k_work(int m, const double *__restrict__ gam, const double *__restrict__ g,
-                                                   const double *__restrict__ qv, double *__restrict__ partials,
-                                                   unsigned *__restrict__ ticket, double *__restrict__ out) {
+                                                   const double *__restrict__ qv, double *__restrict__ partials) {
     __shared__ double sh[4][kWaves];
-    __shared__ bool last;
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     double w = 0.0, z0 = 0.0, z1 = 0.0, z2 = 0.0;
     if (c < m) w = gam[c] * (g[c] - qv[c]);
     block_reduce4(w, z0, z1, z2, sh);
-    if (threadIdx.x == 0) {
-        partials[blockIdx.x] = w;
-        __threadfence();
-        unsigned t = atomicAdd(ticket, 1u);
-        last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    w = 0.0;
-    z0 = z1 = z2 = 0.0;
-    for (int k = threadIdx.x; k < (int)gridDim.x; k += kThreads) w += __builtin_nontemporal_load(partials + k);
-    block_reduce4(w, z0, z1, z2, sh);
-    if (threadIdx.x == 0) {
-        out[0] = w;
-        ticket[0] = 0;
-    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = w;
 }
 
 __global__ void k_pair_lambda(int m, const int *__restrict__ rec, const int *__restrict__ pair,
@@ -948,10 +956,10 @@ void launch_demote(int m, const double *g64, float *g32, hipStream_t s) {
     if (m > 0) hipLaunchKernelGGL(k_demote, dim3(nblk(m, 256)), dim3(256), 0, s, m, g64, g32);
 }
 
-void launch_work(int m, const double *gam, const double *g, const double *qv, double *partials, unsigned *ticket,
-                 double *out, hipStream_t s) {
-    int nbk = nblk(m > 0 ? m : 1, kThreads);
-    hipLaunchKernelGGL(k_work, dim3(nbk), dim3(kThreads), 0, s, m, gam, g, qv, partials, ticket, out);
+int work_blocks(int m) { return nblk(m > 0 ? m : 1, kThreads); }
+
+void launch_work(int m, const double *gam, const double *g, const double *qv, double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_work, dim3(work_blocks(m)), dim3(kThreads), 0, s, m, gam, g, qv, partials);
 }
 
 void launch_pair_lambda(int m, const int *rec, const int *pair, const double *gam, int level, double *lam,

@@ -69,9 +69,10 @@ __global__ void k_soa_to_aos(int n, int comps, const double *__restrict__ in, in
     size_t o = (size_t)ocomps * perm[i];
     for (int k = 0; k < ocomps; ++k) out[o + k] = in[(c0 + k) * ld + i];
 }
-__global__ void k_scale(int n, double *__restrict__ x, double s) {
+__global__ void k_scale(int n, double *__restrict__ x, int nbox, double *__restrict__ box, double s) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] *= s;
+    if (i < nbox) box[i] *= s;
 }
 
 struct Timer {
@@ -84,6 +85,46 @@ struct Timer {
     }
 };
 
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// small bookkeeping kernels of the step
+// ---------------------------------------------------------------------------
+namespace {
+// Fixed-order reduction of the per-block results of one recursion's tail:
+// largest displacement bound (trial), smallest Phi key and margin key
+// (narrowphase at the trial), work sum; written to host-mapped memory.
+__global__ void __launch_bounds__(256) k_report(int nt, const unsigned long long *disp, int ns,
+                                                const unsigned long long *phi, const unsigned long long *marg, int nw,
+                                                const double *work, unsigned long long *red_h, double *work_h) {
+    __shared__ unsigned long long s0[256], s1[256], s2[256];
+    __shared__ double s3[256];
+    unsigned long long d = 0ull, p = ~0ull, q = ~0ull;
+    double w = 0.0;
+    for (int k = threadIdx.x; k < nt; k += 256) d = disp[k] > d ? disp[k] : d;
+    for (int k = threadIdx.x; k < ns; k += 256) {
+        p = phi[k] < p ? phi[k] : p;
+        q = marg[k] < q ? marg[k] : q;
+    }
+    for (int k = threadIdx.x; k < nw; k += 256) w += work[k];
+    s0[threadIdx.x] = d;
+    s1[threadIdx.x] = p;
+    s2[threadIdx.x] = q;
+    s3[threadIdx.x] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 256; ++k) {
+            d = s0[k] > d ? s0[k] : d;
+            p = s1[k] < p ? s1[k] : p;
+            q = s2[k] < q ? s2[k] : q;
+            w += s3[k];
+        }
+        red_h[0] = d;
+        red_h[1] = p;
+        red_h[2] = q;
+        work_h[0] = w;
+    }
+}
 }  // namespace
 
 // ===========================================================================
@@ -128,6 +169,7 @@ struct relcp_ctx {
     // since the build (vl_used) stays below 2 margin; pairs of the list
     // beyond skin are cut by a bounding-sphere test in the narrowphase
     bool vl_valid = false, prev_is_list = false;
+    bool hint_ok = false;  // snsdt holds the normals of the last accepted trial for the current list
     double vl_used = 0.0;
     double vl_margin() const { return 0.25 * skin; }
     double vl_radius() const { return skin + 2.0 * vl_margin(); }
@@ -144,8 +186,7 @@ struct relcp_ctx {
     // LCP state and reductions
     DBuf<PgdState> pst;
     DBuf<double> partials, work_out;
-    DBuf<unsigned> ticket;
-    DBuf<unsigned long long> red;  // [0] max displacement bits, [1] min Phi key, [2] min margin key
+    DBuf<unsigned long long> red;  // per-block trial results: displacement bits, then min-Phi and margin keys
     DBuf<int> scan_scratch, dtotal;
     // optional kernel timing (HIP events on the stream)
     static constexpr int kClasses = 9;
@@ -189,7 +230,9 @@ struct relcp_ctx {
     }
 
     // pinned host mirrors
-    PgdState *pst_h = nullptr;  // fin and the done slot
+    // small host buffers written by kernels directly (mapped, coherent; read
+    // after the stream is synchronised) and their device addresses
+    PgdState *pst_h = nullptr, *pst_d = nullptr;  // fin and the done slot
     int last_iters[2] = {8, 8};  // previous solve's iteration count (FP32, FP64)
     // LCP execution: mode 0 = automatic, 1 = grid (two passes per iteration
     // over all rows), 2 = resident (one workgroup per packing, one launch),
@@ -227,8 +270,10 @@ struct relcp_ctx {
     DBuf<double> rowscale;
     int m0_last = 0;
     int *int_h = nullptr;
-    unsigned long long *red_h = nullptr;
-    double *dbl_h = nullptr;
+    unsigned long long *red_h = nullptr, *red_hd = nullptr;
+    double *dbl_h = nullptr, *dbl_hd = nullptr;
+    int *int_d = nullptr;
+    void alloc_host();
 
     ~relcp_ctx() {
         DBuf<double> *ds[] = {&x, &q, &u, &p, &rho, &fext, &xt, &qt, &geo, &geot, &Rb, &K, &vfree, &vc64, &vout,
@@ -244,7 +289,6 @@ struct relcp_ctx {
         grids.release();
         keys.release();
         pst.release();
-        ticket.release();
         red.release();
         if (pst_h) (void)hipHostFree(pst_h);
         if (int_h) (void)hipHostFree(int_h);
@@ -275,6 +319,23 @@ struct relcp_ctx {
     int step(double dt, double eps, double tol, relcp_step_stats *st);
     void sync() { HIP_OK(hipStreamSynchronize(stream)); }
 };
+
+template <typename T>
+static T *host_mapped(size_t n, T **dev) {
+    void *h = nullptr, *d = nullptr;
+    HIP_OK(hipHostMalloc(&h, n * sizeof(T), hipHostMallocMapped | hipHostMallocCoherent));
+    std::memset(h, 0, n * sizeof(T));
+    HIP_OK(hipHostGetDevicePointer(&d, h, 0));
+    *dev = static_cast<T *>(d);
+    return static_cast<T *>(h);
+}
+
+void relcp_ctx::alloc_host() {
+    if (!pst_h) pst_h = host_mapped<PgdState>(2, &pst_d);
+    if (!int_h) int_h = host_mapped<int>(16, &int_d);
+    if (!red_h) red_h = host_mapped<unsigned long long>(8, &red_hd);
+    if (!dbl_h) dbl_h = host_mapped<double>(8, &dbl_hd);
+}
 
 // ---------------------------------------------------------------------------
 // validation and upload
@@ -355,6 +416,7 @@ void relcp_ctx::upload_bodies(const relcp_bodies *B, const relcp_shapes *S) {
     log_valid = false;
     vl_valid = false;
     prev_is_list = false;
+    hint_ok = false;
     nbatch = B->n_batch <= 0 ? 1 : B->n_batch;
     boff.assign(nbatch + 1, 0);
     for (int k = 0; k <= nbatch; ++k) boff[k] = B->batch_off ? B->batch_off[k] : (k ? n : 0);
@@ -589,10 +651,9 @@ void relcp_ctx::broadphase(const double *xs, double skin_) {
         launch_pairs(false, N, xs, N, Rb.p, body_batch.p, grids.p, body_cell.p, cell_start.p, cell_count.p,
                      cell_items.p, skin_, pair_count.p, nullptr, nullptr, nullptr, 0, stream);
     });
-    exclusive_scan(pair_count.p, pair_off.p, N, dtotal.p, scan_scratch, stream);
-    HIP_OK(hipMemcpyAsync(int_h, dtotal.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+    exclusive_scan(pair_count.p, pair_off.p, N, int_d, scan_scratch, stream);  // total -> int_h[0]
     sync();
-    np = int_h[0];
+    np = N > 0 ? int_h[0] : 0;
     if (np < 0) throw Error{RELCP_E_CAPACITY, "pair count overflow"};
     ensure_pairs(std::max(np, 1));
     timed(3, [&] {
@@ -607,6 +668,7 @@ void relcp_ctx::candidate_pairs(relcp_step_stats &S) {
         vl_valid = true;
         vl_used = 0.0;
         prev_is_list = false;
+        hint_ok = false;
         S.pairs_rebuilt = 1;
     }
     S.n_pairs = np;
@@ -704,7 +766,10 @@ void relcp_ctx::build_rowgraph(double dt) {
     const int ns = rowgraph_slices(m);
     rg_width.ensure(ns + 1);
     rg_base.ensure(ns + 1);
-    rg_flags.ensure(2);
+    if (!rg_flags.p) {
+        rg_flags.ensure(1);
+        HIP_OK(hipMemsetAsync(rg_flags.p, 0, sizeof(int), stream));  // entry counter, cleared by each fill
+    }
     rg_jb.ensure(12 * (size_t)std::max(m, 1));
     const size_t want = std::max<size_t>((size_t)RELCP_WAVE * ns * 16, 64);
     if (rg_cap < want) {
@@ -714,19 +779,16 @@ void relcp_ctx::build_rowgraph(double dt) {
         rg_val64.ensure(rg_cap);
         rg_val32.ensure(rg_cap);
     }
-    HIP_OK(hipMemsetAsync(rg_flags.p, 0, 2 * sizeof(int), stream));
+    int_h[4] = int_h[5] = int_h[6] = 0;  // slots / 64, entries, overflow (written by the fill)
     launch_rowgraph_width(m, ria.p, rib.p, csr_off.p, rg_width.p, rg_flags.p, stream);
     exclusive_scan(rg_width.p, rg_base.p, ns + 1, nullptr, scan_scratch, stream);
     launch_incidence_jacobian(m, csr_ent.p, rn64.p, rta64.p, rtb64.p, ldr, rg_jb.p, stream);
     RowGraphFill f{};
     f.m = m; f.ldr = ldr; f.ia = ria.p; f.ib = rib.p; f.n = rn64.p; f.ta = rta64.p; f.tb = rtb64.p;
     f.ldb = n; f.K = K.p; f.off = csr_off.p; f.ent = csr_ent.p; f.jb = rg_jb.p; f.base = rg_base.p; f.dt = dt;
-    f.cap = rg_cap; f.overflow = rg_flags.p + 1;
+    f.cap = rg_cap; f.count = rg_flags.p; f.report = int_d + 4;
     f.col = rg_col.p; f.val64 = rg_val64.p; f.val32 = rg_val32.p;
-    launch_rowgraph_fill(f, stream);
-    // slots needed, entry count and overflow flag, read with the solve's first read-back
-    HIP_OK(hipMemcpyAsync(int_h + 4, rg_base.p + ns, sizeof(int), hipMemcpyDeviceToHost, stream));
-    HIP_OK(hipMemcpyAsync(int_h + 5, rg_flags.p, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
+    launch_rowgraph_fill(f, stream);  // reports slots, entries and overflow, read after the solve's first sync
     rg_valid = true;
     rg_dt = dt;
 }
@@ -780,7 +842,7 @@ int relcp_ctx::solve(double dt, double tol, int &iters, double &res) {
     // pst: S[0], S[1], fin, then a slot whose first int is the done flag
     pst.ensure(4);
     PgdCtl C{pst.p, pst.p + 2, reinterpret_cast<int *>(pst.p + 3), partials.p, lcp_gather_blocks(m),
-             lcp_fixed > 0 ? -1.0 : tol};
+             lcp_fixed > 0 ? -1.0 : tol, pst_d, reinterpret_cast<int *>(pst_d + 1)};
     const int cap = lcp_fixed > 0 ? lcp_fixed : lcp_max_iters;
     const int pk = sizeof(T) == 8 ? 1 : 0;
     launch_pgd_init(C, stream);
@@ -799,7 +861,6 @@ int relcp_ctx::solve(double dt, double tol, int &iters, double &res) {
             timed(0, [&] { launch_lcp_scatter<T>(1, R, Bd, C, par, stream); });
             timed(1, [&] { launch_lcp_gather<T>(1, R, Bd, dt, C, par, stream); });
         }
-        HIP_OK(hipMemcpyAsync(pst_h, pst.p + 2, 2 * sizeof(PgdState), hipMemcpyDeviceToHost, stream));
         sync();
         if (*reinterpret_cast<int *>(pst_h + 1)) {
             done = true;
@@ -811,7 +872,6 @@ int relcp_ctx::solve(double dt, double tol, int &iters, double &res) {
         // account for the last gather (iteration cap or fixed-iteration run):
         // the state after it follows S[(j - 1) & 1] into slot j & 1
         launch_pgd_finalize(C, j & 1, stream);
-        HIP_OK(hipMemcpyAsync(pst_h, pst.p + 2, 2 * sizeof(PgdState), hipMemcpyDeviceToHost, stream));
         sync();
     }
     const bool conv = *reinterpret_cast<int *>(pst_h + 1) != 0;
@@ -849,7 +909,7 @@ int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt
     const int cap = lcp_fixed > 0 ? lcp_fixed : lcp_max_iters;
     const int pk = sizeof(T) == 8 ? 1 : 0;
     PgdCtl C{pst.p, pst.p + 2, reinterpret_cast<int *>(pst.p + 3), partials.p, lcp_gather_blocks(m),
-             lcp_fixed > 0 ? -1.0 : tol};
+             lcp_fixed > 0 ? -1.0 : tol, pst_d, reinterpret_cast<int *>(pst_d + 1)};
     auto ctl = [&](int par) {  // control block of a pass with parity par: reads the other partials buffer
         PgdCtl c = C;
         c.partials = partials.p + (size_t)(par ^ 1) * stride;
@@ -883,7 +943,6 @@ int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt
                                        par ? g1 : g0, ctl(par), partials.p + (size_t)par * stride, par, stream);
                 });
             }
-            HIP_OK(hipMemcpyAsync(pst_h, pst.p + 2, 2 * sizeof(PgdState), hipMemcpyDeviceToHost, stream));
             sync();
             if (first && fresh) {
                 first = false;
@@ -913,13 +972,13 @@ int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt
             PgdCtl cf = C;
             cf.partials = partials.p + (size_t)((j - 1) & 1) * stride;
             launch_pgd_finalize(cf, j & 1, stream);
-            HIP_OK(hipMemcpyAsync(pst_h, pst.p + 2, 2 * sizeof(PgdState), hipMemcpyDeviceToHost, stream));
         }
         break;
     }
+    const bool seen = *reinterpret_cast<int *>(pst_h + 1) != 0;  // converged at a read-back: pst_h is final
     launch_rowstate_unpack<T>(m, z0, z1, g0, g1, C.fin, R.gam, R.g, stream);
     if constexpr (sizeof(T) == 8) timed(0, [&] { launch_lcp_scatter<T>(0, R, Bd, C, 0, stream); });
-    sync();
+    if (!seen) sync();
     const bool conv = *reinterpret_cast<int *>(pst_h + 1) != 0;
     iters = pst_h[0].iter;
     res = pst_h[0].res;
@@ -952,16 +1011,17 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     t_other += tm.ms();
 
     // SNSD at C^k, iteration-0 set A_0 = {Phi_0 <= skin}
-    red.ensure(4);
     SnsdArgs sa{};
     sa.m = np; sa.pa = pa.p; sa.pb = pb.p; sa.body_batch = body_batch.p; sa.x = x.p; sa.ldx = N; sa.geo = geo.p;
     sa.ldg = N; sa.kind = kind.p; sa.p = p.p; sa.ldp = N; sa.boxes = boxes.p; sa.planar = planar; sa.hint = nullptr;
     sa.out = snsd0.p; sa.ldo = ldp; sa.mode = 0; sa.thresh = skin; sa.eps = eps; sa.flag = pflag.p;
     sa.minphi = nullptr; sa.minmarg = nullptr; sa.Rb = Rb.p;
+    // Newton starts from the normals of the accepted trial of the previous
+    // step (the same configuration up to the caller's rescale)
+    if (hint_ok) sa.hint = snsdt.p + ldp;
     timed(2, [&] { launch_snsd_pairs(sa, stream); });
-    exclusive_scan(pflag.p, pscan.p, np, dtotal.p, scan_scratch, stream);
+    exclusive_scan(pflag.p, pscan.p, np, np > 0 ? int_d : nullptr, scan_scratch, stream);  // total -> int_h[0]
     launch_compact(np, pflag.p, pscan.p, sel.p, stream);
-    HIP_OK(hipMemcpyAsync(int_h, dtotal.p, sizeof(int), hipMemcpyDeviceToHost, stream));
     sync();
     int m0 = np > 0 ? int_h[0] : 0;
     t_narrow += tm.ms();
@@ -1009,15 +1069,13 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         // W_n = gamma^T A gamma (its block partials need their own sizing:
         // the resident LCP mode never touches the grid-mode partials)
         partials.ensure(lcp_partials_needed(m));
-        work_out.ensure(1);
-        ticket.ensure(1);
-        HIP_OK(hipMemsetAsync(ticket.p, 0, sizeof(unsigned), stream));
-        launch_work(m, rgam64.p, rg64.p, rqv64.p, partials.p, ticket.p, work_out.p, stream);
+        const int nw = work_blocks(m), nt = trial_blocks(N), nsb = snsd_blocks(np);
+        work_out.ensure(nw);
+        red.ensure((size_t)nt + 2 * (size_t)nsb);
+        launch_work(m, rgam64.p, rg64.p, rqv64.p, work_out.p, stream);
         t_lcp += tm.ms();
 
         // trial configuration C_{n+1} = C^k (+) dt V_n
-        unsigned long long init[3] = {0ull, ~0ull, ~0ull};
-        HIP_OK(hipMemcpyAsync(red.p, init, sizeof(init), hipMemcpyHostToDevice, stream));
         timed(4, [&] {
             launch_trial(N, x.p, N, q.p, N, vfree.p, vc64.p, N, dt, kind.p, p.p, N, Rb.p, xt.p, qt.p, geot.p, N,
                          vout.p, red.p, stream);
@@ -1025,13 +1083,12 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         // SNSD of every candidate pair at the trial configuration
         SnsdArgs sb = sa;
         sb.x = xt.p; sb.geo = geot.p; sb.hint = snsd0.p + ldp; sb.out = snsdt.p; sb.mode = 1; sb.flag = pflag.p;
-        sb.minphi = red.p + 1; sb.minmarg = red.p + 2;
+        sb.minphi = red.p + nt; sb.minmarg = red.p + nt + nsb;
         timed(2, [&] { launch_snsd_pairs(sb, stream); });
-        exclusive_scan(pflag.p, pscan.p, np, dtotal.p, scan_scratch, stream);
+        exclusive_scan(pflag.p, pscan.p, np, np > 0 ? int_d : nullptr, scan_scratch, stream);  // -> int_h[0]
         launch_compact(np, pflag.p, pscan.p, sel.p, stream);
-        HIP_OK(hipMemcpyAsync(red_h, red.p, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
-        HIP_OK(hipMemcpyAsync(int_h, dtotal.p, sizeof(int), hipMemcpyDeviceToHost, stream));
-        HIP_OK(hipMemcpyAsync(dbl_h, work_out.p, sizeof(double), hipMemcpyDeviceToHost, stream));
+        hipLaunchKernelGGL(k_report, dim3(1), dim3(256), 0, stream, nt, red.p, np > 0 ? nsb : 0, red.p + nt,
+                           red.p + nt + nsb, nw, work_out.p, red_hd, dbl_hd);
         sync();
         t_narrow += tm.ms();
         int nv = np > 0 ? int_h[0] : 0;
@@ -1078,8 +1135,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         // accept: C^{k+1} = C_{n+1}; U^{k+1} = V_n
         std::swap(x.p, xt.p);
         std::swap(q.p, qt.p);
-        std::swap(u.p, vout.p);
-        HIP_OK(hipMemcpyAsync(vout.p, u.p, 6 * (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        std::swap(u.p, vout.p);  // every trial writes all of vout
         // multiplier sum per pair, for the next warm start
         HIP_OK(hipMemsetAsync(lam.p, 0, std::max(np, 1) * sizeof(double), stream));
         for (int lv = 0; lv <= rec; ++lv) launch_pair_lambda(m, rrec.p, rpair.p, rgam64.p, lv, lam.p, stream);
@@ -1105,7 +1161,8 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         m_acc = m;
         m0_last = m0;
         log_valid = log_on;
-        sync();
+        hint_ok = true;
+        // no wait here: the caller's next call is ordered on the stream
     }
     if (timing) {
         sync();
@@ -1174,10 +1231,7 @@ int relcp_create(const relcp_bodies *bodies, const relcp_shapes *shapes, const r
             HIP_OK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
             c->own_stream = true;
         }
-        HIP_OK(hipHostMalloc((void **)&c->pst_h, 2 * sizeof(PgdState), hipHostMallocDefault));
-        HIP_OK(hipHostMalloc((void **)&c->int_h, 16 * sizeof(int), hipHostMallocDefault));
-        HIP_OK(hipHostMalloc((void **)&c->red_h, 8 * sizeof(unsigned long long), hipHostMallocDefault));
-        HIP_OK(hipHostMalloc((void **)&c->dbl_h, 8 * sizeof(double), hipHostMallocDefault));
+        c->alloc_host();
         c->upload_bodies(bodies, shapes);
         *out = c;
         return RELCP_OK;
@@ -1304,15 +1358,15 @@ int relcp_affine_rescale(relcp_ctx *ctx, double s) {
                     throw Error{RELCP_E_INVALID, "box would become smaller than 2 (R_max + skin)"};
             }
         for (auto &v : ctx->box) v *= s;
-        HIP_OK(hipMemcpyAsync(ctx->boxes.p, ctx->box.data(), ctx->box.size() * sizeof(double),
-                              hipMemcpyHostToDevice, ctx->stream));
-        hipLaunchKernelGGL(k_scale, dim3(nblk(3LL * ctx->n, 256)), dim3(256), 0, ctx->stream, 3 * ctx->n, ctx->x.p,
-                           s);
+        // positions and the device copy of the boxes, stream-ordered (no wait)
+        const int nbox = (int)ctx->box.size();
+        hipLaunchKernelGGL(k_scale, dim3(nblk(std::max(3LL * ctx->n, (long long)nbox), 256)), dim3(256), 0,
+                           ctx->stream, 3 * ctx->n, ctx->x.p, nbox, ctx->boxes.p, s);
+        HIP_OK(hipGetLastError());
         // a pair of the list is at most 2 R_max + radius apart: its gap shrinks by at most (1 - s) times that
         double rm = 0.0;
         for (double r : ctx->rmax) rm = std::max(rm, r);
         ctx->vl_used += std::max(0.0, 1.0 - s) * (2.0 * rm + ctx->vl_radius());
-        ctx->sync();
         return RELCP_OK;
     });
 }
@@ -1688,7 +1742,7 @@ int relcp_broadphase_device(int32_t nb, const double *x, const int32_t *kind, co
     relcp_ctx c;
     c.stream = (hipStream_t)stream;
     try {
-        HIP_OK(hipHostMalloc((void **)&c.int_h, 16 * sizeof(int), hipHostMallocDefault));
+        c.alloc_host();
         c.n = nb;
         c.nbatch = 1;
         c.boff = {0, nb};
@@ -1797,8 +1851,7 @@ int relcp_lcp_solve_device(int32_t nb, int32_t m, const int32_t *ia, const int32
     relcp_ctx c;
     c.stream = (hipStream_t)stream;
     try {
-        HIP_OK(hipHostMalloc((void **)&c.pst_h, 2 * sizeof(PgdState), hipHostMallocDefault));
-        HIP_OK(hipHostMalloc((void **)&c.int_h, 16 * sizeof(int), hipHostMallocDefault));
+        c.alloc_host();
         c.n = nb;
         c.lcp_mode = mode == 1 ? 1 : 3;
         c.lcp_max_iters = max_iters > 0 ? max_iters : 100000;
