@@ -61,6 +61,17 @@ def lcp_bytes(kind, m, nb, w):
     return m * (8 + 12 * w) + nb * (4 + 15 * w)
 
 
+def rowgraph_bytes(m, e, w, iters):
+    """Algorithmic bytes of the row-graph passes of one solve: m rows, e
+    stored entries of A (padding excluded), word size w, iters iterations.
+    Every pass reads each entry's column (4 B) and value (w).  The start
+    pass reads gamma0, qv, A_rr and writes the row state (gamma, h) and g
+    (6w per row); an iteration pass reads the row's previous state (gamma,
+    h), g, qv, A_rr and writes the new state and g (8w per row; the
+    neighbours' states it gathers are the same array, counted once)."""
+    return (iters + 1) * e * (4 + w) + m * w * (6 + 8 * iters)
+
+
 def learned_comparison(args, state):
     """Learned against previous-step warm start on the same workload.  The
     model is trained on the GPU (library kernels) on about a million rows of
@@ -221,8 +232,8 @@ def cpu_baseline(args, bench_pairs, bench_rec):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
     ap.add_argument("--seed", type=int, default=4)
@@ -232,6 +243,9 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--skin", type=float, default=0.05)
+    ap.add_argument("--lcp-mode", type=int, default=0, choices=(0, 1, 2, 3, 4),
+                    help="LCP execution: 0 automatic, 1 grid, 2 resident, 3 row graph (graph-replayed passes), "
+                         "4 row graph (one launch per pass)")
     ap.add_argument("--roofline-steps", type=int, default=5)
     ap.add_argument("--cpu-n", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -269,6 +283,8 @@ def main():
                    skin=args.skin, log=log)
     sim = C.sim
     log("set-up done: phi %.4f (%.1fs)" % (C.phi, time.time() - t0))
+    if args.lcp_mode:
+        sim.set_lcp_config(args.lcp_mode)
     start_state = C.state()
     C.steps(args.warmup, args.dphi)
     log("warm-up done, timing %d steps" % args.steps)
@@ -281,7 +297,9 @@ def main():
     value = args.steps / elapsed
     pgd = [s["lcp_iters_total"] for s in stats]
     citers = sum(int(np.dot(s["n_contacts"], s["lcp_iters"])) for s in stats)
-    log("timed: %.3f s, %.2f steps/s, PGD iters/step %.1f" % (elapsed, value, np.mean(pgd)))
+    log("timed: %.3f s, %.2f steps/s, PGD iters/step %.1f, host waits/step %.2f (%.3f ms)" %
+        (elapsed, value, np.mean(pgd), np.mean([s["n_waits"] for s in stats]),
+         np.mean([s["t_wait"] for s in stats])))
 
     # roofline: kernel durations from HIP events recorded by the library on
     # its stream, over further steps of the same protocol
@@ -291,16 +309,20 @@ def main():
     tm = sim.get_timing(reset=True)
     sim.set_timing(False)
     nb = args.n
-    tot_bytes = {"lcp_gather": 0.0, "lcp_scatter": 0.0}
+    tot_bytes = {"lcp_gather": 0.0, "lcp_scatter": 0.0, "lcp_rowgraph": 0.0}
     busy = 0  # launches that did work (the rest return at once after convergence)
     for s in rstats:
-        for m, it, it64 in zip(s["n_contacts"], s["lcp_iters"], s["lcp_iters64"]):
+        for m, it, it64, e in zip(s["n_contacts"], s["lcp_iters"], s["lcp_iters64"], s["rowgraph_entries"]):
             itlo = it - it64
-            for cls in tot_bytes:
+            for cls in ("lcp_gather", "lcp_scatter"):
                 if args.precision == 32:
                     tot_bytes[cls] += (itlo + 1) * lcp_bytes(cls, m, nb, 4) + (it64 + 1) * lcp_bytes(cls, m, nb, 8)
                 else:
                     tot_bytes[cls] += (it + 1) * lcp_bytes(cls, m, nb, 8)
+            if args.precision == 32:
+                tot_bytes["lcp_rowgraph"] += rowgraph_bytes(m, e, 4, itlo) + rowgraph_bytes(m, e, 8, it64)
+            else:
+                tot_bytes["lcp_rowgraph"] += rowgraph_bytes(m, e, 8, it)
             busy += int((itlo + 1 + it64 + 1) if args.precision == 32 else (it + 1))
     dom = max(tm, key=lambda k: tm[k][1])
     cnt, ms = tm[dom]
@@ -336,11 +358,13 @@ def main():
         "config": {"workload": "compaction of %d periodic ellipsoids (semiaxes U[0.5,1]), phi %.2f -> %.5f at "
                                "dphi %.0e/step, overdamped, dt %.0e, overlap_tol %.0e, lcp_tol %.0e, previous-step "
                                "warm start" % (args.n, args.phi0, C.phi, args.dphi, args.dt, args.eps, args.tol),
-                   "bodies": args.n, "precision": args.precision, "skin": args.skin},
+                   "bodies": args.n, "precision": args.precision, "skin": args.skin, "lcp_mode": args.lcp_mode},
         "pgd_iters_per_step": {"plain": float(np.mean(pgd)),
                                "learned": learned["learned"]["pgd_iters_per_step"] if learned else None},
         "learned_warm_start": learned,
         "contact_iters_per_s": citers / elapsed,
+        "host_waits_per_step": {"n": float(np.mean([s["n_waits"] for s in stats])),
+                                "ms": float(np.mean([s["t_wait"] for s in stats]))},
         "recursions_per_step": float(np.mean([s["recursions"] for s in stats])),
         "contacts_final": int(stats[-1]["n_contacts_final"]),
         "residual_fp64_max": float(max(s["residual_fp64"] for s in stats)),

@@ -118,6 +118,8 @@ typedef struct {
     double t_narrow, t_lcp, t_other; /* milliseconds (host clock, stream-synchronised) */
     int32_t rowgraph_entries[RELCP_MAX_RECORDED]; /* entries of A over rows per recursion (row-graph LCP mode; 0 otherwise) */
     int32_t pairs_rebuilt;       /* 1 if the candidate list was rebuilt at this step (it is kept while valid) */
+    int32_t n_waits;             /* host waits on the stream during the step */
+    double t_wait;               /* milliseconds of host clock spent in those waits */
 } relcp_step_stats;
 
 /* Create a context (Sec. 2.1.1 state, Sec. 2.1.2 laws of motion).  Validates
@@ -160,19 +162,23 @@ RELCP_API int relcp_get_contacts(const relcp_ctx *ctx, int32_t *ia, int32_t *ib,
 
 /* Execution of the LCP loop (the same Jacobi-scaled projected gradient in
  * every mode).  mode 0 = automatic (resident when every packing has at
- * most 8192 bodies, else row graph), 1 = grid (two passes per iteration
+ * most 8192 bodies, else row graph with one launch per pass), 1 = grid (two passes per iteration
  * over all rows and bodies, through the velocities K D gamma, launched in
  * chunks), 2 = resident (one workgroup per packing runs its whole solve in
  * one launch; block = workgroup size 256, 512 or 1024; lds = stage the
  * packing's velocities in LDS when they fit), 3 = row graph (A = dt D^T K D
- * assembled over rows once per recursion, one pass per iteration). */
+ * assembled over rows once per recursion, one pass per iteration, the
+ * passes replayed in chunks from an instantiated HIP graph that reads the
+ * solve's parameters from device memory; one launch per pass where graphs
+ * are unavailable), 4 = row graph with one launch per pass. */
 RELCP_API int relcp_set_lcp_config(relcp_ctx *ctx, int32_t mode, int32_t block, int32_t lds);
 
 /* Autotuner: times every LCP configuration (grid; resident x {256, 512,
- * 1024} x {global, LDS}; row graph) on the rows of the last accepted step,
- * from the same start, reps times each, keeps the fastest for this context
- * and writes it to config[3] = {mode, block, lds} and the average
- * milliseconds per configuration to ms[8] in that order (either may be
+ * 1024} x {global, LDS}; row graph; row graph per-pass launches) on the
+ * rows of the last accepted step, from the same start, reps times each,
+ * keeps the fastest for this context and writes it to config[3] = {mode,
+ * block, lds} and the average milliseconds per configuration to ms[9] in
+ * that order (either may be
  * NULL; a configuration that does not fit reports 0).  The multipliers of
  * the last step are restored. */
 RELCP_API int relcp_autotune(relcp_ctx *ctx, double dt, double lcp_tol, int32_t reps, int32_t *config, double *ms);
@@ -280,8 +286,8 @@ RELCP_API int relcp_broadphase_device(int32_t nb, const double *x, const int32_t
  * rows ia, ib (m), n, ta = r_a x n, tb = r_b x n (3 arrays of m each), qv (m),
  * body operator kt (nb), Kr (6 arrays of nb: xx, yy, zz, xy, xz, yz), gamma
  * (m, in/out).  mode: LCP execution as in relcp_set_lcp_config, 1 = grid,
- * 3 = row graph (0 = row graph).  *iters and *residual (FP64 residual) are
- * host outputs. */
+ * 3 = row graph with graph-replayed passes, 4 = row graph with one launch
+ * per pass (0 = 4).  *iters and *residual (FP64 residual) are host outputs. */
 RELCP_API int relcp_lcp_solve_device(int32_t nb, int32_t m, const int32_t *ia, const int32_t *ib, const double *n,
                            const double *ta, const double *tb, const double *qv, const double *kt, const double *Kr,
                            double dt, int32_t planar, int32_t precision, int32_t mode, double tol, int32_t max_iters,

@@ -130,6 +130,36 @@ template <typename T>
 void launch_lcp_spmv(int mode, const RowGraphT<T> &G, const T *qv, const T *dA, const T *gam0,
                      const RowStep<T> *zin, const T *gin, RowStep<T> *zout, T *gout, const PgdCtl &C, double *pout,
                      int par, hipStream_t s);
+// Parameters of a row-graph solve in device memory, read by k_spmv_dev:
+// the passes of a solve are then identical launches (parity aside) and can
+// be recorded once in a graph.  nbg = blocks of a pass over m rows; a pass
+// stops the solve (done) once converged or after cap iterations.
+template <typename T>
+struct LcpDev {
+    int m, nbg, cap;
+    double tol;
+    const int *base, *col;
+    const T *val;
+    size_t slots;
+    const T *qv, *dA;
+    RowStep<T> *z[2];
+    T *g[2];
+    double *part[2];
+    PgdState *S, *fin;
+    int *done;
+    PgdState *fin_h;
+    int *done_h;
+};
+template <typename T>
+void launch_set_lcpdev(LcpDev<T> *D, const LcpDev<T> &v, hipStream_t s);
+// one iteration pass of parity par over a grid covering grid_rows rows (>= m)
+template <typename T>
+void launch_spmv_dev(const LcpDev<T> *D, int grid_rows, int par, hipStream_t s);
+// An instantiated graph of k passes (k even; parities 1, 0, 1, ..., so a
+// chunk starts at an odd iteration) over a grid covering grid_rows rows, all
+// reading *D.  Returns 0, or -1 with *out = null.
+template <typename T>
+int make_spmv_graph(const LcpDev<T> *D, int grid_rows, int k, hipGraphExec_t *out);
 // gamma, g <- the state of the pass that holds the final iterate (fin.iter & 1)
 template <typename T>
 void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, const T *g0, const T *g1,

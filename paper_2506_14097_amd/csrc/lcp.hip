@@ -646,63 +646,110 @@ __device__ inline float step_h(float gm, float h, float al) {
     return v > 0.0f ? v : 0.0f;
 }
 
-// One pass per iteration.  Each thread takes one row.  Everything that does
-// not depend on the step length is loaded first (its own state, up to KP
-// matrix entries and the previous state of the rows they point at), so that
-// the reduction of the previous pass's partial sums (fixed order, every
-// block) overlaps those loads; then the projected steps, g' = qv + A gamma',
-// the row's new state and its share of the step-size sums and residual.
+// One row of a row-graph pass, split so that everything that does not
+// depend on the step length (the row's own state, up to KP matrix entries
+// and the previous state of the rows they point at) is loaded before the
+// reduction that yields the step length.
+constexpr int kPre = 16;
+
+template <typename T>
+struct RowPre {
+    int w;
+    const int *col;
+    const T *val;
+    T gm, hm, gold, dA, q;
+    int cj[kPre];
+    T vj[kPre], gj[kPre], hj[kPre];
+};
+
+template <typename T, int MODE>
+__device__ inline void row_preload(const RowGraphT<T> &G, const T *__restrict__ qv, const T *__restrict__ dA0,
+                                   const T *__restrict__ gam0, const RowStep<T> *__restrict__ zin,
+                                   const T *__restrict__ gin, int r, RowPre<T> &P) {
+    const int lane = r & (RELCP_WAVE - 1), sl = r / RELCP_WAVE;
+    const int b0 = G.base[sl];
+    P.w = G.base[sl + 1] - b0;
+    // an overflowed assembly left this slice unwritten: no entries (the
+    // caller sees the overflow report, re-sizes and starts the solve over)
+    if ((size_t)RELCP_WAVE * (b0 + P.w) > G.cap) P.w = 0;
+    P.col = G.col + (size_t)RELCP_WAVE * b0 + lane;
+    P.val = G.val + (size_t)RELCP_WAVE * b0 + lane;
+    P.dA = dA0[r];
+    P.q = qv[r];
+    if (MODE == 1) {
+        const RowStep<T> z = zin[r];
+        P.gm = z.gam;
+        P.hm = z.h;
+        P.gold = gin[r];
+    } else {
+        P.gm = gam0[r];
+        P.hm = T(0);
+        P.gold = T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) P.cj[k] = k < P.w ? P.col[RELCP_WAVE * k] : r;
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+        P.vj[k] = k < P.w ? P.val[RELCP_WAVE * k] : T(0);
+        if (MODE == 1) {
+            const RowStep<T> z = zin[P.cj[k]];
+            P.gj[k] = z.gam;
+            P.hj[k] = z.h;
+        } else {
+            P.gj[k] = gam0[P.cj[k]];
+            P.hj[k] = T(0);
+        }
+    }
+}
+
+// projected steps, g' = qv + A gamma', the row's new state and its share
+// of the step-size sums (s^T D s, s^T y, y^T D^-1 y) and residual
+template <typename T, int MODE>
+__device__ inline void row_finish(const RowPre<T> &P, T al, const RowStep<T> *__restrict__ zin,
+                                  const T *__restrict__ gam0, RowStep<T> *__restrict__ zout, T *__restrict__ gout,
+                                  int r, double &ss, double &sy, double &yy, double &res) {
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) acc += P.vj[k] * (MODE == 1 ? step_h(P.gj[k], P.hj[k], al) : clamp0(P.gj[k]));
+    for (int k = kPre; k < P.w; ++k) {
+        const int j = P.col[RELCP_WAVE * k];
+        const T v = P.val[RELCP_WAVE * k];
+        if (MODE == 1) {
+            const RowStep<T> z = zin[j];
+            acc += v * step_h(z.gam, z.h, al);
+        } else {
+            acc += v * clamp0(gam0[j]);
+        }
+    }
+    const T gv = MODE == 1 ? step_h(P.gm, P.hm, al) : clamp0(P.gm);
+    const T gn = P.q + acc;
+    zout[r] = RowStep<T>{gv, gn / P.dA};
+    gout[r] = gn;
+    const T dg = P.dA * gv;
+    res = fmax(res, fabs((double)(dg < gn ? dg : gn)));
+    if (MODE == 1) {
+        const double sd = (double)gv - (double)P.gm, yd = (double)gn - (double)P.gold;
+        ss += (double)P.dA * sd * sd;
+        sy += sd * yd;
+        yy += yd * yd / (double)P.dA;
+    }
+}
+
+// One pass per launch (chunked mode): every block first reduces the
+// previous pass's partial sums (fixed order) into the new state and step
+// length, overlapped with the row's loads.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads)
     k_spmv(RowGraphT<T> G, const T *__restrict__ qv, const T *__restrict__ dA0, const T *__restrict__ gam0,
            const RowStep<T> *__restrict__ zin, const T *__restrict__ gin, RowStep<T> *__restrict__ zout,
            T *__restrict__ gout, PgdCtl C, double *__restrict__ pout, int par) {
-    constexpr int KP = 16;
     __shared__ double sh[4][kWaves];
     __shared__ PgdState ns;
     if (MODE == 1 && *C.done) return;
     const int r = blockIdx.x * kThreads + threadIdx.x;
     const bool act = r < G.m;
-    int w = 0;
-    const int *col = nullptr;
-    const T *val = nullptr;
-    T gm = T(0), hm = T(0), gold = T(0), dA = T(1), q = T(0);
-    int cj[KP];
-    T vj[KP], gj[KP], hj[KP];
-    if (act) {
-        const int lane = r & (RELCP_WAVE - 1), sl = r / RELCP_WAVE;
-        const int b0 = G.base[sl];
-        w = G.base[sl + 1] - b0;
-        // an overflowed assembly left this slice unwritten: no entries (the
-        // caller sees the overflow flag, re-sizes and starts the solve over)
-        if ((size_t)RELCP_WAVE * (b0 + w) > G.cap) w = 0;
-        col = G.col + (size_t)RELCP_WAVE * b0 + lane;
-        val = G.val + (size_t)RELCP_WAVE * b0 + lane;
-        dA = dA0[r];
-        q = qv[r];
-        if (MODE == 1) {
-            const RowStep<T> z = zin[r];
-            gm = z.gam;
-            hm = z.h;
-            gold = gin[r];
-        } else {
-            gm = gam0[r];
-        }
-#pragma unroll
-        for (int k = 0; k < KP; ++k) cj[k] = k < w ? col[RELCP_WAVE * k] : r;
-#pragma unroll
-        for (int k = 0; k < KP; ++k) {
-            vj[k] = k < w ? val[RELCP_WAVE * k] : T(0);
-            if (MODE == 1) {
-                const RowStep<T> z = zin[cj[k]];
-                gj[k] = z.gam;
-                hj[k] = z.h;
-            } else {
-                gj[k] = gam0[cj[k]];
-                hj[k] = T(0);
-            }
-        }
-    }
+    RowPre<T> P;
+    if (act) row_preload<T, MODE>(G, qv, dA0, gam0, zin, gin, r, P);
     T al = T(0);
     if (MODE == 1) {
         reduce_partials(C, par, &ns, sh);
@@ -719,33 +766,7 @@ __global__ void __launch_bounds__(kThreads)
         al = (T)ns.alpha;
     }
     double ss = 0.0, sy = 0.0, yy = 0.0, res = 0.0;
-    if (act) {
-        T acc = T(0);
-#pragma unroll
-        for (int k = 0; k < KP; ++k) acc += vj[k] * (MODE == 1 ? step_h(gj[k], hj[k], al) : clamp0(gj[k]));
-        for (int k = KP; k < w; ++k) {
-            const int j = col[RELCP_WAVE * k];
-            const T v = val[RELCP_WAVE * k];
-            if (MODE == 1) {
-                const RowStep<T> z = zin[j];
-                acc += v * step_h(z.gam, z.h, al);
-            } else {
-                acc += v * clamp0(gam0[j]);
-            }
-        }
-        const T gv = MODE == 1 ? step_h(gm, hm, al) : clamp0(gm);
-        const T gn = q + acc;
-        zout[r] = RowStep<T>{gv, gn / dA};
-        gout[r] = gn;
-        const T dg = dA * gv;
-        res = fabs((double)(dg < gn ? dg : gn));
-        if (MODE == 1) {
-            const double sd = (double)gv - (double)gm, yd = (double)gn - (double)gold;
-            ss = (double)dA * sd * sd;
-            sy = sd * yd;
-            yy = yd * yd / (double)dA;
-        }
-    }
+    if (act) row_finish<T, MODE>(P, al, zin, gam0, zout, gout, r, ss, sy, yy, res);
     block_reduce4(ss, sy, yy, res, sh);
     if (threadIdx.x == 0) {
         double *p = pout + 4 * blockIdx.x;
@@ -754,6 +775,57 @@ __global__ void __launch_bounds__(kThreads)
         p[2] = yy;
         p[3] = res;
     }
+}
+
+// A pass whose parameters live in device memory (LcpDev), so that the
+// same launch can be recorded once in a graph and replayed for every solve.
+// The grid covers a row capacity; blocks past the current row count leave
+// at once.  A pass that finds the solve converged, or the iteration cap
+// reached, records the final state and stops the later passes.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_spmv_dev(const LcpDev<T> *__restrict__ D, int par) {
+    __shared__ double sh[4][kWaves];
+    __shared__ PgdState ns;
+    const LcpDev<T> &d = *D;
+    if (*d.done) return;
+    const int nbg = d.nbg;
+    if ((int)blockIdx.x >= nbg) return;
+    const RowGraphT<T> G{d.m, d.base, d.col, d.val, d.slots};
+    const int r = blockIdx.x * kThreads + threadIdx.x;
+    const bool act = r < d.m;
+    RowPre<T> P;
+    if (act) row_preload<T, 1>(G, d.qv, d.dA, nullptr, d.z[par ^ 1], d.g[par ^ 1], r, P);
+    PgdCtl C{d.S, d.fin, d.done, d.part[par ^ 1], nbg, d.tol, d.fin_h, d.done_h};
+    reduce_partials(C, par, &ns, sh);
+    const bool stop = ns.conv || ns.iter >= d.cap;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        d.S[par] = ns;
+        if (stop) {
+            // done stops the passes; the host mirror done_h reports convergence
+            // only (a capped solve is seen from fin_h->iter)
+            *d.fin = ns;
+            *d.done = 1;
+            if (d.fin_h) *d.fin_h = ns;
+            if (d.done_h && ns.conv) *d.done_h = 1;
+        }
+    }
+    if (stop) return;
+    double ss = 0.0, sy = 0.0, yy = 0.0, res = 0.0;
+    if (act) row_finish<T, 1>(P, (T)ns.alpha, d.z[par ^ 1], nullptr, d.z[par], d.g[par], r, ss, sy, yy, res);
+    block_reduce4(ss, sy, yy, res, sh);
+    if (threadIdx.x == 0) {
+        double *p = d.part[par] + 4 * blockIdx.x;
+        p[0] = ss;
+        p[1] = sy;
+        p[2] = yy;
+        p[3] = res;
+    }
+}
+
+// the parameters of the next solve, copied in stream order
+template <typename T>
+__global__ void k_set_lcpdev(LcpDev<T> *D, LcpDev<T> v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *D = v;
 }
 
 template <typename T>
@@ -928,6 +1000,48 @@ void launch_lcp_spmv(int mode, const RowGraphT<T> &G, const T *qv, const T *dA, 
 }
 
 template <typename T>
+void launch_set_lcpdev(LcpDev<T> *D, const LcpDev<T> &v, hipStream_t s) {
+    hipLaunchKernelGGL((k_set_lcpdev<T>), dim3(1), dim3(64), 0, s, D, v);
+}
+
+template <typename T>
+void launch_spmv_dev(const LcpDev<T> *D, int grid_rows, int par, hipStream_t s) {
+    hipLaunchKernelGGL((k_spmv_dev<T>), dim3(nblk(grid_rows > 0 ? grid_rows : 1, kThreads)), dim3(kThreads), 0, s, D,
+                       par);
+}
+
+template <typename T>
+int make_spmv_graph(const LcpDev<T> *D, int grid_rows, int k, hipGraphExec_t *out) {
+    *out = nullptr;
+    if (k <= 0 || (k & 1)) return -1;
+    hipGraph_t g = nullptr;
+    if (hipGraphCreate(&g, 0) != hipSuccess) return -1;
+    const LcpDev<T> *dp = D;
+    hipGraphNode_t prev = nullptr;
+    int rc = 0;
+    for (int t = 0; t < k && rc == 0; ++t) {
+        int par = (t & 1) ? 0 : 1;  // the passes of a chunk start at an odd iteration
+        void *args[] = {(void *)&dp, (void *)&par};
+        hipKernelNodeParams p{};
+        p.func = reinterpret_cast<void *>(&k_spmv_dev<T>);
+        p.gridDim = dim3(nblk(grid_rows > 0 ? grid_rows : 1, kThreads));
+        p.blockDim = dim3(kThreads);
+        p.sharedMemBytes = 0;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        hipGraphNode_t node = nullptr;
+        if (hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess) rc = -1;
+        prev = node;
+    }
+    if (rc == 0 && hipGraphInstantiate(out, g, nullptr, nullptr, 0) != hipSuccess) {
+        *out = nullptr;
+        rc = -1;
+    }
+    (void)hipGraphDestroy(g);
+    return rc;
+}
+
+template <typename T>
 void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, const T *g0, const T *g1,
                             const PgdState *fin, T *gam, T *g, hipStream_t s) {
     if (m > 0)
@@ -944,7 +1058,10 @@ void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, c
                                      const RowStep<T> *, const T *, RowStep<T> *, T *, const PgdCtl &, double *,  \
                                      int, hipStream_t);                                                           \
     template void launch_rowstate_unpack<T>(int, const RowStep<T> *, const RowStep<T> *, const T *, const T *,    \
-                                            const PgdState *, T *, T *, hipStream_t);
+                                            const PgdState *, T *, T *, hipStream_t);                             \
+    template void launch_set_lcpdev<T>(LcpDev<T> *, const LcpDev<T> &, hipStream_t);                               \
+    template void launch_spmv_dev<T>(const LcpDev<T> *, int, int, hipStream_t);                                    \
+    template int make_spmv_graph<T>(const LcpDev<T> *, int, int, hipGraphExec_t *);
 RELCP_INST(double)
 RELCP_INST(float)
 #undef RELCP_INST

@@ -247,6 +247,16 @@ struct relcp_ctx {
     DBuf<float> zg32;
     bool rg_valid = false;
     double rg_dt = 0.0;
+    // row-graph passes replayed from an instantiated graph (per precision):
+    // parameters in device memory, grid covering graph_rows rows
+    static constexpr int kGraphPasses = 8;
+    DBuf<LcpDev<double>> lcpdev64;
+    DBuf<LcpDev<float>> lcpdev32;
+    hipGraphExec_t spmv_graph[2] = {nullptr, nullptr};
+    int graph_rows[2] = {0, 0};
+    bool graph_ok = true;
+    template <typename T>
+    hipGraphExec_t spmv_graph_for(int rows, LcpDev<T> **dev);
     size_t rg_cap = 0;     // entry slots allocated
     int rg_entries = 0;    // entries of the current graph (known after the solve's first read-back)
     bool rowgraph_mode() const { return !resident_mode() && lcp_mode != 1; }
@@ -256,7 +266,7 @@ struct relcp_ctx {
     DBuf<PgdState> pk_state;
     PgdState *pk_state_h = nullptr;
     bool resident_mode() const {
-        if (lcp_mode == 1 || lcp_mode == 3) return false;
+        if (lcp_mode == 1 || lcp_mode == 3 || lcp_mode == 4) return false;
         if (lcp_mode == 2) return true;
         return maxpk <= 8192;
     }
@@ -300,6 +310,9 @@ struct relcp_ctx {
         mlp_w.release(); feat.release(); rowscale.release();
         rg_width.release(); rg_base.release(); rg_col.release(); rg_flags.release(); rg_val64.release();
         rg_jb.release(); rg_val32.release(); z64.release(); z32.release(); zg64.release(); zg32.release();
+        lcpdev64.release(); lcpdev32.release();
+        for (auto &ge : spmv_graph)
+            if (ge) (void)hipGraphExecDestroy(ge);
         for (auto e : ev_pool) (void)hipEventDestroy(e);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
@@ -317,7 +330,15 @@ struct relcp_ctx {
     template <typename T>
     int solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt, double tol, int &iters, double &res);
     int step(double dt, double eps, double tol, relcp_step_stats *st);
-    void sync() { HIP_OK(hipStreamSynchronize(stream)); }
+    // host waits on the stream (counted per step)
+    int n_waits = 0;
+    double t_wait = 0.0;
+    void sync() {
+        Timer t;
+        HIP_OK(hipStreamSynchronize(stream));
+        t_wait += t.ms();
+        ++n_waits;
+    }
 };
 
 template <typename T>
@@ -883,6 +904,35 @@ int relcp_ctx::solve(double dt, double tol, int &iters, double &res) {
     return conv ? RELCP_OK : RELCP_E_LCP_MAXITER;
 }
 
+// The instantiated pass graph of precision T for at least `rows` rows and
+// its parameter block; null if graphs are unavailable (per-pass launches).
+template <typename T>
+hipGraphExec_t relcp_ctx::spmv_graph_for(int rows, LcpDev<T> **dev) {
+    const int pk = sizeof(T) == 8 ? 1 : 0;
+    if constexpr (sizeof(T) == 8) {
+        lcpdev64.ensure(1);
+        *dev = lcpdev64.p;
+    } else {
+        lcpdev32.ensure(1);
+        *dev = lcpdev32.p;
+    }
+    if (spmv_graph[pk] && graph_rows[pk] >= rows) return spmv_graph[pk];
+    if (spmv_graph[pk]) {
+        sync();
+        (void)hipGraphExecDestroy(spmv_graph[pk]);
+        spmv_graph[pk] = nullptr;
+    }
+    // grid headroom so that a growing contact set rarely re-instantiates
+    const int want = std::max(4096, rows + rows / 4);
+    if (make_spmv_graph<T>(*dev, want, kGraphPasses, &spmv_graph[pk]) != 0) {
+        (void)hipGetLastError();
+        graph_ok = false;
+        return nullptr;
+    }
+    graph_rows[pk] = want;
+    return spmv_graph[pk];
+}
+
 // Row-graph LCP loop: pass 0 forms g at the start, pass j (parity j & 1)
 // reads state buffer z[(j - 1) & 1] and the partials of pass j - 1 and
 // writes z[j & 1] and its own partials; the final iterate is unpacked into
@@ -915,6 +965,8 @@ int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt
         c.partials = partials.p + (size_t)(par ^ 1) * stride;
         return c;
     };
+    int *const conv_h = reinterpret_cast<int *>(pst_h + 1);
+    bool seen = false;  // pst_h holds the final state
     for (int attempt = 0;; ++attempt) {
         bool fresh = false;
         if (!rg_valid || rg_dt != dt) {
@@ -926,22 +978,45 @@ int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt
             G.val = rg_val64.p;
         else
             G.val = rg_val32.p;
+        hipGraphExec_t ge = nullptr;
+        if (lcp_mode == 3 && graph_ok) {
+            LcpDev<T> *dev = nullptr;
+            ge = spmv_graph_for<T>(m, &dev);
+            if (ge) {
+                LcpDev<T> v{};
+                v.m = m; v.nbg = C.nbg; v.cap = cap; v.tol = C.tol;
+                v.base = G.base; v.col = G.col; v.val = G.val; v.slots = G.cap;
+                v.qv = R.qv; v.dA = R.dA;
+                v.z[0] = z0; v.z[1] = z1; v.g[0] = g0; v.g[1] = g1;
+                v.part[0] = partials.p; v.part[1] = partials.p + stride;
+                v.S = C.S; v.fin = C.fin; v.done = C.done; v.fin_h = C.fin_h; v.done_h = C.done_h;
+                launch_set_lcpdev<T>(dev, v, stream);
+            }
+        }
         launch_pgd_init(C, stream);
         timed(7, [&] {
             launch_lcp_spmv<T>(0, G, R.qv, R.dA, R.gam, nullptr, nullptr, z0, g0, C, partials.p, 0, stream);
         });
         int j = 1;
         int chunk = std::max(2, std::min(64, (last_iters[pk] + 3) & ~1));
-        bool done = false, first = true;
+        bool first = true;
+        seen = false;
         for (;;) {
-            int k = std::min(chunk, cap - (j - 1));
-            if (k <= 0) break;
-            for (int t = 0; t < k; ++t, ++j) {
-                const int par = j & 1;
-                timed(7, [&] {
-                    launch_lcp_spmv<T>(1, G, R.qv, R.dA, nullptr, par ? z0 : z1, par ? g0 : g1, par ? z1 : z0,
-                                       par ? g1 : g0, ctl(par), partials.p + (size_t)par * stride, par, stream);
-                });
+            if (ge) {
+                // whole graphs; the passes past the end of the solve return at once
+                const int ng = (chunk + kGraphPasses - 1) / kGraphPasses;
+                for (int t = 0; t < ng; ++t, j += kGraphPasses)
+                    timed(7, [&] { HIP_OK(hipGraphLaunch(ge, stream)); });
+            } else {
+                const int k = std::min(chunk, cap - (j - 1));
+                if (k <= 0) break;
+                for (int t = 0; t < k; ++t, ++j) {
+                    const int par = j & 1;
+                    timed(7, [&] {
+                        launch_lcp_spmv<T>(1, G, R.qv, R.dA, nullptr, par ? z0 : z1, par ? g0 : g1, par ? z1 : z0,
+                                           par ? g1 : g0, ctl(par), partials.p + (size_t)par * stride, par, stream);
+                    });
+                }
             }
             sync();
             if (first && fresh) {
@@ -950,10 +1025,11 @@ int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt
                 const size_t need = (size_t)RELCP_WAVE * int_h[4];
                 if (int_h[6] || need > rg_cap) break;
             }
-            if (*reinterpret_cast<int *>(pst_h + 1)) {
-                done = true;
+            if (*conv_h || (ge && pst_h[0].iter >= cap)) {
+                seen = true;
                 break;
             }
+            if (ge && j > cap + 1) throw Error{RELCP_E_DEVICE, "LCP passes ran past the iteration cap"};
             chunk = std::min(64, std::max(8, 2 * chunk));
         }
         if (fresh && (int_h[6] || (size_t)RELCP_WAVE * int_h[4] > rg_cap)) {
@@ -967,7 +1043,7 @@ int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt
             rg_valid = false;
             continue;
         }
-        if (!done) {
+        if (!seen) {
             // the state after the last pass (iteration cap or fixed iterations)
             PgdCtl cf = C;
             cf.partials = partials.p + (size_t)((j - 1) & 1) * stride;
@@ -975,11 +1051,10 @@ int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt
         }
         break;
     }
-    const bool seen = *reinterpret_cast<int *>(pst_h + 1) != 0;  // converged at a read-back: pst_h is final
     launch_rowstate_unpack<T>(m, z0, z1, g0, g1, C.fin, R.gam, R.g, stream);
     if constexpr (sizeof(T) == 8) timed(0, [&] { launch_lcp_scatter<T>(0, R, Bd, C, 0, stream); });
     if (!seen) sync();
-    const bool conv = *reinterpret_cast<int *>(pst_h + 1) != 0;
+    const bool conv = *conv_h != 0;
     iters = pst_h[0].iter;
     res = pst_h[0].res;
     last_iters[pk] = iters;
@@ -997,6 +1072,8 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     Timer tm;
     double t_narrow = 0, t_lcp = 0, t_other = 0;
     const int N = n;
+    n_waits = 0;
+    t_wait = 0.0;
 
     // set-up at C^k: geometry, K, U_free
     BodySetupArgs ba{};
@@ -1172,6 +1249,8 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     S.t_narrow = t_narrow;
     S.t_lcp = t_lcp;
     S.t_other = t_other;
+    S.n_waits = n_waits;
+    S.t_wait = t_wait;
     if (st) *st = S;
     return status;
 }
@@ -1450,8 +1529,8 @@ int relcp_get_contacts(const relcp_ctx *cc, int32_t *ia, int32_t *ib, int32_t *r
 
 int relcp_set_lcp_config(relcp_ctx *ctx, int32_t mode, int32_t block, int32_t lds) {
     if (!ctx) return RELCP_E_INVALID;
-    if (mode < 0 || mode > 3 || (block != 256 && block != 512 && block != 1024)) {
-        ctx->err = "mode must be 0..3 and block 256, 512 or 1024";
+    if (mode < 0 || mode > 4 || (block != 256 && block != 512 && block != 1024)) {
+        ctx->err = "mode must be 0..4 and block 256, 512 or 1024";
         return RELCP_E_INVALID;
     }
     ctx->lcp_mode = mode;
@@ -1502,6 +1581,7 @@ int relcp_autotune(relcp_ctx *ctx, double dt, double lcp_tol, int32_t reps, int3
         for (int b : {256, 512, 1024})
             for (int l : {0, 1}) cfgs.push_back({2, b, l});
         cfgs.push_back({3, 256, 0});
+        cfgs.push_back({4, 256, 0});
         const int save_mode = ctx->lcp_mode, save_block = ctx->res_block, save_lds = ctx->res_lds;
         hipEvent_t e0, e1;
         HIP_OK(hipEventCreate(&e0));
@@ -1846,14 +1926,14 @@ int relcp_lcp_solve_device(int32_t nb, int32_t m, const int32_t *ia, const int32
                            double dt, int32_t planar, int32_t precision, int32_t mode, double tol, int32_t max_iters,
                            double *gamma, int32_t *iters, double *residual, void *stream) {
     if (nb <= 0 || m < 0 || !(dt > 0) || (precision != 32 && precision != 64) || !gamma || !kt || !Kr ||
-        (mode != 0 && mode != 1 && mode != 3))
+        (mode != 0 && mode != 1 && mode != 3 && mode != 4))
         return RELCP_E_INVALID;
     relcp_ctx c;
     c.stream = (hipStream_t)stream;
     try {
         c.alloc_host();
         c.n = nb;
-        c.lcp_mode = mode == 1 ? 1 : 3;
+        c.lcp_mode = mode == 0 ? 4 : mode;
         c.lcp_max_iters = max_iters > 0 ? max_iters : 100000;
         c.K.ensure(9 * (size_t)nb);
         c.K32.ensure(9 * (size_t)nb);

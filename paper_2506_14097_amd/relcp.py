@@ -59,7 +59,8 @@ class StepStats(C.Structure):
                 ("margin", C.c_double * MAX_RECORDED), ("residual_fp64", C.c_double),
                 ("residual_lowp", C.c_double), ("max_overlap", C.c_double), ("max_disp", C.c_double),
                 ("t_narrow", C.c_double), ("t_lcp", C.c_double), ("t_other", C.c_double),
-                ("rowgraph_entries", C.c_int32 * MAX_RECORDED), ("pairs_rebuilt", C.c_int32)]
+                ("rowgraph_entries", C.c_int32 * MAX_RECORDED), ("pairs_rebuilt", C.c_int32),
+                ("n_waits", C.c_int32), ("t_wait", C.c_double)]
 
     def as_dict(self):
         R = self.recursions
@@ -71,7 +72,7 @@ class StepStats(C.Structure):
                     residual_fp64=self.residual_fp64, residual_lowp=self.residual_lowp,
                     max_overlap=self.max_overlap, max_disp=self.max_disp, t_narrow=self.t_narrow, t_lcp=self.t_lcp,
                     t_other=self.t_other, rowgraph_entries=np.array(self.rowgraph_entries[:k]),
-                    pairs_rebuilt=self.pairs_rebuilt)
+                    pairs_rebuilt=self.pairs_rebuilt, n_waits=self.n_waits, t_wait=self.t_wait)
 
 
 _lib = None
@@ -237,11 +238,13 @@ class Simulation:
     TIMING_CLASSES = ("lcp_scatter", "lcp_gather", "snsd", "pairs", "trial", "lcp_resident", "warm_start",
                       "lcp_rowgraph", "rowgraph_build")
     LCP_CONFIGS = ("grid", "resident-256", "resident-256-lds", "resident-512", "resident-512-lds",
-                   "resident-1024", "resident-1024-lds", "rowgraph")
+                   "resident-1024", "resident-1024-lds", "rowgraph", "rowgraph-perpass")
 
     def set_lcp_config(self, mode, block=256, lds=True):
         """mode: 0 automatic, 1 grid, 2 resident (one workgroup per packing),
-        3 row graph (A assembled over rows, one pass per iteration)."""
+        3 row graph (A assembled over rows, one pass per iteration, passes
+        replayed from an instantiated HIP graph), 4 row graph with a launch
+        per pass."""
         rc = lib().relcp_set_lcp_config(self.ctx, mode, block, 1 if lds else 0)
         if rc != OK:
             raise RelcpError(rc, self._err())
@@ -415,7 +418,7 @@ def broadphase_device(x_soa, kind, p_soa, box, skin, cap=None, stream=None):
 
 
 def lcp_solve_device(nb, ia, ib, n_soa, ta_soa, tb_soa, qv, kt, Kr_soa, dt, gamma, *, planar=False, precision=64,
-                     mode=3, tol=1e-12, max_iters=0, stream=None):
+                     mode=0, tol=1e-12, max_iters=0, stream=None):
     """Solve 0 <= qv + dt D^T K D gamma _|_ gamma >= 0 on the GPU (gamma
     in/out).  Returns (iterations, FP64 residual, status)."""
     m = ia.numel()

