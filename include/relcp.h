@@ -183,9 +183,11 @@ RELCP_API int relcp_set_lcp_config(relcp_ctx *ctx, int32_t mode, int32_t block, 
  * the last step are restored. */
 RELCP_API int relcp_autotune(relcp_ctx *ctx, double dt, double lcp_tol, int32_t reps, int32_t *config, double *ms);
 
-/* Kernel timing with HIP events recorded on the context's stream around
- * each launch of the step (off by default; costs one event pair per
- * launch).  Classes: 0 = LCP scatter pass (D gamma -> K), 1 = LCP gather
+/* Kernel timing with HIP events (off by default; one event pair per
+ * timed launch): each kernel of a class is launched with the pair as the
+ * dispatch's own start and end timestamps, so a duration is the kernel's
+ * execution alone; a graph launch of row-graph passes (LCP mode 3) is timed
+ * by a pair recorded on the stream around it.  Classes: 0 = LCP scatter pass (D gamma -> K), 1 = LCP gather
  * pass (D^T V, projection, step-size reductions), 2 = SNSD narrowphase,
  * 3 = candidate pairs, 4 = trial integration, 5 = resident LCP solve,
  * 6 = warm-start features and MLP inference, 7 = row-graph LCP pass,
@@ -292,6 +294,25 @@ RELCP_API int relcp_lcp_solve_device(int32_t nb, int32_t m, const int32_t *ia, c
                            const double *ta, const double *tb, const double *qv, const double *kt, const double *Kr,
                            double dt, int32_t planar, int32_t precision, int32_t mode, double tol, int32_t max_iters,
                            double *gamma, int32_t *iters, double *residual, void *stream);
+
+/* ---- building blocks of the step (exposed for testing and reuse) ----
+ *
+ * Exclusive prefix sum of n device ints, out[i] = in[0] + ... + in[i-1]
+ * (out may alias in); *total (a device int, or NULL) receives the sum of
+ * all n.  The step uses it for the per-body offsets of the incidence lists,
+ * the cell lists of the candidate search and the slice bases of the row
+ * graph.  Runs on stream and returns after it has finished; RELCP_E_INVALID
+ * for n < 0 or missing arrays. */
+RELCP_API int relcp_exclusive_scan_device(const int32_t *in, int32_t *out, int32_t n, int32_t *total,
+                                          void *stream);
+/* Stream compaction: out[j] = index of the j-th nonzero flag among the n
+ * device ints flags (increasing order), *count (a device int, or NULL) = the
+ * number of them.  The step selects the pairs of A_0 (Phi_0 <= delta_c) and
+ * the constraints added by an augmentation (Alg. 1) this way.  out holds up
+ * to n ints and must not alias flags.  Runs on stream and returns after it
+ * has finished; RELCP_E_INVALID for bad sizes or pointers. */
+RELCP_API int relcp_compact_flags_device(const int32_t *flags, int32_t n, int32_t *out, int32_t *count,
+                                         void *stream);
 
 #ifdef __cplusplus
 }

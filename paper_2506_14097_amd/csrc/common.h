@@ -6,9 +6,11 @@
 // stored as 6 components (xx, yy, zz, xy, xz, yz).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -30,6 +32,30 @@ struct Error {
         if (_e != hipSuccess)                                                                         \
             throw ::relcp::Error{-3, std::string(#expr) + ": " + hipGetErrorString(_e)};              \
     } while (0)
+
+// ---------------------------------------------------------------------------
+// kernel timing: when an event pair is armed, the next launch made through
+// launch_k takes it as the dispatch's own start and end timestamps (the
+// kernel's execution, without the host's enqueue time), then disarms it
+// ---------------------------------------------------------------------------
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+inline LaunchEvents &armed_launch_events() {
+    static thread_local LaunchEvents e;
+    return e;
+}
+template <typename K, typename... Args>
+inline void launch_k(K kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, Args &&...args) {
+    LaunchEvents &e = armed_launch_events();
+    if (e.start) {
+        const LaunchEvents t = e;
+        e = LaunchEvents{};
+        hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, t.start, t.stop, 0u, std::forward<Args>(args)...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shmem, s, std::forward<Args>(args)...);
+    }
+}
 
 // ---------------------------------------------------------------------------
 // device buffers
@@ -139,5 +165,12 @@ struct PgdState {
 // scan.hip: exclusive prefix sum of n ints (out may alias in); the total is
 // written to total_dev[0] when total_dev is not null.  scratch grows as needed.
 void exclusive_scan(const int *in, int *out, int n, int *total_dev, DBuf<int> &scratch, hipStream_t s);
+// scan.hip: out[j] = index of the j-th set flag (increasing), the count to
+// total_dev[0] when not null.  bcount: the set flags of each group of 256
+// (flag_groups(n) entries, written by the flags' producer), or null to count
+// them here.  out must not alias flags.
+int flag_groups(int n);
+void compact_flags(const int *flags, int n, const int *bcount, int *out, int *total_dev, DBuf<int> &scratch,
+                   hipStream_t s);
 
 }  // namespace relcp

@@ -29,6 +29,8 @@ struct SnsdArgs {
     // the centre-to-centre normal
     const double *Rb;
     int *flag;                   // per pair, or null
+    int *bcount;                 // set flags per block of 256 pairs (snsd_blocks(m) slots), or null
+    double *clear;               // per pair, set to 0 (a per-pair accumulator for later), or null
     // per-block order keys of min Phi and min |Phi + eps| (snsd_blocks(m)
     // slots each), or null
     unsigned long long *minphi;

@@ -438,6 +438,7 @@ __device__ inline unsigned long long order_key(double v) {
 __global__ void __launch_bounds__(256) k_snsd_pairs(SnsdArgs A) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     double phi = 1e300, marg = 1e300;
+    int fl = 0;
     if (k < A.m) {
         int a = A.pa[k], b = A.pb[k];
         int pk = A.body_batch ? A.body_batch[a] : 0;
@@ -485,7 +486,17 @@ __global__ void __launch_bounds__(256) k_snsd_pairs(SnsdArgs A) {
         A.out[9 * A.ldo + k] = s.rb.z;
         phi = s.phi;
         marg = fabs(s.phi + A.eps);
-        if (A.flag) A.flag[k] = (A.mode == 0) ? (s.phi <= A.thresh ? 1 : 0) : (s.phi < -A.eps ? 1 : 0);
+        fl = (A.mode == 0) ? (s.phi <= A.thresh ? 1 : 0) : (s.phi < -A.eps ? 1 : 0);
+        if (A.flag) A.flag[k] = fl;
+        if (A.clear) A.clear[k] = 0.0;
+    }
+    if (A.bcount) {
+        // this block's count of set flags (the compaction's tile offsets)
+        __shared__ int wcnt[4];
+        const int c = __popcll(__ballot(fl != 0));
+        if ((threadIdx.x & (RELCP_WAVE - 1)) == 0) wcnt[threadIdx.x / RELCP_WAVE] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) A.bcount[blockIdx.x] = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
     }
     if (A.minphi) {
         // block minima into this block's slots (reduced in a fixed order later)
@@ -654,7 +665,7 @@ void launch_trial(int nb, const double *x, int ldx, const double *q, int ldq, co
                   int ldv, double dt, const int *kind, const double *p, int ldp, const double *Rb, double *xt,
                   double *qt, double *geo, int ldg, double *vout, unsigned long long *maxdisp, hipStream_t s) {
     if (nb <= 0) return;
-    hipLaunchKernelGGL(k_trial, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, x, ldx, q, ldq, vfree, vc, ldv, dt, kind, p,
+    launch_k(k_trial, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, x, ldx, q, ldq, vfree, vc, ldv, dt, kind, p,
                        ldp, Rb, xt, qt, geo, ldg, vout, maxdisp);
 }
 
@@ -663,7 +674,7 @@ int trial_blocks(int nb) { return nblk(nb > 0 ? nb : 1, 256); }
 
 void launch_snsd_pairs(const SnsdArgs &a, hipStream_t s) {
     if (a.m <= 0) return;
-    hipLaunchKernelGGL(k_snsd_pairs, dim3(nblk(a.m, 256)), dim3(256), 0, s, a);
+    launch_k(k_snsd_pairs, dim3(nblk(a.m, 256)), dim3(256), 0, s, a);
 }
 
 void launch_cell_assign(int nb, const double *x, int ldx, const int *body_batch, const PackGrid *grids,
@@ -684,10 +695,10 @@ void launch_pairs(bool fill, int nb, const double *x, int ldx, const double *Rb,
                   hipStream_t s) {
     if (nb <= 0) return;
     if (fill)
-        hipLaunchKernelGGL(k_pairs<true>, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, x, ldx, Rb, body_batch, grids,
+        launch_k(k_pairs<true>, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, x, ldx, Rb, body_batch, grids,
                            body_cell, cell_start, cell_count, items, skin, pair_count, pair_off, pa, pb, cap);
     else
-        hipLaunchKernelGGL(k_pairs<false>, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, x, ldx, Rb, body_batch, grids,
+        launch_k(k_pairs<false>, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, x, ldx, Rb, body_batch, grids,
                            body_cell, cell_start, cell_count, items, skin, pair_count, pair_off, pa, pb, cap);
 }
 

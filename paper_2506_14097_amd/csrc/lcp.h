@@ -41,10 +41,13 @@ struct RowBuildArgs {
     const double *vfree; // 6 comps
     const double *vc;    // 6 comps (new rows: V_n - U_free) or null (iteration-0 rows)
     int ldb;
-    // warm start from the previous step (sorted pair list) or null
+    // warm start from the previous step (sorted pair list) or null; with
+    // prev_direct the previous list is the current candidate list and the
+    // pair's multiplier is prev_lam[pair] (no search)
     int nprev;
     const int *prev_a, *prev_b;
     const double *prev_lam;
+    int prev_direct;
     // outputs, ld = ldr
     int ldr;
     int *ia, *ib, *pair, *rec_out;
@@ -53,9 +56,10 @@ struct RowBuildArgs {
 };
 
 void launch_rows_build(const RowBuildArgs &a, hipStream_t s);
-void launch_compact(int n, const int *flags, const int *scanned, int *out, hipStream_t s);
+// CSR of the rows at each body; cleared: cnt and cursor (2 (nb + 1) ints)
+// are known to be zero (every build leaves them so)
 void launch_csr(int nb, int m, const int *ia, const int *ib, int *cnt, int *off, int *cursor, int *ent,
-                DBuf<int> &scan_scratch, hipStream_t s);
+                bool cleared, DBuf<int> &scan_scratch, hipStream_t s);
 
 // Device control block of one solve: ping-pong states S[0], S[1], the
 // final state, the done flag and the per-block partial sums of the last
@@ -123,11 +127,12 @@ void launch_incidence_jacobian(int m, const int *ent, const double *n, const dou
                                double *jb, hipStream_t s);
 void launch_rowgraph_fill(const RowGraphFill &a, hipStream_t s);
 // One pass of the row-graph LCP loop over m rows with A in G and the
-// diagonal dA.  mode 0: start, gamma0 = max(0, gam0), g at gamma0; mode 1:
+// diagonal dA.  mode 0: start, gamma0 = max(0, gam0) (FP64 start rounded to
+// T), g at gamma0, and the control block C reset for a new solve; mode 1:
 // iteration with parity par, reading the previous pass's state (zin, gin)
 // and partials, writing (zout, gout) and its own partials pout.
 template <typename T>
-void launch_lcp_spmv(int mode, const RowGraphT<T> &G, const T *qv, const T *dA, const T *gam0,
+void launch_lcp_spmv(int mode, const RowGraphT<T> &G, const T *qv, const T *dA, const double *gam0,
                      const RowStep<T> *zin, const T *gin, RowStep<T> *zout, T *gout, const PgdCtl &C, double *pout,
                      int par, hipStream_t s);
 // Parameters of a row-graph solve in device memory, read by k_spmv_dev:
@@ -160,10 +165,11 @@ void launch_spmv_dev(const LcpDev<T> *D, int grid_rows, int par, hipStream_t s);
 // reading *D.  Returns 0, or -1 with *out = null.
 template <typename T>
 int make_spmv_graph(const LcpDev<T> *D, int grid_rows, int k, hipGraphExec_t *out);
-// gamma, g <- the state of the pass that holds the final iterate (fin.iter & 1)
+// gamma, g <- the state of the pass that holds the final iterate (fin.iter &
+// 1); gam64 (or null) <- the same gamma widened to FP64
 template <typename T>
 void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, const T *g0, const T *g1,
-                            const PgdState *fin, T *gam, T *g, hipStream_t s);
+                            const PgdState *fin, T *gam, T *g, double *gam64, hipStream_t s);
 
 // Passes of the projected-gradient loop.  Iteration j (j = 1, 2, ...) is
 // scatter(mode 1, par = j & 1) then gather(mode 1, par = j & 1); a solve

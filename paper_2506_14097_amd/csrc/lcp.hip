@@ -81,7 +81,9 @@ __global__ void k_rows_build(RowBuildArgs A) {
     double dA = A.dt * (quad(a, ta) + quad(b, tb));
     if (!(dA > 0.0)) dA = 1.0;
     double g0 = 0.0;
-    if (A.prev_lam && A.nprev > 0) {
+    if (A.prev_lam && A.prev_direct) {
+        g0 = A.prev_lam[pr];
+    } else if (A.prev_lam && A.nprev > 0) {
         int lo = 0, hi = A.nprev - 1;
         while (lo <= hi) {
             int mid = (lo + hi) >> 1;
@@ -119,11 +121,6 @@ __global__ void k_rows_build(RowBuildArgs A) {
     A.phi64[r] = phi;
 }
 
-__global__ void k_compact(int n, const int *__restrict__ flags, const int *__restrict__ scanned,
-                          int *__restrict__ out) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && flags[i]) out[scanned[i]] = i;
-}
 
 // ---------------------------------------------------------------------------
 // incidence lists (CSR by body)
@@ -144,10 +141,14 @@ __global__ void k_csr_fill(int m, const int *__restrict__ ia, const int *__restr
     ent[off[b] + atomicAdd(cursor + b, 1)] = (r << 1) | 1;
 }
 
-// order each body's list by entry (row index) so summation order is fixed
-__global__ void k_csr_sort(int nb, const int *__restrict__ off, int *__restrict__ ent) {
+// order each body's list by entry (row index) so summation order is fixed,
+// and clear the body's count and cursor for the next build
+__global__ void k_csr_sort(int nb, const int *__restrict__ off, int *__restrict__ ent, int *__restrict__ cnt,
+                           int *__restrict__ cursor) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nb) return;
+    cnt[i] = 0;
+    cursor[i] = 0;
     int lo = off[i], hi = off[i + 1];
     for (int k = lo + 1; k < hi; ++k) {
         int v = ent[k], j = k - 1;
@@ -260,18 +261,21 @@ __device__ inline void reduce_partials(const PgdCtl &C, int par, PgdState *out, 
     __syncthreads();
 }
 
+// the control block of a new solve (states before iteration 0, not done)
+__device__ inline void pgd_reset(const PgdCtl &C) {
+    PgdState s{};
+    s.alpha = 1.0;
+    s.iter = -1;
+    C.S[0] = s;
+    C.S[1] = s;
+    *C.fin = s;
+    *C.done = 0;
+    if (C.fin_h) *C.fin_h = s;
+    if (C.done_h) *C.done_h = 0;
+}
+
 __global__ void k_pgd_init(PgdCtl C) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        PgdState s{};
-        s.alpha = 1.0;
-        s.iter = -1;
-        C.S[0] = s;
-        C.S[1] = s;
-        *C.fin = s;
-        *C.done = 0;
-        if (C.fin_h) *C.fin_h = s;
-        if (C.done_h) *C.done_h = 0;
-    }
+    if (threadIdx.x == 0 && blockIdx.x == 0) pgd_reset(C);
 }
 
 // Velocity storage of the LCP loop: the global array (ld, body index) or a
@@ -664,7 +668,7 @@ struct RowPre {
 
 template <typename T, int MODE>
 __device__ inline void row_preload(const RowGraphT<T> &G, const T *__restrict__ qv, const T *__restrict__ dA0,
-                                   const T *__restrict__ gam0, const RowStep<T> *__restrict__ zin,
+                                   const double *__restrict__ gam0, const RowStep<T> *__restrict__ zin,
                                    const T *__restrict__ gin, int r, RowPre<T> &P) {
     const int lane = r & (RELCP_WAVE - 1), sl = r / RELCP_WAVE;
     const int b0 = G.base[sl];
@@ -682,7 +686,7 @@ __device__ inline void row_preload(const RowGraphT<T> &G, const T *__restrict__ 
         P.hm = z.h;
         P.gold = gin[r];
     } else {
-        P.gm = gam0[r];
+        P.gm = (T)gam0[r];
         P.hm = T(0);
         P.gold = T(0);
     }
@@ -696,7 +700,7 @@ __device__ inline void row_preload(const RowGraphT<T> &G, const T *__restrict__ 
             P.gj[k] = z.gam;
             P.hj[k] = z.h;
         } else {
-            P.gj[k] = gam0[P.cj[k]];
+            P.gj[k] = (T)gam0[P.cj[k]];
             P.hj[k] = T(0);
         }
     }
@@ -706,7 +710,7 @@ __device__ inline void row_preload(const RowGraphT<T> &G, const T *__restrict__ 
 // of the step-size sums (s^T D s, s^T y, y^T D^-1 y) and residual
 template <typename T, int MODE>
 __device__ inline void row_finish(const RowPre<T> &P, T al, const RowStep<T> *__restrict__ zin,
-                                  const T *__restrict__ gam0, RowStep<T> *__restrict__ zout, T *__restrict__ gout,
+                                  const double *__restrict__ gam0, RowStep<T> *__restrict__ zout, T *__restrict__ gout,
                                   int r, double &ss, double &sy, double &yy, double &res) {
     T acc = T(0);
 #pragma unroll
@@ -718,7 +722,7 @@ __device__ inline void row_finish(const RowPre<T> &P, T al, const RowStep<T> *__
             const RowStep<T> z = zin[j];
             acc += v * step_h(z.gam, z.h, al);
         } else {
-            acc += v * clamp0(gam0[j]);
+            acc += v * clamp0((T)gam0[j]);
         }
     }
     const T gv = MODE == 1 ? step_h(P.gm, P.hm, al) : clamp0(P.gm);
@@ -740,12 +744,13 @@ __device__ inline void row_finish(const RowPre<T> &P, T al, const RowStep<T> *__
 // length, overlapped with the row's loads.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads)
-    k_spmv(RowGraphT<T> G, const T *__restrict__ qv, const T *__restrict__ dA0, const T *__restrict__ gam0,
+    k_spmv(RowGraphT<T> G, const T *__restrict__ qv, const T *__restrict__ dA0, const double *__restrict__ gam0,
            const RowStep<T> *__restrict__ zin, const T *__restrict__ gin, RowStep<T> *__restrict__ zout,
            T *__restrict__ gout, PgdCtl C, double *__restrict__ pout, int par) {
     __shared__ double sh[4][kWaves];
     __shared__ PgdState ns;
     if (MODE == 1 && *C.done) return;
+    if (MODE == 0 && blockIdx.x == 0 && threadIdx.x == 0) pgd_reset(C);
     const int r = blockIdx.x * kThreads + threadIdx.x;
     const bool act = r < G.m;
     RowPre<T> P;
@@ -831,12 +836,15 @@ __global__ void k_set_lcpdev(LcpDev<T> *D, LcpDev<T> v) {
 template <typename T>
 __global__ void k_rowstate_unpack(int m, const RowStep<T> *__restrict__ z0, const RowStep<T> *__restrict__ z1,
                                   const T *__restrict__ g0, const T *__restrict__ g1,
-                                  const PgdState *__restrict__ fin, T *__restrict__ gam, T *__restrict__ g) {
+                                  const PgdState *__restrict__ fin, T *__restrict__ gam, T *__restrict__ g,
+                                  double *__restrict__ gam64) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= m) return;
     const bool odd = fin->iter & 1;
-    gam[r] = (odd ? z1 : z0)[r].gam;
+    const T v = (odd ? z1 : z0)[r].gam;
+    gam[r] = v;
     g[r] = (odd ? g1 : g0)[r];
+    if (gam64) gam64[r] = (double)v;
 }
 
 __global__ void k_promote(int m, const float *__restrict__ a, double *__restrict__ b) {
@@ -878,20 +886,17 @@ void launch_rows_build(const RowBuildArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_rows_build, dim3(nblk(a.nsel, 256)), dim3(256), 0, s, a);
 }
 
-void launch_compact(int n, const int *flags, const int *scanned, int *out, hipStream_t s) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_compact, dim3(nblk(n, 256)), dim3(256), 0, s, n, flags, scanned, out);
-}
 
 void launch_csr(int nb, int m, const int *ia, const int *ib, int *cnt, int *off, int *cursor, int *ent,
-                DBuf<int> &scan_scratch, hipStream_t s) {
-    // cnt and cursor are adjacent (cursor = cnt + nb + 1): one clear
-    HIP_OK(hipMemsetAsync(cnt, 0, sizeof(int) * 2 * (nb + 1), s));
+                bool cleared, DBuf<int> &scan_scratch, hipStream_t s) {
+    // cnt and cursor are adjacent (cursor = cnt + nb + 1): one clear, unless
+    // the last build's sort pass left them at zero
+    if (!cleared) HIP_OK(hipMemsetAsync(cnt, 0, sizeof(int) * 2 * (nb + 1), s));
     if (m > 0) hipLaunchKernelGGL(k_csr_count, dim3(nblk(m, 256)), dim3(256), 0, s, m, ia, ib, cnt);
     exclusive_scan(cnt, off, nb + 1, nullptr, scan_scratch, s);
     if (m > 0) {
         hipLaunchKernelGGL(k_csr_fill, dim3(nblk(m, 256)), dim3(256), 0, s, m, ia, ib, off, cursor, ent);
-        hipLaunchKernelGGL(k_csr_sort, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, off, ent);
+        hipLaunchKernelGGL(k_csr_sort, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, off, ent, cnt, cursor);
     }
 }
 
@@ -899,9 +904,9 @@ template <typename T>
 void launch_lcp_scatter(int mode, const RowsT<T> &r, const BodiesT<T> &b, const PgdCtl &C, int par, hipStream_t s) {
     int nbk = nblk(b.nb > 0 ? b.nb : 1, kThreads);
     if (mode == 0)
-        hipLaunchKernelGGL((k_scatter<T, 0>), dim3(nbk), dim3(kThreads), 0, s, r, b, C, par);
+        launch_k(k_scatter<T, 0>, dim3(nbk), dim3(kThreads), 0, s, r, b, C, par);
     else
-        hipLaunchKernelGGL((k_scatter<T, 1>), dim3(nbk), dim3(kThreads), 0, s, r, b, C, par);
+        launch_k(k_scatter<T, 1>, dim3(nbk), dim3(kThreads), 0, s, r, b, C, par);
 }
 
 template <typename T>
@@ -909,9 +914,9 @@ void launch_lcp_gather(int mode, const RowsT<T> &r, const BodiesT<T> &b, double 
                        hipStream_t s) {
     int nbk = nblk(r.m > 0 ? r.m : 1, kThreads);
     if (mode == 0)
-        hipLaunchKernelGGL((k_gather<T, 0>), dim3(nbk), dim3(kThreads), 0, s, r, b, dt, C, par);
+        launch_k(k_gather<T, 0>, dim3(nbk), dim3(kThreads), 0, s, r, b, dt, C, par);
     else
-        hipLaunchKernelGGL((k_gather<T, 1>), dim3(nbk), dim3(kThreads), 0, s, r, b, dt, C, par);
+        launch_k(k_gather<T, 1>, dim3(nbk), dim3(kThreads), 0, s, r, b, dt, C, par);
 }
 
 int lcp_gather_blocks(int m) { return nblk(m > 0 ? m : 1, kThreads); }
@@ -925,8 +930,8 @@ static int launch_res(const ResidentArgs<T> &a, hipStream_t s) {
             hipSuccess)
             return -1;
     }
-    hipLaunchKernelGGL(fn, dim3(a.npk), dim3(BS), lds, s, a.R, a.B, a.boff, a.roff, a.rlist, a.dt, a.tol, a.cap,
-                       a.out, a.lds_ld);
+    launch_k(fn, dim3(a.npk), dim3(BS), lds, s, a.R, a.B, a.boff, a.roff, a.rlist, a.dt, a.tol, a.cap, a.out,
+             a.lds_ld);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -971,31 +976,31 @@ int rowgraph_slices(int m) { return (m + RELCP_WAVE - 1) / RELCP_WAVE; }
 
 void launch_rowgraph_width(int m, const int *ia, const int *ib, const int *off, int *width, int *count,
                            hipStream_t s) {
-    hipLaunchKernelGGL(k_rowgraph_width, dim3(nblk(m > 0 ? m : 1, kThreads)), dim3(kThreads), 0, s, m, ia, ib, off,
+    launch_k(k_rowgraph_width, dim3(nblk(m > 0 ? m : 1, kThreads)), dim3(kThreads), 0, s, m, ia, ib, off,
                        width, count);
 }
 
 void launch_incidence_jacobian(int m, const int *ent, const double *n, const double *ta, const double *tb, int ldr,
                                double *jb, hipStream_t s) {
     if (m > 0)
-        hipLaunchKernelGGL(k_incidence_jacobian, dim3(nblk(2 * (long long)m, kThreads)), dim3(kThreads), 0, s, 2 * m,
+        launch_k(k_incidence_jacobian, dim3(nblk(2 * (long long)m, kThreads)), dim3(kThreads), 0, s, 2 * m,
                            ent, n, ta, tb, ldr, jb);
 }
 
 void launch_rowgraph_fill(const RowGraphFill &a, hipStream_t s) {
-    if (a.m > 0) hipLaunchKernelGGL(k_rowgraph_fill, dim3(nblk(a.m, kThreads)), dim3(kThreads), 0, s, a);
+    if (a.m > 0) launch_k(k_rowgraph_fill, dim3(nblk(a.m, kThreads)), dim3(kThreads), 0, s, a);
 }
 
 template <typename T>
-void launch_lcp_spmv(int mode, const RowGraphT<T> &G, const T *qv, const T *dA, const T *gam0,
+void launch_lcp_spmv(int mode, const RowGraphT<T> &G, const T *qv, const T *dA, const double *gam0,
                      const RowStep<T> *zin, const T *gin, RowStep<T> *zout, T *gout, const PgdCtl &C, double *pout,
                      int par, hipStream_t s) {
     const int nb = nblk(G.m > 0 ? G.m : 1, kThreads);
     if (mode == 0)
-        hipLaunchKernelGGL((k_spmv<T, 0>), dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C,
+        launch_k(k_spmv<T, 0>, dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C,
                            pout, par);
     else
-        hipLaunchKernelGGL((k_spmv<T, 1>), dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C,
+        launch_k(k_spmv<T, 1>, dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C,
                            pout, par);
 }
 
@@ -1043,10 +1048,10 @@ int make_spmv_graph(const LcpDev<T> *D, int grid_rows, int k, hipGraphExec_t *ou
 
 template <typename T>
 void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, const T *g0, const T *g1,
-                            const PgdState *fin, T *gam, T *g, hipStream_t s) {
+                            const PgdState *fin, T *gam, T *g, double *gam64, hipStream_t s) {
     if (m > 0)
         hipLaunchKernelGGL((k_rowstate_unpack<T>), dim3(nblk(m, 256)), dim3(256), 0, s, m, z0, z1, g0, g1, fin, gam,
-                           g);
+                           g, gam64);
 }
 
 #define RELCP_INST(T)                                                                                              \
@@ -1054,11 +1059,11 @@ void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, c
                                         hipStream_t);                                                             \
     template void launch_lcp_gather<T>(int, const RowsT<T> &, const BodiesT<T> &, double, const PgdCtl &, int,    \
                                        hipStream_t);                                                              \
-    template void launch_lcp_spmv<T>(int, const RowGraphT<T> &, const T *, const T *, const T *,                  \
+    template void launch_lcp_spmv<T>(int, const RowGraphT<T> &, const T *, const T *, const double *,             \
                                      const RowStep<T> *, const T *, RowStep<T> *, T *, const PgdCtl &, double *,  \
                                      int, hipStream_t);                                                           \
     template void launch_rowstate_unpack<T>(int, const RowStep<T> *, const RowStep<T> *, const T *, const T *,    \
-                                            const PgdState *, T *, T *, hipStream_t);                             \
+                                            const PgdState *, T *, T *, double *, hipStream_t);                   \
     template void launch_set_lcpdev<T>(LcpDev<T> *, const LcpDev<T> &, hipStream_t);                               \
     template void launch_spmv_dev<T>(const LcpDev<T> *, int, int, hipStream_t);                                    \
     template int make_spmv_graph<T>(const LcpDev<T> *, int, int, hipGraphExec_t *);

@@ -458,7 +458,7 @@ inline int nblk(long long n, int t) { return (int)((n + t - 1) / t); }
 // launchers
 // ---------------------------------------------------------------------------
 void launch_features(const FeatureArgs &a, hipStream_t s) {
-    if (a.m0 > 0) hipLaunchKernelGGL(k_features, dim3(nblk(a.m0, 256)), dim3(256), 0, s, a);
+    if (a.m0 > 0) launch_k(k_features, dim3(nblk(a.m0, 256)), dim3(256), 0, s, a);
 }
 
 void launch_mlp_forward(const MlpArgs &a, hipStream_t s) {
@@ -468,7 +468,7 @@ void launch_mlp_forward(const MlpArgs &a, hipStream_t s) {
     // persistent: two resident blocks per CU (73 KB of LDS each), weights
     // staged once per block
     const int blocks = std::min(nblk(tiles, NW), 512);
-    hipLaunchKernelGGL((k_mlp<false, NW>), dim3(blocks), dim3(NW * 64), 0, s, a);
+    launch_k(k_mlp<false, NW>, dim3(blocks), dim3(NW * 64), 0, s, a);
 }
 
 int mlp_slots(int n) { return std::max(1, (n + 31) / 32); }
@@ -477,7 +477,7 @@ void launch_mlp_grad(const MlpArgs &a, float *grad, float *loss, hipStream_t s) 
     constexpr int NW = 4;
     const int tiles = (a.n + 31) / 32;
     if (tiles > 0) {
-        hipLaunchKernelGGL((k_mlp<true, NW>), dim3(nblk(tiles, NW)), dim3(NW * 64), 0, s, a);
+        launch_k(k_mlp<true, NW>, dim3(nblk(tiles, NW)), dim3(NW * 64), 0, s, a);
         hipLaunchKernelGGL(k_mlp_reduce, dim3(nblk(MLP_NPARAM + 1, 256)), dim3(256), 0, s, a.partial, tiles,
                            1.0f / (float)a.n, grad, loss);
     } else {

@@ -94,29 +94,45 @@ namespace {
 // Fixed-order reduction of the per-block results of one recursion's tail:
 // largest displacement bound (trial), smallest Phi key and margin key
 // (narrowphase at the trial), work sum; written to host-mapped memory.
+__device__ inline unsigned long long u64_max(unsigned long long a, unsigned long long b) { return a > b ? a : b; }
+__device__ inline unsigned long long u64_min(unsigned long long a, unsigned long long b) { return a < b ? a : b; }
+
+// Sums of the per-block results of a trial into host-mapped memory: the
+// largest displacement key, the smallest Phi and margin keys and the work
+// gamma^T A gamma (strided per-thread sums, then a fixed shuffle tree, so
+// the work sum is the same on every run).
 __global__ void __launch_bounds__(256) k_report(int nt, const unsigned long long *disp, int ns,
                                                 const unsigned long long *phi, const unsigned long long *marg, int nw,
                                                 const double *work, unsigned long long *red_h, double *work_h) {
-    __shared__ unsigned long long s0[256], s1[256], s2[256];
-    __shared__ double s3[256];
+    __shared__ unsigned long long s0[4], s1[4], s2[4];
+    __shared__ double s3[4];
     unsigned long long d = 0ull, p = ~0ull, q = ~0ull;
     double w = 0.0;
-    for (int k = threadIdx.x; k < nt; k += 256) d = disp[k] > d ? disp[k] : d;
+    for (int k = threadIdx.x; k < nt; k += 256) d = u64_max(d, disp[k]);
     for (int k = threadIdx.x; k < ns; k += 256) {
-        p = phi[k] < p ? phi[k] : p;
-        q = marg[k] < q ? marg[k] : q;
+        p = u64_min(p, phi[k]);
+        q = u64_min(q, marg[k]);
     }
     for (int k = threadIdx.x; k < nw; k += 256) w += work[k];
-    s0[threadIdx.x] = d;
-    s1[threadIdx.x] = p;
-    s2[threadIdx.x] = q;
-    s3[threadIdx.x] = w;
+    for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) {
+        d = u64_max(d, __shfl_xor(d, o, RELCP_WAVE));
+        p = u64_min(p, __shfl_xor(p, o, RELCP_WAVE));
+        q = u64_min(q, __shfl_xor(q, o, RELCP_WAVE));
+        w += __shfl_xor(w, o, RELCP_WAVE);
+    }
+    const int lane = threadIdx.x & (RELCP_WAVE - 1), wv = threadIdx.x / RELCP_WAVE;
+    if (lane == 0) {
+        s0[wv] = d;
+        s1[wv] = p;
+        s2[wv] = q;
+        s3[wv] = w;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int k = 1; k < 256; ++k) {
-            d = s0[k] > d ? s0[k] : d;
-            p = s1[k] < p ? s1[k] : p;
-            q = s2[k] < q ? s2[k] : q;
+        for (int k = 1; k < 4; ++k) {
+            d = u64_max(d, s0[k]);
+            p = u64_min(p, s1[k]);
+            q = u64_min(q, s2[k]);
             w += s3[k];
         }
         red_h[0] = d;
@@ -158,7 +174,8 @@ struct relcp_ctx {
 
     // pairs (ld = ldp)
     int np = 0, ldp = 0;
-    DBuf<int> pa, pb, pflag, pscan, sel;
+    const int *csr_clear = nullptr;      // csr_cnt while its counters are known to be zero
+    DBuf<int> pa, pb, pflag, pcnt, sel;  // pcnt: set flags per block of 256 pairs
     DBuf<double> snsd0, snsdt, lam;
     // previous step (warm start): sorted pairs and multiplier sums
     int nprev = 0, ldprev = 0;
@@ -196,13 +213,7 @@ struct relcp_ctx {
     size_t ev_used = 0;
     long long t_count[kClasses] = {};
     double t_ms[kClasses] = {};
-    // record a start/stop event pair around launch `f` when timing is on
-    template <typename F>
-    void timed(int cls, F &&f) {
-        if (!timing) {
-            f();
-            return;
-        }
+    void ev_reserve() {
         if (ev_used + 2 > ev_pool.size()) {
             for (int k = 0; k < 256; ++k) {
                 hipEvent_t e;
@@ -211,6 +222,36 @@ struct relcp_ctx {
             }
             ev_class.resize(ev_pool.size() / 2);
         }
+    }
+    // when timing is on, time the one kernel that `f` launches through
+    // launch_k by the dispatch's own start and end (nothing is counted if f
+    // launches none)
+    template <typename F>
+    void timed(int cls, F &&f) {
+        if (!timing) {
+            f();
+            return;
+        }
+        ev_reserve();
+        LaunchEvents &a = armed_launch_events();
+        a = LaunchEvents{ev_pool[ev_used], ev_pool[ev_used + 1]};
+        f();
+        if (a.start) {
+            a = LaunchEvents{};
+            return;
+        }
+        ev_class[ev_used / 2] = cls;
+        ev_used += 2;
+    }
+    // an event pair recorded on the stream around f (a graph launch): the
+    // span includes any wait of the stream for the host between the two
+    template <typename F>
+    void timed_span(int cls, F &&f) {
+        if (!timing) {
+            f();
+            return;
+        }
+        ev_reserve();
         HIP_OK(hipEventRecord(ev_pool[ev_used], stream));
         f();
         HIP_OK(hipEventRecord(ev_pool[ev_used + 1], stream));
@@ -293,7 +334,7 @@ struct relcp_ctx {
         DBuf<float> *fs[] = {&K32, &vc32, &rn32, &rta32, &rtb32, &rqv32, &rdA32, &rgam32, &rg32};
         for (auto *b : fs) b->release();
         DBuf<int> *is[] = {&kind, &body_batch, &perm_d, &body_cell, &cell_count, &cell_start, &cell_cursor, &cell_items,
-                           &pair_count, &pair_off, &pa, &pb, &pflag, &pscan, &sel, &prev_a, &prev_b, &ria, &rib,
+                           &pair_count, &pair_off, &pa, &pb, &pflag, &pcnt, &sel, &prev_a, &prev_b, &ria, &rib,
                            &rpair, &rrec, &csr_cnt, &csr_off, &csr_cur, &csr_ent, &scan_scratch, &dtotal};
         for (auto *b : is) b->release();
         grids.release();
@@ -434,6 +475,7 @@ static uint64_t spread3(uint64_t v) {
 
 void relcp_ctx::upload_bodies(const relcp_bodies *B, const relcp_shapes *S) {
     n = B->n;
+    csr_clear = nullptr;
     log_valid = false;
     vl_valid = false;
     prev_is_list = false;
@@ -553,9 +595,9 @@ void relcp_ctx::upload_bodies(const relcp_bodies *B, const relcp_shapes *S) {
 void relcp_ctx::ensure_pairs(int need) {
     if (need <= ldp) return;
     size_t nld = std::max<size_t>((size_t)need + need / 4 + 1024, 2 * (size_t)ldp);
-    pa.release(); pb.release(); pflag.release(); pscan.release(); sel.release();
+    pa.release(); pb.release(); pflag.release(); pcnt.release(); sel.release();
     snsd0.release(); snsdt.release(); lam.release();
-    pa.ensure(nld); pb.ensure(nld); pflag.ensure(nld + 1); pscan.ensure(nld + 1); sel.ensure(nld);
+    pa.ensure(nld); pb.ensure(nld); pflag.ensure(nld + 1); pcnt.ensure(snsd_blocks((int)nld) + 1); sel.ensure(nld);
     snsd0.ensure(10 * nld); snsdt.ensure(10 * nld); lam.ensure(nld);
     ldp = (int)nld;
 }
@@ -717,6 +759,7 @@ void relcp_ctx::build_rows(int nsel, int rec, const double *snsd, const double *
     a.prev_a = prev_a.p;
     a.prev_b = prev_b.p;
     a.prev_lam = warm ? prev_lam.p : nullptr;
+    a.prev_direct = warm && prev_is_list ? 1 : 0;
     a.ldr = ldr;
     a.ia = ria.p; a.ib = rib.p; a.pair = rpair.p; a.rec_out = rrec.p;
     a.n64 = rn64.p; a.ta64 = rta64.p; a.tb64 = rtb64.p; a.qv64 = rqv64.p; a.dA64 = rdA64.p; a.gam64 = rgam64.p;
@@ -750,7 +793,11 @@ void relcp_ctx::rebuild_csr() {
     csr_cnt.ensure(2 * (size_t)(n + 1));
     csr_off.ensure(n + 1);
     csr_ent.ensure(2 * (size_t)std::max(m, 1));
-    launch_csr(n, m, ria.p, rib.p, csr_cnt.p, csr_off.p, csr_cnt.p + (n + 1), csr_ent.p, scan_scratch, stream);
+    const bool cleared = csr_clear == csr_cnt.p;
+    csr_clear = nullptr;
+    launch_csr(n, m, ria.p, rib.p, csr_cnt.p, csr_off.p, csr_cnt.p + (n + 1), csr_ent.p, cleared, scan_scratch,
+               stream);
+    csr_clear = csr_cnt.p;  // the build's last pass clears the counters again
 }
 
 // Features of the iteration-0 rows (their multipliers hold the previous
@@ -765,14 +812,14 @@ void relcp_ctx::warm_start_rows(int m0, double dt) {
     fa.ldb = n; fa.kind = kind.p; fa.p = p.p; fa.u = u.p; fa.off = csr_off.p; fa.ent = csr_ent.p;
     fa.perm = perm_d.p;
     fa.dt = dt; fa.feat = feat.p; fa.rowscale = rowscale.p;
-    launch_features(fa, stream);
+    timed(6, [&] { launch_features(fa, stream); });
     if (warm_start == RELCP_WS_LEARNED) {
         MlpArgs ma{};
         ma.n = m0; ma.X = feat.p; ma.params = mlp_w.p;
         std::memcpy(ma.norm, mlp_norm, sizeof(mlp_norm));
         ma.rowscale = rowscale.p;
         ma.out64 = rgam64.p;
-        launch_mlp_forward(ma, stream);
+        timed(6, [&] { launch_mlp_forward(ma, stream); });
     } else if (warm_start == RELCP_WS_COLD && m0 > 0) {
         HIP_OK(hipMemsetAsync(rgam64.p, 0, (size_t)m0 * sizeof(double), stream));
     }
@@ -801,15 +848,15 @@ void relcp_ctx::build_rowgraph(double dt) {
         rg_val32.ensure(rg_cap);
     }
     int_h[4] = int_h[5] = int_h[6] = 0;  // slots / 64, entries, overflow (written by the fill)
-    launch_rowgraph_width(m, ria.p, rib.p, csr_off.p, rg_width.p, rg_flags.p, stream);
+    timed(8, [&] { launch_rowgraph_width(m, ria.p, rib.p, csr_off.p, rg_width.p, rg_flags.p, stream); });
     exclusive_scan(rg_width.p, rg_base.p, ns + 1, nullptr, scan_scratch, stream);
-    launch_incidence_jacobian(m, csr_ent.p, rn64.p, rta64.p, rtb64.p, ldr, rg_jb.p, stream);
+    timed(8, [&] { launch_incidence_jacobian(m, csr_ent.p, rn64.p, rta64.p, rtb64.p, ldr, rg_jb.p, stream); });
     RowGraphFill f{};
     f.m = m; f.ldr = ldr; f.ia = ria.p; f.ib = rib.p; f.n = rn64.p; f.ta = rta64.p; f.tb = rtb64.p;
     f.ldb = n; f.K = K.p; f.off = csr_off.p; f.ent = csr_ent.p; f.jb = rg_jb.p; f.base = rg_base.p; f.dt = dt;
     f.cap = rg_cap; f.count = rg_flags.p; f.report = int_d + 4;
     f.col = rg_col.p; f.val64 = rg_val64.p; f.val32 = rg_val32.p;
-    launch_rowgraph_fill(f, stream);  // reports slots, entries and overflow, read after the solve's first sync
+    timed(8, [&] { launch_rowgraph_fill(f, stream); });  // reports slots, entries and overflow, read after the solve's first sync
     rg_valid = true;
     rg_dt = dt;
 }
@@ -970,7 +1017,7 @@ int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt
     for (int attempt = 0;; ++attempt) {
         bool fresh = false;
         if (!rg_valid || rg_dt != dt) {
-            timed(8, [&] { build_rowgraph(dt); });
+            build_rowgraph(dt);
             fresh = true;
         }
         RowGraphT<T> G{m, rg_base.p, rg_col.p, nullptr, rg_cap};
@@ -993,9 +1040,9 @@ int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt
                 launch_set_lcpdev<T>(dev, v, stream);
             }
         }
-        launch_pgd_init(C, stream);
+        // the start pass also resets the control block
         timed(7, [&] {
-            launch_lcp_spmv<T>(0, G, R.qv, R.dA, R.gam, nullptr, nullptr, z0, g0, C, partials.p, 0, stream);
+            launch_lcp_spmv<T>(0, G, R.qv, R.dA, rgam64.p, nullptr, nullptr, z0, g0, C, partials.p, 0, stream);
         });
         int j = 1;
         int chunk = std::max(2, std::min(64, (last_iters[pk] + 3) & ~1));
@@ -1006,7 +1053,7 @@ int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt
                 // whole graphs; the passes past the end of the solve return at once
                 const int ng = (chunk + kGraphPasses - 1) / kGraphPasses;
                 for (int t = 0; t < ng; ++t, j += kGraphPasses)
-                    timed(7, [&] { HIP_OK(hipGraphLaunch(ge, stream)); });
+                    timed_span(7, [&] { HIP_OK(hipGraphLaunch(ge, stream)); });
             } else {
                 const int k = std::min(chunk, cap - (j - 1));
                 if (k <= 0) break;
@@ -1051,7 +1098,8 @@ int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt
         }
         break;
     }
-    launch_rowstate_unpack<T>(m, z0, z1, g0, g1, C.fin, R.gam, R.g, stream);
+    // FP32: the final iterate widened into the FP64 multipliers as well
+    launch_rowstate_unpack<T>(m, z0, z1, g0, g1, C.fin, R.gam, R.g, sizeof(T) == 4 ? rgam64.p : nullptr, stream);
     if constexpr (sizeof(T) == 8) timed(0, [&] { launch_lcp_scatter<T>(0, R, Bd, C, 0, stream); });
     if (!seen) sync();
     const bool conv = *conv_h != 0;
@@ -1092,13 +1140,13 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     sa.m = np; sa.pa = pa.p; sa.pb = pb.p; sa.body_batch = body_batch.p; sa.x = x.p; sa.ldx = N; sa.geo = geo.p;
     sa.ldg = N; sa.kind = kind.p; sa.p = p.p; sa.ldp = N; sa.boxes = boxes.p; sa.planar = planar; sa.hint = nullptr;
     sa.out = snsd0.p; sa.ldo = ldp; sa.mode = 0; sa.thresh = skin; sa.eps = eps; sa.flag = pflag.p;
+    sa.bcount = pcnt.p;
     sa.minphi = nullptr; sa.minmarg = nullptr; sa.Rb = Rb.p;
     // Newton starts from the normals of the accepted trial of the previous
     // step (the same configuration up to the caller's rescale)
     if (hint_ok) sa.hint = snsdt.p + ldp;
     timed(2, [&] { launch_snsd_pairs(sa, stream); });
-    exclusive_scan(pflag.p, pscan.p, np, np > 0 ? int_d : nullptr, scan_scratch, stream);  // total -> int_h[0]
-    launch_compact(np, pflag.p, pscan.p, sel.p, stream);
+    compact_flags(pflag.p, np, pcnt.p, sel.p, int_d, scan_scratch, stream);  // count -> int_h[0]
     sync();
     int m0 = np > 0 ? int_h[0] : 0;
     t_narrow += tm.ms();
@@ -1109,7 +1157,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     log_valid = false;
     build_rows(m0, 0, snsd0.p, nullptr, warm_start == RELCP_WS_PREV || need_feat, dt);
     rebuild_csr();
-    if (need_feat) timed(6, [&] { warm_start_rows(m0, dt); });
+    if (need_feat) warm_start_rows(m0, dt);
     if (resident_mode()) rows_by_packing_init(m0);
     t_other += tm.ms();
 
@@ -1122,11 +1170,13 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         int it = 0, it64 = 0;
         double res = 0, res64 = 0;
         if (precision == 32) {
-            launch_demote(m, rgam64.p, rgam32.p, stream);
+            // (the row-graph solve reads the FP64 start and writes the FP64
+            // result itself)
+            if (!rowgraph_mode()) launch_demote(m, rgam64.p, rgam32.p, stream);
             status = solve<float>(dt, tol, it, res);
             if (status == RELCP_OK || status == RELCP_E_LCP_MAXITER) {
                 // FP64 residual of the FP32 iterate, polished in FP64 if needed
-                launch_promote(m, rgam32.p, rgam64.p, stream);
+                if (!rowgraph_mode()) launch_promote(m, rgam32.p, rgam64.p, stream);
                 status = solve<double>(dt, tol, it64, res64);
             }
         } else {
@@ -1161,9 +1211,9 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         SnsdArgs sb = sa;
         sb.x = xt.p; sb.geo = geot.p; sb.hint = snsd0.p + ldp; sb.out = snsdt.p; sb.mode = 1; sb.flag = pflag.p;
         sb.minphi = red.p + nt; sb.minmarg = red.p + nt + nsb;
+        sb.clear = lam.p;  // the pair sums of an accepted step are accumulated there
         timed(2, [&] { launch_snsd_pairs(sb, stream); });
-        exclusive_scan(pflag.p, pscan.p, np, np > 0 ? int_d : nullptr, scan_scratch, stream);  // -> int_h[0]
-        launch_compact(np, pflag.p, pscan.p, sel.p, stream);
+        compact_flags(pflag.p, np, pcnt.p, sel.p, int_d, scan_scratch, stream);  // count -> int_h[0]
         hipLaunchKernelGGL(k_report, dim3(1), dim3(256), 0, stream, nt, red.p, np > 0 ? nsb : 0, red.p + nt,
                            red.p + nt + nsb, nw, work_out.p, red_hd, dbl_hd);
         sync();
@@ -1214,7 +1264,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         std::swap(q.p, qt.p);
         std::swap(u.p, vout.p);  // every trial writes all of vout
         // multiplier sum per pair, for the next warm start
-        HIP_OK(hipMemsetAsync(lam.p, 0, std::max(np, 1) * sizeof(double), stream));
+        // (lam was cleared by the last trial's SNSD pass)
         for (int lv = 0; lv <= rec; ++lv) launch_pair_lambda(m, rrec.p, rpair.p, rgam64.p, lv, lam.p, stream);
         if (!prev_is_list) {
             // the previous-step pairs are the candidate list itself until it is rebuilt
@@ -1955,9 +2005,9 @@ int relcp_lcp_solve_device(int32_t nb, int32_t m, const int32_t *ia, const int32
         int it = 0, it64 = 0, rc;
         double res = 0, res64 = 0;
         if (precision == 32) {
-            launch_demote(m, c.rgam64.p, c.rgam32.p, c.stream);
+            if (!c.rowgraph_mode()) launch_demote(m, c.rgam64.p, c.rgam32.p, c.stream);
             rc = c.solve<float>(dt, tol, it, res);
-            launch_promote(m, c.rgam32.p, c.rgam64.p, c.stream);
+            if (!c.rowgraph_mode()) launch_promote(m, c.rgam32.p, c.rgam64.p, c.stream);
             if (rc == RELCP_OK || rc == RELCP_E_LCP_MAXITER) rc = c.solve<double>(dt, tol, it64, res64);
         } else {
             rc = c.solve<double>(dt, tol, it, res64);
@@ -1972,6 +2022,38 @@ int relcp_lcp_solve_device(int32_t nb, int32_t m, const int32_t *ia, const int32
         c.stream = nullptr;
         return e.code;
     }
+}
+
+int relcp_exclusive_scan_device(const int32_t *in, int32_t *out, int32_t n, int32_t *total, void *stream) {
+    if (n < 0 || (n > 0 && (!in || !out))) return RELCP_E_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    DBuf<int> scratch;
+    try {
+        exclusive_scan(in, out, n, total, scratch, s);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipStreamSynchronize(s));
+    } catch (const Error &e) {
+        scratch.release();
+        return e.code;
+    }
+    scratch.release();
+    return RELCP_OK;
+}
+
+int relcp_compact_flags_device(const int32_t *flags, int32_t n, int32_t *out, int32_t *count, void *stream) {
+    if (n < 0 || (n > 0 && (!flags || !out)) || (const void *)flags == (const void *)out) return RELCP_E_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    DBuf<int> scratch;
+    try {
+        compact_flags(flags, n, nullptr, out, count, scratch, s);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipStreamSynchronize(s));
+    } catch (const Error &e) {
+        scratch.release();
+        return e.code;
+    }
+    scratch.release();
+    return RELCP_OK;
 }
 
 }  // extern "C"

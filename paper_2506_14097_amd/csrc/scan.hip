@@ -1,8 +1,14 @@
-// scan.hip -- exclusive prefix sums for compaction, CSR offsets and cells.
+// scan.hip -- exclusive prefix sums (CSR offsets, cell lists, slice bases)
+// and stream compaction of flagged items.
 //
-// Three passes: per-block scans of 2048 items (256 threads x 8 items, wave
-// scans through DPP shuffles, block totals through LDS), a recursive scan of
-// the block totals, and an add-back pass.
+// A scan of at most kSmall items runs in one block of 1024 threads.  A
+// larger one takes two passes over tiles of 2048 items (256 threads x 8
+// items): the tile totals, then the tile scans, each block adding the sum of
+// the totals of the tiles before its own (it sums them itself while there are
+// at most kDirect tiles; past that the totals are scanned first, by the same
+// routine).  Within a tile: wave scans through cross-lane shuffles, wave
+// totals through LDS.  Every sum is over integers, so the order does not
+// change the result.
 #include "common.h"
 
 namespace relcp {
@@ -12,6 +18,9 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kItems = 8;
 constexpr int kTile = kThreads * kItems;
+constexpr int kSmallThreads = 1024;
+constexpr int kSmall = kSmallThreads * kItems;
+constexpr int kDirect = 1024;  // tiles whose offsets a block sums by itself
 
 __device__ inline int wave_incl_scan(int v) {
     const int lane = threadIdx.x & (RELCP_WAVE - 1);
@@ -23,69 +32,205 @@ __device__ inline int wave_incl_scan(int v) {
     return v;
 }
 
-__global__ void __launch_bounds__(kThreads) k_scan_tiles(const int *__restrict__ in, int *__restrict__ out, int n,
-                                                         int *__restrict__ tile_sums) {
-    __shared__ int wsum[kThreads / RELCP_WAVE];
-    const long long base = (long long)blockIdx.x * kTile + (long long)threadIdx.x * kItems;
-    int v[kItems];
+__device__ inline int wave_total(int v) {
+#pragma unroll
+    for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, RELCP_WAVE);
+    return v;
+}
+
+// sum of v over the block (every thread gets it); sh holds one int per wave
+template <int NT>
+__device__ inline int block_total(int v, int *sh) {
+    v = wave_total(v);
+    const int lane = threadIdx.x & (RELCP_WAVE - 1), w = threadIdx.x / RELCP_WAVE;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    int t = 0;
+#pragma unroll
+    for (int k = 0; k < NT / RELCP_WAVE; ++k) t += sh[k];
+    __syncthreads();
+    return t;
+}
+
+// Exclusive scan of the kItems values of each thread of an NT-thread block,
+// offset by `base`: on return v[k] holds the exclusive prefix of item k and
+// the block total is returned.
+template <int NT>
+__device__ inline int block_scan_items(int (&v)[kItems], int base, int *wsum) {
     int acc = 0;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        long long i = base + k;
-        v[k] = (i < n) ? in[i] : 0;
-        acc += v[k];
-    }
-    int inc = wave_incl_scan(acc);
+    for (int k = 0; k < kItems; ++k) acc += v[k];
+    const int inc = wave_incl_scan(acc);
     const int lane = threadIdx.x & (RELCP_WAVE - 1), w = threadIdx.x / RELCP_WAVE;
     if (lane == RELCP_WAVE - 1) wsum[w] = inc;
     __syncthreads();
-    int woff = 0;
-    for (int j = 0; j < w; ++j) woff += wsum[j];
-    int run = woff + inc - acc;
+    int woff = 0, tot = 0;
+#pragma unroll
+    for (int j = 0; j < NT / RELCP_WAVE; ++j) {
+        woff += j < w ? wsum[j] : 0;
+        tot += wsum[j];
+    }
+    int run = base + woff + inc - acc;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        long long i = base + k;
-        if (i < n) out[i] = run;
-        run += v[k];
+        const int x = v[k];
+        v[k] = run;
+        run += x;
     }
-    if (threadIdx.x == kThreads - 1) tile_sums[blockIdx.x] = woff + inc;
+    return tot;
 }
 
-__global__ void __launch_bounds__(kThreads) k_scan_add(int *__restrict__ out, int n, const int *__restrict__ offs) {
-    const long long base = (long long)blockIdx.x * kTile;
-    const int add = offs[blockIdx.x];
-    for (int k = threadIdx.x; k < kTile; k += kThreads) {
-        long long i = base + k;
-        if (i < n) out[i] += add;
-    }
+__global__ void __launch_bounds__(kSmallThreads) k_scan_small(const int *__restrict__ in, int *__restrict__ out,
+                                                              int n, int *__restrict__ total) {
+    __shared__ int wsum[kSmallThreads / RELCP_WAVE];
+    const int base = threadIdx.x * kItems;
+    int v[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) v[k] = base + k < n ? in[base + k] : 0;
+    const int tot = block_scan_items<kSmallThreads>(v, 0, wsum);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k)
+        if (base + k < n) out[base + k] = v[k];
+    if (total && threadIdx.x == 0) *total = tot;
 }
 
-// Scan of one level; the total of the whole input ends in `total` (the top
-// level is a single tile whose block sum is the total).
-void scan_rec(const int *in, int *out, int n, int *scratch, int *total, hipStream_t s) {
-    int nt = (n + kTile - 1) / kTile;
-    if (nt == 1) {
-        int *sums = total ? total : scratch;
-        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kThreads), 0, s, in, out, n, sums);
-        return;
-    }
-    int *sums = scratch;
-    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kThreads), 0, s, in, out, n, sums);
-    scan_rec(sums, sums, nt, scratch + nt, total, s);
-    hipLaunchKernelGGL(k_scan_add, dim3(nt), dim3(kThreads), 0, s, out, n, sums);
+__global__ void __launch_bounds__(kThreads) k_tile_sums(const int *__restrict__ in, int n, int *__restrict__ sums) {
+    __shared__ int sh[kThreads / RELCP_WAVE];
+    const long long base = (long long)blockIdx.x * kTile + (long long)threadIdx.x * kItems;
+    int acc = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) acc += base + k < n ? in[base + k] : 0;
+    const int t = block_total<kThreads>(acc, sh);
+    if (threadIdx.x == 0) sums[blockIdx.x] = t;
+}
+
+// The offset of tile b: offs[b] when the totals are already scanned, else
+// the sum of sums[0 .. b) (every thread of the block gets it).
+__device__ inline int tile_offset(const int *sums, const int *offs, int b, int *sh) {
+    if (offs) return offs[b];
+    int acc = 0;
+    for (int k = threadIdx.x; k < b; k += kThreads) acc += sums[k];
+    return block_total<kThreads>(acc, sh);
+}
+
+__global__ void __launch_bounds__(kThreads) k_scan_apply(const int *__restrict__ in, int *__restrict__ out, int n,
+                                                         const int *__restrict__ sums, const int *__restrict__ offs,
+                                                         int *__restrict__ total) {
+    __shared__ int sh[kThreads / RELCP_WAVE];
+    __shared__ int wsum[kThreads / RELCP_WAVE];
+    const int b = blockIdx.x;
+    const int off = tile_offset(sums, offs, b, sh);
+    const long long base = (long long)b * kTile + (long long)threadIdx.x * kItems;
+    int v[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) v[k] = base + k < n ? in[base + k] : 0;
+    const int tot = block_scan_items<kThreads>(v, off, wsum);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k)
+        if (base + k < n) out[base + k] = v[k];
+    if (total && b == (int)gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
+}
+
+// Flag counts per 256 items (for callers whose flags come without them).
+__global__ void __launch_bounds__(kThreads) k_count_flags(const int *__restrict__ flags, int n,
+                                                          int *__restrict__ bcount) {
+    __shared__ int sh[kThreads / RELCP_WAVE];
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    const int f = i < n && flags[i] ? 1 : 0;
+    const int t = block_total<kThreads>(f, sh);
+    if (threadIdx.x == 0) bcount[blockIdx.x] = t;
+}
+
+// Compaction of tile b (2048 flags = 8 count groups of 256): its offset is
+// the number of set flags in the groups before it.
+__global__ void __launch_bounds__(kThreads) k_compact_tiles(const int *__restrict__ flags, int n,
+                                                            const int *__restrict__ bcount,
+                                                            const int *__restrict__ boffs, int *__restrict__ out,
+                                                            int *__restrict__ total) {
+    __shared__ int sh[kThreads / RELCP_WAVE];
+    __shared__ int wsum[kThreads / RELCP_WAVE];
+    const int b = blockIdx.x;
+    const int g0 = b * (kTile / kThreads);  // first count group of the tile
+    const int off = tile_offset(bcount, boffs, g0, sh);
+    const long long base = (long long)b * kTile + (long long)threadIdx.x * kItems;
+    int v[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) v[k] = base + k < n && flags[base + k] ? 1 : 0;
+    int set[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) set[k] = v[k];
+    const int tot = block_scan_items<kThreads>(v, off, wsum);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k)
+        if (set[k]) out[v[k]] = (int)(base + k);
+    if (total && b == (int)gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
 }
 
 }  // namespace
+
+int flag_groups(int n) { return (n + kThreads - 1) / kThreads; }
+
+// scratch use of a scan of n items: the tile totals, then (past kDirect
+// tiles) their scan and the scratch of that scan
+static size_t scan_scratch_need(long long n) {
+    if (n <= kSmall) return 0;
+    const long long nt = (n + kTile - 1) / kTile;
+    size_t need = (size_t)nt;
+    if (nt > kDirect) need += (size_t)nt + scan_scratch_need(nt);
+    return need;
+}
+
+static void scan_into(const int *in, int *out, int n, int *total_dev, int *scratch, hipStream_t s) {
+    if (n <= kSmall) {
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kSmallThreads), 0, s, in, out, n, total_dev);
+        return;
+    }
+    const int nt = (n + kTile - 1) / kTile;
+    int *sums = scratch;
+    hipLaunchKernelGGL(k_tile_sums, dim3(nt), dim3(kThreads), 0, s, in, n, sums);
+    int *offs = nullptr;
+    if (nt > kDirect) {
+        offs = scratch + nt;
+        scan_into(sums, offs, nt, nullptr, scratch + 2 * (size_t)nt, s);
+    }
+    hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(kThreads), 0, s, in, out, n, sums, offs, total_dev);
+}
 
 void exclusive_scan(const int *in, int *out, int n, int *total_dev, DBuf<int> &scratch, hipStream_t s) {
     if (n <= 0) {
         if (total_dev) HIP_OK(hipMemsetAsync(total_dev, 0, sizeof(int), s));
         return;
     }
-    size_t need = 1;
-    for (long long m = n; m > 1; m = (m + kTile - 1) / kTile) need += (m + kTile - 1) / kTile;
-    scratch.ensure(need + 2);
-    scan_rec(in, out, n, scratch.p, total_dev, s);
+    scratch.ensure(scan_scratch_need(n) + 2);
+    scan_into(in, out, n, total_dev, scratch.p, s);
+}
+
+void compact_flags(const int *flags, int n, const int *bcount, int *out, int *total_dev, DBuf<int> &scratch,
+                   hipStream_t s) {
+    if (n <= 0) {
+        if (total_dev) HIP_OK(hipMemsetAsync(total_dev, 0, sizeof(int), s));
+        return;
+    }
+    const int ng = flag_groups(n);
+    const int nt = (n + kTile - 1) / kTile;
+    size_t need = 2;
+    int *cnt = nullptr;
+    if (!bcount) need += (size_t)ng;
+    if (ng > kDirect) need += (size_t)ng + scan_scratch_need(ng);
+    scratch.ensure(need);
+    int *p = scratch.p;
+    if (!bcount) {
+        cnt = p;
+        p += ng;
+        hipLaunchKernelGGL(k_count_flags, dim3(ng), dim3(kThreads), 0, s, flags, n, cnt);
+        bcount = cnt;
+    }
+    int *boffs = nullptr;
+    if (ng > kDirect) {
+        boffs = p;
+        scan_into(bcount, boffs, ng, nullptr, p + ng, s);
+    }
+    hipLaunchKernelGGL(k_compact_tiles, dim3(nt), dim3(kThreads), 0, s, flags, n, bcount, boffs, out, total_dev);
 }
 
 }  // namespace relcp

@@ -110,6 +110,8 @@ _SIGS = {
     "relcp_lcp_solve_device": (C.c_int, [C.c_int32, C.c_int32] + [C.c_void_p] * 8 + [C.c_double, C.c_int32, C.c_int32,
                                          C.c_int32, C.c_double, C.c_int32, C.c_void_p, C.POINTER(C.c_int32),
                                          C.POINTER(C.c_double), C.c_void_p]),
+    "relcp_exclusive_scan_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "relcp_compact_flags_device": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
 
@@ -428,6 +430,28 @@ def lcp_solve_device(nb, ia, ib, n_soa, ta_soa, tb_soa, qv, kt, Kr_soa, dt, gamm
                                       _tptr(qv), _tptr(kt), _tptr(Kr_soa), dt, 1 if planar else 0, precision, mode,
                                       tol, max_iters, _tptr(gamma), C.byref(it), C.byref(res), stream)
     return it.value, res.value, rc
+
+
+def exclusive_scan_device(x, out=None, stream=None):
+    """Exclusive prefix sum of an int32 device tensor; returns (out, total)."""
+    import torch
+    out = torch.empty_like(x) if out is None else out
+    tot = torch.zeros(1, dtype=torch.int32, device=x.device)
+    rc = lib().relcp_exclusive_scan_device(_tptr(x), _tptr(out), x.numel(), _tptr(tot), stream)
+    if rc != OK:
+        raise RelcpError(rc, "exclusive scan failed")
+    return out, int(tot.item())
+
+
+def compact_flags_device(flags, stream=None):
+    """Indices of the nonzero entries of an int32 device tensor (increasing)."""
+    import torch
+    out = torch.empty(max(flags.numel(), 1), dtype=torch.int32, device=flags.device)
+    cnt = torch.zeros(1, dtype=torch.int32, device=flags.device)
+    rc = lib().relcp_compact_flags_device(_tptr(flags), flags.numel(), _tptr(out), _tptr(cnt), stream)
+    if rc != OK:
+        raise RelcpError(rc, "compaction failed")
+    return out[:int(cnt.item())]
 
 
 def header_symbols():

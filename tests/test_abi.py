@@ -83,3 +83,40 @@ def test_null_context_calls_fail_cleanly():
     assert L.relcp_get_state(None, None, None, None, None) == R.E_INVALID
     assert L.relcp_affine_rescale(None, 0.9) == R.E_INVALID
     L.relcp_destroy(None)
+
+
+def _c_kind(decl):
+    """Kind of a C parameter or return declaration from include/relcp.h."""
+    d = " ".join(decl.split())
+    if "*" in d:
+        return "ptr"
+    for word, kind in (("double", "f64"), ("float", "f32"), ("size_t", "size"), ("int32_t", "i32"),
+                       ("int", "i32"), ("void", "void")):
+        if word in d.split():
+            return kind
+    raise AssertionError("unclassified declaration: " + decl)
+
+
+def _ctypes_kind(t):
+    if t is None:
+        return "void"
+    if t in (C.c_void_p, C.c_char_p) or (isinstance(t, type) and issubclass(t, C._Pointer)):
+        return "ptr"
+    return {C.c_double: "f64", C.c_float: "f32", C.c_size_t: "size", C.c_int32: "i32", C.c_int: "i32"}[t]
+
+
+def test_binding_signatures_match_header():
+    """Every ctypes signature in the binding has the parameter count, order
+    and kinds (pointer, 32-bit int, size_t, float, double) of the header's
+    declaration: a swapped pair would pass a truncated pointer to the GPU."""
+    import re
+    with open(R.HEADER) as f:
+        txt = re.sub(r"/\*.*?\*/", " ", f.read(), flags=re.S)
+    decls = re.findall(r"RELCP_API\s+([\w\s\*]+?)\b(relcp_\w+)\s*\(([^)]*)\)\s*;", txt)
+    assert len(decls) == len(R._SIGS)
+    for ret, name, params in decls:
+        res, args = R._SIGS[name]
+        ps = [p for p in params.split(",") if p.strip()]
+        kinds = [] if [p.strip() for p in ps] == ["void"] else [_c_kind(p) for p in ps]
+        assert [_ctypes_kind(a) for a in args] == kinds, name
+        assert _ctypes_kind(res) == _c_kind(ret), name
