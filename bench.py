@@ -38,6 +38,12 @@ FP64_PEAK_TFLOPS = 78.6
 MEASURED_TRAFFIC = {"sha256_prefix": "05a6215d8c110f99", "lcp_scatter": 2.4678e7, "lcp_gather": 1.7280e7}
 
 
+# timing class -> kernel
+KERNEL_SYMBOLS = {"lcp_rowgraph": "relcp::k_spmv<float, 1>", "lcp_rowgraph64": "relcp::k_spmv<double, 1>",
+                  "lcp_rowgraph_start": "relcp::k_spmv<T, 0>", "lcp_gather": "relcp::k_gather<T, 1>",
+                  "lcp_scatter": "relcp::k_scatter<T, 1>"}
+
+
 def kernel_source_sha():
     import hashlib
     with open(os.path.join(ROOT, "paper_2506_14097_amd", "csrc", "lcp.hip"), "rb") as f:
@@ -121,6 +127,47 @@ def learned_comparison(args, state):
         log("  %s: %s" % (name, out[name]))
         D.sim.close()
     return out
+
+
+def lcp_sweep(args):
+    """The LCP loop alone at many sizes: lattice contact graphs (about 1.3
+    rows per body, rows sorted by body), solved on the GPU through the
+    stateless entry point in the row-graph mode with one launch per pass, 40
+    FP32 iterations then 40 FP64 iterations (tolerance out of reach, so the
+    pass count is fixed).  Wall time per solve (second of two runs); the
+    per-pass kernel durations come from a rocprofv3 kernel trace of this
+    command."""
+    import torch
+    from paper_2506_14097_amd import inputs as I
+    from paper_2506_14097_amd import relcp as R
+    dev = torch.device("cuda:0")
+
+    def soa(a):
+        return torch.tensor(np.ascontiguousarray(np.asarray(a).T), dtype=torch.float64, device=dev).contiguous()
+
+    out = []
+    for mt in [int(v) for v in args.sweep_rows.split(",")]:
+        L = I.lattice_lcp(1, mt)
+        m = int(L["ia"].size)
+        a = (L["n"], torch.tensor(L["ia"], device=dev), torch.tensor(L["ib"], device=dev), soa(L["nrm"]),
+             soa(L["ta"]), soa(L["tb"]), torch.tensor(L["qv"], dtype=torch.float64, device=dev),
+             torch.tensor(L["kt"], dtype=torch.float64, device=dev),
+             torch.tensor(L["Kr6"], dtype=torch.float64, device=dev), 0.05)
+        for _ in range(2):
+            g = torch.zeros(m, dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            it, res, rc = R.lcp_solve_device(*a, g, precision=32, mode=4, tol=1e-14, max_iters=40)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+        rec = {"rows": m, "bodies": int(L["n"]), "entries": int(L["E"]), "iterations": int(it),
+               "solve_ms": 1e3 * el,
+               "bytes_per_pass_fp32": rowgraph_bytes(m, L["E"], 4, 1) - rowgraph_bytes(m, L["E"], 4, 0),
+               "bytes_per_pass_fp64": rowgraph_bytes(m, L["E"], 8, 1) - rowgraph_bytes(m, L["E"], 8, 0)}
+        log("lcp sweep: %s" % json.dumps(rec))
+        out.append(rec)
+    print(json.dumps({"metric": "row-graph LCP solve time vs size (lattice contact graphs)", "unit": "ms",
+                      "data": "synthetic", "sizes": out}), flush=True)
 
 
 def packings_workload(args):
@@ -251,7 +298,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start comparison")
     ap.add_argument("--learned-steps", type=int, default=20)
-    ap.add_argument("--workload", default="compaction100k", choices=("compaction100k", "packings512"))
+    ap.add_argument("--workload", default="compaction100k", choices=("compaction100k", "packings512", "lcp-sweep"))
+    ap.add_argument("--sweep-rows", default="25000,100000,400000,1600000,6400000",
+                    help="lcp-sweep: target row counts of the lattice LCPs")
     ap.add_argument("--packings", type=int, default=512)
     ap.add_argument("--copy-probe-mb", type=float, default=0.0,
                     help="only run a device-to-device copy of this many MB (reference for HBM counters)")
@@ -274,6 +323,9 @@ def main():
         return
     if args.workload == "packings512":
         packings_workload(args)
+        return
+    if args.workload == "lcp-sweep":
+        lcp_sweep(args)
         return
     R.lib()
 
@@ -309,7 +361,8 @@ def main():
     tm = sim.get_timing(reset=True)
     sim.set_timing(False)
     nb = args.n
-    tot_bytes = {"lcp_gather": 0.0, "lcp_scatter": 0.0, "lcp_rowgraph": 0.0}
+    tot_bytes = {"lcp_gather": 0.0, "lcp_scatter": 0.0, "lcp_rowgraph": 0.0, "lcp_rowgraph64": 0.0,
+                 "lcp_rowgraph_start": 0.0}
     busy = 0  # launches that did work (the rest return at once after convergence)
     for s in rstats:
         for m, it, it64, e in zip(s["n_contacts"], s["lcp_iters"], s["lcp_iters64"], s["rowgraph_entries"]):
@@ -319,11 +372,12 @@ def main():
                     tot_bytes[cls] += (itlo + 1) * lcp_bytes(cls, m, nb, 4) + (it64 + 1) * lcp_bytes(cls, m, nb, 8)
                 else:
                     tot_bytes[cls] += (it + 1) * lcp_bytes(cls, m, nb, 8)
-            if args.precision == 32:
-                tot_bytes["lcp_rowgraph"] += rowgraph_bytes(m, e, 4, itlo) + rowgraph_bytes(m, e, 8, it64)
-            else:
-                tot_bytes["lcp_rowgraph"] += rowgraph_bytes(m, e, 8, it)
-            busy += int((itlo + 1 + it64 + 1) if args.precision == 32 else (it + 1))
+            # row graph: iteration passes per precision, start passes apart
+            for w, k in (((4, itlo), (8, it64)) if args.precision == 32 else ((8, it),)):
+                start = rowgraph_bytes(m, e, w, 0)
+                tot_bytes["lcp_rowgraph" if w == 4 else "lcp_rowgraph64"] += rowgraph_bytes(m, e, w, k) - start
+                tot_bytes["lcp_rowgraph_start"] += start
+            busy += int(itlo if args.precision == 32 else it)
     dom = max(tm, key=lambda k: tm[k][1])
     cnt, ms = tm[dom]
     if dom in tot_bytes:
@@ -331,9 +385,10 @@ def main():
         traffic = None
         if kernel_source_sha() == MEASURED_TRAFFIC["sha256_prefix"] and args.n == 100000 and args.precision == 32:
             traffic = MEASURED_TRAFFIC[dom]
-        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        roof = {"kernel": dom, "kernel_symbol": KERNEL_SYMBOLS.get(dom), "bound": "hbm", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "launches": int(cnt), "busy_launches": int(busy),
-                "avg_us": 1e3 * ms / max(busy, 1), "bytes_per_launch": tot_bytes[dom] / max(busy, 1)}
+                "avg_us": 1e3 * ms / max(cnt, 1), "bytes_per_launch": tot_bytes[dom] / max(cnt, 1)}
     else:
         roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": None, "traffic": None, "launches": cnt, "avg_us": 1e3 * ms / max(cnt, 1)}

@@ -170,7 +170,11 @@ RELCP_API int relcp_get_contacts(const relcp_ctx *ctx, int32_t *ia, int32_t *ib,
  * assembled over rows once per recursion, one pass per iteration, the
  * passes replayed in chunks from an instantiated HIP graph that reads the
  * solve's parameters from device memory; one launch per pass where graphs
- * are unavailable), 4 = row graph with one launch per pass. */
+ * are unavailable), 4 = row graph with one launch per pass.  In mode 4, a
+ * pass over at least RELCP_REDUCE_SPLIT_BLOCKS workgroups of 256 rows
+ * (environment, read when a context is created; default 1024) has the last
+ * pass's partial sums reduced by a separate one-workgroup launch instead of
+ * by each of its workgroups (the same iterates either way). */
 RELCP_API int relcp_set_lcp_config(relcp_ctx *ctx, int32_t mode, int32_t block, int32_t lds);
 
 /* Autotuner: times every LCP configuration (grid; resident x {256, 512,
@@ -190,10 +194,12 @@ RELCP_API int relcp_autotune(relcp_ctx *ctx, double dt, double lcp_tol, int32_t 
  * by a pair recorded on the stream around it.  Classes: 0 = LCP scatter pass (D gamma -> K), 1 = LCP gather
  * pass (D^T V, projection, step-size reductions), 2 = SNSD narrowphase,
  * 3 = candidate pairs, 4 = trial integration, 5 = resident LCP solve,
- * 6 = warm-start features and MLP inference, 7 = row-graph LCP pass,
- * 8 = row-graph assembly.  relcp_get_timing fills count[9] (launches) and
- * ms[9] (summed durations) since the last reset, and resets when
- * reset != 0. */
+ * 6 = warm-start features and MLP inference, 7 = row-graph LCP iteration
+ * pass in FP32, 8 = row-graph assembly, 9 = row-graph passes launched after
+ * the solve had finished (they return at once; LCP mode 4), 10 = row-graph
+ * iteration pass in FP64, 11 = row-graph start pass (either precision).
+ * relcp_get_timing fills count[12] (launches) and ms[12] (summed
+ * durations) since the last reset, and resets when reset != 0. */
 RELCP_API int relcp_set_timing(relcp_ctx *ctx, int32_t enable);
 RELCP_API int relcp_get_timing(relcp_ctx *ctx, int32_t *count, double *ms, int32_t reset);
 

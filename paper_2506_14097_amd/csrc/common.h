@@ -34,6 +34,19 @@ struct Error {
     } while (0)
 
 // ---------------------------------------------------------------------------
+// XCD-aware block order.  The dispatcher hands workgroup b of a launch to
+// XCD b % 8 (each XCD has its own L2); xcd_block maps it to a logical block
+// so that each XCD runs one contiguous range of the nb logical blocks, and
+// reads of nearby items (the rows a row couples to) hit that XCD's L2.
+// ---------------------------------------------------------------------------
+constexpr int kXcds = 8;
+__device__ inline int xcd_block(int b, int nb) {
+    const int x = b % kXcds, i = b / kXcds;
+    const int q = nb / kXcds, r = nb % kXcds;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// ---------------------------------------------------------------------------
 // kernel timing: when an event pair is armed, the next launch made through
 // launch_k takes it as the dispatch's own start and end timestamps (the
 // kernel's execution, without the host's enqueue time), then disarms it

@@ -130,7 +130,9 @@ void launch_rowgraph_fill(const RowGraphFill &a, hipStream_t s);
 // diagonal dA.  mode 0: start, gamma0 = max(0, gam0) (FP64 start rounded to
 // T), g at gamma0, and the control block C reset for a new solve; mode 1:
 // iteration with parity par, reading the previous pass's state (zin, gin)
-// and partials, writing (zout, gout) and its own partials pout.
+// and partials, writing (zout, gout) and its own partials pout; mode 2: the
+// same iteration with the partials reduced first by a one-block launch
+// (for passes over many blocks; identical iterates).
 template <typename T>
 void launch_lcp_spmv(int mode, const RowGraphT<T> &G, const T *qv, const T *dA, const double *gam0,
                      const RowStep<T> *zin, const T *gin, RowStep<T> *zout, T *gout, const PgdCtl &C, double *pout,

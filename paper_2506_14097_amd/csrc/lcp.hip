@@ -249,12 +249,25 @@ __device__ inline PgdState pgd_next(const PgdState &s, double ss, double sy, dou
 // the state; thread 0 of every block ends with the new state in `out`.
 __device__ inline void reduce_partials(const PgdCtl &C, int par, PgdState *out, double (*sh)[kWaves]) {
     double ss = 0.0, sy = 0.0, yy = 0.0, res = 0.0;
-    for (int k = threadIdx.x; k < C.nbg; k += kThreads) {
-        const double *p = C.partials + 4 * k;
-        ss += p[0];
-        sy += p[1];
-        yy += p[2];
-        res = fmax(res, p[3]);
+    // thread t adds partials t, t + kThreads, ... in that order; the loads of
+    // kU of them are issued before their adds
+    constexpr int kU = 8;
+    for (int k0 = threadIdx.x; k0 < C.nbg; k0 += kU * kThreads) {
+        double4 v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int k = k0 + u * kThreads;
+            v[u] = k < C.nbg ? *reinterpret_cast<const double4 *>(C.partials + 4 * k) : double4{0.0, 0.0, 0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (k0 + u * kThreads < C.nbg) {
+                ss += v[u].x;
+                sy += v[u].y;
+                yy += v[u].z;
+                res = fmax(res, v[u].w);
+            }
+        }
     }
     block_reduce4(ss, sy, yy, res, sh);
     if (threadIdx.x == 0) *out = pgd_next(C.S[par ^ 1], ss, sy, yy, res, C.tol);
@@ -540,6 +553,27 @@ __global__ void __launch_bounds__(kThreads) k_pgd_finalize(PgdCtl C, int par) {
     }
 }
 
+// The reduction of the last pass's partial sums into the new state, in one
+// block and in the order every block of an iteration pass uses (so the
+// iterates are the same either way), for passes over many blocks: there,
+// every block re-reading all partial sums would cost reads quadratic in the
+// block count.  Stops the solve (done) on convergence.
+__global__ void __launch_bounds__(kThreads) k_pgd_reduce(PgdCtl C, int par) {
+    __shared__ double sh[4][kWaves];
+    __shared__ PgdState ns;
+    if (*C.done) return;
+    reduce_partials(C, par, &ns, sh);
+    if (threadIdx.x == 0) {
+        C.S[par] = ns;
+        if (ns.conv) {
+            *C.fin = ns;
+            *C.done = 1;
+            if (C.fin_h) *C.fin_h = ns;
+            if (C.done_h) *C.done_h = 1;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // row-graph LCP: A = dt D^T K D assembled over rows, one pass per iteration
 // ---------------------------------------------------------------------------
@@ -749,13 +783,21 @@ __global__ void __launch_bounds__(kThreads)
            T *__restrict__ gout, PgdCtl C, double *__restrict__ pout, int par) {
     __shared__ double sh[4][kWaves];
     __shared__ PgdState ns;
-    if (MODE == 1 && *C.done) return;
+    constexpr int RM = MODE == 0 ? 0 : 1;  // row arithmetic: start or iteration
+    if (MODE != 0 && *C.done) return;
     if (MODE == 0 && blockIdx.x == 0 && threadIdx.x == 0) pgd_reset(C);
-    const int r = blockIdx.x * kThreads + threadIdx.x;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);  // logical block: a contiguous row range per XCD
+    const int r = lb * kThreads + threadIdx.x;
     const bool act = r < G.m;
     RowPre<T> P;
-    if (act) row_preload<T, MODE>(G, qv, dA0, gam0, zin, gin, r, P);
+    if (act) row_preload<T, RM>(G, qv, dA0, gam0, zin, gin, r, P);
     T al = T(0);
+    if (MODE == 2) {
+        // the state was advanced by k_pgd_reduce
+        if (threadIdx.x == 0) ns = C.S[par];
+        __syncthreads();
+        al = (T)ns.alpha;
+    }
     if (MODE == 1) {
         reduce_partials(C, par, &ns, sh);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -771,10 +813,10 @@ __global__ void __launch_bounds__(kThreads)
         al = (T)ns.alpha;
     }
     double ss = 0.0, sy = 0.0, yy = 0.0, res = 0.0;
-    if (act) row_finish<T, MODE>(P, al, zin, gam0, zout, gout, r, ss, sy, yy, res);
+    if (act) row_finish<T, RM>(P, al, zin, gam0, zout, gout, r, ss, sy, yy, res);
     block_reduce4(ss, sy, yy, res, sh);
     if (threadIdx.x == 0) {
-        double *p = pout + 4 * blockIdx.x;
+        double *p = pout + 4 * lb;
         p[0] = ss;
         p[1] = sy;
         p[2] = yy;
@@ -796,7 +838,8 @@ __global__ void __launch_bounds__(kThreads) k_spmv_dev(const LcpDev<T> *__restri
     const int nbg = d.nbg;
     if ((int)blockIdx.x >= nbg) return;
     const RowGraphT<T> G{d.m, d.base, d.col, d.val, d.slots};
-    const int r = blockIdx.x * kThreads + threadIdx.x;
+    const int lb = xcd_block(blockIdx.x, nbg);  // the same order as the per-pass launch over nbg blocks
+    const int r = lb * kThreads + threadIdx.x;
     const bool act = r < d.m;
     RowPre<T> P;
     if (act) row_preload<T, 1>(G, d.qv, d.dA, nullptr, d.z[par ^ 1], d.g[par ^ 1], r, P);
@@ -819,7 +862,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_dev(const LcpDev<T> *__restri
     if (act) row_finish<T, 1>(P, (T)ns.alpha, d.z[par ^ 1], nullptr, d.z[par], d.g[par], r, ss, sy, yy, res);
     block_reduce4(ss, sy, yy, res, sh);
     if (threadIdx.x == 0) {
-        double *p = d.part[par] + 4 * blockIdx.x;
+        double *p = d.part[par] + 4 * lb;
         p[0] = ss;
         p[1] = sy;
         p[2] = yy;
@@ -996,10 +1039,14 @@ void launch_lcp_spmv(int mode, const RowGraphT<T> &G, const T *qv, const T *dA, 
                      const RowStep<T> *zin, const T *gin, RowStep<T> *zout, T *gout, const PgdCtl &C, double *pout,
                      int par, hipStream_t s) {
     const int nb = nblk(G.m > 0 ? G.m : 1, kThreads);
-    if (mode == 0)
+    if (mode == 0) {
         launch_k(k_spmv<T, 0>, dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C,
                            pout, par);
-    else
+    } else if (mode == 2) {
+        hipLaunchKernelGGL(k_pgd_reduce, dim3(1), dim3(kThreads), 0, s, C, par);
+        launch_k(k_spmv<T, 2>, dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C, pout,
+                 par);
+    } else
         launch_k(k_spmv<T, 1>, dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C,
                            pout, par);
 }

@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "../../include/relcp.h"
@@ -73,6 +74,14 @@ __global__ void k_scale(int n, double *__restrict__ x, int nbox, double *__restr
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] *= s;
     if (i < nbox) box[i] *= s;
+}
+
+int env_int(const char *name, int dflt) {
+    const char *v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    char *end = nullptr;
+    const long x = std::strtol(v, &end, 10);
+    return (end && *end == 0 && x > 0 && x < (1L << 30)) ? (int)x : dflt;
 }
 
 struct Timer {
@@ -206,10 +215,12 @@ struct relcp_ctx {
     DBuf<unsigned long long> red;  // per-block trial results: displacement bits, then min-Phi and margin keys
     DBuf<int> scan_scratch, dtotal;
     // optional kernel timing (HIP events on the stream)
-    static constexpr int kClasses = 9;
+    static constexpr int kClasses = 12;
+    static constexpr int kIdlePass = 9;  // row-graph passes launched after the solve had finished
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_class;
+    std::vector<std::pair<size_t, int>> pass_ev;  // (event pair, pass) of the current row-graph solve
     size_t ev_used = 0;
     long long t_count[kClasses] = {};
     double t_ms[kClasses] = {};
@@ -291,6 +302,9 @@ struct relcp_ctx {
     // row-graph passes replayed from an instantiated graph (per precision):
     // parameters in device memory, grid covering graph_rows rows
     static constexpr int kGraphPasses = 8;
+    // iteration passes over at least this many blocks reduce the last pass's
+    // partial sums in a separate one-block launch (RELCP_REDUCE_SPLIT_BLOCKS)
+    int reduce_split_blocks = env_int("RELCP_REDUCE_SPLIT_BLOCKS", 1024);
     DBuf<LcpDev<double>> lcpdev64;
     DBuf<LcpDev<float>> lcpdev32;
     hipGraphExec_t spmv_graph[2] = {nullptr, nullptr};
@@ -1014,6 +1028,7 @@ int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt
     };
     int *const conv_h = reinterpret_cast<int *>(pst_h + 1);
     bool seen = false;  // pst_h holds the final state
+    pass_ev.clear();
     for (int attempt = 0;; ++attempt) {
         bool fresh = false;
         if (!rg_valid || rg_dt != dt) {
@@ -1041,26 +1056,30 @@ int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt
             }
         }
         // the start pass also resets the control block
-        timed(7, [&] {
+        timed(11, [&] {
             launch_lcp_spmv<T>(0, G, R.qv, R.dA, rgam64.p, nullptr, nullptr, z0, g0, C, partials.p, 0, stream);
         });
         int j = 1;
         int chunk = std::max(2, std::min(64, (last_iters[pk] + 3) & ~1));
         bool first = true;
         seen = false;
+        // over many blocks the partial sums are reduced once per pass by a
+        // separate launch instead of by every block
+        const int pass_mode = C.nbg >= reduce_split_blocks ? 2 : 1;
         for (;;) {
             if (ge) {
                 // whole graphs; the passes past the end of the solve return at once
                 const int ng = (chunk + kGraphPasses - 1) / kGraphPasses;
                 for (int t = 0; t < ng; ++t, j += kGraphPasses)
-                    timed_span(7, [&] { HIP_OK(hipGraphLaunch(ge, stream)); });
+                    timed_span(sizeof(T) == 4 ? 7 : 10, [&] { HIP_OK(hipGraphLaunch(ge, stream)); });
             } else {
                 const int k = std::min(chunk, cap - (j - 1));
                 if (k <= 0) break;
                 for (int t = 0; t < k; ++t, ++j) {
                     const int par = j & 1;
-                    timed(7, [&] {
-                        launch_lcp_spmv<T>(1, G, R.qv, R.dA, nullptr, par ? z0 : z1, par ? g0 : g1, par ? z1 : z0,
+                    if (timing) pass_ev.emplace_back(ev_used / 2, j);
+                    timed(sizeof(T) == 4 ? 7 : 10, [&] {
+                        launch_lcp_spmv<T>(pass_mode, G, R.qv, R.dA, nullptr, par ? z0 : z1, par ? g0 : g1, par ? z1 : z0,
                                            par ? g1 : g0, ctl(par), partials.p + (size_t)par * stride, par, stream);
                     });
                 }
@@ -1106,6 +1125,11 @@ int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt
     iters = pst_h[0].iter;
     res = pst_h[0].res;
     last_iters[pk] = iters;
+    // passes past the last iteration only reduced (or returned at once):
+    // timed apart from the iteration passes
+    for (const auto &pe : pass_ev)
+        if (pe.second > iters && pe.first < ev_class.size()) ev_class[pe.first] = kIdlePass;
+    pass_ev.clear();
     if (!std::isfinite(res)) return RELCP_E_NAN;
     if (lcp_fixed > 0) return RELCP_OK;
     return conv ? RELCP_OK : RELCP_E_LCP_MAXITER;

@@ -5,9 +5,9 @@
 // larger one takes two passes over tiles of 2048 items (256 threads x 8
 // items): the tile totals, then the tile scans, each block adding the sum of
 // the totals of the tiles before its own (it sums them itself while there are
-// at most kDirect tiles; past that the totals are scanned first, by the same
-// routine).  Within a tile: wave scans through cross-lane shuffles, wave
-// totals through LDS.  Every sum is over integers, so the order does not
+// at most kDirect tiles, 16 loads per thread; past that the totals are
+// scanned first, by the same routine).  Within a tile: wave scans through
+// cross-lane shuffles, wave totals through LDS.  Every sum is over integers, so the order does not
 // change the result.
 #include "common.h"
 
@@ -20,7 +20,7 @@ constexpr int kItems = 8;
 constexpr int kTile = kThreads * kItems;
 constexpr int kSmallThreads = 1024;
 constexpr int kSmall = kSmallThreads * kItems;
-constexpr int kDirect = 1024;  // tiles whose offsets a block sums by itself
+constexpr int kDirect = 4096;  // tiles (groups) whose offsets a block sums by itself
 
 __device__ inline int wave_incl_scan(int v) {
     const int lane = threadIdx.x & (RELCP_WAVE - 1);

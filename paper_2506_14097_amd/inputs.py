@@ -176,3 +176,43 @@ def batch_of_packings(seed: int, count: int, n_lo: int, n_hi: int, phi_lo: float
                 kind=np.concatenate([p["kind"] for p in parts]), shape=np.concatenate([p["shape"] for p in parts]),
                 rho_xi=np.concatenate([p["rho_xi"] for p in parts]), box=np.stack([p["box"] for p in parts]),
                 batch_off=off, phi=np.array([p["phi"] for p in parts]), phi_target=phis)
+
+
+def lattice_lcp(seed: int, m_target: int, bonds_per_body: float = 1.3) -> dict:
+    """A contact-shaped LCP of about m_target rows for timing the LCP loop
+    alone at many sizes: bodies on a cubic lattice (index x-fastest, so
+    lattice neighbours are 1, s and s^2 apart), each +x, +y, +z bond present
+    with the probability that gives bonds_per_body rows per body (1.3 is the
+    compaction at volume fraction 0.40), rows sorted by (a, b) as the step
+    generates them; unit normals and lever arms of scale 0.5, K with
+    k_t in [0.5, 1] and diagonal K_r in [0.5, 1], qv ~ N(0, 0.01).  Returns
+    n, ia, ib, n (m x 3), ta, tb (m x 3), kt (n), Kr6 (6 x n: xx yy zz xy xz
+    yz), qv (m) and E = sum over rows of the rows at their two bodies (the
+    stored entries of A over rows)."""
+    rng = rng_for(seed)
+    n = int(m_target / bonds_per_body)
+    s = max(2, int(round(n ** (1.0 / 3.0))))
+    n = s ** 3
+    idx = np.arange(n)
+    x, y, z = idx % s, (idx // s) % s, idx // (s * s)
+    p = bonds_per_body / 3.0
+    A, B = [], []
+    for d, ok in ((1, x < s - 1), (s, y < s - 1), (s * s, z < s - 1)):
+        pick = ok & (rng.random(n) < p)
+        A.append(idx[pick])
+        B.append(idx[pick] + d)
+    ia = np.concatenate(A)
+    ib = np.concatenate(B)
+    o = np.lexsort((ib, ia))
+    ia, ib = ia[o].astype(np.int32), ib[o].astype(np.int32)
+    m = ia.size
+    nrm = rng.normal(size=(m, 3))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    ta = np.cross(rng.normal(size=(m, 3)) * 0.5, nrm)
+    tb = np.cross(rng.normal(size=(m, 3)) * 0.5, nrm)
+    kt = rng.uniform(0.5, 1.0, n)
+    Kr6 = np.concatenate([rng.uniform(0.5, 1.0, (3, n)), np.zeros((3, n))], 0)
+    qv = rng.normal(size=m) * 0.01
+    deg = np.bincount(ia, minlength=n) + np.bincount(ib, minlength=n)
+    E = int((deg[ia] + deg[ib]).sum())
+    return dict(n=n, ia=ia, ib=ib, nrm=nrm, ta=ta, tb=tb, kt=kt, Kr6=Kr6, qv=qv, E=E)

@@ -238,7 +238,8 @@ class Simulation:
             raise RelcpError(rc, self._err())
 
     TIMING_CLASSES = ("lcp_scatter", "lcp_gather", "snsd", "pairs", "trial", "lcp_resident", "warm_start",
-                      "lcp_rowgraph", "rowgraph_build")
+                      "lcp_rowgraph", "rowgraph_build", "lcp_rowgraph_idle", "lcp_rowgraph64",
+                      "lcp_rowgraph_start")
     LCP_CONFIGS = ("grid", "resident-256", "resident-256-lds", "resident-512", "resident-512-lds",
                    "resident-1024", "resident-1024-lds", "rowgraph", "rowgraph-perpass")
 

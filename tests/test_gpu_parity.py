@@ -10,6 +10,8 @@ Bars ("parity"):
  * contact sets per recursion: identical (pair, recursion) lists unless the
    oracle reports a pair within 1e-9 of the overlap threshold (flagged).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -422,7 +424,8 @@ def test_candidate_list_kept_across_steps(dev, mode):
 def test_rowgraph_graph_replay_matches_per_pass_launches(dev, precision):
     """Passes replayed from the instantiated graph (parameters read from
     device memory, a grid with spare blocks, passes past the end of the solve
-    returning at once) and one launch per pass run the same iteration: on a
+    returning at once), one launch per pass, and one launch per pass after a
+    separate reduction of the partial sums run the same iteration: on a
     40,000-row system the same iteration count and the same multipliers bit
     for bit, converged and after a capped run of 7 iterations."""
     n, m = 8000, 40000
@@ -432,18 +435,27 @@ def test_rowgraph_graph_replay_matches_per_pass_launches(dev, precision):
             tens(qv, dev, torch.float64), tens(kt, dev, torch.float64), tens(Kr6, dev, torch.float64), 0.05)
     tol = 1e-10 if precision == 64 else 1e-5
     out = {}
-    for mode in (3, 4):
-        g = torch.zeros(m, dtype=torch.float64, device=dev)
-        it, res, rc = R.lcp_solve_device(*args, g, precision=precision, mode=mode, tol=tol)
-        print("mode", mode, "iters", it, "res", res, flush=True)
-        assert rc == 0 and res <= tol
-        out[mode] = (it, g.cpu().numpy())
-        gf = torch.zeros(m, dtype=torch.float64, device=dev)
-        it, res, rc = R.lcp_solve_device(*args, gf, precision=precision, mode=mode, tol=tol, max_iters=7)
-        out[(mode, "capped")] = (it, rc, gf.cpu().numpy())
-    assert out[3][0] == out[4][0]
-    assert np.array_equal(out[3][1], out[4][1])
-    a, b = out[(3, "capped")], out[(4, "capped")]
-    # FP32 runs its capped iterations, then the capped FP64 polish: 2 x 7
-    assert a[0] == b[0] == (7 if precision == 64 else 14) and a[1] == b[1]
-    assert np.array_equal(a[2], b[2])
+    # "split": per-pass launches with the partial sums reduced by a separate
+    # launch before every pass (forced at this size; the default above 1024
+    # blocks)
+    for mode, split in ((3, None), (4, None), (4, "1")):
+        if split:
+            os.environ["RELCP_REDUCE_SPLIT_BLOCKS"] = split
+        try:
+            g = torch.zeros(m, dtype=torch.float64, device=dev)
+            it, res, rc = R.lcp_solve_device(*args, g, precision=precision, mode=mode, tol=tol)
+            print("mode", mode, "split", split, "iters", it, "res", res, flush=True)
+            assert rc == 0 and res <= tol
+            out[(mode, split)] = (it, g.cpu().numpy())
+            gf = torch.zeros(m, dtype=torch.float64, device=dev)
+            it, res, rc = R.lcp_solve_device(*args, gf, precision=precision, mode=mode, tol=tol, max_iters=7)
+            out[(mode, split, "capped")] = (it, rc, gf.cpu().numpy())
+        finally:
+            os.environ.pop("RELCP_REDUCE_SPLIT_BLOCKS", None)
+    for other in ((4, None), (4, "1")):
+        assert out[(3, None)][0] == out[other][0]
+        assert np.array_equal(out[(3, None)][1], out[other][1])
+        a, b = out[(3, None, "capped")], out[other + ("capped",)]
+        # FP32 runs its capped iterations, then the capped FP64 polish: 2 x 7
+        assert a[0] == b[0] == (7 if precision == 64 else 14) and a[1] == b[1]
+        assert np.array_equal(a[2], b[2])

@@ -2,9 +2,9 @@
 selection of A_0 and of each augmentation, incidence offsets, cell lists,
 row-graph slice bases), through the C ABI, against numpy.  Integer work:
 bit-exact.  Sizes cover each path: empty, one block (up to 8192 items), two
-passes with offsets summed per block (up to 1024 tiles of 2048), and past
+passes with offsets summed per block (up to 4096 tiles of 2048), and past
 that with the tile totals scanned first; compaction with the group offsets
-summed per block (up to 1024 groups of 256) and scanned first."""
+summed per block (up to 4096 groups of 256) and scanned first."""
 import numpy as np
 import pytest
 
@@ -22,7 +22,7 @@ def dev():
     return torch.device("cuda:0")
 
 
-SCAN_SIZES = [0, 1, 2, 255, 2047, 2048, 2049, 8191, 8192, 8193, 300_001, 2048 * 1024, 2048 * 1024 + 1, 5_000_003]
+SCAN_SIZES = [0, 1, 2, 255, 2047, 2048, 2049, 8191, 8192, 8193, 300_001, 2048 * 4096, 2048 * 4096 + 1, 9_000_003]
 
 
 @pytest.mark.parametrize("n", SCAN_SIZES)
@@ -46,7 +46,7 @@ def test_exclusive_scan_in_place(dev):
     assert np.array_equal(t.cpu().numpy(), np.concatenate([[0], np.cumsum(x)[:-1]]).astype(np.int32))
 
 
-COMPACT_SIZES = [0, 1, 255, 256, 257, 2048, 2049, 262_144, 262_145, 300_000, 3_000_001]
+COMPACT_SIZES = [0, 1, 255, 256, 257, 2048, 2049, 300_000, 1_048_576, 1_048_577, 3_000_001]
 
 
 @pytest.mark.parametrize("n", COMPACT_SIZES)
