@@ -31,11 +31,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
-# HBM bytes per non-empty launch of the LCP passes at this workload, from two
-# rocprofv3 --pmc runs (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, the scales a plain
-# copy of known size reads), recorded in profiles/lcp_passes_100k_hbm_traffic.md
-# for the kernel source with the given sha256 prefix (stale once it changes).
-MEASURED_TRAFFIC = {"sha256_prefix": "05a6215d8c110f99", "lcp_scatter": 2.4678e7, "lcp_gather": 1.7280e7}
+# HBM bytes per iterating launch of the FP32 row-graph pass at this workload,
+# from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, the scales
+# a plain copy of known size reads), recorded in
+# profiles/lcp_rowgraph_pass_100k_hbm_traffic.md for the kernel source with
+# the given sha256 prefix (stale once it changes).
+MEASURED_TRAFFIC = {"sha256_prefix": "dd80cd2ad7db1bfc", "lcp_rowgraph": 1.6258e7}
 
 
 # timing class -> kernel
@@ -384,7 +385,7 @@ def main():
         achieved = tot_bytes[dom] / (ms * 1e-3) / 1e9
         traffic = None
         if kernel_source_sha() == MEASURED_TRAFFIC["sha256_prefix"] and args.n == 100000 and args.precision == 32:
-            traffic = MEASURED_TRAFFIC[dom]
+            traffic = MEASURED_TRAFFIC.get(dom)
         roof = {"kernel": dom, "kernel_symbol": KERNEL_SYMBOLS.get(dom), "bound": "hbm", "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "launches": int(cnt), "busy_launches": int(busy),
