@@ -81,11 +81,14 @@ def rowgraph_bytes(m, e, w, iters):
 
 def learned_comparison(args, state):
     """Learned against previous-step warm start on the same workload.  The
-    model is trained on the GPU (library kernels) on about a million rows of
-    A_0 logged from a 10,000-ellipsoid compaction (seed 1) at volume
-    fractions 0.40 to 0.55; then two contexts start from the benchmark's
-    state, take three previous-step warm-up steps and `learned_steps` timed
-    steps each, one per warm start."""
+    model is trained on the GPU (library kernels) on rows of A_0 logged from
+    a 10,000-ellipsoid compaction (seed 1) at volume fractions 0.40 to 0.60;
+    then, at the benchmark's state (0.40) and after compressing it further to
+    0.60, two contexts start from the same state, take three previous-step
+    warm-up steps and `learned_steps` timed steps each, one per warm start.
+    Reported per level: PGD iterations per step, wall ms per step, the
+    host-clock LCP time per step (time to the 1e-6 residual, inference
+    included) and the summed duration of the warm-start kernels."""
     import torch
     from paper_2506_14097_amd import learned as L
     from paper_2506_14097_amd import relcp as R
@@ -94,7 +97,7 @@ def learned_comparison(args, state):
     C = Compaction(1, 10000, 0.40, dt=args.dt, eps=args.eps, tol=args.tol, precision=args.precision, skin=args.skin)
     C.sim.enable_contact_log(True)
     rows = L.ContactLog()
-    for level in (0.40, 0.45, 0.50, 0.55):
+    for level in (0.40, 0.45, 0.50, 0.55, 0.60):
         C.compress_to(level)
         C.steps(5, args.dphi)
         C.steps(15, args.dphi, on_step=lambda s, r: rows.record(s))
@@ -110,23 +113,37 @@ def learned_comparison(args, state):
     log("learned warm start: %d training rows, loss %.2e -> %.2e, %.1fs training (%.1fs with logging)" %
         (feat.shape[0], hist[0], hist[-1], t_train, time.time() - t0))
     out = {"training_rows": int(feat.shape[0]), "epochs": 20, "train_s": t_train,
-           "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
-    for name, mode in (("plain", R.WS_PREV), ("learned", R.WS_LEARNED)):
-        D = Compaction(None, None, None, state=state, dt=args.dt, eps=args.eps, tol=args.tol,
-                       precision=args.precision, skin=args.skin)
-        D.sim.set_warmstart_model(W, norm)
-        D.steps(3, args.dphi)
-        D.sim.set_warm_start(mode)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        st = D.steps(args.learned_steps, args.dphi)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t
-        out[name] = {"pgd_iters_per_step": float(np.mean([s["lcp_iters_total"] for s in st])),
-                     "ms_per_step": 1e3 * el / args.learned_steps,
-                     "lcp_ms_per_step": float(np.mean([s["t_lcp"] for s in st]))}
-        log("  %s: %s" % (name, out[name]))
-        D.sim.close()
+           "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1], "levels": {}}
+    B = Compaction(None, None, None, state=state, dt=args.dt, eps=args.eps, tol=args.tol, precision=args.precision,
+                   skin=args.skin)
+    for level in (0.40, 0.60):
+        B.compress_to(max(level, B.phi))
+        st0 = B.state()
+        res = {"volume_fraction": B.phi}
+        for name, mode in (("plain", R.WS_PREV), ("learned", R.WS_LEARNED)):
+            D = Compaction(None, None, None, state=st0, dt=args.dt, eps=args.eps, tol=args.tol,
+                           precision=args.precision, skin=args.skin)
+            D.sim.set_warmstart_model(W, norm)
+            D.steps(3, args.dphi)
+            D.sim.set_warm_start(mode)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = D.steps(args.learned_steps, args.dphi)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            D.sim.set_timing(True)
+            D.sim.get_timing(reset=True)
+            D.steps(3, args.dphi)
+            tm = D.sim.get_timing(reset=True)
+            res[name] = {"pgd_iters_per_step": float(np.mean([s["lcp_iters_total"] for s in st])),
+                         "ms_per_step": 1e3 * el / args.learned_steps,
+                         "lcp_ms_per_step": float(np.mean([s["t_lcp"] for s in st])),
+                         "warm_start_kernel_ms_per_step": tm["warm_start"][1] / 3.0,
+                         "contacts": int(st[-1]["n_contacts_final"])}
+            log("  phi %.3f %s: %s" % (B.phi, name, res[name]))
+            D.sim.close()
+        out["levels"]["%.2f" % level] = res
+    B.sim.close()
     return out
 
 
@@ -298,7 +315,7 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start comparison")
-    ap.add_argument("--learned-steps", type=int, default=20)
+    ap.add_argument("--learned-steps", type=int, default=50)
     ap.add_argument("--workload", default="compaction100k", choices=("compaction100k", "packings512", "lcp-sweep"))
     ap.add_argument("--sweep-rows", default="25000,100000,400000,1600000,6400000",
                     help="lcp-sweep: target row counts of the lattice LCPs")
@@ -416,7 +433,8 @@ def main():
                                "warm start" % (args.n, args.phi0, C.phi, args.dphi, args.dt, args.eps, args.tol),
                    "bodies": args.n, "precision": args.precision, "skin": args.skin, "lcp_mode": args.lcp_mode},
         "pgd_iters_per_step": {"plain": float(np.mean(pgd)),
-                               "learned": learned["learned"]["pgd_iters_per_step"] if learned else None},
+                               "learned": learned["levels"]["0.40"]["learned"]["pgd_iters_per_step"]
+                               if learned else None},
         "learned_warm_start": learned,
         "contact_iters_per_s": citers / elapsed,
         "host_waits_per_step": {"n": float(np.mean([s["n_waits"] for s in stats])),
