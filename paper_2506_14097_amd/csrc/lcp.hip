@@ -501,10 +501,23 @@ __global__ void __launch_bounds__(BS) k_lcp_resident(RowsT<T> R, BodiesT<T> B, c
 }
 
 // rows grouped by packing: count the rows of each packing in [m0, m1)
+// Rows per packing.  Rows arrive grouped by packing, so the lanes of a wave
+// mostly share one counter: each round, the lanes holding the packing of the
+// lowest pending lane add their count in one atomic (usually one or two
+// rounds per wave instead of 64 contended atomics).
 __global__ void k_rows_per_packing(int m0, int m1, const int *__restrict__ ia, const int *__restrict__ body_batch,
                                    int *__restrict__ cnt) {
-    int r = m0 + blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < m1) atomicAdd(cnt + body_batch[ia[r]], 1);
+    const int r = m0 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (RELCP_WAVE - 1);
+    const int p = r < m1 ? body_batch[ia[r]] : -1;
+    unsigned long long pending = __ballot(p >= 0);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int key = __shfl(p, leader, RELCP_WAVE);
+        const unsigned long long same = __ballot(p == key) & pending;
+        if (lane == leader) atomicAdd(cnt + key, __popcll(same));
+        pending &= ~same;
+    }
 }
 
 // New row list after appending rows [m_old, m_old + nv) (themselves grouped
@@ -646,6 +659,14 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_fill(RowGraphFill A) {
         A.report[2] = 1;
         return;
     }
+    // the output does not alias the inputs: the gathers of several entries
+    // can be in flight before their stores
+    const double *__restrict__ jb = A.jb;
+    const int *__restrict__ ent = A.ent;
+    int *__restrict__ col = A.col;
+    double *__restrict__ v64 = A.val64;
+    float *__restrict__ v32 = A.val32;
+    constexpr int kU = 4;
     int k = 0;
     for (int side = 0; side < 2; ++side) {
         const int c = side ? A.ib[r] : A.ia[r];
@@ -657,20 +678,37 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_fill(RowGraphFill A) {
         const d3 Kn = mk(sr * K[c] * nr.x, sr * K[lb + c] * nr.y, sr * K[2 * lb + c] * nr.z);
         const sym3 Kr{K[3 * lb + c], K[4 * lb + c], K[5 * lb + c], K[6 * lb + c], K[7 * lb + c], K[8 * lb + c]};
         const d3 Ku = sr * mul(Kr, ur);
-        for (int e = A.off[c]; e < A.off[c + 1]; ++e, ++k) {
-            const double *J = A.jb + 6 * (size_t)e;
-            const double v = A.dt * (J[0] * Kn.x + J[1] * Kn.y + J[2] * Kn.z + J[3] * Ku.x + J[4] * Ku.y + J[5] * Ku.z);
-            const size_t at = (size_t)RELCP_WAVE * (b0 + k) + lane;
-            A.col[at] = A.ent[e] >> 1;
-            A.val64[at] = v;
-            A.val32[at] = (float)v;
+        const int e1 = A.off[c + 1];
+        for (int e = A.off[c]; e < e1; e += kU) {
+            double J[kU][6];
+            int cj[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int eu = e + u < e1 ? e + u : e;
+                const double *Jp = jb + 6 * (size_t)eu;
+#pragma unroll
+                for (int t = 0; t < 6; ++t) J[u][t] = Jp[t];
+                cj[u] = ent[eu] >> 1;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                if (e + u < e1) {
+                    const double v = A.dt * (J[u][0] * Kn.x + J[u][1] * Kn.y + J[u][2] * Kn.z + J[u][3] * Ku.x +
+                                             J[u][4] * Ku.y + J[u][5] * Ku.z);
+                    const size_t at = (size_t)RELCP_WAVE * (b0 + k + u) + lane;
+                    col[at] = cj[u];
+                    v64[at] = v;
+                    v32[at] = (float)v;
+                }
+            }
+            k += min(kU, e1 - e);
         }
     }
     for (; k < w; ++k) {
         const size_t at = (size_t)RELCP_WAVE * (b0 + k) + lane;
-        A.col[at] = r;
-        A.val64[at] = 0.0;
-        A.val32[at] = 0.0f;
+        col[at] = r;
+        v64[at] = 0.0;
+        v32[at] = 0.0f;
     }
 }
 

@@ -316,6 +316,7 @@ struct relcp_ctx {
     int rg_entries = 0;    // entries of the current graph (known after the solve's first read-back)
     bool rowgraph_mode() const { return !resident_mode() && lcp_mode != 1; }
     void build_rowgraph(double dt);
+    void rg_reserve(size_t slots);
     int maxpk = 0;                       // bodies of the largest packing
     DBuf<int> boff_d, roff, rlist, rlist2, rcnt, rE;
     DBuf<PgdState> pk_state;
@@ -839,6 +840,20 @@ void relcp_ctx::warm_start_rows(int m0, double dt) {
     }
 }
 
+// Entry slots of the row graph: at least `slots` in every array.  Buffers
+// are replaced only when too small, with half again as much headroom (a
+// growing contact set would otherwise free and re-allocate, and so wait on
+// the device, at every step); rg_cap is what all three actually hold.
+void relcp_ctx::rg_reserve(size_t slots) {
+    if (rg_col.cap < slots || rg_val64.cap < slots || rg_val32.cap < slots) {
+        rg_col.release(); rg_val64.release(); rg_val32.release();
+        rg_col.ensure(slots + slots / 2);
+        rg_val64.ensure(slots + slots / 2);
+        rg_val32.ensure(slots + slots / 2);
+    }
+    rg_cap = std::min(rg_col.cap, std::min(rg_val64.cap, rg_val32.cap));
+}
+
 // Row graph of the current rows: slice widths and their scan, the columns of
 // D in incidence order, then the entries.  Nothing is read back here: the
 // entry slots are sized from an estimate (twice the current need seen so
@@ -853,14 +868,7 @@ void relcp_ctx::build_rowgraph(double dt) {
         HIP_OK(hipMemsetAsync(rg_flags.p, 0, sizeof(int), stream));  // entry counter, cleared by each fill
     }
     rg_jb.ensure(12 * (size_t)std::max(m, 1));
-    const size_t want = std::max<size_t>((size_t)RELCP_WAVE * ns * 16, 64);
-    if (rg_cap < want) {
-        rg_cap = std::max(want, rg_cap);
-        rg_col.release(); rg_val64.release(); rg_val32.release();
-        rg_col.ensure(rg_cap);
-        rg_val64.ensure(rg_cap);
-        rg_val32.ensure(rg_cap);
-    }
+    rg_reserve(std::max<size_t>((size_t)RELCP_WAVE * ns * 16, 64));
     int_h[4] = int_h[5] = int_h[6] = 0;  // slots / 64, entries, overflow (written by the fill)
     timed(8, [&] { launch_rowgraph_width(m, ria.p, rib.p, csr_off.p, rg_width.p, rg_flags.p, stream); });
     exclusive_scan(rg_width.p, rg_base.p, ns + 1, nullptr, scan_scratch, stream);
@@ -1060,7 +1068,11 @@ int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt
             launch_lcp_spmv<T>(0, G, R.qv, R.dA, rgam64.p, nullptr, nullptr, z0, g0, C, partials.p, 0, stream);
         });
         int j = 1;
+        // passes of the first chunk: the last solve's iterations plus the pass
+        // that sees convergence and a spare (even for the graph's chunks; a
+        // polish that last converged at its start needs one pass)
         int chunk = std::max(2, std::min(64, (last_iters[pk] + 3) & ~1));
+        if (!(lcp_mode == 3 && graph_ok) && last_iters[pk] == 0) chunk = 1;
         bool first = true;
         seen = false;
         // over many blocks the partial sums are reduced once per pass by a
@@ -1101,11 +1113,7 @@ int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt
         if (fresh && (int_h[6] || (size_t)RELCP_WAVE * int_h[4] > rg_cap)) {
             // the entry slots did not suffice: re-size to twice the need and start over
             if (attempt > 0) throw Error{RELCP_E_DEVICE, "row graph sizing failed"};
-            rg_cap = 2 * (size_t)RELCP_WAVE * int_h[4];
-            rg_col.release(); rg_val64.release(); rg_val32.release();
-            rg_col.ensure(rg_cap);
-            rg_val64.ensure(rg_cap);
-            rg_val32.ensure(rg_cap);
+            rg_reserve(2 * (size_t)RELCP_WAVE * int_h[4]);
             rg_valid = false;
             continue;
         }
