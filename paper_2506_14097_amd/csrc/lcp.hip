@@ -171,15 +171,26 @@ __device__ inline double wave_max(double v) {
     for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, RELCP_WAVE));
     return v;
 }
+// three sums and a max over the wave: the same butterflies as wave_sum and
+// wave_max (so the same results), with the four exchanges of each round
+// issued together instead of four dependent chains one after another
+__device__ inline void wave_reduce4(double &a, double &b, double &c, double &mx) {
+#pragma unroll
+    for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) {
+        const double ta = __shfl_xor(a, o, RELCP_WAVE), tb = __shfl_xor(b, o, RELCP_WAVE);
+        const double tc = __shfl_xor(c, o, RELCP_WAVE), tm = __shfl_xor(mx, o, RELCP_WAVE);
+        a += ta;
+        b += tb;
+        c += tc;
+        mx = fmax(mx, tm);
+    }
+}
 
 // Block reduction of 3 sums and 1 max in a fixed order over NW waves; the
 // result is valid in thread 0.
 template <int NW>
 __device__ inline void block_reduce4n(double &a, double &b, double &c, double &mx, double (*sh)[NW]) {
-    a = wave_sum(a);
-    b = wave_sum(b);
-    c = wave_sum(c);
-    mx = wave_max(mx);
+    wave_reduce4(a, b, c, mx);
     const int lane = threadIdx.x & (RELCP_WAVE - 1), w = threadIdx.x / RELCP_WAVE;
     if (lane == 0) {
         sh[0][w] = a;
@@ -202,10 +213,7 @@ __device__ inline void block_reduce4n(double &a, double &b, double &c, double &m
 }
 
 __device__ inline void block_reduce4(double &a, double &b, double &c, double &mx, double (*sh)[kWaves]) {
-    a = wave_sum(a);
-    b = wave_sum(b);
-    c = wave_sum(c);
-    mx = wave_max(mx);
+    wave_reduce4(a, b, c, mx);
     const int lane = threadIdx.x & (RELCP_WAVE - 1), w = threadIdx.x / RELCP_WAVE;
     if (lane == 0) {
         sh[0][w] = a;
