@@ -70,8 +70,8 @@ def lcp_bytes(kind, m, nb, w):
 
 def rowgraph_bytes(m, e, w, iters):
     """Algorithmic bytes of the row-graph passes of one solve: m rows, e
-    stored entries of A (padding excluded), word size w, iters iterations.
-    Every pass reads each entry's column (4 B) and value (w).  The start
+    stored off-diagonal entries of A (padding excluded), word size w, iters
+    iterations.  Every pass reads each entry's column (4 B) and value (w).  The start
     pass reads gamma0, qv, A_rr and writes the row state (gamma, h) and g
     (6w per row); an iteration pass reads the row's previous state (gamma,
     h), g, qv, A_rr and writes the new state and g (8w per row; the

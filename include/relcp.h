@@ -116,7 +116,7 @@ typedef struct {
     double max_overlap;          /* max over pairs of -Phi at the accepted configuration (>= 0) */
     double max_disp;             /* largest surface-point displacement bound of the accepted trial */
     double t_narrow, t_lcp, t_other; /* milliseconds (host clock, stream-synchronised) */
-    int32_t rowgraph_entries[RELCP_MAX_RECORDED]; /* entries of A over rows per recursion (row-graph LCP mode; 0 otherwise) */
+    int32_t rowgraph_entries[RELCP_MAX_RECORDED]; /* off-diagonal entries of A over rows per recursion (row-graph LCP mode; 0 otherwise) */
     int32_t pairs_rebuilt;       /* 1 if the candidate list was rebuilt at this step (it is kept while valid) */
     int32_t n_waits;             /* host waits on the stream during the step */
     double t_wait;               /* milliseconds of host clock spent in those waits */

@@ -435,7 +435,7 @@ __device__ inline unsigned long long order_key(double v) {
     return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
 }
 
-__global__ void __launch_bounds__(256) k_snsd_pairs(SnsdArgs A) {
+__global__ void __launch_bounds__(256, 4) k_snsd_pairs(SnsdArgs A) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     double phi = 1e300, marg = 1e300;
     int fl = 0;

@@ -77,9 +77,10 @@ struct PgdCtl {
     int *done_h;
 };
 
-// Row-graph form of the LCP matrix A = dt D^T K D: one entry per (row,
-// row) pair sharing a body and per shared body (a pair of rows sharing both
-// bodies has two entries; the diagonal is split into its two body parts).
+// Row-graph form of the LCP matrix A = dt D^T K D off its diagonal: one
+// entry per pair of distinct rows sharing a body and per shared body (two
+// rows sharing both bodies have two entries); the diagonal is the rows'
+// A_aa, applied by the pass itself.
 // Sliced ELL: slice s holds rows [64 s, 64 s + 64) with width w_s, entry k
 // of row r at 64 base[s] + 64 k + r % 64 (base = exclusive scan of the
 // widths); padding entries point at the row itself with value 0.
@@ -117,8 +118,8 @@ struct RowGraphFill {
 };
 
 int rowgraph_slices(int m);
-// width[s] = largest row degree (rows at body a + rows at body b) in slice s;
-// *count += the sum of the row degrees (the entries without padding)
+// width[s] = largest count of other rows at a row's two bodies in slice s;
+// *count += the sum of those counts (the entries without padding)
 void launch_rowgraph_width(int m, const int *ia, const int *ib, const int *off, int *width, int *count,
                            hipStream_t s);
 // jb[6 e ..] = s (n, tau) of the row of incidence entry e (s = -1, tau = r_a x n

@@ -605,7 +605,7 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_width(int m, const int *_
     int w = 0;
     if (r < m) {
         const int a = ia[r], b = ib[r];
-        w = off[a + 1] - off[a] + off[b + 1] - off[b];
+        w = off[a + 1] - off[a] + off[b + 1] - off[b] - 2;  // the row itself at a and at b: the diagonal
     }
     __shared__ int bsum[kWaves];
     int sum = w;
@@ -647,9 +647,10 @@ __global__ void __launch_bounds__(kThreads) k_incidence_jacobian(int m2, const i
     o[5] = s * t[2 * L + j];
 }
 
-// Entries of row r: for each of its bodies c (a, then b) and each row j at
-// c (incidence order), dt J_r^c . (K_c J_j^c) with J the column of D at c,
-// then padding entries (the row itself, value 0).
+// Entries of row r: for each of its bodies c (a, then b) and each other row
+// j at c (incidence order), dt J_r^c . (K_c J_j^c) with J the column of D at
+// c, then padding entries (the row itself, value 0).  The diagonal A_rr is
+// not stored: a pass takes it from the rows' A_aa.
 __global__ void __launch_bounds__(kThreads) k_rowgraph_fill(RowGraphFill A) {
     const int r = blockIdx.x * kThreads + threadIdx.x;
     if (r >= A.m) return;
@@ -700,16 +701,16 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_fill(RowGraphFill A) {
             }
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                if (e + u < e1) {
+                if (e + u < e1 && cj[u] != r) {
                     const double v = A.dt * (J[u][0] * Kn.x + J[u][1] * Kn.y + J[u][2] * Kn.z + J[u][3] * Ku.x +
                                              J[u][4] * Ku.y + J[u][5] * Ku.z);
-                    const size_t at = (size_t)RELCP_WAVE * (b0 + k + u) + lane;
+                    const size_t at = (size_t)RELCP_WAVE * (b0 + k) + lane;
                     col[at] = cj[u];
                     v64[at] = v;
                     v32[at] = (float)v;
+                    ++k;
                 }
             }
-            k += min(kU, e1 - e);
         }
     }
     for (; k < w; ++k) {
@@ -792,7 +793,9 @@ template <typename T, int MODE>
 __device__ inline void row_finish(const RowPre<T> &P, T al, const RowStep<T> *__restrict__ zin,
                                   const double *__restrict__ gam0, RowStep<T> *__restrict__ zout, T *__restrict__ gout,
                                   int r, double &ss, double &sy, double &yy, double &res) {
-    T acc = T(0);
+    // the diagonal first (A_rr, not stored in the graph), then the entries
+    const T gv = MODE == 1 ? step_h(P.gm, P.hm, al) : clamp0(P.gm);
+    T acc = P.dA * gv;
 #pragma unroll
     for (int k = 0; k < kPre; ++k) acc += P.vj[k] * (MODE == 1 ? step_h(P.gj[k], P.hj[k], al) : clamp0(P.gj[k]));
     for (int k = kPre; k < P.w; ++k) {
@@ -805,7 +808,6 @@ __device__ inline void row_finish(const RowPre<T> &P, T al, const RowStep<T> *__
             acc += v * clamp0((T)gam0[j]);
         }
     }
-    const T gv = MODE == 1 ? step_h(P.gm, P.hm, al) : clamp0(P.gm);
     const T gn = P.q + acc;
     zout[r] = RowStep<T>{gv, gn / P.dA};
     gout[r] = gn;

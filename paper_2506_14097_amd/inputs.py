@@ -187,8 +187,8 @@ def lattice_lcp(seed: int, m_target: int, bonds_per_body: float = 1.3) -> dict:
     generates them; unit normals and lever arms of scale 0.5, K with
     k_t in [0.5, 1] and diagonal K_r in [0.5, 1], qv ~ N(0, 0.01).  Returns
     n, ia, ib, n (m x 3), ta, tb (m x 3), kt (n), Kr6 (6 x n: xx yy zz xy xz
-    yz), qv (m) and E = sum over rows of the rows at their two bodies (the
-    stored entries of A over rows)."""
+    yz), qv (m) and E = sum over rows of the other rows at their two bodies
+    (the stored off-diagonal entries of A over rows)."""
     rng = rng_for(seed)
     n = int(m_target / bonds_per_body)
     s = max(2, int(round(n ** (1.0 / 3.0))))
@@ -214,5 +214,5 @@ def lattice_lcp(seed: int, m_target: int, bonds_per_body: float = 1.3) -> dict:
     Kr6 = np.concatenate([rng.uniform(0.5, 1.0, (3, n)), np.zeros((3, n))], 0)
     qv = rng.normal(size=m) * 0.01
     deg = np.bincount(ia, minlength=n) + np.bincount(ib, minlength=n)
-    E = int((deg[ia] + deg[ib]).sum())
+    E = int((deg[ia] + deg[ib] - 2).sum())
     return dict(n=n, ia=ia, ib=ib, nrm=nrm, ta=ta, tb=tb, kt=kt, Kr6=Kr6, qv=qv, E=E)
