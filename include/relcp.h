@@ -179,12 +179,13 @@ RELCP_API int relcp_set_lcp_config(relcp_ctx *ctx, int32_t mode, int32_t block, 
 
 /* Autotuner: times every LCP configuration (grid; resident x {256, 512,
  * 1024} x {global, LDS}; row graph; row graph per-pass launches) on the
- * rows of the last accepted step, from the same start, reps times each,
- * keeps the fastest for this context and writes it to config[3] = {mode,
- * block, lds} and the average milliseconds per configuration to ms[9] in
- * that order (either may be
- * NULL; a configuration that does not fit reports 0).  The multipliers of
- * the last step are restored. */
+ * rows of the last accepted step, each solve from gamma = 0 (the step's
+ * own multipliers already solve that LCP), once untimed and then reps
+ * times each; keeps the fastest for this context and writes it to
+ * config[3] = {mode, block, lds} and the average milliseconds per
+ * configuration to ms[9] in that order (either may be NULL; a
+ * configuration that does not fit reports 0).  The multipliers of the last
+ * step are restored. */
 RELCP_API int relcp_autotune(relcp_ctx *ctx, double dt, double lcp_tol, int32_t reps, int32_t *config, double *ms);
 
 /* Kernel timing with HIP events (off by default; one event pair per

@@ -132,19 +132,51 @@ __global__ void k_csr_count(int m, const int *__restrict__ ia, const int *__rest
     atomicAdd(cnt + ib[r], 1);
 }
 
-__global__ void k_csr_fill(int m, const int *__restrict__ ia, const int *__restrict__ ib, const int *__restrict__ off,
-                           int *__restrict__ cursor, int *__restrict__ ent) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= m) return;
-    int a = ia[r], b = ib[r];
-    ent[off[a] + atomicAdd(cursor + a, 1)] = r << 1;
-    ent[off[b] + atomicAdd(cursor + b, 1)] = (r << 1) | 1;
+// Incidence entries of each row at its two bodies.  With width set (the
+// row-graph layout), also the row-graph slice widths: the largest count of
+// other rows at a row's two bodies over each slice of 64 rows (the 64 lanes
+// of a wave: blocks start at multiples of 256 rows), and their sum into
+// *count.
+__global__ void __launch_bounds__(256) k_csr_fill(int m, const int *__restrict__ ia, const int *__restrict__ ib,
+                                                  const int *__restrict__ off, int *__restrict__ cursor,
+                                                  int *__restrict__ ent, int *__restrict__ width,
+                                                  int *__restrict__ count) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    int w = 0;
+    if (r < m) {
+        const int a = ia[r], b = ib[r];
+        ent[off[a] + atomicAdd(cursor + a, 1)] = r << 1;
+        ent[off[b] + atomicAdd(cursor + b, 1)] = (r << 1) | 1;
+        w = off[a + 1] - off[a] + off[b + 1] - off[b] - 2;  // the row itself at a and at b: the diagonal
+    }
+    if (!width) return;
+    __shared__ int bsum[4];
+    int sum = w;
+    for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) {
+        w = max(w, __shfl_xor(w, o, RELCP_WAVE));
+        sum += __shfl_xor(sum, o, RELCP_WAVE);
+    }
+    const int ns = (m + RELCP_WAVE - 1) / RELCP_WAVE;
+    const int lane = threadIdx.x & (RELCP_WAVE - 1), wv = threadIdx.x / RELCP_WAVE;
+    if (lane == 0) {
+        if (r / RELCP_WAVE < ns) width[r / RELCP_WAVE] = w;
+        bsum[wv] = sum;
+    }
+    if (r == 0) width[ns] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int t = bsum[0] + bsum[1] + bsum[2] + bsum[3];
+        if (t) atomicAdd(count, t);
+    }
 }
 
-// order each body's list by entry (row index) so summation order is fixed,
-// and clear the body's count and cursor for the next build
+// Order each body's list by entry (row index) so summation order is fixed,
+// and clear the body's count and cursor for the next build.  With jb set
+// (the row-graph layout), also the column of D at this body of each listed
+// row, in list order: s (n, r x n) with s = -1 at body a, +1 at body b.
 __global__ void k_csr_sort(int nb, const int *__restrict__ off, int *__restrict__ ent, int *__restrict__ cnt,
-                           int *__restrict__ cursor) {
+                           int *__restrict__ cursor, double *__restrict__ jb, const double *__restrict__ n,
+                           const double *__restrict__ ta, const double *__restrict__ tb, int L) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nb) return;
     cnt[i] = 0;
@@ -157,6 +189,19 @@ __global__ void k_csr_sort(int nb, const int *__restrict__ off, int *__restrict_
             --j;
         }
         ent[j + 1] = v;
+    }
+    if (!jb) return;
+    for (int e = lo; e < hi; ++e) {
+        const int en = ent[e], j = en >> 1;
+        const double sg = (en & 1) ? 1.0 : -1.0;
+        const double *t = (en & 1) ? tb : ta;
+        double *o = jb + 6 * (size_t)e;
+        o[0] = sg * n[j];
+        o[1] = sg * n[L + j];
+        o[2] = sg * n[2 * L + j];
+        o[3] = sg * t[j];
+        o[4] = sg * t[L + j];
+        o[5] = sg * t[2 * L + j];
     }
 }
 
@@ -979,15 +1024,18 @@ void launch_rows_build(const RowBuildArgs &a, hipStream_t s) {
 
 
 void launch_csr(int nb, int m, const int *ia, const int *ib, int *cnt, int *off, int *cursor, int *ent,
-                bool cleared, DBuf<int> &scan_scratch, hipStream_t s) {
+                bool cleared, DBuf<int> &scan_scratch, hipStream_t s, const CsrRowGraphOut *rg) {
     // cnt and cursor are adjacent (cursor = cnt + nb + 1): one clear, unless
     // the last build's sort pass left them at zero
     if (!cleared) HIP_OK(hipMemsetAsync(cnt, 0, sizeof(int) * 2 * (nb + 1), s));
     if (m > 0) hipLaunchKernelGGL(k_csr_count, dim3(nblk(m, 256)), dim3(256), 0, s, m, ia, ib, cnt);
     exclusive_scan(cnt, off, nb + 1, nullptr, scan_scratch, s);
     if (m > 0) {
-        hipLaunchKernelGGL(k_csr_fill, dim3(nblk(m, 256)), dim3(256), 0, s, m, ia, ib, off, cursor, ent);
-        hipLaunchKernelGGL(k_csr_sort, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, off, ent, cnt, cursor);
+        hipLaunchKernelGGL(k_csr_fill, dim3(nblk(m, 256)), dim3(256), 0, s, m, ia, ib, off, cursor, ent,
+                           rg ? rg->width : nullptr, rg ? rg->count : nullptr);
+        hipLaunchKernelGGL(k_csr_sort, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, off, ent, cnt, cursor,
+                           rg ? rg->jb : nullptr, rg ? rg->n : nullptr, rg ? rg->ta : nullptr,
+                           rg ? rg->tb : nullptr, rg ? rg->ldr : 0);
     }
 }
 

@@ -317,6 +317,8 @@ struct relcp_ctx {
     bool rowgraph_mode() const { return !resident_mode() && lcp_mode != 1; }
     void build_rowgraph(double dt);
     void rg_reserve(size_t slots);
+    void rg_prepare();
+    bool rg_pre = false;  // the incidence build made this graph's widths and columns of D
     int maxpk = 0;                       // bodies of the largest packing
     DBuf<int> boff_d, roff, rlist, rlist2, rcnt, rE;
     DBuf<PgdState> pk_state;
@@ -810,8 +812,19 @@ void relcp_ctx::rebuild_csr() {
     csr_ent.ensure(2 * (size_t)std::max(m, 1));
     const bool cleared = csr_clear == csr_cnt.p;
     csr_clear = nullptr;
+    // in the row-graph mode the same passes also produce the graph's slice
+    // widths and the columns of D in list order
+    CsrRowGraphOut rgo{};
+    // (a build whose graph was never assembled left its width sum in the
+    // entry counter: clear it)
+    if (rg_pre && rg_flags.p) HIP_OK(hipMemsetAsync(rg_flags.p, 0, sizeof(int), stream));
+    rg_pre = rowgraph_mode() && m > 0;
+    if (rg_pre) {
+        rg_prepare();
+        rgo = CsrRowGraphOut{rg_width.p, rg_flags.p, rg_jb.p, rn64.p, rta64.p, rtb64.p, ldr};
+    }
     launch_csr(n, m, ria.p, rib.p, csr_cnt.p, csr_off.p, csr_cnt.p + (n + 1), csr_ent.p, cleared, scan_scratch,
-               stream);
+               stream, rg_pre ? &rgo : nullptr);
     csr_clear = csr_cnt.p;  // the build's last pass clears the counters again
 }
 
@@ -859,7 +872,8 @@ void relcp_ctx::rg_reserve(size_t slots) {
 // entry slots are sized from an estimate (twice the current need seen so
 // far, at least 16 per row) and the fill flags an overflow, which the solve
 // checks at its first read-back (then re-sizes, rebuilds and restarts).
-void relcp_ctx::build_rowgraph(double dt) {
+// buffers of the row graph's widths, entry counter and columns of D
+void relcp_ctx::rg_prepare() {
     const int ns = rowgraph_slices(m);
     rg_width.ensure(ns + 1);
     rg_base.ensure(ns + 1);
@@ -868,11 +882,20 @@ void relcp_ctx::build_rowgraph(double dt) {
         HIP_OK(hipMemsetAsync(rg_flags.p, 0, sizeof(int), stream));  // entry counter, cleared by each fill
     }
     rg_jb.ensure(12 * (size_t)std::max(m, 1));
+}
+
+void relcp_ctx::build_rowgraph(double dt) {
+    const int ns = rowgraph_slices(m);
+    rg_prepare();
     rg_reserve(std::max<size_t>((size_t)RELCP_WAVE * ns * 16, 64));
     int_h[4] = int_h[5] = int_h[6] = 0;  // slots / 64, entries, overflow (written by the fill)
-    timed(8, [&] { launch_rowgraph_width(m, ria.p, rib.p, csr_off.p, rg_width.p, rg_flags.p, stream); });
+    if (!rg_pre) {
+        // widths and columns of D not made by the incidence build (a rebuild)
+        timed(8, [&] { launch_rowgraph_width(m, ria.p, rib.p, csr_off.p, rg_width.p, rg_flags.p, stream); });
+        timed(8, [&] { launch_incidence_jacobian(m, csr_ent.p, rn64.p, rta64.p, rtb64.p, ldr, rg_jb.p, stream); });
+    }
+    rg_pre = false;
     exclusive_scan(rg_width.p, rg_base.p, ns + 1, nullptr, scan_scratch, stream);
-    timed(8, [&] { launch_incidence_jacobian(m, csr_ent.p, rn64.p, rta64.p, rtb64.p, ldr, rg_jb.p, stream); });
     RowGraphFill f{};
     f.m = m; f.ldr = ldr; f.ia = ria.p; f.ib = rib.p; f.n = rn64.p; f.ta = rta64.p; f.tb = rtb64.p;
     f.ldb = n; f.K = K.p; f.off = csr_off.p; f.ent = csr_ent.p; f.jb = rg_jb.p; f.base = rg_base.p; f.dt = dt;
@@ -1621,8 +1644,9 @@ int relcp_set_lcp_config(relcp_ctx *ctx, int32_t mode, int32_t block, int32_t ld
     return RELCP_OK;
 }
 
-// Time every LCP configuration on the rows of the last accepted step (the
-// same start, restored before each trial) and keep the fastest.
+// Time every LCP configuration on the rows of the last accepted step, each
+// solve from zero (the step's own multipliers already solve that LCP), and
+// keep the fastest; the step's multipliers are restored afterwards.
 int relcp_autotune(relcp_ctx *ctx, double dt, double lcp_tol, int32_t reps, int32_t *config, double *ms) {
     if (!ctx) return RELCP_E_INVALID;
     return guarded(ctx, [&]() -> int {
@@ -1676,11 +1700,11 @@ int relcp_autotune(relcp_ctx *ctx, double dt, double lcp_tol, int32_t reps, int3
             ctx->res_block = c.block;
             ctx->res_lds = c.lds;
             double tot = 0.0;
-            for (int r = 0; r < reps; ++r) {
-                cp(ctx->rgam64.p, s64.p, M * 8);
-                cp(ctx->rg64.p, s64.p + M, M * 8);
-                cp(ctx->rgam32.p, s32.p, M * 4);
-                cp(ctx->rg32.p, s32.p + M, M * 4);
+            // one untimed solve first (graph instantiation, buffer growth)
+            for (int r = -1; r < reps; ++r) {
+                // from zero: the last step's multipliers solve this LCP already
+                HIP_OK(hipMemsetAsync(ctx->rgam64.p, 0, M * 8, ctx->stream));
+                HIP_OK(hipMemsetAsync(ctx->rgam32.p, 0, M * 4, ctx->stream));
                 int it = 0;
                 double res = 0;
                 HIP_OK(hipEventRecord(e0, ctx->stream));
@@ -1694,7 +1718,7 @@ int relcp_autotune(relcp_ctx *ctx, double dt, double lcp_tol, int32_t reps, int3
                 }
                 float t = 0.f;
                 HIP_OK(hipEventElapsedTime(&t, e0, e1));
-                tot += t;
+                if (r >= 0) tot += t;
             }
             double avg = tot / reps;
             if (ms) ms[&c - &cfgs[0]] = avg;
