@@ -141,11 +141,12 @@ void launch_rowgraph_fill(const RowGraphFill &a, hipStream_t s);
 // iteration with parity par, reading the previous pass's state (zin, gin)
 // and partials, writing (zout, gout) and its own partials pout; mode 2: the
 // same iteration with the partials reduced first by a one-block launch
-// (for passes over many blocks; identical iterates).
+// (for passes over many blocks; identical iterates).  save (mode 0, or
+// null): receives gam0 (the start, for a restart).
 template <typename T>
 void launch_lcp_spmv(int mode, const RowGraphT<T> &G, const T *qv, const T *dA, const double *gam0,
                      const RowStep<T> *zin, const T *gin, RowStep<T> *zout, T *gout, const PgdCtl &C, double *pout,
-                     int par, hipStream_t s);
+                     int par, hipStream_t s, double *save = nullptr);
 // Parameters of a row-graph solve in device memory, read by k_spmv_dev:
 // the passes of a solve are then identical launches (parity aside) and can
 // be recorded once in a graph.  nbg = blocks of a pass over m rows; a pass
@@ -177,10 +178,12 @@ void launch_spmv_dev(const LcpDev<T> *D, int grid_rows, int par, hipStream_t s);
 template <typename T>
 int make_spmv_graph(const LcpDev<T> *D, int grid_rows, int k, hipGraphExec_t *out);
 // gamma, g <- the state of the pass that holds the final iterate (fin.iter &
-// 1); gam64 (or null) <- the same gamma widened to FP64
+// 1), or, while the done flag (if given) is not set, that of the last pass
+// launched (parity last_par); gam64 (or null) <- the same gamma in FP64
 template <typename T>
 void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, const T *g0, const T *g1,
-                            const PgdState *fin, T *gam, T *g, double *gam64, hipStream_t s);
+                            const PgdState *fin, const int *done, int last_par, T *gam, T *g, double *gam64,
+                            hipStream_t s);
 
 // Passes of the projected-gradient loop.  Iteration j (j = 1, 2, ...) is
 // scatter(mode 1, par = j & 1) then gather(mode 1, par = j & 1); a solve

@@ -873,7 +873,7 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads)
     k_spmv(RowGraphT<T> G, const T *__restrict__ qv, const T *__restrict__ dA0, const double *__restrict__ gam0,
            const RowStep<T> *__restrict__ zin, const T *__restrict__ gin, RowStep<T> *__restrict__ zout,
-           T *__restrict__ gout, PgdCtl C, double *__restrict__ pout, int par) {
+           T *__restrict__ gout, PgdCtl C, double *__restrict__ pout, int par, double *__restrict__ save) {
     __shared__ double sh[4][kWaves];
     __shared__ PgdState ns;
     constexpr int RM = MODE == 0 ? 0 : 1;  // row arithmetic: start or iteration
@@ -884,6 +884,7 @@ __global__ void __launch_bounds__(kThreads)
     const bool act = r < G.m;
     RowPre<T> P;
     if (act) row_preload<T, RM>(G, qv, dA0, gam0, zin, gin, r, P);
+    if (MODE == 0 && save && act) save[r] = gam0[r];  // the start, kept for a restart
     T al = T(0);
     if (MODE == 2) {
         // the state was advanced by k_pgd_reduce
@@ -972,11 +973,12 @@ __global__ void k_set_lcpdev(LcpDev<T> *D, LcpDev<T> v) {
 template <typename T>
 __global__ void k_rowstate_unpack(int m, const RowStep<T> *__restrict__ z0, const RowStep<T> *__restrict__ z1,
                                   const T *__restrict__ g0, const T *__restrict__ g1,
-                                  const PgdState *__restrict__ fin, T *__restrict__ gam, T *__restrict__ g,
-                                  double *__restrict__ gam64) {
+                                  const PgdState *__restrict__ fin, const int *__restrict__ done, int last_par,
+                                  T *__restrict__ gam, T *__restrict__ g, double *__restrict__ gam64) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= m) return;
-    const bool odd = fin->iter & 1;
+    // a finished solve: the state of its final iterate; else that of the last pass launched
+    const bool odd = (done && !*done) ? (last_par & 1) : (fin->iter & 1);
     const T v = (odd ? z1 : z0)[r].gam;
     gam[r] = v;
     g[r] = (odd ? g1 : g0)[r];
@@ -1133,18 +1135,18 @@ void launch_rowgraph_fill(const RowGraphFill &a, hipStream_t s) {
 template <typename T>
 void launch_lcp_spmv(int mode, const RowGraphT<T> &G, const T *qv, const T *dA, const double *gam0,
                      const RowStep<T> *zin, const T *gin, RowStep<T> *zout, T *gout, const PgdCtl &C, double *pout,
-                     int par, hipStream_t s) {
+                     int par, hipStream_t s, double *save) {
     const int nb = nblk(G.m > 0 ? G.m : 1, kThreads);
     if (mode == 0) {
         launch_k(k_spmv<T, 0>, dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C,
-                           pout, par);
+                           pout, par, save);
     } else if (mode == 2) {
         hipLaunchKernelGGL(k_pgd_reduce, dim3(1), dim3(kThreads), 0, s, C, par);
         launch_k(k_spmv<T, 2>, dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C, pout,
-                 par);
+                 par, (double *)nullptr);
     } else
         launch_k(k_spmv<T, 1>, dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C,
-                           pout, par);
+                           pout, par, (double *)nullptr);
 }
 
 template <typename T>
@@ -1191,10 +1193,11 @@ int make_spmv_graph(const LcpDev<T> *D, int grid_rows, int k, hipGraphExec_t *ou
 
 template <typename T>
 void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, const T *g0, const T *g1,
-                            const PgdState *fin, T *gam, T *g, double *gam64, hipStream_t s) {
+                            const PgdState *fin, const int *done, int last_par, T *gam, T *g, double *gam64,
+                            hipStream_t s) {
     if (m > 0)
-        hipLaunchKernelGGL((k_rowstate_unpack<T>), dim3(nblk(m, 256)), dim3(256), 0, s, m, z0, z1, g0, g1, fin, gam,
-                           g, gam64);
+        hipLaunchKernelGGL((k_rowstate_unpack<T>), dim3(nblk(m, 256)), dim3(256), 0, s, m, z0, z1, g0, g1, fin, done,
+                           last_par, gam, g, gam64);
 }
 
 #define RELCP_INST(T)                                                                                              \
@@ -1204,9 +1207,9 @@ void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, c
                                        hipStream_t);                                                              \
     template void launch_lcp_spmv<T>(int, const RowGraphT<T> &, const T *, const T *, const double *,             \
                                      const RowStep<T> *, const T *, RowStep<T> *, T *, const PgdCtl &, double *,  \
-                                     int, hipStream_t);                                                           \
+                                     int, hipStream_t, double *);                                                 \
     template void launch_rowstate_unpack<T>(int, const RowStep<T> *, const RowStep<T> *, const T *, const T *,    \
-                                            const PgdState *, T *, T *, double *, hipStream_t);                   \
+                                            const PgdState *, const int *, int, T *, T *, double *, hipStream_t); \
     template void launch_set_lcpdev<T>(LcpDev<T> *, const LcpDev<T> &, hipStream_t);                               \
     template void launch_spmv_dev<T>(const LcpDev<T> *, int, int, hipStream_t);                                    \
     template int make_spmv_graph<T>(const LcpDev<T> *, int, int, hipGraphExec_t *);

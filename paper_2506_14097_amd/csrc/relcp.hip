@@ -220,7 +220,11 @@ struct relcp_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_class;
-    std::vector<std::pair<size_t, int>> pass_ev;  // (event pair, pass) of the current row-graph solve
+    struct PassEv {
+        size_t slot;
+        int j, pk;
+    };
+    std::vector<PassEv> pass_ev;  // (event pair, pass, precision) of the current row-graph solves
     size_t ev_used = 0;
     long long t_count[kClasses] = {};
     double t_ms[kClasses] = {};
@@ -363,6 +367,7 @@ struct relcp_ctx {
         if (red_h) (void)hipHostFree(red_h);
         if (dbl_h) (void)hipHostFree(dbl_h);
         if (pk_state_h) (void)hipHostFree(pk_state_h);
+        gam_save.release();
         boff_d.release(); roff.release(); rlist.release(); rlist2.release(); rcnt.release(); rE.release();
         pk_state.release();
         mlp_w.release(); feat.release(); rowscale.release();
@@ -386,7 +391,41 @@ struct relcp_ctx {
     template <typename T>
     int solve(double dt, double tol, int &iters, double &res);
     template <typename T>
+    RowsT<T> rows_of() const;
+    template <typename T>
+    BodiesT<T> bodies_of() const;
+    template <typename T>
     int solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt, double tol, int &iters, double &res);
+    template <typename T>
+    int solve_rowgraph_graph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt, double tol, int &iters,
+                             double &res);
+    // pieces of a row-graph solve with one launch per pass (per precision)
+    struct RgRun {
+        int j = 1, chunk = 2, pass_mode = 1;
+        bool fresh = false;  // the graph was assembled by this solve's start
+    };
+    RgRun rgr[2];
+    template <typename T>
+    struct RgBufs {
+        RowStep<T> *z0, *z1;
+        T *g0, *g1;
+        double *part;
+        size_t stride;
+        PgdCtl C;
+        RowGraphT<T> G;
+    };
+    template <typename T>
+    RgBufs<T> rg_bufs(const RowsT<T> &R, double tol);
+    template <typename T>
+    void rg_passes(const RgBufs<T> &B, const RowsT<T> &R, int k);
+    template <typename T>
+    void rg_start(const RowsT<T> &R, double dt, double tol, const double *gam0, double *save);
+    DBuf<double> gam_save;  // the start of the first solve of a recursion, for a restart
+    template <typename T>
+    void rg_unpack(const RowsT<T> &R, const BodiesT<T> &Bd, double tol);
+    template <typename T>
+    int rg_finish(const RowsT<T> &R, const BodiesT<T> &Bd, double tol, int &iters, double &res, bool &relaunched);
+    bool rg_overflowed();
     int step(double dt, double eps, double tol, relcp_step_stats *st);
     // host waits on the stream (counted per step)
     int n_waits = 0;
@@ -410,7 +449,7 @@ static T *host_mapped(size_t n, T **dev) {
 }
 
 void relcp_ctx::alloc_host() {
-    if (!pst_h) pst_h = host_mapped<PgdState>(2, &pst_d);
+    if (!pst_h) pst_h = host_mapped<PgdState>(4, &pst_d);  // final state and done flag per precision
     if (!int_h) int_h = host_mapped<int>(16, &int_d);
     if (!red_h) red_h = host_mapped<unsigned long long>(8, &red_hd);
     if (!dbl_h) dbl_h = host_mapped<double>(8, &dbl_hd);
@@ -910,24 +949,39 @@ void relcp_ctx::build_rowgraph(double dt) {
 // LCP of one recursion
 // ---------------------------------------------------------------------------
 template <typename T>
-int relcp_ctx::solve(double dt, double tol, int &iters, double &res) {
+RowsT<T> relcp_ctx::rows_of() const {
     RowsT<T> R{};
-    BodiesT<T> Bd{};
     R.m = m;
     R.ld = ldr;
     R.ia = ria.p;
     R.ib = rib.p;
     if constexpr (sizeof(T) == 8) {
         R.n = rn64.p; R.ta = rta64.p; R.tb = rtb64.p; R.qv = rqv64.p; R.dA = rdA64.p; R.gam = rgam64.p; R.g = rg64.p;
-        Bd.K = K.p; Bd.vc = vc64.p;
     } else {
         R.n = rn32.p; R.ta = rta32.p; R.tb = rtb32.p; R.qv = rqv32.p; R.dA = rdA32.p; R.gam = rgam32.p; R.g = rg32.p;
+    }
+    return R;
+}
+
+template <typename T>
+BodiesT<T> relcp_ctx::bodies_of() const {
+    BodiesT<T> Bd{};
+    if constexpr (sizeof(T) == 8) {
+        Bd.K = K.p; Bd.vc = vc64.p;
+    } else {
         Bd.K = K32.p; Bd.vc = vc32.p;
     }
     Bd.nb = n;
     Bd.ld = n;
     Bd.off = csr_off.p;
     Bd.ent = csr_ent.p;
+    return Bd;
+}
+
+template <typename T>
+int relcp_ctx::solve(double dt, double tol, int &iters, double &res) {
+    const RowsT<T> R = rows_of<T>();
+    const BodiesT<T> Bd = bodies_of<T>();
     if (resident_mode()) {
         ResidentArgs<T> a{R, Bd, nbatch, boff_d.p, roff.p, rlist.p, dt, lcp_fixed > 0 ? -1.0 : tol,
                           lcp_fixed > 0 ? lcp_fixed : lcp_max_iters, pk_state.p, maxpk};
@@ -1031,139 +1085,249 @@ hipGraphExec_t relcp_ctx::spmv_graph_for(int rows, LcpDev<T> **dev) {
 // the rows' gamma and g, and (FP64) the contact velocities K D gamma that
 // the trial integration needs are formed once.
 template <typename T>
-int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt, double tol, int &iters,
-                              double &res) {
+relcp_ctx::RgBufs<T> relcp_ctx::rg_bufs(const RowsT<T> &R, double tol) {
     const size_t mz = std::max(m, 1);
-    RowStep<T> *z0, *z1;
-    T *g0, *g1;
+    const int pk = sizeof(T) == 8 ? 1 : 0;
+    RgBufs<T> B{};
     if constexpr (sizeof(T) == 8) {
         z64.ensure(2 * mz);
         zg64.ensure(2 * mz);
-        z0 = z64.p; z1 = z64.p + mz; g0 = zg64.p; g1 = zg64.p + mz;
+        B.z0 = z64.p; B.z1 = z64.p + mz; B.g0 = zg64.p; B.g1 = zg64.p + mz;
     } else {
         z32.ensure(2 * mz);
         zg32.ensure(2 * mz);
-        z0 = z32.p; z1 = z32.p + mz; g0 = zg32.p; g1 = zg32.p + mz;
+        B.z0 = z32.p; B.z1 = z32.p + mz; B.g0 = zg32.p; B.g1 = zg32.p + mz;
     }
-    const size_t stride = lcp_partials_needed(m);
-    partials.ensure(2 * stride);
-    pst.ensure(4);
-    const int cap = lcp_fixed > 0 ? lcp_fixed : lcp_max_iters;
+    // each precision has its own control block and partial sums, so that an
+    // FP32 solve can continue after FP64 passes were launched behind it
+    B.stride = lcp_partials_needed(m);
+    partials.ensure(4 * B.stride);
+    B.part = partials.p + 2 * B.stride * pk;
+    pst.ensure(8);
+    PgdState *cb = pst.p + 4 * pk;
+    B.C = PgdCtl{cb, cb + 2, reinterpret_cast<int *>(cb + 3), B.part, lcp_gather_blocks(m),
+                 lcp_fixed > 0 ? -1.0 : tol, pst_d + 2 * pk, reinterpret_cast<int *>(pst_d + 2 * pk + 1)};
+    B.G = RowGraphT<T>{m, rg_base.p, rg_col.p, nullptr, rg_cap};
+    if constexpr (sizeof(T) == 8)
+        B.G.val = rg_val64.p;
+    else
+        B.G.val = rg_val32.p;
+    (void)R;
+    return B;
+}
+
+// k iteration passes from pass rgr[pk].j on
+template <typename T>
+void relcp_ctx::rg_passes(const RgBufs<T> &B, const RowsT<T> &R, int k) {
     const int pk = sizeof(T) == 8 ? 1 : 0;
-    PgdCtl C{pst.p, pst.p + 2, reinterpret_cast<int *>(pst.p + 3), partials.p, lcp_gather_blocks(m),
-             lcp_fixed > 0 ? -1.0 : tol, pst_d, reinterpret_cast<int *>(pst_d + 1)};
-    auto ctl = [&](int par) {  // control block of a pass with parity par: reads the other partials buffer
-        PgdCtl c = C;
-        c.partials = partials.p + (size_t)(par ^ 1) * stride;
-        return c;
-    };
-    int *const conv_h = reinterpret_cast<int *>(pst_h + 1);
-    bool seen = false;  // pst_h holds the final state
-    pass_ev.clear();
+    RgRun &st = rgr[pk];
+    for (int t = 0; t < k; ++t, ++st.j) {
+        const int par = st.j & 1;
+        PgdCtl c = B.C;
+        c.partials = B.part + (size_t)(par ^ 1) * B.stride;  // the previous pass's partial sums
+        if (timing) pass_ev.push_back(PassEv{ev_used / 2, st.j, pk});
+        timed(sizeof(T) == 4 ? 7 : 10, [&] {
+            launch_lcp_spmv<T>(st.pass_mode, B.G, R.qv, R.dA, nullptr, par ? B.z0 : B.z1, par ? B.g0 : B.g1,
+                               par ? B.z1 : B.z0, par ? B.g1 : B.g0, c, B.part + (size_t)par * B.stride, par, stream);
+        });
+    }
+}
+
+// Row-graph solve, launch part: the graph of the current rows (if not
+// valid), the start pass and a first chunk of iteration passes (the last
+// solve's count plus the pass that sees convergence and a spare).  Nothing
+// is waited for.
+template <typename T>
+void relcp_ctx::rg_start(const RowsT<T> &R, double dt, double tol, const double *gam0, double *save) {
+    const int pk = sizeof(T) == 8 ? 1 : 0;
+    RgRun &st = rgr[pk];
+    st.fresh = false;
+    if (!rg_valid || rg_dt != dt) {
+        build_rowgraph(dt);
+        st.fresh = true;
+    }
+    const RgBufs<T> B = rg_bufs<T>(R, tol);
+    // the start pass also resets the control block
+    timed(11, [&] {
+        launch_lcp_spmv<T>(0, B.G, R.qv, R.dA, gam0, nullptr, nullptr, B.z0, B.g0, B.C, B.part, 0, stream, save);
+    });
+    st.j = 1;
+    // the last solve's count, the pass that sees convergence and headroom: a
+    // short first chunk costs a wait and, in a step, the work launched behind
+    // it, while a spare pass returns at once
+    st.chunk = std::max(2, std::min(64, last_iters[pk] + std::max(3, last_iters[pk] / 4) + 1));
+    // over many blocks the partial sums are reduced once per pass by a
+    // separate launch instead of by every block
+    st.pass_mode = B.C.nbg >= reduce_split_blocks ? 2 : 1;
+    const int cap = lcp_fixed > 0 ? lcp_fixed : lcp_max_iters;
+    rg_passes<T>(B, R, std::min(st.chunk, cap));
+}
+
+// The rows' gamma and g from the solve's final iterate, or from its last
+// pass while it has not finished (chosen on the device); FP32 also widens
+// gamma into the FP64 multipliers, FP64 forms the contact velocities K D
+// gamma the trial needs.
+template <typename T>
+void relcp_ctx::rg_unpack(const RowsT<T> &R, const BodiesT<T> &Bd, double tol) {
+    const int pk = sizeof(T) == 8 ? 1 : 0;
+    const RgBufs<T> B = rg_bufs<T>(R, tol);
+    launch_rowstate_unpack<T>(m, B.z0, B.z1, B.g0, B.g1, B.C.fin, B.C.done, (rgr[pk].j - 1) & 1, R.gam, R.g,
+                              sizeof(T) == 4 ? rgam64.p : nullptr, stream);
+    if constexpr (sizeof(T) == 8) timed(0, [&] { launch_lcp_scatter<T>(0, R, Bd, B.C, 0, stream); });
+}
+
+// After a wait: true if the last graph assembly overflowed its slots (then
+// they are re-sized and the graph is marked for re-assembly).
+bool relcp_ctx::rg_overflowed() {
+    rg_entries = int_h[5];
+    if (!int_h[6] && (size_t)RELCP_WAVE * int_h[4] <= rg_cap) return false;
+    rg_reserve(2 * (size_t)RELCP_WAVE * int_h[4]);
+    rg_valid = false;
+    return true;
+}
+
+// Row-graph solve, completion (after a wait that covered the launched
+// passes): if the solve has not converged, further chunks (waiting after
+// each), the state after the last pass if the cap is reached, and the unpack
+// again (relaunched = true: everything launched after the first unpack is
+// stale).  Returns the status; iters and res from the final state.
+template <typename T>
+int relcp_ctx::rg_finish(const RowsT<T> &R, const BodiesT<T> &Bd, double tol, int &iters, double &res,
+                         bool &relaunched) {
+    const int pk = sizeof(T) == 8 ? 1 : 0;
+    RgRun &st = rgr[pk];
+    const RgBufs<T> B = rg_bufs<T>(R, tol);
+    const int *done_h = reinterpret_cast<const int *>(pst_h + 2 * pk + 1);
+    const int cap = lcp_fixed > 0 ? lcp_fixed : lcp_max_iters;
+    relaunched = false;
+    if (!*done_h) {
+        relaunched = true;
+        for (;;) {
+            const int k = std::min(st.chunk, cap - (st.j - 1));
+            if (k <= 0) break;
+            rg_passes<T>(B, R, k);
+            sync();
+            if (*done_h) break;
+            st.chunk = std::min(64, std::max(8, 2 * st.chunk));
+        }
+        if (!*done_h) {
+            // the state after the last pass (iteration cap or fixed iterations)
+            PgdCtl cf = B.C;
+            cf.partials = B.part + (size_t)((st.j - 1) & 1) * B.stride;
+            launch_pgd_finalize(cf, st.j & 1, stream);
+        }
+        rg_unpack<T>(R, Bd, tol);
+        sync();
+    }
+    const bool conv = *done_h != 0;
+    iters = pst_h[2 * pk].iter;
+    res = pst_h[2 * pk].res;
+    last_iters[pk] = iters;
+    // passes past the last iteration only reduced (or returned at once):
+    // timed apart from the iteration passes
+    for (auto &pe : pass_ev)
+        if (pe.pk == pk && pe.j > iters && pe.slot < ev_class.size()) ev_class[pe.slot] = kIdlePass;
+    if (!std::isfinite(res)) return RELCP_E_NAN;
+    if (lcp_fixed > 0) return RELCP_OK;
+    return conv ? RELCP_OK : RELCP_E_LCP_MAXITER;
+}
+
+// Row-graph LCP loop, one solve waited for: pass 0 forms g at the start,
+// pass j (parity j & 1) reads state buffer z[(j - 1) & 1] and the partials
+// of pass j - 1 and writes z[j & 1] and its own partials; the final iterate
+// is unpacked into the rows' gamma and g, and (FP64) the contact velocities
+// K D gamma that the trial integration needs are formed once.  LCP mode 3
+// replays the passes from an instantiated graph.
+template <typename T>
+int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt, double tol, int &iters,
+                              double &res) {
+    if (lcp_mode == 3 && graph_ok && lcp_fixed == 0) return solve_rowgraph_graph<T>(R, Bd, dt, tol, iters, res);
+    gam_save.ensure(std::max(m, 1));
+    for (int attempt = 0;; ++attempt) {
+        // a restart (the graph did not fit its slots) begins from the same start
+        rg_start<T>(R, dt, tol, attempt ? gam_save.p : rgam64.p, attempt ? nullptr : gam_save.p);
+        rg_unpack<T>(R, Bd, tol);
+        sync();
+        if (rgr[sizeof(T) == 8 ? 1 : 0].fresh && rg_overflowed()) {
+            if (attempt > 0) throw Error{RELCP_E_DEVICE, "row graph sizing failed"};
+            continue;
+        }
+        bool again = false;
+        return rg_finish<T>(R, Bd, tol, iters, res, again);
+    }
+}
+
+// Graph replay of the passes (LCP mode 3): whole graphs of kGraphPasses
+// passes reading their parameters from device memory; passes past the end
+// of the solve return at once.
+template <typename T>
+int relcp_ctx::solve_rowgraph_graph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt, double tol, int &iters,
+                                    double &res) {
+    const int pk = sizeof(T) == 8 ? 1 : 0;
+    const int cap = lcp_max_iters;
+    const int *done_h = reinterpret_cast<const int *>(pst_h + 2 * pk + 1);
     for (int attempt = 0;; ++attempt) {
         bool fresh = false;
         if (!rg_valid || rg_dt != dt) {
             build_rowgraph(dt);
             fresh = true;
         }
-        RowGraphT<T> G{m, rg_base.p, rg_col.p, nullptr, rg_cap};
-        if constexpr (sizeof(T) == 8)
-            G.val = rg_val64.p;
-        else
-            G.val = rg_val32.p;
-        hipGraphExec_t ge = nullptr;
-        if (lcp_mode == 3 && graph_ok) {
-            LcpDev<T> *dev = nullptr;
-            ge = spmv_graph_for<T>(m, &dev);
-            if (ge) {
-                LcpDev<T> v{};
-                v.m = m; v.nbg = C.nbg; v.cap = cap; v.tol = C.tol;
-                v.base = G.base; v.col = G.col; v.val = G.val; v.slots = G.cap;
-                v.qv = R.qv; v.dA = R.dA;
-                v.z[0] = z0; v.z[1] = z1; v.g[0] = g0; v.g[1] = g1;
-                v.part[0] = partials.p; v.part[1] = partials.p + stride;
-                v.S = C.S; v.fin = C.fin; v.done = C.done; v.fin_h = C.fin_h; v.done_h = C.done_h;
-                launch_set_lcpdev<T>(dev, v, stream);
-            }
+        const RgBufs<T> B = rg_bufs<T>(R, tol);
+        LcpDev<T> *dev = nullptr;
+        hipGraphExec_t ge = spmv_graph_for<T>(m, &dev);
+        if (!ge) {
+            // graphs unavailable: per-pass launches from here on
+            graph_ok = false;
+            return solve_rowgraph<T>(R, Bd, dt, tol, iters, res);
         }
-        // the start pass also resets the control block
+        LcpDev<T> v{};
+        v.m = m; v.nbg = B.C.nbg; v.cap = cap; v.tol = B.C.tol;
+        v.base = B.G.base; v.col = B.G.col; v.val = B.G.val; v.slots = B.G.cap;
+        v.qv = R.qv; v.dA = R.dA;
+        v.z[0] = B.z0; v.z[1] = B.z1; v.g[0] = B.g0; v.g[1] = B.g1;
+        v.part[0] = B.part; v.part[1] = B.part + B.stride;
+        v.S = B.C.S; v.fin = B.C.fin; v.done = B.C.done; v.fin_h = B.C.fin_h; v.done_h = B.C.done_h;
+        launch_set_lcpdev<T>(dev, v, stream);
         timed(11, [&] {
-            launch_lcp_spmv<T>(0, G, R.qv, R.dA, rgam64.p, nullptr, nullptr, z0, g0, C, partials.p, 0, stream);
+            launch_lcp_spmv<T>(0, B.G, R.qv, R.dA, rgam64.p, nullptr, nullptr, B.z0, B.g0, B.C, B.part, 0, stream);
         });
         int j = 1;
-        // passes of the first chunk: the last solve's iterations plus the pass
-        // that sees convergence and a spare (even for the graph's chunks; a
-        // polish that last converged at its start needs one pass)
         int chunk = std::max(2, std::min(64, (last_iters[pk] + 3) & ~1));
-        if (!(lcp_mode == 3 && graph_ok) && last_iters[pk] == 0) chunk = 1;
-        bool first = true;
-        seen = false;
-        // over many blocks the partial sums are reduced once per pass by a
-        // separate launch instead of by every block
-        const int pass_mode = C.nbg >= reduce_split_blocks ? 2 : 1;
+        bool first = true, overflow = false;
         for (;;) {
-            if (ge) {
-                // whole graphs; the passes past the end of the solve return at once
-                const int ng = (chunk + kGraphPasses - 1) / kGraphPasses;
-                for (int t = 0; t < ng; ++t, j += kGraphPasses)
-                    timed_span(sizeof(T) == 4 ? 7 : 10, [&] { HIP_OK(hipGraphLaunch(ge, stream)); });
-            } else {
-                const int k = std::min(chunk, cap - (j - 1));
-                if (k <= 0) break;
-                for (int t = 0; t < k; ++t, ++j) {
-                    const int par = j & 1;
-                    if (timing) pass_ev.emplace_back(ev_used / 2, j);
-                    timed(sizeof(T) == 4 ? 7 : 10, [&] {
-                        launch_lcp_spmv<T>(pass_mode, G, R.qv, R.dA, nullptr, par ? z0 : z1, par ? g0 : g1, par ? z1 : z0,
-                                           par ? g1 : g0, ctl(par), partials.p + (size_t)par * stride, par, stream);
-                    });
-                }
-            }
+            const int ng = (chunk + kGraphPasses - 1) / kGraphPasses;
+            for (int t = 0; t < ng; ++t, j += kGraphPasses)
+                timed_span(sizeof(T) == 4 ? 7 : 10, [&] { HIP_OK(hipGraphLaunch(ge, stream)); });
             sync();
             if (first && fresh) {
                 first = false;
-                rg_entries = int_h[5];
-                const size_t need = (size_t)RELCP_WAVE * int_h[4];
-                if (int_h[6] || need > rg_cap) break;
+                if (rg_overflowed()) {
+                    overflow = true;
+                    break;
+                }
             }
-            if (*conv_h || (ge && pst_h[0].iter >= cap)) {
-                seen = true;
-                break;
-            }
-            if (ge && j > cap + 1) throw Error{RELCP_E_DEVICE, "LCP passes ran past the iteration cap"};
+            if (*done_h || pst_h[2 * pk].iter >= cap) break;
+            if (j > cap + 1) throw Error{RELCP_E_DEVICE, "LCP passes ran past the iteration cap"};
             chunk = std::min(64, std::max(8, 2 * chunk));
         }
-        if (fresh && (int_h[6] || (size_t)RELCP_WAVE * int_h[4] > rg_cap)) {
-            // the entry slots did not suffice: re-size to twice the need and start over
+        if (overflow) {
             if (attempt > 0) throw Error{RELCP_E_DEVICE, "row graph sizing failed"};
-            rg_reserve(2 * (size_t)RELCP_WAVE * int_h[4]);
-            rg_valid = false;
             continue;
         }
-        if (!seen) {
-            // the state after the last pass (iteration cap or fixed iterations)
-            PgdCtl cf = C;
-            cf.partials = partials.p + (size_t)((j - 1) & 1) * stride;
-            launch_pgd_finalize(cf, j & 1, stream);
-        }
-        break;
+        // done is set (the stop pass wrote the final state)
+        launch_rowstate_unpack<T>(m, B.z0, B.z1, B.g0, B.g1, B.C.fin, nullptr, 0, R.gam, R.g,
+                                  sizeof(T) == 4 ? rgam64.p : nullptr, stream);
+        if constexpr (sizeof(T) == 8) timed(0, [&] { launch_lcp_scatter<T>(0, R, Bd, B.C, 0, stream); });
+        sync();
+        // the stop pass marks done on convergence and at the cap; done_h
+        // mirrors convergence only
+        const bool conv = *done_h != 0;
+        iters = pst_h[2 * pk].iter;
+        res = pst_h[2 * pk].res;
+        last_iters[pk] = iters;
+        if (!std::isfinite(res)) return RELCP_E_NAN;
+        return conv ? RELCP_OK : RELCP_E_LCP_MAXITER;
     }
-    // FP32: the final iterate widened into the FP64 multipliers as well
-    launch_rowstate_unpack<T>(m, z0, z1, g0, g1, C.fin, R.gam, R.g, sizeof(T) == 4 ? rgam64.p : nullptr, stream);
-    if constexpr (sizeof(T) == 8) timed(0, [&] { launch_lcp_scatter<T>(0, R, Bd, C, 0, stream); });
-    if (!seen) sync();
-    const bool conv = *conv_h != 0;
-    iters = pst_h[0].iter;
-    res = pst_h[0].res;
-    last_iters[pk] = iters;
-    // passes past the last iteration only reduced (or returned at once):
-    // timed apart from the iteration passes
-    for (const auto &pe : pass_ev)
-        if (pe.second > iters && pe.first < ev_class.size()) ev_class[pe.first] = kIdlePass;
-    pass_ev.clear();
-    if (!std::isfinite(res)) return RELCP_E_NAN;
-    if (lcp_fixed > 0) return RELCP_OK;
-    return conv ? RELCP_OK : RELCP_E_LCP_MAXITER;
 }
 
 // ---------------------------------------------------------------------------
@@ -1177,6 +1341,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     const int N = n;
     n_waits = 0;
     t_wait = 0.0;
+    pass_ev.clear();
 
     // set-up at C^k: geometry, K, U_free
     BodySetupArgs ba{};
@@ -1220,11 +1385,86 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     int rec = 0;
     int iters_total = 0;
     double minphi = 0.0;
+    // Row-graph mode with one launch per pass: each recursion's FP32 solve
+    // (if any), FP64 polish and trial are launched before one wait; a solve
+    // found unfinished at that wait is continued and what follows it redone
+    const bool spec = rowgraph_mode() && !(lcp_mode == 3 && graph_ok) && lcp_fixed == 0;
     for (;; ++rec) {
         // LCP of recursion rec
         int it = 0, it64 = 0;
         double res = 0, res64 = 0;
-        if (precision == 32) {
+        const int nw = work_blocks(m), nt = trial_blocks(N), nsb = snsd_blocks(np);
+        // W_n = gamma^T A gamma, trial configuration C_{n+1} = C^k (+) dt V_n,
+        // SNSD of every candidate pair there, violators, report
+        auto launch_tail = [&]() {
+            work_out.ensure(nw);
+            red.ensure((size_t)nt + 2 * (size_t)nsb);
+            launch_work(m, rgam64.p, rg64.p, rqv64.p, work_out.p, stream);
+            timed(4, [&] {
+                launch_trial(N, x.p, N, q.p, N, vfree.p, vc64.p, N, dt, kind.p, p.p, N, Rb.p, xt.p, qt.p, geot.p, N,
+                             vout.p, red.p, stream);
+            });
+            SnsdArgs sb = sa;
+            sb.x = xt.p; sb.geo = geot.p; sb.hint = snsd0.p + ldp; sb.out = snsdt.p; sb.mode = 1; sb.flag = pflag.p;
+            sb.minphi = red.p + nt; sb.minmarg = red.p + nt + nsb;
+            sb.clear = lam.p;  // the pair sums of an accepted step are accumulated there
+            timed(2, [&] { launch_snsd_pairs(sb, stream); });
+            compact_flags(pflag.p, np, pcnt.p, sel.p, int_d, scan_scratch, stream);  // count -> int_h[0]
+            hipLaunchKernelGGL(k_report, dim3(1), dim3(256), 0, stream, nt, red.p, np > 0 ? nsb : 0, red.p + nt,
+                               red.p + nt + nsb, nw, work_out.p, red_hd, dbl_hd);
+        };
+        bool tail_ready = false;  // the tail ran on the final multipliers and was waited for
+        if (spec) {
+            const RowsT<float> R32 = rows_of<float>();
+            const RowsT<double> R64 = rows_of<double>();
+            const BodiesT<float> B32 = bodies_of<float>();
+            const BodiesT<double> B64 = bodies_of<double>();
+            gam_save.ensure(std::max(m, 1));
+            for (int attempt = 0;; ++attempt) {
+                // the first solve keeps its start: a restart (the graph did
+                // not fit its slots) begins from the same one
+                const double *g0 = attempt ? gam_save.p : rgam64.p;
+                double *keep = attempt ? nullptr : gam_save.p;
+                if (precision == 32) {
+                    rg_start<float>(R32, dt, tol, g0, keep);
+                    rg_unpack<float>(R32, B32, tol);
+                    g0 = rgam64.p;
+                    keep = nullptr;
+                }
+                rg_start<double>(R64, dt, tol, g0, keep);
+                rg_unpack<double>(R64, B64, tol);
+                launch_tail();
+                sync();
+                if ((rgr[0].fresh || rgr[1].fresh) && rg_overflowed()) {
+                    if (attempt > 0) throw Error{RELCP_E_DEVICE, "row graph sizing failed"};
+                    continue;
+                }
+                break;
+            }
+            bool again32 = false, again64 = false;
+            if (precision == 32) {
+                status = rg_finish<float>(R32, B32, tol, it, res, again32);
+                if (status == RELCP_OK || status == RELCP_E_LCP_MAXITER) {
+                    if (again32) {
+                        // the polish started from an unfinished FP32 iterate: again
+                        rg_start<double>(R64, dt, tol, rgam64.p, nullptr);
+                        rg_unpack<double>(R64, B64, tol);
+                        sync();
+                    }
+                    status = rg_finish<double>(R64, B64, tol, it64, res64, again64);
+                }
+            } else {
+                status = rg_finish<double>(R64, B64, tol, it, res64, again64);
+                res = res64;
+            }
+            if (status == RELCP_OK) {
+                if (again32 || again64) {
+                    launch_tail();
+                    sync();
+                }
+                tail_ready = true;
+            }
+        } else if (precision == 32) {
             // (the row-graph solve reads the FP64 start and writes the FP64
             // result itself)
             if (!rowgraph_mode()) launch_demote(m, rgam64.p, rgam32.p, stream);
@@ -1248,30 +1488,11 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         S.residual_fp64 = res64;
         S.residual_lowp = res;
         if (status != RELCP_OK) break;
-        // W_n = gamma^T A gamma (its block partials need their own sizing:
-        // the resident LCP mode never touches the grid-mode partials)
-        partials.ensure(lcp_partials_needed(m));
-        const int nw = work_blocks(m), nt = trial_blocks(N), nsb = snsd_blocks(np);
-        work_out.ensure(nw);
-        red.ensure((size_t)nt + 2 * (size_t)nsb);
-        launch_work(m, rgam64.p, rg64.p, rqv64.p, work_out.p, stream);
         t_lcp += tm.ms();
-
-        // trial configuration C_{n+1} = C^k (+) dt V_n
-        timed(4, [&] {
-            launch_trial(N, x.p, N, q.p, N, vfree.p, vc64.p, N, dt, kind.p, p.p, N, Rb.p, xt.p, qt.p, geot.p, N,
-                         vout.p, red.p, stream);
-        });
-        // SNSD of every candidate pair at the trial configuration
-        SnsdArgs sb = sa;
-        sb.x = xt.p; sb.geo = geot.p; sb.hint = snsd0.p + ldp; sb.out = snsdt.p; sb.mode = 1; sb.flag = pflag.p;
-        sb.minphi = red.p + nt; sb.minmarg = red.p + nt + nsb;
-        sb.clear = lam.p;  // the pair sums of an accepted step are accumulated there
-        timed(2, [&] { launch_snsd_pairs(sb, stream); });
-        compact_flags(pflag.p, np, pcnt.p, sel.p, int_d, scan_scratch, stream);  // count -> int_h[0]
-        hipLaunchKernelGGL(k_report, dim3(1), dim3(256), 0, stream, nt, red.p, np > 0 ? nsb : 0, red.p + nt,
-                           red.p + nt + nsb, nw, work_out.p, red_hd, dbl_hd);
-        sync();
+        if (!tail_ready) {
+            launch_tail();
+            sync();
+        }
         t_narrow += tm.ms();
         int nv = np > 0 ? int_h[0] : 0;
         double maxdisp;

@@ -459,3 +459,39 @@ def test_rowgraph_graph_replay_matches_per_pass_launches(dev, precision):
         # FP32 runs its capped iterations, then the capped FP64 polish: 2 x 7
         assert a[0] == b[0] == (7 if precision == 64 else 14) and a[1] == b[1]
         assert np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_single_wait_steps_match_waited_solves(dev, precision):
+    """A step in the row-graph mode with one launch per pass launches the
+    FP32 solve, the FP64 polish and the trial before one wait, continuing a
+    solve found unfinished and redoing what follows it; graph replay waits
+    after every solve.  Both run the same iterations: over a compaction with
+    augmentations and warm starts (the first steps need more iterations than
+    the first chunk), the same states, contact sets, iteration counts and
+    residuals bit for bit."""
+    S = compressed_packing(4, 150, 26)
+    sims = []
+    for mode in (3, 4):
+        sim = sim_from(dict(S, box=S["box"].copy()), skin=0.2, warm_start=R.WS_PREV, precision=precision)
+        sim.set_lcp_config(mode, 256, True)
+        sims.append(sim)
+    recs = 0
+    for k in range(6):
+        out = []
+        for sim in sims:
+            sim.affine_rescale(0.995)
+            res = sim.step(5e-3, 1e-5, 1e-10 if precision == 64 else 1e-6)
+            out.append((res, sim.get_state()))
+        (ra, sa), (rb, sb) = out
+        print("step", k, "iters", ra["lcp_iters"], rb["lcp_iters"], "rec", ra["recursions"], flush=True)
+        assert ra["status"] == rb["status"] == 0
+        assert ra["recursions"] == rb["recursions"]
+        assert np.array_equal(ra["n_contacts"], rb["n_contacts"])
+        assert np.array_equal(ra["lcp_iters"], rb["lcp_iters"])
+        assert np.array_equal(ra["lcp_iters64"], rb["lcp_iters64"])
+        assert ra["residual_fp64"] == rb["residual_fp64"]
+        for a, b in zip(sa, sb):
+            assert np.array_equal(a, b)
+        recs += ra["recursions"]
+    assert recs > 0
