@@ -58,13 +58,9 @@ struct RowBuildArgs {
 void launch_rows_build(const RowBuildArgs &a, hipStream_t s);
 // CSR of the rows at each body; cleared: cnt and cursor (2 (nb + 1) ints)
 // are known to be zero (every build leaves them so).  rg (or null): also
-// the row-graph slice widths with their sum (as launch_rowgraph_width) and
-// the columns of D per incidence entry (as launch_incidence_jacobian).
+// the row-graph slice widths with their sum (as launch_rowgraph_width).
 struct CsrRowGraphOut {
     int *width, *count;
-    double *jb;
-    const double *n, *ta, *tb;
-    int ldr;
 };
 void launch_csr(int nb, int m, const int *ia, const int *ib, int *cnt, int *off, int *cursor, int *ent,
                 bool cleared, DBuf<int> &scan_scratch, hipStream_t s, const CsrRowGraphOut *rg = nullptr);

@@ -171,12 +171,9 @@ __global__ void __launch_bounds__(256) k_csr_fill(int m, const int *__restrict__
 }
 
 // Order each body's list by entry (row index) so summation order is fixed,
-// and clear the body's count and cursor for the next build.  With jb set
-// (the row-graph layout), also the column of D at this body of each listed
-// row, in list order: s (n, r x n) with s = -1 at body a, +1 at body b.
+// and clear the body's count and cursor for the next build.
 __global__ void k_csr_sort(int nb, const int *__restrict__ off, int *__restrict__ ent, int *__restrict__ cnt,
-                           int *__restrict__ cursor, double *__restrict__ jb, const double *__restrict__ n,
-                           const double *__restrict__ ta, const double *__restrict__ tb, int L) {
+                           int *__restrict__ cursor) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nb) return;
     cnt[i] = 0;
@@ -189,19 +186,6 @@ __global__ void k_csr_sort(int nb, const int *__restrict__ off, int *__restrict_
             --j;
         }
         ent[j + 1] = v;
-    }
-    if (!jb) return;
-    for (int e = lo; e < hi; ++e) {
-        const int en = ent[e], j = en >> 1;
-        const double sg = (en & 1) ? 1.0 : -1.0;
-        const double *t = (en & 1) ? tb : ta;
-        double *o = jb + 6 * (size_t)e;
-        o[0] = sg * n[j];
-        o[1] = sg * n[L + j];
-        o[2] = sg * n[2 * L + j];
-        o[3] = sg * t[j];
-        o[4] = sg * t[L + j];
-        o[5] = sg * t[2 * L + j];
     }
 }
 
@@ -1035,9 +1019,7 @@ void launch_csr(int nb, int m, const int *ia, const int *ib, int *cnt, int *off,
     if (m > 0) {
         hipLaunchKernelGGL(k_csr_fill, dim3(nblk(m, 256)), dim3(256), 0, s, m, ia, ib, off, cursor, ent,
                            rg ? rg->width : nullptr, rg ? rg->count : nullptr);
-        hipLaunchKernelGGL(k_csr_sort, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, off, ent, cnt, cursor,
-                           rg ? rg->jb : nullptr, rg ? rg->n : nullptr, rg ? rg->ta : nullptr,
-                           rg ? rg->tb : nullptr, rg ? rg->ldr : 0);
+        hipLaunchKernelGGL(k_csr_sort, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, off, ent, cnt, cursor);
     }
 }
 

@@ -322,7 +322,7 @@ struct relcp_ctx {
     void build_rowgraph(double dt);
     void rg_reserve(size_t slots);
     void rg_prepare();
-    bool rg_pre = false;  // the incidence build made this graph's widths and columns of D
+    bool rg_pre = false;  // the incidence build made this graph's slice widths
     int maxpk = 0;                       // bodies of the largest packing
     DBuf<int> boff_d, roff, rlist, rlist2, rcnt, rE;
     DBuf<PgdState> pk_state;
@@ -851,8 +851,7 @@ void relcp_ctx::rebuild_csr() {
     csr_ent.ensure(2 * (size_t)std::max(m, 1));
     const bool cleared = csr_clear == csr_cnt.p;
     csr_clear = nullptr;
-    // in the row-graph mode the same passes also produce the graph's slice
-    // widths and the columns of D in list order
+    // in the row-graph mode the fill pass also produces the graph's slice widths
     CsrRowGraphOut rgo{};
     // (a build whose graph was never assembled left its width sum in the
     // entry counter: clear it)
@@ -860,7 +859,7 @@ void relcp_ctx::rebuild_csr() {
     rg_pre = rowgraph_mode() && m > 0;
     if (rg_pre) {
         rg_prepare();
-        rgo = CsrRowGraphOut{rg_width.p, rg_flags.p, rg_jb.p, rn64.p, rta64.p, rtb64.p, ldr};
+        rgo = CsrRowGraphOut{rg_width.p, rg_flags.p};
     }
     launch_csr(n, m, ria.p, rib.p, csr_cnt.p, csr_off.p, csr_cnt.p + (n + 1), csr_ent.p, cleared, scan_scratch,
                stream, rg_pre ? &rgo : nullptr);
@@ -929,11 +928,11 @@ void relcp_ctx::build_rowgraph(double dt) {
     rg_reserve(std::max<size_t>((size_t)RELCP_WAVE * ns * 16, 64));
     int_h[4] = int_h[5] = int_h[6] = 0;  // slots / 64, entries, overflow (written by the fill)
     if (!rg_pre) {
-        // widths and columns of D not made by the incidence build (a rebuild)
+        // widths not made by the incidence build (a rebuild)
         timed(8, [&] { launch_rowgraph_width(m, ria.p, rib.p, csr_off.p, rg_width.p, rg_flags.p, stream); });
-        timed(8, [&] { launch_incidence_jacobian(m, csr_ent.p, rn64.p, rta64.p, rtb64.p, ldr, rg_jb.p, stream); });
     }
     rg_pre = false;
+    timed(8, [&] { launch_incidence_jacobian(m, csr_ent.p, rn64.p, rta64.p, rtb64.p, ldr, rg_jb.p, stream); });
     exclusive_scan(rg_width.p, rg_base.p, ns + 1, nullptr, scan_scratch, stream);
     RowGraphFill f{};
     f.m = m; f.ldr = ldr; f.ia = ria.p; f.ib = rib.p; f.n = rn64.p; f.ta = rta64.p; f.tb = rtb64.p;
@@ -1156,6 +1155,7 @@ void relcp_ctx::rg_start(const RowsT<T> &R, double dt, double tol, const double 
     // short first chunk costs a wait and, in a step, the work launched behind
     // it, while a spare pass returns at once
     st.chunk = std::max(2, std::min(64, last_iters[pk] + std::max(3, last_iters[pk] / 4) + 1));
+    if (last_iters[pk] == 0) st.chunk = 2;  // a polish that last converged at its start
     // over many blocks the partial sums are reduced once per pass by a
     // separate launch instead of by every block
     st.pass_mode = B.C.nbg >= reduce_split_blocks ? 2 : 1;
