@@ -200,19 +200,40 @@ __device__ inline double wave_max(double v) {
     for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, RELCP_WAVE));
     return v;
 }
-// three sums and a max over the wave: the same butterflies as wave_sum and
-// wave_max (so the same results), with the four exchanges of each round
-// issued together instead of four dependent chains one after another
+// Wave totals through DPP row operations (VALU lane moves, no LDS
+// crossbar): quad permutes, row shifts by 4 and 8, then the broadcasts of
+// lanes 15 and 31 into the following rows; the total ends in lane 63 and is
+// read from there.  Lanes whose source is out of range read 0, the identity
+// of the sums and of the max of non-negative values.  A fixed order.
+template <int CTRL, int ROWS = 0xf>
+__device__ inline double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline double lane63(double v) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                            __builtin_amdgcn_readlane(__double2loint(v), 63));
+}
+// three sums and the max of non-negative values over the wave (every lane
+// gets the results)
 __device__ inline void wave_reduce4(double &a, double &b, double &c, double &mx) {
-#pragma unroll
-    for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) {
-        const double ta = __shfl_xor(a, o, RELCP_WAVE), tb = __shfl_xor(b, o, RELCP_WAVE);
-        const double tc = __shfl_xor(c, o, RELCP_WAVE), tm = __shfl_xor(mx, o, RELCP_WAVE);
-        a += ta;
-        b += tb;
-        c += tc;
-        mx = fmax(mx, tm);
-    }
+#define RELCP_DPP_STEP(CTRL, ROWS)                \
+    a += dpp_move<CTRL, ROWS>(a);                 \
+    b += dpp_move<CTRL, ROWS>(b);                 \
+    c += dpp_move<CTRL, ROWS>(c);                 \
+    mx = fmax(mx, dpp_move<CTRL, ROWS>(mx));
+    RELCP_DPP_STEP(0xb1, 0xf)   // quad_perm 1,0,3,2
+    RELCP_DPP_STEP(0x4e, 0xf)   // quad_perm 2,3,0,1
+    RELCP_DPP_STEP(0x114, 0xf)  // row_shr 4
+    RELCP_DPP_STEP(0x118, 0xf)  // row_shr 8
+    RELCP_DPP_STEP(0x142, 0xa)  // row_bcast 15 into rows 1 and 3
+    RELCP_DPP_STEP(0x143, 0xc)  // row_bcast 31 into rows 2 and 3
+#undef RELCP_DPP_STEP
+    a = lane63(a);
+    b = lane63(b);
+    c = lane63(c);
+    mx = lane63(mx);
 }
 
 // Block reduction of 3 sums and 1 max in a fixed order over NW waves; the
