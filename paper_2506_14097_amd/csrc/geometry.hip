@@ -47,7 +47,9 @@ __device__ double gap_newton(d3 &n, d3 d, const sym3 &A, const sym3 &B, int maxi
         double g1 = dot(e1, grad), g2 = dot(e2, grad);
         double scale = dl + ha + hb;
         double gnorm = sqrt(g1 * g1 + g2 * g2);
-        if (gnorm <= 1e-14 * scale) break;
+        // Phi is stationary at the maximiser: a tangential gradient of 1e-11
+        // of the scale leaves the normal good to ~1e-11 and Phi to ~1e-22
+        if (gnorm <= 1e-11 * scale) break;
         // projected Hessian of f on the sphere: P (Hess f) P - (n.grad f) P
         d3 Ae1 = mul(A, e1), Ae2 = mul(A, e2), Be1 = mul(B, e1), Be2 = mul(B, e2);
         double ia = 1.0 / ha, ib = 1.0 / hb, ia3 = ia * ia * ia, ib3 = ib * ib * ib;
