@@ -34,25 +34,42 @@ __device__ inline void tangent_frame(d3 n, d3 &e1, d3 &e2) {
     e2 = cross(n, e1);
 }
 
+// The support gap at n with the pieces a Newton step reuses: A n, B n and
+// the support radii h_a = sqrt(n.A n), h_b.
+struct GapEval {
+    double F, ha, hb;
+    d3 an, bn;
+};
+__device__ inline GapEval gap_eval(d3 n, d3 d, const sym3 &A, const sym3 &B) {
+    GapEval g;
+    g.an = mul(A, n);
+    g.bn = mul(B, n);
+    g.ha = sqrt(dot(n, g.an));
+    g.hb = sqrt(dot(n, g.bn));
+    g.F = dot(n, d) - g.ha - g.hb;
+    return g;
+}
+
 __device__ double gap_newton(d3 &n, d3 d, const sym3 &A, const sym3 &B, int maxit) {
-    double F = support_gap(n, d, A, B);
+    GapEval G = gap_eval(n, d, A, B);
     const double dl = len(d);
     for (int it = 0; it < maxit; ++it) {
-        d3 an = mul(A, n), bn = mul(B, n);
-        double ha = sqrt(dot(n, an)), hb = sqrt(dot(n, bn));
-        d3 grad = d - (1.0 / ha) * an - (1.0 / hb) * bn;  // p_b - p_a
+        const d3 an = G.an, bn = G.bn;
+        const double ha = G.ha, hb = G.hb;
+        const double ia = 1.0 / ha, ib = 1.0 / hb;
+        d3 grad = d - ia * an - ib * bn;  // p_b - p_a
         double fn = dot(n, grad);
         d3 e1, e2;
         tangent_frame(n, e1, e2);
         double g1 = dot(e1, grad), g2 = dot(e2, grad);
         double scale = dl + ha + hb;
-        double gnorm = sqrt(g1 * g1 + g2 * g2);
+        double gn2 = g1 * g1 + g2 * g2;
         // Phi is stationary at the maximiser: a tangential gradient of 1e-11
         // of the scale leaves the normal good to ~1e-11 and Phi to ~1e-22
-        if (gnorm <= 1e-11 * scale) break;
+        if (gn2 <= 1e-22 * scale * scale) break;
         // projected Hessian of f on the sphere: P (Hess f) P - (n.grad f) P
         d3 Ae1 = mul(A, e1), Ae2 = mul(A, e2), Be1 = mul(B, e1), Be2 = mul(B, e2);
-        double ia = 1.0 / ha, ib = 1.0 / hb, ia3 = ia * ia * ia, ib3 = ib * ib * ib;
+        double ia3 = ia * ia * ia, ib3 = ib * ib * ib;
         double a1 = dot(e1, an), a2 = dot(e2, an), b1 = dot(e1, bn), b2 = dot(e2, bn);
         double h11 = -(dot(e1, Ae1) * ia - a1 * a1 * ia3) - (dot(e1, Be1) * ib - b1 * b1 * ib3) - fn;
         double h12 = -(dot(e1, Ae2) * ia - a1 * a2 * ia3) - (dot(e1, Be2) * ib - b1 * b2 * ib3);
@@ -60,42 +77,42 @@ __device__ double gap_newton(d3 &n, d3 d, const sym3 &A, const sym3 &B, int maxi
         double det = h11 * h22 - h12 * h12;
         double v1, v2;
         if (h11 < 0.0 && det > 0.0) {
-            v1 = (-h22 * g1 + h12 * g2) / det;
-            v2 = (h12 * g1 - h11 * g2) / det;
+            const double idet = 1.0 / det;
+            v1 = (-h22 * g1 + h12 * g2) * idet;
+            v2 = (h12 * g1 - h11 * g2) * idet;
         } else {
+            const double gnorm = sqrt(gn2);
             double curv = fabs(h11) + fabs(h22) + 2.0 * fabs(h12) + 1e-300;
             double t = 1.0 / curv;
             if (t * gnorm > 0.5) t = 0.5 / gnorm;
             v1 = t * g1;
             v2 = t * g2;
         }
-        double vl = sqrt(v1 * v1 + v2 * v2);
-        if (vl > 0.5) {
-            v1 *= 0.5 / vl;
-            v2 *= 0.5 / vl;
-            vl = 0.5;
+        double vl2 = v1 * v1 + v2 * v2;
+        if (vl2 > 0.25) {
+            const double f = 0.5 / sqrt(vl2);
+            v1 *= f;
+            v2 *= f;
+            vl2 = 0.25;
         }
-        double t = 1.0, Fn = F;
-        d3 nn = n;
+        double t = 1.0;
         bool ok = false;
         for (int ls = 0; ls < 40; ++ls) {
             d3 c = n + t * (v1 * e1 + v2 * e2);
             c = (1.0 / len(c)) * c;
-            double Fc = support_gap(c, d, A, B);
-            if (Fc >= F - 1e-15 * scale) {
-                nn = c;
-                Fn = Fc;
+            const GapEval Gc = gap_eval(c, d, A, B);
+            if (Gc.F >= G.F - 1e-15 * scale) {
+                n = c;
+                G = Gc;
                 ok = true;
                 break;
             }
             t *= 0.5;
         }
         if (!ok) break;
-        n = nn;
-        F = Fn;
-        if (t * vl < 1e-15) break;
+        if (t * t * vl2 < 1e-30) break;
     }
-    return F;
+    return G.F;
 }
 
 // Result: Phi, n (a -> b), r_a = p_a - x_a, r_b = p_b - x_b.

@@ -700,15 +700,20 @@ __global__ void __launch_bounds__(kThreads) k_incidence_jacobian(int m2, const i
 // Entries of row r: for each of its bodies c (a, then b) and each other row
 // j at c (incidence order), dt J_r^c . (K_c J_j^c) with J the column of D at
 // c, then padding entries (the row itself, value 0).  The diagonal A_rr is
-// not stored: a pass takes it from the rows' A_aa.
+// not stored: a pass takes it from the rows' A_aa.  Two threads per row, one
+// per body: a block covers kFillRows rows, its first half of waves at body
+// a (slots from 0), the second at body b (slots after the deg_a - 1 of body
+// a, then the padding); each wave is one slice.
+constexpr int kFillRows = kThreads / 2;
 __global__ void __launch_bounds__(kThreads) k_rowgraph_fill(RowGraphFill A) {
-    const int r = blockIdx.x * kThreads + threadIdx.x;
+    const int side = threadIdx.x / kFillRows;
+    const int r = blockIdx.x * kFillRows + (threadIdx.x & (kFillRows - 1));
     if (r >= A.m) return;
     const int lane = r & (RELCP_WAVE - 1), sl = r / RELCP_WAVE;
     const int b0 = A.base[sl], w = A.base[sl + 1] - b0;
     const int L = A.ldr, lb = A.ldb;
     const d3 nr = mk(A.n[r], A.n[L + r], A.n[2 * L + r]);
-    if (r == 0) {
+    if (r == 0 && side == 0) {
         // the width pass and the scan are complete: report and clear its counter
         A.report[0] = A.base[(A.m + RELCP_WAVE - 1) / RELCP_WAVE];
         A.report[1] = *A.count;
@@ -726,43 +731,46 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_fill(RowGraphFill A) {
     double *__restrict__ v64 = A.val64;
     float *__restrict__ v32 = A.val32;
     constexpr int kU = 4;
+    const int c = side ? A.ib[r] : A.ia[r];
     int k = 0;
-    for (int side = 0; side < 2; ++side) {
-        const int c = side ? A.ib[r] : A.ia[r];
-        const double *tr = side ? A.tb : A.ta;
-        const double sr = side ? 1.0 : -1.0;
-        const d3 ur = mk(tr[r], tr[L + r], tr[2 * L + r]);
-        const double *K = A.K;
-        // K_c applied to this row's column (sign included)
-        const d3 Kn = mk(sr * K[c] * nr.x, sr * K[lb + c] * nr.y, sr * K[2 * lb + c] * nr.z);
-        const sym3 Kr{K[3 * lb + c], K[4 * lb + c], K[5 * lb + c], K[6 * lb + c], K[7 * lb + c], K[8 * lb + c]};
-        const d3 Ku = sr * mul(Kr, ur);
-        const int e1 = A.off[c + 1];
-        for (int e = A.off[c]; e < e1; e += kU) {
-            double J[kU][6];
-            int cj[kU];
+    if (side) {
+        const int a = A.ia[r];
+        k = A.off[a + 1] - A.off[a] - 1;  // the slots of body a's other rows
+    }
+    const double *tr = side ? A.tb : A.ta;
+    const double sr = side ? 1.0 : -1.0;
+    const d3 ur = mk(tr[r], tr[L + r], tr[2 * L + r]);
+    const double *K = A.K;
+    // K_c applied to this row's column (sign included)
+    const d3 Kn = mk(sr * K[c] * nr.x, sr * K[lb + c] * nr.y, sr * K[2 * lb + c] * nr.z);
+    const sym3 Kr{K[3 * lb + c], K[4 * lb + c], K[5 * lb + c], K[6 * lb + c], K[7 * lb + c], K[8 * lb + c]};
+    const d3 Ku = sr * mul(Kr, ur);
+    const int e1 = A.off[c + 1];
+    for (int e = A.off[c]; e < e1; e += kU) {
+        double J[kU][6];
+        int cj[kU];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int eu = e + u < e1 ? e + u : e;
-                const double *Jp = jb + 6 * (size_t)eu;
+        for (int u = 0; u < kU; ++u) {
+            const int eu = e + u < e1 ? e + u : e;
+            const double *Jp = jb + 6 * (size_t)eu;
 #pragma unroll
-                for (int t = 0; t < 6; ++t) J[u][t] = Jp[t];
-                cj[u] = ent[eu] >> 1;
-            }
+            for (int t = 0; t < 6; ++t) J[u][t] = Jp[t];
+            cj[u] = ent[eu] >> 1;
+        }
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                if (e + u < e1 && cj[u] != r) {
-                    const double v = A.dt * (J[u][0] * Kn.x + J[u][1] * Kn.y + J[u][2] * Kn.z + J[u][3] * Ku.x +
-                                             J[u][4] * Ku.y + J[u][5] * Ku.z);
-                    const size_t at = (size_t)RELCP_WAVE * (b0 + k) + lane;
-                    col[at] = cj[u];
-                    v64[at] = v;
-                    v32[at] = (float)v;
-                    ++k;
-                }
+        for (int u = 0; u < kU; ++u) {
+            if (e + u < e1 && cj[u] != r) {
+                const double v = A.dt * (J[u][0] * Kn.x + J[u][1] * Kn.y + J[u][2] * Kn.z + J[u][3] * Ku.x +
+                                         J[u][4] * Ku.y + J[u][5] * Ku.z);
+                const size_t at = (size_t)RELCP_WAVE * (b0 + k) + lane;
+                col[at] = cj[u];
+                v64[at] = v;
+                v32[at] = (float)v;
+                ++k;
             }
         }
     }
+    if (!side) return;
     for (; k < w; ++k) {
         const size_t at = (size_t)RELCP_WAVE * (b0 + k) + lane;
         col[at] = r;
@@ -1132,7 +1140,7 @@ void launch_incidence_jacobian(int m, const int *ent, const double *n, const dou
 }
 
 void launch_rowgraph_fill(const RowGraphFill &a, hipStream_t s) {
-    if (a.m > 0) launch_k(k_rowgraph_fill, dim3(nblk(a.m, kThreads)), dim3(kThreads), 0, s, a);
+    if (a.m > 0) launch_k(k_rowgraph_fill, dim3(nblk(a.m, kFillRows)), dim3(kThreads), 0, s, a);
 }
 
 template <typename T>
