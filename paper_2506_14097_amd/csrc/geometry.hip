@@ -25,27 +25,43 @@ __device__ inline double support_gap(d3 n, d3 d, const sym3 &A, const sym3 &B) {
     return dot(n, d) - sqrt(dot(n, mul(A, n))) - sqrt(dot(n, mul(B, n)));
 }
 
+// 1 / sqrt(q) for q in [1e-4, 1e4] (support radii squared, squared lengths
+// of near-unit vectors): the hardware estimate (v_rsq_f64, relative error
+// well under 1e-6) refined by two Newton steps y <- y + y (1 - q y^2) / 2,
+// each of which squares the relative error, so the result is within a few
+// ulp.  Cheaper than sqrt followed by a division.
+__device__ inline double rsqrt_nr(double q) {
+    double y = __builtin_amdgcn_rsq(q);
+    double e = fma(-q * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-q * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
 __device__ inline void tangent_frame(d3 n, d3 &e1, d3 &e2) {
-    // cross with the coordinate axis least aligned with n
+    // cross with the coordinate axis least aligned with n (|e1|^2 >= 2/3)
     double ax = fabs(n.x), ay = fabs(n.y), az = fabs(n.z);
     d3 a = (ax <= ay && ax <= az) ? mk(1, 0, 0) : ((ay <= az) ? mk(0, 1, 0) : mk(0, 0, 1));
     e1 = cross(n, a);
-    e1 = (1.0 / len(e1)) * e1;
+    e1 = rsqrt_nr(dot(e1, e1)) * e1;
     e2 = cross(n, e1);
 }
 
-// The support gap at n with the pieces a Newton step reuses: A n, B n and
-// the support radii h_a = sqrt(n.A n), h_b.
+// The support gap at a unit n with the pieces a Newton step reuses: A n,
+// B n, the support radii h_a = sqrt(n.A n), h_b and their inverses.
 struct GapEval {
-    double F, ha, hb;
+    double F, ha, hb, ia, ib;
     d3 an, bn;
 };
 __device__ inline GapEval gap_eval(d3 n, d3 d, const sym3 &A, const sym3 &B) {
     GapEval g;
     g.an = mul(A, n);
     g.bn = mul(B, n);
-    g.ha = sqrt(dot(n, g.an));
-    g.hb = sqrt(dot(n, g.bn));
+    const double qa = dot(n, g.an), qb = dot(n, g.bn);
+    g.ia = rsqrt_nr(qa);
+    g.ib = rsqrt_nr(qb);
+    g.ha = qa * g.ia;
+    g.hb = qb * g.ib;
     g.F = dot(n, d) - g.ha - g.hb;
     return g;
 }
@@ -56,7 +72,7 @@ __device__ double gap_newton(d3 &n, d3 d, const sym3 &A, const sym3 &B, int maxi
     for (int it = 0; it < maxit; ++it) {
         const d3 an = G.an, bn = G.bn;
         const double ha = G.ha, hb = G.hb;
-        const double ia = 1.0 / ha, ib = 1.0 / hb;
+        const double ia = G.ia, ib = G.ib;
         d3 grad = d - ia * an - ib * bn;  // p_b - p_a
         double fn = dot(n, grad);
         d3 e1, e2;
@@ -99,7 +115,7 @@ __device__ double gap_newton(d3 &n, d3 d, const sym3 &A, const sym3 &B, int maxi
         bool ok = false;
         for (int ls = 0; ls < 40; ++ls) {
             d3 c = n + t * (v1 * e1 + v2 * e2);
-            c = (1.0 / len(c)) * c;
+            c = rsqrt_nr(dot(c, c)) * c;
             const GapEval Gc = gap_eval(c, d, A, B);
             if (Gc.F >= G.F - 1e-15 * scale) {
                 n = c;
@@ -167,8 +183,8 @@ __device__ Snsd snsd_ellipsoid(d3 d, const sym3 &A, const sym3 &B, d3 hint, bool
     Snsd o;
     o.phi = best;
     o.n = best_n;
-    o.ra = (1.0 / sqrt(dot(best_n, an))) * an;
-    o.rb = (-1.0 / sqrt(dot(best_n, bn))) * bn;
+    o.ra = rsqrt_nr(dot(best_n, an)) * an;
+    o.rb = (-rsqrt_nr(dot(best_n, bn))) * bn;
     return o;
 }
 
@@ -459,38 +475,51 @@ __global__ void __launch_bounds__(256, 4) k_snsd_pairs(SnsdArgs A) {
     double phi = 1e300, marg = 1e300;
     int fl = 0;
     if (k < A.m) {
-        int a = A.pa[k], b = A.pb[k];
-        int pk = A.body_batch ? A.body_batch[a] : 0;
-        d3 d = mk(A.x[b] - A.x[a], A.x[A.ldx + b] - A.x[A.ldx + a], A.x[2 * A.ldx + b] - A.x[2 * A.ldx + a]);
+        const int a = A.pa[k], b = A.pb[k];
+        // Every datum the pair may need is loaded up front, so the loads
+        // form two dependent groups (pair, then bodies) and the packing's
+        // box a third: the hint with the pair indices, then positions,
+        // bounding radii, kind and geometry of both bodies together.
+        d3 hint = mk(1, 0, 0);
+        if (A.hint) hint = mk(A.hint[k], A.hint[A.ldo + k], A.hint[2 * A.ldo + k]);
+        const int pk = A.body_batch ? A.body_batch[a] : 0;
+        const d3 xa = mk(A.x[a], A.x[A.ldx + a], A.x[2 * A.ldx + a]);
+        const d3 xb = mk(A.x[b], A.x[A.ldx + b], A.x[2 * A.ldx + b]);
+        const double rba = A.Rb ? A.Rb[a] : 0.0, rbb = A.Rb ? A.Rb[b] : 0.0;
+        const int kd = A.kind[a];
+        double ga[6], gb[6];
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+            ga[t] = A.geo[t * A.ldg + a];
+            gb[t] = A.geo[t * A.ldg + b];
+        }
         const double *bx = A.boxes + 3 * pk;
-        if (bx[0] > 0.0) d.x -= bx[0] * rint(d.x / bx[0]);
-        if (bx[1] > 0.0) d.y -= bx[1] * rint(d.y / bx[1]);
-        if (bx[2] > 0.0) d.z -= bx[2] * rint(d.z / bx[2]);
+        const double L0 = bx[0], L1 = bx[1], L2 = bx[2];
+        d3 d = xb - xa;
+        if (L0 > 0.0) d.x -= L0 * rint(d.x / L0);
+        if (L1 > 0.0) d.y -= L1 * rint(d.y / L1);
+        if (L2 > 0.0) d.z -= L2 * rint(d.z / L2);
         Snsd s;
         const double dl = len(d);
-        const double sgap = A.Rb ? dl - A.Rb[a] - A.Rb[b] : -1e300;
+        const double sgap = A.Rb ? dl - rba - rbb : -1e300;
         if (sgap > (A.mode == 0 ? A.thresh : 0.0) && dl > 0.0) {
             s.phi = sgap;
             s.n = (1.0 / dl) * d;
-            s.ra = A.Rb[a] * s.n;
-            s.rb = (-A.Rb[b]) * s.n;
-        } else if (A.kind[a] == 0) {
-            sym3 Sa{A.geo[a], A.geo[A.ldg + a], A.geo[2 * A.ldg + a], A.geo[3 * A.ldg + a], A.geo[4 * A.ldg + a],
-                    A.geo[5 * A.ldg + a]};
-            sym3 Sb{A.geo[b], A.geo[A.ldg + b], A.geo[2 * A.ldg + b], A.geo[3 * A.ldg + b], A.geo[4 * A.ldg + b],
-                    A.geo[5 * A.ldg + b]};
-            d3 hint = mk(1, 0, 0);
+            s.ra = rba * s.n;
+            s.rb = (-rbb) * s.n;
+        } else if (kd == 0) {
+            const sym3 Sa{ga[0], ga[1], ga[2], ga[3], ga[4], ga[5]};
+            const sym3 Sb{gb[0], gb[1], gb[2], gb[3], gb[4], gb[5]};
             bool has = false;
             if (A.hint) {
-                hint = mk(A.hint[k], A.hint[A.ldo + k], A.hint[2 * A.ldo + k]);
-                double hl = len(hint);
+                const double hl = len(hint);
                 has = hl > 0.5;
                 if (has) hint = (1.0 / hl) * hint;
             }
-            s = snsd_ellipsoid(d, Sa, Sb, hint, has);
+            s = snsd_ellipsoid(d, Sa, Sb, has ? hint : mk(1, 0, 0), has);
         } else {
-            d3 ta = mk(A.geo[a], A.geo[A.ldg + a], A.geo[2 * A.ldg + a]);
-            d3 tb = mk(A.geo[b], A.geo[A.ldg + b], A.geo[2 * A.ldg + b]);
+            const d3 ta = mk(ga[0], ga[1], ga[2]);
+            const d3 tb = mk(gb[0], gb[1], gb[2]);
             s = snsd_spherocyl(d, ta, A.p[A.ldp + a], A.p[a], tb, A.p[A.ldp + b], A.p[b], A.planar != 0);
         }
         A.out[k] = s.phi;
