@@ -112,7 +112,8 @@ __device__ inline unsigned long long u64_min(unsigned long long a, unsigned long
 // the work sum is the same on every run).
 __global__ void __launch_bounds__(256) k_report(int nt, const unsigned long long *disp, int ns,
                                                 const unsigned long long *phi, const unsigned long long *marg, int nw,
-                                                const double *work, unsigned long long *red_h, double *work_h) {
+                                                const double *work, unsigned long long *red_h, double *work_h,
+                                                int *tok, int seq) {
     __shared__ unsigned long long s0[4], s1[4], s2[4];
     __shared__ double s3[4];
     unsigned long long d = 0ull, p = ~0ull, q = ~0ull;
@@ -148,6 +149,12 @@ __global__ void __launch_bounds__(256) k_report(int nt, const unsigned long long
         red_h[1] = p;
         red_h[2] = q;
         work_h[0] = w;
+        if (tok) {
+            // everything the host reads after this recursion is written: the
+            // token goes last, after a system-scope fence
+            __threadfence_system();
+            *(volatile int *)tok = seq;
+        }
     }
 }
 }  // namespace
@@ -345,6 +352,9 @@ struct relcp_ctx {
     unsigned long long *red_h = nullptr, *red_hd = nullptr;
     double *dbl_h = nullptr, *dbl_hd = nullptr;
     int *int_d = nullptr;
+    // host-mapped token written last by the report kernel of a recursion
+    int *tok_h = nullptr, *tok_d = nullptr;
+    int tok_seq = 0;
     void alloc_host();
 
     ~relcp_ctx() {
@@ -366,6 +376,7 @@ struct relcp_ctx {
         if (int_h) (void)hipHostFree(int_h);
         if (red_h) (void)hipHostFree(red_h);
         if (dbl_h) (void)hipHostFree(dbl_h);
+        if (tok_h) (void)hipHostFree(tok_h);
         if (pk_state_h) (void)hipHostFree(pk_state_h);
         gam_save.release();
         boff_d.release(); roff.release(); rlist.release(); rlist2.release(); rcnt.release(); rE.release();
@@ -436,6 +447,34 @@ struct relcp_ctx {
         t_wait += t.ms();
         ++n_waits;
     }
+    // Wait until a kernel has written a host-mapped int (coherent memory,
+    // written with plain stores) different from `unset`, by polling it:
+    // waking on the stream's completion costs 5-20 us more per wait.  After
+    // 10 s without it, the stream is synchronised (which reports a failed
+    // kernel) and the value read as it is.
+    int wait_mapped(const int *h, int unset) {
+        Timer t;
+        const auto t0 = std::chrono::steady_clock::now();
+        int v;
+        int spins = 0;
+        while ((v = __atomic_load_n(h, __ATOMIC_ACQUIRE)) == unset) {
+            if (++spins == 4096) {
+                spins = 0;
+                if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(10)) {
+                    HIP_OK(hipStreamSynchronize(stream));
+                    v = __atomic_load_n(h, __ATOMIC_ACQUIRE);
+                    break;
+                }
+            }
+        }
+        t_wait += t.ms();
+        ++n_waits;
+        return v;
+    }
+    // the report kernel's token of the last recursion launched
+    void wait_report() {
+        if (wait_mapped(tok_h, tok_seq - 1) != tok_seq) throw Error{RELCP_E_DEVICE, "report token not written"};
+    }
 };
 
 template <typename T>
@@ -453,6 +492,7 @@ void relcp_ctx::alloc_host() {
     if (!int_h) int_h = host_mapped<int>(16, &int_d);
     if (!red_h) red_h = host_mapped<unsigned long long>(8, &red_hd);
     if (!dbl_h) dbl_h = host_mapped<double>(8, &dbl_hd);
+    if (!tok_h) tok_h = host_mapped<int>(1, &tok_d);
 }
 
 // ---------------------------------------------------------------------------
@@ -1365,10 +1405,11 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     // Newton starts from the normals of the accepted trial of the previous
     // step (the same configuration up to the caller's rescale)
     if (hint_ok) sa.hint = snsdt.p + ldp;
+    int_h[0] = -1;  // no GPU work in flight writes it: the compaction below sets the count
     timed(2, [&] { launch_snsd_pairs(sa, stream); });
     compact_flags(pflag.p, np, pcnt.p, sel.p, int_d, scan_scratch, stream);  // count -> int_h[0]
-    sync();
-    int m0 = np > 0 ? int_h[0] : 0;
+    const int m0 = wait_mapped(int_h, -1);
+    if (m0 < 0 || m0 > np) throw Error{RELCP_E_DEVICE, "bad contact count"};
     t_narrow += tm.ms();
     m = 0;
     ensure_rows(m0);
@@ -1410,8 +1451,9 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
             sb.clear = lam.p;  // the pair sums of an accepted step are accumulated there
             timed(2, [&] { launch_snsd_pairs(sb, stream); });
             compact_flags(pflag.p, np, pcnt.p, sel.p, int_d, scan_scratch, stream);  // count -> int_h[0]
+            ++tok_seq;
             hipLaunchKernelGGL(k_report, dim3(1), dim3(256), 0, stream, nt, red.p, np > 0 ? nsb : 0, red.p + nt,
-                               red.p + nt + nsb, nw, work_out.p, red_hd, dbl_hd);
+                               red.p + nt + nsb, nw, work_out.p, red_hd, dbl_hd, tok_d, tok_seq);
         };
         bool tail_ready = false;  // the tail ran on the final multipliers and was waited for
         if (spec) {
@@ -1434,7 +1476,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
                 rg_start<double>(R64, dt, tol, g0, keep);
                 rg_unpack<double>(R64, B64, tol);
                 launch_tail();
-                sync();
+                wait_report();
                 if ((rgr[0].fresh || rgr[1].fresh) && rg_overflowed()) {
                     if (attempt > 0) throw Error{RELCP_E_DEVICE, "row graph sizing failed"};
                     continue;
@@ -1460,7 +1502,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
             if (status == RELCP_OK) {
                 if (again32 || again64) {
                     launch_tail();
-                    sync();
+                    wait_report();
                 }
                 tail_ready = true;
             }
@@ -1491,7 +1533,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         t_lcp += tm.ms();
         if (!tail_ready) {
             launch_tail();
-            sync();
+            wait_report();
         }
         t_narrow += tm.ms();
         int nv = np > 0 ? int_h[0] : 0;
