@@ -2,6 +2,7 @@
 #pragma once
 
 #include "common.h"
+#include "lcp.h"
 
 namespace relcp {
 
@@ -66,9 +67,13 @@ int snsd_blocks(int m);
 // maxdisp: trial_blocks(nb) slots, each the bits of its block's largest
 // surface-point displacement bound
 int trial_blocks(int nb);
+// R, Bd (or null): the FP64 rows with their multipliers and the incidence
+// lists; then the contact velocities vc = K D max(0, gamma) are formed here
+// (and stored to Bd->vc, which must be vc) instead of read from vc.
 void launch_trial(int nb, const double *x, int ldx, const double *q, int ldq, const double *vfree, const double *vc,
                   int ldv, double dt, const int *kind, const double *p, int ldp, const double *Rb, double *xt,
-                  double *qt, double *geo, int ldg, double *vout, unsigned long long *maxdisp, hipStream_t s);
+                  double *qt, double *geo, int ldg, double *vout, unsigned long long *maxdisp, hipStream_t s,
+                  const RowsT<double> *R = nullptr, const BodiesT<double> *Bd = nullptr);
 void launch_snsd_pairs(const SnsdArgs &a, hipStream_t s);
 void launch_cell_assign(int nb, const double *x, int ldx, const int *body_batch, const PackGrid *grids,
                         int *body_cell, int *cell_count, hipStream_t s);

@@ -7,6 +7,7 @@
 // 5.3.  Laws of motion: Sec. 2.1.2 (Eq. law_inertia, Eq. law_overdamped, Eq.
 // ellipsoid_mobility).
 #include "geometry.h"
+#include "scatter.h"
 
 namespace relcp {
 
@@ -396,12 +397,24 @@ __global__ void k_trial(int nb, const double *__restrict__ x, int ldx, const dou
                         const int *__restrict__ kind, const double *__restrict__ p, int ldp,
                         const double *__restrict__ Rb, double *__restrict__ xt, double *__restrict__ qt,
                         double *__restrict__ geo, int ldg, double *__restrict__ vout,
-                        unsigned long long *__restrict__ maxdisp) {
+                        unsigned long long *__restrict__ maxdisp, RowsT<double> R, BodiesT<double> Bd,
+                        int vc_rows) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     double disp = 0.0;
     if (i < nb) {
         double v[6];
-        for (int k = 0; k < 6; ++k) v[k] = vfree[k * ldv + i] + vc[k * ldv + i];
+        if (vc_rows) {
+            // the body's contact velocity K D max(0, gamma) over its incident
+            // rows (the LCP's own scatter arithmetic), kept for later row builds
+            double w[6];
+            scatter_body<double, 0>(R, Bd, i, 0.0, VRegs<double>{w});
+            for (int k = 0; k < 6; ++k) {
+                Bd.vc[k * Bd.ld + i] = w[k];
+                v[k] = vfree[k * ldv + i] + w[k];
+            }
+        } else {
+            for (int k = 0; k < 6; ++k) v[k] = vfree[k * ldv + i] + vc[k * ldv + i];
+        }
         if (vout)
             for (int k = 0; k < 6; ++k) vout[k * ldv + i] = v[k];
         for (int k = 0; k < 3; ++k) xt[k * ldx + i] = x[k * ldx + i] + dt * v[k];
@@ -711,10 +724,13 @@ void launch_body_setup(const BodySetupArgs &a, hipStream_t s) {
 
 void launch_trial(int nb, const double *x, int ldx, const double *q, int ldq, const double *vfree, const double *vc,
                   int ldv, double dt, const int *kind, const double *p, int ldp, const double *Rb, double *xt,
-                  double *qt, double *geo, int ldg, double *vout, unsigned long long *maxdisp, hipStream_t s) {
+                  double *qt, double *geo, int ldg, double *vout, unsigned long long *maxdisp, hipStream_t s,
+                  const RowsT<double> *R, const BodiesT<double> *Bd) {
     if (nb <= 0) return;
+    const bool rows = R && Bd;
     launch_k(k_trial, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, x, ldx, q, ldq, vfree, vc, ldv, dt, kind, p,
-                       ldp, Rb, xt, qt, geo, ldg, vout, maxdisp);
+             ldp, Rb, xt, qt, geo, ldg, vout, maxdisp, rows ? *R : RowsT<double>{}, rows ? *Bd : BodiesT<double>{},
+             rows ? 1 : 0);
 }
 
 int snsd_blocks(int m) { return nblk(m > 0 ? m : 1, 256); }

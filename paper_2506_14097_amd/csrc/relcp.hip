@@ -1205,15 +1205,14 @@ void relcp_ctx::rg_start(const RowsT<T> &R, double dt, double tol, const double 
 
 // The rows' gamma and g from the solve's final iterate, or from its last
 // pass while it has not finished (chosen on the device); FP32 also widens
-// gamma into the FP64 multipliers, FP64 forms the contact velocities K D
-// gamma the trial needs.
+// gamma into the FP64 multipliers.
 template <typename T>
 void relcp_ctx::rg_unpack(const RowsT<T> &R, const BodiesT<T> &Bd, double tol) {
     const int pk = sizeof(T) == 8 ? 1 : 0;
     const RgBufs<T> B = rg_bufs<T>(R, tol);
     launch_rowstate_unpack<T>(m, B.z0, B.z1, B.g0, B.g1, B.C.fin, B.C.done, (rgr[pk].j - 1) & 1, R.gam, R.g,
                               sizeof(T) == 4 ? rgam64.p : nullptr, stream);
-    if constexpr (sizeof(T) == 8) timed(0, [&] { launch_lcp_scatter<T>(0, R, Bd, B.C, 0, stream); });
+    // (FP64: the trial forms the contact velocities K D gamma itself)
 }
 
 // After a wait: true if the last graph assembly overflowed its slots (then
@@ -1357,7 +1356,6 @@ int relcp_ctx::solve_rowgraph_graph(const RowsT<T> &R, const BodiesT<T> &Bd, dou
         // done is set (the stop pass wrote the final state)
         launch_rowstate_unpack<T>(m, B.z0, B.z1, B.g0, B.g1, B.C.fin, nullptr, 0, R.gam, R.g,
                                   sizeof(T) == 4 ? rgam64.p : nullptr, stream);
-        if constexpr (sizeof(T) == 8) timed(0, [&] { launch_lcp_scatter<T>(0, R, Bd, B.C, 0, stream); });
         sync();
         // the stop pass marks done on convergence and at the cap; done_h
         // mirrors convergence only
@@ -1442,8 +1440,12 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
             red.ensure((size_t)nt + 2 * (size_t)nsb);
             launch_work(m, rgam64.p, rg64.p, rqv64.p, work_out.p, stream);
             timed(4, [&] {
+                // row-graph solves leave the contact velocities to the trial
+                const RowsT<double> Rt = rows_of<double>();
+                const BodiesT<double> Bt = bodies_of<double>();
+                const bool vrows = rowgraph_mode();
                 launch_trial(N, x.p, N, q.p, N, vfree.p, vc64.p, N, dt, kind.p, p.p, N, Rb.p, xt.p, qt.p, geot.p, N,
-                             vout.p, red.p, stream);
+                             vout.p, red.p, stream, vrows ? &Rt : nullptr, vrows ? &Bt : nullptr);
             });
             SnsdArgs sb = sa;
             sb.x = xt.p; sb.geo = geot.p; sb.hint = snsd0.p + ldp; sb.out = snsdt.p; sb.mode = 1; sb.flag = pflag.p;
