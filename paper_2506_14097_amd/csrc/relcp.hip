@@ -175,6 +175,10 @@ struct relcp_ctx {
     std::vector<double> box;    // 3 nbatch
     std::vector<double> rmax;   // nbatch
     bool has_fext = false;
+    // overdamped bodies: K, K32, Rb and U_free are constant and the geometry
+    // at C^k is the accepted trial's (geo and geot swap on acceptance), so
+    // the set-up pass runs only after the bodies or forces change
+    bool setup_valid = false;
 
     // bodies (SoA, ld = n)
     DBuf<double> x, q, u, p, rho, fext, xt, qt, geo, geot, Rb, K, vfree, vc64, vout, boxes;
@@ -682,6 +686,7 @@ void relcp_ctx::upload_bodies(const relcp_bodies *B, const relcp_shapes *S) {
     if (pk_state_h) HIP_OK(hipHostFree(pk_state_h));
     HIP_OK(hipHostMalloc((void **)&pk_state_h, nbatch * sizeof(PgdState), hipHostMallocDefault));
     has_fext = false;
+    setup_valid = false;
     nprev = 0;
     m = 0;
     m_acc = 0;
@@ -1387,7 +1392,10 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     ba.u = u.p; ba.ldu = N; ba.fext = has_fext ? fext.p : nullptr; ba.ldf = N;
     ba.dynamics = dynamics; ba.planar = planar; ba.dt = dt;
     ba.geo = geo.p; ba.ldg = N; ba.Rb = Rb.p; ba.K = K.p; ba.ldk = N; ba.K32 = K32.p; ba.vfree = vfree.p; ba.ldv = N;
-    launch_body_setup(ba, stream);
+    if (!(dynamics == RELCP_OVERDAMPED && setup_valid)) {
+        launch_body_setup(ba, stream);
+        setup_valid = dynamics == RELCP_OVERDAMPED;
+    }
 
     // candidate pairs at C^k
     candidate_pairs(S);
@@ -1582,6 +1590,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         // accept: C^{k+1} = C_{n+1}; U^{k+1} = V_n
         std::swap(x.p, xt.p);
         std::swap(q.p, qt.p);
+        std::swap(geo.p, geot.p);  // the trial's geometry is that of C^{k+1}
         std::swap(u.p, vout.p);  // every trial writes all of vout
         // multiplier sum per pair, for the next warm start
         // (lam was cleared by the last trial's SNSD pass)
@@ -1706,6 +1715,7 @@ int relcp_set_external(relcp_ctx *ctx, const double *f) {
     return guarded(ctx, [&]() -> int {
         if (!f) {
             ctx->has_fext = false;
+            ctx->setup_valid = false;
             return RELCP_OK;
         }
         size_t N = ctx->n;
@@ -1719,6 +1729,7 @@ int relcp_set_external(relcp_ctx *ctx, const double *f) {
         HIP_OK(hipMemcpyAsync(ctx->fext.p, t.data(), 6 * N * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
         ctx->sync();
         ctx->has_fext = true;
+        ctx->setup_valid = false;
         return RELCP_OK;
     });
 }
