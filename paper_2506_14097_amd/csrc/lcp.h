@@ -175,11 +175,13 @@ template <typename T>
 int make_spmv_graph(const LcpDev<T> *D, int grid_rows, int k, hipGraphExec_t *out);
 // gamma, g <- the state of the pass that holds the final iterate (fin.iter &
 // 1), or, while the done flag (if given) is not set, that of the last pass
-// launched (parity last_par); gam64 (or null) <- the same gamma in FP64
+// launched (parity last_par); gam64 (or null) <- the same gamma in FP64;
+// work (or null): the per-block sums of gamma (g - qv) of launch_work
+// (work_blocks(m) slots)
 template <typename T>
 void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, const T *g0, const T *g1,
                             const PgdState *fin, const int *done, int last_par, T *gam, T *g, double *gam64,
-                            hipStream_t s);
+                            hipStream_t s, const T *qv = nullptr, double *work = nullptr);
 
 // Passes of the projected-gradient loop.  Iteration j (j = 1, 2, ...) is
 // scatter(mode 1, par = j & 1) then gather(mode 1, par = j & 1); a solve

@@ -895,18 +895,29 @@ __global__ void k_set_lcpdev(LcpDev<T> *D, LcpDev<T> v) {
 }
 
 template <typename T>
-__global__ void k_rowstate_unpack(int m, const RowStep<T> *__restrict__ z0, const RowStep<T> *__restrict__ z1,
-                                  const T *__restrict__ g0, const T *__restrict__ g1,
-                                  const PgdState *__restrict__ fin, const int *__restrict__ done, int last_par,
-                                  T *__restrict__ gam, T *__restrict__ g, double *__restrict__ gam64) {
+__global__ void __launch_bounds__(kThreads)
+    k_rowstate_unpack(int m, const RowStep<T> *__restrict__ z0, const RowStep<T> *__restrict__ z1,
+                      const T *__restrict__ g0, const T *__restrict__ g1, const PgdState *__restrict__ fin,
+                      const int *__restrict__ done, int last_par, T *__restrict__ gam, T *__restrict__ g,
+                      double *__restrict__ gam64, const T *__restrict__ qv, double *__restrict__ work) {
+    __shared__ double sh[4][kWaves];
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= m) return;
-    // a finished solve: the state of its final iterate; else that of the last pass launched
-    const bool odd = (done && !*done) ? (last_par & 1) : (fin->iter & 1);
-    const T v = (odd ? z1 : z0)[r].gam;
-    gam[r] = v;
-    g[r] = (odd ? g1 : g0)[r];
-    if (gam64) gam64[r] = (double)v;
+    double w = 0.0, z0s = 0.0, z1s = 0.0, z2s = 0.0;
+    if (r < m) {
+        // a finished solve: the state of its final iterate; else that of the last pass launched
+        const bool odd = (done && !*done) ? (last_par & 1) : (fin->iter & 1);
+        const T v = (odd ? z1 : z0)[r].gam;
+        const T gv = (odd ? g1 : g0)[r];
+        gam[r] = v;
+        g[r] = gv;
+        if (gam64) gam64[r] = (double)v;
+        if (work) w = (double)v * ((double)gv - (double)qv[r]);
+    }
+    if (work) {
+        // the work partials of this block, as k_work forms them
+        block_reduce4(w, z0s, z1s, z2s, sh);
+        if (threadIdx.x == 0) work[blockIdx.x] = w;
+    }
 }
 
 __global__ void k_promote(int m, const float *__restrict__ a, double *__restrict__ b) {
@@ -1116,10 +1127,10 @@ int make_spmv_graph(const LcpDev<T> *D, int grid_rows, int k, hipGraphExec_t *ou
 template <typename T>
 void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, const T *g0, const T *g1,
                             const PgdState *fin, const int *done, int last_par, T *gam, T *g, double *gam64,
-                            hipStream_t s) {
-    if (m > 0)
-        hipLaunchKernelGGL((k_rowstate_unpack<T>), dim3(nblk(m, 256)), dim3(256), 0, s, m, z0, z1, g0, g1, fin, done,
-                           last_par, gam, g, gam64);
+                            hipStream_t s, const T *qv, double *work) {
+    if (m > 0 || work)
+        hipLaunchKernelGGL((k_rowstate_unpack<T>), dim3(work_blocks(m)), dim3(kThreads), 0, s, m, z0, z1, g0, g1,
+                           fin, done, last_par, gam, g, gam64, qv, work);
 }
 
 #define RELCP_INST(T)                                                                                              \
@@ -1131,7 +1142,8 @@ void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, c
                                      const RowStep<T> *, const T *, RowStep<T> *, T *, const PgdCtl &, double *,  \
                                      int, hipStream_t, double *);                                                 \
     template void launch_rowstate_unpack<T>(int, const RowStep<T> *, const RowStep<T> *, const T *, const T *,    \
-                                            const PgdState *, const int *, int, T *, T *, double *, hipStream_t); \
+                                            const PgdState *, const int *, int, T *, T *, double *, hipStream_t,  \
+                                            const T *, double *);                                                 \
     template void launch_set_lcpdev<T>(LcpDev<T> *, const LcpDev<T> &, hipStream_t);                               \
     template void launch_spmv_dev<T>(const LcpDev<T> *, int, int, hipStream_t);                                    \
     template int make_spmv_graph<T>(const LcpDev<T> *, int, int, hipGraphExec_t *);

@@ -1215,9 +1215,12 @@ template <typename T>
 void relcp_ctx::rg_unpack(const RowsT<T> &R, const BodiesT<T> &Bd, double tol) {
     const int pk = sizeof(T) == 8 ? 1 : 0;
     const RgBufs<T> B = rg_bufs<T>(R, tol);
+    // FP64 also forms the work gamma^T A gamma's partial sums (the trial
+    // forms the contact velocities K D gamma itself)
+    if constexpr (sizeof(T) == 8) work_out.ensure(work_blocks(m));
     launch_rowstate_unpack<T>(m, B.z0, B.z1, B.g0, B.g1, B.C.fin, B.C.done, (rgr[pk].j - 1) & 1, R.gam, R.g,
-                              sizeof(T) == 4 ? rgam64.p : nullptr, stream);
-    // (FP64: the trial forms the contact velocities K D gamma itself)
+                              sizeof(T) == 4 ? rgam64.p : nullptr, stream, sizeof(T) == 8 ? R.qv : nullptr,
+                              sizeof(T) == 8 ? work_out.p : nullptr);
 }
 
 // After a wait: true if the last graph assembly overflowed its slots (then
@@ -1359,8 +1362,10 @@ int relcp_ctx::solve_rowgraph_graph(const RowsT<T> &R, const BodiesT<T> &Bd, dou
             continue;
         }
         // done is set (the stop pass wrote the final state)
+        if constexpr (sizeof(T) == 8) work_out.ensure(work_blocks(m));
         launch_rowstate_unpack<T>(m, B.z0, B.z1, B.g0, B.g1, B.C.fin, nullptr, 0, R.gam, R.g,
-                                  sizeof(T) == 4 ? rgam64.p : nullptr, stream);
+                                  sizeof(T) == 4 ? rgam64.p : nullptr, stream, sizeof(T) == 8 ? R.qv : nullptr,
+                                  sizeof(T) == 8 ? work_out.p : nullptr);
         sync();
         // the stop pass marks done on convergence and at the cap; done_h
         // mirrors convergence only
@@ -1446,7 +1451,8 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         auto launch_tail = [&]() {
             work_out.ensure(nw);
             red.ensure((size_t)nt + 2 * (size_t)nsb);
-            launch_work(m, rgam64.p, rg64.p, rqv64.p, work_out.p, stream);
+            // (row-graph solves: the FP64 unpack has formed the work's partials)
+            if (!rowgraph_mode()) launch_work(m, rgam64.p, rg64.p, rqv64.p, work_out.p, stream);
             timed(4, [&] {
                 // row-graph solves leave the contact velocities to the trial
                 const RowsT<double> Rt = rows_of<double>();
