@@ -38,7 +38,7 @@ struct RowBuildArgs {
     int rec;             // recursion at which the rows are generated
     double dt;
     const double *K;     // 9 comps, ld = ldb
-    const double *vfree; // 6 comps
+    const double *vfree; // 6 comps, or null where U_free is zero
     const double *vc;    // 6 comps (new rows: V_n - U_free) or null (iteration-0 rows)
     int ldb;
     // warm start from the previous step (sorted pair list) or null; with

@@ -57,7 +57,7 @@ __global__ void k_rows_build(RowBuildArgs A) {
     // qv = c + dt D^T U_free, with c = Phi at C^k for iteration-0 rows and
     // c = Phi(C_{n+1}) - dt D^T V_n for rows pulled back from a trial, so
     // that for those qv = Phi(C_{n+1}) - dt D^T (V_n - U_free).
-    double qv = A.vc ? phi - A.dt * rate(A.vc) : phi + A.dt * rate(A.vfree);
+    double qv = A.vc ? phi - A.dt * rate(A.vc) : (A.vfree ? phi + A.dt * rate(A.vfree) : phi);
     // A_rr = dt (n.kt_a n + ta.Kr_a ta + n.kt_b n + tb.Kr_b tb)
     auto quad = [&](int i, d3 t) {
         const double *K = A.K;

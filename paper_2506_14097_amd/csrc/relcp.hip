@@ -853,7 +853,8 @@ void relcp_ctx::build_rows(int nsel, int rec, const double *snsd, const double *
     a.rec = rec;
     a.dt = dt;
     a.K = K.p;
-    a.vfree = vfree.p;
+    // overdamped bodies without external forces: U_free = 0
+    a.vfree = dynamics == RELCP_OVERDAMPED && !has_fext ? nullptr : vfree.p;
     a.vc = vc;
     a.ldb = n;
     a.nprev = warm ? nprev : 0;
