@@ -188,6 +188,67 @@ def lcp_sweep(args):
                       "data": "synthetic", "sizes": out}), flush=True)
 
 
+def two_ellipsoid_study(args):
+    """Timestep refinement of the two-ellipsoid sliding collision (Sec. 5.1,
+    Table 1): ReLCP and LCP-SNSD (the same step with no recursions, the
+    first trial accepted) from t0 = 98 to --t-end at each timestep of --dts,
+    FP64, overlap_tol 1e-5, lcp_tol 1e-12.  Error of a run: root mean square
+    over unit-time samples of the difference of the upper body's centre (x,
+    y) and of the angle of its long axis from the ReLCP run at the finest
+    timestep.  Per run: wall ms per step, the steps that needed recursions,
+    the largest recursion count and the largest accepted overlap."""
+    import torch
+    from paper_2506_14097_amd import inputs as I
+    from paper_2506_14097_amd import relcp as R
+    S = I.glancing_ellipsoids()
+    dts = sorted((float(v) for v in args.dts.split(",")), reverse=True)
+    t0, t_end = S["t0"], args.t_end
+
+    def long_axis_angle(q):
+        s, a, b, c = q
+        # third column of the rotation matrix: the body z (long) axis
+        return np.arctan2(2 * (b * c - s * a), 2 * (a * c + s * b))
+
+    runs = []
+    for dt in dts:
+        for method, mr in (("ReLCP", 64), ("LCP-SNSD", 0)):
+            if method == "LCP-SNSD" and dt == dts[-1] and len(dts) > 1:
+                continue  # the reference timestep: ReLCP only
+            sim = R.Simulation(S["x"], S["q"], S["kind"], S["shape"], S["rho_xi"], S["box"], precision=64,
+                               skin=0.5, max_recursions=mr, warm_start=R.WS_PREV)
+            sim.set_external(S["fext"])
+            n = int(round((t_end - t0) / dt))
+            every = int(round(1.0 / dt))
+            samples, nrec, maxrec, maxov = [], 0, 0, 0.0
+            torch.cuda.synchronize()
+            tw = time.perf_counter()
+            for k in range(1, n + 1):
+                res = sim.step(dt, 1e-5, 1e-12)
+                nrec += res["recursions"] > 0
+                maxrec = max(maxrec, res["recursions"])
+                maxov = max(maxov, res["max_overlap"])
+                if k % every == 0:
+                    x, q, _ = sim.get_state()
+                    samples.append((x[1, 0], x[1, 1], long_axis_angle(q[1])))
+                if k % 100000 == 0:
+                    log("two ellipsoids: %s dt %g step %d of %d" % (method, dt, k, n))
+            el = time.perf_counter() - tw
+            sim.close()
+            runs.append(dict(method=method, dt=dt, steps=n, ms_per_step=1e3 * el / n, steps_with_recursions=int(nrec),
+                             max_recursions=int(maxrec), max_overlap=maxov, samples=np.array(samples)))
+            log("two ellipsoids: %s dt %g: %d steps, %.3f ms/step, %d with recursions, max overlap %.3g" % (
+                method, dt, n, 1e3 * el / n, nrec, maxov))
+    ref = runs[-1]["samples"]
+    out = []
+    for r in runs:
+        e = np.sqrt(((r.pop("samples") - ref) ** 2).mean(axis=0))
+        r.update(err_x=float(e[0]), err_y=float(e[1]), err_angle=float(e[2]))
+        out.append(r)
+    print(json.dumps({"metric": "two-ellipsoid timestep refinement: L2 error against the finest ReLCP run",
+                      "unit": "length, length, rad", "data": "synthetic", "t0": t0, "t_end": t_end,
+                      "xi": float(S["rho_xi"][0]), "runs": out}), flush=True)
+
+
 def packings_workload(args):
     """Batched workload: 512 independent periodic packings (body counts
     log-uniform in [200, 5000], target volume fractions uniform in [0.3,
@@ -316,7 +377,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start comparison")
     ap.add_argument("--learned-steps", type=int, default=50)
-    ap.add_argument("--workload", default="compaction100k", choices=("compaction100k", "packings512", "lcp-sweep"))
+    ap.add_argument("--workload", default="compaction100k",
+                    choices=("compaction100k", "packings512", "lcp-sweep", "two-ellipsoids"))
+    ap.add_argument("--dts", default="0.1,0.01,0.001,0.0001", help="two-ellipsoids: the timesteps")
+    ap.add_argument("--t-end", type=float, default=200.0, help="two-ellipsoids: end time (contact from t = 100)")
     ap.add_argument("--sweep-rows", default="25000,100000,400000,1600000,6400000",
                     help="lcp-sweep: target row counts of the lattice LCPs")
     ap.add_argument("--packings", type=int, default=512)
@@ -344,6 +408,9 @@ def main():
         return
     if args.workload == "lcp-sweep":
         lcp_sweep(args)
+        return
+    if args.workload == "two-ellipsoids":
+        two_ellipsoid_study(args)
         return
     R.lib()
 

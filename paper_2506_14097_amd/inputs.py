@@ -70,6 +70,32 @@ _RSA_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_librsa.so"
 _rsa = None
 
 
+def glancing_ellipsoids(t0: float = 98.0, xi: float = 1.0) -> dict:
+    """The two-ellipsoid sliding collision of Sec. 5.1: identical ellipsoids
+    with semiaxes (1, 1, 2) lying in the x-y plane (long axis turned onto x,
+    then 45 degrees about z), centres 1 apart along x, driven by unit forces
+    along y towards each other (the upper body down, the lower up), linear
+    drag xi with L = 4, open boundaries.  The paper leaves xi and the vertical
+    offset out and puts first contact near t = 100.  The bodies touch at a
+    centre separation of 3 along y (the boundary of the Minkowski sum of two
+    parallel copies) and close at 2 / (4 xi), so the offset that puts first
+    contact at t = 100 is 3 + 50 xi; free motion under a constant force is
+    exact at any timestep, so the bodies start at time t0 as far apart as
+    that offset leaves them then."""
+    half = np.pi / 4
+    qy = np.array([np.cos(half), 0.0, np.sin(half), 0.0])      # body z onto world x
+    qz = np.array([np.cos(half / 2), 0.0, 0.0, np.sin(half / 2)])  # 45 degrees about z
+    s1, v1, s2, v2 = qz[0], qz[1:], qy[0], qy[1:]
+    q = np.concatenate([[s1 * s2 - v1 @ v2], s1 * v2 + s2 * v1 + np.cross(v1, v2)])
+    q /= np.linalg.norm(q)
+    sep = 3.0 + (100.0 - t0) * 2.0 / (4.0 * xi)
+    x = np.array([[-0.5, -0.5 * sep, 0.0], [0.5, 0.5 * sep, 0.0]])
+    fext = np.zeros((2, 6))
+    fext[0, 1], fext[1, 1] = 1.0, -1.0
+    return dict(x=x, q=np.stack([q, q]), kind=np.zeros(2, np.int32), shape=np.array([[1.0, 1.0, 2.0]] * 2),
+                rho_xi=np.full(2, xi), box=np.zeros(3), fext=fext, t0=t0)
+
+
 def build_rsa(force: bool = False) -> str:
     """Compile the placement helper (plain C, gcc)."""
     if force or not os.path.exists(_RSA_LIB) or os.path.getmtime(_RSA_LIB) < os.path.getmtime(_RSA_SRC):
