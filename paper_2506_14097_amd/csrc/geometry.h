@@ -78,10 +78,22 @@ void launch_snsd_pairs(const SnsdArgs &a, hipStream_t s);
 void launch_cell_assign(int nb, const double *x, int ldx, const int *body_batch, const PackGrid *grids,
                         int *body_cell, int *cell_count, hipStream_t s);
 void launch_cell_fill(int nb, const int *body_cell, const int *cell_start, int *cursor, int *items, hipStream_t s);
+// Shapes for the candidate search's second test (all null: bounding spheres
+// only): Sigma (6 comps) or axis (3), kind, shape parameters (3 comps).
+struct PairShapes {
+    const double *geo;
+    int ldg;
+    const int *kind;
+    const double *p;
+    int ldp;
+};
+// Candidate pairs: bounding spheres within skin; with shapes also the support
+// gap along the centre line within skin (it bounds Phi from below, so a pair
+// beyond it is farther than skin apart).
 void launch_pairs(bool fill, int nb, const double *x, int ldx, const double *Rb, const int *body_batch,
                   const PackGrid *grids, const int *body_cell, const int *cell_start, const int *cell_count,
                   const int *items, double skin, int *pair_count, const int *pair_off, int *pa, int *pb, int cap,
-                  hipStream_t s);
+                  hipStream_t s, const PairShapes *shapes = nullptr);
 
 // host helpers of the order keys used by the min reductions
 inline unsigned long long order_key_host(double v) {

@@ -645,6 +645,20 @@ __device__ inline int nbr_cells(int c, int k, const PackGrid &g, int out[3]) {
     return m;
 }
 
+// Support radius h(n) = max over the body of n.(y - x) for a unit n:
+// sqrt(n^T Sigma n) for an ellipsoid, r + (l/2) |t.n| for a spherocylinder
+// (axis t, radius r = p0, length l = p1).
+__device__ inline double support_radius(const PairShapes &S, int i, d3 n) {
+    const double *g = S.geo;
+    const int L = S.ldg;
+    if (S.kind[i] == 0) {
+        const sym3 Sg{g[i], g[L + i], g[2 * L + i], g[3 * L + i], g[4 * L + i], g[5 * L + i]};
+        return sqrt(dot(n, mul(Sg, n)));
+    }
+    const d3 t = mk(g[i], g[L + i], g[2 * L + i]);
+    return S.p[i] + 0.5 * S.p[S.ldp + i] * fabs(dot(t, n));
+}
+
 template <bool kFill>
 __global__ void __launch_bounds__(256) k_pairs(int nb, const double *__restrict__ x, int ldx,
                                                const double *__restrict__ Rb, const int *__restrict__ body_batch,
@@ -652,7 +666,7 @@ __global__ void __launch_bounds__(256) k_pairs(int nb, const double *__restrict_
                                                const int *__restrict__ cell_start, const int *__restrict__ cell_count,
                                                const int *__restrict__ items, double skin,
                                                int *__restrict__ pair_count, const int *__restrict__ pair_off,
-                                               int *__restrict__ pa, int *__restrict__ pb, int cap) {
+                                               int *__restrict__ pa, int *__restrict__ pb, int cap, PairShapes sh) {
     // threads walk the bodies in cell order, so neighbouring lanes scan the
     // same neighbour cells
     int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -681,7 +695,15 @@ __global__ void __launch_bounds__(256) k_pairs(int nb, const double *__restrict_
                     if (g.periodic[0]) dx -= g.box[0] * rint(dx / g.box[0]);
                     if (g.periodic[1]) dy -= g.box[1] * rint(dy / g.box[1]);
                     if (g.periodic[2]) dz -= g.box[2] * rint(dz / g.box[2]);
-                    if (sqrt(dx * dx + dy * dy + dz * dz) - ra - Rb[b] <= skin) {
+                    const double dl = sqrt(dx * dx + dy * dy + dz * dz);
+                    bool near = dl - ra - Rb[b] <= skin;
+                    if (near && sh.geo && dl > 0.0) {
+                        // the support gap along the centre line is a lower
+                        // bound of Phi (Phi is its maximum over normals)
+                        const d3 u = mk(dx / dl, dy / dl, dz / dl);
+                        near = dl - support_radius(sh, a, u) - support_radius(sh, b, u) <= skin;
+                    }
+                    if (near) {
                         if (kFill) {
                             int pos = base + cnt;
                             if (pos < cap) {
@@ -756,14 +778,15 @@ void launch_cell_fill(int nb, const int *body_cell, const int *cell_start, int *
 void launch_pairs(bool fill, int nb, const double *x, int ldx, const double *Rb, const int *body_batch,
                   const PackGrid *grids, const int *body_cell, const int *cell_start, const int *cell_count,
                   const int *items, double skin, int *pair_count, const int *pair_off, int *pa, int *pb, int cap,
-                  hipStream_t s) {
+                  hipStream_t s, const PairShapes *shapes) {
     if (nb <= 0) return;
+    const PairShapes sh = shapes ? *shapes : PairShapes{};
     if (fill)
         launch_k(k_pairs<true>, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, x, ldx, Rb, body_batch, grids,
-                           body_cell, cell_start, cell_count, items, skin, pair_count, pair_off, pa, pb, cap);
+                 body_cell, cell_start, cell_count, items, skin, pair_count, pair_off, pa, pb, cap, sh);
     else
         launch_k(k_pairs<false>, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, x, ldx, Rb, body_batch, grids,
-                           body_cell, cell_start, cell_count, items, skin, pair_count, pair_off, pa, pb, cap);
+                 body_cell, cell_start, cell_count, items, skin, pair_count, pair_off, pa, pb, cap, sh);
 }
 
 }  // namespace relcp

@@ -201,10 +201,11 @@ struct relcp_ctx {
     int nprev = 0, ldprev = 0;
     DBuf<int> prev_a, prev_b;
     // the candidate list pa, pb is kept across steps (a Verlet list): built
-    // with bounding-sphere gap <= skin + 2 margin, it holds every pair within
-    // skin as long as the accumulated bound on how much any gap has shrunk
-    // since the build (vl_used) stays below 2 margin; pairs of the list
-    // beyond skin are cut by a bounding-sphere test in the narrowphase
+    // with bounding-sphere gap and centre-line support gap (a lower bound of
+    // Phi) both <= skin + 2 margin, it holds every pair within skin as long
+    // as the accumulated bound on how much any gap has shrunk since the build
+    // (vl_used) stays below 2 margin; pairs of the list beyond skin are cut by
+    // a bounding-sphere test in the narrowphase
     bool vl_valid = false, prev_is_list = false;
     bool hint_ok = false;  // snsdt holds the normals of the last accepted trial for the current list
     double vl_used = 0.0;
@@ -399,7 +400,7 @@ struct relcp_ctx {
     void upload_bodies(const relcp_bodies *B, const relcp_shapes *S);
     void ensure_pairs(int need);
     void ensure_rows(int need);
-    void broadphase(const double *xs, double skin_);
+    void broadphase(const double *xs, double skin_, bool bound = false);
     void build_rows(int nsel, int rec, const double *snsd, const double *vc, bool warm, double dt);
     void rebuild_csr();
     void warm_start_rows(int m0, double dt);
@@ -736,7 +737,11 @@ void relcp_ctx::ensure_rows(int need) {
 // ---------------------------------------------------------------------------
 // candidate pairs (all a < b of one packing with bounding gap <= skin)
 // ---------------------------------------------------------------------------
-void relcp_ctx::broadphase(const double *xs, double skin_) {
+// Candidate pairs within skin_ of each other's bounding sphere; with bound,
+// also within skin_ by the support gap along the centre line (a lower bound
+// of Phi; needs the geometry of the positions xs in geo).
+void relcp_ctx::broadphase(const double *xs, double skin_, bool bound) {
+    const PairShapes shp{geo.p, n, kind.p, p.p, n};
     const int N = n;
     keys.ensure(6 * nbatch + 1);
     bool any_open = false;
@@ -813,7 +818,7 @@ void relcp_ctx::broadphase(const double *xs, double skin_) {
     launch_cell_fill(N, body_cell.p, cell_start.p, cell_cur, cell_items.p, stream);
     timed(3, [&] {
         launch_pairs(false, N, xs, N, Rb.p, body_batch.p, grids.p, body_cell.p, cell_start.p, cell_count.p,
-                     cell_items.p, skin_, pair_count.p, nullptr, nullptr, nullptr, 0, stream);
+                     cell_items.p, skin_, pair_count.p, nullptr, nullptr, nullptr, 0, stream, bound ? &shp : nullptr);
     });
     exclusive_scan(pair_count.p, pair_off.p, N, int_d, scan_scratch, stream);  // total -> int_h[0]
     sync();
@@ -822,13 +827,15 @@ void relcp_ctx::broadphase(const double *xs, double skin_) {
     ensure_pairs(std::max(np, 1));
     timed(3, [&] {
         launch_pairs(true, N, xs, N, Rb.p, body_batch.p, grids.p, body_cell.p, cell_start.p, cell_count.p,
-                     cell_items.p, skin_, pair_count.p, pair_off.p, pa.p, pb.p, ldp, stream);
+                     cell_items.p, skin_, pair_count.p, pair_off.p, pa.p, pb.p, ldp, stream, bound ? &shp : nullptr);
     });
 }
 
 void relcp_ctx::candidate_pairs(relcp_step_stats &S) {
     if (!vl_valid || vl_used >= 2.0 * vl_margin()) {
-        broadphase(x.p, vl_radius());
+        // the kept list: bounding spheres and the centre-line support gap
+        // within the list radius (the displacement bound covers Phi too)
+        broadphase(x.p, vl_radius(), true);
         vl_valid = true;
         vl_used = 0.0;
         prev_is_list = false;

@@ -415,7 +415,10 @@ def test_candidate_list_kept_across_steps(dev, mode):
         rebuilt.append(res["pairs_rebuilt"])
         print("step", k, "rebuilt", res["pairs_rebuilt"], "pairs", res["n_pairs"], "oracle pairs", ref["n_pairs"],
               flush=True)
-        assert res["n_pairs"] >= ref["n_pairs"]
+        # the kept list leaves out pairs whose centre-line support gap (a lower
+        # bound of Phi) exceeds the list radius, so it can be shorter than the
+        # oracle's bounding-sphere list; the contact sets below show that it
+        # holds every pair within skin
         _compare_step(res, sim, ref, 1e-8)
     assert rebuilt[0] == 1 and sum(rebuilt) < len(rebuilt)
 
