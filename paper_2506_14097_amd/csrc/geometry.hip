@@ -645,18 +645,27 @@ __device__ inline int nbr_cells(int c, int k, const PackGrid &g, int out[3]) {
     return m;
 }
 
-// Support radius h(n) = max over the body of n.(y - x) for a unit n:
-// sqrt(n^T Sigma n) for an ellipsoid, r + (l/2) |t.n| for a spherocylinder
-// (axis t, radius r = p0, length l = p1).
-__device__ inline double support_radius(const PairShapes &S, int i, d3 n) {
-    const double *g = S.geo;
-    const int L = S.ldg;
-    if (S.kind[i] == 0) {
-        const sym3 Sg{g[i], g[L + i], g[2 * L + i], g[3 * L + i], g[4 * L + i], g[5 * L + i]};
-        return sqrt(dot(n, mul(Sg, n)));
-    }
-    const d3 t = mk(g[i], g[L + i], g[2 * L + i]);
-    return S.p[i] + 0.5 * S.p[S.ldp + i] * fabs(dot(t, n));
+// Shape of a body for its support radius h(n) = max over the body of
+// n.(y - x), n a unit vector: sqrt(n^T Sigma n) for an ellipsoid, r + (l/2)
+// |t.n| for a spherocylinder (axis t, radius r = p0, length l = p1).
+struct SupportShape {
+    bool ell;
+    sym3 S;     // Sigma, or the axis in its first three entries
+    double r, l;
+};
+__device__ inline SupportShape support_shape(const PairShapes &P, int i) {
+    const double *g = P.geo;
+    const int L = P.ldg;
+    SupportShape s;
+    s.ell = P.kind[i] == 0;
+    s.S = sym3{g[i], g[L + i], g[2 * L + i], g[3 * L + i], g[4 * L + i], g[5 * L + i]};
+    s.r = s.ell ? 0.0 : P.p[i];
+    s.l = s.ell ? 0.0 : P.p[P.ldp + i];
+    return s;
+}
+__device__ inline double support_radius(const SupportShape &s, d3 n) {
+    if (s.ell) return sqrt(dot(n, mul(s.S, n)));
+    return s.r + 0.5 * s.l * fabs(s.S.xx * n.x + s.S.yy * n.y + s.S.zz * n.z);
 }
 
 template <bool kFill>
@@ -681,6 +690,8 @@ __global__ void __launch_bounds__(256) k_pairs(int nb, const double *__restrict_
     int cz = (int)(local / ((long long)g.nc[0] * g.nc[1]));
     int ox[3], oy[3], oz[3];
     int nx = nbr_cells(cx, 0, g, ox), ny = nbr_cells(cy, 1, g, oy), nz = nbr_cells(cz, 2, g, oz);
+    SupportShape sa{};
+    if (sh.geo) sa = support_shape(sh, a);  // body a's shape, once
     int cnt = 0;
     int base = kFill ? pair_off[a] : 0;
     for (int iz = 0; iz < nz; ++iz)
@@ -701,7 +712,7 @@ __global__ void __launch_bounds__(256) k_pairs(int nb, const double *__restrict_
                         // the support gap along the centre line is a lower
                         // bound of Phi (Phi is its maximum over normals)
                         const d3 u = mk(dx / dl, dy / dl, dz / dl);
-                        near = dl - support_radius(sh, a, u) - support_radius(sh, b, u) <= skin;
+                        near = dl - support_radius(sa, u) - support_radius(support_shape(sh, b), u) <= skin;
                     }
                     if (near) {
                         if (kFill) {
