@@ -105,7 +105,7 @@ typedef struct {
     int32_t recursions;          /* augmentations before acceptance */
     int32_t lcp_iters_total;     /* projected-gradient iterations over all recursions */
     int32_t n_pairs;             /* pairs of the candidate list: bounding-sphere gap and centre-line
-                                    support gap (a lower bound of Phi) <= 1.5 skin when built */
+                                    support gap (a lower bound of Phi) <= 2 skin when built */
     int32_t n_contacts_final;    /* rows at acceptance */
     int32_t n_contacts[RELCP_MAX_RECORDED];
     int32_t lcp_iters[RELCP_MAX_RECORDED];   /* iterations per recursion (all precisions) */

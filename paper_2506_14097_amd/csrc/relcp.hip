@@ -209,7 +209,7 @@ struct relcp_ctx {
     bool vl_valid = false, prev_is_list = false;
     bool hint_ok = false;  // snsdt holds the normals of the last accepted trial for the current list
     double vl_used = 0.0;
-    double vl_margin() const { return 0.25 * skin; }
+    double vl_margin() const { return 0.5 * skin; }
     double vl_radius() const { return skin + 2.0 * vl_margin(); }
     void candidate_pairs(relcp_step_stats &S);
     DBuf<double> prev_lam;
