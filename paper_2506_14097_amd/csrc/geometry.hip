@@ -694,25 +694,55 @@ __global__ void __launch_bounds__(256) k_pairs(int nb, const double *__restrict_
     if (sh.geo) sa = support_shape(sh, a);  // body a's shape, once
     int cnt = 0;
     int base = kFill ? pair_off[a] : 0;
+    // per row of neighbour cells (fixed z and y offsets): the ranges of its
+    // (up to) three cells first, then the candidates in batches of kU whose
+    // indices, then positions, are loaded together; the order is that of the
+    // cells and of their items
+    constexpr int kU = 8;
     for (int iz = 0; iz < nz; ++iz)
-        for (int iy = 0; iy < ny; ++iy)
-            for (int ix = 0; ix < nx; ++ix) {
-                long long c = g.cell_off + ((long long)oz[iz] * g.nc[1] + oy[iy]) * g.nc[0] + ox[ix];
-                int s0 = cell_start[c], s1 = s0 + cell_count[c];
-                for (int t = s0; t < s1; ++t) {
-                    int b = items[t];
-                    if (b <= a) continue;
-                    double dx = x[b] - xa, dy = x[ldx + b] - ya, dz = x[2 * ldx + b] - za;
+        for (int iy = 0; iy < ny; ++iy) {
+            const long long rowc = g.cell_off + ((long long)oz[iz] * g.nc[1] + oy[iy]) * g.nc[0];
+            int s0[3] = {0, 0, 0}, n0[3] = {0, 0, 0};
+#pragma unroll
+            for (int ix = 0; ix < 3; ++ix)
+                if (ix < nx) {
+                    const long long c = rowc + ox[ix];
+                    s0[ix] = cell_start[c];
+                    n0[ix] = cell_count[c];
+                }
+            const int tot = n0[0] + n0[1] + n0[2];
+            for (int j0 = 0; j0 < tot; j0 += kU) {
+                int bb[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int j = j0 + u;
+                    const int tt = j < n0[0] ? s0[0] + j : (j < n0[0] + n0[1] ? s0[1] + j - n0[0] : s0[2] + j - n0[0] - n0[1]);
+                    bb[u] = j < tot ? items[tt] : -1;
+                }
+                double bx[kU], by[kU], bz[kU], br[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int b = bb[u] > a ? bb[u] : a;  // a itself for a skipped slot: in bounds
+                    bx[u] = x[b];
+                    by[u] = x[ldx + b];
+                    bz[u] = x[2 * ldx + b];
+                    br[u] = Rb[b];
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int b = bb[u];
+                    if (b <= a) continue;  // also past the last candidate (b = -1)
+                    double dx = bx[u] - xa, dy = by[u] - ya, dz = bz[u] - za;
                     if (g.periodic[0]) dx -= g.box[0] * rint(dx / g.box[0]);
                     if (g.periodic[1]) dy -= g.box[1] * rint(dy / g.box[1]);
                     if (g.periodic[2]) dz -= g.box[2] * rint(dz / g.box[2]);
                     const double dl = sqrt(dx * dx + dy * dy + dz * dz);
-                    bool near = dl - ra - Rb[b] <= skin;
+                    bool near = dl - ra - br[u] <= skin;
                     if (near && sh.geo && dl > 0.0) {
                         // the support gap along the centre line is a lower
                         // bound of Phi (Phi is its maximum over normals)
-                        const d3 u = mk(dx / dl, dy / dl, dz / dl);
-                        near = dl - support_radius(sa, u) - support_radius(support_shape(sh, b), u) <= skin;
+                        const d3 u3 = mk(dx / dl, dy / dl, dz / dl);
+                        near = dl - support_radius(sa, u3) - support_radius(support_shape(sh, b), u3) <= skin;
                     }
                     if (near) {
                         if (kFill) {
@@ -726,6 +756,7 @@ __global__ void __launch_bounds__(256) k_pairs(int nb, const double *__restrict_
                     }
                 }
             }
+        }
     if (!kFill) {
         pair_count[a] = cnt;
     } else {
