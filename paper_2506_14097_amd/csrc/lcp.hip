@@ -112,10 +112,27 @@ __global__ void k_rows_build(RowBuildArgs A) {
 // ---------------------------------------------------------------------------
 // incidence lists (CSR by body)
 // ---------------------------------------------------------------------------
+// Runs of equal keys over consecutive lanes of a wave (the rows of a
+// step's first set are sorted by their first body): the lane's run head,
+// and the run's length (valid at the head).  Inactive lanes (key -1) form
+// runs of their own.
+__device__ inline void key_runs(int key, int &head, int &len) {
+    const int lane = threadIdx.x & (RELCP_WAVE - 1);
+    const int prev = __shfl_up(key, 1, RELCP_WAVE);
+    const unsigned long long heads = __ballot(lane == 0 || prev != key);
+    head = RELCP_WAVE - 1 - __clzll(heads & ((2ull << lane) - 1ull));
+    const unsigned long long above = lane == RELCP_WAVE - 1 ? 0ull : heads & (~0ull << (lane + 1));
+    len = (above ? __ffsll((long long)above) - 1 : RELCP_WAVE) - lane;
+}
+
 __global__ void k_csr_count(int m, const int *__restrict__ ia, const int *__restrict__ ib, int *__restrict__ cnt) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int a = r < m ? ia[r] : -1;
+    int head, len;
+    key_runs(a, head, len);
     if (r >= m) return;
-    atomicAdd(cnt + ia[r], 1);
+    // one atomic per run of rows sharing their first body
+    if ((threadIdx.x & (RELCP_WAVE - 1)) == head) atomicAdd(cnt + a, len);
     atomicAdd(cnt + ib[r], 1);
 }
 
@@ -130,9 +147,18 @@ __global__ void __launch_bounds__(256) k_csr_fill(int m, const int *__restrict__
                                                   int *__restrict__ count) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     int w = 0;
+    const int a = r < m ? ia[r] : -1;
+    int head, len;
+    key_runs(a, head, len);
+    // a run of rows sharing their first body takes consecutive slots there
+    // with one atomic (the sort pass orders each body's list afterwards)
+    const int lane = threadIdx.x & (RELCP_WAVE - 1);
+    int slot = 0;
+    if (r < m && lane == head) slot = atomicAdd(cursor + a, len);
+    slot = __shfl(slot, head, RELCP_WAVE) + (lane - head);
     if (r < m) {
-        const int a = ia[r], b = ib[r];
-        ent[off[a] + atomicAdd(cursor + a, 1)] = r << 1;
+        const int b = ib[r];
+        ent[off[a] + slot] = r << 1;
         ent[off[b] + atomicAdd(cursor + b, 1)] = (r << 1) | 1;
         w = off[a + 1] - off[a] + off[b + 1] - off[b] - 2;  // the row itself at a and at b: the diagonal
     }
@@ -144,7 +170,7 @@ __global__ void __launch_bounds__(256) k_csr_fill(int m, const int *__restrict__
         sum += __shfl_xor(sum, o, RELCP_WAVE);
     }
     const int ns = (m + RELCP_WAVE - 1) / RELCP_WAVE;
-    const int lane = threadIdx.x & (RELCP_WAVE - 1), wv = threadIdx.x / RELCP_WAVE;
+    const int wv = threadIdx.x / RELCP_WAVE;
     if (lane == 0) {
         if (r / RELCP_WAVE < ns) width[r / RELCP_WAVE] = w;
         bsum[wv] = sum;
