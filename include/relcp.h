@@ -84,8 +84,10 @@ typedef struct {
  * max_recursions: cap on Alg. 1 augmentations (0 = the plain single-
  * constraint SNSD LCP, first trial always accepted).  lcp_max_iters: cap on
  * projected-gradient iterations per LCP (0 = 100000).  skin: near-contact
- * distance delta_c; pairs whose bounding spheres are within skin are
- * candidates and pairs with Phi_0 <= skin start in A_0.  warm_start: start
+ * distance delta_c: pairs with Phi_0 <= skin start in A_0 (the candidate
+ * search examines pairs whose bounding spheres and whose support gap along
+ * the centre line, a lower bound of Phi, are both within 2 skin, and keeps
+ * that list while a bound on the bodies' displacement allows).  warm_start: start
  * of the iteration-0 LCP, RELCP_WS_COLD (zero) or RELCP_WS_PREV (the pair's
  * previous-step multiplier sum, the default); RELCP_WS_LEARNED is selected
  * with relcp_set_warm_start once a model is installed.  stream: a
@@ -119,7 +121,8 @@ typedef struct {
     double t_narrow, t_lcp, t_other; /* milliseconds (host clock, stream-synchronised) */
     int32_t rowgraph_entries[RELCP_MAX_RECORDED]; /* off-diagonal entries of A over rows per recursion (row-graph LCP mode; 0 otherwise) */
     int32_t pairs_rebuilt;       /* 1 if the candidate list was rebuilt at this step (it is kept while valid) */
-    int32_t n_waits;             /* host waits on the stream during the step */
+    int32_t n_waits;             /* host waits during the step (polls of results the kernels write to
+                                    host-mapped memory, or stream synchronisations) */
     double t_wait;               /* milliseconds of host clock spent in those waits */
 } relcp_step_stats;
 
