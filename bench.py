@@ -41,7 +41,7 @@ MEASURED_TRAFFIC = {"sha256_prefix": "0b3f7c108d1bfa48", "lcp_rowgraph": 1.4027e
 
 # timing class -> kernel
 KERNEL_SYMBOLS = {"lcp_rowgraph": "relcp::k_spmv<float, 1>", "lcp_rowgraph64": "relcp::k_spmv<double, 1>",
-                  "lcp_rowgraph_start": "relcp::k_spmv<T, 0>", "lcp_gather": "relcp::k_gather<T, 1>",
+                  "lcp_rowgraph_start": "relcp::k_spmv<T, 0> / k_spmv<double, 3>", "lcp_gather": "relcp::k_gather<T, 1>",
                   "lcp_scatter": "relcp::k_scatter<T, 1>"}
 
 

@@ -132,15 +132,27 @@ void launch_incidence_jacobian(int m, const int *ent, const double *n, const dou
                                double *jb, hipStream_t s);
 void launch_rowgraph_fill(const RowGraphFill &a, hipStream_t s);
 // One pass of the row-graph LCP loop over m rows with A in G and the
-// diagonal dA.  mode 0: start, gamma0 = max(0, gam0) (FP64 start rounded to
+// diagonal dA.  mode 0: start, gamma0 = max(0, start) (FP64 start rounded to
 // T), g at gamma0, and the control block C reset for a new solve; mode 1:
 // iteration with parity par, reading the previous pass's state (zin, gin)
 // and partials, writing (zout, gout) and its own partials pout; mode 2: the
 // same iteration with the partials reduced first by a one-block launch
 // (for passes over many blocks; identical iterates).  save (mode 0, or
-// null): receives gam0 (the start, for a restart).
+// null): receives the start in FP64 (kept for a restart, or as the FP64
+// multipliers when the start is an FP32 solve's state).
+// The start gamma0 of a row-graph solve: gam64 (FP64 multipliers), or, with
+// gam64 null, the final state of an FP32 row-graph solve widened to FP64 --
+// z[fin.iter & 1], or z[last_par & 1] while its done flag is not set (the
+// state k_rowstate_unpack would pick).
+struct StartSrc {
+    const double *gam64;
+    const RowStep<float> *z[2];
+    const PgdState *fin;
+    const int *done;
+    int last_par;
+};
 template <typename T>
-void launch_lcp_spmv(int mode, const RowGraphT<T> &G, const T *qv, const T *dA, const double *gam0,
+void launch_lcp_spmv(int mode, const RowGraphT<T> &G, const T *qv, const T *dA, const StartSrc &start,
                      const RowStep<T> *zin, const T *gin, RowStep<T> *zout, T *gout, const PgdCtl &C, double *pout,
                      int par, hipStream_t s, double *save = nullptr);
 // Parameters of a row-graph solve in device memory, read by k_spmv_dev:

@@ -21,6 +21,8 @@
 // D^T vc -> g' with the step-size reductions.  The last block of the gather
 // finishes the reductions in a fixed order, so the result does not depend
 // on block scheduling.
+#include <type_traits>
+
 #include "lcp.h"
 #include "scatter.h"
 
@@ -732,6 +734,23 @@ __device__ inline float step_h(float gm, float h, float al) {
 // reduction that yields the step length.
 constexpr int kPre = 16;
 
+// The start values of a solve as its start pass reads them (see StartSrc):
+// an FP64 array, or the final state of an FP32 solve; a compile-time choice,
+// so the start pass's loads carry no branch.
+struct StartF64 {
+    const double *g;
+    __device__ double operator[](int j) const { return g[j]; }
+    __device__ static StartF64 from(const StartSrc &S) { return StartF64{S.gam64}; }
+};
+struct StartF32 {
+    const RowStep<float> *z;
+    __device__ double operator[](int j) const { return (double)z[j].gam; }
+    __device__ static StartF32 from(const StartSrc &S) {
+        const bool odd = (S.done && !*S.done) ? (S.last_par & 1) : (S.fin->iter & 1);
+        return StartF32{S.z[odd ? 1 : 0]};
+    }
+};
+
 template <typename T>
 struct RowPre {
     int w;
@@ -742,9 +761,9 @@ struct RowPre {
     T vj[kPre], gj[kPre], hj[kPre];
 };
 
-template <typename T, int MODE>
+template <typename T, int MODE, class SV>
 __device__ inline void row_preload(const RowGraphT<T> &G, const T *__restrict__ qv, const T *__restrict__ dA0,
-                                   const double *__restrict__ gam0, const RowStep<T> *__restrict__ zin,
+                                   const SV &gam0, const RowStep<T> *__restrict__ zin,
                                    const T *__restrict__ gin, int r, RowPre<T> &P) {
     const int lane = r & (RELCP_WAVE - 1), sl = r / RELCP_WAVE;
     const int b0 = G.base[sl];
@@ -784,9 +803,9 @@ __device__ inline void row_preload(const RowGraphT<T> &G, const T *__restrict__ 
 
 // projected steps, g' = qv + A gamma', the row's new state and its share
 // of the step-size sums (s^T D s, s^T y, y^T D^-1 y) and residual
-template <typename T, int MODE>
+template <typename T, int MODE, class SV>
 __device__ inline void row_finish(const RowPre<T> &P, T al, const RowStep<T> *__restrict__ zin,
-                                  const double *__restrict__ gam0, RowStep<T> *__restrict__ zout, T *__restrict__ gout,
+                                  const SV &gam0, RowStep<T> *__restrict__ zout, T *__restrict__ gout,
                                   int r, double &ss, double &sy, double &yy, double &res) {
     // the diagonal first (A_rr, not stored in the graph), then the entries
     const T gv = MODE == 1 ? step_h(P.gm, P.hm, al) : clamp0(P.gm);
@@ -821,20 +840,25 @@ __device__ inline void row_finish(const RowPre<T> &P, T al, const RowStep<T> *__
 // length, overlapped with the row's loads.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads)
-    k_spmv(RowGraphT<T> G, const T *__restrict__ qv, const T *__restrict__ dA0, const double *__restrict__ gam0,
+    k_spmv(RowGraphT<T> G, const T *__restrict__ qv, const T *__restrict__ dA0, StartSrc start,
            const RowStep<T> *__restrict__ zin, const T *__restrict__ gin, RowStep<T> *__restrict__ zout,
            T *__restrict__ gout, PgdCtl C, double *__restrict__ pout, int par, double *__restrict__ save) {
     __shared__ double sh[4][kWaves];
     __shared__ PgdState ns;
-    constexpr int RM = MODE == 0 ? 0 : 1;  // row arithmetic: start or iteration
-    if (MODE != 0 && *C.done) return;
-    if (MODE == 0 && blockIdx.x == 0 && threadIdx.x == 0) pgd_reset(C);
+    // MODE 3: a start from the final state of an FP32 solve (StartF32)
+    constexpr bool START = MODE == 0 || MODE == 3;
+    constexpr int RM = START ? 0 : 1;  // row arithmetic: start or iteration
+    using SV = typename std::conditional<MODE == 3, StartF32, StartF64>::type;
+    if (!START && *C.done) return;
+    if (START && blockIdx.x == 0 && threadIdx.x == 0) pgd_reset(C);
     const int lb = xcd_block(blockIdx.x, gridDim.x);  // logical block: a contiguous row range per XCD
     const int r = lb * kThreads + threadIdx.x;
     const bool act = r < G.m;
+    SV gam0{};
+    if (START) gam0 = SV::from(start);
     RowPre<T> P;
-    if (act) row_preload<T, RM>(G, qv, dA0, gam0, zin, gin, r, P);
-    if (MODE == 0 && save && act) save[r] = gam0[r];  // the start, kept for a restart
+    if (act) row_preload<T, RM, SV>(G, qv, dA0, gam0, zin, gin, r, P);
+    if (START && save && act) save[r] = gam0[r];  // the start, kept for a restart
     T al = T(0);
     if (MODE == 2) {
         // the state was advanced by k_pgd_reduce
@@ -857,7 +881,7 @@ __global__ void __launch_bounds__(kThreads)
         al = (T)ns.alpha;
     }
     double ss = 0.0, sy = 0.0, yy = 0.0, res = 0.0;
-    if (act) row_finish<T, RM>(P, al, zin, gam0, zout, gout, r, ss, sy, yy, res);
+    if (act) row_finish<T, RM, SV>(P, al, zin, gam0, zout, gout, r, ss, sy, yy, res);
     block_reduce4(ss, sy, yy, res, sh);
     if (threadIdx.x == 0) {
         double *p = pout + 4 * lb;
@@ -886,7 +910,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_dev(const LcpDev<T> *__restri
     const int r = lb * kThreads + threadIdx.x;
     const bool act = r < d.m;
     RowPre<T> P;
-    if (act) row_preload<T, 1>(G, d.qv, d.dA, nullptr, d.z[par ^ 1], d.g[par ^ 1], r, P);
+    if (act) row_preload<T, 1, StartF64>(G, d.qv, d.dA, StartF64{nullptr}, d.z[par ^ 1], d.g[par ^ 1], r, P);
     PgdCtl C{d.S, d.fin, d.done, d.part[par ^ 1], nbg, d.tol, d.fin_h, d.done_h};
     reduce_partials(C, par, &ns, sh);
     const bool stop = ns.conv || ns.iter >= d.cap;
@@ -903,7 +927,9 @@ __global__ void __launch_bounds__(kThreads) k_spmv_dev(const LcpDev<T> *__restri
     }
     if (stop) return;
     double ss = 0.0, sy = 0.0, yy = 0.0, res = 0.0;
-    if (act) row_finish<T, 1>(P, (T)ns.alpha, d.z[par ^ 1], nullptr, d.z[par], d.g[par], r, ss, sy, yy, res);
+    if (act)
+        row_finish<T, 1, StartF64>(P, (T)ns.alpha, d.z[par ^ 1], StartF64{nullptr}, d.z[par], d.g[par], r, ss, sy,
+                                   yy, res);
     block_reduce4(ss, sy, yy, res, sh);
     if (threadIdx.x == 0) {
         double *p = d.part[par] + 4 * lb;
@@ -1092,20 +1118,23 @@ void launch_rowgraph_fill(const RowGraphFill &a, hipStream_t s) {
 }
 
 template <typename T>
-void launch_lcp_spmv(int mode, const RowGraphT<T> &G, const T *qv, const T *dA, const double *gam0,
+void launch_lcp_spmv(int mode, const RowGraphT<T> &G, const T *qv, const T *dA, const StartSrc &gam0,
                      const RowStep<T> *zin, const T *gin, RowStep<T> *zout, T *gout, const PgdCtl &C, double *pout,
                      int par, hipStream_t s, double *save) {
     const int nb = nblk(G.m > 0 ? G.m : 1, kThreads);
-    if (mode == 0) {
-        launch_k(k_spmv<T, 0>, dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C,
-                           pout, par, save);
+    if (mode == 0 && gam0.gam64) {
+        launch_k(k_spmv<T, 0>, dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C, pout, par,
+                 save);
+    } else if (mode == 0) {
+        launch_k(k_spmv<T, 3>, dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C, pout, par,
+                 save);
     } else if (mode == 2) {
         hipLaunchKernelGGL(k_pgd_reduce, dim3(1), dim3(kThreads), 0, s, C, par);
-        launch_k(k_spmv<T, 2>, dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C, pout,
-                 par, (double *)nullptr);
+        launch_k(k_spmv<T, 2>, dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C, pout, par,
+                 (double *)nullptr);
     } else
-        launch_k(k_spmv<T, 1>, dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C,
-                           pout, par, (double *)nullptr);
+        launch_k(k_spmv<T, 1>, dim3(nb), dim3(kThreads), 0, s, G, qv, dA, gam0, zin, gin, zout, gout, C, pout, par,
+                 (double *)nullptr);
 }
 
 template <typename T>
@@ -1164,7 +1193,7 @@ void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, c
                                         hipStream_t);                                                             \
     template void launch_lcp_gather<T>(int, const RowsT<T> &, const BodiesT<T> &, double, const PgdCtl &, int,    \
                                        hipStream_t);                                                              \
-    template void launch_lcp_spmv<T>(int, const RowGraphT<T> &, const T *, const T *, const double *,             \
+    template void launch_lcp_spmv<T>(int, const RowGraphT<T> &, const T *, const T *, const StartSrc &,           \
                                      const RowStep<T> *, const T *, RowStep<T> *, T *, const PgdCtl &, double *,  \
                                      int, hipStream_t, double *);                                                 \
     template void launch_rowstate_unpack<T>(int, const RowStep<T> *, const RowStep<T> *, const T *, const T *,    \

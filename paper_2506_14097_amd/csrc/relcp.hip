@@ -435,7 +435,8 @@ struct relcp_ctx {
     template <typename T>
     void rg_passes(const RgBufs<T> &B, const RowsT<T> &R, int k);
     template <typename T>
-    void rg_start(const RowsT<T> &R, double dt, double tol, const double *gam0, double *save);
+    void rg_start(const RowsT<T> &R, double dt, double tol, const double *gam0, double *save,
+                  const StartSrc *src = nullptr);
     DBuf<double> gam_save;  // the start of the first solve of a recursion, for a restart
     template <typename T>
     void rg_unpack(const RowsT<T> &R, const BodiesT<T> &Bd, double tol);
@@ -1179,7 +1180,7 @@ void relcp_ctx::rg_passes(const RgBufs<T> &B, const RowsT<T> &R, int k) {
         c.partials = B.part + (size_t)(par ^ 1) * B.stride;  // the previous pass's partial sums
         if (timing) pass_ev.push_back(PassEv{ev_used / 2, st.j, pk});
         timed(sizeof(T) == 4 ? 7 : 10, [&] {
-            launch_lcp_spmv<T>(st.pass_mode, B.G, R.qv, R.dA, nullptr, par ? B.z0 : B.z1, par ? B.g0 : B.g1,
+            launch_lcp_spmv<T>(st.pass_mode, B.G, R.qv, R.dA, StartSrc{}, par ? B.z0 : B.z1, par ? B.g0 : B.g1,
                                par ? B.z1 : B.z0, par ? B.g1 : B.g0, c, B.part + (size_t)par * B.stride, par, stream);
         });
     }
@@ -1190,7 +1191,10 @@ void relcp_ctx::rg_passes(const RgBufs<T> &B, const RowsT<T> &R, int k) {
 // solve's count plus the pass that sees convergence and a spare).  Nothing
 // is waited for.
 template <typename T>
-void relcp_ctx::rg_start(const RowsT<T> &R, double dt, double tol, const double *gam0, double *save) {
+// Start of a row-graph solve from gam0, or from src (with gam0 null): the
+// final state of the FP32 solve, for the FP64 polish.
+void relcp_ctx::rg_start(const RowsT<T> &R, double dt, double tol, const double *gam0, double *save,
+                         const StartSrc *src) {
     const int pk = sizeof(T) == 8 ? 1 : 0;
     RgRun &st = rgr[pk];
     st.fresh = false;
@@ -1201,7 +1205,8 @@ void relcp_ctx::rg_start(const RowsT<T> &R, double dt, double tol, const double 
     const RgBufs<T> B = rg_bufs<T>(R, tol);
     // the start pass also resets the control block
     timed(11, [&] {
-        launch_lcp_spmv<T>(0, B.G, R.qv, R.dA, gam0, nullptr, nullptr, B.z0, B.g0, B.C, B.part, 0, stream, save);
+        const StartSrc start = src ? *src : StartSrc{gam0, {nullptr, nullptr}, nullptr, nullptr, 0};
+        launch_lcp_spmv<T>(0, B.G, R.qv, R.dA, start, nullptr, nullptr, B.z0, B.g0, B.C, B.part, 0, stream, save);
     });
     st.j = 1;
     // the last solve's count, the pass that sees convergence and headroom: a
@@ -1290,8 +1295,8 @@ int relcp_ctx::rg_finish(const RowsT<T> &R, const BodiesT<T> &Bd, double tol, in
 // Row-graph LCP loop, one solve waited for: pass 0 forms g at the start,
 // pass j (parity j & 1) reads state buffer z[(j - 1) & 1] and the partials
 // of pass j - 1 and writes z[j & 1] and its own partials; the final iterate
-// is unpacked into the rows' gamma and g, and (FP64) the contact velocities
-// K D gamma that the trial integration needs are formed once.  LCP mode 3
+// is unpacked into the rows' gamma and g (FP64: with the work's partial
+// sums; the trial forms the contact velocities K D gamma).  LCP mode 3
 // replays the passes from an instantiated graph.
 template <typename T>
 int relcp_ctx::solve_rowgraph(const RowsT<T> &R, const BodiesT<T> &Bd, double dt, double tol, int &iters,
@@ -1344,7 +1349,8 @@ int relcp_ctx::solve_rowgraph_graph(const RowsT<T> &R, const BodiesT<T> &Bd, dou
         v.S = B.C.S; v.fin = B.C.fin; v.done = B.C.done; v.fin_h = B.C.fin_h; v.done_h = B.C.done_h;
         launch_set_lcpdev<T>(dev, v, stream);
         timed(11, [&] {
-            launch_lcp_spmv<T>(0, B.G, R.qv, R.dA, rgam64.p, nullptr, nullptr, B.z0, B.g0, B.C, B.part, 0, stream);
+            launch_lcp_spmv<T>(0, B.G, R.qv, R.dA, StartSrc{rgam64.p, {nullptr, nullptr}, nullptr, nullptr, 0}, nullptr,
+                               nullptr, B.z0, B.g0, B.C, B.part, 0, stream);
         });
         int j = 1;
         int chunk = std::max(2, std::min(64, (last_iters[pk] + 3) & ~1));
@@ -1493,11 +1499,15 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
                 double *keep = attempt ? nullptr : gam_save.p;
                 if (precision == 32) {
                     rg_start<float>(R32, dt, tol, g0, keep);
-                    rg_unpack<float>(R32, B32, tol);
-                    g0 = rgam64.p;
-                    keep = nullptr;
+                    // the polish starts from the FP32 solve's final state
+                    // (picked on the device, no unpack) and keeps it, in
+                    // FP64, in the multipliers
+                    const RgBufs<float> Bf = rg_bufs<float>(R32, tol);
+                    const StartSrc src{nullptr, {Bf.z0, Bf.z1}, Bf.C.fin, Bf.C.done, (rgr[0].j - 1) & 1};
+                    rg_start<double>(R64, dt, tol, nullptr, rgam64.p, &src);
+                } else {
+                    rg_start<double>(R64, dt, tol, g0, keep);
                 }
-                rg_start<double>(R64, dt, tol, g0, keep);
                 rg_unpack<double>(R64, B64, tol);
                 launch_tail();
                 wait_report();
