@@ -181,9 +181,12 @@ void exclusive_scan(const int *in, int *out, int n, int *total_dev, DBuf<int> &s
 // scan.hip: out[j] = index of the j-th set flag (increasing), the count to
 // total_dev[0] when not null.  bcount: the set flags of each group of 256
 // (flag_groups(n) entries, written by the flags' producer), or null to count
-// them here.  out must not alias flags.
+// them here.  out must not alias flags.  rep (optional): a tail report
+// (report.h) that the compaction's last workgroup writes after the count;
+// returns whether it was written (false when n <= 0: nothing was launched).
+struct TailReport;
 int flag_groups(int n);
-void compact_flags(const int *flags, int n, const int *bcount, int *out, int *total_dev, DBuf<int> &scratch,
-                   hipStream_t s);
+bool compact_flags(const int *flags, int n, const int *bcount, int *out, int *total_dev, DBuf<int> &scratch,
+                   hipStream_t s, const TailReport *rep = nullptr);
 
 }  // namespace relcp

@@ -18,6 +18,7 @@
 #include "geometry.h"
 #include "lcp.h"
 #include "mlp.h"
+#include "report.h"
 
 static_assert(RELCP_MLP_NPARAM == relcp::MLP_NPARAM && RELCP_MLP_NORM == relcp::MLP_NORM, "model layout");
 
@@ -100,63 +101,8 @@ struct Timer {
 // small bookkeeping kernels of the step
 // ---------------------------------------------------------------------------
 namespace {
-// Fixed-order reduction of the per-block results of one recursion's tail:
-// largest displacement bound (trial), smallest Phi key and margin key
-// (narrowphase at the trial), work sum; written to host-mapped memory.
-__device__ inline unsigned long long u64_max(unsigned long long a, unsigned long long b) { return a > b ? a : b; }
-__device__ inline unsigned long long u64_min(unsigned long long a, unsigned long long b) { return a < b ? a : b; }
-
-// Sums of the per-block results of a trial into host-mapped memory: the
-// largest displacement key, the smallest Phi and margin keys and the work
-// gamma^T A gamma (strided per-thread sums, then a fixed shuffle tree, so
-// the work sum is the same on every run).
-__global__ void __launch_bounds__(256) k_report(int nt, const unsigned long long *disp, int ns,
-                                                const unsigned long long *phi, const unsigned long long *marg, int nw,
-                                                const double *work, unsigned long long *red_h, double *work_h,
-                                                int *tok, int seq) {
-    __shared__ unsigned long long s0[4], s1[4], s2[4];
-    __shared__ double s3[4];
-    unsigned long long d = 0ull, p = ~0ull, q = ~0ull;
-    double w = 0.0;
-    for (int k = threadIdx.x; k < nt; k += 256) d = u64_max(d, disp[k]);
-    for (int k = threadIdx.x; k < ns; k += 256) {
-        p = u64_min(p, phi[k]);
-        q = u64_min(q, marg[k]);
-    }
-    for (int k = threadIdx.x; k < nw; k += 256) w += work[k];
-    for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) {
-        d = u64_max(d, __shfl_xor(d, o, RELCP_WAVE));
-        p = u64_min(p, __shfl_xor(p, o, RELCP_WAVE));
-        q = u64_min(q, __shfl_xor(q, o, RELCP_WAVE));
-        w += __shfl_xor(w, o, RELCP_WAVE);
-    }
-    const int lane = threadIdx.x & (RELCP_WAVE - 1), wv = threadIdx.x / RELCP_WAVE;
-    if (lane == 0) {
-        s0[wv] = d;
-        s1[wv] = p;
-        s2[wv] = q;
-        s3[wv] = w;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 1; k < 4; ++k) {
-            d = u64_max(d, s0[k]);
-            p = u64_min(p, s1[k]);
-            q = u64_min(q, s2[k]);
-            w += s3[k];
-        }
-        red_h[0] = d;
-        red_h[1] = p;
-        red_h[2] = q;
-        work_h[0] = w;
-        if (tok) {
-            // everything the host reads after this recursion is written: the
-            // token goes last, after a system-scope fence
-            __threadfence_system();
-            *(volatile int *)tok = seq;
-        }
-    }
-}
+// The tail report as its own kernel (used where no compaction runs).
+__global__ void __launch_bounds__(256) k_report(TailReport R) { tail_report(R); }
 }  // namespace
 
 // ===========================================================================
@@ -1480,10 +1426,13 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
             sb.minphi = red.p + nt; sb.minmarg = red.p + nt + nsb;
             sb.clear = lam.p;  // the pair sums of an accepted step are accumulated there
             timed(2, [&] { launch_snsd_pairs(sb, stream); });
-            compact_flags(pflag.p, np, pcnt.p, sel.p, int_d, scan_scratch, stream);  // count -> int_h[0]
             ++tok_seq;
-            hipLaunchKernelGGL(k_report, dim3(1), dim3(256), 0, stream, nt, red.p, np > 0 ? nsb : 0, red.p + nt,
-                               red.p + nt + nsb, nw, work_out.p, red_hd, dbl_hd, tok_d, tok_seq);
+            const TailReport rep{nt, red.p, np > 0 ? nsb : 0, red.p + nt, red.p + nt + nsb, nw, work_out.p,
+                                 red_hd, dbl_hd, tok_d, tok_seq};
+            // count -> int_h[0], then the report from the compaction's last
+            // workgroup (or on its own when there are no candidate pairs)
+            if (!compact_flags(pflag.p, np, pcnt.p, sel.p, int_d, scan_scratch, stream, &rep))
+                hipLaunchKernelGGL(k_report, dim3(1), dim3(256), 0, stream, rep);
         };
         bool tail_ready = false;  // the tail ran on the final multipliers and was waited for
         if (spec) {

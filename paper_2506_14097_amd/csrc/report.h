@@ -1,0 +1,77 @@
+// report.h -- the fixed-order reduction of one recursion's tail results
+// (largest displacement key of the trial, smallest Phi and margin keys of
+// the overlap check, the work gamma^T A gamma) into host-mapped memory,
+// then a token written last after a system-scope fence: the host polls the
+// token.  Run by one workgroup of 256 threads, either the report kernel or
+// the last workgroup of the compaction of the violators.
+#pragma once
+
+#include "common.h"
+
+namespace relcp {
+
+struct TailReport {
+    int nt;                            // trial blocks
+    const unsigned long long *disp;    // their displacement keys
+    int ns;                            // overlap-check blocks (0: none)
+    const unsigned long long *phi, *marg;
+    int nw;                            // work partial sums
+    const double *work;
+    unsigned long long *red_h;         // host-mapped: [0] displacement, [1] Phi, [2] margin keys
+    double *work_h;                    // host-mapped: the work
+    int *tok;                          // host-mapped token (or null)
+    int seq;
+};
+
+__device__ inline unsigned long long u64_max(unsigned long long a, unsigned long long b) { return a > b ? a : b; }
+__device__ inline unsigned long long u64_min(unsigned long long a, unsigned long long b) { return a < b ? a : b; }
+
+// Strided per-thread sums, then a fixed shuffle tree and the four waves in
+// order, so the work sum is the same on every run.  All 256 threads of the
+// workgroup call it.
+__device__ inline void tail_report(const TailReport &R) {
+    __shared__ unsigned long long s0[4], s1[4], s2[4];
+    __shared__ double s3[4];
+    unsigned long long d = 0ull, p = ~0ull, q = ~0ull;
+    double w = 0.0;
+    for (int k = threadIdx.x; k < R.nt; k += 256) d = u64_max(d, R.disp[k]);
+    for (int k = threadIdx.x; k < R.ns; k += 256) {
+        p = u64_min(p, R.phi[k]);
+        q = u64_min(q, R.marg[k]);
+    }
+    for (int k = threadIdx.x; k < R.nw; k += 256) w += R.work[k];
+    for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) {
+        d = u64_max(d, __shfl_xor(d, o, RELCP_WAVE));
+        p = u64_min(p, __shfl_xor(p, o, RELCP_WAVE));
+        q = u64_min(q, __shfl_xor(q, o, RELCP_WAVE));
+        w += __shfl_xor(w, o, RELCP_WAVE);
+    }
+    const int lane = threadIdx.x & (RELCP_WAVE - 1), wv = threadIdx.x / RELCP_WAVE;
+    if (lane == 0) {
+        s0[wv] = d;
+        s1[wv] = p;
+        s2[wv] = q;
+        s3[wv] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 4; ++k) {
+            d = u64_max(d, s0[k]);
+            p = u64_min(p, s1[k]);
+            q = u64_min(q, s2[k]);
+            w += s3[k];
+        }
+        R.red_h[0] = d;
+        R.red_h[1] = p;
+        R.red_h[2] = q;
+        R.work_h[0] = w;
+        if (R.tok) {
+            // everything the host reads after this recursion is written: the
+            // token goes last, after a system-scope fence
+            __threadfence_system();
+            *(volatile int *)R.tok = R.seq;
+        }
+    }
+}
+
+}  // namespace relcp

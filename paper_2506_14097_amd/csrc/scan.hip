@@ -10,6 +10,7 @@
 // cross-lane shuffles, wave totals through LDS.  Every sum is over integers, so the order does not
 // change the result.
 #include "common.h"
+#include "report.h"
 
 namespace relcp {
 
@@ -146,7 +147,7 @@ __global__ void __launch_bounds__(kThreads) k_count_flags(const int *__restrict_
 __global__ void __launch_bounds__(kThreads) k_compact_tiles(const int *__restrict__ flags, int n,
                                                             const int *__restrict__ bcount,
                                                             const int *__restrict__ boffs, int *__restrict__ out,
-                                                            int *__restrict__ total) {
+                                                            int *__restrict__ total, TailReport rep) {
     __shared__ int sh[kThreads / RELCP_WAVE];
     __shared__ int wsum[kThreads / RELCP_WAVE];
     const int b = blockIdx.x;
@@ -163,7 +164,11 @@ __global__ void __launch_bounds__(kThreads) k_compact_tiles(const int *__restric
 #pragma unroll
     for (int k = 0; k < kItems; ++k)
         if (set[k]) out[v[k]] = (int)(base + k);
-    if (total && b == (int)gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
+    if (b != (int)gridDim.x - 1) return;
+    if (total && threadIdx.x == 0) *total = off + tot;
+    // the count is stored (thread 0 before its fence): the tail report, whose
+    // inputs all come from earlier launches, goes last
+    if (rep.red_h) tail_report(rep);
 }
 
 }  // namespace
@@ -205,11 +210,11 @@ void exclusive_scan(const int *in, int *out, int n, int *total_dev, DBuf<int> &s
     scan_into(in, out, n, total_dev, scratch.p, s);
 }
 
-void compact_flags(const int *flags, int n, const int *bcount, int *out, int *total_dev, DBuf<int> &scratch,
-                   hipStream_t s) {
+bool compact_flags(const int *flags, int n, const int *bcount, int *out, int *total_dev, DBuf<int> &scratch,
+                   hipStream_t s, const TailReport *rep) {
     if (n <= 0) {
         if (total_dev) HIP_OK(hipMemsetAsync(total_dev, 0, sizeof(int), s));
-        return;
+        return false;
     }
     const int ng = flag_groups(n);
     const int nt = (n + kTile - 1) / kTile;
@@ -230,7 +235,10 @@ void compact_flags(const int *flags, int n, const int *bcount, int *out, int *to
         boffs = p;
         scan_into(bcount, boffs, ng, nullptr, p + ng, s);
     }
-    hipLaunchKernelGGL(k_compact_tiles, dim3(nt), dim3(kThreads), 0, s, flags, n, bcount, boffs, out, total_dev);
+    TailReport none{};
+    hipLaunchKernelGGL(k_compact_tiles, dim3(nt), dim3(kThreads), 0, s, flags, n, bcount, boffs, out, total_dev,
+                       rep ? *rep : none);
+    return rep != nullptr;
 }
 
 }  // namespace relcp
