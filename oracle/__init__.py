@@ -114,6 +114,17 @@ def snsd_spherocyl(d, ta, la, ra, tb, lb, rb, planar=0):
     return out[0], out[1:4].copy(), out[4:7].copy(), out[7:10].copy()
 
 
+def snsd_torus(d, ea, Ra, ra, eb, Rb, rb):
+    """Torus SNSD (Sec. 6, rings): centre-circle distance minus the minor
+    radii.  Returns (Phi, n, r_a, r_b, margin) with margin the centre-circle
+    distance of the best other local minimum (inf if none)."""
+    out = np.zeros(10)
+    sec = C.c_double(0.0)
+    lib().orc_snsd_torus(_p(_d(d, 3)), _p(_d(ea, 3)), C.c_double(Ra), C.c_double(ra), _p(_d(eb, 3)),
+                         C.c_double(Rb), C.c_double(rb), _p(out), C.byref(sec))
+    return out[0], out[1:4].copy(), out[4:7].copy(), out[7:10].copy(), sec.value
+
+
 def snsd_pairs(pa, pb, x, q, kind, shape, box, planar=0):
     """SNSD of every listed pair at configuration (x, q): array (m, 10) of
     [Phi, n(3), r_a(3), r_b(3)]."""

@@ -367,13 +367,204 @@ void orc_snsd_spherocyl(const double d[3], const double ta[3], double la, double
 }
 
 /* ------------------------------------------------------------------------ */
+/* SNSD of two tori (Sec. 6, non-convex rings): the distance between the two */
+/* centre circles, minus the two minor radii.  The paper minimises the       */
+/* distance over the two circle angles; here the minimum over both angles is */
+/* written as the minimum over the angle of circle a of the distance from    */
+/* that point to circle b, which has a closed form, so only a 1-D search is  */
+/* left: the circle of a is sampled at ORC_TORUS_NS equal steps, and each of */
+/* the ORC_TORUS_K smallest sampled local minima is refined by golden-       */
+/* section search inside its two neighbouring steps.                          */
+/* Readings (the paper asks only for a deterministic selection rule where    */
+/* the closest pair is not unique): the smallest refined value wins, the     */
+/* earlier sample on ties; where the centre circles meet (distance below     */
+/* 1e-12), n = t_a x t_b (tangents of the two circles there), or, with       */
+/* parallel tangents, the axis of a; n is signed so that n.d >= 0.            */
+/* ------------------------------------------------------------------------ */
+#define ORC_TORUS_NS 4096
+#define ORC_TORUS_K 8
+
+/* Unit vectors u, v completing the unit axis e to a right-handed frame. */
+static void plane_basis(const double e[3], double u[3], double v[3]) {
+    double ax = fabs(e[0]), ay = fabs(e[1]), az = fabs(e[2]);
+    double c[3] = {0.0, 0.0, 0.0};
+    if (ax <= ay && ax <= az) c[0] = 1.0;
+    else if (ay <= az) c[1] = 1.0;
+    else c[2] = 1.0;
+    cross3(e, c, u);
+    double l = norm3(u);
+    for (int i = 0; i < 3; ++i) u[i] /= l;
+    cross3(e, u, v);
+}
+
+/* Closest point q of the circle (centre c, unit axis e, radius R) to the
+ * point y; returns |y - q|^2 = h^2 + (rho - R)^2 with h the height of y over
+ * the circle's plane and rho its distance from the axis.  On the axis every
+ * point of the circle is closest; q is then taken along `fallback`. */
+static double circle_closest(const double y[3], const double c[3], const double e[3], double R,
+                             const double fallback[3], double q[3]) {
+    double w[3], up[3];
+    for (int i = 0; i < 3; ++i) w[i] = y[i] - c[i];
+    double h = dot3(w, e);
+    for (int i = 0; i < 3; ++i) up[i] = w[i] - h * e[i];
+    double rho = norm3(up);
+    if (q) {
+        if (rho > 0.0) for (int i = 0; i < 3; ++i) q[i] = c[i] + R * up[i] / rho;
+        else for (int i = 0; i < 3; ++i) q[i] = c[i] + R * fallback[i];
+    }
+    return h * h + (rho - R) * (rho - R);
+}
+
+typedef struct {
+    double d[3], ea[3], ua[3], va[3], eb[3], ub[3];
+    double Ra, Rb;
+} torus_pair;
+
+/* Point of circle a at angle t (relative to x_a) and its squared distance to
+ * circle b (centre d). */
+static void ring_point(const torus_pair *T, double t, double y[3]) {
+    double ct = cos(t), st = sin(t);
+    for (int i = 0; i < 3; ++i) y[i] = T->Ra * (ct * T->ua[i] + st * T->va[i]);
+}
+static double ring_gap2(const torus_pair *T, double t) {
+    double y[3];
+    ring_point(T, t, y);
+    return circle_closest(y, T->d, T->eb, T->Rb, T->ub, NULL);
+}
+
+/* Derivative of ring_gap2 at t: by the envelope theorem it is
+ * 2 (y - q).y'(t), q the closest point of circle b to y = ring_point(t). */
+static double ring_gap2_dt(const torus_pair *T, double t) {
+    double y[3], q[3], dy[3];
+    ring_point(T, t, y);
+    circle_closest(y, T->d, T->eb, T->Rb, T->ub, q);
+    double ct = cos(t), st = sin(t);
+    for (int i = 0; i < 3; ++i) dy[i] = T->Ra * (-st * T->ua[i] + ct * T->va[i]);
+    double acc = 0.0;
+    for (int i = 0; i < 3; ++i) acc += (y[i] - q[i]) * dy[i];
+    return 2.0 * acc;
+}
+
+/* Golden-section search for the minimum of ring_gap2 on [lo, hi], then, as
+ * golden section locates a minimum only to about the square root of the
+ * rounding unit, bisection on the sign of the derivative in a small bracket
+ * around it where the derivative goes from negative to positive (values
+ * alone cannot tell points that close apart). */
+static double golden_min(const torus_pair *T, double lo, double hi, double *tmin) {
+    const double g = 0.5 * (sqrt(5.0) - 1.0);
+    double x1 = hi - g * (hi - lo), x2 = lo + g * (hi - lo);
+    double f1 = ring_gap2(T, x1), f2 = ring_gap2(T, x2);
+    for (int it = 0; it < 200 && hi - lo > 1e-15; ++it) {
+        if (f1 <= f2) {
+            hi = x2; x2 = x1; f2 = f1;
+            x1 = hi - g * (hi - lo); f1 = ring_gap2(T, x1);
+        } else {
+            lo = x1; x1 = x2; f1 = f2;
+            x2 = lo + g * (hi - lo); f2 = ring_gap2(T, x2);
+        }
+    }
+    double t = f1 <= f2 ? x1 : x2, ft = f1 <= f2 ? f1 : f2;
+    double a = t - 1e-6, b = t + 1e-6;
+    if (ring_gap2_dt(T, a) < 0.0 && ring_gap2_dt(T, b) > 0.0) {
+        for (int it = 0; it < 100 && b - a > 0.0; ++it) {
+            double mid = 0.5 * (a + b);
+            if (mid <= a || mid >= b) break;
+            if (ring_gap2_dt(T, mid) < 0.0) a = mid;
+            else b = mid;
+        }
+        t = 0.5 * (a + b);
+        ft = ring_gap2(T, t);
+    }
+    *tmin = t;
+    return ft;
+}
+
+/* d = x_b - x_a; ea, eb unit axes; Ra, Rb major and ra, rb minor radii.
+ * out = [Phi, n(3), p_a - x_a (3), p_b - x_b (3)].  second (if not NULL):
+ * the smallest centre-circle distance among the other refined minima more
+ * than three sample steps away (+inf if none): a margin of uniqueness. */
+void orc_snsd_torus(const double d[3], const double ea[3], double Ra, double ra, const double eb[3], double Rb,
+                    double rb, double out[10], double *second) {
+    torus_pair T;
+    for (int i = 0; i < 3; ++i) { T.d[i] = d[i]; T.ea[i] = ea[i]; T.eb[i] = eb[i]; }
+    T.Ra = Ra;
+    T.Rb = Rb;
+    plane_basis(ea, T.ua, T.va);
+    double vb[3];
+    plane_basis(eb, T.ub, vb);
+    const double step = 2.0 * M_PI / ORC_TORUS_NS;
+    static double f[ORC_TORUS_NS];
+    for (int i = 0; i < ORC_TORUS_NS; ++i) f[i] = ring_gap2(&T, step * i);
+    /* the ORC_TORUS_K smallest sampled local minima, in sample order on ties */
+    int idx[ORC_TORUS_K];
+    int nk = 0;
+    for (int i = 0; i < ORC_TORUS_NS; ++i) {
+        double fp = f[(i + ORC_TORUS_NS - 1) % ORC_TORUS_NS], fn = f[(i + 1) % ORC_TORUS_NS];
+        if (!(f[i] <= fp && f[i] <= fn)) continue;
+        int pos = nk;
+        while (pos > 0 && f[idx[pos - 1]] > f[i]) --pos;
+        if (pos >= ORC_TORUS_K) continue;
+        int last = nk < ORC_TORUS_K ? nk : ORC_TORUS_K - 1;
+        for (int j = last; j > pos; --j) idx[j] = idx[j - 1];
+        idx[pos] = i;
+        if (nk < ORC_TORUS_K) ++nk;
+    }
+    double tk[ORC_TORUS_K], fk[ORC_TORUS_K];
+    int best = 0;
+    for (int k = 0; k < nk; ++k) {
+        double t0 = step * idx[k];
+        fk[k] = golden_min(&T, t0 - step, t0 + step, &tk[k]);
+        if (fk[k] < fk[best]) best = k;
+    }
+    if (second) {
+        double sv = INFINITY;
+        for (int k = 0; k < nk; ++k) {
+            int di = abs(idx[k] - idx[best]);
+            if (di > ORC_TORUS_NS / 2) di = ORC_TORUS_NS - di;
+            if (di > 3 && fk[k] < sv) sv = fk[k];
+        }
+        *second = isinf(sv) ? sv : sqrt(sv);
+    }
+    double pa[3], pb[3], w[3], n[3];
+    ring_point(&T, tk[best], pa);
+    circle_closest(pa, d, eb, Rb, T.ub, pb);
+    for (int i = 0; i < 3; ++i) w[i] = pb[i] - pa[i];
+    double dist = norm3(w);
+    if (dist >= 1e-12) {
+        for (int i = 0; i < 3; ++i) n[i] = w[i] / dist;
+    } else {
+        double tpa[3], tpb[3], rel[3];
+        cross3(ea, pa, tpa);
+        for (int i = 0; i < 3; ++i) rel[i] = pb[i] - d[i];
+        cross3(eb, rel, tpb);
+        cross3(tpa, tpb, n);
+        double l = norm3(n);
+        if (l * l < 1e-12 * (dot3(tpa, tpa) * dot3(tpb, tpb) + 1e-300)) {
+            for (int i = 0; i < 3; ++i) n[i] = ea[i];
+            l = 1.0;
+        }
+        for (int i = 0; i < 3; ++i) n[i] /= l;
+        if (dot3(n, d) < 0.0) for (int i = 0; i < 3; ++i) n[i] = -n[i];
+    }
+    out[0] = dist - ra - rb;
+    for (int i = 0; i < 3; ++i) {
+        out[1 + i] = n[i];
+        out[4 + i] = pa[i] + ra * n[i];            /* p_a - x_a */
+        out[7 + i] = (pb[i] - d[i]) - rb * n[i];   /* p_b - x_b */
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Body geometry and the pair list                                           */
 /* ------------------------------------------------------------------------ */
 /* kind 0 = ellipsoid with semiaxes p = (a, b, c) along body axes x, y, z;
  * kind 1 = spherocylinder p = (r, l, 0): radius r, cylinder length l (caps
- * excluded), axis = body x axis. */
+ * excluded), axis = body x axis;
+ * kind 2 = torus p = (R, r, 0): major radius R (centre circle), minor radius
+ * r (tube), symmetry axis = body z axis. */
 static double bounding_radius(int kind, const double p[3]) {
     if (kind == 0) return fmax(p[0], fmax(p[1], p[2]));
+    if (kind == 2) return p[0] + p[1];
     return 0.5 * p[1] + p[0];
 }
 
@@ -412,6 +603,13 @@ static void pair_snsd(int a, int b, const double *x, const double *q, const int 
     min_image(x + 3 * a, x + 3 * b, box, d);
     if (kind[a] == 0) {
         orc_snsd_ellipsoid(d, q + 4 * a, shape + 3 * a, q + 4 * b, shape + 3 * b, 2000, out);
+    } else if (kind[a] == 2) {
+        double Ra[9], Rb[9];
+        orc_quat_to_R(q + 4 * a, Ra);
+        orc_quat_to_R(q + 4 * b, Rb);
+        double ea[3] = {Ra[2], Ra[5], Ra[8]}, eb[3] = {Rb[2], Rb[5], Rb[8]};
+        orc_snsd_torus(d, ea, shape[3 * a + 0], shape[3 * a + 1], eb, shape[3 * b + 0], shape[3 * b + 1], out,
+                       NULL);
     } else {
         double Ra[9], Rb[9];
         orc_quat_to_R(q + 4 * a, Ra);
@@ -436,7 +634,7 @@ void orc_snsd_pairs(int m, const int *pa, const int *pb, const double *x, const 
  *  - overdamped, local drag (Sec. 2.1.2 Eq. law_overdamped; Eq.
  *    ellipsoid_mobility): K = M = (1/xi) diag(I/L, 12 I/L^3); L = 2 x major
  *    semiaxis for ellipsoids; reading for spherocylinders: L = l + 2r (tip to
- *    tip); U_free = M F_ext.
+ *    tip); for tori: L = 2 (R + r) (outer diameter); U_free = M F_ext.
  *  - inertial (Sec. 2.1.2 Eq. law_inertia, Eq. cqpp): K = dt M^{-1} with
  *    M^{-1} = diag(I/m, R diag(1/I_body) R^T) of a solid ellipsoid of density
  *    rho; U_free = U^k + dt M^{-1} F_ext.
@@ -446,7 +644,8 @@ static int body_K(int dynamics, int planar, double dt, int kind, const double p[
                   double rho_xi, double kt[3], double Kr[9]) {
     memset(Kr, 0, 9 * sizeof(double));
     if (dynamics == 0) {
-        double L = (kind == 0) ? 2.0 * fmax(p[0], fmax(p[1], p[2])) : p[1] + 2.0 * p[0];
+        double L = (kind == 0) ? 2.0 * fmax(p[0], fmax(p[1], p[2]))
+                 : (kind == 2 ? 2.0 * (p[0] + p[1]) : p[1] + 2.0 * p[0]);
         double xi = rho_xi;
         if (!(L > 0.0) || !(xi > 0.0)) return ORC_E_INVALID;
         double a = 1.0 / (xi * L), r = 12.0 / (xi * L * L * L);
