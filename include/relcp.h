@@ -51,7 +51,7 @@ enum {
     RELCP_E_CAPACITY = -8       /* contact or pair buffer would exceed the configured maximum */
 };
 
-enum { RELCP_ELLIPSOID = 0, RELCP_SPHEROCYLINDER = 1 };
+enum { RELCP_ELLIPSOID = 0, RELCP_SPHEROCYLINDER = 1, RELCP_TORUS = 2 };
 enum { RELCP_OVERDAMPED = 0, RELCP_INERTIAL = 1 };
 enum { RELCP_WS_COLD = 0, RELCP_WS_PREV = 1, RELCP_WS_LEARNED = 2 };
 
@@ -70,9 +70,14 @@ typedef struct {
 
 /* Shapes: kind[i] = RELCP_ELLIPSOID with p[3i..] = semiaxes (a, b, c) along
  * the body x, y, z axes; or RELCP_SPHEROCYLINDER with p[3i..] = (r, l, 0):
- * cap radius r and cylinder length l, axis along body x (Sec. 5.3).
+ * cap radius r and cylinder length l, axis along body x (Sec. 5.3); or
+ * RELCP_TORUS with p[3i..] = (R, r, 0): centre-circle (major) radius R >= 0
+ * and tube (minor) radius r > 0, symmetry axis along body z (the rings of
+ * Sec. 6; SNSD = distance between the centre circles minus both minor
+ * radii; overdamped only, not in a monolayer, no learned warm start).
  * rho_or_xi[i] = density (inertial) or drag coefficient xi (overdamped, Eq.
- * ellipsoid_mobility).  One packing holds one kind only. */
+ * ellipsoid_mobility; mobility length L = 2 max semiaxis, l + 2 r or
+ * 2 (R + r)).  One packing holds one kind only. */
 typedef struct {
     const int32_t *kind;
     const double *p;

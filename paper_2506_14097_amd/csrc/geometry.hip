@@ -288,13 +288,158 @@ __device__ Snsd snsd_spherocyl(d3 d, d3 ta, double la, double ra, d3 tb, double 
 }
 
 // ===========================================================================
+// SNSD of two tori (Sec. 6, rings): the distance between the two centre
+// circles minus the two minor radii.  For a point y(t) of circle a (angle t)
+// the squared distance to circle b is g(t) = |w|^2 - 2 R_b rho + R_b^2, with
+// w = y - d and rho the distance of y from b's axis, so the 2-D minimisation
+// over both angles is a 1-D one over t.  g is sampled at kTorusNs angles;
+// each of the kTorusK smallest sampled local minima is refined by Newton's
+// method on g' (analytic g', g'') inside its two neighbouring steps, with a
+// bisection step whenever Newton leaves the bracket, and the smallest result
+// wins (the earlier sample on ties).  Readings where the closest pair is
+// degenerate: centre circles that meet get n = t_a x t_b (their tangents
+// there), or the axis of a when the tangents are parallel, signed n.d >= 0;
+// a point of a on b's axis takes b's first frame vector as the direction.
+// ===========================================================================
+constexpr int kTorusNs = 128;
+constexpr int kTorusK = 4;
+
+struct RingPoint {
+    double g, g1, g2;
+};
+
+// g and (with kDeriv) its first two derivatives at (cos t, sin t) = (c, s).
+template <bool kDeriv>
+__device__ inline RingPoint ring_point(double c, double s, d3 e1, d3 e2, double Ra, d3 d, d3 eb, double Rb) {
+    const d3 y = Ra * (c * e1 + s * e2);
+    const d3 w = y - d;
+    const double h = dot(w, eb);
+    const d3 up = w - h * eb;
+    const double rho = sqrt(dot(up, up));
+    RingPoint r;
+    r.g = dot(w, w) - 2.0 * Rb * rho + Rb * Rb;
+    r.g1 = r.g2 = 0.0;
+    if (kDeriv) {
+        const d3 y1 = Ra * (c * e2 - s * e1);  // y' (and y'' = -y)
+        const double irho = rho > 0.0 ? 1.0 / rho : 0.0;
+        const double h1 = dot(y1, eb), uy1 = dot(up, y1), y1y1 = dot(y1, y1);
+        const double rho1 = uy1 * irho;
+        const double rho2 = (y1y1 - h1 * h1 - dot(up, y)) * irho - rho1 * rho1 * irho;
+        r.g1 = 2.0 * dot(w, y1) - 2.0 * Rb * rho1;
+        r.g2 = 2.0 * (y1y1 - dot(w, y)) - 2.0 * Rb * rho2;
+    }
+    return r;
+}
+
+__device__ Snsd snsd_torus(d3 d, d3 ea, double Ra, double ra, d3 eb, double Rb, double rb) {
+    d3 e1, e2, f1, f2;
+    tangent_frame(ea, e1, e2);
+    tangent_frame(eb, f1, f2);
+    const double step = 2.0 * M_PI / kTorusNs;
+    double cs, sn;
+    sincos(step, &sn, &cs);
+    // the kTorusK smallest sampled local minima (value, sample), ascending
+    double kv[kTorusK];
+    int ki[kTorusK];
+#pragma unroll
+    for (int k = 0; k < kTorusK; ++k) {
+        kv[k] = 1e300;
+        ki[k] = -1;
+    }
+    // samples by rotation of (cos, sin) by the step (drift of a few ulp over
+    // the turn: the samples only pick the brackets)
+    const double gl = ring_point<false>(cs, -sn, e1, e2, Ra, d, eb, Rb).g;  // t = -step
+    const double g0 = ring_point<false>(1.0, 0.0, e1, e2, Ra, d, eb, Rb).g;
+    double gp = gl, gc = g0, c = 1.0, s = 0.0;
+    for (int i = 0; i < kTorusNs; ++i) {
+        const double cn = c * cs - s * sn, snx = s * cs + c * sn;
+        const double gn = i + 1 < kTorusNs ? ring_point<false>(cn, snx, e1, e2, Ra, d, eb, Rb).g : g0;
+        if (gc <= gp && gc <= gn && gc < kv[kTorusK - 1]) {
+            kv[kTorusK - 1] = gc;
+            ki[kTorusK - 1] = i;
+#pragma unroll
+            for (int k = kTorusK - 1; k > 0; --k)
+                if (kv[k] < kv[k - 1]) {
+                    const double tv = kv[k];
+                    kv[k] = kv[k - 1];
+                    kv[k - 1] = tv;
+                    const int ti = ki[k];
+                    ki[k] = ki[k - 1];
+                    ki[k - 1] = ti;
+                }
+        }
+        gp = gc;
+        gc = gn;
+        c = cn;
+        s = snx;
+    }
+    double bt = 0.0, bg = 1e300;
+#pragma unroll
+    for (int k = 0; k < kTorusK; ++k) {
+        if (ki[k] < 0) continue;
+        double t = step * ki[k], lo = t - step, hi = t + step;
+        for (int it = 0; it < 40; ++it) {
+            double st, ct;
+            sincos(t, &st, &ct);
+            const RingPoint r = ring_point<true>(ct, st, e1, e2, Ra, d, eb, Rb);
+            if (r.g1 < 0.0)
+                lo = t;
+            else
+                hi = t;
+            double tn = r.g2 > 0.0 ? t - r.g1 / r.g2 : 0.5 * (lo + hi);
+            if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+            const bool done = fabs(tn - t) <= 1e-15 * (1.0 + fabs(t));
+            t = tn;
+            if (done) break;
+        }
+        double st, ct;
+        sincos(t, &st, &ct);
+        const double g = ring_point<false>(ct, st, e1, e2, Ra, d, eb, Rb).g;
+        if (g < bg) {
+            bg = g;
+            bt = t;
+        }
+    }
+    double st, ct;
+    sincos(bt, &st, &ct);
+    const d3 pa = Ra * (ct * e1 + st * e2);  // centre-circle point of a (relative to x_a)
+    const d3 w = pa - d;
+    const d3 up = w - dot(w, eb) * eb;
+    const double rho = sqrt(dot(up, up));
+    const d3 pb = d + (rho > 0.0 ? (Rb / rho) * up : Rb * f1);  // of b (relative to x_a)
+    const d3 wc = pb - pa;
+    const double dist = len(wc);
+    d3 n;
+    if (dist >= 1e-12) {
+        n = (1.0 / dist) * wc;
+    } else {
+        const d3 ta = cross(ea, pa), tb = cross(eb, pb - d);
+        n = cross(ta, tb);
+        double l2 = dot(n, n);
+        if (l2 < 1e-12 * (dot(ta, ta) * dot(tb, tb) + 1e-300)) {
+            n = ea;
+            l2 = 1.0;
+        }
+        n = (1.0 / sqrt(l2)) * n;
+        if (dot(n, d) < 0.0) n = -1.0 * n;
+    }
+    Snsd o;
+    o.phi = dist - ra - rb;
+    o.n = n;
+    o.ra = pa + ra * n;
+    o.rb = (pb - d) - rb * n;
+    return o;
+}
+
+// ===========================================================================
 // per-body set-up at C^k: geometry (Sigma or axis), bounding radius,
 // operator K, free velocity U_free
 // ===========================================================================
 // K per body (9 comps): translational diagonal (3) and rotational symmetric
 // (6), already projected for a monolayer (z translation, x/y rotation off).
 //  overdamped: K = M = (1/xi) diag(I/L, 12 I/L^3), L = 2 max semiaxis
-//              (ellipsoid) or l + 2 r (spherocylinder, tip to tip)
+//              (ellipsoid), l + 2 r (spherocylinder, tip to tip) or
+//              2 (R + r) (torus, outer diameter)
 //  inertial:   K = dt M^-1, M^-1 = diag(I/m, R diag(1/I_body) R^T), solid
 //              ellipsoid of density rho
 __global__ void k_body_setup(int nb, const double *__restrict__ q, int ldq, const int *__restrict__ kind,
@@ -321,18 +466,20 @@ __global__ void k_body_setup(int nb, const double *__restrict__ q, int ldq, cons
         geo[5 * ldg + i] = a2 * c0.y * c0.z + b2 * c1.y * c1.z + c2s * c2.y * c2.z;
         Rb[i] = fmax(a, fmax(b, c));
     } else {
-        geo[0 * ldg + i] = c0.x;
-        geo[1 * ldg + i] = c0.y;
-        geo[2 * ldg + i] = c0.z;
+        // the axis: body x (spherocylinder) or body z (torus)
+        const d3 ax = kd == 2 ? c2 : c0;
+        geo[0 * ldg + i] = ax.x;
+        geo[1 * ldg + i] = ax.y;
+        geo[2 * ldg + i] = ax.z;
         geo[3 * ldg + i] = 0.0;
         geo[4 * ldg + i] = 0.0;
         geo[5 * ldg + i] = 0.0;
-        Rb[i] = 0.5 * b + a;
+        Rb[i] = kd == 2 ? a + b : 0.5 * b + a;
     }
     if (!K) return;
     double kt[3], kr[6];
     if (dynamics == 0) {
-        double L = (kd == 0) ? 2.0 * fmax(a, fmax(b, c)) : b + 2.0 * a;
+        double L = (kd == 0) ? 2.0 * fmax(a, fmax(b, c)) : (kd == 2 ? 2.0 * (a + b) : b + 2.0 * a);
         double xi = rho_xi[i];
         double t = 1.0 / (xi * L), r = 12.0 / (xi * L * L * L);
         kt[0] = kt[1] = kt[2] = t;
@@ -452,9 +599,10 @@ __global__ void k_trial(int nb, const double *__restrict__ x, int ldx, const dou
             geo[4 * ldg + i] = a2 * c0.x * c0.z + b2 * c1.x * c1.z + cc * c2.x * c2.z;
             geo[5 * ldg + i] = a2 * c0.y * c0.z + b2 * c1.y * c1.z + cc * c2.y * c2.z;
         } else {
-            geo[0 * ldg + i] = c0.x;
-            geo[1 * ldg + i] = c0.y;
-            geo[2 * ldg + i] = c0.z;
+            const d3 ax = kind[i] == 2 ? c2 : c0;
+            geo[0 * ldg + i] = ax.x;
+            geo[1 * ldg + i] = ax.y;
+            geo[2 * ldg + i] = ax.z;
             geo[3 * ldg + i] = 0.0;
             geo[4 * ldg + i] = 0.0;
             geo[5 * ldg + i] = 0.0;
@@ -530,6 +678,9 @@ __global__ void __launch_bounds__(256, 4) k_snsd_pairs(SnsdArgs A) {
                 if (has) hint = (1.0 / hl) * hint;
             }
             s = snsd_ellipsoid(d, Sa, Sb, has ? hint : mk(1, 0, 0), has);
+        } else if (kd == 2) {
+            s = snsd_torus(d, mk(ga[0], ga[1], ga[2]), A.p[a], A.p[A.ldp + a], mk(gb[0], gb[1], gb[2]), A.p[b],
+                           A.p[A.ldp + b]);
         } else {
             const d3 ta = mk(ga[0], ga[1], ga[2]);
             const d3 tb = mk(gb[0], gb[1], gb[2]);
@@ -647,25 +798,28 @@ __device__ inline int nbr_cells(int c, int k, const PackGrid &g, int out[3]) {
 
 // Shape of a body for its support radius h(n) = max over the body of
 // n.(y - x), n a unit vector: sqrt(n^T Sigma n) for an ellipsoid, r + (l/2)
-// |t.n| for a spherocylinder (axis t, radius r = p0, length l = p1).
+// |t.n| for a spherocylinder (axis t, radius r = p0, length l = p1), and
+// R sqrt(1 - (e.n)^2) + r for a torus (axis e, radii R = p0, r = p1).
 struct SupportShape {
-    bool ell;
+    int kind;
     sym3 S;     // Sigma, or the axis in its first three entries
-    double r, l;
+    double r, l;  // shape parameters p0, p1 (0 for an ellipsoid)
 };
 __device__ inline SupportShape support_shape(const PairShapes &P, int i) {
     const double *g = P.geo;
     const int L = P.ldg;
     SupportShape s;
-    s.ell = P.kind[i] == 0;
+    s.kind = P.kind[i];
     s.S = sym3{g[i], g[L + i], g[2 * L + i], g[3 * L + i], g[4 * L + i], g[5 * L + i]};
-    s.r = s.ell ? 0.0 : P.p[i];
-    s.l = s.ell ? 0.0 : P.p[P.ldp + i];
+    s.r = s.kind == 0 ? 0.0 : P.p[i];
+    s.l = s.kind == 0 ? 0.0 : P.p[P.ldp + i];
     return s;
 }
 __device__ inline double support_radius(const SupportShape &s, d3 n) {
-    if (s.ell) return sqrt(dot(n, mul(s.S, n)));
-    return s.r + 0.5 * s.l * fabs(s.S.xx * n.x + s.S.yy * n.y + s.S.zz * n.z);
+    if (s.kind == 0) return sqrt(dot(n, mul(s.S, n)));
+    const double c = s.S.xx * n.x + s.S.yy * n.y + s.S.zz * n.z;  // axis . n
+    if (s.kind == 2) return s.r * sqrt(fmax(0.0, 1.0 - c * c)) + s.l;
+    return s.r + 0.5 * s.l * fabs(c);
 }
 
 template <bool kFill>

@@ -295,6 +295,7 @@ struct relcp_ctx {
     // learned warm start: model (fp32 master weights + standardisation),
     // features of the iteration-0 rows, contact log of the last accepted step
     bool has_model = false, log_on = false, log_valid = false;
+    bool has_torus = false;  // some body is a torus (no learned warm start then)
     float mlp_norm[MLP_NORM] = {};
     DBuf<float> mlp_w, feat;
     DBuf<double> rowscale;
@@ -450,6 +451,13 @@ void relcp_ctx::alloc_host() {
 // ---------------------------------------------------------------------------
 // validation and upload
 // ---------------------------------------------------------------------------
+// Bounding radius of a shape: largest semiaxis, l/2 + r, or R + r.
+static double bound_radius(int kind, const double *pp) {
+    if (kind == RELCP_ELLIPSOID) return std::max(pp[0], std::max(pp[1], pp[2]));
+    if (kind == RELCP_TORUS) return pp[0] + pp[1];
+    return 0.5 * pp[1] + pp[0];
+}
+
 static void validate(const relcp_bodies *B, const relcp_shapes *S, const relcp_params *P, double skin) {
     if (!B || !S || !B->x || !B->q || !S->kind || !S->p || !S->rho_or_xi) throw Error{RELCP_E_INVALID, "null input"};
     if (B->n <= 0) throw Error{RELCP_E_INVALID, "need at least one body"};
@@ -477,6 +485,12 @@ static void validate(const relcp_bodies *B, const relcp_shapes *S, const relcp_p
             if (!(pp[0] > 0 && pp[1] >= 0)) throw Error{RELCP_E_INVALID, "bad spherocylinder radius or length"};
             if (P && P->dynamics == RELCP_INERTIAL)
                 throw Error{RELCP_E_INVALID, "inertial dynamics needs ellipsoids (mass properties)"};
+        } else if (kd == RELCP_TORUS) {
+            if (!(pp[0] >= 0 && pp[1] > 0 && std::isfinite(pp[0]) && std::isfinite(pp[1])))
+                throw Error{RELCP_E_INVALID, "bad torus radii (R >= 0, r > 0)"};
+            if (P && P->dynamics == RELCP_INERTIAL)
+                throw Error{RELCP_E_INVALID, "inertial dynamics needs ellipsoids (mass properties)"};
+            if (P && P->planar) throw Error{RELCP_E_INVALID, "tori are not supported in a monolayer"};
         } else {
             throw Error{RELCP_E_INVALID, "unknown shape kind"};
         }
@@ -495,7 +509,7 @@ static void validate(const relcp_bodies *B, const relcp_shapes *S, const relcp_p
         for (int i = b0; i < b1; ++i) {
             if (S->kind[i] != S->kind[b0]) throw Error{RELCP_E_INVALID, "one shape kind per packing"};
             const double *pp = S->p + 3 * i;
-            R = std::max(R, S->kind[i] == 0 ? std::max(pp[0], std::max(pp[1], pp[2])) : 0.5 * pp[1] + pp[0]);
+            R = std::max(R, bound_radius(S->kind[i], pp));
         }
         for (int k = 0; k < 3; ++k) {
             double L = B->box ? B->box[3 * pk + k] : 0.0;
@@ -535,13 +549,14 @@ void relcp_ctx::upload_bodies(const relcp_bodies *B, const relcp_shapes *S) {
     if (B->box)
         for (int k = 0; k < 3 * nbatch; ++k) box[k] = B->box[k];
     rmax.assign(nbatch, 0.0);
+    has_torus = false;
     std::vector<int> bb(n);
     for (int pk = 0; pk < nbatch; ++pk)
         for (int i = boff[pk]; i < boff[pk + 1]; ++i) {
             bb[i] = pk;
             const double *pp = S->p + 3 * i;
-            double R = S->kind[i] == 0 ? std::max(pp[0], std::max(pp[1], pp[2])) : 0.5 * pp[1] + pp[0];
-            rmax[pk] = std::max(rmax[pk], R);
+            rmax[pk] = std::max(rmax[pk], bound_radius(S->kind[i], pp));
+            if (S->kind[i] == RELCP_TORUS) has_torus = true;
         }
     // spatial order inside each packing
     perm.resize(n);
@@ -1772,9 +1787,12 @@ int relcp_set_state(relcp_ctx *ctx, const relcp_bodies *bodies, const relcp_shap
     if (!ctx) return RELCP_E_INVALID;
     return guarded(ctx, [&]() -> int {
         validate(bodies, shapes, nullptr, ctx->skin);
-        if (ctx->dynamics == RELCP_INERTIAL)
-            for (int i = 0; i < bodies->n; ++i)
-                if (shapes->kind[i] != RELCP_ELLIPSOID) throw Error{RELCP_E_INVALID, "inertial needs ellipsoids"};
+        for (int i = 0; i < bodies->n; ++i) {
+            if (ctx->dynamics == RELCP_INERTIAL && shapes->kind[i] != RELCP_ELLIPSOID)
+                throw Error{RELCP_E_INVALID, "inertial needs ellipsoids"};
+            if (shapes->kind[i] == RELCP_TORUS && (ctx->planar || ctx->warm_start == RELCP_WS_LEARNED))
+                throw Error{RELCP_E_INVALID, "tori: not in a monolayer, no learned warm start"};
+        }
         ctx->upload_bodies(bodies, shapes);
         return RELCP_OK;
     });
@@ -2034,6 +2052,8 @@ int relcp_set_warm_start(relcp_ctx *ctx, int32_t mode) {
         if (mode < RELCP_WS_COLD || mode > RELCP_WS_LEARNED) throw Error{RELCP_E_INVALID, "bad warm start"};
         if (mode == RELCP_WS_LEARNED && !ctx->has_model)
             throw Error{RELCP_E_INVALID, "learned warm start needs a model (relcp_set_warmstart_model)"};
+        if (mode == RELCP_WS_LEARNED && ctx->has_torus)
+            throw Error{RELCP_E_INVALID, "the learned warm start covers ellipsoids and spherocylinders"};
         ctx->warm_start = mode;
         return RELCP_OK;
     });

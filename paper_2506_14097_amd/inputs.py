@@ -9,7 +9,9 @@ Workload shapes (Sec. 5 of Palmer, Aktulga, Gao, arXiv 2506.14097):
   * two ellipsoids meeting head-on (inertial);
   * periodic packings of ellipsoids with semiaxes uniform in [0.5, 1.0] at a
     prescribed volume fraction (compacting suspension, Sec. 5.2);
-  * monolayers of spherocylinders of diameter 1 (colony, Sec. 5.3).
+  * monolayers of spherocylinders of diameter 1 (colony, Sec. 5.3);
+  * a chainmail of interlaced rings (tori of major radius 1 and minor radius
+    0.1) on a square lattice, pulled by the extensile field of Sec. 6.
 """
 from __future__ import annotations
 
@@ -22,6 +24,7 @@ import numpy as np
 
 ELLIPSOID = 0
 SPHEROCYLINDER = 1
+TORUS = 2
 
 
 def rng_for(seed: int) -> np.random.Generator:
@@ -47,7 +50,65 @@ def ellipsoid_volume(shape: np.ndarray) -> np.ndarray:
 
 
 def bounding_radius(kind: np.ndarray, shape: np.ndarray) -> np.ndarray:
-    return np.where(kind == ELLIPSOID, shape.max(axis=1), 0.5 * shape[:, 1] + shape[:, 0])
+    return np.where(kind == ELLIPSOID, shape.max(axis=1),
+                    np.where(kind == TORUS, shape[:, 0] + shape[:, 1], 0.5 * shape[:, 1] + shape[:, 0]))
+
+
+# quaternions (scalar first) taking the body z axis to z, y and x
+RING_FLAT = (1.0, 0.0, 0.0, 0.0)
+RING_AXIS_Y = (math.cos(math.pi / 4), -math.sin(math.pi / 4), 0.0, 0.0)
+RING_AXIS_X = (math.cos(math.pi / 4), 0.0, math.sin(math.pi / 4), 0.0)
+
+
+def chainmail(nx: int = 5, ny: int = 5, R: float = 1.0, r: float = 0.1, slack: float = 0.45,
+              xi: float = 1.0) -> dict:
+    """Interlaced rings on a square lattice (the paper's layout is not
+    given; this one is ours): flat rings (axis z) at the nodes (i L, j L, 0)
+    of an nx x ny lattice centred at the origin, and one connector ring per
+    lattice edge at its midpoint, standing upright with its axis horizontal
+    and normal to the edge (edges along x: axis y; along y: axis x).  A
+    connector threads both rings of its edge: its centre circle crosses the
+    plane z = 0 at L/2 - R from each node, inside the hole.  L is chosen so
+    that pulling a connector and a node ring apart along the edge closes a
+    surface gap of `slack` before the tubes touch: L/2 = 2 (R - r) - slack.
+    Overdamped drag xi; the extensile field is `extensile_field`."""
+    half = 2.0 * (R - r) - slack
+    if not (half > R + 2.0 * r and half < 2.0 * R - 2.0 * r):
+        raise ValueError("slack outside the range that keeps the rings linked and apart")
+    L = 2.0 * half
+    x, q = [], []
+    for j in range(ny):
+        for i in range(nx):
+            x.append((i * L, j * L, 0.0))
+            q.append(RING_FLAT)
+    for j in range(ny):
+        for i in range(nx - 1):
+            x.append(((i + 0.5) * L, j * L, 0.0))
+            q.append(RING_AXIS_Y)
+    for j in range(ny - 1):
+        for i in range(nx):
+            x.append((i * L, (j + 0.5) * L, 0.0))
+            q.append(RING_AXIS_X)
+    x = np.array(x, float)
+    x -= np.array([(nx - 1) * L / 2, (ny - 1) * L / 2, 0.0])
+    n = x.shape[0]
+    return dict(x=x, q=np.array(q, float), kind=np.full(n, TORUS, np.int32), shape=np.tile([R, r, 0.0], (n, 1)),
+                rho_xi=np.full(n, xi), box=np.zeros(3), n_nodes=nx * ny, spacing=L)
+
+
+def extensile_field(x: np.ndarray) -> np.ndarray:
+    """External wrench of the chainmail (Sec. 6): the force
+    F(x) = x (|x| - sin|x|) / |x|^2 at each ring's centre, no torque; the
+    series |x|^3 / 6 - |x|^5 / 120 replaces |x| - sin|x| below |x| = 1e-3."""
+    x = np.asarray(x, float).reshape(-1, 3)
+    s = np.linalg.norm(x, axis=1)
+    small = s < 1e-3
+    num = np.where(small, s ** 3 / 6.0 - s ** 5 / 120.0, s - np.sin(s))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        scale = np.where(s > 0, num / np.where(s > 0, s * s, 1.0), 0.0)
+    f = np.zeros((x.shape[0], 6))
+    f[:, :3] = x * scale[:, None]
+    return f
 
 
 def two_ellipsoids(seed: int = 0, separation: float = 3.0, closing_speed: float = 1.0, spin_sd: float = 0.05,

@@ -21,7 +21,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "relcp.h")
 OK = 0
 E_INVALID, E_OOM, E_DEVICE, E_LCP_MAXITER, E_RECURSION_CAP, E_SKIN, E_NAN, E_CAPACITY = (-1, -2, -3, -4, -5, -6,
                                                                                        -7, -8)
-ELLIPSOID, SPHEROCYLINDER = 0, 1
+ELLIPSOID, SPHEROCYLINDER, TORUS = 0, 1, 2
 OVERDAMPED, INERTIAL = 0, 1
 WS_COLD, WS_PREV, WS_LEARNED = 0, 1, 2
 MAX_RECORDED = 65
