@@ -249,6 +249,67 @@ def two_ellipsoid_study(args):
                       "xi": float(S["rho_xi"][0]), "runs": out}), flush=True)
 
 
+def chainmail_study(args):
+    """Chainmail of interlaced rings pulled taut by the extensile field (Sec.
+    6, Fig. chainmail): ReLCP against LCP-SNSD (no recursions, the first
+    trial accepted) at --cm-dt up to --cm-t-end, FP64, overlap_tol 1e-5,
+    lcp_tol 1e-12, on a --cm-n x --cm-n lattice of node rings with their
+    connectors (tori R = 1, r = 0.1, drag --cm-xi, seeded placement jitter
+    --cm-jitter; LCP tolerance --cm-lcp-tol, at most 10^6 iterations; a
+    step that fails ends its run, which records it).  The field depends on the
+    positions, so each step reads the state back and sets the external
+    wrench first.  The violation of a step is the largest overlap of the
+    accepted configuration on the true ring surfaces (exact torus SNSD).
+    Per method: the largest violation, the steps with recursions, ms per
+    step (with the read-back) and the violation per window of 1/20 of the
+    run; the extent of the network at the end."""
+    import torch
+    from paper_2506_14097_amd import inputs as I
+    from paper_2506_14097_amd import relcp as R
+    S = I.chainmail(args.cm_n, args.cm_n, xi=args.cm_xi, jitter=args.cm_jitter, seed=0)
+    dt, n = args.cm_dt, int(round(args.cm_t_end / args.cm_dt))
+    win = max(1, n // 20)
+    runs = []
+    for method, mr in (("ReLCP", 64), ("LCP-SNSD", 0)):
+        sim = R.Simulation(S["x"], S["q"], S["kind"], S["shape"], S["rho_xi"], S["box"], precision=64, skin=0.1,
+                           max_recursions=mr, warm_start=R.WS_PREV, lcp_max_iters=1000000)
+        series, wmax, nrec, maxrec, maxov, cont, failed = [], 0.0, 0, 0, 0.0, 0, None
+        torch.cuda.synchronize()
+        tw = time.perf_counter()
+        for k in range(1, n + 1):
+            x, _, _ = sim.get_state()
+            sim.set_external(I.extensile_field(x))
+            res = sim.step(dt, 1e-5, args.cm_lcp_tol, raise_on_error=False)
+            if res["status"] != 0:
+                failed = dict(step=k, t=round(k * dt, 6), status=int(res["status"]))
+                log("chainmail: %s stopped at t %.3f, status %d" % (method, k * dt, res["status"]))
+                break
+            nrec += res["recursions"] > 0
+            maxrec = max(maxrec, res["recursions"])
+            wmax = max(wmax, res["max_overlap"])
+            cont = res["n_contacts_final"]
+            if k % win == 0:
+                series.append([round(k * dt, 6), wmax, int(cont)])
+                maxov = max(maxov, wmax)
+                wmax = 0.0
+                log("chainmail: %s t %.3f max violation %.3g contacts %d" % (method, k * dt, series[-1][1], cont))
+        el = time.perf_counter() - tw
+        x, _, _ = sim.get_state()
+        sim.close()
+        done = failed["step"] - 1 if failed else n
+        runs.append(dict(method=method, steps=done, failed=failed, ms_per_step=1e3 * el / max(done, 1),
+                         steps_with_recursions=int(nrec),
+                         max_recursions=int(maxrec), max_violation=max(maxov, wmax),
+                         extent_xy=[float(np.ptp(x[:, 0])), float(np.ptp(x[:, 1]))], series=series))
+    print(json.dumps({"metric": "chainmail: largest overlap of the accepted configurations (true ring surfaces)",
+                      "unit": "length (minor radius 0.1)", "data": "synthetic", "rings": int(len(S["x"])),
+                      "dt": dt, "t_end": args.cm_t_end, "overlap_tol": 1e-5, "lcp_tol": args.cm_lcp_tol,
+                      "xi": args.cm_xi,
+                      "jitter": args.cm_jitter,
+                      "extent_xy_start": [float(np.ptp(S["x"][:, 0])), float(np.ptp(S["x"][:, 1]))],
+                      "runs": runs}), flush=True)
+
+
 def packings_workload(args):
     """Batched workload: 512 independent periodic packings (body counts
     log-uniform in [200, 5000], target volume fractions uniform in [0.3,
@@ -378,9 +439,15 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start comparison")
     ap.add_argument("--learned-steps", type=int, default=50)
     ap.add_argument("--workload", default="compaction100k",
-                    choices=("compaction100k", "packings512", "lcp-sweep", "two-ellipsoids"))
+                    choices=("compaction100k", "packings512", "lcp-sweep", "two-ellipsoids", "chainmail"))
     ap.add_argument("--dts", default="0.1,0.01,0.001,0.0001", help="two-ellipsoids: the timesteps")
     ap.add_argument("--t-end", type=float, default=200.0, help="two-ellipsoids: end time (contact from t = 100)")
+    ap.add_argument("--cm-n", type=int, default=5, help="chainmail: node rings per lattice side")
+    ap.add_argument("--cm-dt", type=float, default=1e-3, help="chainmail: timestep")
+    ap.add_argument("--cm-t-end", type=float, default=10.0, help="chainmail: end time")
+    ap.add_argument("--cm-xi", type=float, default=0.1, help="chainmail: drag coefficient")
+    ap.add_argument("--cm-jitter", type=float, default=0.05, help="chainmail: placement jitter (rad)")
+    ap.add_argument("--cm-lcp-tol", type=float, default=1e-9, help="chainmail: LCP residual tolerance")
     ap.add_argument("--sweep-rows", default="25000,100000,400000,1600000,6400000",
                     help="lcp-sweep: target row counts of the lattice LCPs")
     ap.add_argument("--packings", type=int, default=512)
@@ -408,6 +475,9 @@ def main():
         return
     if args.workload == "lcp-sweep":
         lcp_sweep(args)
+        return
+    if args.workload == "chainmail":
+        chainmail_study(args)
         return
     if args.workload == "two-ellipsoids":
         two_ellipsoid_study(args)

@@ -60,8 +60,13 @@ RING_AXIS_Y = (math.cos(math.pi / 4), -math.sin(math.pi / 4), 0.0, 0.0)
 RING_AXIS_X = (math.cos(math.pi / 4), 0.0, math.sin(math.pi / 4), 0.0)
 
 
+def _qmul(a, b):
+    s1, v1, s2, v2 = a[0], np.asarray(a[1:]), b[0], np.asarray(b[1:])
+    return np.concatenate([[s1 * s2 - v1 @ v2], s1 * v2 + s2 * v1 + np.cross(v1, v2)])
+
+
 def chainmail(nx: int = 5, ny: int = 5, R: float = 1.0, r: float = 0.1, slack: float = 0.45,
-              xi: float = 1.0) -> dict:
+              xi: float = 1.0, jitter: float = 0.0, seed: int = 0) -> dict:
     """Interlaced rings on a square lattice (the paper's layout is not
     given; this one is ours): flat rings (axis z) at the nodes (i L, j L, 0)
     of an nx x ny lattice centred at the origin, and one connector ring per
@@ -71,7 +76,11 @@ def chainmail(nx: int = 5, ny: int = 5, R: float = 1.0, r: float = 0.1, slack: f
     plane z = 0 at L/2 - R from each node, inside the hole.  L is chosen so
     that pulling a connector and a node ring apart along the edge closes a
     surface gap of `slack` before the tubes touch: L/2 = 2 (R - r) - slack.
-    Overdamped drag xi; the extensile field is `extensile_field`."""
+    jitter > 0 turns each ring by a seeded random angle of up to `jitter`
+    (radians, random axis) and moves it by up to jitter / 2 along each
+    coordinate, breaking the lattice's symmetry (keep it well below the
+    smallest gap, about 0.3 at slack 0.45).  Overdamped drag xi; the
+    extensile field is `extensile_field`."""
     half = 2.0 * (R - r) - slack
     if not (half > R + 2.0 * r and half < 2.0 * R - 2.0 * r):
         raise ValueError("slack outside the range that keeps the rings linked and apart")
@@ -92,6 +101,13 @@ def chainmail(nx: int = 5, ny: int = 5, R: float = 1.0, r: float = 0.1, slack: f
     x = np.array(x, float)
     x -= np.array([(nx - 1) * L / 2, (ny - 1) * L / 2, 0.0])
     n = x.shape[0]
+    if jitter > 0:
+        rng = rng_for(seed)
+        ax = rng.normal(size=(n, 3))
+        ax /= np.linalg.norm(ax, axis=1, keepdims=True)
+        ang = jitter * rng.random(n)
+        q = [_qmul(np.concatenate([[math.cos(a / 2)], math.sin(a / 2) * e]), qi) for a, e, qi in zip(ang, ax, q)]
+        x = x + 0.5 * jitter * rng.uniform(-1, 1, (n, 3))
     return dict(x=x, q=np.array(q, float), kind=np.full(n, TORUS, np.int32), shape=np.tile([R, r, 0.0], (n, 1)),
                 rho_xi=np.full(n, xi), box=np.zeros(3), n_nodes=nx * ny, spacing=L)
 

@@ -200,3 +200,40 @@ def test_torus_mobility_length():
     L = 2 * (R + r)
     np.testing.assert_allclose(np.ravel(kt)[:3], 1 / (xi * L), rtol=1e-15)
     np.testing.assert_allclose(np.ravel(Kr)[[0, 4, 8]], 12 / (xi * L ** 3), rtol=1e-15)
+
+
+def test_chainmail_lattice_linked_and_apart():
+    """The chainmail input: no two rings overlap (oracle SNSD over every pair
+    within reach), each connector's centre circle crosses the plane of the
+    node rings inside the holes of both rings of its edge, and stretching an
+    edge closes exactly the stated slack before the tubes touch."""
+    from paper_2506_14097_amd import inputs as I
+    for slack in (0.45, 0.05):
+        S = I.chainmail(3, 3, slack=slack)
+        x, q, shape = S["x"], S["q"], S["shape"]
+        pa, pb = O.broadphase(x, S["kind"], shape, S["box"], 0.5)
+        phi = O.snsd_pairs(pa, pb, x, q, S["kind"], shape, S["box"])[:, 0]
+        assert phi.min() > 0 and abs(phi.min() - min(slack, np.sqrt(2) * (S["spacing"] / 2 - 1) - 0.2)) < 1e-12
+        nodes = x[:S["n_nodes"]]
+        R, r = shape[0, 0], shape[0, 1]
+        for k in range(S["n_nodes"], len(x)):
+            e = O.quat_to_R(q[k])[:, 2]
+            u = np.cross(e, [0, 0, 1.0])          # horizontal, in the connector's plane
+            for p in (x[k] + R * u, x[k] - R * u):   # where its centre circle meets z = 0
+                dn = np.linalg.norm(nodes - p, axis=1).min()
+                assert dn < R - 2 * r
+        # the link of the first edge: node 0 and its connector, gap along x
+        k = S["n_nodes"]
+        out = O.snsd_pairs([0], [k], x, q, S["kind"], shape, S["box"])[0]
+        assert abs(out[0] - slack) < 1e-12
+
+
+def test_extensile_field():
+    from paper_2506_14097_amd import inputs as I
+    x = np.array([[0, 0, 0], [3.0, 4.0, 0.0], [0, 0, 9.99e-4], [0, 0, 1.001e-3]])
+    f = I.extensile_field(x)
+    np.testing.assert_array_equal(f[0], 0.0)
+    np.testing.assert_allclose(f[1, :3], x[1] * (5 - np.sin(5)) / 25, rtol=1e-15)
+    assert np.all(f[:, 3:] == 0)
+    # the series and the direct form meet smoothly at |x| = 1e-3
+    assert abs(f[2, 2] / 9.99e-4 ** 2 - f[3, 2] / 1.001e-3 ** 2) < 1e-6
