@@ -36,6 +36,10 @@ struct SnsdArgs {
     // slots each), or null
     unsigned long long *minphi;
     unsigned long long *minmarg;
+    // 2: every body is a torus, so the launch may use the kernel built for
+    // tori alone (no ellipsoid or spherocylinder code to share registers
+    // with); anything else: the kernel for every kind
+    int only_kind = -1;
 };
 
 struct BodySetupArgs {

@@ -338,13 +338,16 @@ __device__ Snsd snsd_torus(d3 d, d3 ea, double Ra, double ra, d3 eb, double Rb, 
     const double step = 2.0 * M_PI / kTorusNs;
     double cs, sn;
     sincos(step, &sn, &cs);
-    // the kTorusK smallest sampled local minima (value, sample), ascending
-    double kv[kTorusK];
+    // the kTorusK smallest sampled local minima (value, sample, cos, sin),
+    // ascending
+    double kv[kTorusK], kc[kTorusK], ks[kTorusK];
     int ki[kTorusK];
 #pragma unroll
     for (int k = 0; k < kTorusK; ++k) {
         kv[k] = 1e300;
         ki[k] = -1;
+        kc[k] = 1.0;
+        ks[k] = 0.0;
     }
     // samples by rotation of (cos, sin) by the step (drift of a few ulp over
     // the turn: the samples only pick the brackets)
@@ -357,12 +360,18 @@ __device__ Snsd snsd_torus(d3 d, d3 ea, double Ra, double ra, d3 eb, double Rb, 
         if (gc <= gp && gc <= gn && gc < kv[kTorusK - 1]) {
             kv[kTorusK - 1] = gc;
             ki[kTorusK - 1] = i;
+            kc[kTorusK - 1] = c;
+            ks[kTorusK - 1] = s;
 #pragma unroll
             for (int k = kTorusK - 1; k > 0; --k)
                 if (kv[k] < kv[k - 1]) {
-                    const double tv = kv[k];
+                    const double tv = kv[k], tc = kc[k], ts = ks[k];
                     kv[k] = kv[k - 1];
+                    kc[k] = kc[k - 1];
+                    ks[k] = ks[k - 1];
                     kv[k - 1] = tv;
+                    kc[k - 1] = tc;
+                    ks[k - 1] = ts;
                     const int ti = ki[k];
                     ki[k] = ki[k - 1];
                     ki[k - 1] = ti;
@@ -373,14 +382,16 @@ __device__ Snsd snsd_torus(d3 d, d3 ea, double Ra, double ra, d3 eb, double Rb, 
         c = cn;
         s = snx;
     }
-    double bt = 0.0, bg = 1e300;
+    // Newton on g' from each candidate; (cos t, sin t) follow t by rotation
+    // through the step taken (its cosine and sine by their Taylor series to
+    // degree 8 and 9 below 0.05 rad, error under 1e-17; sincos above)
+    double bg = 1e300, bc = 1.0, bs = 0.0;
 #pragma unroll
     for (int k = 0; k < kTorusK; ++k) {
         if (ki[k] < 0) continue;
         double t = step * ki[k], lo = t - step, hi = t + step;
+        double ct = kc[k], st = ks[k];
         for (int it = 0; it < 40; ++it) {
-            double st, ct;
-            sincos(t, &st, &ct);
             const RingPoint r = ring_point<true>(ct, st, e1, e2, Ra, d, eb, Rb);
             if (r.g1 < 0.0)
                 lo = t;
@@ -388,21 +399,29 @@ __device__ Snsd snsd_torus(d3 d, d3 ea, double Ra, double ra, d3 eb, double Rb, 
                 hi = t;
             double tn = r.g2 > 0.0 ? t - r.g1 / r.g2 : 0.5 * (lo + hi);
             if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-            const bool done = fabs(tn - t) <= 1e-15 * (1.0 + fabs(t));
+            const double dl = tn - t;
+            double cd, sd;
+            if (fabs(dl) < 0.05) {
+                const double z = dl * dl;
+                cd = 1.0 - z * (1.0 / 2 - z * (1.0 / 24 - z * (1.0 / 720 - z * (1.0 / 40320))));
+                sd = dl * (1.0 - z * (1.0 / 6 - z * (1.0 / 120 - z * (1.0 / 5040 - z * (1.0 / 362880)))));
+            } else {
+                sincos(dl, &sd, &cd);
+            }
+            const double cn = ct * cd - st * sd;
+            st = st * cd + ct * sd;
+            ct = cn;
             t = tn;
-            if (done) break;
+            if (fabs(dl) <= 1e-15 * (1.0 + fabs(t))) break;
         }
-        double st, ct;
-        sincos(t, &st, &ct);
         const double g = ring_point<false>(ct, st, e1, e2, Ra, d, eb, Rb).g;
         if (g < bg) {
             bg = g;
-            bt = t;
+            bc = ct;
+            bs = st;
         }
     }
-    double st, ct;
-    sincos(bt, &st, &ct);
-    const d3 pa = Ra * (ct * e1 + st * e2);  // centre-circle point of a (relative to x_a)
+    const d3 pa = Ra * (bc * e1 + bs * e2);  // centre-circle point of a (relative to x_a)
     const d3 w = pa - d;
     const d3 up = w - dot(w, eb) * eb;
     const double rho = sqrt(dot(up, up));
@@ -631,6 +650,9 @@ __device__ inline unsigned long long order_key(double v) {
     return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
 }
 
+// KIND = -1: every shape kind; KIND = 2: tori only (the ellipsoid Newton
+// code, whose register demand spills the kernel for every kind, is absent).
+template <int KIND>
 __global__ void __launch_bounds__(256, 4) k_snsd_pairs(SnsdArgs A) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     double phi = 1e300, marg = 1e300;
@@ -647,7 +669,7 @@ __global__ void __launch_bounds__(256, 4) k_snsd_pairs(SnsdArgs A) {
         const d3 xa = mk(A.x[a], A.x[A.ldx + a], A.x[2 * A.ldx + a]);
         const d3 xb = mk(A.x[b], A.x[A.ldx + b], A.x[2 * A.ldx + b]);
         const double rba = A.Rb ? A.Rb[a] : 0.0, rbb = A.Rb ? A.Rb[b] : 0.0;
-        const int kd = A.kind[a];
+        const int kd = KIND >= 0 ? KIND : A.kind[a];
         double ga[6], gb[6];
 #pragma unroll
         for (int t = 0; t < 6; ++t) {
@@ -668,7 +690,7 @@ __global__ void __launch_bounds__(256, 4) k_snsd_pairs(SnsdArgs A) {
             s.n = (1.0 / dl) * d;
             s.ra = rba * s.n;
             s.rb = (-rbb) * s.n;
-        } else if (kd == 0) {
+        } else if (KIND < 0 && kd == 0) {
             const sym3 Sa{ga[0], ga[1], ga[2], ga[3], ga[4], ga[5]};
             const sym3 Sb{gb[0], gb[1], gb[2], gb[3], gb[4], gb[5]};
             bool has = false;
@@ -681,7 +703,7 @@ __global__ void __launch_bounds__(256, 4) k_snsd_pairs(SnsdArgs A) {
         } else if (kd == 2) {
             s = snsd_torus(d, mk(ga[0], ga[1], ga[2]), A.p[a], A.p[A.ldp + a], mk(gb[0], gb[1], gb[2]), A.p[b],
                            A.p[A.ldp + b]);
-        } else {
+        } else if (KIND < 0) {
             const d3 ta = mk(ga[0], ga[1], ga[2]);
             const d3 tb = mk(gb[0], gb[1], gb[2]);
             s = snsd_spherocyl(d, ta, A.p[A.ldp + a], A.p[a], tb, A.p[A.ldp + b], A.p[b], A.planar != 0);
@@ -956,7 +978,10 @@ int trial_blocks(int nb) { return nblk(nb > 0 ? nb : 1, 256); }
 
 void launch_snsd_pairs(const SnsdArgs &a, hipStream_t s) {
     if (a.m <= 0) return;
-    launch_k(k_snsd_pairs, dim3(nblk(a.m, 256)), dim3(256), 0, s, a);
+    if (a.only_kind == 2)
+        launch_k(k_snsd_pairs<2>, dim3(nblk(a.m, 256)), dim3(256), 0, s, a);
+    else
+        launch_k(k_snsd_pairs<-1>, dim3(nblk(a.m, 256)), dim3(256), 0, s, a);
 }
 
 void launch_cell_assign(int nb, const double *x, int ldx, const int *body_batch, const PackGrid *grids,

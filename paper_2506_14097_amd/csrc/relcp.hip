@@ -296,6 +296,7 @@ struct relcp_ctx {
     // features of the iteration-0 rows, contact log of the last accepted step
     bool has_model = false, log_on = false, log_valid = false;
     bool has_torus = false;  // some body is a torus (no learned warm start then)
+    bool all_torus = false;  // every body is a torus (the SNSD kernel built for tori alone)
     float mlp_norm[MLP_NORM] = {};
     DBuf<float> mlp_w, feat;
     DBuf<double> rowscale;
@@ -550,13 +551,17 @@ void relcp_ctx::upload_bodies(const relcp_bodies *B, const relcp_shapes *S) {
         for (int k = 0; k < 3 * nbatch; ++k) box[k] = B->box[k];
     rmax.assign(nbatch, 0.0);
     has_torus = false;
+    all_torus = true;
     std::vector<int> bb(n);
     for (int pk = 0; pk < nbatch; ++pk)
         for (int i = boff[pk]; i < boff[pk + 1]; ++i) {
             bb[i] = pk;
             const double *pp = S->p + 3 * i;
             rmax[pk] = std::max(rmax[pk], bound_radius(S->kind[i], pp));
-            if (S->kind[i] == RELCP_TORUS) has_torus = true;
+            if (S->kind[i] == RELCP_TORUS)
+                has_torus = true;
+            else
+                all_torus = false;
         }
     // spatial order inside each packing
     perm.resize(n);
@@ -1385,6 +1390,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     SnsdArgs sa{};
     sa.m = np; sa.pa = pa.p; sa.pb = pb.p; sa.body_batch = body_batch.p; sa.x = x.p; sa.ldx = N; sa.geo = geo.p;
     sa.ldg = N; sa.kind = kind.p; sa.p = p.p; sa.ldp = N; sa.boxes = boxes.p; sa.planar = planar; sa.hint = nullptr;
+    sa.only_kind = all_torus ? 2 : -1;
     sa.out = snsd0.p; sa.ldo = ldp; sa.mode = 0; sa.thresh = skin; sa.eps = eps; sa.flag = pflag.p;
     sa.bcount = pcnt.p;
     sa.minphi = nullptr; sa.minmarg = nullptr; sa.Rb = Rb.p;
