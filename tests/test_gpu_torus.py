@@ -8,6 +8,8 @@
   step against the oracle's step from the GPU's own state: the same contact
   sets per recursion, velocities to 1e-8 of their scale, positions and
   orientations to 1e-10;
+* the contrast of Sec. 6 on a small chainmail at drag 0.1, dt 1e-3: ReLCP
+  within the overlap tolerance, LCP-SNSD beyond it;
 * shape checks: tori are refused in a monolayer, under inertial dynamics and
   with a negative major radius.
 """
@@ -147,3 +149,26 @@ def test_torus_shape_checks(dev):
     bad[0, 0] = -1.0
     with pytest.raises(R.RelcpError):
         R.Simulation(S["x"], S["q"], S["kind"], bad, S["rho_xi"], S["box"])
+
+
+def test_chainmail_relcp_against_snsd(dev):
+    """The contrast of Sec. 6 through the library: ReLCP within the overlap
+    tolerance with recursions, LCP-SNSD beyond it (the oracle shows the same
+    on this input)."""
+    out = {}
+    for mr in (64, 0):
+        S = I.chainmail(3, 3, slack=0.05, xi=0.1, jitter=0.05)
+        sim = R.Simulation(S["x"], S["q"], S["kind"], S["shape"], S["rho_xi"], S["box"], precision=64, skin=0.1,
+                           max_recursions=mr)
+        worst = nrec = 0
+        for _ in range(50):
+            x, _, _ = sim.get_state()
+            sim.set_external(I.extensile_field(x))
+            res = sim.step(1e-3, 1e-5, 1e-9)
+            worst = max(worst, res["max_overlap"])
+            nrec += res["recursions"] > 0
+        sim.close()
+        out[mr] = (worst, nrec)
+    print("chainmail ReLCP", out[64], "LCP-SNSD", out[0], flush=True)
+    assert out[64][0] <= 1e-5 and out[64][1] >= 10
+    assert out[0][0] > 2e-5 and out[0][1] == 0

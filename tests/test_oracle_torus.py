@@ -12,7 +12,10 @@ step between rings:
 * symmetries: exchanging the bodies, a rigid rotation of the pair;
 * a step: two interlaced rings pulled apart by equal and opposite forces
   (a taut chain link), and two coplanar rings pressed together, where the
-  multiplier is exactly the force and the rings stay touching.
+  multiplier is exactly the force and the rings stay touching;
+* the chainmail input (linked, apart, the slack exact), the extensile field,
+  and the contrast of Sec. 6: ReLCP within the overlap tolerance where the
+  single-constraint SNSD LCP overlaps beyond it.
 """
 import numpy as np
 import pytest
@@ -237,3 +240,25 @@ def test_extensile_field():
     assert np.all(f[:, 3:] == 0)
     # the series and the direct form meet smoothly at |x| = 1e-3
     assert abs(f[2, 2] / 9.99e-4 ** 2 - f[3, 2] / 1.001e-3 ** 2) < 1e-6
+
+
+def test_chainmail_augmentation_holds_the_tolerance():
+    """Sec. 6: on a chainmail pulled taut at a timestep outside the linear
+    regime, ReLCP keeps every accepted configuration within the overlap
+    tolerance by appending constraints, while the single-constraint SNSD LCP
+    (no recursions) overlaps beyond it (3 x 3 nodes, drag 0.1, dt 1e-3)."""
+    from paper_2506_14097_amd import inputs as I
+    out = {}
+    for mr in (64, 0):
+        S = I.chainmail(3, 3, slack=0.05, xi=0.1, jitter=0.05)
+        x, q, prev, worst, nrec = S["x"], S["q"], None, 0.0, 0
+        for _ in range(50):
+            ref = O.relcp_step(x, q, S["kind"], S["shape"], S["rho_xi"], S["box"], dt=1e-3, eps=1e-5, tol=1e-9,
+                               skin=0.1, fext=I.extensile_field(x), max_recursions=mr, prev=prev)
+            assert ref["status"] == 0
+            x, q, prev = ref["x"], ref["q"], O.pair_lambda(ref)
+            worst = max(worst, ref["max_overlap"])
+            nrec += ref["recursions"] > 0
+        out[mr] = (worst, nrec)
+    assert out[64][0] <= 1e-5 and out[64][1] >= 10
+    assert out[0][0] > 2e-5 and out[0][1] == 0
