@@ -285,7 +285,9 @@ RELCP_API int relcp_mlp_adam(float *params, const float *grad, float *m, float *
  * ball) of m pairs, FP64.  Device SoA inputs for the bodies: x (3 arrays of
  * nb), q (4 arrays of nb), kind, p (3 arrays of nb); pairs pa, pb (m);
  * box[3] host.  Output out (10 arrays of m): Phi, n (3), r_a = p_a - x_a (3),
- * r_b = p_b - x_b (3).  Runs on `stream` (hipStream_t, NULL = default) and
+ * r_b = p_b - x_b (3).  Both bodies of a pair share one kind (ellipsoids,
+ * spherocylinders, or tori: the centre-circle distance minus both minor
+ * radii, Sec. 6).  Runs on `stream` (hipStream_t, NULL = default) and
  * synchronises before returning. */
 RELCP_API int relcp_snsd_device(int32_t nb, const double *x, const double *q, const int32_t *kind, const double *p, int32_t m,
                       const int32_t *pa, const int32_t *pb, const double *box, int32_t planar, double *out,
