@@ -301,7 +301,7 @@ __device__ Snsd snsd_spherocyl(d3 d, d3 ta, double la, double ra, d3 tb, double 
 // there), or the axis of a when the tangents are parallel, signed n.d >= 0;
 // a point of a on b's axis takes b's first frame vector as the direction.
 // ===========================================================================
-constexpr int kTorusNs = 128;
+constexpr int kTorusNs = 64;
 constexpr int kTorusK = 4;
 
 struct RingPoint {

@@ -1,6 +1,7 @@
 """GPU: tori (the rings of Sec. 6) through the C ABI against the oracle.
 
-* SNSD of random torus pairs and of special configurations: Phi (the
+* SNSD of random torus pairs, of linked or nearly linked pairs (competing
+  local minima) and of special configurations: Phi (the
   centre-circle distance minus the minor radii) to 1e-11; where the closest
   pair is unique (the oracle's next local minimum is 1e-6 worse), the normal
   and both contact points to 1e-9;
@@ -172,3 +173,32 @@ def test_chainmail_relcp_against_snsd(dev):
     print("chainmail ReLCP", out[64], "LCP-SNSD", out[0], flush=True)
     assert out[64][0] <= 1e-5 and out[64][1] >= 10
     assert out[0][0] > 2e-5 and out[0][1] == 0
+
+
+def test_snsd_tori_linked_pairs(dev):
+    """Pairs whose second ring is centred near the first ring's centre circle
+    (linked or nearly so, random axes): several local minima compete, so the
+    sampled search must still find the global one."""
+    rng = np.random.default_rng(7)
+    m = 2000
+    qa, qb = I.shoemake_quaternions(rng, m), I.shoemake_quaternions(rng, m)
+    Ra, Rb = rng.uniform(0.6, 1.2, m), rng.uniform(0.6, 1.2, m)
+    t = rng.uniform(0, 2 * np.pi, m)
+    x = np.zeros((2 * m, 3))
+    q = np.zeros((2 * m, 4))
+    shape = np.zeros((2 * m, 3))
+    for k in range(m):
+        Ma = O.quat_to_R(qa[k])
+        c = Ra[k] * (np.cos(t[k]) * Ma[:, 0] + np.sin(t[k]) * Ma[:, 1])
+        x[2 * k] = (10.0 * k, 0, 0)
+        x[2 * k + 1] = x[2 * k] + c + rng.normal(0, 0.25, 3)
+        q[2 * k], q[2 * k + 1] = qa[k], qb[k]
+        shape[2 * k, :2], shape[2 * k + 1, :2] = (Ra[k], 0.1), (Rb[k], 0.08)
+    kind = np.full(2 * m, I.TORUS, np.int32)
+    pa, pb = np.arange(0, 2 * m, 2, dtype=np.int32), np.arange(1, 2 * m, 2, dtype=np.int32)
+    out = gpu_snsd(dev, x, q, kind, shape, pa, pb)
+    ref, unique = oracle_with_margin(x, q, shape, pa, pb)
+    err = np.abs(out[:, 0] - ref[:, 0])
+    print("linked pairs: max |dPhi| %.3g, unique %d of %d" % (err.max(), unique.sum(), m), flush=True)
+    assert err.max() < 1e-11
+    assert np.abs(out[unique, 1:] - ref[unique, 1:]).max() < 1e-9
