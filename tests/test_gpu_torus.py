@@ -9,6 +9,8 @@
   step against the oracle's step from the GPU's own state: the same contact
   sets per recursion, velocities to 1e-8 of their scale, positions and
   orientations to 1e-10;
+* a context holding an ellipsoid packing and a chainmail (the narrowphase
+  kernel for every kind), each packing against its own oracle step;
 * the contrast of Sec. 6 on a small chainmail at drag 0.1, dt 1e-3: ReLCP
   within the overlap tolerance, LCP-SNSD beyond it;
 * shape checks: tori are refused in a monolayer, under inertial dynamics and
@@ -20,6 +22,8 @@ import pytest
 import oracle as O
 from paper_2506_14097_amd import inputs as I
 from paper_2506_14097_amd import relcp as R
+
+from states import compressed_packing
 
 pytestmark = pytest.mark.gpu
 
@@ -202,3 +206,43 @@ def test_snsd_tori_linked_pairs(dev):
     print("linked pairs: max |dPhi| %.3g, unique %d of %d" % (err.max(), unique.sum(), m), flush=True)
     assert err.max() < 1e-11
     assert np.abs(out[unique, 1:] - ref[unique, 1:]).max() < 1e-9
+
+
+def test_mixed_batch_of_ellipsoids_and_rings(dev):
+    """One context holding a periodic ellipsoid packing and an open chainmail
+    (one kind per packing): the narrowphase kernel for every kind then
+    handles the rings.  Each packing's step against the oracle's step of
+    that packing alone, from the GPU's own state, over 20 steps."""
+    P = compressed_packing(3, 120, 24)
+    Cm = I.chainmail(3, 3, slack=0.02)
+    parts = [dict(P, x=P["x"] * 0.99, box=P["box"] * 0.99), Cm]
+    off = np.cumsum([0] + [len(p["x"]) for p in parts]).astype(np.int32)
+    cat = lambda k: np.concatenate([p[k] for p in parts])
+    sim = R.Simulation(cat("x"), cat("q"), cat("kind"), cat("shape"), cat("rho_xi"), np.stack([p["box"] for p in parts]),
+                       batch_off=off, precision=64, skin=0.2, warm_start=R.WS_COLD)
+    ring = slice(off[1], off[2])
+    compared = 0
+    for k in range(20):
+        x, q, _ = sim.get_state()
+        f = np.zeros((len(x), 6))
+        f[ring] = I.extensile_field(x[ring])
+        sim.set_external(f)
+        refs = []
+        for j, p in enumerate(parts):
+            sl = slice(off[j], off[j + 1])
+            refs.append(O.relcp_step(x[sl], q[sl], p["kind"], p["shape"], p["rho_xi"], p["box"], dt=0.01, eps=1e-5,
+                                     tol=1e-12, skin=0.2, fext=f[sl], lcp_mode=1, prev=None))
+        res = sim.step(0.01, 1e-5, 1e-12)
+        assert res["status"] == 0 and all(r["status"] == 0 for r in refs), k
+        xg, qg, Ug = sim.get_state()
+        if any(np.any(r["margin"] < 1e-9) for r in refs):
+            continue
+        for j, r in enumerate(refs):
+            sl = slice(off[j], off[j + 1])
+            assert np.abs(Ug[sl] - r["U"]).max() < 1e-8 * max(1.0, np.abs(r["U"]).max()), (k, j)
+            assert np.abs(xg[sl] - r["x"]).max() < 1e-10, (k, j)
+            assert np.abs(qg[sl] - r["q"]).max() < 1e-10, (k, j)
+        compared += 1
+    print("mixed batch: steps compared", compared, flush=True)
+    sim.close()
+    assert compared > 15
