@@ -1,7 +1,7 @@
 """GPU parity: the HIP library (through its C ABI) against the CPU oracle on
 identical seeded inputs.
 
-Bars ("parity"):
+Bars:
  * candidate pairs: bit-exact lists;
  * SNSD (FP64): |Phi| to 1e-10, normals and lever arms to 1e-8;
  * LCP / step, FP64 path: velocities and wrenches within 1e-8 relative to
