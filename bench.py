@@ -14,6 +14,12 @@ Prints one JSON line with steps/s, the roofline of the dominant kernel
 learned warm start against the previous-step one on the same workload
 (projected-gradient iterations and time per step; the model is trained on
 the GPU first, untimed) and the CPU oracle timed on a bounded sample.
+
+Other workloads (--workload): packings512 (512 independent packings in one
+context), lcp-sweep (the LCP pass across sizes), two-ellipsoids (the
+timestep refinement of Sec. 5.1) and chainmail (interlaced rings under the
+extensile field of Sec. 6, ReLCP against LCP-SNSD); each prints its own
+JSON line.
 """
 from __future__ import annotations
 
