@@ -129,6 +129,8 @@ typedef struct {
     int32_t n_waits;             /* host waits during the step (polls of results the kernels write to
                                     host-mapped memory, or stream synchronisations) */
     double t_wait;               /* milliseconds of host clock spent in those waits */
+    int32_t rowgraph_restarts;   /* row-graph assemblies that overflowed their entry slots and were
+                                    re-sized, their solve restarted from the same start */
 } relcp_step_stats;
 
 /* Create a context (Sec. 2.1.1 state, Sec. 2.1.2 laws of motion).  Validates

@@ -29,10 +29,12 @@ OK, E_INVALID, E_OOM, E_DEVICE, E_LCP_MAXITER, E_RECURSION_CAP, E_SKIN, E_NAN, E
 
 
 def build(force: bool = False) -> str:
-    """Compile the C oracle with gcc (no FMA contraction)."""
+    """Compile the C oracle with gcc (no FMA contraction; OpenMP shares
+    independent pairs among threads, OMP_NUM_THREADS sets how many)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC,
+                               "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -62,8 +64,15 @@ def lib():
         assert L.orc_stats_size() == C.sizeof(Stats), "oracle stats layout mismatch"
         assert L.orc_params_size() == C.sizeof(Params), "oracle params layout mismatch"
         L.orc_broadphase.restype = C.c_int64
+        L.orc_broadphase_cells.restype = C.c_int64
         _lib = L
     return _lib
+
+
+def threads(n=0):
+    """Set the OpenMP threads of the per-pair loops (n > 0); returns the
+    number in use."""
+    return int(lib().orc_threads(C.c_int(n)))
 
 
 def _d(a, n=None):
@@ -136,18 +145,19 @@ def snsd_pairs(pa, pb, x, q, kind, shape, box, planar=0):
     return out[:m]
 
 
-def broadphase(x, kind, shape, box, skin):
-    """All pairs a < b with bounding-sphere gap <= skin, sorted by (a, b)."""
+def broadphase(x, kind, shape, box, skin, cells=False):
+    """All pairs a < b with bounding-sphere gap <= skin, sorted by (a, b):
+    by brute force over all pairs, or (cells=True) through a cell grid, the
+    search the oracle step uses for large n."""
     x = _d(x)
     n = x.size // 3
     kind, shape, box = _i(kind), _d(shape), _d(box, 3)
     L = lib()
-    m = L.orc_broadphase(C.c_int(n), _p(x), _p(kind), _p(shape), _p(box), C.c_double(skin), C.c_int64(0),
-                         None, None)
+    f = L.orc_broadphase_cells if cells else L.orc_broadphase
+    m = f(C.c_int(n), _p(x), _p(kind), _p(shape), _p(box), C.c_double(skin), C.c_int64(0), None, None)
     pa = np.zeros(max(m, 1), np.int32)
     pb = np.zeros(max(m, 1), np.int32)
-    L.orc_broadphase(C.c_int(n), _p(x), _p(kind), _p(shape), _p(box), C.c_double(skin), C.c_int64(m), _p(pa),
-                     _p(pb))
+    f(C.c_int(n), _p(x), _p(kind), _p(shape), _p(box), C.c_double(skin), C.c_int64(m), _p(pa), _p(pb))
     return pa[:m], pb[:m]
 
 

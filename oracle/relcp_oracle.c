@@ -13,10 +13,12 @@
  * algorithm).  Where the paper is silent the reading used is stated in the
  * comment; the GPU library takes the same readings.
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, so the
- * arithmetic is exactly the order written here).
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (no FMA
+ * contraction, so the arithmetic is exactly the order written here; OpenMP
+ * only shares independent pairs among threads).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -493,7 +495,7 @@ void orc_snsd_torus(const double d[3], const double ea[3], double Ra, double ra,
     double vb[3];
     plane_basis(eb, T.ub, vb);
     const double step = 2.0 * M_PI / ORC_TORUS_NS;
-    static double f[ORC_TORUS_NS];
+    double *f = malloc(sizeof(double) * ORC_TORUS_NS); /* per call: pairs run on several threads */
     for (int i = 0; i < ORC_TORUS_NS; ++i) f[i] = ring_gap2(&T, step * i);
     /* the ORC_TORUS_K smallest sampled local minima, in sample order on ties */
     int idx[ORC_TORUS_K];
@@ -516,6 +518,7 @@ void orc_snsd_torus(const double d[3], const double ea[3], double Ra, double ra,
         fk[k] = golden_min(&T, t0 - step, t0 + step, &tk[k]);
         if (fk[k] < fk[best]) best = k;
     }
+    free(f);
     if (second) {
         double sv = INFINITY;
         for (int k = 0; k < nk; ++k) {
@@ -596,6 +599,125 @@ int64_t orc_broadphase(int n, const double *x, const int *kind, const double *sh
     return m;
 }
 
+/* The same pairs, in the same order, found through a uniform grid of cells
+ * (for large n; the step uses it above ORC_CELLS_FROM bodies).  A pair whose
+ * bounding-sphere gap is <= skin has its centres (minimum image) within
+ * h = 2 R_max + skin of each other, so with cells at least h wide its bodies
+ * sit in the same or neighbouring cells along every direction.  Each
+ * neighbouring cell is visited once even where a periodic direction has
+ * fewer than three cells; the test applied to each candidate is the one of
+ * orc_broadphase, and every body's partners are sorted, so the list is
+ * identical to the all-pairs search. */
+#define ORC_CELLS_FROM 4096
+
+static int cmp_int(const void *a, const void *b) {
+    int x = *(const int *)a, y = *(const int *)b;
+    return (x > y) - (x < y);
+}
+
+int64_t orc_broadphase_cells(int n, const double *x, const int *kind, const double *shape, const double box[3],
+                             double skin, int64_t cap, int *pa, int *pb) {
+    if (n <= 0) return 0;
+    double Rmax = 0.0;
+    for (int a = 0; a < n; ++a) Rmax = fmax(Rmax, bounding_radius(kind[a], shape + 3 * a));
+    const double h = (2.0 * Rmax + skin) * (1.0 + 1e-9);
+    double lo[3], w[3], ext[3];
+    int nc[3];
+    for (int k = 0; k < 3; ++k) {
+        if (box[k] > 0.0) {
+            lo[k] = 0.0;
+            ext[k] = box[k];
+            nc[k] = (int)floor(box[k] / h);
+            if (nc[k] < 1) nc[k] = 1;
+            w[k] = box[k] / nc[k];
+        } else {
+            double mn = INFINITY, mx = -INFINITY;
+            for (int a = 0; a < n; ++a) { mn = fmin(mn, x[3 * a + k]); mx = fmax(mx, x[3 * a + k]); }
+            lo[k] = mn;
+            ext[k] = mx - mn;
+            w[k] = h;
+            nc[k] = (int)floor(ext[k] / w[k]) + 1;
+        }
+    }
+    /* open directions: wider cells where the bodies are sparse */
+    for (;;) {
+        if ((double)nc[0] * nc[1] * nc[2] <= 8.0 * n + 64.0) break;
+        int widened = 0;
+        for (int k = 0; k < 3; ++k)
+            if (!(box[k] > 0.0) && nc[k] > 1) {
+                w[k] *= 2.0;
+                nc[k] = (int)floor(ext[k] / w[k]) + 1;
+                widened = 1;
+            }
+        if (!widened) break;
+    }
+    const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+    int *cell = malloc(sizeof(int) * (size_t)n);
+    int *start = calloc((size_t)ncell + 1, sizeof(int));
+    int *items = malloc(sizeof(int) * (size_t)n);
+    int *cand = malloc(sizeof(int) * (size_t)n);
+    int (*cc)[3] = malloc(sizeof(int[3]) * (size_t)n);
+    for (int a = 0; a < n; ++a) {
+        int64_t id = 0;
+        for (int k = 0; k < 3; ++k) {
+            double v = x[3 * a + k] - lo[k];
+            if (box[k] > 0.0) v -= box[k] * floor(v / box[k]);
+            int c = (int)floor(v / w[k]);
+            if (c < 0) c = 0;
+            if (c >= nc[k]) c = nc[k] - 1;
+            cc[a][k] = c;
+            id = id * nc[k] + c;
+        }
+        cell[a] = (int)id;
+        start[id + 1] += 1;
+    }
+    for (int64_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
+    {
+        int *cur = malloc(sizeof(int) * (size_t)(ncell + 1));
+        memcpy(cur, start, sizeof(int) * (size_t)(ncell + 1));
+        for (int a = 0; a < n; ++a) items[cur[cell[a]]++] = a;
+        free(cur);
+    }
+    int64_t m = 0;
+    for (int a = 0; a < n; ++a) {
+        const double Ra = bounding_radius(kind[a], shape + 3 * a);
+        /* distinct neighbouring cell indices along each direction */
+        int nb[3][3], cnt[3];
+        for (int k = 0; k < 3; ++k) {
+            cnt[k] = 0;
+            for (int o = -1; o <= 1; ++o) {
+                int c = cc[a][k] + o;
+                if (box[k] > 0.0) c = (c % nc[k] + nc[k]) % nc[k];
+                else if (c < 0 || c >= nc[k]) continue;
+                int seen = 0;
+                for (int t = 0; t < cnt[k]; ++t) seen |= nb[k][t] == c;
+                if (!seen) nb[k][cnt[k]++] = c;
+            }
+        }
+        int nck = 0;
+        for (int i0 = 0; i0 < cnt[0]; ++i0)
+            for (int i1 = 0; i1 < cnt[1]; ++i1)
+                for (int i2 = 0; i2 < cnt[2]; ++i2) {
+                    int64_t id = ((int64_t)nb[0][i0] * nc[1] + nb[1][i1]) * nc[2] + nb[2][i2];
+                    for (int t = start[id]; t < start[id + 1]; ++t) {
+                        int b = items[t];
+                        if (b <= a) continue;
+                        double Rb = bounding_radius(kind[b], shape + 3 * b);
+                        double d[3];
+                        min_image(x + 3 * a, x + 3 * b, box, d);
+                        if (norm3(d) - Ra - Rb <= skin) cand[nck++] = b;
+                    }
+                }
+        qsort(cand, (size_t)nck, sizeof(int), cmp_int);
+        for (int t = 0; t < nck; ++t) {
+            if (m < cap) { pa[m] = a; pb[m] = cand[t]; }
+            ++m;
+        }
+    }
+    free(cell); free(start); free(items); free(cand); free(cc);
+    return m;
+}
+
 /* SNSD of one pair at a configuration (x, q). */
 static void pair_snsd(int a, int b, const double *x, const double *q, const int *kind, const double *shape,
                       const double box[3], int planar, double out[10]) {
@@ -620,9 +742,12 @@ static void pair_snsd(int a, int b, const double *x, const double *q, const int 
     }
 }
 
-/* SNSD of a list of pairs (used by the tests and by the per-pair checks). */
+/* SNSD of a list of pairs (used by the tests and by the step).  Pairs are
+ * independent, so they are shared among OpenMP threads; every pair's
+ * arithmetic is the same whatever the thread count. */
 void orc_snsd_pairs(int m, const int *pa, const int *pb, const double *x, const double *q, const int *kind,
                     const double *shape, const double box[3], int planar, double *out /* 10*m */) {
+#pragma omp parallel for schedule(dynamic, 64)
     for (int k = 0; k < m; ++k) pair_snsd(pa[k], pb[k], x, q, kind, shape, box, planar, out + 10 * k);
 }
 
@@ -1050,7 +1175,7 @@ int orc_relcp_step(int n, const double *x, const double *q, const double *u, con
     int m = 0, rcap = 0;
     double *gam = NULL, *gprev = NULL, *phitil = NULL, *qv = NULL, *dA = NULL, *Ag = NULL;
     int *pa = NULL, *pb = NULL;
-    double *snsd = NULL;
+    double *snsd = NULL, *snsdt = NULL;
 
     /* K, U_free (Sec. 2.1.2) */
     for (int b = 0; b < n; ++b) {
@@ -1071,13 +1196,16 @@ int orc_relcp_step(int n, const double *x, const double *q, const double *u, con
     }
 
     /* candidate pairs and SNSD at C^k (Alg. 1 initialisation) */
-    int64_t np = orc_broadphase(n, x, kind, shape, box, P->skin, 0, NULL, NULL);
+    int64_t (*search)(int, const double *, const int *, const double *, const double *, double, int64_t, int *,
+                      int *) = n >= ORC_CELLS_FROM ? orc_broadphase_cells : orc_broadphase;
+    int64_t np = search(n, x, kind, shape, box, P->skin, 0, NULL, NULL);
     pa = malloc(sizeof(int) * (size_t)(np + 1));
     pb = malloc(sizeof(int) * (size_t)(np + 1));
-    orc_broadphase(n, x, kind, shape, box, P->skin, np, pa, pb);
+    search(n, x, kind, shape, box, P->skin, np, pa, pb);
     st->n_pairs = (int)np;
     snsd = malloc(sizeof(double) * 10 * (size_t)(np + 1));
-    for (int64_t k = 0; k < np; ++k) pair_snsd(pa[k], pb[k], x, q, kind, shape, box, P->planar, snsd + 10 * k);
+    snsdt = malloc(sizeof(double) * 10 * (size_t)(np + 1));
+    orc_snsd_pairs((int)np, pa, pb, x, q, kind, shape, box, P->planar, snsd);
 
     /* A_0: one row per near-contacting pair, Phi_0 <= skin */
     for (int64_t k = 0; k < np; ++k) {
@@ -1180,9 +1308,9 @@ int orc_relcp_step(int n, const double *x, const double *q, const double *u, con
         double minphi = INFINITY, margin = INFINITY;
         int nv = 0;
         int mold = m;
+        orc_snsd_pairs((int)np, pa, pb, xt, qt, kind, shape, box, P->planar, snsdt);
         for (int64_t k = 0; k < np; ++k) {
-            double s[10];
-            pair_snsd(pa[k], pb[k], xt, qt, kind, shape, box, P->planar, s);
+            const double *s = snsdt + 10 * k;
             if (s[0] < minphi) minphi = s[0];
             double mg = fabs(s[0] + P->eps);
             if (mg < margin) margin = mg;
@@ -1255,8 +1383,15 @@ done:
     st->status = status;
     free(kt); free(Kr); free(Ufree); free(work); free(Vn); free(xt); free(qt); free(Rb);
     free(rows); free(gam); free(gprev); free(phitil); free(qv); free(dA); free(Ag);
-    free(pa); free(pb); free(snsd);
+    free(pa); free(pb); free(snsd); free(snsdt);
     return status;
+}
+
+/* OpenMP threads for the per-pair loops (n > 0 sets them); returns the
+ * number in use. */
+int orc_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }
 
 /* The body operator K for external callers (tests): kt 3n, Kr 9n. */

@@ -267,6 +267,10 @@ struct relcp_ctx {
     // iteration passes over at least this many blocks reduce the last pass's
     // partial sums in a separate one-block launch (RELCP_REDUCE_SPLIT_BLOCKS)
     int reduce_split_blocks = env_int("RELCP_REDUCE_SPLIT_BLOCKS", 1024);
+    // first estimate of row-graph entry slots per row (RELCP_RG_SLOTS_PER_ROW);
+    // an assembly that does not fit is re-sized and its solve restarted
+    int rg_slots_per_row = env_int("RELCP_RG_SLOTS_PER_ROW", 16);
+    int rg_restarts = 0;  // of the current step
     DBuf<LcpDev<double>> lcpdev64;
     DBuf<LcpDev<float>> lcpdev32;
     hipGraphExec_t spmv_graph[2] = {nullptr, nullptr};
@@ -945,7 +949,7 @@ void relcp_ctx::rg_prepare() {
 void relcp_ctx::build_rowgraph(double dt) {
     const int ns = rowgraph_slices(m);
     rg_prepare();
-    rg_reserve(std::max<size_t>((size_t)RELCP_WAVE * ns * 16, 64));
+    rg_reserve(std::max<size_t>((size_t)RELCP_WAVE * ns * rg_slots_per_row, 64));
     int_h[4] = int_h[5] = int_h[6] = 0;  // slots / 64, entries, overflow (written by the fill)
     if (!rg_pre) {
         // widths not made by the incidence build (a rebuild)
@@ -1209,6 +1213,7 @@ bool relcp_ctx::rg_overflowed() {
     if (!int_h[6] && (size_t)RELCP_WAVE * int_h[4] <= rg_cap) return false;
     rg_reserve(2 * (size_t)RELCP_WAVE * int_h[4]);
     rg_valid = false;
+    ++rg_restarts;
     return true;
 }
 
@@ -1369,6 +1374,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     const int N = n;
     n_waits = 0;
     t_wait = 0.0;
+    rg_restarts = 0;
     pass_ev.clear();
 
     // set-up at C^k: geometry, K, U_free
@@ -1624,6 +1630,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     S.t_other = t_other;
     S.n_waits = n_waits;
     S.t_wait = t_wait;
+    S.rowgraph_restarts = rg_restarts;
     if (st) *st = S;
     return status;
 }

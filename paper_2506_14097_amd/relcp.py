@@ -60,7 +60,7 @@ class StepStats(C.Structure):
                 ("residual_lowp", C.c_double), ("max_overlap", C.c_double), ("max_disp", C.c_double),
                 ("t_narrow", C.c_double), ("t_lcp", C.c_double), ("t_other", C.c_double),
                 ("rowgraph_entries", C.c_int32 * MAX_RECORDED), ("pairs_rebuilt", C.c_int32),
-                ("n_waits", C.c_int32), ("t_wait", C.c_double)]
+                ("n_waits", C.c_int32), ("t_wait", C.c_double), ("rowgraph_restarts", C.c_int32)]
 
     def as_dict(self):
         R = self.recursions
@@ -72,7 +72,8 @@ class StepStats(C.Structure):
                     residual_fp64=self.residual_fp64, residual_lowp=self.residual_lowp,
                     max_overlap=self.max_overlap, max_disp=self.max_disp, t_narrow=self.t_narrow, t_lcp=self.t_lcp,
                     t_other=self.t_other, rowgraph_entries=np.array(self.rowgraph_entries[:k]),
-                    pairs_rebuilt=self.pairs_rebuilt, n_waits=self.n_waits, t_wait=self.t_wait)
+                    pairs_rebuilt=self.pairs_rebuilt, n_waits=self.n_waits, t_wait=self.t_wait,
+                    rowgraph_restarts=self.rowgraph_restarts)
 
 
 _lib = None
