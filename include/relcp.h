@@ -325,6 +325,20 @@ RELCP_API int relcp_lcp_solve_device(int32_t nb, int32_t m, const int32_t *ia, c
  * for n < 0 or missing arrays. */
 RELCP_API int relcp_exclusive_scan_device(const int32_t *in, int32_t *out, int32_t n, int32_t *total,
                                           void *stream);
+/* The same prefix sum for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, hosts that forbid
+ * hipMalloc): no allocation and no host wait.  Scratch (one int per tile of
+ * 2048 items) lives in a file-scope device array of RELCP_NOALLOC_SCAN_MAX /
+ * 2048 ints (16 KiB) per GPU, held until the process ends; its address is
+ * looked up on a device's first call.  n up to RELCP_NOALLOC_SCAN_MAX
+ * (RELCP_E_CAPACITY above it, nothing launched), RELCP_E_INVALID for n < 0
+ * or missing arrays.  Asynchronous: the kernels are ordered on stream and
+ * the call returns after launching them.  Every call on a GPU shares that
+ * GPU's array, so calls that overlap on one GPU (other streams, other host
+ * threads) race; calls ordered on one stream do not. */
+#define RELCP_NOALLOC_SCAN_MAX 8388608
+RELCP_API int relcp_exclusive_scan_device_noalloc(const int32_t *in, int32_t *out, int32_t n, int32_t *total,
+                                                  void *stream);
 /* Stream compaction: out[j] = index of the j-th nonzero flag among the n
  * device ints flags (increasing order), *count (a device int, or NULL) = the
  * number of them.  The step selects the pairs of A_0 (Phi_0 <= delta_c) and

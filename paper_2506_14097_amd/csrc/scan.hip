@@ -11,6 +11,9 @@
 // change the result.
 #include "common.h"
 #include "report.h"
+#include "../../include/relcp.h"
+
+#include <mutex>
 
 namespace relcp {
 
@@ -210,6 +213,40 @@ void exclusive_scan(const int *in, int *out, int n, int *total_dev, DBuf<int> &s
     scan_into(in, out, n, total_dev, scratch.p, s);
 }
 
+// ---------------------------------------------------------------------------
+// the scan without allocation: tile totals in a file-scope device array
+// ---------------------------------------------------------------------------
+// Scratch of relcp_exclusive_scan_device_noalloc: one int per tile of a scan
+// of up to RELCP_NOALLOC_SCAN_MAX items (kDirect tiles: the totals are summed
+// by each block, never scanned themselves, so no further scratch).  Each GPU
+// holds its own copy until the process ends.
+constexpr int kNoAllocTiles = kDirect;
+static_assert((long long)kNoAllocTiles * kTile == RELCP_NOALLOC_SCAN_MAX, "scratch bound");
+static __device__ __align__(256) int scratch[kNoAllocTiles];
+
+namespace {
+__global__ void k_set_zero(int *p) { *p = 0; }
+
+// The array's device address on the current device, looked up once per
+// device (host code must never pass the array's own name to a kernel).
+constexpr int kMaxDevices = 64;
+int *g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+int scratch_ptr(int **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return RELCP_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return RELCP_E_DEVICE;
+        g_scratch_ptr[dev] = static_cast<int *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return RELCP_OK;
+}
+}  // namespace
+
 bool compact_flags(const int *flags, int n, const int *bcount, int *out, int *total_dev, DBuf<int> &scratch,
                    hipStream_t s, const TailReport *rep) {
     if (n <= 0) {
@@ -242,3 +279,21 @@ bool compact_flags(const int *flags, int n, const int *bcount, int *out, int *to
 }
 
 }  // namespace relcp
+
+extern "C" int relcp_exclusive_scan_device_noalloc(const int32_t *in, int32_t *out, int32_t n, int32_t *total,
+                                                   void *stream) {
+    using namespace relcp;
+    if (n < 0 || (n > 0 && (!in || !out))) return RELCP_E_INVALID;
+    if (n > RELCP_NOALLOC_SCAN_MAX) return RELCP_E_CAPACITY;
+    hipStream_t s = (hipStream_t)stream;
+    int *tiles = nullptr;
+    const int rc = scratch_ptr(&tiles);
+    if (rc != RELCP_OK) return rc;
+    if (n == 0) {
+        if (total) hipLaunchKernelGGL(k_set_zero, dim3(1), dim3(1), 0, s, total);
+    } else {
+        // at most kDirect tiles: scan_into uses `tiles` for their totals only
+        scan_into(in, out, n, total, tiles, s);
+    }
+    return hipGetLastError() == hipSuccess ? RELCP_OK : RELCP_E_DEVICE;
+}

@@ -112,6 +112,7 @@ _SIGS = {
                                          C.c_int32, C.c_double, C.c_int32, C.c_void_p, C.POINTER(C.c_int32),
                                          C.POINTER(C.c_double), C.c_void_p]),
     "relcp_exclusive_scan_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "relcp_exclusive_scan_device_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "relcp_compact_flags_device": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
@@ -443,6 +444,16 @@ def exclusive_scan_device(x, out=None, stream=None):
     if rc != OK:
         raise RelcpError(rc, "exclusive scan failed")
     return out, int(tot.item())
+
+
+NOALLOC_SCAN_MAX = 8388608
+
+
+def exclusive_scan_device_noalloc(x, out, total, stream=None):
+    """The same prefix sum through the entry point that allocates nothing
+    (scratch in the library's static device array; asynchronous on the
+    stream).  Returns the status."""
+    return lib().relcp_exclusive_scan_device_noalloc(_tptr(x), _tptr(out), x.numel(), _tptr(total), stream)
 
 
 def compact_flags_device(flags, stream=None):
