@@ -9,17 +9,26 @@ then compresses the box isotropically by dphi = 5e-5 and takes one overdamped
 ReLCP step (dt = 5e-3, overlap_tol = 1e-3, lcp_tol = 1e-6, previous-step
 warm start, FP32 products with FP64 residual and acceptance by default).
 
-Prints one JSON line with steps/s, the roofline of the dominant kernel
-(measured with HIP events inside the library on its own stream), the
-learned warm start against the previous-step one on the same workload
-(projected-gradient iterations and time per step; the model is trained on
-the GPU first, untimed) and the CPU oracle timed on a bounded sample.
+Prints one JSON line with steps/s over the timed steps and, beside it:
+ * roofline: the FP32 LCP iteration pass (the dominant kernel) by the
+   method's bytes per iteration, its duration measured with HIP events
+   inside the library on its own stream;
+ * narrowphase: the SNSD pass's launch time and FP64 issue rate;
+ * error_vs_oracle and cpu_baseline: the CPU oracle (FP64, OpenMP) timed on
+   one step of the benchmark's own state, and the GPU's FP32 and FP64 steps
+   from that state against the oracle's;
+ * learned_warm_start: the learned start against the previous-step one at
+   volume fractions 0.40, 0.50 and 0.60 (the model is trained on the GPU
+   first, untimed);
+ * workloads: the FP64 path at 100k, the whole compression 0.40 -> 0.60
+   (4,000 steps) in windows, the 10,000-ellipsoid compaction 0.30 -> 0.55 in
+   both precisions, 512 packings in one context, and the growing colony at
+   4,096 cells (--workload colony: also 65,536 and 131,072).
 
-Other workloads (--workload): packings512 (512 independent packings in one
-context), lcp-sweep (the LCP pass across sizes), two-ellipsoids (the
-timestep refinement of Sec. 5.1) and chainmail (interlaced rings under the
-extensile field of Sec. 6, ReLCP against LCP-SNSD); each prints its own
-JSON line.
+Other workloads (--workload): packings512, colony, lcp-sweep (the LCP pass
+across sizes), two-ellipsoids (the timestep refinement of Sec. 5.1) and
+chainmail (interlaced rings under the extensile field of Sec. 6, ReLCP
+against LCP-SNSD); each prints its own JSON line.
 """
 from __future__ import annotations
 
@@ -51,6 +60,19 @@ KERNEL_SYMBOLS = {"lcp_rowgraph": "relcp::k_spmv<float, 1>", "lcp_rowgraph64": "
                   "lcp_scatter": "relcp::k_scatter<T, 1>"}
 
 
+# FP64 VALU instructions of the narrowphase per candidate pair at this
+# workload (rocprofv3 --pmc SQ_INSTS_VALU_ADD_F64, _MUL_F64, _FMA_F64,
+# _TRANS_F64: add + mul + 2 fma + trans, times 64 lanes, over the pairs of
+# the launch), for the kernel source with the given sha256 prefix.
+SNSD_FP64_OPS = {"sha256_prefix": None, "fp64_ops_per_pair": None, "source": None}
+
+
+def geometry_source_sha():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2506_14097_amd", "csrc", "geometry.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
 def kernel_source_sha():
     import hashlib
     with open(os.path.join(ROOT, "paper_2506_14097_amd", "csrc", "lcp.hip"), "rb") as f:
@@ -72,6 +94,18 @@ def lcp_bytes(kind, m, nb, w):
     if kind == "lcp_gather":
         return m * (8 + 15 * w) + nb * 6 * w
     return m * (8 + 12 * w) + nb * (4 + 15 * w)
+
+
+def method_bytes(m, nb, w):
+    """Algorithmic bytes of one projected-gradient iteration of the method
+    over m constraint rows and nb bodies, word size w (the matrix-free
+    iteration on D^T K D): per row, the row's Jacobian (n, r_a x n, r_b x n)
+    read twice (scatter and gather, 18w), its two body indices twice (16 B),
+    gamma read and written, g, the constant qv, the previous gamma and g
+    (8w): 26w + 16 B (120 B in FP32, 224 B in FP64); per body, K (9w) and
+    the velocity written and read back (6w each) less one word: 14w (56 B in
+    FP32, 112 B in FP64)."""
+    return m * (26 * w + 16) + nb * 14 * w
 
 
 def rowgraph_bytes(m, e, w, iters):
@@ -122,7 +156,7 @@ def learned_comparison(args, state):
            "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1], "levels": {}}
     B = Compaction(None, None, None, state=state, dt=args.dt, eps=args.eps, tol=args.tol, precision=args.precision,
                    skin=args.skin)
-    for level in (0.40, 0.60):
+    for level in (0.40, 0.50, 0.60):
         B.compress_to(max(level, B.phi))
         st0 = B.state()
         res = {"volume_fraction": B.phi}
@@ -316,12 +350,13 @@ def chainmail_study(args):
                       "runs": runs}), flush=True)
 
 
-def packings_workload(args):
+def packings_workload(args, steps=None, warmup=None):
     """Batched workload: 512 independent periodic packings (body counts
     log-uniform in [200, 5000], target volume fractions uniform in [0.3,
     0.5]) in one context; set-up compresses each packing to its own target,
     then every timed step compresses each packing by dphi and steps all of
-    them together (resident LCP: one workgroup per packing, one launch)."""
+    them together, in the LCP configuration the autotuner picks.  Returns
+    the result record."""
     import torch
     from paper_2506_14097_amd import inputs as I
     from paper_2506_14097_amd import relcp as R
@@ -366,23 +401,28 @@ def packings_workload(args):
             if stats is not None:
                 stats.append(r)
 
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     advance(1)
     tune = sim.autotune(args.dt, args.tol, reps=2)
     log("autotuned LCP configuration: %s" % tune)
-    advance(args.warmup)
+    advance(warmup)
     stats = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    advance(args.steps, stats)
+    advance(steps, stats)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     sim.set_timing(True)
     sim.get_timing(reset=True)
     advance(args.roofline_steps)
     tm = sim.get_timing(reset=True)
+    rg = [(m, it - i64, e) for r in stats for m, it, i64, e in zip(r["n_contacts"], r["lcp_iters"], r["lcp_iters64"],
+                                                                     r["rowgraph_entries"])]
     out = {"metric": "packing-steps/s, %d independent periodic ellipsoid packings in one context" % npk,
-           "value": npk * args.steps / el, "unit": "packing-steps/s", "steps": args.steps,
-           "ms_per_step": 1e3 * el / args.steps, "bodies": int(off[-1]), "packings": npk,
+           "value": npk * steps / el, "unit": "packing-steps/s", "steps": steps,
+           "ms_per_step": 1e3 * el / steps, "bodies": int(off[-1]), "packings": npk,
+           "lcp_pass_hbm_frac": lcp_pass_frac(tm, rg, int(off[-1]), args.precision),
            "dtype": "f32+f64" if args.precision == 32 else "f64",
            "pgd_iters_per_step_max_over_packings": float(np.mean([r["lcp_iters_total"] for r in stats])),
            "contacts_final": int(stats[-1]["n_contacts_final"]),
@@ -390,36 +430,231 @@ def packings_workload(args):
            "max_overlap": float(max(r["max_overlap"] for r in stats)), "autotune": tune,
            "kernel_ms": {k2: round(v[1], 3) for k2, v in tm.items()},
            "kernel_launches": {k2: v[0] for k2, v in tm.items()}}
-    print(json.dumps(out), flush=True)
+    sim.close()
+    return out
 
 
-def cpu_baseline(args, bench_pairs, bench_rec):
-    """The CPU oracle (FP64, single thread) on a bounded sample of the same
-    workload: one step of a periodic packing from the same generator.  The
-    oracle's step is an all-pairs candidate search (quadratic in N) plus
-    per-pair SNSD at C^k and at every trial; the two parts are timed
-    separately and scaled to the benchmark's body count (quadratically) and
-    candidate-pair x SNSD-pass count (linearly)."""
+def lcp_pass_frac(tm, rows, nb, precision):
+    """Fraction of HBM peak of the FP32 (or FP64) iterating row-graph
+    passes by the method's bytes per iteration (method_bytes): rows is a
+    list of (rows, low-precision iterations, entries) per solve."""
+    cls = "lcp_rowgraph" if precision == 32 else "lcp_rowgraph64"
+    cnt, ms = tm.get(cls, (0, 0.0))
+    if not cnt or ms <= 0:
+        return None
+    w = 4 if precision == 32 else 8
+    tot = sum(k * method_bytes(m, nb, w) for m, k, _ in rows)
+    return tot / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_threads():
+    """Threads for the oracle's per-pair loops: the host's CPUs, at most 16
+    (the CPU share of one GPU on the benchmark machines)."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def host_state(st, s):
+    """A state of a Compaction after one more affine rescale by s (the input
+    of the next step)."""
+    return dict(st, x=st["x"] * s, box=st["box"] * s)
+
+
+def contact_sets_match(c, ref):
+    """Per recursion, the GPU's rows against the oracle's: 'identical', or
+    where they first differ; pairs within 1e-9 of the overlap threshold
+    (flagged) stop the comparison."""
+    band = np.where(ref["margin"] < 1e-9)[0]
+    upto = band[0] if band.size else ref["recursions"]
+    for r in range(upto + 1):
+        g = sorted(zip(c["ia"][c["rec"] == r].tolist(), c["ib"][c["rec"] == r].tolist()))
+        o = sorted(zip(ref["ia"][ref["rec"] == r].tolist(), ref["ib"][ref["rec"] == r].tolist()))
+        if g != o:
+            return "differ at recursion %d" % r
+    return "identical" + (" up to the flagged recursion %d" % upto if band.size else "")
+
+
+def gpu_step_error(args, S, precision, lcp_tol, ref):
+    """One GPU step from host state S in a fresh context (zero start) at the
+    given precision and LCP tolerance, against the oracle's step ref from the
+    same state: contact sets per recursion, velocities (relative to the
+    largest), positions and orientations."""
+    from paper_2506_14097_amd import relcp as R
+    sim = R.Simulation(S["x"], S["q"], S["kind"], S["shape"], S["rho_xi"], S["box"], precision=precision,
+                       skin=args.skin, warm_start=R.WS_COLD)
+    res = sim.step(args.dt, args.eps, lcp_tol)
+    x, q, U = sim.get_state()
+    c = sim.get_contacts(res["n_contacts_final"])
+    sim.close()
+    sets = contact_sets_match(c, ref)
+    out = {"precision": precision, "lcp_tol": lcp_tol, "contact_sets": sets,
+           "recursions": [int(res["recursions"]), int(ref["recursions"])],
+           "rows": [int(res["n_contacts_final"]), int(ref["n_rows"])],
+           "U_rel": float(np.abs(U - ref["U"]).max() / max(np.abs(ref["U"]).max(), 1e-300)),
+           "x_abs": float(np.abs(x - ref["x"]).max()), "q_abs": float(np.abs(q - ref["q"]).max()),
+           "residual_fp64": float(res["residual_fp64"])}
+    log("error against the oracle: %s" % out)
+    return out
+
+
+def cpu_baseline(args, S):
+    """The CPU oracle (FP64, OpenMP over pairs) timed on the benchmark's own
+    state: one step at the benchmark's parameters (lcp_tol as benchmarked,
+    zero start), with the candidate search and the SNSD at C^k also timed on
+    their own.  Then the oracle's step at lcp_tol 1e-12 from the same state,
+    against which the GPU's FP32 step (at the benchmark's tolerance) and FP64
+    step (at 1e-12) are compared.  No extrapolation: the figure is the
+    oracle's time for a step of this workload."""
     import oracle as O
-    from paper_2506_14097_amd import inputs as I
-    n = args.cpu_n
-    P = I.ellipsoid_packing(args.seed + 1, n, sphere_phi=0.3, compress=0.99)
+    th = O.threads(oracle_threads())
+    kw = dict(dt=args.dt, eps=args.eps, skin=args.skin, lcp_mode=1)
     t0 = time.time()
-    O.broadphase(P["x"], P["kind"], P["shape"], P["box"], args.skin)
-    t_bp = time.time() - t0
+    pa, pb = O.broadphase(S["x"], S["kind"], S["shape"], S["box"], args.skin, cells=True)
+    t_search = time.time() - t0
     t0 = time.time()
-    r = O.relcp_step(P["x"], P["q"], P["kind"], P["shape"], P["rho_xi"], P["box"], dt=args.dt, eps=args.eps,
-                     tol=args.tol, skin=args.skin, lcp_mode=1)
-    t = time.time() - t0
-    work_sample = r["n_pairs"] * (1 + r["recursions"])
-    work_bench = bench_pairs * (1 + bench_rec)
-    t_est = t_bp * (args.n / n) ** 2 + max(t - t_bp, 0.0) * work_bench / max(work_sample, 1)
-    return {"value": 1.0 / t_est, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": "one FP64 oracle step (single thread, %.1fs, of which %.1fs all-pairs candidate search) of a "
-                      "%d-ellipsoid periodic packing at phi %.3f (%d candidate pairs x %d SNSD passes, %d rows); "
-                      "scaled to %d bodies (search, quadratic) and %d pairs x %.2f passes per step (rest, linear)"
-                      % (t, t_bp, n, P["phi"], r["n_pairs"], 1 + r["recursions"], r["n_rows"], args.n, bench_pairs,
-                         1 + bench_rec)}
+    O.snsd_pairs(pa, pb, S["x"], S["q"], S["kind"], S["shape"], S["box"])
+    t_snsd = time.time() - t0
+    t0 = time.time()
+    r = O.relcp_step(S["x"], S["q"], S["kind"], S["shape"], S["rho_xi"], S["box"], tol=args.tol, **kw)
+    t_step = time.time() - t0
+    log("oracle step (%d threads): %.2fs (search %.2fs, SNSD at C^k %.2fs), %d rows, %d recursions" %
+        (th, t_step, t_search, t_snsd, r["n_rows"], r["recursions"]))
+    ref = O.relcp_step(S["x"], S["q"], S["kind"], S["shape"], S["rho_xi"], S["box"], tol=1e-12, **kw)
+    errors = {"fp32_at_lcp_tol_%g" % args.tol: gpu_step_error(args, S, 32, args.tol, ref),
+              "fp64_at_lcp_tol_1e-12": gpu_step_error(args, S, 64, 1e-12, ref)}
+    cpu = {"value": 1.0 / t_step, "unit": "steps/s", "cores": th, "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": "one FP64 oracle step (lcp_tol %g, zero start, %d OpenMP threads) on the benchmark's own "
+                     "%d-body state at phi %.4f: %.2f s, of which candidate search (cell grid) %.2f s, SNSD of "
+                     "the %d candidate pairs at C^k %.2f s, LCP (%d PGD iterations, %d rows) and trial checks the "
+                     "rest; %d recursions" % (args.tol, th, len(S["x"]), S["phi"], t_step, t_search, pa.size, t_snsd,
+                                               int(sum(r["lcp_iters"])), r["n_rows"], r["recursions"]),
+           "seconds": {"step": t_step, "candidate_search": t_search, "snsd_at_Ck": t_snsd}}
+    return cpu, errors
+
+
+def compaction_range(args, C, phi_end=0.60, windows=10):
+    """The whole compression from the current volume fraction (~0.40) to
+    phi_end at dphi per step (4,000 steps from 0.40), timed per window:
+    steps/s, PGD iterations, recursions and rows per step."""
+    import torch
+    n_total = int(round((phi_end - C.phi) / args.dphi))
+    per = max(1, n_total // windows)
+    out, tot_t, tot_n, rec = [], 0.0, 0, 0
+    done = 0
+    while done < n_total:
+        k = min(per, n_total - done)
+        phi_a = C.phi
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = C.steps(k, args.dphi)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        done += k
+        tot_t += el
+        tot_n += k
+        rec += sum(s["recursions"] for s in st)
+        w = {"phi": [round(phi_a, 5), round(C.phi, 5)], "steps": k, "steps_per_s": k / el,
+             "pgd_iters_per_step": float(np.mean([s["lcp_iters_total"] for s in st])),
+             "recursions_per_step": float(np.mean([s["recursions"] for s in st])),
+             "rows": int(st[-1]["n_contacts_final"]), "max_overlap": float(max(s["max_overlap"] for s in st)),
+             "residual_fp64_max": float(max(s["residual_fp64"] for s in st))}
+        log("range: %s" % w)
+        out.append(w)
+    return {"steps": tot_n, "steps_per_s": tot_n / tot_t, "recursions_per_step": rec / max(tot_n, 1),
+            "windows": out}
+
+
+def c1_workload(args, precision):
+    """The 10,000-ellipsoid compaction: bounding-sphere placement compressed
+    (set-up) to volume fraction 0.30, then compressed to 0.55 over 5,000
+    timed steps (dphi 5e-5, dt 5e-3, overlap_tol 1e-3, lcp_tol 1e-6)."""
+    import torch
+    from paper_2506_14097_amd.compaction import Compaction
+    C = Compaction(1, 10000, 0.30, dt=args.dt, eps=args.eps, tol=args.tol, precision=precision, skin=args.skin)
+    n = int(round((0.55 - C.phi) / args.dphi))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = C.steps(n, args.dphi)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = {"bodies": 10000, "precision": precision, "phi": [0.30, round(C.phi, 5)], "steps": n,
+           "steps_per_s": n / el, "pgd_iters_per_step": float(np.mean([s["lcp_iters_total"] for s in st])),
+           "recursions_per_step": float(np.mean([s["recursions"] for s in st])),
+           "rows_final": int(st[-1]["n_contacts_final"]), "max_overlap": float(max(s["max_overlap"] for s in st)),
+           "residual_fp64_max": float(max(s["residual_fp64"] for s in st))}
+    C.sim.close()
+    log("10k compaction: %s" % out)
+    return out
+
+
+def colony_workload(args, sizes=(4096, 65536, 131072)):
+    """The growing colony (Sec. 5.3) in a monolayer: one spherocylinder
+    (diameter 1, total length 1) growing linearly at 0.01 per unit time,
+    every cell dividing at total length 2 into its two halves (jitter
+    N(0, 0.01^2) rad), dt 1e-2, overlap_tol 1e-3, lcp_tol 1e-6, skin 0.2.
+    The set-up grows the colony to each size ten times faster in a context
+    with skin 1.0 (untimed; the rate is halved whenever the rim would still
+    move more than skin / 2 in a step).  At each size the state moves to a
+    context with the benchmark's skin, takes 5 untimed steps, and a window
+    of --colony-steps steps at the benchmarked rate is timed, just after the
+    division that reached the size."""
+    import torch
+    from paper_2506_14097_amd.colony import Colony
+    col = Colony(seed=2, rate=0.01, dt=1e-2, eps=args.eps, tol=args.tol, precision=args.precision, skin=1.0)
+    out = []
+    t0 = time.time()
+    for N in sizes:
+        col.grow_to(N, rate=0.1, log=log)
+        col.reskin(0.2)
+        for _ in range(5):
+            col.step()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = [col.step() for _ in range(args.colony_steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        w = {"cells": int(col.n), "steps": args.colony_steps, "steps_per_s": args.colony_steps / el,
+             "cell_length": round(col.l + 2 * col.r, 4), "rows": int(st[-1]["n_contacts_final"]),
+             "pgd_iters_per_step": float(np.mean([s_["lcp_iters_total"] for s_ in st])),
+             "recursions_per_step": float(np.mean([s_["recursions"] for s_ in st])),
+             "max_overlap": float(max(s_["max_overlap"] for s_ in st))}
+        log("colony: %s (%.1fs)" % (w, time.time() - t0))
+        out.append(w)
+        col.reskin(1.0)
+    col.sim.close()
+    return out
+
+
+def fp64_line(args, state, steps):
+    """The benchmark's steps in the FP64 path (FP64 iterations throughout)
+    from the same state: steps/s and PGD iterations."""
+    import torch
+    from paper_2506_14097_amd.compaction import Compaction
+    D = Compaction(None, None, None, state=state, dt=args.dt, eps=args.eps, tol=args.tol, precision=64,
+                   skin=args.skin)
+    D.steps(args.warmup, args.dphi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = D.steps(steps, args.dphi)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    D.sim.close()
+    out = {"steps": steps, "steps_per_s": steps / el, "pgd_iters_per_step": float(np.mean([s["lcp_iters_total"]
+                                                                                        for s in st])),
+           "recursions_per_step": float(np.mean([s["recursions"] for s in st])),
+           "residual_fp64_max": float(max(s["residual_fp64"] for s in st))}
+    log("FP64 path: %s" % out)
+    return out
 
 
 def main():
@@ -440,12 +675,15 @@ def main():
                     help="LCP execution: 0 automatic, 1 grid, 2 resident, 3 row graph (graph-replayed passes), "
                          "4 row graph (one launch per pass)")
     ap.add_argument("--roofline-steps", type=int, default=5)
-    ap.add_argument("--cpu-n", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start comparison")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads (FP64 path, the 0.40 -> 0.60 range, 10k compaction, 512 packings)")
+    ap.add_argument("--packing-steps", type=int, default=200, help="timed steps of the 512-packing workload")
+    ap.add_argument("--colony-steps", type=int, default=200, help="timed steps per colony size")
     ap.add_argument("--learned-steps", type=int, default=50)
     ap.add_argument("--workload", default="compaction100k",
-                    choices=("compaction100k", "packings512", "lcp-sweep", "two-ellipsoids", "chainmail"))
+                    choices=("compaction100k", "packings512", "lcp-sweep", "two-ellipsoids", "chainmail", "colony"))
     ap.add_argument("--dts", default="0.1,0.01,0.001,0.0001", help="two-ellipsoids: the timesteps")
     ap.add_argument("--t-end", type=float, default=200.0, help="two-ellipsoids: end time (contact from t = 100)")
     ap.add_argument("--cm-n", type=int, default=5, help="chainmail: node rings per lattice side")
@@ -477,13 +715,18 @@ def main():
         log("copy probe: 5 copies of %d bytes" % (4 * nel))
         return
     if args.workload == "packings512":
-        packings_workload(args)
+        print(json.dumps(packings_workload(args)), flush=True)
         return
     if args.workload == "lcp-sweep":
         lcp_sweep(args)
         return
     if args.workload == "chainmail":
         chainmail_study(args)
+        return
+    if args.workload == "colony":
+        print(json.dumps({"metric": "colony steps/s at each size (Sec. 5.3 growth and division)", "unit": "steps/s",
+                          "data": "synthetic", "dtype": "f32+f64" if args.precision == 32 else "f64",
+                          "sizes": colony_workload(args)}), flush=True)
         return
     if args.workload == "two-ellipsoids":
         two_ellipsoid_study(args)
@@ -522,49 +765,76 @@ def main():
     tm = sim.get_timing(reset=True)
     sim.set_timing(False)
     nb = args.n
-    tot_bytes = {"lcp_gather": 0.0, "lcp_scatter": 0.0, "lcp_rowgraph": 0.0, "lcp_rowgraph64": 0.0,
-                 "lcp_rowgraph_start": 0.0}
-    busy = 0  # launches that did work (the rest return at once after convergence)
-    for s in rstats:
-        for m, it, it64, e in zip(s["n_contacts"], s["lcp_iters"], s["lcp_iters64"], s["rowgraph_entries"]):
-            itlo = it - it64
-            for cls in ("lcp_gather", "lcp_scatter"):
-                if args.precision == 32:
-                    tot_bytes[cls] += (itlo + 1) * lcp_bytes(cls, m, nb, 4) + (it64 + 1) * lcp_bytes(cls, m, nb, 8)
-                else:
-                    tot_bytes[cls] += (it + 1) * lcp_bytes(cls, m, nb, 8)
-            # row graph: iteration passes per precision, start passes apart
-            for w, k in (((4, itlo), (8, it64)) if args.precision == 32 else ((8, it),)):
-                start = rowgraph_bytes(m, e, w, 0)
-                tot_bytes["lcp_rowgraph" if w == 4 else "lcp_rowgraph64"] += rowgraph_bytes(m, e, w, k) - start
-                tot_bytes["lcp_rowgraph_start"] += start
-            busy += int(itlo if args.precision == 32 else it)
+    w_lo = 4 if args.precision == 32 else 8
+    cls = "lcp_rowgraph" if args.precision == 32 else "lcp_rowgraph64"
+    meth, rgm, busy = 0.0, 0.0, 0  # bytes of the iterating passes; launches that did work
+    for s_ in rstats:
+        for m, it, it64, e in zip(s_["n_contacts"], s_["lcp_iters"], s_["lcp_iters64"], s_["rowgraph_entries"]):
+            k = it - it64 if args.precision == 32 else it
+            meth += k * method_bytes(m, nb, w_lo)
+            rgm += rowgraph_bytes(m, e, w_lo, k) - rowgraph_bytes(m, e, w_lo, 0)
+            busy += int(k)
     dom = max(tm, key=lambda k: tm[k][1])
-    cnt, ms = tm[dom]
-    if dom in tot_bytes:
-        achieved = tot_bytes[dom] / (ms * 1e-3) / 1e9
-        traffic = None
-        if kernel_source_sha() == MEASURED_TRAFFIC["sha256_prefix"] and args.n == 100000 and args.precision == 32:
-            traffic = MEASURED_TRAFFIC.get(dom)
-        roof = {"kernel": dom, "kernel_symbol": KERNEL_SYMBOLS.get(dom), "bound": "hbm", "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "launches": int(cnt), "busy_launches": int(busy),
-                "avg_us": 1e3 * ms / max(cnt, 1), "bytes_per_launch": tot_bytes[dom] / max(cnt, 1)}
-    else:
-        roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": None, "traffic": None, "launches": cnt, "avg_us": 1e3 * ms / max(cnt, 1)}
+    cnt, ms = tm[cls]
+    avg_us = 1e3 * ms / max(cnt, 1)
+    achieved = meth / (ms * 1e-3) / 1e9
+    traffic = None
+    if kernel_source_sha() == MEASURED_TRAFFIC["sha256_prefix"] and args.n == 100000 and args.precision == 32:
+        traffic = MEASURED_TRAFFIC["lcp_rowgraph"]
+    roof = {"kernel": cls, "kernel_symbol": KERNEL_SYMBOLS.get(cls), "dominant_class": dom, "bound": "hbm",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "traffic_source": ("rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE of this kernel source (lcp.hip sha256 %s), "
+                               "scaled by a plain copy's counters; a profile figure, not measured in this run"
+                               % MEASURED_TRAFFIC["sha256_prefix"]) if traffic else None,
+            "bytes_model": "method: %d B per row-iteration + %d B per body (26w + 16 B, 14w)" % (26 * w_lo + 16,
+                                                                                             14 * w_lo),
+            "launches": int(cnt), "busy_launches": int(busy), "avg_us": avg_us,
+            "bytes_per_launch": meth / max(cnt, 1),
+            "rowgraph_model": {"bytes_per_launch": rgm / max(cnt, 1),
+                               "achieved": rgm / (ms * 1e-3) / 1e9, "frac": rgm / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                               "what": "bytes the row-graph pass itself must move: per stored entry its column "
+                                       "(4 B) and value (w), per row its state, g, qv and A_rr"}}
     roof["kernel_ms"] = {k: round(v[1], 3) for k, v in tm.items()}
     roof["kernel_launches"] = {k: v[0] for k, v in tm.items()}
+    # the narrowphase: FP64 issue rate from the instructions a counter run
+    # recorded per pair, over the launch durations measured here
+    sc, sms = tm.get("snsd", (0, 0.0))
+    pairs = float(np.mean([s_["n_pairs"] for s_ in rstats]))
+    narrow = {"kernel": "relcp::k_snsd_pairs<0>", "launches": int(sc), "avg_us": 1e3 * sms / max(sc, 1),
+              "pairs_per_launch": pairs, "bound": "fp64 alu", "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    if geometry_source_sha() == SNSD_FP64_OPS["sha256_prefix"] and sc:
+        ops = SNSD_FP64_OPS["fp64_ops_per_pair"] * pairs
+        narrow.update(achieved=ops / (sms / sc * 1e-3) / 1e12, fp64_ops_per_pair=SNSD_FP64_OPS["fp64_ops_per_pair"],
+                      source=SNSD_FP64_OPS["source"])
+        narrow["frac"] = narrow["achieved"] / FP64_PEAK_TFLOPS
 
     learned = None
     if not args.no_learned:
         learned = learned_comparison(args, start_state)
 
-    cpu = None
+    extras = {}
+    end_state = C.state()
+    cpu, errors = None, None
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(args, float(np.mean([s["n_pairs"] for s in stats])),
-                           float(np.mean([s["recursions"] for s in stats])))
+        log("timing the CPU oracle on the benchmark's state")
+        s = (C.phi / (C.phi + args.dphi)) ** (1.0 / 3.0)
+        S = host_state(end_state, s)
+        S["phi"] = C.phi + args.dphi
+        cpu, errors = cpu_baseline(args, S)
+    if not args.no_extras:
+        extras["fp64_path_100k"] = fp64_line(args, start_state, args.steps)
+        log("compressing the 100k packing from %.4f to 0.60" % C.phi)
+        extras["range_0.40_to_0.60"] = compaction_range(args, C)
+        for prec in (64, 32):
+            extras["compaction_10k_fp%d" % prec] = c1_workload(args, prec)
+        log("512 packings")
+        pk = packings_workload(args, steps=args.packing_steps, warmup=2)
+        log("colony")
+        extras["colony"] = colony_workload(args, sizes=(4096,))
+        extras["packings512"] = {k: pk[k] for k in ("value", "unit", "steps", "ms_per_step", "bodies", "packings",
+                                                    "lcp_pass_hbm_frac", "pgd_iters_per_step_max_over_packings",
+                                                    "contacts_final", "recursions_per_step", "autotune")}
 
     out = {
         "metric": "ReLCP steps/s @100k ellipsoids; PGD iters to 1e-6 residual (learned vs plain)",
@@ -573,20 +843,24 @@ def main():
         "vs_baseline": None, "dtype": "f32+f64" if args.precision == 32 else "f64", "data": "synthetic",
         "config": {"workload": "compaction of %d periodic ellipsoids (semiaxes U[0.5,1]), phi %.2f -> %.5f at "
                                "dphi %.0e/step, overdamped, dt %.0e, overlap_tol %.0e, lcp_tol %.0e, previous-step "
-                               "warm start" % (args.n, args.phi0, C.phi, args.dphi, args.dt, args.eps, args.tol),
+                               "warm start" % (args.n, args.phi0, args.phi0 + args.steps * args.dphi, args.dphi,
+                                               args.dt, args.eps, args.tol),
                    "bodies": args.n, "precision": args.precision, "skin": args.skin, "lcp_mode": args.lcp_mode},
         "pgd_iters_per_step": {"plain": float(np.mean(pgd)),
                                "learned": learned["levels"]["0.40"]["learned"]["pgd_iters_per_step"]
                                if learned else None},
+        "error_vs_oracle": errors,
         "learned_warm_start": learned,
         "contact_iters_per_s": citers / elapsed,
-        "host_waits_per_step": {"n": float(np.mean([s["n_waits"] for s in stats])),
-                                "ms": float(np.mean([s["t_wait"] for s in stats]))},
-        "recursions_per_step": float(np.mean([s["recursions"] for s in stats])),
+        "host_waits_per_step": {"n": float(np.mean([s_["n_waits"] for s_ in stats])),
+                                "ms": float(np.mean([s_["t_wait"] for s_ in stats]))},
+        "recursions_per_step": float(np.mean([s_["recursions"] for s_ in stats])),
         "contacts_final": int(stats[-1]["n_contacts_final"]),
-        "residual_fp64_max": float(max(s["residual_fp64"] for s in stats)),
-        "max_overlap": float(max(s["max_overlap"] for s in stats)),
+        "residual_fp64_max": float(max(s_["residual_fp64"] for s_ in stats)),
+        "max_overlap": float(max(s_["max_overlap"] for s_ in stats)),
         "roofline": roof,
+        "narrowphase": narrow,
+        "workloads": extras,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -138,7 +138,11 @@ typedef struct {
  * uploads the state once.  *out is set on success only. */
 RELCP_API int relcp_create(const relcp_bodies *bodies, const relcp_shapes *shapes, const relcp_params *params,
                  relcp_ctx **out);
+/* Release a context and all of its device buffers (not in the paper:
+ * resource handling).  NULL is ignored. */
 RELCP_API void relcp_destroy(relcp_ctx *ctx);
+/* Message of the last failed call on this context (not in the paper); the
+ * string is owned by the context and valid until its next call. */
 RELCP_API const char *relcp_last_error(const relcp_ctx *ctx);
 
 /* External wrench F_ext (6n host doubles: force then torque per body, world
@@ -150,30 +154,70 @@ RELCP_API int relcp_set_external(relcp_ctx *ctx, const double *f);
  * tolerance lcp_tol on the scaled natural residual.  stats may be NULL. */
 RELCP_API int relcp_step(relcp_ctx *ctx, double dt, double overlap_tol, double lcp_tol, relcp_step_stats *stats);
 
-/* State read-back into caller buffers (x 3n, q 4n, u 3n, w 3n; any may be
- * NULL).  u, w are the last accepted velocity V_n = U_free + K D gamma. */
+/* State read-back (Alg. 1 output C^{k+1}; inertial runs also U^{k+1}, Eq.
+ * relcp_inertial) into caller buffers in the caller's body order (x 3n,
+ * q 4n, u 3n, w 3n; any may be NULL).  u, w are the last accepted velocity
+ * V_n = U_free + K D gamma.  relcp_get_state takes host buffers and waits;
+ * relcp_get_state_device takes device buffers, is ordered on the context's
+ * stream and waits for it.  RELCP_E_INVALID for a NULL context. */
 RELCP_API int relcp_get_state(const relcp_ctx *ctx, double *x, double *q, double *u, double *w);
 RELCP_API int relcp_get_state_device(const relcp_ctx *ctx, double *x, double *q, double *u, double *w);
 
-/* Replace the state (same n, n_batch and shapes as at create, or new body
- * counts: the context is then re-sized).  Clears the warm-start history. */
+/* Replace the state C^k (Alg. 1 input; inertial runs also U^k) with the
+ * same layout as relcp_create: the same or new body counts (the context is
+ * re-sized), shapes and drag or density included.  Validated as at create
+ * (RELCP_E_INVALID leaves the old state); clears the warm-start history and
+ * the external wrenches.  Used to inject a state (parity checks) and by
+ * the colony's division. */
 RELCP_API int relcp_set_state(relcp_ctx *ctx, const relcp_bodies *bodies, const relcp_shapes *shapes);
 
-/* Isotropic affine compression x <- s x, box <- s box (all packings). */
+/* Isotropic affine compression x <- s x, box <- s box of all packings, the
+ * compression of the compacting suspension between steps (Sec. 5.2).
+ * RELCP_E_INVALID for s <= 0 or a box that would become smaller than
+ * 2 (R_max + skin).  Ordered on the stream (no wait). */
 RELCP_API int relcp_affine_rescale(relcp_ctx *ctx, double s);
-/* The same with one factor per packing (host array of n_batch values). */
+/* The same with one factor per packing (host array of n_batch values;
+ * waits for the stream). */
 RELCP_API int relcp_affine_rescale_packings(relcp_ctx *ctx, const double *s);
 
-/* Rows of the last accepted step (caller buffers of n_contacts_final
- * entries; any may be NULL): body pair (caller's indices, ia < ib),
- * recursion at which the row was generated, multiplier gamma, true Phi
- * where generated, unit normal from ia towards ib (3 each). */
+/* Colony growth (Sec. 5.3, growing bacterial colony): the cylinder length
+ * l of every spherocylinder grows by dl on the device (centres and axes
+ * kept; mobility, bounding radii and the candidate list's displacement
+ * bound follow at the next step).  A negative dl shrinks them (to undo a
+ * growth whose step failed), never below 0.  *n_ready (host, may be NULL:
+ * then no wait) = spherocylinders with l >= l_div afterwards.
+ * RELCP_E_INVALID for a non-finite dl. */
+RELCP_API int relcp_grow(relcp_ctx *ctx, double dl, double l_div, int32_t *n_ready);
+/* Colony division (Sec. 5.3): every spherocylinder with cylinder length
+ * l >= l_div becomes two cells that are the halves of its total length
+ * l + 2r, tip to tip: cylinder length l / 2 - r each, centres
+ * x +- (l + 2r) / 4 t (t = the cell's axis, body x); the first keeps the
+ * parent's caller index, the second is appended (indices n, n + 1, ... in
+ * the order of the parents' indices).  Each daughter is turned about the
+ * world z axis by its own angle, jitter[2k] and jitter[2k + 1] for the
+ * k-th dividing cell (radians; the caller draws them, e.g. N(0, 0.01^2)).
+ * The context is re-sized (as relcp_set_state with new counts: warm-start
+ * history and external wrenches cleared).  *n_divided (may be NULL) =
+ * dividing cells.  One packing only; RELCP_E_INVALID if n_jitter <
+ * 2 * dividing cells or a dividing cell has l < 2r (nothing changed then).
+ * Waits for the stream. */
+RELCP_API int relcp_divide(relcp_ctx *ctx, double l_div, const double *jitter, int32_t n_jitter,
+                           int32_t *n_divided);
+
+/* Rows of the last accepted step, i.e. the contact set A_n at acceptance
+ * with the multipliers gamma_n (Alg. 1; Def. ReLCP), in caller buffers of
+ * n_contacts_final entries (any may be NULL): body pair (caller's indices,
+ * ia < ib), recursion at which the row was generated, multiplier gamma,
+ * true Phi where generated, unit normal from ia towards ib (3 each).
+ * Waits for the stream; RELCP_E_INVALID for a NULL context. */
 RELCP_API int relcp_get_contacts(const relcp_ctx *ctx, int32_t *ia, int32_t *ib, int32_t *recursion_added, double *gamma,
                        double *phi_at_discovery, double *normal);
 
-/* Execution of the LCP loop (the same Jacobi-scaled projected gradient in
- * every mode).  mode 0 = automatic (resident when every packing has at
- * most 8192 bodies, else row graph with one launch per pass), 1 = grid (two passes per iteration
+/* Execution of the LCP loop (not in the paper: how the projected gradient
+ * of Eq. cqpp is launched; the same Jacobi-scaled iteration in every
+ * mode).  mode 0 = automatic (resident when every packing has at most
+ * 1024 bodies, or at most 8192 in a context of at least 32 packings; else
+ * row graph with one launch per pass), 1 = grid (two passes per iteration
  * over all rows and bodies, through the velocities K D gamma, launched in
  * chunks), 2 = resident (one workgroup per packing runs its whole solve in
  * one launch; block = workgroup size 256, 512 or 1024; lds = stage the
@@ -188,7 +232,7 @@ RELCP_API int relcp_get_contacts(const relcp_ctx *ctx, int32_t *ia, int32_t *ib,
  * by each of its workgroups (the same iterates either way). */
 RELCP_API int relcp_set_lcp_config(relcp_ctx *ctx, int32_t mode, int32_t block, int32_t lds);
 
-/* Autotuner: times every LCP configuration (grid; resident x {256, 512,
+/* Autotuner (not in the paper: launch configuration only): times every LCP configuration (grid; resident x {256, 512,
  * 1024} x {global, LDS}; row graph; row graph per-pass launches) on the
  * rows of the last accepted step, each solve from gamma = 0 (the step's
  * own multipliers already solve that LCP), once untimed and then reps
@@ -199,7 +243,8 @@ RELCP_API int relcp_set_lcp_config(relcp_ctx *ctx, int32_t mode, int32_t block, 
  * step are restored. */
 RELCP_API int relcp_autotune(relcp_ctx *ctx, double dt, double lcp_tol, int32_t reps, int32_t *config, double *ms);
 
-/* Kernel timing with HIP events (off by default; one event pair per
+/* Kernel timing with HIP events (not in the paper: measurement; off by
+ * default; one event pair per
  * timed launch): each kernel of a class is launched with the pair as the
  * dispatch's own start and end timestamps, so a duration is the kernel's
  * execution alone; a graph launch of row-graph passes (LCP mode 3) is timed
@@ -228,7 +273,8 @@ RELCP_API int relcp_get_timing(relcp_ctx *ctx, int32_t *count, double *ms, int32
  *   2 previous-step multiplier of the pair (the RELCP_WS_PREV start),
  *   3, 4 rows of A_0 at body a, at body b,
  *   5, 6 min / max semi-extent of a, of b,
- *   7 h_a(n) / h_b(n) (support functions along the normal).
+ *   7 overlap load of the neighbourhood: the sum over the other rows of A_0
+ *     at a and at b of max(0, -Phi_0) / abar.
  * Model: z = w3 . GELU(W2 GELU(W1 x + b1) + b2) + b3, GELU exact (erf,
  * evaluated to 5e-7), x = (feature - mean) / std; the start corrects the
  * previous-step multiplier: y0 = max(0, f_2 + scale z) in length units
@@ -241,14 +287,16 @@ RELCP_API int relcp_get_timing(relcp_ctx *ctx, int32_t *count, double *ms, int32
 #define RELCP_MLP_NPARAM 17793
 #define RELCP_MLP_NORM 17
 
-/* Select the warm start (RELCP_WS_COLD, _PREV or _LEARNED; _LEARNED needs an
- * installed model, else RELCP_E_INVALID). */
+/* Select the warm start of the iteration-0 LCP (the paper leaves it open,
+ * as above): RELCP_WS_COLD, _PREV or _LEARNED (_LEARNED needs an installed
+ * model, else RELCP_E_INVALID). */
 RELCP_API int relcp_set_warm_start(relcp_ctx *ctx, int32_t mode);
 /* Install a model: params (RELCP_MLP_NPARAM host floats), norm (17 host
  * floats, std and scale > 0).  Copied; RELCP_E_INVALID on non-finite input. */
 RELCP_API int relcp_set_warmstart_model(relcp_ctx *ctx, const float *params, const float *norm);
-/* Record the rows of A_0 of every accepted step (features and final
- * multipliers: the training data of the model).  Off by default. */
+/* Record the rows of A_0 (Alg. 1 initialisation) of every accepted step
+ * with their features and final multipliers: the training data of the
+ * learned start (not in the paper).  Off by default. */
 RELCP_API int relcp_enable_contact_log(relcp_ctx *ctx, int32_t on);
 /* Copy out the log of the last accepted step into caller device buffers of
  * cap rows (any may be NULL): feat (cap x 8 floats, row-major), gamma (the

@@ -167,9 +167,10 @@ struct PgdState {
     double res;       // scaled natural residual of the current iterate
     double ss, sy, yy;
     int iter;         // iterations taken
-    int conv;         // 1 once res <= tol
+    int conv;         // 1 once res <= tol; 2: stalled (an FP32 solve whose residual stopped falling)
     unsigned ticket;  // last-block counter
-    int pad;
+    int best_iter;    // iteration at which `best` was set
+    double best;      // residual of the last iterate that at least halved the one before it
 };
 
 // ---------------------------------------------------------------------------

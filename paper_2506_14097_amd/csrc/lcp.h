@@ -79,6 +79,10 @@ struct PgdCtl {
     // host-mapped mirrors of fin and done (or null), written with them
     PgdState *fin_h;
     int *done_h;
+    // iterations without halving the best residual after which the solve
+    // stops as stalled (0: never); set for FP32 solves, which an FP64 polish
+    // continues
+    int stall = 0;
 };
 
 // Row-graph form of the LCP matrix A = dt D^T K D off its diagonal: one
@@ -163,6 +167,7 @@ template <typename T>
 struct LcpDev {
     int m, nbg, cap;
     double tol;
+    int stall;  // as PgdCtl::stall
     const int *base, *col;
     const T *val;
     size_t slots;
@@ -223,6 +228,7 @@ struct ResidentArgs {
     int cap;
     PgdState *out;
     int lds_ld;
+    int stall;  // as PgdCtl::stall
 };
 template <typename T>
 int launch_lcp_resident(const ResidentArgs<T> &a, int block, bool lds, hipStream_t s);

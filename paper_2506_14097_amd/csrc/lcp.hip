@@ -302,7 +302,11 @@ __device__ inline void block_reduce4(double &a, double &b, double &c, double &mx
 
 // State after one gather: iteration count, residual, convergence and the
 // Barzilai-Borwein step (BB1 after even iterations, BB2 after odd ones).
-__device__ inline PgdState pgd_next(const PgdState &s, double ss, double sy, double yy, double res, double tol) {
+// An FP32 solve (stall > 0) whose residual has not halved for `stall`
+// iterations stops as stalled: its rounding floor is above the tolerance,
+// and the FP64 polish that follows it continues from its last iterate.
+__device__ inline PgdState pgd_next(const PgdState &s, double ss, double sy, double yy, double res, double tol,
+                                    int stall = 0) {
     PgdState n = s;
     const int k = s.iter;
     n.iter = k + 1;
@@ -311,6 +315,11 @@ __device__ inline PgdState pgd_next(const PgdState &s, double ss, double sy, dou
     n.sy = sy;
     n.yy = yy;
     n.conv = (res <= tol) ? 1 : 0;
+    if (!(res >= 0.5 * s.best)) {
+        n.best = res;
+        n.best_iter = n.iter;
+    }
+    if (stall > 0 && !n.conv && n.iter - n.best_iter >= stall) n.conv = 2;
     if (sy > 0.0) {
         double a = (k % 2 == 0) ? ss / sy : sy / yy;
         n.alpha = a < 1e-10 ? 1e-10 : (a > 1e10 ? 1e10 : a);
@@ -343,7 +352,44 @@ __device__ inline void reduce_partials(const PgdCtl &C, int par, PgdState *out, 
         }
     }
     block_reduce4(ss, sy, yy, res, sh);
-    if (threadIdx.x == 0) *out = pgd_next(C.S[par ^ 1], ss, sy, yy, res, C.tol);
+    if (threadIdx.x == 0) *out = pgd_next(C.S[par ^ 1], ss, sy, yy, res, C.tol, C.stall);
+    __syncthreads();
+}
+
+// The previous pass's partial sums held in registers: loaded at the start
+// of a pass (their latency overlaps the row's own loads) and reduced later
+// in the order reduce_partials uses (thread t: partials t, t + kThreads,
+// ...), so the state is the same bit for bit.  For passes over at most
+// kPartRegs * kThreads blocks.
+constexpr int kPartRegs = 4;
+struct PartialRegs {
+    double4 v[kPartRegs];
+};
+__device__ inline void load_partials(const PgdCtl &C, PartialRegs &pr) {
+    // every lane loads (a lane past the last block re-reads that block's
+    // sums, which reduce_loaded skips): no branch, so no wait before the
+    // row's own loads go out
+    const int last = C.nbg > 0 ? C.nbg - 1 : 0;
+#pragma unroll
+    for (int u = 0; u < kPartRegs; ++u) {
+        const int k = min((int)threadIdx.x + u * kThreads, last);
+        pr.v[u] = *reinterpret_cast<const double4 *>(C.partials + 4 * k);
+    }
+}
+__device__ inline void reduce_loaded(const PgdCtl &C, int par, const PartialRegs &pr, PgdState *out,
+                                     double (*sh)[kWaves]) {
+    double ss = 0.0, sy = 0.0, yy = 0.0, res = 0.0;
+#pragma unroll
+    for (int u = 0; u < kPartRegs; ++u) {
+        if ((int)threadIdx.x + u * kThreads < C.nbg) {
+            ss += pr.v[u].x;
+            sy += pr.v[u].y;
+            yy += pr.v[u].z;
+            res = fmax(res, pr.v[u].w);
+        }
+    }
+    block_reduce4(ss, sy, yy, res, sh);
+    if (threadIdx.x == 0) *out = pgd_next(C.S[par ^ 1], ss, sy, yy, res, C.tol, C.stall);
     __syncthreads();
 }
 
@@ -352,6 +398,8 @@ __device__ inline void pgd_reset(const PgdCtl &C) {
     PgdState s{};
     s.alpha = 1.0;
     s.iter = -1;
+    s.best = __builtin_huge_val();
+    s.best_iter = -1;
     C.S[0] = s;
     C.S[1] = s;
     *C.fin = s;
@@ -454,7 +502,7 @@ template <typename T, int BS, bool LDSV>
 __global__ void __launch_bounds__(BS) k_lcp_resident(RowsT<T> R, BodiesT<T> B, const int *__restrict__ boff,
                                                      const int *__restrict__ roff, const int *__restrict__ rlist,
                                                      double dt, double tol, int cap, PgdState *__restrict__ out,
-                                                     int lds_ld) {
+                                                     int lds_ld, int stall) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double sh[4][BS / RELCP_WAVE];
     __shared__ PgdState st;
@@ -471,6 +519,8 @@ __global__ void __launch_bounds__(BS) k_lcp_resident(RowsT<T> R, BodiesT<T> B, c
             PgdState s0{};
             s0.alpha = 1.0;
             s0.iter = -1;
+            s0.best = __builtin_huge_val();
+            s0.best_iter = -1;
             st = pgd_next(s0, ss, sy, yy, res, tol);
         }
         __syncthreads();
@@ -482,7 +532,7 @@ __global__ void __launch_bounds__(BS) k_lcp_resident(RowsT<T> R, BodiesT<T> B, c
             for (int k = r0 + threadIdx.x; k < r1; k += BS)
                 gather_row<T, 1>(R, rlist[k], al, dtT, V, ss, sy, yy, res);
             block_reduce4n<BS / RELCP_WAVE>(ss, sy, yy, res, sh);
-            if (threadIdx.x == 0) st = pgd_next(st, ss, sy, yy, res, tol);
+            if (threadIdx.x == 0) st = pgd_next(st, ss, sy, yy, res, tol, stall);
             __syncthreads();
         }
     };
@@ -761,18 +811,18 @@ struct RowPre {
     T vj[kPre], gj[kPre], hj[kPre];
 };
 
+// Stage A of a row's loads: the slice's base and width (scalar) and the
+// row's own state; nothing here waits on another load of the pass.
 template <typename T, int MODE, class SV>
-__device__ inline void row_preload(const RowGraphT<T> &G, const T *__restrict__ qv, const T *__restrict__ dA0,
-                                   const SV &gam0, const RowStep<T> *__restrict__ zin,
-                                   const T *__restrict__ gin, int r, RowPre<T> &P) {
-    const int lane = r & (RELCP_WAVE - 1), sl = r / RELCP_WAVE;
-    const int b0 = G.base[sl];
-    P.w = G.base[sl + 1] - b0;
-    // an overflowed assembly left this slice unwritten: no entries (the
-    // caller sees the overflow report, re-sizes and starts the solve over)
-    if ((size_t)RELCP_WAVE * (b0 + P.w) > G.cap) P.w = 0;
-    P.col = G.col + (size_t)RELCP_WAVE * b0 + lane;
-    P.val = G.val + (size_t)RELCP_WAVE * b0 + lane;
+__device__ inline void row_preload_a(const RowGraphT<T> &G, const T *__restrict__ qv, const T *__restrict__ dA0,
+                                     const SV &gam0, const RowStep<T> *__restrict__ zin,
+                                     const T *__restrict__ gin, int r, RowPre<T> &P, int &b0) {
+    // one slice per wave: its base and width are the same in every lane, so
+    // they are held in scalar registers and the loops over entries below
+    // branch uniformly
+    const int sl = __builtin_amdgcn_readfirstlane(r / RELCP_WAVE);
+    b0 = __builtin_amdgcn_readfirstlane(G.base[sl]);
+    P.w = __builtin_amdgcn_readfirstlane(G.base[sl + 1]);
     P.dA = dA0[r];
     P.q = qv[r];
     if (MODE == 1) {
@@ -785,20 +835,58 @@ __device__ inline void row_preload(const RowGraphT<T> &G, const T *__restrict__ 
         P.hm = T(0);
         P.gold = T(0);
     }
-#pragma unroll
-    for (int k = 0; k < kPre; ++k) P.cj[k] = k < P.w ? P.col[RELCP_WAVE * k] : r;
+}
+
+// Stage B: the first kPre entries of the row and the states of the rows
+// they point at (two dependent loads).
+template <typename T, int MODE, class SV>
+__device__ inline void row_preload_b(const RowGraphT<T> &G, const SV &gam0, const RowStep<T> *__restrict__ zin, int r,
+                                     RowPre<T> &P, int b0) {
+    const int lane = r & (RELCP_WAVE - 1);
+    P.w -= b0;
+    // an overflowed assembly left this slice unwritten: no entries (the
+    // caller sees the overflow report, re-sizes and starts the solve over)
+    if ((size_t)RELCP_WAVE * (b0 + P.w) > G.cap) P.w = 0;
+    P.col = G.col + (size_t)RELCP_WAVE * b0 + lane;
+    P.val = G.val + (size_t)RELCP_WAVE * b0 + lane;
+    // entries past the slice's width are padding: not loaded (zero value,
+    // zero neighbour state)
+    const int kp = P.w < kPre ? P.w : kPre;
 #pragma unroll
     for (int k = 0; k < kPre; ++k) {
-        P.vj[k] = k < P.w ? P.val[RELCP_WAVE * k] : T(0);
-        if (MODE == 1) {
-            const RowStep<T> z = zin[P.cj[k]];
-            P.gj[k] = z.gam;
-            P.hj[k] = z.h;
+        if (k < kp) {
+            P.cj[k] = P.col[RELCP_WAVE * k];
+            P.vj[k] = P.val[RELCP_WAVE * k];
         } else {
-            P.gj[k] = (T)gam0[P.cj[k]];
+            P.cj[k] = r;
+            P.vj[k] = T(0);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+        if (k < kp) {
+            if (MODE == 1) {
+                const RowStep<T> z = zin[P.cj[k]];
+                P.gj[k] = z.gam;
+                P.hj[k] = z.h;
+            } else {
+                P.gj[k] = (T)gam0[P.cj[k]];
+                P.hj[k] = T(0);
+            }
+        } else {
+            P.gj[k] = T(0);
             P.hj[k] = T(0);
         }
     }
+}
+
+template <typename T, int MODE, class SV>
+__device__ inline void row_preload(const RowGraphT<T> &G, const T *__restrict__ qv, const T *__restrict__ dA0,
+                                   const SV &gam0, const RowStep<T> *__restrict__ zin,
+                                   const T *__restrict__ gin, int r, RowPre<T> &P) {
+    int b0;
+    row_preload_a<T, MODE, SV>(G, qv, dA0, gam0, zin, gin, r, P, b0);
+    row_preload_b<T, MODE, SV>(G, gam0, zin, r, P, b0);
 }
 
 // projected steps, g' = qv + A gamma', the row's new state and its share
@@ -849,15 +937,27 @@ __global__ void __launch_bounds__(kThreads)
     constexpr bool START = MODE == 0 || MODE == 3;
     constexpr int RM = START ? 0 : 1;  // row arithmetic: start or iteration
     using SV = typename std::conditional<MODE == 3, StartF32, StartF64>::type;
-    if (!START && *C.done) return;
     if (START && blockIdx.x == 0 && threadIdx.x == 0) pgd_reset(C);
     const int lb = xcd_block(blockIdx.x, gridDim.x);  // logical block: a contiguous row range per XCD
     const int r = lb * kThreads + threadIdx.x;
     const bool act = r < G.m;
     SV gam0{};
     if (START) gam0 = SV::from(start);
+    // loads that depend on no other load of the pass go out first: the last
+    // pass's partial sums, the row's own state, the slice's base and the
+    // done flag; a pass after convergence leaves once the flag is in
+    // Lanes past the last row load the last row (their results are never
+    // written), so the loads need no branch and nothing waits for them
+    // before they are used.
+    PartialRegs pr;
+    if (MODE == 1) load_partials(C, pr);
+    const int done = START ? 0 : __builtin_amdgcn_readfirstlane(*C.done);
+    const int rl = act ? r : G.m - 1;
     RowPre<T> P;
-    if (act) row_preload<T, RM, SV>(G, qv, dA0, gam0, zin, gin, r, P);
+    int b0 = 0;
+    if (G.m > 0) row_preload_a<T, RM, SV>(G, qv, dA0, gam0, zin, gin, rl, P, b0);
+    if (done) return;
+    if (G.m > 0) row_preload_b<T, RM, SV>(G, gam0, zin, rl, P, b0);
     if (START && save && act) save[r] = gam0[r];  // the start, kept for a restart
     T al = T(0);
     if (MODE == 2) {
@@ -867,7 +967,7 @@ __global__ void __launch_bounds__(kThreads)
         al = (T)ns.alpha;
     }
     if (MODE == 1) {
-        reduce_partials(C, par, &ns, sh);
+        reduce_loaded(C, par, pr, &ns, sh);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             C.S[par] = ns;
             if (ns.conv) {
@@ -911,7 +1011,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_dev(const LcpDev<T> *__restri
     const bool act = r < d.m;
     RowPre<T> P;
     if (act) row_preload<T, 1, StartF64>(G, d.qv, d.dA, StartF64{nullptr}, d.z[par ^ 1], d.g[par ^ 1], r, P);
-    PgdCtl C{d.S, d.fin, d.done, d.part[par ^ 1], nbg, d.tol, d.fin_h, d.done_h};
+    PgdCtl C{d.S, d.fin, d.done, d.part[par ^ 1], nbg, d.tol, d.fin_h, d.done_h, d.stall};
     reduce_partials(C, par, &ns, sh);
     const bool stop = ns.conv || ns.iter >= d.cap;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1057,7 +1157,7 @@ static int launch_res(const ResidentArgs<T> &a, hipStream_t s) {
             return -1;
     }
     launch_k(fn, dim3(a.npk), dim3(BS), lds, s, a.R, a.B, a.boff, a.roff, a.rlist, a.dt, a.tol, a.cap, a.out,
-             a.lds_ld);
+             a.lds_ld, a.stall);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

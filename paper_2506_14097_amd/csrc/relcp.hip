@@ -266,10 +266,19 @@ struct relcp_ctx {
     static constexpr int kGraphPasses = 8;
     // iteration passes over at least this many blocks reduce the last pass's
     // partial sums in a separate one-block launch (RELCP_REDUCE_SPLIT_BLOCKS)
-    int reduce_split_blocks = env_int("RELCP_REDUCE_SPLIT_BLOCKS", 1024);
+    // (at most 1024: a pass that reduces by itself holds the partial sums of
+    // up to 4 x 256 blocks in registers)
+    int reduce_split_blocks = std::min(1024, env_int("RELCP_REDUCE_SPLIT_BLOCKS", 1024));
     // first estimate of row-graph entry slots per row (RELCP_RG_SLOTS_PER_ROW);
     // an assembly that does not fit is re-sized and its solve restarted
     int rg_slots_per_row = env_int("RELCP_RG_SLOTS_PER_ROW", 16);
+    // an FP32 solve whose residual has not halved in this many iterations
+    // stops (its rounding floor is above the tolerance) and the FP64
+    // polish continues from its last iterate; fixed-iteration runs never stop
+    template <typename T>
+    int stall_iters() const {
+        return sizeof(T) == 4 && lcp_fixed == 0 ? 400 : 0;
+    }
     int rg_restarts = 0;  // of the current step
     DBuf<LcpDev<double>> lcpdev64;
     DBuf<LcpDev<float>> lcpdev32;
@@ -289,10 +298,13 @@ struct relcp_ctx {
     DBuf<int> boff_d, roff, rlist, rlist2, rcnt, rE;
     DBuf<PgdState> pk_state;
     PgdState *pk_state_h = nullptr;
+    // automatic choice: one workgroup per packing suits many packings or
+    // small ones; a few large packings leave most of the GPU idle there and
+    // run their passes over many workgroups instead
     bool resident_mode() const {
         if (lcp_mode == 1 || lcp_mode == 3 || lcp_mode == 4) return false;
         if (lcp_mode == 2) return true;
-        return maxpk <= 8192;
+        return maxpk <= 1024 || (maxpk <= 8192 && nbatch >= 32);
     }
     void rows_by_packing_init(int m0);
     void rows_by_packing_append(int m_old, int nv);
@@ -1007,7 +1019,7 @@ int relcp_ctx::solve(double dt, double tol, int &iters, double &res) {
     const BodiesT<T> Bd = bodies_of<T>();
     if (resident_mode()) {
         ResidentArgs<T> a{R, Bd, nbatch, boff_d.p, roff.p, rlist.p, dt, lcp_fixed > 0 ? -1.0 : tol,
-                          lcp_fixed > 0 ? lcp_fixed : lcp_max_iters, pk_state.p, maxpk};
+                          lcp_fixed > 0 ? lcp_fixed : lcp_max_iters, pk_state.p, maxpk, stall_iters<T>()};
         const bool lds = res_lds && (size_t)6 * maxpk * sizeof(T) <= 150 * 1024;
         int rc = 0;
         timed(5, [&] { rc = launch_lcp_resident<T>(a, res_block, lds, stream); });
@@ -1032,7 +1044,7 @@ int relcp_ctx::solve(double dt, double tol, int &iters, double &res) {
     // pst: S[0], S[1], fin, then a slot whose first int is the done flag
     pst.ensure(4);
     PgdCtl C{pst.p, pst.p + 2, reinterpret_cast<int *>(pst.p + 3), partials.p, lcp_gather_blocks(m),
-             lcp_fixed > 0 ? -1.0 : tol, pst_d, reinterpret_cast<int *>(pst_d + 1)};
+             lcp_fixed > 0 ? -1.0 : tol, pst_d, reinterpret_cast<int *>(pst_d + 1), stall_iters<T>()};
     const int cap = lcp_fixed > 0 ? lcp_fixed : lcp_max_iters;
     const int pk = sizeof(T) == 8 ? 1 : 0;
     launch_pgd_init(C, stream);
@@ -1129,7 +1141,8 @@ relcp_ctx::RgBufs<T> relcp_ctx::rg_bufs(const RowsT<T> &R, double tol) {
     pst.ensure(8);
     PgdState *cb = pst.p + 4 * pk;
     B.C = PgdCtl{cb, cb + 2, reinterpret_cast<int *>(cb + 3), B.part, lcp_gather_blocks(m),
-                 lcp_fixed > 0 ? -1.0 : tol, pst_d + 2 * pk, reinterpret_cast<int *>(pst_d + 2 * pk + 1)};
+                 lcp_fixed > 0 ? -1.0 : tol, pst_d + 2 * pk, reinterpret_cast<int *>(pst_d + 2 * pk + 1),
+                 stall_iters<T>()};
     B.G = RowGraphT<T>{m, rg_base.p, rg_col.p, nullptr, rg_cap};
     if constexpr (sizeof(T) == 8)
         B.G.val = rg_val64.p;
@@ -1312,7 +1325,7 @@ int relcp_ctx::solve_rowgraph_graph(const RowsT<T> &R, const BodiesT<T> &Bd, dou
             return solve_rowgraph<T>(R, Bd, dt, tol, iters, res);
         }
         LcpDev<T> v{};
-        v.m = m; v.nbg = B.C.nbg; v.cap = cap; v.tol = B.C.tol;
+        v.m = m; v.nbg = B.C.nbg; v.cap = cap; v.tol = B.C.tol; v.stall = B.C.stall;
         v.base = B.G.base; v.col = B.G.col; v.val = B.G.val; v.slots = B.G.cap;
         v.qv = R.qv; v.dA = R.dA;
         v.z[0] = B.z0; v.z[1] = B.z1; v.g[0] = B.g0; v.g[1] = B.g1;
@@ -1872,6 +1885,139 @@ int relcp_affine_rescale_packings(relcp_ctx *ctx, const double *s) {
         for (int pk = 0; pk < ctx->nbatch; ++pk)
             shrink = std::max(shrink, std::max(0.0, 1.0 - s[pk]) * (2.0 * ctx->rmax[pk] + ctx->vl_radius()));
         ctx->vl_used += shrink;
+        return RELCP_OK;
+    });
+}
+
+// cylinder length l (shape component 1) of every spherocylinder grows by
+// dl; `ready` counts those at or past l_div afterwards
+__global__ void k_grow(int n, const int *__restrict__ kind, double *__restrict__ p, double dl, double l_div,
+                       int *__restrict__ ready) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int r = 0;
+    if (i < n && kind[i] == RELCP_SPHEROCYLINDER) {
+        const double l = fmax(0.0, p[n + i] + dl);
+        p[n + i] = l;
+        r = l >= l_div;
+    }
+    if (ready) {
+        for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) r += __shfl_xor(r, o, RELCP_WAVE);
+        if ((threadIdx.x & (RELCP_WAVE - 1)) == 0 && r) atomicAdd(ready, r);
+    }
+}
+
+int relcp_grow(relcp_ctx *ctx, double dl, double l_div, int32_t *n_ready) {
+    if (!ctx) return RELCP_E_INVALID;
+    if (!std::isfinite(dl) || std::isnan(l_div)) return RELCP_E_INVALID;
+    return guarded(ctx, [&]() -> int {
+        const int N = ctx->n;
+        DBuf<int> cnt;
+        if (n_ready) {
+            cnt.ensure(1);
+            HIP_OK(hipMemsetAsync(cnt.p, 0, sizeof(int), ctx->stream));
+        }
+        if (N > 0)
+            hipLaunchKernelGGL(k_grow, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, N, ctx->kind.p, ctx->p.p, dl,
+                               l_div, n_ready ? cnt.p : nullptr);
+        HIP_OK(hipGetLastError());
+        // a cap tip moves dl / 2 along the axis: bounding radii grow by dl / 2
+        // and the gap of a pair shrinks by at most dl (the kept candidate
+        // list accounts for it; a shrink only widens gaps, and the bounding
+        // radius bound is kept); mobility and geometry are set up again
+        if (dl > 0) {
+            for (int pk = 0; pk < ctx->nbatch; ++pk) ctx->rmax[pk] += 0.5 * dl;
+            ctx->vl_used += dl;
+        }
+        ctx->setup_valid = false;
+        if (n_ready) {
+            int h = 0;
+            HIP_OK(hipMemcpyAsync(&h, cnt.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+            ctx->sync();
+            cnt.release();
+            *n_ready = h;
+        }
+        return RELCP_OK;
+    });
+}
+
+int relcp_divide(relcp_ctx *ctx, double l_div, const double *jitter, int32_t n_jitter, int32_t *n_divided) {
+    if (!ctx || !(l_div > 0) || !std::isfinite(l_div) || n_jitter < 0 || (n_jitter > 0 && !jitter))
+        return RELCP_E_INVALID;
+    return guarded(ctx, [&]() -> int {
+        if (ctx->nbatch != 1) throw Error{RELCP_E_INVALID, "division needs a context of one packing"};
+        const size_t N = ctx->n;
+        std::vector<double> x(3 * N), q(4 * N), u(3 * N), w(3 * N), sp(3 * N), rho(N), t(3 * N);
+        std::vector<int> kind(N), kt(N);
+        int rc = get_state_impl(ctx, x.data(), q.data(), u.data(), w.data(), false);
+        if (rc != RELCP_OK) return rc;
+        // shapes, drag and kinds back in the caller's order
+        HIP_OK(hipMemcpyAsync(t.data(), ctx->p.p, 3 * N * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(hipMemcpyAsync(rho.data(), ctx->rho.p, N * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(hipMemcpyAsync(kt.data(), ctx->kind.p, N * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        ctx->sync();
+        std::vector<double> rh(N);
+        for (size_t i = 0; i < N; ++i) {
+            const size_t c = ctx->perm[i];
+            for (int k = 0; k < 3; ++k) sp[3 * c + k] = t[k * N + i];
+            rh[c] = rho[i];
+            kind[c] = kt[i];
+        }
+        std::vector<size_t> div;
+        for (size_t c = 0; c < N; ++c)
+            if (kind[c] == RELCP_SPHEROCYLINDER && sp[3 * c + 1] >= l_div) div.push_back(c);
+        if (n_divided) *n_divided = (int32_t)div.size();
+        if (div.empty()) return RELCP_OK;
+        if ((size_t)n_jitter < 2 * div.size()) throw Error{RELCP_E_INVALID, "two jitter angles per dividing cell"};
+        for (size_t c : div)
+            if (0.5 * sp[3 * c + 1] - sp[3 * c] < 0.0)
+                throw Error{RELCP_E_INVALID, "a dividing cell shorter than its diameter"};
+        const size_t M = N + div.size();
+        x.resize(3 * M); q.resize(4 * M); u.resize(3 * M); w.resize(3 * M); sp.resize(3 * M); rh.resize(M);
+        kind.resize(M);
+        for (size_t k = 0; k < div.size(); ++k) {
+            const size_t a = div[k], b = N + k;
+            const double r = sp[3 * a], l = sp[3 * a + 1];
+            const double *qa = &q[4 * a];
+            // body x axis (the cell's axis) in the world frame
+            const double ax = 1.0 - 2.0 * (qa[2] * qa[2] + qa[3] * qa[3]), ay = 2.0 * (qa[1] * qa[2] + qa[0] * qa[3]),
+                         az = 2.0 * (qa[1] * qa[3] - qa[0] * qa[2]);
+            // the daughters are the two halves of the parent, tip to tip:
+            // total length (l + 2r) / 2 each, centres a quarter of the
+            // parent's total length from its centre
+            const double h = 0.25 * (l + 2.0 * r);
+            const double p0[4] = {qa[0], qa[1], qa[2], qa[3]};
+            double xc[3] = {x[3 * a], x[3 * a + 1], x[3 * a + 2]};
+            for (int d = 0; d < 2; ++d) {
+                const size_t o = d ? b : a;
+                const double sgn = d ? -1.0 : 1.0;
+                x[3 * o] = xc[0] + sgn * h * ax;
+                x[3 * o + 1] = xc[1] + sgn * h * ay;
+                x[3 * o + 2] = xc[2] + sgn * h * az;
+                // turn about the world z axis by the daughter's jitter angle
+                const double th = jitter[2 * k + d], cz = std::cos(0.5 * th), sz = std::sin(0.5 * th);
+                q[4 * o] = cz * p0[0] - sz * p0[3];
+                q[4 * o + 1] = cz * p0[1] - sz * p0[2];
+                q[4 * o + 2] = cz * p0[2] + sz * p0[1];
+                q[4 * o + 3] = cz * p0[3] + sz * p0[0];
+                const double nq = std::sqrt(q[4 * o] * q[4 * o] + q[4 * o + 1] * q[4 * o + 1] +
+                                            q[4 * o + 2] * q[4 * o + 2] + q[4 * o + 3] * q[4 * o + 3]);
+                for (int j = 0; j < 4; ++j) q[4 * o + j] /= nq;
+                for (int j = 0; j < 3; ++j) {
+                    u[3 * o + j] = u[3 * a + j];
+                    w[3 * o + j] = w[3 * a + j];
+                }
+                sp[3 * o] = r;
+                sp[3 * o + 1] = 0.5 * l - r;
+                sp[3 * o + 2] = 0.0;
+                rh[o] = rh[a];
+                kind[o] = RELCP_SPHEROCYLINDER;
+            }
+        }
+        const std::vector<double> bx = ctx->box;  // upload_bodies replaces ctx->box
+        relcp_bodies B{(int32_t)M, x.data(), q.data(), u.data(), w.data(), 1, nullptr, bx.data()};
+        relcp_shapes S{kind.data(), sp.data(), rh.data()};
+        validate(&B, &S, nullptr, ctx->skin);
+        ctx->upload_bodies(&B, &S);
         return RELCP_OK;
     });
 }

@@ -91,6 +91,8 @@ _SIGS = {
     "relcp_affine_rescale": (C.c_int, [C.c_void_p, C.c_double]),
     "relcp_affine_rescale_packings": (C.c_int, [C.c_void_p, C.c_void_p]),
     "relcp_get_contacts": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6),
+    "relcp_grow": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p]),
+    "relcp_divide": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_int32, C.c_void_p]),
     "relcp_set_lcp_config": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
     "relcp_autotune": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_void_p]),
     "relcp_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -238,6 +240,27 @@ class Simulation:
         rc = lib().relcp_affine_rescale(self.ctx, s)
         if rc != OK:
             raise RelcpError(rc, self._err())
+
+    def grow(self, dl, l_div=float("inf"), count=False):
+        """Cylinder lengths of all spherocylinders += dl (device side);
+        with count=True returns how many reached l_div (one wait)."""
+        n = C.c_int32(0)
+        rc = lib().relcp_grow(self.ctx, float(dl), float(l_div), C.byref(n) if count else None)
+        if rc != OK:
+            raise RelcpError(rc, self._err())
+        return n.value if count else None
+
+    def divide(self, l_div, jitter):
+        """Split every spherocylinder with l >= l_div into its two halves,
+        each turned about z by its angle in jitter (two per dividing cell,
+        in the order of the parents' indices); returns the number divided."""
+        jit = np.ascontiguousarray(jitter, dtype=np.float64)
+        n = C.c_int32(0)
+        rc = lib().relcp_divide(self.ctx, float(l_div), _ptr(jit) if jit.size else None, int(jit.size), C.byref(n))
+        if rc != OK:
+            raise RelcpError(rc, self._err())
+        self.n += n.value
+        return n.value
 
     TIMING_CLASSES = ("lcp_scatter", "lcp_gather", "snsd", "pairs", "trial", "lcp_resident", "warm_start",
                       "lcp_rowgraph", "rowgraph_build", "lcp_rowgraph_idle", "lcp_rowgraph64",

@@ -1,18 +1,3 @@
-def oracle_residual(ref, c, S, s):
-    """Scaled natural residual max |min(A_aa gamma, g)| of the GPU's
-    multipliers, placed on the oracle step's rows (the same contact set, no
-    augmentation: qv = Phi_0), under the oracle's operator A = dt D^T K D."""
-    o = np.lexsort((ref["ib"], ref["ia"]))
-    g = np.lexsort((c["ib"], c["ia"]))
-    gam = np.empty(ref["n_rows"])
-    gam[o] = c["gamma"][g]
-    kt, Kr = O.body_K(0, 0, 5e-3, S["kind"], S["shape"], S["q"], S["rho_xi"])
-    _, it, res = O.lcp_bbpgd_rows(len(S["x"]), ref["ia"], ref["ib"], ref["n"], ref["ta"], ref["tb"], kt, Kr, 5e-3,
-                                  ref["phi"], gamma0=gam, tol=0.0, max_iter=0)
-    assert it == -1
-    return res
-
-
 """GPU parity at the benchmark's size, in the launch configuration the
 benchmark times (row-graph LCP with one launch per pass over hundreds of
 workgroups, multi-tile compaction, candidate search over a 100,000-body
@@ -90,14 +75,19 @@ def oracle_step(case, tol=1e-12):
     return ref
 
 
-def oracle_residual(ref, gam, S, s):
-    """Scaled natural residual max |min(A_aa gamma, g)| of multipliers gam on
-    the oracle step's rows (the operator A = dt D^T K D of the oracle)."""
+def oracle_residual(ref, c, S, s):
+    """Scaled natural residual max |min(A_aa gamma, g)| of the GPU's
+    multipliers, placed on the oracle step's rows (the same contact set, no
+    augmentation: qv = Phi_0), under the oracle's operator A = dt D^T K D."""
+    o = np.lexsort((ref["ib"], ref["ia"]))
+    g = np.lexsort((c["ib"], c["ia"]))
+    gam = np.empty(ref["n_rows"])
+    gam[o] = c["gamma"][g]
     kt, Kr = O.body_K(0, 0, 5e-3, S["kind"], S["shape"], S["q"], S["rho_xi"])
-    n = len(S["x"])
-    A_g, _, _ = O.lcp_bbpgd_rows(n, ref["ia"], ref["ib"], ref["n"], ref["ta"], ref["tb"], kt, Kr, 5e-3,
-                                 np.zeros(ref["n_rows"]), gamma0=gam, tol=0.0, max_iter=0)
-    return A_g
+    _, it, res = O.lcp_bbpgd_rows(len(S["x"]), ref["ia"], ref["ib"], ref["n"], ref["ta"], ref["tb"], kt, Kr, 5e-3,
+                                  ref["phi"], gamma0=gam, tol=0.0, max_iter=0)
+    assert it == -1
+    return res
 
 
 @pytest.mark.parametrize("case,precision,lcp_tol",
@@ -117,6 +107,12 @@ def test_fullsize_step_matches_oracle(dev, case, precision, lcp_tol):
           list(ref["lcp_iters"]), "margin", list(ref["margin"]), flush=True)
     assert res["status"] == 0
     assert ref["n_rows"] > 50000 and len(S["x"]) == 100000
+    if precision == 32:
+        # FP32 iterations whose residual stops falling above the tolerance
+        # hand over to the FP64 polish instead of running to the cap
+        lo = np.asarray(res["lcp_iters"]) - np.asarray(res["lcp_iters64"])
+        print("  FP32 iterations per recursion", list(lo), "FP64", list(res["lcp_iters64"]), flush=True)
+        assert lo.max() < 2000
     if case == "augmented":
         assert ref["recursions"] >= 1
     # contact sets per recursion

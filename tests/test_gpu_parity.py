@@ -82,6 +82,9 @@ def test_snsd_ellipsoids(dev, seed):
     assert np.abs(out[shallow, 4:] - ref[shallow, 4:]).max() < 1e-8
     assert np.all(out[:, 0] <= ref[:, 0] + 1e-10)
     assert np.mean(phi_ok < 1e-10) > 0.995
+    deep = ~shallow
+    print("pairs %d, deep (Phi < -0.1) %d, of which at another local maximum %d" %
+          (len(pa), deep.sum(), int(np.sum(phi_ok[deep] >= 1e-10))), flush=True)
 
 
 def test_snsd_spherocylinders(dev):
@@ -204,9 +207,10 @@ def _lcp_cases(dev, case):
     return host, args, len(ia)
 
 
-# measured divergence of the FP64 iterates from the oracle's after k
-# iterations (relative to the largest oracle multiplier); the bars hold the
-# measured values with headroom
+# iteration counts at which the FP64 iterates are compared with the
+# oracle's; measured on MI355X, the k-th iterates agree to 2.5e-16 - 1.2e-14
+# relative to the largest multiplier (both systems, both modes, k <= 40):
+# the bar 1e-12 holds that with two orders of headroom
 FIXED_ITERS = (1, 2, 3, 5, 10, 20, 40)
 
 
@@ -217,8 +221,9 @@ def test_lcp_fixed_iterations(dev, case, mode):
     Barzilai-Borwein iterations from the same start (both capped at k with a
     tolerance of 0), the multipliers agree with the oracle's k-th iterate.
     Rounding differs (FMA, summation order of A gamma), and the step length
-    alpha = s^T D s / s^T y of each iteration feeds that difference forward,
-    so the bar grows with k; each k's divergence is printed."""
+    alpha = s^T D s / s^T y of each iteration feeds that difference forward;
+    over 40 iterations it stays at the rounding level.  Each k's divergence
+    is printed."""
     host, args, m = _lcp_cases(dev, case)
     for k in FIXED_ITERS:
         g_or, it_or, _ = O.lcp_bbpgd_rows(*host, tol=0.0, max_iter=k)
@@ -228,7 +233,7 @@ def test_lcp_fixed_iterations(dev, case, mode):
         assert rc == R.E_LCP_MAXITER and it == k
         err = rel(g.cpu().numpy(), g_or)
         print("case", case, "mode", mode, "k", k, "iterate divergence", err, flush=True)
-        assert err < (1e-12 if k <= 10 else 1e-9)
+        assert err < 1e-12
 
 
 @pytest.mark.parametrize("mode", [1, 3, 4], ids=["grid", "rowgraph", "rowgraph-perpass"])
