@@ -51,7 +51,7 @@ FP64_PEAK_TFLOPS = 78.6
 # a plain copy of known size reads), recorded in
 # profiles/lcp_rowgraph_pass_100k_hbm_traffic.md for the kernel source with
 # the given sha256 prefix (stale once it changes).
-MEASURED_TRAFFIC = {"sha256_prefix": "c39b1e6f88132ba6", "lcp_rowgraph": 1.4028e7}
+MEASURED_TRAFFIC = {"sha256_prefix": "60708ab3b018557b", "lcp_rowgraph": 1.4028e7}
 
 
 # timing class -> kernel
@@ -64,7 +64,9 @@ KERNEL_SYMBOLS = {"lcp_rowgraph": "relcp::k_spmv<float, 1>", "lcp_rowgraph64": "
 # workload (rocprofv3 --pmc SQ_INSTS_VALU_ADD_F64, _MUL_F64, _FMA_F64,
 # _TRANS_F64: add + mul + 2 fma + trans, times 64 lanes, over the pairs of
 # the launch), for the kernel source with the given sha256 prefix.
-SNSD_FP64_OPS = {"sha256_prefix": None, "fp64_ops_per_pair": None, "source": None}
+SNSD_FP64_OPS = {"sha256_prefix": "8bd873bcad2f4d6d", "fp64_ops_per_pair": 1277.0,
+                 "source": "profiles/snsd_pairs_100k_fp64_counters.md: issued FP64 operations (64 lanes per wave "
+                           "instruction) per candidate pair, mean of the pass at C^k and the pass at the trial"}
 
 
 def geometry_source_sha():
@@ -415,10 +417,13 @@ def packings_workload(args, steps=None, warmup=None):
     el = time.perf_counter() - t0
     sim.set_timing(True)
     sim.get_timing(reset=True)
-    advance(args.roofline_steps)
+    rstats = []
+    advance(args.roofline_steps, rstats)
     tm = sim.get_timing(reset=True)
-    rg = [(m, it - i64, e) for r in stats for m, it, i64, e in zip(r["n_contacts"], r["lcp_iters"], r["lcp_iters64"],
-                                                                     r["rowgraph_entries"])]
+    # the timed launches' rows and iterations (a launch covers every packing)
+    rg = [(m, it - i64, e) for r in rstats for m, it, i64, e in zip(r["n_contacts"], r["lcp_iters"], r["lcp_iters64"],
+                                                                      r["rowgraph_entries"])]
+
     out = {"metric": "packing-steps/s, %d independent periodic ellipsoid packings in one context" % npk,
            "value": npk * steps / el, "unit": "packing-steps/s", "steps": steps,
            "ms_per_step": 1e3 * el / steps, "bodies": int(off[-1]), "packings": npk,
@@ -603,14 +608,14 @@ def colony_workload(args, sizes=(4096, 65536, 131072)):
     every cell dividing at total length 2 into its two halves (jitter
     N(0, 0.01^2) rad), dt 1e-2, overlap_tol 1e-3, lcp_tol 1e-6, skin 0.2.
     The set-up grows the colony to each size ten times faster in a context
-    with skin 1.0 (untimed; the rate is halved whenever the rim would still
+    with skin 0.5 (untimed; the rate is halved whenever the rim would still
     move more than skin / 2 in a step).  At each size the state moves to a
     context with the benchmark's skin, takes 5 untimed steps, and a window
     of --colony-steps steps at the benchmarked rate is timed, just after the
     division that reached the size."""
     import torch
     from paper_2506_14097_amd.colony import Colony
-    col = Colony(seed=2, rate=0.01, dt=1e-2, eps=args.eps, tol=args.tol, precision=args.precision, skin=1.0)
+    col = Colony(seed=2, rate=0.01, dt=1e-2, eps=args.eps, tol=args.tol, precision=args.precision, skin=0.5)
     out = []
     t0 = time.time()
     for N in sizes:
@@ -630,7 +635,7 @@ def colony_workload(args, sizes=(4096, 65536, 131072)):
              "max_overlap": float(max(s_["max_overlap"] for s_ in st))}
         log("colony: %s (%.1fs)" % (w, time.time() - t0))
         out.append(w)
-        col.reskin(1.0)
+        col.reskin(0.5)
     col.sim.close()
     return out
 

@@ -216,7 +216,7 @@ RELCP_API int relcp_get_contacts(const relcp_ctx *ctx, int32_t *ia, int32_t *ib,
 /* Execution of the LCP loop (not in the paper: how the projected gradient
  * of Eq. cqpp is launched; the same Jacobi-scaled iteration in every
  * mode).  mode 0 = automatic (resident when every packing has at most
- * 1024 bodies, or at most 8192 in a context of at least 32 packings; else
+ * 256 bodies, or at most 8192 in a context of at least 32 packings; else
  * row graph with one launch per pass), 1 = grid (two passes per iteration
  * over all rows and bodies, through the velocities K D gamma, launched in
  * chunks), 2 = resident (one workgroup per packing runs its whole solve in

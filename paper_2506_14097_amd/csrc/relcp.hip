@@ -304,7 +304,7 @@ struct relcp_ctx {
     bool resident_mode() const {
         if (lcp_mode == 1 || lcp_mode == 3 || lcp_mode == 4) return false;
         if (lcp_mode == 2) return true;
-        return maxpk <= 1024 || (maxpk <= 8192 && nbatch >= 32);
+        return maxpk <= 256 || (maxpk <= 8192 && nbatch >= 32);
     }
     void rows_by_packing_init(int m0);
     void rows_by_packing_append(int m_old, int nv);
