@@ -608,19 +608,21 @@ def colony_workload(args, sizes=(4096, 65536, 131072)):
     every cell dividing at total length 2 into its two halves (jitter
     N(0, 0.01^2) rad), dt 1e-2, overlap_tol 1e-3, lcp_tol 1e-6, skin 0.2.
     The set-up grows the colony to each size ten times faster in a context
-    with skin 0.5 (untimed; the rate is halved whenever the rim would still
-    move more than skin / 2 in a step).  At each size the state moves to a
+    with skin 0.5 and at most 20,000 LCP iterations (untimed; the rate is
+    halved whenever the rim would still move more than skin / 2 in a step or
+    an LCP does not converge).  At each size the state moves to a
     context with the benchmark's skin, takes 5 untimed steps, and a window
     of --colony-steps steps at the benchmarked rate is timed, just after the
     division that reached the size."""
     import torch
     from paper_2506_14097_amd.colony import Colony
-    col = Colony(seed=2, rate=0.01, dt=1e-2, eps=args.eps, tol=args.tol, precision=args.precision, skin=0.5)
+    col = Colony(seed=2, rate=0.01, dt=1e-2, eps=args.eps, tol=args.tol, precision=args.precision, skin=0.5,
+                 lcp_max_iters=20000)
     out = []
     t0 = time.time()
     for N in sizes:
         col.grow_to(N, rate=0.1, log=log)
-        col.reskin(0.2)
+        col.reskin(0.2, lcp_max_iters=0)
         for _ in range(5):
             col.step()
         torch.cuda.synchronize()
@@ -635,7 +637,7 @@ def colony_workload(args, sizes=(4096, 65536, 131072)):
              "max_overlap": float(max(s_["max_overlap"] for s_ in st))}
         log("colony: %s (%.1fs)" % (w, time.time() - t0))
         out.append(w)
-        col.reskin(0.5)
+        col.reskin(0.5, lcp_max_iters=20000)
     col.sim.close()
     return out
 

@@ -28,10 +28,10 @@ class Colony:
     may move a surface point by at most skin / 2."""
 
     def __init__(self, seed=2, *, radius=0.5, length0=1.0, length_div=2.0, rate=0.01, dt=1e-2, eps=1e-3,
-                 tol=1e-6, precision=64, skin=0.2, xi=1.0, jitter=0.01, state=None):
+                 tol=1e-6, precision=64, skin=0.2, xi=1.0, jitter=0.01, lcp_max_iters=0, state=None):
         self.r, self.length_div, self.rate, self.dt = radius, length_div, rate, dt
         self.eps, self.tol, self.jitter = eps, tol, jitter
-        self.xi, self.precision = xi, precision
+        self.xi, self.precision, self.lcp_max_iters = xi, precision, lcp_max_iters
         self.rng = I.rng_for(seed)
         if state is None:
             x = np.zeros((1, 3))
@@ -43,23 +43,27 @@ class Colony:
             x, q, shape, rho = state["x"], state["q"], state["shape"], state["rho_xi"]
             self.l = float(shape[0, 1])
         self.sim = R.Simulation(x, q, np.full(len(x), I.SPHEROCYLINDER, np.int32), shape, rho, np.zeros(3),
-                                precision=precision, skin=skin, planar=True, warm_start=R.WS_PREV)
+                                precision=precision, skin=skin, planar=True, warm_start=R.WS_PREV,
+                                lcp_max_iters=lcp_max_iters)
         self.divisions = 0
 
     @property
     def n(self):
         return self.sim.n
 
-    def reskin(self, skin):
+    def reskin(self, skin, lcp_max_iters=None):
         """Continue from the current state in a new context with another
         skin (a larger one lets a set-up grow faster; warm-start history is
-        not carried over)."""
+        not carried over) and, if given, another LCP iteration cap."""
+        if lcp_max_iters is not None:
+            self.lcp_max_iters = lcp_max_iters
         x, q, _ = self.sim.get_state()
         n = len(x)
         shape = np.tile([self.r, self.l, 0.0], (n, 1))
         self.sim.close()
         self.sim = R.Simulation(x, q, np.full(n, I.SPHEROCYLINDER, np.int32), shape, np.full(n, self.xi),
-                                np.zeros(3), precision=self.precision, skin=skin, planar=True, warm_start=R.WS_PREV)
+                                np.zeros(3), precision=self.precision, skin=skin, planar=True, warm_start=R.WS_PREV,
+                                lcp_max_iters=self.lcp_max_iters)
 
     @property
     def l_div(self):
@@ -83,16 +87,18 @@ class Colony:
     def grow_to(self, n_cells, rate=0.1, log=None):
         """Steps until the colony holds at least n_cells cells: the set-up of
         a timed window, at a faster growth (`rate`).  A step that fails
-        because the rim moved too far for the candidate list (skin) is taken
-        again with half its growth undone and the growth rate halved (never
-        below the benchmarked rate; the failed step left the state
-        unchanged), and the rate recovers by a quarter every 1,000 steps."""
+        because the rim moved too far for the candidate list (skin) or
+        whose LCP did not converge within the iteration cap (an overlap too
+        large for one step) is taken again with half its growth undone and
+        the growth rate halved (never below the benchmarked rate; the
+        failed step left the state unchanged), and the rate recovers by a
+        quarter every 1,000 steps."""
         k, ok, r = 0, 0, rate
         t_log = time.time()
         while self.n < n_cells:
             res = self.step(r, raise_on_error=False)
             back = r * self.dt
-            while res["status"] == R.E_SKIN and not self._divided and back > 1e-6 * self.dt:
+            while res["status"] in (R.E_SKIN, R.E_LCP_MAXITER) and not self._divided and back > 1e-6 * self.dt:
                 back *= 0.5
                 self.sim.grow(-back)
                 self.l -= back

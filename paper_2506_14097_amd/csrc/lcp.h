@@ -114,7 +114,6 @@ struct RowGraphFill {
     int ldb;
     const double *K;   // 9 comps, ld = ldb
     const int *off, *ent;
-    const double *jb;  // per incidence entry e: s (n, tau) of its row at that body (6 values, ent order)
     const int *base;
     double dt;
     size_t cap;        // entry slots allocated
@@ -130,10 +129,6 @@ int rowgraph_slices(int m);
 // *count += the sum of those counts (the entries without padding)
 void launch_rowgraph_width(int m, const int *ia, const int *ib, const int *off, int *width, int *count,
                            hipStream_t s);
-// jb[6 e ..] = s (n, tau) of the row of incidence entry e (s = -1, tau = r_a x n
-// at body a; s = +1, tau = r_b x n at body b): the column of D at that body
-void launch_incidence_jacobian(int m, const int *ent, const double *n, const double *ta, const double *tb, int ldr,
-                               double *jb, hipStream_t s);
 void launch_rowgraph_fill(const RowGraphFill &a, hipStream_t s);
 // One pass of the row-graph LCP loop over m rows with A in G and the
 // diagonal dA.  mode 0: start, gamma0 = max(0, start) (FP64 start rounded to

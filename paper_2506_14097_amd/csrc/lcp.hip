@@ -667,41 +667,50 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_width(int m, const int *_
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_incidence_jacobian(int m2, const int *__restrict__ ent,
-                                                                 const double *__restrict__ n,
-                                                                 const double *__restrict__ ta,
-                                                                 const double *__restrict__ tb, int L,
-                                                                 double *__restrict__ jb) {
-    const int e = blockIdx.x * kThreads + threadIdx.x;
-    if (e >= m2) return;
-    const int en = ent[e], j = en >> 1;
+
+// Entries of the row graph, one thread per incidence entry in CSR order
+// (entry e of body c: row r, side): the thread forms its own column of D at
+// c, s (n_r, tau_r), shares it through LDS with the other entries of c in
+// its block, and writes row r's entries at c: for every other entry j of c,
+// in incidence order, column r_j and value dt J_j . K_c J_e (so row r holds
+// its entries at body a, then those at body b), and, at body b, the row's
+// padding (the row itself, value 0) up to the slice's width.  A column of
+// an entry outside the block (a body that straddles two blocks) is formed
+// again from the rows.  The diagonal A_rr is not stored: a pass takes it
+// from the rows' A_aa.
+__device__ inline void column_of(const RowGraphFill &A, int en, double J[6]) {
+    const int L = A.ldr, j = en >> 1;
     const double s = (en & 1) ? 1.0 : -1.0;
-    const double *t = (en & 1) ? tb : ta;
-    double *o = jb + 6 * (size_t)e;
-    o[0] = s * n[j];
-    o[1] = s * n[L + j];
-    o[2] = s * n[2 * L + j];
-    o[3] = s * t[j];
-    o[4] = s * t[L + j];
-    o[5] = s * t[2 * L + j];
+    const double *t = (en & 1) ? A.tb : A.ta;
+    J[0] = s * A.n[j];
+    J[1] = s * A.n[L + j];
+    J[2] = s * A.n[2 * L + j];
+    J[3] = s * t[j];
+    J[4] = s * t[L + j];
+    J[5] = s * t[2 * L + j];
 }
 
-// Entries of row r: for each of its bodies c (a, then b) and each other row
-// j at c (incidence order), dt J_r^c . (K_c J_j^c) with J the column of D at
-// c, then padding entries (the row itself, value 0).  The diagonal A_rr is
-// not stored: a pass takes it from the rows' A_aa.  Two threads per row, one
-// per body: a block covers kFillRows rows, its first half of waves at body
-// a (slots from 0), the second at body b (slots after the deg_a - 1 of body
-// a, then the padding); each wave is one slice.
-constexpr int kFillRows = kThreads / 2;
-__global__ void __launch_bounds__(kThreads) k_rowgraph_fill(RowGraphFill A) {
-    const int side = threadIdx.x / kFillRows;
-    const int r = blockIdx.x * kFillRows + (threadIdx.x & (kFillRows - 1));
-    if (r >= A.m) return;
+__global__ void __launch_bounds__(kThreads) k_rowgraph_fill_entries(RowGraphFill A) {
+    __shared__ double shJ[6][kThreads];
+    const int E0 = blockIdx.x * kThreads;
+    const int e = E0 + threadIdx.x;
+    const int m2 = 2 * A.m;
+    const bool act = e < m2;
+    int en = 0, r = 0, side = 0, c = 0;
+    double J[6] = {0, 0, 0, 0, 0, 0};
+    if (act) {
+        en = A.ent[e];
+        r = en >> 1;
+        side = en & 1;
+        c = side ? A.ib[r] : A.ia[r];
+        column_of(A, en, J);
+    }
+#pragma unroll
+    for (int t = 0; t < 6; ++t) shJ[t][threadIdx.x] = J[t];
+    __syncthreads();
+    if (!act) return;
     const int lane = r & (RELCP_WAVE - 1), sl = r / RELCP_WAVE;
     const int b0 = A.base[sl], w = A.base[sl + 1] - b0;
-    const int L = A.ldr, lb = A.ldb;
-    const d3 nr = mk(A.n[r], A.n[L + r], A.n[2 * L + r]);
     if (r == 0 && side == 0) {
         // the width pass and the scan are complete: report and clear its counter
         A.report[0] = A.base[(A.m + RELCP_WAVE - 1) / RELCP_WAVE];
@@ -712,52 +721,44 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_fill(RowGraphFill A) {
         A.report[2] = 1;
         return;
     }
-    // the output does not alias the inputs: the gathers of several entries
-    // can be in flight before their stores
-    const double *__restrict__ jb = A.jb;
-    const int *__restrict__ ent = A.ent;
     int *__restrict__ col = A.col;
     double *__restrict__ v64 = A.val64;
     float *__restrict__ v32 = A.val32;
-    constexpr int kU = 4;
-    const int c = side ? A.ib[r] : A.ia[r];
+    const int lb = A.ldb;
+    const double sr = side ? 1.0 : -1.0;
+    // K_c applied to this row's column (sign included)
+    const double *K = A.K;
+    const d3 nr = mk(sr * J[0], sr * J[1], sr * J[2]);
+    const d3 ur = mk(sr * J[3], sr * J[4], sr * J[5]);
+    const d3 Kn = mk(sr * K[c] * nr.x, sr * K[lb + c] * nr.y, sr * K[2 * lb + c] * nr.z);
+    const sym3 Kr{K[3 * lb + c], K[4 * lb + c], K[5 * lb + c], K[6 * lb + c], K[7 * lb + c], K[8 * lb + c]};
+    const d3 Ku = sr * mul(Kr, ur);
     int k = 0;
     if (side) {
         const int a = A.ia[r];
         k = A.off[a + 1] - A.off[a] - 1;  // the slots of body a's other rows
     }
-    const double *tr = side ? A.tb : A.ta;
-    const double sr = side ? 1.0 : -1.0;
-    const d3 ur = mk(tr[r], tr[L + r], tr[2 * L + r]);
-    const double *K = A.K;
-    // K_c applied to this row's column (sign included)
-    const d3 Kn = mk(sr * K[c] * nr.x, sr * K[lb + c] * nr.y, sr * K[2 * lb + c] * nr.z);
-    const sym3 Kr{K[3 * lb + c], K[4 * lb + c], K[5 * lb + c], K[6 * lb + c], K[7 * lb + c], K[8 * lb + c]};
-    const d3 Ku = sr * mul(Kr, ur);
-    const int e1 = A.off[c + 1];
-    for (int e = A.off[c]; e < e1; e += kU) {
-        double J[kU][6];
-        int cj[kU];
+    const int j0 = A.off[c], j1 = A.off[c + 1];
+    for (int j = j0; j < j1; ++j) {
+        if (j == e) continue;
+        double Jj[6];
+        int cj;
+        if (j >= E0 && j < E0 + kThreads) {
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int eu = e + u < e1 ? e + u : e;
-            const double *Jp = jb + 6 * (size_t)eu;
-#pragma unroll
-            for (int t = 0; t < 6; ++t) J[u][t] = Jp[t];
-            cj[u] = ent[eu] >> 1;
+            for (int t = 0; t < 6; ++t) Jj[t] = shJ[t][j - E0];
+            cj = A.ent[j] >> 1;
+        } else {
+            const int ej = A.ent[j];
+            column_of(A, ej, Jj);
+            cj = ej >> 1;
         }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            if (e + u < e1 && cj[u] != r) {
-                const double v = A.dt * (J[u][0] * Kn.x + J[u][1] * Kn.y + J[u][2] * Kn.z + J[u][3] * Ku.x +
-                                         J[u][4] * Ku.y + J[u][5] * Ku.z);
-                const size_t at = (size_t)RELCP_WAVE * (b0 + k) + lane;
-                col[at] = cj[u];
-                v64[at] = v;
-                v32[at] = (float)v;
-                ++k;
-            }
-        }
+        const double v =
+            A.dt * (Jj[0] * Kn.x + Jj[1] * Kn.y + Jj[2] * Kn.z + Jj[3] * Ku.x + Jj[4] * Ku.y + Jj[5] * Ku.z);
+        const size_t at = (size_t)RELCP_WAVE * (b0 + k) + lane;
+        col[at] = cj;
+        v64[at] = v;
+        v32[at] = (float)v;
+        ++k;
     }
     if (!side) return;
     for (; k < w; ++k) {
@@ -1206,15 +1207,9 @@ void launch_rowgraph_width(int m, const int *ia, const int *ib, const int *off, 
                        width, count);
 }
 
-void launch_incidence_jacobian(int m, const int *ent, const double *n, const double *ta, const double *tb, int ldr,
-                               double *jb, hipStream_t s) {
-    if (m > 0)
-        launch_k(k_incidence_jacobian, dim3(nblk(2 * (long long)m, kThreads)), dim3(kThreads), 0, s, 2 * m,
-                           ent, n, ta, tb, ldr, jb);
-}
 
 void launch_rowgraph_fill(const RowGraphFill &a, hipStream_t s) {
-    if (a.m > 0) launch_k(k_rowgraph_fill, dim3(nblk(a.m, kFillRows)), dim3(kThreads), 0, s, a);
+    if (a.m > 0) launch_k(k_rowgraph_fill_entries, dim3(nblk(2 * (long long)a.m, kThreads)), dim3(kThreads), 0, s, a);
 }
 
 template <typename T>

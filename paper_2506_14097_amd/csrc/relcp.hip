@@ -253,7 +253,7 @@ struct relcp_ctx {
     // 3 = row graph (A assembled over rows, one pass per iteration)
     int lcp_mode = 0, res_block = 256, res_lds = 1;
     DBuf<int> rg_width, rg_base, rg_col, rg_flags;  // flags: [0] entry count, [1] overflow
-    DBuf<double> rg_val64, rg_jb;
+    DBuf<double> rg_val64;
     DBuf<float> rg_val32;
     DBuf<RowStep<double>> z64;
     DBuf<RowStep<float>> z32;
@@ -352,7 +352,7 @@ struct relcp_ctx {
         pk_state.release();
         mlp_w.release(); feat.release(); rowscale.release();
         rg_width.release(); rg_base.release(); rg_col.release(); rg_flags.release(); rg_val64.release();
-        rg_jb.release(); rg_val32.release(); z64.release(); z32.release(); zg64.release(); zg32.release();
+        rg_val32.release(); z64.release(); z32.release(); zg64.release(); zg32.release();
         lcpdev64.release(); lcpdev32.release();
         for (auto &ge : spmv_graph)
             if (ge) (void)hipGraphExecDestroy(ge);
@@ -941,12 +941,13 @@ void relcp_ctx::rg_reserve(size_t slots) {
     rg_cap = std::min(rg_col.cap, std::min(rg_val64.cap, rg_val32.cap));
 }
 
-// Row graph of the current rows: slice widths and their scan, the columns of
-// D in incidence order, then the entries.  Nothing is read back here: the
+// Row graph of the current rows: slice widths and their scan, then the
+// entries (one thread per incidence entry).  Nothing is read back here: the
 // entry slots are sized from an estimate (twice the current need seen so
-// far, at least 16 per row) and the fill flags an overflow, which the solve
-// checks at its first read-back (then re-sizes, rebuilds and restarts).
-// buffers of the row graph's widths, entry counter and columns of D
+// far, at first RELCP_RG_SLOTS_PER_ROW per row) and the fill flags an
+// overflow, which the solve checks at its first read-back (then re-sizes,
+// rebuilds and restarts).
+// buffers of the row graph's widths and entry counter
 void relcp_ctx::rg_prepare() {
     const int ns = rowgraph_slices(m);
     rg_width.ensure(ns + 1);
@@ -955,7 +956,7 @@ void relcp_ctx::rg_prepare() {
         rg_flags.ensure(1);
         HIP_OK(hipMemsetAsync(rg_flags.p, 0, sizeof(int), stream));  // entry counter, cleared by each fill
     }
-    rg_jb.ensure(12 * (size_t)std::max(m, 1));
+
 }
 
 void relcp_ctx::build_rowgraph(double dt) {
@@ -968,11 +969,11 @@ void relcp_ctx::build_rowgraph(double dt) {
         timed(8, [&] { launch_rowgraph_width(m, ria.p, rib.p, csr_off.p, rg_width.p, rg_flags.p, stream); });
     }
     rg_pre = false;
-    timed(8, [&] { launch_incidence_jacobian(m, csr_ent.p, rn64.p, rta64.p, rtb64.p, ldr, rg_jb.p, stream); });
+
     exclusive_scan(rg_width.p, rg_base.p, ns + 1, nullptr, scan_scratch, stream);
     RowGraphFill f{};
     f.m = m; f.ldr = ldr; f.ia = ria.p; f.ib = rib.p; f.n = rn64.p; f.ta = rta64.p; f.tb = rtb64.p;
-    f.ldb = n; f.K = K.p; f.off = csr_off.p; f.ent = csr_ent.p; f.jb = rg_jb.p; f.base = rg_base.p; f.dt = dt;
+    f.ldb = n; f.K = K.p; f.off = csr_off.p; f.ent = csr_ent.p; f.base = rg_base.p; f.dt = dt;
     f.cap = rg_cap; f.count = rg_flags.p; f.report = int_d + 4;
     f.col = rg_col.p; f.val64 = rg_val64.p; f.val32 = rg_val32.p;
     timed(8, [&] { launch_rowgraph_fill(f, stream); });  // reports slots, entries and overflow, read after the solve's first sync
