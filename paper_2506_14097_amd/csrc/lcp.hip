@@ -21,6 +21,7 @@
 // D^T vc -> g' with the step-size reductions.  The last block of the gather
 // finishes the reductions in a fixed order, so the result does not depend
 // on block scheduling.
+#include <climits>
 #include <type_traits>
 
 #include "lcp.h"
@@ -186,7 +187,11 @@ __global__ void __launch_bounds__(256) k_csr_fill(int m, const int *__restrict__
 }
 
 // Order each body's list by entry (row index) so summation order is fixed,
-// and clear the body's count and cursor for the next build.
+// and clear the body's count and cursor for the next build.  Lists of up to
+// kSortRegs entries (nearly all) are sorted in registers by odd-even
+// transposition, all their loads in flight together; longer ones in place.
+// Entries are distinct, so either way gives the one sorted order.
+constexpr int kSortRegs = 8;
 __global__ void k_csr_sort(int nb, const int *__restrict__ off, int *__restrict__ ent, int *__restrict__ cnt,
                            int *__restrict__ cursor) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -194,6 +199,23 @@ __global__ void k_csr_sort(int nb, const int *__restrict__ off, int *__restrict_
     cnt[i] = 0;
     cursor[i] = 0;
     int lo = off[i], hi = off[i + 1];
+    if (hi - lo <= kSortRegs) {
+        int v[kSortRegs];
+#pragma unroll
+        for (int k = 0; k < kSortRegs; ++k) v[k] = lo + k < hi ? ent[lo + k] : INT_MAX;
+#pragma unroll
+        for (int rd = 0; rd < kSortRegs; ++rd)
+#pragma unroll
+            for (int k = rd & 1; k + 1 < kSortRegs; k += 2) {
+                const int a = min(v[k], v[k + 1]), b = max(v[k], v[k + 1]);
+                v[k] = a;
+                v[k + 1] = b;
+            }
+#pragma unroll
+        for (int k = 0; k < kSortRegs; ++k)
+            if (lo + k < hi) ent[lo + k] = v[k];
+        return;
+    }
     for (int k = lo + 1; k < hi; ++k) {
         int v = ent[k], j = k - 1;
         while (j >= lo && ent[j] > v) {

@@ -248,6 +248,7 @@ struct relcp_ctx {
     // after the stream is synchronised) and their device addresses
     PgdState *pst_h = nullptr, *pst_d = nullptr;  // fin and the done slot
     int last_iters[2] = {8, 8};  // previous solve's iteration count (FP32, FP64)
+    int zero_run[2] = {0, 0};    // solves in a row that converged at their start pass
     // LCP execution: mode 0 = automatic, 1 = grid (two passes per iteration
     // over all rows), 2 = resident (one workgroup per packing, one launch),
     // 3 = row graph (A assembled over rows, one pass per iteration)
@@ -1197,7 +1198,10 @@ void relcp_ctx::rg_start(const RowsT<T> &R, double dt, double tol, const double 
     // short first chunk costs a wait and, in a step, the work launched behind
     // it, while a spare pass returns at once
     st.chunk = std::max(2, std::min(64, last_iters[pk] + std::max(3, last_iters[pk] / 4) + 1));
-    if (last_iters[pk] == 0) st.chunk = 2;  // a polish that last converged at its start
+    // a polish that last converged at its start: the pass that sees it and
+    // a spare one; only the first once it has done so several times in a row
+    // (a miss costs a wait)
+    if (last_iters[pk] == 0) st.chunk = zero_run[pk] >= 4 ? 1 : 2;
     // over many blocks the partial sums are reduced once per pass by a
     // separate launch instead of by every block
     st.pass_mode = B.C.nbg >= reduce_split_blocks ? 2 : 1;
@@ -1268,6 +1272,7 @@ int relcp_ctx::rg_finish(const RowsT<T> &R, const BodiesT<T> &Bd, double tol, in
     iters = pst_h[2 * pk].iter;
     res = pst_h[2 * pk].res;
     last_iters[pk] = iters;
+    zero_run[pk] = iters == 0 ? zero_run[pk] + 1 : 0;
     // passes past the last iteration only reduced (or returned at once):
     // timed apart from the iteration passes
     for (auto &pe : pass_ev)
