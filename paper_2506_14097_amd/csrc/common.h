@@ -185,9 +185,18 @@ void exclusive_scan(const int *in, int *out, int n, int *total_dev, DBuf<int> &s
 // them here.  out must not alias flags.  rep (optional): a tail report
 // (report.h) that the compaction's last workgroup writes after the count;
 // returns whether it was written (false when n <= 0: nothing was launched).
+// pos (optional, n entries): item i's index in out, or -1 for an unset flag.
 struct TailReport;
 int flag_groups(int n);
 bool compact_flags(const int *flags, int n, const int *bcount, int *out, int *total_dev, DBuf<int> &scratch,
-                   hipStream_t s, const TailReport *rep = nullptr);
+                   hipStream_t s, const TailReport *rep = nullptr, int *pos = nullptr);
+// scan.hip: lists of n items (off, ent: entries (j << 1) | side, as the
+// incidence lists) keeping the entries whose j has pos[j] >= 0, renumbered
+// (pos[j] << 1) | side, each list in its own order: cnt (n) the kept counts,
+// off (n + 1) and ent (the kept entries) the filtered lists; pairs_out (a
+// device int, or null) <- the sum over items of c (c - 1), c the kept count.
+// scratch grows as needed.
+void filter_lists(int n, const int *boff, const int *bent, const int *pos, int *cnt, int *off, int *ent,
+                  DBuf<int> &scratch, hipStream_t s, int *pairs_out = nullptr);
 
 }  // namespace relcp

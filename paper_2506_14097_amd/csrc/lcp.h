@@ -126,7 +126,8 @@ struct RowGraphFill {
 
 int rowgraph_slices(int m);
 // width[s] = largest count of other rows at a row's two bodies in slice s;
-// *count += the sum of those counts (the entries without padding)
+// *count += the sum of those counts (the entries without padding), unless
+// count is null
 void launch_rowgraph_width(int m, const int *ia, const int *ib, const int *off, int *width, int *count,
                            hipStream_t s);
 void launch_rowgraph_fill(const RowGraphFill &a, hipStream_t s);

@@ -685,7 +685,7 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_width(int m, const int *_
     if (threadIdx.x == 0) {
         int t = 0;
         for (int k = 0; k < kWaves; ++k) t += bsum[k];
-        if (t) atomicAdd(count, t);
+        if (t && count) atomicAdd(count, t);
     }
 }
 

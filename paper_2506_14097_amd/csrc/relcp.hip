@@ -77,12 +77,12 @@ __global__ void k_scale(int n, double *__restrict__ x, int nbox, double *__restr
     if (i < nbox) box[i] *= s;
 }
 
-int env_int(const char *name, int dflt) {
+int env_int(const char *name, int dflt, int lo = 1) {
     const char *v = std::getenv(name);
     if (!v || !*v) return dflt;
     char *end = nullptr;
     const long x = std::strtol(v, &end, 10);
-    return (end && *end == 0 && x > 0 && x < (1L << 30)) ? (int)x : dflt;
+    return (end && *end == 0 && x >= lo && x < (1L << 30)) ? (int)x : dflt;
 }
 
 struct Timer {
@@ -166,6 +166,14 @@ struct relcp_ctx {
     DBuf<double> rn64, rta64, rtb64, rqv64, rdA64, rgam64, rg64, rphi64;
     DBuf<float> rn32, rta32, rtb32, rqv32, rdA32, rgam32, rg32;
     DBuf<int> csr_cnt, csr_off, csr_cur, csr_ent;
+    // incidence lists of the candidate pairs (entries (pair << 1) | side, each
+    // body's in pair order), built once per candidate list; the step's first
+    // rows are the selected pairs in pair order, so their lists are these
+    // lists filtered through prow (the pair's row, or -1), already in row
+    // order: no atomics and no sort per step
+    DBuf<int> pcsr_cnt, pcsr_off, pcsr_ent, prow, fl_cnt;
+    bool pcsr_valid = false;
+    const int *pcsr_clear = nullptr;  // pcsr_cnt while its counters are known to be zero
 
     // LCP state and reductions
     DBuf<PgdState> pst;
@@ -273,6 +281,9 @@ struct relcp_ctx {
     // first estimate of row-graph entry slots per row (RELCP_RG_SLOTS_PER_ROW);
     // an assembly that does not fit is re-sized and its solve restarted
     int rg_slots_per_row = env_int("RELCP_RG_SLOTS_PER_ROW", 16);
+    // the first rows' incidence lists filtered from the candidate pairs' (1)
+    // or built from the rows (0) (RELCP_FIRST_LISTS); the same lists
+    int first_lists = env_int("RELCP_FIRST_LISTS", 1, 0);
     // an FP32 solve whose residual has not halved in this many iterations
     // stops (its rounding floor is above the tolerance) and the FP64
     // polish continues from its last iterate; fixed-iteration runs never stop
@@ -295,6 +306,7 @@ struct relcp_ctx {
     void rg_reserve(size_t slots);
     void rg_prepare();
     bool rg_pre = false;  // the incidence build made this graph's slice widths
+    bool rg_counted = false;  // the incidence build stored this graph's entry count
     int maxpk = 0;                       // bodies of the largest packing
     DBuf<int> boff_d, roff, rlist, rlist2, rcnt, rE;
     DBuf<PgdState> pk_state;
@@ -336,7 +348,8 @@ struct relcp_ctx {
         for (auto *b : fs) b->release();
         DBuf<int> *is[] = {&kind, &body_batch, &perm_d, &body_cell, &cell_count, &cell_start, &cell_cursor, &cell_items,
                            &pair_count, &pair_off, &pa, &pb, &pflag, &pcnt, &sel, &prev_a, &prev_b, &ria, &rib,
-                           &rpair, &rrec, &csr_cnt, &csr_off, &csr_cur, &csr_ent, &scan_scratch, &dtotal};
+                           &rpair, &rrec, &csr_cnt, &csr_off, &csr_cur, &csr_ent, &scan_scratch, &dtotal,
+                           &pcsr_cnt, &pcsr_off, &pcsr_ent, &prow, &fl_cnt};
         for (auto *b : is) b->release();
         grids.release();
         keys.release();
@@ -368,6 +381,7 @@ struct relcp_ctx {
     void broadphase(const double *xs, double skin_, bool bound = false);
     void build_rows(int nsel, int rec, const double *snsd, const double *vc, bool warm, double dt);
     void rebuild_csr();
+    void first_rows_csr();
     void warm_start_rows(int m0, double dt);
     template <typename T>
     int solve(double dt, double tol, int &iters, double &res);
@@ -556,6 +570,8 @@ static uint64_t spread3(uint64_t v) {
 void relcp_ctx::upload_bodies(const relcp_bodies *B, const relcp_shapes *S) {
     n = B->n;
     csr_clear = nullptr;
+    pcsr_clear = nullptr;
+    pcsr_valid = false;
     log_valid = false;
     vl_valid = false;
     prev_is_list = false;
@@ -813,6 +829,7 @@ void relcp_ctx::broadphase(const double *xs, double skin_, bool bound) {
         launch_pairs(true, N, xs, N, Rb.p, body_batch.p, grids.p, body_cell.p, cell_start.p, cell_count.p,
                      cell_items.p, skin_, pair_count.p, pair_off.p, pa.p, pb.p, ldp, stream, bound ? &shp : nullptr);
     });
+    pcsr_valid = false;
 }
 
 void relcp_ctx::candidate_pairs(relcp_step_stats &S) {
@@ -894,6 +911,7 @@ void relcp_ctx::rebuild_csr() {
     // entry counter: clear it)
     if (rg_pre && rg_flags.p) HIP_OK(hipMemsetAsync(rg_flags.p, 0, sizeof(int), stream));
     rg_pre = rowgraph_mode() && m > 0;
+    rg_counted = false;
     if (rg_pre) {
         rg_prepare();
         rgo = CsrRowGraphOut{rg_width.p, rg_flags.p};
@@ -901,6 +919,40 @@ void relcp_ctx::rebuild_csr() {
     launch_csr(n, m, ria.p, rib.p, csr_cnt.p, csr_off.p, csr_cnt.p + (n + 1), csr_ent.p, cleared, scan_scratch,
                stream, rg_pre ? &rgo : nullptr);
     csr_clear = csr_cnt.p;  // the build's last pass clears the counters again
+}
+
+// Incidence lists of the step's first rows (the selected candidate pairs,
+// row k = the k-th selected pair, prow filled by the compaction): the
+// candidate pairs' lists (built when the candidate list changed) filtered
+// through prow.  The same lists as rebuild_csr builds, bit for bit; the
+// row graph's slice widths come from its own pass.
+void relcp_ctx::first_rows_csr() {
+    if (!pcsr_valid) {
+        pcsr_cnt.ensure(2 * (size_t)(n + 1));
+        pcsr_off.ensure(n + 1);
+        pcsr_ent.ensure(2 * (size_t)std::max(np, 1));
+        launch_csr(n, np, pa.p, pb.p, pcsr_cnt.p, pcsr_off.p, pcsr_cnt.p + (n + 1), pcsr_ent.p,
+                   pcsr_clear == pcsr_cnt.p, scan_scratch, stream, nullptr);
+        pcsr_clear = pcsr_cnt.p;
+        pcsr_valid = true;
+    }
+    rg_valid = false;
+    csr_off.ensure(n + 1);
+    csr_ent.ensure(2 * (size_t)std::max(m, 1));
+    fl_cnt.ensure(n + 1);
+    // in the row-graph mode the filter also stores the graph's entry count
+    // (the ordered pairs of rows sharing a body) in the entry counter, so
+    // the width pass need not add it up
+    rg_pre = false;
+    rg_counted = rowgraph_mode() && m > 0;
+    if (rg_counted) rg_prepare();
+    if (np > 0) {
+        filter_lists(n, pcsr_off.p, pcsr_ent.p, prow.p, fl_cnt.p, csr_off.p, csr_ent.p, scan_scratch, stream,
+                     rg_counted ? rg_flags.p : nullptr);
+    } else {
+        HIP_OK(hipMemsetAsync(csr_off.p, 0, (n + 1) * sizeof(int), stream));
+        if (rg_counted) HIP_OK(hipMemsetAsync(rg_flags.p, 0, sizeof(int), stream));
+    }
 }
 
 // Features of the iteration-0 rows (their multipliers hold the previous
@@ -966,10 +1018,14 @@ void relcp_ctx::build_rowgraph(double dt) {
     rg_reserve(std::max<size_t>((size_t)RELCP_WAVE * ns * rg_slots_per_row, 64));
     int_h[4] = int_h[5] = int_h[6] = 0;  // slots / 64, entries, overflow (written by the fill)
     if (!rg_pre) {
-        // widths not made by the incidence build (a rebuild)
-        timed(8, [&] { launch_rowgraph_width(m, ria.p, rib.p, csr_off.p, rg_width.p, rg_flags.p, stream); });
+        // widths not made by the incidence build (a rebuild, or the first
+        // rows' filtered lists, which counted the entries)
+        timed(8, [&] {
+            launch_rowgraph_width(m, ria.p, rib.p, csr_off.p, rg_width.p, rg_counted ? nullptr : rg_flags.p, stream);
+        });
     }
     rg_pre = false;
+    rg_counted = false;
 
     exclusive_scan(rg_width.p, rg_base.p, ns + 1, nullptr, scan_scratch, stream);
     RowGraphFill f{};
@@ -1424,7 +1480,9 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     if (hint_ok) sa.hint = snsdt.p + ldp;
     int_h[0] = -1;  // no GPU work in flight writes it: the compaction below sets the count
     timed(2, [&] { launch_snsd_pairs(sa, stream); });
-    compact_flags(pflag.p, np, pcnt.p, sel.p, int_d, scan_scratch, stream);  // count -> int_h[0]
+    // count -> int_h[0]; each pair's row (or -1) -> prow
+    prow.ensure(std::max(np, 1));
+    compact_flags(pflag.p, np, pcnt.p, sel.p, int_d, scan_scratch, stream, nullptr, prow.p);
     const int m0 = wait_mapped(int_h, -1);
     if (m0 < 0 || m0 > np) throw Error{RELCP_E_DEVICE, "bad contact count"};
     t_narrow += tm.ms();
@@ -1434,7 +1492,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     const bool need_feat = learned || log_on;
     log_valid = false;
     build_rows(m0, 0, snsd0.p, nullptr, warm_start == RELCP_WS_PREV || need_feat, dt);
-    rebuild_csr();
+    if (first_lists) first_rows_csr(); else rebuild_csr();
     if (need_feat) warm_start_rows(m0, dt);
     if (resident_mode()) rows_by_packing_init(m0);
     t_other += tm.ms();

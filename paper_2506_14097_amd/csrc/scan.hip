@@ -150,7 +150,8 @@ __global__ void __launch_bounds__(kThreads) k_count_flags(const int *__restrict_
 __global__ void __launch_bounds__(kThreads) k_compact_tiles(const int *__restrict__ flags, int n,
                                                             const int *__restrict__ bcount,
                                                             const int *__restrict__ boffs, int *__restrict__ out,
-                                                            int *__restrict__ total, TailReport rep) {
+                                                            int *__restrict__ total, TailReport rep,
+                                                            int *__restrict__ pos) {
     __shared__ int sh[kThreads / RELCP_WAVE];
     __shared__ int wsum[kThreads / RELCP_WAVE];
     const int b = blockIdx.x;
@@ -167,6 +168,11 @@ __global__ void __launch_bounds__(kThreads) k_compact_tiles(const int *__restric
 #pragma unroll
     for (int k = 0; k < kItems; ++k)
         if (set[k]) out[v[k]] = (int)(base + k);
+    if (pos) {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k)
+            if (base + k < n) pos[base + k] = set[k] ? v[k] : -1;
+    }
     if (b != (int)gridDim.x - 1) return;
     if (total && threadIdx.x == 0) *total = off + tot;
     // the count is stored (thread 0 before its fence): the tail report, whose
@@ -248,7 +254,7 @@ int scratch_ptr(int **out) {
 }  // namespace
 
 bool compact_flags(const int *flags, int n, const int *bcount, int *out, int *total_dev, DBuf<int> &scratch,
-                   hipStream_t s, const TailReport *rep) {
+                   hipStream_t s, const TailReport *rep, int *pos) {
     if (n <= 0) {
         if (total_dev) HIP_OK(hipMemsetAsync(total_dev, 0, sizeof(int), s));
         return false;
@@ -274,8 +280,105 @@ bool compact_flags(const int *flags, int n, const int *bcount, int *out, int *to
     }
     TailReport none{};
     hipLaunchKernelGGL(k_compact_tiles, dim3(nt), dim3(kThreads), 0, s, flags, n, bcount, boffs, out, total_dev,
-                       rep ? *rep : none);
+                       rep ? *rep : none, pos);
     return rep != nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// filtered incidence lists
+// ---------------------------------------------------------------------------
+// The kept entries of item i's list (pos of the entry's index >= 0), up to
+// kFiltU entries per round with all their loads in flight.
+constexpr int kFiltU = 4;
+template <bool WRITE>
+__device__ inline int filter_list(const int *__restrict__ boff, const int *__restrict__ bent,
+                                  const int *__restrict__ pos, int i, int *__restrict__ ent, int at) {
+    const int j0 = boff[i], j1 = boff[i + 1];
+    int c = 0;
+    for (int j = j0; j < j1; j += kFiltU) {
+        int e[kFiltU], q[kFiltU];
+#pragma unroll
+        for (int u = 0; u < kFiltU; ++u) e[u] = j + u < j1 ? bent[j + u] : -1;
+#pragma unroll
+        for (int u = 0; u < kFiltU; ++u) q[u] = e[u] >= 0 ? pos[e[u] >> 1] : -1;
+#pragma unroll
+        for (int u = 0; u < kFiltU; ++u) {
+            if (q[u] < 0) continue;
+            if (WRITE) ent[at + c] = (q[u] << 1) | (e[u] & 1);
+            ++c;
+        }
+    }
+    return c;
+}
+
+// one item per thread: its kept count c, and per block of kThreads items
+// the sum of c (sums[b]) and of c (c - 1) (sums[nb + b]: ordered pairs of
+// kept entries of one item)
+__global__ void __launch_bounds__(kThreads) k_filter_count(int n, const int *__restrict__ boff,
+                                                           const int *__restrict__ bent, const int *__restrict__ pos,
+                                                           int *__restrict__ cnt, int *__restrict__ sums) {
+    __shared__ int sh[kThreads / RELCP_WAVE];
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    int c = 0;
+    if (i < n) {
+        c = filter_list<false>(boff, bent, pos, i, nullptr, 0);
+        cnt[i] = c;
+    }
+    const int t = block_total<kThreads>(c, sh);
+    const int tp = block_total<kThreads>(c * (c - 1), sh);
+    if (threadIdx.x == 0) {
+        sums[blockIdx.x] = t;
+        sums[gridDim.x + blockIdx.x] = tp;
+    }
+}
+
+// offsets (the counts of the blocks before this one, then a block scan) and
+// the kept entries, renumbered; off[n] = the total
+__global__ void __launch_bounds__(kThreads) k_filter_fill(int n, const int *__restrict__ boff,
+                                                          const int *__restrict__ bent, const int *__restrict__ pos,
+                                                          const int *__restrict__ cnt, const int *__restrict__ sums,
+                                                          const int *__restrict__ offs, int *__restrict__ off,
+                                                          int *__restrict__ ent, int *__restrict__ pairs_out) {
+    __shared__ int sh[kThreads / RELCP_WAVE];
+    __shared__ int wsum[kThreads / RELCP_WAVE];
+    const int b = blockIdx.x;
+    const int i = b * kThreads + threadIdx.x;
+    const int c = i < n ? cnt[i] : 0;
+    if (pairs_out && b == (int)gridDim.x - 1) {
+        // the last block adds up the pair counts of all blocks
+        int acc = 0;
+        for (int k = threadIdx.x; k < (int)gridDim.x; k += kThreads) acc += sums[gridDim.x + k];
+        const int tp = block_total<kThreads>(acc, sh);
+        if (threadIdx.x == 0) *pairs_out = tp;
+    }
+    const int toff = tile_offset(sums, offs, b, sh);
+    const int inc = wave_incl_scan(c);
+    const int lane = threadIdx.x & (RELCP_WAVE - 1), w = threadIdx.x / RELCP_WAVE;
+    if (lane == RELCP_WAVE - 1) wsum[w] = inc;
+    __syncthreads();
+    int woff = 0;
+#pragma unroll
+    for (int k = 0; k < kThreads / RELCP_WAVE; ++k) woff += k < w ? wsum[k] : 0;
+    const int at = toff + woff + inc - c;
+    if (i >= n) return;
+    off[i] = at;
+    if (i == n - 1) off[n] = at + c;
+    if (c) filter_list<true>(boff, bent, pos, i, ent, at);
+}
+
+void filter_lists(int n, const int *boff, const int *bent, const int *pos, int *cnt, int *off, int *ent,
+                  DBuf<int> &scratch, hipStream_t s, int *pairs_out) {
+    if (n <= 0) return;
+    const int nb = (n + kThreads - 1) / kThreads;
+    // past kDirect blocks the block counts are scanned first (a block would
+    // otherwise sum all the counts before it)
+    const bool scan_first = nb > kDirect;
+    scratch.ensure(2 * (size_t)nb + (scan_first ? (size_t)nb + scan_scratch_need(nb) : 0));
+    int *sums = scratch.p, *offs = scan_first ? scratch.p + 2 * (size_t)nb : nullptr;
+    hipLaunchKernelGGL(k_filter_count, dim3(nb), dim3(kThreads), 0, s, n, boff, bent, pos, cnt, sums);
+    if (scan_first) scan_into(sums, offs, nb, nullptr, offs + nb, s);
+    hipLaunchKernelGGL(k_filter_fill, dim3(nb), dim3(kThreads), 0, s, n, boff, bent, pos, cnt, sums, offs, off, ent,
+                       pairs_out);
 }
 
 }  // namespace relcp
