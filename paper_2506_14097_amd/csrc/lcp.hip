@@ -33,16 +33,17 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / RELCP_WAVE;
+// candidate-pair groups of kThreads up to which the iteration-0 rows are
+// selected and built in one pass (each block sums the groups before it)
+constexpr int kSelectGroupsMax = 4096;
 
 inline int nblk(long long n, int t) { return (int)((n + t - 1) / t); }
 
 // ---------------------------------------------------------------------------
 // rows
 // ---------------------------------------------------------------------------
-__global__ void k_rows_build(RowBuildArgs A) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.nsel) return;
-    int pr = A.sel[k];
+// Row m0 + k of pair pr.
+__device__ inline void build_row(const RowBuildArgs &A, int k, int pr) {
     int a = A.pa[pr], b = A.pb[pr];
     int r = A.m0 + k;
     const int lp = A.ldp;
@@ -109,6 +110,62 @@ __global__ void k_rows_build(RowBuildArgs A) {
     A.gam64[r] = g0;
     A.gam32[r] = (float)g0;
     A.phi64[r] = phi;
+}
+
+__global__ void k_rows_build(RowBuildArgs A) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= A.nsel) return;
+    build_row(A, k, A.sel[k]);
+}
+
+// The iteration-0 rows straight from the narrowphase's flags, without a
+// separate compaction: one thread per candidate pair, one block per group of
+// kThreads pairs (the groups whose set flags the narrowphase counted).  A
+// pair's row is the number of set flags before it (the counts of the groups
+// before the block, then a scan over the block), as the compaction numbers
+// them; a selected pair builds its row there.  Also sel (row -> pair), pos
+// (pair -> row, or -1) and, from the last block, the row count.
+__global__ void __launch_bounds__(kThreads) k_select_rows(RowBuildArgs A, int np, const int *__restrict__ flags,
+                                                          const int *__restrict__ gcount, int *__restrict__ sel,
+                                                          int *__restrict__ pos, int *__restrict__ total) {
+    __shared__ int sh[kWaves];
+    __shared__ int goff;
+    const int b = blockIdx.x;
+    const int p = b * kThreads + threadIdx.x;
+    const int lane = threadIdx.x & (RELCP_WAVE - 1), w = threadIdx.x / RELCP_WAVE;
+    const int f = p < np && flags[p] ? 1 : 0;
+    // set flags of the groups before this one
+    int acc = 0;
+    for (int g = threadIdx.x; g < b; g += kThreads) acc += gcount[g];
+    for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, RELCP_WAVE);
+    if (lane == 0) sh[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int k = 0; k < kWaves; ++k) t += sh[k];
+        goff = t;
+    }
+    __syncthreads();
+    // inclusive scan of the flags over the wave, then over the waves
+    int inc = f;
+    for (int o = 1; o < RELCP_WAVE; o <<= 1) {
+        const int t = __shfl_up(inc, o, RELCP_WAVE);
+        if (lane >= o) inc += t;
+    }
+    if (lane == RELCP_WAVE - 1) sh[w] = inc;
+    __syncthreads();
+    int woff = 0, btot = 0;
+    for (int k = 0; k < kWaves; ++k) {
+        woff += k < w ? sh[k] : 0;
+        btot += sh[k];
+    }
+    const int k = goff + woff + inc - f;
+    if (b == (int)gridDim.x - 1 && threadIdx.x == 0) *total = goff + btot;
+    if (p >= np) return;
+    pos[p] = f ? k : -1;
+    if (!f) return;
+    sel[k] = p;
+    build_row(A, k, p);
 }
 
 
@@ -1132,6 +1189,15 @@ int lcp_partials_needed(int m) { return 4 * (nblk(m > 0 ? m : 1, kThreads) + 1);
 void launch_rows_build(const RowBuildArgs &a, hipStream_t s) {
     if (a.nsel <= 0) return;
     hipLaunchKernelGGL(k_rows_build, dim3(nblk(a.nsel, 256)), dim3(256), 0, s, a);
+}
+
+int select_rows_max_pairs() { return kSelectGroupsMax * kThreads; }
+
+void launch_select_rows(const RowBuildArgs &a, int np, const int *flags, const int *gcount, int *sel, int *pos,
+                        int *total, hipStream_t s) {
+    if (np <= 0 || np > select_rows_max_pairs()) return;
+    hipLaunchKernelGGL(k_select_rows, dim3(nblk(np, kThreads)), dim3(kThreads), 0, s, a, np, flags, gcount, sel, pos,
+                       total);
 }
 
 

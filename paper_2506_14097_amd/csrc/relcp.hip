@@ -284,6 +284,9 @@ struct relcp_ctx {
     // the first rows' incidence lists filtered from the candidate pairs' (1)
     // or built from the rows (0) (RELCP_FIRST_LISTS); the same lists
     int first_lists = env_int("RELCP_FIRST_LISTS", 1, 0);
+    // the iteration-0 rows selected and built in one pass (1) or compacted
+    // first (0) (RELCP_FUSED_SELECT); the same rows
+    int fused_select = env_int("RELCP_FUSED_SELECT", 1, 0);
     // an FP32 solve whose residual has not halved in this many iterations
     // stops (its rounding floor is above the tolerance) and the FP64
     // polish continues from its last iterate; fixed-iteration runs never stop
@@ -380,6 +383,7 @@ struct relcp_ctx {
     void ensure_rows(int need);
     void broadphase(const double *xs, double skin_, bool bound = false);
     void build_rows(int nsel, int rec, const double *snsd, const double *vc, bool warm, double dt);
+    RowBuildArgs row_args(int nsel, int rec, const double *snsd, const double *vc, bool warm, double dt);
     void rebuild_csr();
     void first_rows_csr();
     void warm_start_rows(int m0, double dt);
@@ -850,6 +854,12 @@ void relcp_ctx::candidate_pairs(relcp_step_stats &S) {
 // rows and incidence
 // ---------------------------------------------------------------------------
 void relcp_ctx::build_rows(int nsel, int rec, const double *snsd, const double *vc, bool warm, double dt) {
+    const RowBuildArgs a = row_args(nsel, rec, snsd, vc, warm, dt);
+    launch_rows_build(a, stream);
+    m += nsel;
+}
+
+RowBuildArgs relcp_ctx::row_args(int nsel, int rec, const double *snsd, const double *vc, bool warm, double dt) {
     RowBuildArgs a{};
     a.nsel = nsel;
     a.sel = sel.p;
@@ -875,8 +885,7 @@ void relcp_ctx::build_rows(int nsel, int rec, const double *snsd, const double *
     a.n64 = rn64.p; a.ta64 = rta64.p; a.tb64 = rtb64.p; a.qv64 = rqv64.p; a.dA64 = rdA64.p; a.gam64 = rgam64.p;
     a.phi64 = rphi64.p;
     a.n32 = rn32.p; a.ta32 = rta32.p; a.tb32 = rtb32.p; a.qv32 = rqv32.p; a.dA32 = rdA32.p; a.gam32 = rgam32.p;
-    launch_rows_build(a, stream);
-    m += nsel;
+    return a;
 }
 
 // Rows grouped by packing for the resident LCP kernel: rlist holds row
@@ -1480,18 +1489,31 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     if (hint_ok) sa.hint = snsdt.p + ldp;
     int_h[0] = -1;  // no GPU work in flight writes it: the compaction below sets the count
     timed(2, [&] { launch_snsd_pairs(sa, stream); });
-    // count -> int_h[0]; each pair's row (or -1) -> prow
+    const bool learned = warm_start == RELCP_WS_LEARNED;
+    const bool need_feat = learned || log_on;
+    const bool warm0 = warm_start == RELCP_WS_PREV || need_feat;
+    log_valid = false;
+    m = 0;
+    // count -> int_h[0]; each pair's row (or -1) -> prow; with fused_select
+    // the rows are built by the same pass (room for every pair)
     prow.ensure(std::max(np, 1));
-    compact_flags(pflag.p, np, pcnt.p, sel.p, int_d, scan_scratch, stream, nullptr, prow.p);
+    const bool fused = fused_select && np > 0 && np <= select_rows_max_pairs();
+    if (fused) {
+        ensure_rows(np);
+        launch_select_rows(row_args(0, 0, snsd0.p, nullptr, warm0, dt), np, pflag.p, pcnt.p, sel.p, prow.p, int_d,
+                           stream);
+    } else {
+        compact_flags(pflag.p, np, pcnt.p, sel.p, int_d, scan_scratch, stream, nullptr, prow.p);
+    }
     const int m0 = wait_mapped(int_h, -1);
     if (m0 < 0 || m0 > np) throw Error{RELCP_E_DEVICE, "bad contact count"};
     t_narrow += tm.ms();
-    m = 0;
-    ensure_rows(m0);
-    const bool learned = warm_start == RELCP_WS_LEARNED;
-    const bool need_feat = learned || log_on;
-    log_valid = false;
-    build_rows(m0, 0, snsd0.p, nullptr, warm_start == RELCP_WS_PREV || need_feat, dt);
+    if (fused) {
+        m = m0;
+    } else {
+        ensure_rows(m0);
+        build_rows(m0, 0, snsd0.p, nullptr, warm0, dt);
+    }
     if (first_lists) first_rows_csr(); else rebuild_csr();
     if (need_feat) warm_start_rows(m0, dt);
     if (resident_mode()) rows_by_packing_init(m0);

@@ -694,20 +694,24 @@ def test_rowgraph_overflow_restart(dev, precision):
 
 
 @pytest.mark.parametrize("precision", [64, 32])
-def test_first_row_lists_match_lists_built_from_rows(dev, precision):
-    """The incidence lists of a step's first rows, filtered from the
-    candidate pairs' lists (RELCP_FIRST_LISTS=1, the default) and built from
-    the rows with atomics and a sort (0), are the same lists: steps over a
+def test_first_rows_paths_match(dev, precision):
+    """The iteration-0 rows selected and built in one pass over the candidate
+    pairs (RELCP_FUSED_SELECT=1, the default) or compacted first and built
+    after (0), and their incidence lists filtered from the candidate pairs'
+    lists (RELCP_FIRST_LISTS=1, the default) or built from the rows with
+    atomics and a sort (0), are the same rows and lists: steps over a
     compaction with augmentations and candidate-list rebuilds give the same
     states, contact sets, iteration counts and residuals bit for bit."""
     S = compressed_packing(4, 150, 26)
     sims = []
-    for fl in ("0", "1"):
+    for fl, fs in (("0", "0"), ("1", "0"), ("1", "1")):
         os.environ["RELCP_FIRST_LISTS"] = fl
+        os.environ["RELCP_FUSED_SELECT"] = fs
         try:
             sim = sim_from(dict(S, box=S["box"].copy()), skin=0.2, warm_start=R.WS_PREV, precision=precision)
         finally:
             os.environ.pop("RELCP_FIRST_LISTS", None)
+            os.environ.pop("RELCP_FUSED_SELECT", None)
         sims.append(sim)
     recs, rebuilt = 0, 0
     for k in range(8):
@@ -716,19 +720,21 @@ def test_first_row_lists_match_lists_built_from_rows(dev, precision):
             sim.affine_rescale(0.995)
             res = sim.step(5e-3, 1e-5, 1e-10 if precision == 64 else 1e-6)
             out.append((res, sim.get_state()))
-        (ra, sa), (rb, sb) = out
-        print("step", k, "iters", ra["lcp_iters"], rb["lcp_iters"], "rec", ra["recursions"], "pairs rebuilt",
+        ra, sa = out[0]
+        print("step", k, "iters", [o[0]["lcp_iters"] for o in out], "rec", ra["recursions"], "pairs rebuilt",
               ra["pairs_rebuilt"], flush=True)
-        assert ra["status"] == rb["status"] == 0
-        assert np.array_equal(ra["n_contacts"], rb["n_contacts"])
-        assert np.array_equal(ra["lcp_iters"], rb["lcp_iters"])
-        assert np.array_equal(ra["rowgraph_entries"], rb["rowgraph_entries"])
-        assert ra["residual_fp64"] == rb["residual_fp64"]
-        for a, b in zip(sa, sb):
-            assert np.array_equal(a, b)
-        ca, cb = sims[0].get_contacts(ra["n_contacts_final"]), sims[1].get_contacts(rb["n_contacts_final"])
-        for key in ca:
-            assert np.array_equal(ca[key], cb[key])
+        ca = sims[0].get_contacts(ra["n_contacts_final"])
+        for sim, (rb, sb) in zip(sims[1:], out[1:]):
+            assert ra["status"] == rb["status"] == 0
+            assert np.array_equal(ra["n_contacts"], rb["n_contacts"])
+            assert np.array_equal(ra["lcp_iters"], rb["lcp_iters"])
+            assert np.array_equal(ra["rowgraph_entries"], rb["rowgraph_entries"])
+            assert ra["residual_fp64"] == rb["residual_fp64"]
+            for a, b in zip(sa, sb):
+                assert np.array_equal(a, b)
+            cb = sim.get_contacts(rb["n_contacts_final"])
+            for key in ca:
+                assert np.array_equal(ca[key], cb[key])
         recs += ra["recursions"]
         rebuilt += ra["pairs_rebuilt"]
     assert recs > 0 and rebuilt > 0
