@@ -32,6 +32,10 @@ struct SnsdArgs {
     int *flag;                   // per pair, or null
     int *bcount;                 // set flags per block of 256 pairs (snsd_blocks(m) slots), or null
     double *clear;               // per pair, set to 0 (a per-pair accumulator for later), or null
+    // with clear: per pair a row (or -1) whose init_gam value clear starts
+    // from instead of 0, or null
+    const int *init_row;
+    const double *init_gam;
     // per-block order keys of min Phi and min |Phi + eps| (snsd_blocks(m)
     // slots each), or null
     unsigned long long *minphi;

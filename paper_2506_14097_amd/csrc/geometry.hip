@@ -659,6 +659,7 @@ __global__ void __launch_bounds__(256, 4) k_snsd_pairs(SnsdArgs A) {
     int fl = 0;
     if (k < A.m) {
         const int a = A.pa[k], b = A.pb[k];
+        const int ir = A.init_row ? A.init_row[k] : -1;
         // Every datum the pair may need is loaded up front, so the loads
         // form two dependent groups (pair, then bodies) and the packing's
         // box a third: the hint with the pair indices, then positions,
@@ -676,6 +677,7 @@ __global__ void __launch_bounds__(256, 4) k_snsd_pairs(SnsdArgs A) {
             ga[t] = A.geo[t * A.ldg + a];
             gb[t] = A.geo[t * A.ldg + b];
         }
+        const double lam0 = ir >= 0 ? A.init_gam[ir] : 0.0;
         const double *bx = A.boxes + 3 * pk;
         const double L0 = bx[0], L1 = bx[1], L2 = bx[2];
         d3 d = xb - xa;
@@ -722,7 +724,7 @@ __global__ void __launch_bounds__(256, 4) k_snsd_pairs(SnsdArgs A) {
         marg = fabs(s.phi + A.eps);
         fl = (A.mode == 0) ? (s.phi <= A.thresh ? 1 : 0) : (s.phi < -A.eps ? 1 : 0);
         if (A.flag) A.flag[k] = fl;
-        if (A.clear) A.clear[k] = 0.0;
+        if (A.clear) A.clear[k] = lam0;
     }
     if (A.bcount) {
         // this block's count of set flags (the compaction's tile offsets)

@@ -199,11 +199,18 @@ int make_spmv_graph(const LcpDev<T> *D, int grid_rows, int k, hipGraphExec_t *ou
 // 1), or, while the done flag (if given) is not set, that of the last pass
 // launched (parity last_par); gam64 (or null) <- the same gamma in FP64;
 // work (or null): the per-block sums of gamma (g - qv) of launch_work
-// (work_blocks(m) slots)
+// (work_blocks(m) slots).  check (or null): a solve of which only the start
+// pass ran (its partial sums in check->partials); the unpack reduces them as
+// the first iteration pass would and, if the start meets the tolerance,
+// records the final state and done flags and unpacks the start (else what
+// it writes is to be redone once the solve has been continued).  Only where
+// unpack_can_check(m).
 template <typename T>
 void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, const T *g0, const T *g1,
                             const PgdState *fin, const int *done, int last_par, T *gam, T *g, double *gam64,
-                            hipStream_t s, const T *qv = nullptr, double *work = nullptr);
+                            hipStream_t s, const T *qv = nullptr, double *work = nullptr,
+                            const PgdCtl *check = nullptr);
+bool unpack_can_check(int m);
 
 // Passes of the projected-gradient loop.  Iteration j (j = 1, 2, ...) is
 // scatter(mode 1, par = j & 1) then gather(mode 1, par = j & 1); a solve

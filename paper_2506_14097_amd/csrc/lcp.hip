@@ -1131,13 +1131,35 @@ __global__ void __launch_bounds__(kThreads)
     k_rowstate_unpack(int m, const RowStep<T> *__restrict__ z0, const RowStep<T> *__restrict__ z1,
                       const T *__restrict__ g0, const T *__restrict__ g1, const PgdState *__restrict__ fin,
                       const int *__restrict__ done, int last_par, T *__restrict__ gam, T *__restrict__ g,
-                      double *__restrict__ gam64, const T *__restrict__ qv, double *__restrict__ work) {
+                      double *__restrict__ gam64, const T *__restrict__ qv, double *__restrict__ work,
+                      PgdCtl C, int check) {
     __shared__ double sh[4][kWaves];
+    __shared__ PgdState ns;
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     double w = 0.0, z0s = 0.0, z1s = 0.0, z2s = 0.0;
+    int conv = 0;
+    if (check) {
+        // no pass followed the start pass: reduce its partial sums here, as
+        // the first iteration pass would (same order), and stop the solve
+        // if its start meets the tolerance (else the caller finds it
+        // unfinished and continues it with passes)
+        PartialRegs pr;
+        load_partials(C, pr);
+        reduce_loaded(C, 1, pr, &ns, sh);
+        conv = ns.conv;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            C.S[1] = ns;
+            if (ns.conv) {
+                *C.fin = ns;
+                *C.done = 1;
+                if (C.fin_h) *C.fin_h = ns;
+                if (C.done_h) *C.done_h = 1;
+            }
+        }
+    }
     if (r < m) {
         // a finished solve: the state of its final iterate; else that of the last pass launched
-        const bool odd = (done && !*done) ? (last_par & 1) : (fin->iter & 1);
+        const bool odd = check ? (conv ? false : (last_par & 1)) : (done && !*done) ? (last_par & 1) : (fin->iter & 1);
         const T v = (odd ? z1 : z0)[r].gam;
         const T gv = (odd ? g1 : g0)[r];
         gam[r] = v;
@@ -1365,11 +1387,14 @@ int make_spmv_graph(const LcpDev<T> *D, int grid_rows, int k, hipGraphExec_t *ou
 template <typename T>
 void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, const T *g0, const T *g1,
                             const PgdState *fin, const int *done, int last_par, T *gam, T *g, double *gam64,
-                            hipStream_t s, const T *qv, double *work) {
+                            hipStream_t s, const T *qv, double *work, const PgdCtl *check) {
+    const PgdCtl none{};
     if (m > 0 || work)
         hipLaunchKernelGGL((k_rowstate_unpack<T>), dim3(work_blocks(m)), dim3(kThreads), 0, s, m, z0, z1, g0, g1,
-                           fin, done, last_par, gam, g, gam64, qv, work);
+                           fin, done, last_par, gam, g, gam64, qv, work, check ? *check : none, check ? 1 : 0);
 }
+
+bool unpack_can_check(int m) { return work_blocks(m) <= kPartRegs * kThreads; }
 
 #define RELCP_INST(T)                                                                                              \
     template void launch_lcp_scatter<T>(int, const RowsT<T> &, const BodiesT<T> &, const PgdCtl &, int,           \
@@ -1381,7 +1406,7 @@ void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, c
                                      int, hipStream_t, double *);                                                 \
     template void launch_rowstate_unpack<T>(int, const RowStep<T> *, const RowStep<T> *, const T *, const T *,    \
                                             const PgdState *, const int *, int, T *, T *, double *, hipStream_t,  \
-                                            const T *, double *);                                                 \
+                                            const T *, double *, const PgdCtl *);                                 \
     template void launch_set_lcpdev<T>(LcpDev<T> *, const LcpDev<T> &, hipStream_t);                               \
     template void launch_spmv_dev<T>(const LcpDev<T> *, int, int, hipStream_t);                                    \
     template int make_spmv_graph<T>(const LcpDev<T> *, int, int, hipGraphExec_t *);

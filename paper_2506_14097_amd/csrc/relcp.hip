@@ -402,6 +402,7 @@ struct relcp_ctx {
     struct RgRun {
         int j = 1, chunk = 2, pass_mode = 1;
         bool fresh = false;  // the graph was assembled by this solve's start
+        bool check = false;  // no pass after the start: the unpack checks convergence
     };
     RgRun rgr[2];
     template <typename T>
@@ -1263,10 +1264,12 @@ void relcp_ctx::rg_start(const RowsT<T> &R, double dt, double tol, const double 
     // short first chunk costs a wait and, in a step, the work launched behind
     // it, while a spare pass returns at once
     st.chunk = std::max(2, std::min(64, last_iters[pk] + std::max(3, last_iters[pk] / 4) + 1));
-    // a polish that last converged at its start: the pass that sees it and
-    // a spare one; only the first once it has done so several times in a row
-    // (a miss costs a wait)
-    if (last_iters[pk] == 0) st.chunk = zero_run[pk] >= 4 ? 1 : 2;
+    // a solve (the polish) that last converged at its start: the pass that
+    // sees it and a spare one; for an FP64 solve (always unpacked right
+    // after its start) none once it has done so several times in a row: the
+    // unpack then sees it (a miss costs a wait)
+    if (last_iters[pk] == 0) st.chunk = sizeof(T) == 8 && zero_run[pk] >= 4 && unpack_can_check(m) ? 0 : 2;
+    st.check = st.chunk == 0;
     // over many blocks the partial sums are reduced once per pass by a
     // separate launch instead of by every block
     st.pass_mode = B.C.nbg >= reduce_split_blocks ? 2 : 1;
@@ -1284,9 +1287,13 @@ void relcp_ctx::rg_unpack(const RowsT<T> &R, const BodiesT<T> &Bd, double tol) {
     // FP64 also forms the work gamma^T A gamma's partial sums (the trial
     // forms the contact velocities K D gamma itself)
     if constexpr (sizeof(T) == 8) work_out.ensure(work_blocks(m));
+    // (a solve of which only the start pass ran: the unpack checks it, once)
+    PgdCtl c0 = B.C;
+    c0.partials = B.part;
     launch_rowstate_unpack<T>(m, B.z0, B.z1, B.g0, B.g1, B.C.fin, B.C.done, (rgr[pk].j - 1) & 1, R.gam, R.g,
                               sizeof(T) == 4 ? rgam64.p : nullptr, stream, sizeof(T) == 8 ? R.qv : nullptr,
-                              sizeof(T) == 8 ? work_out.p : nullptr);
+                              sizeof(T) == 8 ? work_out.p : nullptr, rgr[pk].check ? &c0 : nullptr);
+    rgr[pk].check = false;
 }
 
 // After a wait: true if the last graph assembly overflowed its slots (then
@@ -1316,6 +1323,7 @@ int relcp_ctx::rg_finish(const RowsT<T> &R, const BodiesT<T> &Bd, double tol, in
     relaunched = false;
     if (!*done_h) {
         relaunched = true;
+        st.chunk = std::max(st.chunk, 2);  // (a first chunk of no passes)
         for (;;) {
             const int k = std::min(st.chunk, cap - (st.j - 1));
             if (k <= 0) break;
@@ -1550,7 +1558,12 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
             SnsdArgs sb = sa;
             sb.x = xt.p; sb.geo = geot.p; sb.hint = snsd0.p + ldp; sb.out = snsdt.p; sb.mode = 1; sb.flag = pflag.p;
             sb.minphi = red.p + nt; sb.minmarg = red.p + nt + nsb;
-            sb.clear = lam.p;  // the pair sums of an accepted step are accumulated there
+            // the pair sums of an accepted step are accumulated there, from the
+            // multipliers of the iteration-0 rows (one per pair; the rows of
+            // later recursions are added after acceptance)
+            sb.clear = lam.p;
+            sb.init_row = prow.p;
+            sb.init_gam = rgam64.p;
             timed(2, [&] { launch_snsd_pairs(sb, stream); });
             ++tok_seq;
             const TailReport rep{nt, red.p, np > 0 ? nsb : 0, red.p + nt, red.p + nt + nsb, nw, work_out.p,
@@ -1691,9 +1704,9 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         std::swap(q.p, qt.p);
         std::swap(geo.p, geot.p);  // the trial's geometry is that of C^{k+1}
         std::swap(u.p, vout.p);  // every trial writes all of vout
-        // multiplier sum per pair, for the next warm start
-        // (lam was cleared by the last trial's SNSD pass)
-        for (int lv = 0; lv <= rec; ++lv) launch_pair_lambda(m, rrec.p, rpair.p, rgam64.p, lv, lam.p, stream);
+        // multiplier sum per pair, for the next warm start (the last trial's
+        // SNSD pass set it to the multiplier of the pair's iteration-0 row)
+        for (int lv = 1; lv <= rec; ++lv) launch_pair_lambda(m, rrec.p, rpair.p, rgam64.p, lv, lam.p, stream);
         if (!prev_is_list) {
             // the previous-step pairs are the candidate list itself until it is rebuilt
             prev_a.ensure(std::max(np, 1));
