@@ -69,7 +69,7 @@ void launch_select_rows(const RowBuildArgs &a, int np, const int *flags, const i
 // are known to be zero (every build leaves them so).  rg (or null): also
 // the row-graph slice widths with their sum (as launch_rowgraph_width).
 struct CsrRowGraphOut {
-    int *width, *count;
+    int *width, *count, *rcnt;
 };
 void launch_csr(int nb, int m, const int *ia, const int *ib, int *cnt, int *off, int *cursor, int *ent,
                 bool cleared, DBuf<int> &scan_scratch, hipStream_t s, const CsrRowGraphOut *rg = nullptr);
@@ -107,6 +107,7 @@ struct RowGraphT {
     const int *base, *col;
     const T *val;
     size_t cap;  // entry slots allocated: a slice past them was not filled and is skipped
+    const int *rcnt;  // entries of each row (slots past them, up to the slice's width, are not written)
 };
 
 // Iteration state of a row seen by the rows it couples to: multiplier and
@@ -134,10 +135,10 @@ struct RowGraphFill {
 };
 
 int rowgraph_slices(int m);
-// width[s] = largest count of other rows at a row's two bodies in slice s;
-// *count += the sum of those counts (the entries without padding), unless
-// count is null
-void launch_rowgraph_width(int m, const int *ia, const int *ib, const int *off, int *width, int *count,
+// rcnt[r] = count of other rows at row r's two bodies (its entries);
+// width[s] = their largest over slice s; *count += their sum, unless count is
+// null
+void launch_rowgraph_width(int m, const int *ia, const int *ib, const int *off, int *width, int *count, int *rcnt,
                            hipStream_t s);
 void launch_rowgraph_fill(const RowGraphFill &a, hipStream_t s);
 // One pass of the row-graph LCP loop over m rows with A in G and the
@@ -176,6 +177,7 @@ struct LcpDev {
     const int *base, *col;
     const T *val;
     size_t slots;
+    const int *rcnt;
     const T *qv, *dA;
     RowStep<T> *z[2];
     T *g[2];

@@ -204,7 +204,7 @@ __global__ void k_csr_count(int m, const int *__restrict__ ia, const int *__rest
 __global__ void __launch_bounds__(256) k_csr_fill(int m, const int *__restrict__ ia, const int *__restrict__ ib,
                                                   const int *__restrict__ off, int *__restrict__ cursor,
                                                   int *__restrict__ ent, int *__restrict__ width,
-                                                  int *__restrict__ count) {
+                                                  int *__restrict__ count, int *__restrict__ rcnt) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     int w = 0;
     const int a = r < m ? ia[r] : -1;
@@ -221,6 +221,7 @@ __global__ void __launch_bounds__(256) k_csr_fill(int m, const int *__restrict__
         ent[off[a] + slot] = r << 1;
         ent[off[b] + atomicAdd(cursor + b, 1)] = (r << 1) | 1;
         w = off[a + 1] - off[a] + off[b + 1] - off[b] - 2;  // the row itself at a and at b: the diagonal
+        if (width) rcnt[r] = w;
     }
     if (!width) return;
     __shared__ int bsum[4];
@@ -718,12 +719,14 @@ __global__ void __launch_bounds__(kThreads) k_pgd_reduce(PgdCtl C, int par) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads) k_rowgraph_width(int m, const int *__restrict__ ia,
                                                              const int *__restrict__ ib, const int *__restrict__ off,
-                                                             int *__restrict__ width, int *__restrict__ count) {
+                                                             int *__restrict__ width, int *__restrict__ count,
+                                                             int *__restrict__ rcnt) {
     const int r = blockIdx.x * kThreads + threadIdx.x;
     int w = 0;
     if (r < m) {
         const int a = ia[r], b = ib[r];
         w = off[a + 1] - off[a] + off[b + 1] - off[b] - 2;  // the row itself at a and at b: the diagonal
+        rcnt[r] = w;
     }
     __shared__ int bsum[kWaves];
     int sum = w;
@@ -752,8 +755,9 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_width(int m, const int *_
 // c, s (n_r, tau_r), shares it through LDS with the other entries of c in
 // its block, and writes row r's entries at c: for every other entry j of c,
 // in incidence order, column r_j and value dt J_j . K_c J_e (so row r holds
-// its entries at body a, then those at body b), and, at body b, the row's
-// padding (the row itself, value 0) up to the slice's width.  A column of
+// its entries at body a, then those at body b).  The slots past a row's
+// entries, up to its slice's width, are not written: the passes read a
+// row's entries only (its count from the width pass).  A column of
 // an entry outside the block (a body that straddles two blocks) is formed
 // again from the rows.  The diagonal A_rr is not stored: a pass takes it
 // from the rows' A_aa.
@@ -839,13 +843,6 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_fill_entries(RowGraphFill
         v32[at] = (float)v;
         ++k;
     }
-    if (!side) return;
-    for (; k < w; ++k) {
-        const size_t at = (size_t)RELCP_WAVE * (b0 + k) + lane;
-        col[at] = r;
-        v64[at] = 0.0;
-        v32[at] = 0.0f;
-    }
 }
 
 // max(0, gamma - alpha h); the same rounding wherever a row's step is formed
@@ -883,7 +880,8 @@ struct StartF32 {
 
 template <typename T>
 struct RowPre {
-    int w;
+    int w;    // the slice's width (the same in every lane of the wave)
+    int cnt;  // this row's entries (<= w)
     const int *col;
     const T *val;
     T gm, hm, gold, dA, q;
@@ -903,6 +901,7 @@ __device__ inline void row_preload_a(const RowGraphT<T> &G, const T *__restrict_
     const int sl = __builtin_amdgcn_readfirstlane(r / RELCP_WAVE);
     b0 = __builtin_amdgcn_readfirstlane(G.base[sl]);
     P.w = __builtin_amdgcn_readfirstlane(G.base[sl + 1]);
+    P.cnt = G.rcnt[r];
     P.dA = dA0[r];
     P.q = qv[r];
     if (MODE == 1) {
@@ -929,12 +928,13 @@ __device__ inline void row_preload_b(const RowGraphT<T> &G, const SV &gam0, cons
     if ((size_t)RELCP_WAVE * (b0 + P.w) > G.cap) P.w = 0;
     P.col = G.col + (size_t)RELCP_WAVE * b0 + lane;
     P.val = G.val + (size_t)RELCP_WAVE * b0 + lane;
-    // entries past the slice's width are padding: not loaded (zero value,
-    // zero neighbour state)
+    // slots past the row's entries are not read (zero value, zero neighbour
+    // state); past the slice's width no lane has any (a uniform branch)
+    if (P.w == 0) P.cnt = 0;
     const int kp = P.w < kPre ? P.w : kPre;
 #pragma unroll
     for (int k = 0; k < kPre; ++k) {
-        if (k < kp) {
+        if (k < kp && k < P.cnt) {
             P.cj[k] = P.col[RELCP_WAVE * k];
             P.vj[k] = P.val[RELCP_WAVE * k];
         } else {
@@ -944,7 +944,7 @@ __device__ inline void row_preload_b(const RowGraphT<T> &G, const SV &gam0, cons
     }
 #pragma unroll
     for (int k = 0; k < kPre; ++k) {
-        if (k < kp) {
+        if (k < kp && k < P.cnt) {
             if (MODE == 1) {
                 const RowStep<T> z = zin[P.cj[k]];
                 P.gj[k] = z.gam;
@@ -980,7 +980,7 @@ __device__ inline void row_finish(const RowPre<T> &P, T al, const RowStep<T> *__
     T acc = P.dA * gv;
 #pragma unroll
     for (int k = 0; k < kPre; ++k) acc += P.vj[k] * (MODE == 1 ? step_h(P.gj[k], P.hj[k], al) : clamp0(P.gj[k]));
-    for (int k = kPre; k < P.w; ++k) {
+    for (int k = kPre; k < P.cnt; ++k) {
         const int j = P.col[RELCP_WAVE * k];
         const T v = P.val[RELCP_WAVE * k];
         if (MODE == 1) {
@@ -1085,7 +1085,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_dev(const LcpDev<T> *__restri
     if (*d.done) return;
     const int nbg = d.nbg;
     if ((int)blockIdx.x >= nbg) return;
-    const RowGraphT<T> G{d.m, d.base, d.col, d.val, d.slots};
+    const RowGraphT<T> G{d.m, d.base, d.col, d.val, d.slots, d.rcnt};
     const int lb = xcd_block(blockIdx.x, nbg);  // the same order as the per-pass launch over nbg blocks
     const int r = lb * kThreads + threadIdx.x;
     const bool act = r < d.m;
@@ -1232,7 +1232,7 @@ void launch_csr(int nb, int m, const int *ia, const int *ib, int *cnt, int *off,
     exclusive_scan(cnt, off, nb + 1, nullptr, scan_scratch, s);
     if (m > 0) {
         hipLaunchKernelGGL(k_csr_fill, dim3(nblk(m, 256)), dim3(256), 0, s, m, ia, ib, off, cursor, ent,
-                           rg ? rg->width : nullptr, rg ? rg->count : nullptr);
+                           rg ? rg->width : nullptr, rg ? rg->count : nullptr, rg ? rg->rcnt : nullptr);
         hipLaunchKernelGGL(k_csr_sort, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, off, ent, cnt, cursor);
     }
 }
@@ -1311,10 +1311,10 @@ void launch_pgd_finalize(const PgdCtl &C, int par, hipStream_t s) {
 
 int rowgraph_slices(int m) { return (m + RELCP_WAVE - 1) / RELCP_WAVE; }
 
-void launch_rowgraph_width(int m, const int *ia, const int *ib, const int *off, int *width, int *count,
+void launch_rowgraph_width(int m, const int *ia, const int *ib, const int *off, int *width, int *count, int *rcnt,
                            hipStream_t s) {
     launch_k(k_rowgraph_width, dim3(nblk(m > 0 ? m : 1, kThreads)), dim3(kThreads), 0, s, m, ia, ib, off,
-                       width, count);
+                       width, count, rcnt);
 }
 
 

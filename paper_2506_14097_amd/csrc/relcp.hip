@@ -262,6 +262,7 @@ struct relcp_ctx {
     // 3 = row graph (A assembled over rows, one pass per iteration)
     int lcp_mode = 0, res_block = 256, res_lds = 1;
     DBuf<int> rg_width, rg_base, rg_col, rg_flags;  // flags: [0] entry count, [1] overflow
+    DBuf<int> rg_rcnt;  // entries of each row
     DBuf<double> rg_val64;
     DBuf<float> rg_val32;
     DBuf<RowStep<double>> z64;
@@ -369,6 +370,7 @@ struct relcp_ctx {
         pk_state.release();
         mlp_w.release(); feat.release(); rowscale.release();
         rg_width.release(); rg_base.release(); rg_col.release(); rg_flags.release(); rg_val64.release();
+        rg_rcnt.release();
         rg_val32.release(); z64.release(); z32.release(); zg64.release(); zg32.release();
         lcpdev64.release(); lcpdev32.release();
         for (auto &ge : spmv_graph)
@@ -924,7 +926,7 @@ void relcp_ctx::rebuild_csr() {
     rg_counted = false;
     if (rg_pre) {
         rg_prepare();
-        rgo = CsrRowGraphOut{rg_width.p, rg_flags.p};
+        rgo = CsrRowGraphOut{rg_width.p, rg_flags.p, rg_rcnt.p};
     }
     launch_csr(n, m, ria.p, rib.p, csr_cnt.p, csr_off.p, csr_cnt.p + (n + 1), csr_ent.p, cleared, scan_scratch,
                stream, rg_pre ? &rgo : nullptr);
@@ -1014,6 +1016,7 @@ void relcp_ctx::rg_reserve(size_t slots) {
 void relcp_ctx::rg_prepare() {
     const int ns = rowgraph_slices(m);
     rg_width.ensure(ns + 1);
+    rg_rcnt.ensure(std::max(m, 1));
     rg_base.ensure(ns + 1);
     if (!rg_flags.p) {
         rg_flags.ensure(1);
@@ -1031,7 +1034,8 @@ void relcp_ctx::build_rowgraph(double dt) {
         // widths not made by the incidence build (a rebuild, or the first
         // rows' filtered lists, which counted the entries)
         timed(8, [&] {
-            launch_rowgraph_width(m, ria.p, rib.p, csr_off.p, rg_width.p, rg_counted ? nullptr : rg_flags.p, stream);
+            launch_rowgraph_width(m, ria.p, rib.p, csr_off.p, rg_width.p, rg_counted ? nullptr : rg_flags.p,
+                                  rg_rcnt.p, stream);
         });
     }
     rg_pre = false;
@@ -1211,7 +1215,7 @@ relcp_ctx::RgBufs<T> relcp_ctx::rg_bufs(const RowsT<T> &R, double tol) {
     B.C = PgdCtl{cb, cb + 2, reinterpret_cast<int *>(cb + 3), B.part, lcp_gather_blocks(m),
                  lcp_fixed > 0 ? -1.0 : tol, pst_d + 2 * pk, reinterpret_cast<int *>(pst_d + 2 * pk + 1),
                  stall_iters<T>()};
-    B.G = RowGraphT<T>{m, rg_base.p, rg_col.p, nullptr, rg_cap};
+    B.G = RowGraphT<T>{m, rg_base.p, rg_col.p, nullptr, rg_cap, rg_rcnt.p};
     if constexpr (sizeof(T) == 8)
         B.G.val = rg_val64.p;
     else
@@ -1405,7 +1409,7 @@ int relcp_ctx::solve_rowgraph_graph(const RowsT<T> &R, const BodiesT<T> &Bd, dou
         }
         LcpDev<T> v{};
         v.m = m; v.nbg = B.C.nbg; v.cap = cap; v.tol = B.C.tol; v.stall = B.C.stall;
-        v.base = B.G.base; v.col = B.G.col; v.val = B.G.val; v.slots = B.G.cap;
+        v.base = B.G.base; v.col = B.G.col; v.val = B.G.val; v.slots = B.G.cap; v.rcnt = B.G.rcnt;
         v.qv = R.qv; v.dA = R.dA;
         v.z[0] = B.z0; v.z[1] = B.z1; v.g[0] = B.g0; v.g[1] = B.g1;
         v.part[0] = B.part; v.part[1] = B.part + B.stride;
@@ -1566,12 +1570,15 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
             sb.init_gam = rgam64.p;
             timed(2, [&] { launch_snsd_pairs(sb, stream); });
             ++tok_seq;
-            const TailReport rep{nt, red.p, np > 0 ? nsb : 0, red.p + nt, red.p + nt + nsb, nw, work_out.p,
-                                 red_hd, dbl_hd, tok_d, tok_seq};
-            // count -> int_h[0], then the report from the compaction's last
-            // workgroup (or on its own when there are no candidate pairs)
-            if (!compact_flags(pflag.p, np, pcnt.p, sel.p, int_d, scan_scratch, stream, &rep))
-                hipLaunchKernelGGL(k_report, dim3(1), dim3(256), 0, stream, rep);
+            TailReport rep{nt, red.p, np > 0 ? nsb : 0, red.p + nt, red.p + nt + nsb, nw, work_out.p,
+                           red_hd, dbl_hd, tok_d, tok_seq};
+            // the violator count (from the check's per-group flag counts) ->
+            // int_h[0], then the report; the violators are compacted only
+            // when there are some (after the wait, for the augmentation)
+            rep.ng = np > 0 ? flag_groups(np) : 0;
+            rep.gcount = pcnt.p;
+            rep.count = int_d;
+            hipLaunchKernelGGL(k_report, dim3(1), dim3(256), 0, stream, rep);
         };
         bool tail_ready = false;  // the tail ran on the final multipliers and was waited for
         if (spec) {
@@ -1688,6 +1695,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         ensure_rows(m + nv);
         {
             const int m_old = m;
+            compact_flags(pflag.p, np, pcnt.p, sel.p, nullptr, scan_scratch, stream);  // the violators
             build_rows(nv, rec + 1, snsdt.p, vc64.p, false, dt);
             rebuild_csr();
             if (resident_mode()) rows_by_packing_append(m_old, nv);

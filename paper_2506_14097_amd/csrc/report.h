@@ -2,8 +2,9 @@
 // (largest displacement key of the trial, smallest Phi and margin keys of
 // the overlap check, the work gamma^T A gamma) into host-mapped memory,
 // then a token written last after a system-scope fence: the host polls the
-// token.  Run by one workgroup of 256 threads, either the report kernel or
-// the last workgroup of the compaction of the violators.
+// token.  Run by one workgroup of 256 threads, either the report kernel
+// (which also adds up the violator count from the overlap check's per-group
+// flag counts) or the last workgroup of a compaction of the violators.
 #pragma once
 
 #include "common.h"
@@ -21,6 +22,11 @@ struct TailReport {
     double *work_h;                    // host-mapped: the work
     int *tok;                          // host-mapped token (or null)
     int seq;
+    // the overlap check's flag counts per group of 256 pairs (ng groups),
+    // summed into *count (the violator count), or gcount null
+    int ng = 0;
+    const int *gcount = nullptr;
+    int *count = nullptr;
 };
 
 __device__ inline unsigned long long u64_max(unsigned long long a, unsigned long long b) { return a > b ? a : b; }
@@ -40,18 +46,24 @@ __device__ inline void tail_report(const TailReport &R) {
         q = u64_min(q, R.marg[k]);
     }
     for (int k = threadIdx.x; k < R.nw; k += 256) w += R.work[k];
+    int c = 0;
+    if (R.gcount)
+        for (int k = threadIdx.x; k < R.ng; k += 256) c += R.gcount[k];
     for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) {
         d = u64_max(d, __shfl_xor(d, o, RELCP_WAVE));
         p = u64_min(p, __shfl_xor(p, o, RELCP_WAVE));
         q = u64_min(q, __shfl_xor(q, o, RELCP_WAVE));
         w += __shfl_xor(w, o, RELCP_WAVE);
+        c += __shfl_xor(c, o, RELCP_WAVE);
     }
+    __shared__ int s4[4];
     const int lane = threadIdx.x & (RELCP_WAVE - 1), wv = threadIdx.x / RELCP_WAVE;
     if (lane == 0) {
         s0[wv] = d;
         s1[wv] = p;
         s2[wv] = q;
         s3[wv] = w;
+        s4[wv] = c;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -60,7 +72,9 @@ __device__ inline void tail_report(const TailReport &R) {
             p = u64_min(p, s1[k]);
             q = u64_min(q, s2[k]);
             w += s3[k];
+            c += s4[k];
         }
+        if (R.gcount) *R.count = c;
         R.red_h[0] = d;
         R.red_h[1] = p;
         R.red_h[2] = q;

@@ -3,10 +3,12 @@
 The row graph stores the off-diagonal entries of A over rows in sliced ELL:
 slice s holds rows [64 s, 64 s + 64), its width w_s is the largest count of
 other rows at a row's two bodies in the slice, and entry k of row r sits in
-slot 64 (base_s + k) + r % 64 (base = exclusive scan of the widths).  The
+slot 64 (base_s + k) + r % 64 (base = exclusive scan of the widths); the
+slots past a row's own entries (up to the slice's width) are neither
+written by the fill nor read by a pass, which takes each row's count.  The
 step sizes the slots from an estimate per row (RELCP_RG_SLOTS_PER_ROW, with
 half again as much headroom) before the widths are known; the fill
-(k_rowgraph_fill) skips a slice whose end 64 (base_s + w_s) passes the
+(k_rowgraph_fill_entries) skips a slice whose end 64 (base_s + w_s) passes the
 allocation and flags the overflow, and the passes (row_preload_b) treat such
 a slice as empty.  This test restates that slot arithmetic and walks every
 slot the fill would write and every slot a pass would read, on the rows of
@@ -47,7 +49,7 @@ def walk(ia, ib, nb, cap):
             overflow = True
             continue
         assert wrow[r] <= w
-        for k in range(w):  # the row's entries, then its padding up to the slice width
+        for k in range(wrow[r]):  # the row's entries (the slots past them are neither written nor read)
             at = W * (b0 + k) + lane
             hi_w = max(hi_w, at + 1)
             hi_r = max(hi_r, at + 1)
