@@ -40,15 +40,35 @@ __device__ inline void tail_report(const TailReport &R) {
     __shared__ double s3[4];
     unsigned long long d = 0ull, p = ~0ull, q = ~0ull;
     double w = 0.0;
-    for (int k = threadIdx.x; k < R.nt; k += 256) d = u64_max(d, R.disp[k]);
-    for (int k = threadIdx.x; k < R.ns; k += 256) {
-        p = u64_min(p, R.phi[k]);
-        q = u64_min(q, R.marg[k]);
-    }
-    for (int k = threadIdx.x; k < R.nw; k += 256) w += R.work[k];
     int c = 0;
-    if (R.gcount)
-        for (int k = threadIdx.x; k < R.ng; k += 256) c += R.gcount[k];
+    // thread t takes items t, t + 256, ... of each array in that order, kU
+    // of each array per round with all their loads issued before any use
+    constexpr int kU = 4;
+    const int ng = R.gcount ? R.ng : 0;
+    const int nmax = max(max(R.nt, R.ns), max(R.nw, ng));
+    for (int k0 = threadIdx.x; k0 < nmax; k0 += kU * 256) {
+        unsigned long long vd[kU], vp[kU], vq[kU];
+        double vw[kU];
+        int vc[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int k = k0 + u * 256;
+            vd[u] = k < R.nt ? R.disp[k] : 0ull;
+            vp[u] = k < R.ns ? R.phi[k] : ~0ull;
+            vq[u] = k < R.ns ? R.marg[k] : ~0ull;
+            vw[u] = k < R.nw ? R.work[k] : 0.0;
+            vc[u] = k < ng ? R.gcount[k] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int k = k0 + u * 256;
+            d = u64_max(d, vd[u]);
+            p = u64_min(p, vp[u]);
+            q = u64_min(q, vq[u]);
+            if (k < R.nw) w += vw[u];
+            c += vc[u];
+        }
+    }
     for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) {
         d = u64_max(d, __shfl_xor(d, o, RELCP_WAVE));
         p = u64_min(p, __shfl_xor(p, o, RELCP_WAVE));
