@@ -195,8 +195,16 @@ bool compact_flags(const int *flags, int n, const int *bcount, int *out, int *to
 // (pos[j] << 1) | side, each list in its own order: cnt (n) the kept counts,
 // off (n + 1) and ent (the kept entries) the filtered lists; pairs_out (a
 // device int, or null) <- the sum over items of c (c - 1), c the kept count.
-// scratch grows as needed.
+// rows (or null): m rows, each kept once in the lists of its two items ia,
+// ib; rcnt[r] <- the other kept entries of those two lists (c_a + c_b - 2),
+// width[s] <- their largest over rows 64 s .. 64 s + 63, width[ceil(m/64)]
+// <- 0.  scratch grows as needed.
+struct ListRowCounts {
+    int m;
+    const int *ia, *ib;
+    int *width, *rcnt;
+};
 void filter_lists(int n, const int *boff, const int *bent, const int *pos, int *cnt, int *off, int *ent,
-                  DBuf<int> &scratch, hipStream_t s, int *pairs_out = nullptr);
+                  DBuf<int> &scratch, hipStream_t s, int *pairs_out = nullptr, const ListRowCounts *rows = nullptr);
 
 }  // namespace relcp

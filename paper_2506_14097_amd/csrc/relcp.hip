@@ -955,12 +955,15 @@ void relcp_ctx::first_rows_csr() {
     // in the row-graph mode the filter also stores the graph's entry count
     // (the ordered pairs of rows sharing a body) in the entry counter, so
     // the width pass need not add it up
-    rg_pre = false;
+    // (and the rows' entry counts and slice widths, as the width pass would)
     rg_counted = rowgraph_mode() && m > 0;
+    rg_pre = false;
     if (rg_counted) rg_prepare();
     if (np > 0) {
+        const ListRowCounts rw{m, ria.p, rib.p, rg_width.p, rg_rcnt.p};
         filter_lists(n, pcsr_off.p, pcsr_ent.p, prow.p, fl_cnt.p, csr_off.p, csr_ent.p, scan_scratch, stream,
-                     rg_counted ? rg_flags.p : nullptr);
+                     rg_counted ? rg_flags.p : nullptr, rg_counted ? &rw : nullptr);
+        rg_pre = rg_counted;
     } else {
         HIP_OK(hipMemsetAsync(csr_off.p, 0, (n + 1) * sizeof(int), stream));
         if (rg_counted) HIP_OK(hipMemsetAsync(rg_flags.p, 0, sizeof(int), stream));

@@ -333,27 +333,46 @@ __global__ void __launch_bounds__(kThreads) k_filter_count(int n, const int *__r
 }
 
 // offsets (the counts of the blocks before this one, then a block scan) and
-// the kept entries, renumbered; off[n] = the total
-__global__ void __launch_bounds__(kThreads) k_filter_fill(int n, const int *__restrict__ boff,
+// the kept entries, renumbered; off[n] = the total.  Blocks 0 .. nbb - 1
+// cover the items; with rw.m > 0 the grid also covers the rows, and block b
+// forms the counts of rows b kThreads .. (the kept counts are complete: the
+// count pass ran before).
+__global__ void __launch_bounds__(kThreads) k_filter_fill(int n, int nbb, const int *__restrict__ boff,
                                                           const int *__restrict__ bent, const int *__restrict__ pos,
                                                           const int *__restrict__ cnt, const int *__restrict__ sums,
                                                           const int *__restrict__ offs, int *__restrict__ off,
-                                                          int *__restrict__ ent, int *__restrict__ pairs_out) {
+                                                          int *__restrict__ ent, int *__restrict__ pairs_out,
+                                                          ListRowCounts rw) {
     __shared__ int sh[kThreads / RELCP_WAVE];
     __shared__ int wsum[kThreads / RELCP_WAVE];
     const int b = blockIdx.x;
     const int i = b * kThreads + threadIdx.x;
+    const int lane = threadIdx.x & (RELCP_WAVE - 1), w = threadIdx.x / RELCP_WAVE;
+    if (rw.m > 0) {
+        // row i: the other kept entries in its two items' lists; each wave's
+        // 64 rows are one slice, whose width is their largest count
+        int wr = 0;
+        if (i < rw.m) {
+            wr = cnt[rw.ia[i]] + cnt[rw.ib[i]] - 2;
+            rw.rcnt[i] = wr;
+        }
+#pragma unroll
+        for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) wr = max(wr, __shfl_xor(wr, o, RELCP_WAVE));
+        const int ns = (rw.m + RELCP_WAVE - 1) / RELCP_WAVE;
+        if (lane == 0 && i / RELCP_WAVE < ns) rw.width[i / RELCP_WAVE] = wr;
+        if (i == 0) rw.width[ns] = 0;
+    }
+    if (b >= nbb) return;  // (a whole block: no barrier below is split)
     const int c = i < n ? cnt[i] : 0;
-    if (pairs_out && b == (int)gridDim.x - 1) {
+    if (pairs_out && b == nbb - 1) {
         // the last block adds up the pair counts of all blocks
         int acc = 0;
-        for (int k = threadIdx.x; k < (int)gridDim.x; k += kThreads) acc += sums[gridDim.x + k];
+        for (int k = threadIdx.x; k < nbb; k += kThreads) acc += sums[nbb + k];
         const int tp = block_total<kThreads>(acc, sh);
         if (threadIdx.x == 0) *pairs_out = tp;
     }
     const int toff = tile_offset(sums, offs, b, sh);
     const int inc = wave_incl_scan(c);
-    const int lane = threadIdx.x & (RELCP_WAVE - 1), w = threadIdx.x / RELCP_WAVE;
     if (lane == RELCP_WAVE - 1) wsum[w] = inc;
     __syncthreads();
     int woff = 0;
@@ -367,7 +386,7 @@ __global__ void __launch_bounds__(kThreads) k_filter_fill(int n, const int *__re
 }
 
 void filter_lists(int n, const int *boff, const int *bent, const int *pos, int *cnt, int *off, int *ent,
-                  DBuf<int> &scratch, hipStream_t s, int *pairs_out) {
+                  DBuf<int> &scratch, hipStream_t s, int *pairs_out, const ListRowCounts *rows) {
     if (n <= 0) return;
     const int nb = (n + kThreads - 1) / kThreads;
     // past kDirect blocks the block counts are scanned first (a block would
@@ -377,8 +396,10 @@ void filter_lists(int n, const int *boff, const int *bent, const int *pos, int *
     int *sums = scratch.p, *offs = scan_first ? scratch.p + 2 * (size_t)nb : nullptr;
     hipLaunchKernelGGL(k_filter_count, dim3(nb), dim3(kThreads), 0, s, n, boff, bent, pos, cnt, sums);
     if (scan_first) scan_into(sums, offs, nb, nullptr, offs + nb, s);
-    hipLaunchKernelGGL(k_filter_fill, dim3(nb), dim3(kThreads), 0, s, n, boff, bent, pos, cnt, sums, offs, off, ent,
-                       pairs_out);
+    const ListRowCounts rw = rows ? *rows : ListRowCounts{};
+    const int nbr = rw.m > 0 ? (rw.m + kThreads - 1) / kThreads : 0;
+    hipLaunchKernelGGL(k_filter_fill, dim3(std::max(nb, nbr)), dim3(kThreads), 0, s, n, nb, boff, bent, pos, cnt, sums,
+                       offs, off, ent, pairs_out, rw);
 }
 
 }  // namespace relcp
