@@ -200,9 +200,10 @@ bool compact_flags(const int *flags, int n, const int *bcount, int *out, int *to
 // width[s] <- their largest over rows 64 s .. 64 s + 63, width[ceil(m/64)]
 // <- 0.  scratch grows as needed.
 struct ListRowCounts {
-    int m;
+    int m;               // rows, or with m_dev the rows' capacity (the grid covers it)
     const int *ia, *ib;
     int *width, *rcnt;
+    const int *m_dev;    // the row count on the device (<= m), or null
 };
 void filter_lists(int n, const int *boff, const int *bent, const int *pos, int *cnt, int *off, int *ent,
                   DBuf<int> &scratch, hipStream_t s, int *pairs_out = nullptr, const ListRowCounts *rows = nullptr);

@@ -60,11 +60,12 @@ void launch_rows_build(const RowBuildArgs &a, hipStream_t s);
 // pairs (a.sel and a.nsel unused; rows a.m0 + k): flags (np) the selection,
 // gcount the set flags of each group of 256 pairs; writes sel (row ->
 // pair), pos (pair -> row or -1) and the row count to *total (a device
-// int).  Only for np <= select_rows_max_pairs() (nothing is launched past
-// it, nor for np <= 0).  The rows need room for all np pairs.
+// int, host-mapped or not) and, if not null, to *total_dev as well.  Only
+// for np <= select_rows_max_pairs() (nothing is launched past it, nor for
+// np <= 0).  The rows need room for all np pairs.
 int select_rows_max_pairs();
 void launch_select_rows(const RowBuildArgs &a, int np, const int *flags, const int *gcount, int *sel, int *pos,
-                        int *total, hipStream_t s);
+                        int *total, hipStream_t s, int *total_dev = nullptr);
 // CSR of the rows at each body; cleared: cnt and cursor (2 (nb + 1) ints)
 // are known to be zero (every build leaves them so).  rg (or null): also
 // the row-graph slice widths with their sum (as launch_rowgraph_width).

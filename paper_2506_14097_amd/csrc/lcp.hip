@@ -127,7 +127,8 @@ __global__ void k_rows_build(RowBuildArgs A) {
 // (pair -> row, or -1) and, from the last block, the row count.
 __global__ void __launch_bounds__(kThreads) k_select_rows(RowBuildArgs A, int np, const int *__restrict__ flags,
                                                           const int *__restrict__ gcount, int *__restrict__ sel,
-                                                          int *__restrict__ pos, int *__restrict__ total) {
+                                                          int *__restrict__ pos, int *__restrict__ total,
+                                                          int *__restrict__ total_dev) {
     __shared__ int sh[kWaves];
     __shared__ int goff;
     const int b = blockIdx.x;
@@ -160,7 +161,10 @@ __global__ void __launch_bounds__(kThreads) k_select_rows(RowBuildArgs A, int np
         btot += sh[k];
     }
     const int k = goff + woff + inc - f;
-    if (b == (int)gridDim.x - 1 && threadIdx.x == 0) *total = goff + btot;
+    if (b == (int)gridDim.x - 1 && threadIdx.x == 0) {
+        if (total_dev) *total_dev = goff + btot;
+        *total = goff + btot;
+    }
     if (p >= np) return;
     pos[p] = f ? k : -1;
     if (!f) return;
@@ -1216,10 +1220,10 @@ void launch_rows_build(const RowBuildArgs &a, hipStream_t s) {
 int select_rows_max_pairs() { return kSelectGroupsMax * kThreads; }
 
 void launch_select_rows(const RowBuildArgs &a, int np, const int *flags, const int *gcount, int *sel, int *pos,
-                        int *total, hipStream_t s) {
+                        int *total, hipStream_t s, int *total_dev) {
     if (np <= 0 || np > select_rows_max_pairs()) return;
     hipLaunchKernelGGL(k_select_rows, dim3(nblk(np, kThreads)), dim3(kThreads), 0, s, a, np, flags, gcount, sel, pos,
-                       total);
+                       total, total_dev);
 }
 
 

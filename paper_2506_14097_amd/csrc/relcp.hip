@@ -308,7 +308,7 @@ struct relcp_ctx {
     bool rowgraph_mode() const { return !resident_mode() && lcp_mode != 1; }
     void build_rowgraph(double dt);
     void rg_reserve(size_t slots);
-    void rg_prepare();
+    void rg_prepare(int mcap = -1);  // buffers for mcap rows (default m)
     bool rg_pre = false;  // the incidence build made this graph's slice widths
     bool rg_counted = false;  // the incidence build stored this graph's entry count
     int maxpk = 0;                       // bodies of the largest packing
@@ -387,7 +387,7 @@ struct relcp_ctx {
     void build_rows(int nsel, int rec, const double *snsd, const double *vc, bool warm, double dt);
     RowBuildArgs row_args(int nsel, int rec, const double *snsd, const double *vc, bool warm, double dt);
     void rebuild_csr();
-    void first_rows_csr();
+    void first_rows_csr(const int *m_dev, int mcap);
     void warm_start_rows(int m0, double dt);
     template <typename T>
     int solve(double dt, double tol, int &iters, double &res);
@@ -938,7 +938,7 @@ void relcp_ctx::rebuild_csr() {
 // candidate pairs' lists (built when the candidate list changed) filtered
 // through prow.  The same lists as rebuild_csr builds, bit for bit; the
 // row graph's slice widths come from its own pass.
-void relcp_ctx::first_rows_csr() {
+void relcp_ctx::first_rows_csr(const int *m_dev, int mcap) {
     if (!pcsr_valid) {
         pcsr_cnt.ensure(2 * (size_t)(n + 1));
         pcsr_off.ensure(n + 1);
@@ -950,17 +950,19 @@ void relcp_ctx::first_rows_csr() {
     }
     rg_valid = false;
     csr_off.ensure(n + 1);
-    csr_ent.ensure(2 * (size_t)std::max(m, 1));
+    csr_ent.ensure(2 * (size_t)std::max(mcap, 1));
     fl_cnt.ensure(n + 1);
     // in the row-graph mode the filter also stores the graph's entry count
     // (the ordered pairs of rows sharing a body) in the entry counter, so
     // the width pass need not add it up
     // (and the rows' entry counts and slice widths, as the width pass would)
-    rg_counted = rowgraph_mode() && m > 0;
+    // With m_dev the row count is still on its way to the host: the buffers
+    // are sized for mcap rows and the filter reads the count on the device.
+    rg_counted = rowgraph_mode() && mcap > 0;
     rg_pre = false;
-    if (rg_counted) rg_prepare();
+    if (rg_counted) rg_prepare(mcap);
     if (np > 0) {
-        const ListRowCounts rw{m, ria.p, rib.p, rg_width.p, rg_rcnt.p};
+        const ListRowCounts rw{mcap, ria.p, rib.p, rg_width.p, rg_rcnt.p, m_dev};
         filter_lists(n, pcsr_off.p, pcsr_ent.p, prow.p, fl_cnt.p, csr_off.p, csr_ent.p, scan_scratch, stream,
                      rg_counted ? rg_flags.p : nullptr, rg_counted ? &rw : nullptr);
         rg_pre = rg_counted;
@@ -1016,10 +1018,11 @@ void relcp_ctx::rg_reserve(size_t slots) {
 // overflow, which the solve checks at its first read-back (then re-sizes,
 // rebuilds and restarts).
 // buffers of the row graph's widths and entry counter
-void relcp_ctx::rg_prepare() {
-    const int ns = rowgraph_slices(m);
+void relcp_ctx::rg_prepare(int mcap) {
+    if (mcap < 0) mcap = m;
+    const int ns = rowgraph_slices(mcap);
     rg_width.ensure(ns + 1);
-    rg_rcnt.ensure(std::max(m, 1));
+    rg_rcnt.ensure(std::max(mcap, 1));
     rg_base.ensure(ns + 1);
     if (!rg_flags.p) {
         rg_flags.ensure(1);
@@ -1513,10 +1516,16 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
     // the rows are built by the same pass (room for every pair)
     prow.ensure(std::max(np, 1));
     const bool fused = fused_select && np > 0 && np <= select_rows_max_pairs();
+    // with the rows built on the device, their incidence lists are launched
+    // before the count reaches the host (they read it on the device), so
+    // the GPU keeps working through the host's wait
+    const bool early_lists = fused && first_lists;
     if (fused) {
         ensure_rows(np);
+        dtotal.ensure(4);
         launch_select_rows(row_args(0, 0, snsd0.p, nullptr, warm0, dt), np, pflag.p, pcnt.p, sel.p, prow.p, int_d,
-                           stream);
+                           stream, dtotal.p + 1);
+        if (early_lists) first_rows_csr(dtotal.p + 1, np);
     } else {
         compact_flags(pflag.p, np, pcnt.p, sel.p, int_d, scan_scratch, stream, nullptr, prow.p);
     }
@@ -1529,7 +1538,13 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         ensure_rows(m0);
         build_rows(m0, 0, snsd0.p, nullptr, warm0, dt);
     }
-    if (first_lists) first_rows_csr(); else rebuild_csr();
+    if (early_lists) {
+        if (m0 == 0) rg_counted = rg_pre = false;
+    } else if (first_lists) {
+        first_rows_csr(nullptr, m0);
+    } else {
+        rebuild_csr();
+    }
     if (need_feat) warm_start_rows(m0, dt);
     if (resident_mode()) rows_by_packing_init(m0);
     t_other += tm.ms();
