@@ -161,6 +161,12 @@ struct StartSrc {
     const PgdState *fin;
     const int *done;
     int last_par;
+    // FP64 starts (or null): the start pass also writes what the unpack of
+    // a solve that converges at its start would -- gamma (into the pass's
+    // save array), g into g_final and the work's per-block partial sums into
+    // work_final (work_blocks(m) slots) -- so that no unpack need follow
+    double *g_final = nullptr;
+    double *work_final = nullptr;
 };
 template <typename T>
 void launch_lcp_spmv(int mode, const RowGraphT<T> &G, const T *qv, const T *dA, const StartSrc &start,
@@ -202,18 +208,21 @@ int make_spmv_graph(const LcpDev<T> *D, int grid_rows, int k, hipGraphExec_t *ou
 // 1), or, while the done flag (if given) is not set, that of the last pass
 // launched (parity last_par); gam64 (or null) <- the same gamma in FP64;
 // work (or null): the per-block sums of gamma (g - qv) of launch_work
-// (work_blocks(m) slots).  check (or null): a solve of which only the start
-// pass ran (its partial sums in check->partials); the unpack reduces them as
-// the first iteration pass would and, if the start meets the tolerance,
-// records the final state and done flags and unpacks the start (else what
-// it writes is to be redone once the solve has been continued).  Only where
-// unpack_can_check(m).
+// (work_blocks(m) slots)
 template <typename T>
 void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, const T *g0, const T *g1,
                             const PgdState *fin, const int *done, int last_par, T *gam, T *g, double *gam64,
-                            hipStream_t s, const T *qv = nullptr, double *work = nullptr,
-                            const PgdCtl *check = nullptr);
+                            hipStream_t s, const T *qv = nullptr, double *work = nullptr);
+// whether launch_report_check can reduce the start pass of m rows (its
+// partial sums fit one workgroup's registers)
 bool unpack_can_check(int m);
+// The tail report (report.h) after checking a solve of which only the start
+// pass ran: its partial sums (C.partials) reduced in the order the first
+// iteration pass would, the state advanced, and the final state and done
+// flags recorded if the start meets the tolerance (else the caller finds the
+// solve unfinished and continues it).  One workgroup.
+struct TailReport;
+void launch_report_check(const TailReport &R, const PgdCtl &C, hipStream_t s);
 
 // Passes of the projected-gradient loop.  Iteration j (j = 1, 2, ...) is
 // scatter(mode 1, par = j & 1) then gather(mode 1, par = j & 1); a solve

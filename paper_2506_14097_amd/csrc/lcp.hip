@@ -25,6 +25,7 @@
 #include <type_traits>
 
 #include "lcp.h"
+#include "report.h"
 #include "scatter.h"
 
 namespace relcp {
@@ -975,10 +976,12 @@ __device__ inline void row_preload(const RowGraphT<T> &G, const T *__restrict__ 
 
 // projected steps, g' = qv + A gamma', the row's new state and its share
 // of the step-size sums (s^T D s, s^T y, y^T D^-1 y) and residual
+// (gv_out, gn_out: the new gamma and g also returned)
 template <typename T, int MODE, class SV>
 __device__ inline void row_finish(const RowPre<T> &P, T al, const RowStep<T> *__restrict__ zin,
                                   const SV &gam0, RowStep<T> *__restrict__ zout, T *__restrict__ gout,
-                                  int r, double &ss, double &sy, double &yy, double &res) {
+                                  int r, double &ss, double &sy, double &yy, double &res, T *gv_out = nullptr,
+                                  T *gn_out = nullptr) {
     // the diagonal first (A_rr, not stored in the graph), then the entries
     const T gv = MODE == 1 ? step_h(P.gm, P.hm, al) : clamp0(P.gm);
     T acc = P.dA * gv;
@@ -997,6 +1000,8 @@ __device__ inline void row_finish(const RowPre<T> &P, T al, const RowStep<T> *__
     const T gn = P.q + acc;
     zout[r] = RowStep<T>{gv, gn / P.dA};
     gout[r] = gn;
+    if (gv_out) *gv_out = gv;
+    if (gn_out) *gn_out = gn;
     const T dg = P.dA * gv;
     res = fmax(res, fabs((double)(dg < gn ? dg : gn)));
     if (MODE == 1) {
@@ -1065,7 +1070,8 @@ __global__ void __launch_bounds__(kThreads)
         al = (T)ns.alpha;
     }
     double ss = 0.0, sy = 0.0, yy = 0.0, res = 0.0;
-    if (act) row_finish<T, RM, SV>(P, al, zin, gam0, zout, gout, r, ss, sy, yy, res);
+    T gv = T(0), gn = T(0);
+    if (act) row_finish<T, RM, SV>(P, al, zin, gam0, zout, gout, r, ss, sy, yy, res, &gv, &gn);
     block_reduce4(ss, sy, yy, res, sh);
     if (threadIdx.x == 0) {
         double *p = pout + 4 * lb;
@@ -1074,6 +1080,40 @@ __global__ void __launch_bounds__(kThreads)
         p[2] = yy;
         p[3] = res;
     }
+    if (MODE == 3 && start.g_final) {
+        // what the unpack of a solve that converges here would write: gamma,
+        // g and the work's partial sums (the unpack's arithmetic, over the
+        // same 256 rows per block)
+        double w = 0.0, z0s = 0.0, z1s = 0.0, z2s = 0.0;
+        if (act) {
+            save[r] = (double)gv;
+            start.g_final[r] = (double)gn;
+            w = (double)gv * ((double)gn - (double)P.q);
+        }
+        block_reduce4(w, z0s, z1s, z2s, sh);
+        if (threadIdx.x == 0) start.work_final[lb] = w;
+    }
+}
+
+// The tail report after checking a solve of which only the start pass ran
+// (see launch_report_check).
+__global__ void __launch_bounds__(kThreads) k_report_check(TailReport R, PgdCtl C) {
+    __shared__ double sh[4][kWaves];
+    __shared__ PgdState ns;
+    PartialRegs pr;
+    load_partials(C, pr);
+    reduce_loaded(C, 1, pr, &ns, sh);
+    if (threadIdx.x == 0) {
+        C.S[1] = ns;
+        if (ns.conv) {
+            *C.fin = ns;
+            *C.done = 1;
+            if (C.fin_h) *C.fin_h = ns;
+            if (C.done_h) *C.done_h = 1;
+        }
+    }
+    __syncthreads();
+    tail_report(R);
 }
 
 // A pass whose parameters live in device memory (LcpDev), so that the
@@ -1135,35 +1175,13 @@ __global__ void __launch_bounds__(kThreads)
     k_rowstate_unpack(int m, const RowStep<T> *__restrict__ z0, const RowStep<T> *__restrict__ z1,
                       const T *__restrict__ g0, const T *__restrict__ g1, const PgdState *__restrict__ fin,
                       const int *__restrict__ done, int last_par, T *__restrict__ gam, T *__restrict__ g,
-                      double *__restrict__ gam64, const T *__restrict__ qv, double *__restrict__ work,
-                      PgdCtl C, int check) {
+                      double *__restrict__ gam64, const T *__restrict__ qv, double *__restrict__ work) {
     __shared__ double sh[4][kWaves];
-    __shared__ PgdState ns;
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     double w = 0.0, z0s = 0.0, z1s = 0.0, z2s = 0.0;
-    int conv = 0;
-    if (check) {
-        // no pass followed the start pass: reduce its partial sums here, as
-        // the first iteration pass would (same order), and stop the solve
-        // if its start meets the tolerance (else the caller finds it
-        // unfinished and continues it with passes)
-        PartialRegs pr;
-        load_partials(C, pr);
-        reduce_loaded(C, 1, pr, &ns, sh);
-        conv = ns.conv;
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            C.S[1] = ns;
-            if (ns.conv) {
-                *C.fin = ns;
-                *C.done = 1;
-                if (C.fin_h) *C.fin_h = ns;
-                if (C.done_h) *C.done_h = 1;
-            }
-        }
-    }
     if (r < m) {
         // a finished solve: the state of its final iterate; else that of the last pass launched
-        const bool odd = check ? (conv ? false : (last_par & 1)) : (done && !*done) ? (last_par & 1) : (fin->iter & 1);
+        const bool odd = (done && !*done) ? (last_par & 1) : (fin->iter & 1);
         const T v = (odd ? z1 : z0)[r].gam;
         const T gv = (odd ? g1 : g0)[r];
         gam[r] = v;
@@ -1391,14 +1409,17 @@ int make_spmv_graph(const LcpDev<T> *D, int grid_rows, int k, hipGraphExec_t *ou
 template <typename T>
 void launch_rowstate_unpack(int m, const RowStep<T> *z0, const RowStep<T> *z1, const T *g0, const T *g1,
                             const PgdState *fin, const int *done, int last_par, T *gam, T *g, double *gam64,
-                            hipStream_t s, const T *qv, double *work, const PgdCtl *check) {
-    const PgdCtl none{};
+                            hipStream_t s, const T *qv, double *work) {
     if (m > 0 || work)
         hipLaunchKernelGGL((k_rowstate_unpack<T>), dim3(work_blocks(m)), dim3(kThreads), 0, s, m, z0, z1, g0, g1,
-                           fin, done, last_par, gam, g, gam64, qv, work, check ? *check : none, check ? 1 : 0);
+                           fin, done, last_par, gam, g, gam64, qv, work);
 }
 
 bool unpack_can_check(int m) { return work_blocks(m) <= kPartRegs * kThreads; }
+
+void launch_report_check(const TailReport &R, const PgdCtl &C, hipStream_t s) {
+    hipLaunchKernelGGL(k_report_check, dim3(1), dim3(kThreads), 0, s, R, C);
+}
 
 #define RELCP_INST(T)                                                                                              \
     template void launch_lcp_scatter<T>(int, const RowsT<T> &, const BodiesT<T> &, const PgdCtl &, int,           \
@@ -1410,7 +1431,7 @@ bool unpack_can_check(int m) { return work_blocks(m) <= kPartRegs * kThreads; }
                                      int, hipStream_t, double *);                                                 \
     template void launch_rowstate_unpack<T>(int, const RowStep<T> *, const RowStep<T> *, const T *, const T *,    \
                                             const PgdState *, const int *, int, T *, T *, double *, hipStream_t,  \
-                                            const T *, double *, const PgdCtl *);                                 \
+                                            const T *, double *);                                                 \
     template void launch_set_lcpdev<T>(LcpDev<T> *, const LcpDev<T> &, hipStream_t);                               \
     template void launch_spmv_dev<T>(const LcpDev<T> *, int, int, hipStream_t);                                    \
     template int make_spmv_graph<T>(const LcpDev<T> *, int, int, hipGraphExec_t *);

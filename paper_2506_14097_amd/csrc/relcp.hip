@@ -404,7 +404,9 @@ struct relcp_ctx {
     struct RgRun {
         int j = 1, chunk = 2, pass_mode = 1;
         bool fresh = false;  // the graph was assembled by this solve's start
-        bool check = false;  // no pass after the start: the unpack checks convergence
+        // the FP64 polish ran only its start pass, which wrote the unpack's
+        // results; the tail's report checks its convergence
+        bool final_start = false;
     };
     RgRun rgr[2];
     template <typename T>
@@ -422,7 +424,7 @@ struct relcp_ctx {
     void rg_passes(const RgBufs<T> &B, const RowsT<T> &R, int k);
     template <typename T>
     void rg_start(const RowsT<T> &R, double dt, double tol, const double *gam0, double *save,
-                  const StartSrc *src = nullptr);
+                  const StartSrc *src = nullptr, bool allow_final = false);
     DBuf<double> gam_save;  // the start of the first solve of a recursion, for a restart
     template <typename T>
     void rg_unpack(const RowsT<T> &R, const BodiesT<T> &Bd, double tol);
@@ -1255,7 +1257,7 @@ template <typename T>
 // Start of a row-graph solve from gam0, or from src (with gam0 null): the
 // final state of the FP32 solve, for the FP64 polish.
 void relcp_ctx::rg_start(const RowsT<T> &R, double dt, double tol, const double *gam0, double *save,
-                         const StartSrc *src) {
+                         const StartSrc *src, bool allow_final) {
     const int pk = sizeof(T) == 8 ? 1 : 0;
     RgRun &st = rgr[pk];
     st.fresh = false;
@@ -1264,22 +1266,34 @@ void relcp_ctx::rg_start(const RowsT<T> &R, double dt, double tol, const double 
         st.fresh = true;
     }
     const RgBufs<T> B = rg_bufs<T>(R, tol);
-    // the start pass also resets the control block
-    timed(11, [&] {
-        const StartSrc start = src ? *src : StartSrc{gam0, {nullptr, nullptr}, nullptr, nullptr, 0};
-        launch_lcp_spmv<T>(0, B.G, R.qv, R.dA, start, nullptr, nullptr, B.z0, B.g0, B.C, B.part, 0, stream, save);
-    });
-    st.j = 1;
     // the last solve's count, the pass that sees convergence and headroom: a
     // short first chunk costs a wait and, in a step, the work launched behind
     // it, while a spare pass returns at once
     st.chunk = std::max(2, std::min(64, last_iters[pk] + std::max(3, last_iters[pk] / 4) + 1));
-    // a solve (the polish) that last converged at its start: the pass that
-    // sees it and a spare one; for an FP64 solve (always unpacked right
-    // after its start) none once it has done so several times in a row: the
-    // unpack then sees it (a miss costs a wait)
-    if (last_iters[pk] == 0) st.chunk = sizeof(T) == 8 && zero_run[pk] >= 4 && unpack_can_check(m) ? 0 : 2;
-    st.check = st.chunk == 0;
+    // a solve that last converged at its start: the pass that sees it and a
+    // spare one; only the first once it has done so several times in a row.
+    // The FP64 polish of a step (allow_final) then runs no pass at all: its
+    // start pass writes what the unpack would, and the tail's report checks
+    // its convergence (a miss costs a wait, as a short chunk does)
+    st.final_start = false;
+    if (last_iters[pk] == 0) {
+        st.chunk = zero_run[pk] >= 4 ? 1 : 2;
+        if (sizeof(T) == 8 && src && allow_final && zero_run[pk] >= 4 && unpack_can_check(m)) {
+            st.chunk = 0;
+            st.final_start = true;
+            work_out.ensure(work_blocks(m));
+        }
+    }
+    // the start pass also resets the control block
+    timed(11, [&] {
+        StartSrc start = src ? *src : StartSrc{gam0, {nullptr, nullptr}, nullptr, nullptr, 0};
+        if (st.final_start) {
+            start.g_final = rg64.p;
+            start.work_final = work_out.p;
+        }
+        launch_lcp_spmv<T>(0, B.G, R.qv, R.dA, start, nullptr, nullptr, B.z0, B.g0, B.C, B.part, 0, stream, save);
+    });
+    st.j = 1;
     // over many blocks the partial sums are reduced once per pass by a
     // separate launch instead of by every block
     st.pass_mode = B.C.nbg >= reduce_split_blocks ? 2 : 1;
@@ -1297,13 +1311,11 @@ void relcp_ctx::rg_unpack(const RowsT<T> &R, const BodiesT<T> &Bd, double tol) {
     // FP64 also forms the work gamma^T A gamma's partial sums (the trial
     // forms the contact velocities K D gamma itself)
     if constexpr (sizeof(T) == 8) work_out.ensure(work_blocks(m));
-    // (a solve of which only the start pass ran: the unpack checks it, once)
-    PgdCtl c0 = B.C;
-    c0.partials = B.part;
+    // (a polish of which only the start pass ran wrote the results itself)
+    if (rgr[pk].final_start) return;
     launch_rowstate_unpack<T>(m, B.z0, B.z1, B.g0, B.g1, B.C.fin, B.C.done, (rgr[pk].j - 1) & 1, R.gam, R.g,
                               sizeof(T) == 4 ? rgam64.p : nullptr, stream, sizeof(T) == 8 ? R.qv : nullptr,
-                              sizeof(T) == 8 ? work_out.p : nullptr, rgr[pk].check ? &c0 : nullptr);
-    rgr[pk].check = false;
+                              sizeof(T) == 8 ? work_out.p : nullptr);
 }
 
 // After a wait: true if the last graph assembly overflowed its slots (then
@@ -1596,7 +1608,16 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
             rep.ng = np > 0 ? flag_groups(np) : 0;
             rep.gcount = pcnt.p;
             rep.count = int_d;
-            hipLaunchKernelGGL(k_report, dim3(1), dim3(256), 0, stream, rep);
+            if (rgr[1].final_start) {
+                // the polish ran only its start pass: the report checks it
+                const RgBufs<double> B64 = rg_bufs<double>(rows_of<double>(), tol);
+                PgdCtl c0 = B64.C;
+                c0.partials = B64.part;
+                launch_report_check(rep, c0, stream);
+                rgr[1].final_start = false;
+            } else {
+                hipLaunchKernelGGL(k_report, dim3(1), dim3(256), 0, stream, rep);
+            }
         };
         bool tail_ready = false;  // the tail ran on the final multipliers and was waited for
         if (spec) {
@@ -1617,7 +1638,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
                     // FP64, in the multipliers
                     const RgBufs<float> Bf = rg_bufs<float>(R32, tol);
                     const StartSrc src{nullptr, {Bf.z0, Bf.z1}, Bf.C.fin, Bf.C.done, (rgr[0].j - 1) & 1};
-                    rg_start<double>(R64, dt, tol, nullptr, rgam64.p, &src);
+                    rg_start<double>(R64, dt, tol, nullptr, rgam64.p, &src, true);
                 } else {
                     rg_start<double>(R64, dt, tol, g0, keep);
                 }
