@@ -51,7 +51,7 @@ FP64_PEAK_TFLOPS = 78.6
 # a plain copy of known size reads), recorded in
 # profiles/lcp_rowgraph_pass_100k_hbm_traffic.md for the kernel source with
 # the given sha256 prefix (stale once it changes).
-MEASURED_TRAFFIC = {"sha256_prefix": "72114b35dcf2815f", "lcp_rowgraph": 1.3886e7}
+MEASURED_TRAFFIC = {"sha256_prefix": "266eee4bab36ac3a", "lcp_rowgraph": 1.3898e7}
 
 
 # timing class -> kernel
@@ -706,7 +706,7 @@ def main():
                     help="only run a device-to-device copy of this many MB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        print("bench.py: the library runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -135,7 +135,17 @@ typedef struct {
 
 /* Create a context (Sec. 2.1.1 state, Sec. 2.1.2 laws of motion).  Validates
  * the inputs (RELCP_E_INVALID), allocates device buffers (RELCP_E_OOM) and
- * uploads the state once.  *out is set on success only. */
+ * uploads the state once.  *out is set on success only.
+ * Environment read here (not in the paper: execution only; every setting
+ * gives the same results, bit for bit, and exists to test one path against
+ * the other or to force a rare one): RELCP_REDUCE_SPLIT_BLOCKS (see
+ * relcp_set_lcp_config); RELCP_RG_SLOTS_PER_ROW, the row graph's first
+ * estimate of entry slots per row (default 16; an overflow re-sizes and
+ * restarts the solve); RELCP_FIRST_LISTS = 0 builds the iteration-0 rows'
+ * incidence lists from the rows (atomic slots and a sort) instead of
+ * filtering the candidate pairs' lists (1, default); RELCP_FUSED_SELECT = 0
+ * compacts the iteration-0 pairs before building their rows instead of
+ * selecting and building them in one pass (1, default). */
 RELCP_API int relcp_create(const relcp_bodies *bodies, const relcp_shapes *shapes, const relcp_params *params,
                  relcp_ctx **out);
 /* Release a context and all of its device buffers (not in the paper:
