@@ -140,8 +140,8 @@ typedef struct {
  * gives the same results, bit for bit, and exists to test one path against
  * the other or to force a rare one): RELCP_REDUCE_SPLIT_BLOCKS (see
  * relcp_set_lcp_config); RELCP_RG_SLOTS_PER_ROW, the row graph's first
- * estimate of entry slots per row (default 16; an overflow re-sizes and
- * restarts the solve); RELCP_FIRST_LISTS = 0 builds the iteration-0 rows'
+ * stride of entry slots per row (default 16; a row with more entries raises
+ * it and restarts the solve); RELCP_FIRST_LISTS = 0 builds the iteration-0 rows'
  * incidence lists from the rows (atomic slots and a sort) instead of
  * filtering the candidate pairs' lists (1, default); RELCP_FUSED_SELECT = 0
  * compacts the iteration-0 pairs before building their rows instead of

@@ -196,13 +196,12 @@ bool compact_flags(const int *flags, int n, const int *bcount, int *out, int *to
 // off (n + 1) and ent (the kept entries) the filtered lists; pairs_out (a
 // device int, or null) <- the sum over items of c (c - 1), c the kept count.
 // rows (or null): m rows, each kept once in the lists of its two items ia,
-// ib; rcnt[r] <- the other kept entries of those two lists (c_a + c_b - 2),
-// width[s] <- their largest over rows 64 s .. 64 s + 63, width[ceil(m/64)]
-// <- 0.  scratch grows as needed.
+// ib; rcnt[r] <- the other kept entries of those two lists (c_a + c_b - 2).
+// scratch grows as needed.
 struct ListRowCounts {
     int m;               // rows, or with m_dev the rows' capacity (the grid covers it)
     const int *ia, *ib;
-    int *width, *rcnt;
+    int *rcnt;
     const int *m_dev;    // the row count on the device (<= m), or null
 };
 void filter_lists(int n, const int *boff, const int *bent, const int *pos, int *cnt, int *off, int *ent,

@@ -68,9 +68,10 @@ void launch_select_rows(const RowBuildArgs &a, int np, const int *flags, const i
                         int *total, hipStream_t s, int *total_dev = nullptr);
 // CSR of the rows at each body; cleared: cnt and cursor (2 (nb + 1) ints)
 // are known to be zero (every build leaves them so).  rg (or null): also
-// the row-graph slice widths with their sum (as launch_rowgraph_width).
+// the row graph's entry count of each row with their sum (as
+// launch_rowgraph_counts).
 struct CsrRowGraphOut {
-    int *width, *count, *rcnt;
+    int *count, *rcnt;
 };
 void launch_csr(int nb, int m, const int *ia, const int *ib, int *cnt, int *off, int *cursor, int *ent,
                 bool cleared, DBuf<int> &scan_scratch, hipStream_t s, const CsrRowGraphOut *rg = nullptr);
@@ -99,16 +100,19 @@ struct PgdCtl {
 // entry per pair of distinct rows sharing a body and per shared body (two
 // rows sharing both bodies have two entries); the diagonal is the rows'
 // A_aa, applied by the pass itself.
-// Sliced ELL: slice s holds rows [64 s, 64 s + 64) with width w_s, entry k
-// of row r at 64 base[s] + 64 k + r % 64 (base = exclusive scan of the
-// widths); padding entries point at the row itself with value 0.
+// Sliced ELL with a fixed stride S: slice s holds rows [64 s, 64 s + 64),
+// entry k of row r at 64 (s S + k) + r % 64, so that no load of the graph
+// waits on another (no slice offsets).  A row with more than S entries does
+// not fit: the assembly skips it and reports the overflow, and the passes
+// read no entry of it (the solve is re-sized and restarted).
 template <typename T>
 struct RowGraphT {
     int m;
-    const int *base, *col;
+    int stride;  // S: entry slots per row
+    const int *col;
     const T *val;
-    size_t cap;  // entry slots allocated: a slice past them was not filled and is skipped
-    const int *rcnt;  // entries of each row (slots past them, up to the slice's width, are not written)
+    size_t cap;  // entry slots allocated (at least 64 S per slice)
+    const int *rcnt;  // entries of each row (slots past them are not written)
 };
 
 // Iteration state of a row seen by the rows it couples to: multiplier and
@@ -125,11 +129,13 @@ struct RowGraphFill {
     int ldb;
     const double *K;   // 9 comps, ld = ldb
     const int *off, *ent;
-    const int *base;
+    const int *rcnt;   // entries of each row (from the count pass)
+    int stride;        // entry slots per row (RowGraphT)
     double dt;
     size_t cap;        // entry slots allocated
-    int *count;        // device entry counter of the width pass (read here, then cleared for the next build)
-    int *report;       // host-mapped: [0] slots needed / 64, [1] entries, [2] set to 1 on overflow
+    int *count;        // device entry counter of the count pass (read here, then cleared for the next build)
+    int *need;         // device: raised to the entry count of every row that does not fit (left otherwise)
+    int *report;       // host-mapped: [1] entries, [2] set to 1 on overflow
     int *col;
     double *val64;
     float *val32;
@@ -137,10 +143,9 @@ struct RowGraphFill {
 
 int rowgraph_slices(int m);
 // rcnt[r] = count of other rows at row r's two bodies (its entries);
-// width[s] = their largest over slice s; *count += their sum, unless count is
-// null
-void launch_rowgraph_width(int m, const int *ia, const int *ib, const int *off, int *width, int *count, int *rcnt,
-                           hipStream_t s);
+// *count += their sum, unless count is null
+void launch_rowgraph_counts(int m, const int *ia, const int *ib, const int *off, int *count, int *rcnt,
+                            hipStream_t s);
 void launch_rowgraph_fill(const RowGraphFill &a, hipStream_t s);
 // One pass of the row-graph LCP loop over m rows with A in G and the
 // diagonal dA.  mode 0: start, gamma0 = max(0, start) (FP64 start rounded to
@@ -181,7 +186,8 @@ struct LcpDev {
     int m, nbg, cap;
     double tol;
     int stall;  // as PgdCtl::stall
-    const int *base, *col;
+    int stride;
+    const int *col;
     const T *val;
     size_t slots;
     const int *rcnt;

@@ -201,15 +201,13 @@ __global__ void k_csr_count(int m, const int *__restrict__ ia, const int *__rest
     atomicAdd(cnt + ib[r], 1);
 }
 
-// Incidence entries of each row at its two bodies.  With width set (the
-// row-graph layout), also the row-graph slice widths: the largest count of
-// other rows at a row's two bodies over each slice of 64 rows (the 64 lanes
-// of a wave: blocks start at multiples of 256 rows), and their sum into
-// *count.
+// Incidence entries of each row at its two bodies.  With rcnt set (the
+// row-graph layout), also each row's count of other rows at its two bodies
+// (its entries in the row graph) and their sum into *count.
 __global__ void __launch_bounds__(256) k_csr_fill(int m, const int *__restrict__ ia, const int *__restrict__ ib,
                                                   const int *__restrict__ off, int *__restrict__ cursor,
-                                                  int *__restrict__ ent, int *__restrict__ width,
-                                                  int *__restrict__ count, int *__restrict__ rcnt) {
+                                                  int *__restrict__ ent, int *__restrict__ count,
+                                                  int *__restrict__ rcnt) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     int w = 0;
     const int a = r < m ? ia[r] : -1;
@@ -226,22 +224,14 @@ __global__ void __launch_bounds__(256) k_csr_fill(int m, const int *__restrict__
         ent[off[a] + slot] = r << 1;
         ent[off[b] + atomicAdd(cursor + b, 1)] = (r << 1) | 1;
         w = off[a + 1] - off[a] + off[b + 1] - off[b] - 2;  // the row itself at a and at b: the diagonal
-        if (width) rcnt[r] = w;
+        if (rcnt) rcnt[r] = w;
     }
-    if (!width) return;
+    if (!rcnt) return;
     __shared__ int bsum[4];
     int sum = w;
-    for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) {
-        w = max(w, __shfl_xor(w, o, RELCP_WAVE));
-        sum += __shfl_xor(sum, o, RELCP_WAVE);
-    }
-    const int ns = (m + RELCP_WAVE - 1) / RELCP_WAVE;
+    for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, RELCP_WAVE);
     const int wv = threadIdx.x / RELCP_WAVE;
-    if (lane == 0) {
-        if (r / RELCP_WAVE < ns) width[r / RELCP_WAVE] = w;
-        bsum[wv] = sum;
-    }
-    if (r == 0) width[ns] = 0;
+    if (lane == 0) bsum[wv] = sum;
     __syncthreads();
     if (threadIdx.x == 0) {
         const int t = bsum[0] + bsum[1] + bsum[2] + bsum[3];
@@ -722,10 +712,9 @@ __global__ void __launch_bounds__(kThreads) k_pgd_reduce(PgdCtl C, int par) {
 // ---------------------------------------------------------------------------
 // row-graph LCP: A = dt D^T K D assembled over rows, one pass per iteration
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_rowgraph_width(int m, const int *__restrict__ ia,
-                                                             const int *__restrict__ ib, const int *__restrict__ off,
-                                                             int *__restrict__ width, int *__restrict__ count,
-                                                             int *__restrict__ rcnt) {
+__global__ void __launch_bounds__(kThreads) k_rowgraph_counts(int m, const int *__restrict__ ia,
+                                                              const int *__restrict__ ib, const int *__restrict__ off,
+                                                              int *__restrict__ count, int *__restrict__ rcnt) {
     const int r = blockIdx.x * kThreads + threadIdx.x;
     int w = 0;
     if (r < m) {
@@ -733,27 +722,19 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_width(int m, const int *_
         w = off[a + 1] - off[a] + off[b + 1] - off[b] - 2;  // the row itself at a and at b: the diagonal
         rcnt[r] = w;
     }
+    if (!count) return;
     __shared__ int bsum[kWaves];
     int sum = w;
-    for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) {
-        w = max(w, __shfl_xor(w, o, RELCP_WAVE));
-        sum += __shfl_xor(sum, o, RELCP_WAVE);
-    }
-    const int ns = (m + RELCP_WAVE - 1) / RELCP_WAVE;
+    for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, RELCP_WAVE);
     const int lane = threadIdx.x & (RELCP_WAVE - 1), wv = threadIdx.x / RELCP_WAVE;
-    if (lane == 0) {
-        if (r / RELCP_WAVE < ns) width[r / RELCP_WAVE] = w;
-        bsum[wv] = sum;
-    }
-    if (r == 0) width[ns] = 0;
+    if (lane == 0) bsum[wv] = sum;
     __syncthreads();
     if (threadIdx.x == 0) {
         int t = 0;
         for (int k = 0; k < kWaves; ++k) t += bsum[k];
-        if (t && count) atomicAdd(count, t);
+        if (t) atomicAdd(count, t);
     }
 }
-
 
 // Entries of the row graph, one thread per incidence entry in CSR order
 // (entry e of body c: row r, side): the thread forms its own column of D at
@@ -761,8 +742,9 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_width(int m, const int *_
 // its block, and writes row r's entries at c: for every other entry j of c,
 // in incidence order, column r_j and value dt J_j . K_c J_e (so row r holds
 // its entries at body a, then those at body b).  The slots past a row's
-// entries, up to its slice's width, are not written: the passes read a
-// row's entries only (its count from the width pass).  A column of
+// entries are not written: the passes read a row's entries only (its count
+// from the count pass).  A row with more entries than the stride is left
+// out (its count raises *need, and the overflow is reported).  A column of
 // an entry outside the block (a body that straddles two blocks) is formed
 // again from the rows.  The diagonal A_rr is not stored: a pass takes it
 // from the rows' A_aa.
@@ -798,14 +780,23 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_fill_entries(RowGraphFill
     __syncthreads();
     if (!act) return;
     const int lane = r & (RELCP_WAVE - 1), sl = r / RELCP_WAVE;
-    const int b0 = A.base[sl], w = A.base[sl + 1] - b0;
+    const int S = A.stride;
+    const size_t b0 = (size_t)sl * S;
     if (r == 0 && side == 0) {
-        // the width pass and the scan are complete: report and clear its counter
-        A.report[0] = A.base[(A.m + RELCP_WAVE - 1) / RELCP_WAVE];
+        // the count pass is complete: report and clear its counter
         A.report[1] = *A.count;
         *A.count = 0;
     }
-    if ((size_t)RELCP_WAVE * (b0 + w) > A.cap) {
+    int k = 0;
+    if (side) {
+        const int a = A.ia[r];
+        k = A.off[a + 1] - A.off[a] - 1;  // the slots of body a's other rows
+    }
+    const int j0 = A.off[c], j1 = A.off[c + 1];
+    // a row that does not fit is left out by both of its entries' threads
+    const int cnt = A.rcnt[r];
+    if (cnt > S || (size_t)RELCP_WAVE * (b0 + S) > A.cap) {
+        atomicMax(A.need, cnt);
         A.report[2] = 1;
         return;
     }
@@ -821,12 +812,6 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_fill_entries(RowGraphFill
     const d3 Kn = mk(sr * K[c] * nr.x, sr * K[lb + c] * nr.y, sr * K[2 * lb + c] * nr.z);
     const sym3 Kr{K[3 * lb + c], K[4 * lb + c], K[5 * lb + c], K[6 * lb + c], K[7 * lb + c], K[8 * lb + c]};
     const d3 Ku = sr * mul(Kr, ur);
-    int k = 0;
-    if (side) {
-        const int a = A.ia[r];
-        k = A.off[a + 1] - A.off[a] - 1;  // the slots of body a's other rows
-    }
-    const int j0 = A.off[c], j1 = A.off[c + 1];
     for (int j = j0; j < j1; ++j) {
         if (j == e) continue;
         double Jj[6];
@@ -842,7 +827,7 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_fill_entries(RowGraphFill
         }
         const double v =
             A.dt * (Jj[0] * Kn.x + Jj[1] * Kn.y + Jj[2] * Kn.z + Jj[3] * Ku.x + Jj[4] * Ku.y + Jj[5] * Ku.z);
-        const size_t at = (size_t)RELCP_WAVE * (b0 + k) + lane;
+        const size_t at = (size_t)RELCP_WAVE * (b0 + (size_t)k) + lane;
         col[at] = cj;
         v64[at] = v;
         v32[at] = (float)v;
@@ -885,8 +870,7 @@ struct StartF32 {
 
 template <typename T>
 struct RowPre {
-    int w;    // the slice's width (the same in every lane of the wave)
-    int cnt;  // this row's entries (<= w)
+    int cnt;  // this row's entries (<= the stride)
     const int *col;
     const T *val;
     T gm, hm, gold, dA, q;
@@ -894,18 +878,12 @@ struct RowPre {
     T vj[kPre], gj[kPre], hj[kPre];
 };
 
-// Stage A of a row's loads: the slice's base and width (scalar) and the
-// row's own state; nothing here waits on another load of the pass.
+// Stage A of a row's loads: the row's own state; nothing here waits on
+// another load of the pass.
 template <typename T, int MODE, class SV>
 __device__ inline void row_preload_a(const RowGraphT<T> &G, const T *__restrict__ qv, const T *__restrict__ dA0,
                                      const SV &gam0, const RowStep<T> *__restrict__ zin,
-                                     const T *__restrict__ gin, int r, RowPre<T> &P, int &b0) {
-    // one slice per wave: its base and width are the same in every lane, so
-    // they are held in scalar registers and the loops over entries below
-    // branch uniformly
-    const int sl = __builtin_amdgcn_readfirstlane(r / RELCP_WAVE);
-    b0 = __builtin_amdgcn_readfirstlane(G.base[sl]);
-    P.w = __builtin_amdgcn_readfirstlane(G.base[sl + 1]);
+                                     const T *__restrict__ gin, int r, RowPre<T> &P) {
     P.cnt = G.rcnt[r];
     P.dA = dA0[r];
     P.q = qv[r];
@@ -922,21 +900,22 @@ __device__ inline void row_preload_a(const RowGraphT<T> &G, const T *__restrict_
 }
 
 // Stage B: the first kPre entries of the row and the states of the rows
-// they point at (two dependent loads).
+// they point at (two dependent loads).  The slice's slots are at a fixed
+// offset (the stride is a launch argument, the same in every lane).
 template <typename T, int MODE, class SV>
 __device__ inline void row_preload_b(const RowGraphT<T> &G, const SV &gam0, const RowStep<T> *__restrict__ zin, int r,
-                                     RowPre<T> &P, int b0) {
+                                     RowPre<T> &P) {
     const int lane = r & (RELCP_WAVE - 1);
-    P.w -= b0;
-    // an overflowed assembly left this slice unwritten: no entries (the
-    // caller sees the overflow report, re-sizes and starts the solve over)
-    if ((size_t)RELCP_WAVE * (b0 + P.w) > G.cap) P.w = 0;
+    const int S = G.stride;
+    const size_t b0 = (size_t)(r / RELCP_WAVE) * S;
+    // a row that did not fit, or a slice past the allocation: no entries
+    // (the caller sees the overflow report, re-sizes and starts over)
+    if (P.cnt > S || (size_t)RELCP_WAVE * (b0 + S) > G.cap) P.cnt = 0;
     P.col = G.col + (size_t)RELCP_WAVE * b0 + lane;
     P.val = G.val + (size_t)RELCP_WAVE * b0 + lane;
     // slots past the row's entries are not read (zero value, zero neighbour
-    // state); past the slice's width no lane has any (a uniform branch)
-    if (P.w == 0) P.cnt = 0;
-    const int kp = P.w < kPre ? P.w : kPre;
+    // state); past the stride no lane has any (a uniform branch)
+    const int kp = S < kPre ? S : kPre;
 #pragma unroll
     for (int k = 0; k < kPre; ++k) {
         if (k < kp && k < P.cnt) {
@@ -969,9 +948,8 @@ template <typename T, int MODE, class SV>
 __device__ inline void row_preload(const RowGraphT<T> &G, const T *__restrict__ qv, const T *__restrict__ dA0,
                                    const SV &gam0, const RowStep<T> *__restrict__ zin,
                                    const T *__restrict__ gin, int r, RowPre<T> &P) {
-    int b0;
-    row_preload_a<T, MODE, SV>(G, qv, dA0, gam0, zin, gin, r, P, b0);
-    row_preload_b<T, MODE, SV>(G, gam0, zin, r, P, b0);
+    row_preload_a<T, MODE, SV>(G, qv, dA0, gam0, zin, gin, r, P);
+    row_preload_b<T, MODE, SV>(G, gam0, zin, r, P);
 }
 
 // projected steps, g' = qv + A gamma', the row's new state and its share
@@ -1033,8 +1011,7 @@ __global__ void __launch_bounds__(kThreads)
     SV gam0{};
     if (START) gam0 = SV::from(start);
     // loads that depend on no other load of the pass go out first: the last
-    // pass's partial sums, the row's own state, the slice's base and the
-    // done flag; a pass after convergence leaves once the flag is in
+    // pass's partial sums, the row's own state and the done flag; a pass after convergence leaves once the flag is in
     // Lanes past the last row load the last row (their results are never
     // written), so the loads need no branch and nothing waits for them
     // before they are used.
@@ -1043,10 +1020,9 @@ __global__ void __launch_bounds__(kThreads)
     const int done = START ? 0 : __builtin_amdgcn_readfirstlane(*C.done);
     const int rl = act ? r : G.m - 1;
     RowPre<T> P;
-    int b0 = 0;
-    if (G.m > 0) row_preload_a<T, RM, SV>(G, qv, dA0, gam0, zin, gin, rl, P, b0);
+    if (G.m > 0) row_preload_a<T, RM, SV>(G, qv, dA0, gam0, zin, gin, rl, P);
     if (done) return;
-    if (G.m > 0) row_preload_b<T, RM, SV>(G, gam0, zin, rl, P, b0);
+    if (G.m > 0) row_preload_b<T, RM, SV>(G, gam0, zin, rl, P);
     if (START && save && act) save[r] = gam0[r];  // the start, kept for a restart
     T al = T(0);
     if (MODE == 2) {
@@ -1100,6 +1076,9 @@ __global__ void __launch_bounds__(kThreads)
 __global__ void __launch_bounds__(kThreads) k_report_check(TailReport R, PgdCtl C) {
     __shared__ double sh[4][kWaves];
     __shared__ PgdState ns;
+    // the report's loads and the partial sums' go out together
+    TailRegs tr;
+    tail_preload(R, tr);
     PartialRegs pr;
     load_partials(C, pr);
     reduce_loaded(C, 1, pr, &ns, sh);
@@ -1113,7 +1092,7 @@ __global__ void __launch_bounds__(kThreads) k_report_check(TailReport R, PgdCtl 
         }
     }
     __syncthreads();
-    tail_report(R);
+    tail_report(R, tr);
 }
 
 // A pass whose parameters live in device memory (LcpDev), so that the
@@ -1129,7 +1108,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_dev(const LcpDev<T> *__restri
     if (*d.done) return;
     const int nbg = d.nbg;
     if ((int)blockIdx.x >= nbg) return;
-    const RowGraphT<T> G{d.m, d.base, d.col, d.val, d.slots, d.rcnt};
+    const RowGraphT<T> G{d.m, d.stride, d.col, d.val, d.slots, d.rcnt};
     const int lb = xcd_block(blockIdx.x, nbg);  // the same order as the per-pass launch over nbg blocks
     const int r = lb * kThreads + threadIdx.x;
     const bool act = r < d.m;
@@ -1254,7 +1233,7 @@ void launch_csr(int nb, int m, const int *ia, const int *ib, int *cnt, int *off,
     exclusive_scan(cnt, off, nb + 1, nullptr, scan_scratch, s);
     if (m > 0) {
         hipLaunchKernelGGL(k_csr_fill, dim3(nblk(m, 256)), dim3(256), 0, s, m, ia, ib, off, cursor, ent,
-                           rg ? rg->width : nullptr, rg ? rg->count : nullptr, rg ? rg->rcnt : nullptr);
+                           rg ? rg->count : nullptr, rg ? rg->rcnt : nullptr);
         hipLaunchKernelGGL(k_csr_sort, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, off, ent, cnt, cursor);
     }
 }
@@ -1333,10 +1312,10 @@ void launch_pgd_finalize(const PgdCtl &C, int par, hipStream_t s) {
 
 int rowgraph_slices(int m) { return (m + RELCP_WAVE - 1) / RELCP_WAVE; }
 
-void launch_rowgraph_width(int m, const int *ia, const int *ib, const int *off, int *width, int *count, int *rcnt,
-                           hipStream_t s) {
-    launch_k(k_rowgraph_width, dim3(nblk(m > 0 ? m : 1, kThreads)), dim3(kThreads), 0, s, m, ia, ib, off,
-                       width, count, rcnt);
+void launch_rowgraph_counts(int m, const int *ia, const int *ib, const int *off, int *count, int *rcnt,
+                            hipStream_t s) {
+    launch_k(k_rowgraph_counts, dim3(nblk(m > 0 ? m : 1, kThreads)), dim3(kThreads), 0, s, m, ia, ib, off, count,
+             rcnt);
 }
 
 

@@ -261,7 +261,7 @@ struct relcp_ctx {
     // over all rows), 2 = resident (one workgroup per packing, one launch),
     // 3 = row graph (A assembled over rows, one pass per iteration)
     int lcp_mode = 0, res_block = 256, res_lds = 1;
-    DBuf<int> rg_width, rg_base, rg_col, rg_flags;  // flags: [0] entry count, [1] overflow
+    DBuf<int> rg_col, rg_flags;  // flags: [0] entry count, [1] largest count of a row that did not fit
     DBuf<int> rg_rcnt;  // entries of each row
     DBuf<double> rg_val64;
     DBuf<float> rg_val32;
@@ -279,9 +279,9 @@ struct relcp_ctx {
     // (at most 1024: a pass that reduces by itself holds the partial sums of
     // up to 4 x 256 blocks in registers)
     int reduce_split_blocks = std::min(1024, env_int("RELCP_REDUCE_SPLIT_BLOCKS", 1024));
-    // first estimate of row-graph entry slots per row (RELCP_RG_SLOTS_PER_ROW);
-    // an assembly that does not fit is re-sized and its solve restarted
-    int rg_slots_per_row = env_int("RELCP_RG_SLOTS_PER_ROW", 16);
+    // the row graph's entry slots per row, at first RELCP_RG_SLOTS_PER_ROW: an
+    // assembly with a row that does not fit raises it and restarts its solve
+    int rg_stride = env_int("RELCP_RG_SLOTS_PER_ROW", 16);
     // the first rows' incidence lists filtered from the candidate pairs' (1)
     // or built from the rows (0) (RELCP_FIRST_LISTS); the same lists
     int first_lists = env_int("RELCP_FIRST_LISTS", 1, 0);
@@ -369,7 +369,7 @@ struct relcp_ctx {
         boff_d.release(); roff.release(); rlist.release(); rlist2.release(); rcnt.release(); rE.release();
         pk_state.release();
         mlp_w.release(); feat.release(); rowscale.release();
-        rg_width.release(); rg_base.release(); rg_col.release(); rg_flags.release(); rg_val64.release();
+        rg_col.release(); rg_flags.release(); rg_val64.release();
         rg_rcnt.release();
         rg_val32.release(); z64.release(); z32.release(); zg64.release(); zg32.release();
         lcpdev64.release(); lcpdev32.release();
@@ -928,7 +928,7 @@ void relcp_ctx::rebuild_csr() {
     rg_counted = false;
     if (rg_pre) {
         rg_prepare();
-        rgo = CsrRowGraphOut{rg_width.p, rg_flags.p, rg_rcnt.p};
+        rgo = CsrRowGraphOut{rg_flags.p, rg_rcnt.p};
     }
     launch_csr(n, m, ria.p, rib.p, csr_cnt.p, csr_off.p, csr_cnt.p + (n + 1), csr_ent.p, cleared, scan_scratch,
                stream, rg_pre ? &rgo : nullptr);
@@ -964,7 +964,7 @@ void relcp_ctx::first_rows_csr(const int *m_dev, int mcap) {
     rg_pre = false;
     if (rg_counted) rg_prepare(mcap);
     if (np > 0) {
-        const ListRowCounts rw{mcap, ria.p, rib.p, rg_width.p, rg_rcnt.p, m_dev};
+        const ListRowCounts rw{mcap, ria.p, rib.p, rg_rcnt.p, m_dev};
         filter_lists(n, pcsr_off.p, pcsr_ent.p, prow.p, fl_cnt.p, csr_off.p, csr_ent.p, scan_scratch, stream,
                      rg_counted ? rg_flags.p : nullptr, rg_counted ? &rw : nullptr);
         rg_pre = rg_counted;
@@ -1013,49 +1013,46 @@ void relcp_ctx::rg_reserve(size_t slots) {
     rg_cap = std::min(rg_col.cap, std::min(rg_val64.cap, rg_val32.cap));
 }
 
-// Row graph of the current rows: slice widths and their scan, then the
-// entries (one thread per incidence entry).  Nothing is read back here: the
-// entry slots are sized from an estimate (twice the current need seen so
-// far, at first RELCP_RG_SLOTS_PER_ROW per row) and the fill flags an
-// overflow, which the solve checks at its first read-back (then re-sizes,
-// rebuilds and restarts).
-// buffers of the row graph's widths and entry counter
+// Row graph of the current rows: the rows' entry counts (unless the
+// incidence build made them), then the entries (one thread per incidence
+// entry) at a fixed stride per row.  Nothing is read back here: a row with
+// more entries than the stride is flagged by the fill, which the solve
+// checks at its first read-back (then raises the stride, rebuilds and
+// restarts).
+// buffers of the row graph's counts and counters
 void relcp_ctx::rg_prepare(int mcap) {
     if (mcap < 0) mcap = m;
-    const int ns = rowgraph_slices(mcap);
-    rg_width.ensure(ns + 1);
     rg_rcnt.ensure(std::max(mcap, 1));
-    rg_base.ensure(ns + 1);
     if (!rg_flags.p) {
-        rg_flags.ensure(1);
-        HIP_OK(hipMemsetAsync(rg_flags.p, 0, sizeof(int), stream));  // entry counter, cleared by each fill
+        rg_flags.ensure(2);
+        // the entry counter (cleared by each fill) and the overflow's count
+        // (cleared after it is read)
+        HIP_OK(hipMemsetAsync(rg_flags.p, 0, 2 * sizeof(int), stream));
     }
-
 }
 
 void relcp_ctx::build_rowgraph(double dt) {
     const int ns = rowgraph_slices(m);
     rg_prepare();
-    rg_reserve(std::max<size_t>((size_t)RELCP_WAVE * ns * rg_slots_per_row, 64));
-    int_h[4] = int_h[5] = int_h[6] = 0;  // slots / 64, entries, overflow (written by the fill)
+    rg_reserve(std::max<size_t>((size_t)RELCP_WAVE * ns * rg_stride, 64));
+    int_h[5] = int_h[6] = 0;  // entries, overflow (written by the fill)
     if (!rg_pre) {
-        // widths not made by the incidence build (a rebuild, or the first
+        // counts not made by the incidence build (a rebuild, or the first
         // rows' filtered lists, which counted the entries)
         timed(8, [&] {
-            launch_rowgraph_width(m, ria.p, rib.p, csr_off.p, rg_width.p, rg_counted ? nullptr : rg_flags.p,
-                                  rg_rcnt.p, stream);
+            launch_rowgraph_counts(m, ria.p, rib.p, csr_off.p, rg_counted ? nullptr : rg_flags.p, rg_rcnt.p,
+                                   stream);
         });
     }
     rg_pre = false;
     rg_counted = false;
 
-    exclusive_scan(rg_width.p, rg_base.p, ns + 1, nullptr, scan_scratch, stream);
     RowGraphFill f{};
     f.m = m; f.ldr = ldr; f.ia = ria.p; f.ib = rib.p; f.n = rn64.p; f.ta = rta64.p; f.tb = rtb64.p;
-    f.ldb = n; f.K = K.p; f.off = csr_off.p; f.ent = csr_ent.p; f.base = rg_base.p; f.dt = dt;
-    f.cap = rg_cap; f.count = rg_flags.p; f.report = int_d + 4;
+    f.ldb = n; f.K = K.p; f.off = csr_off.p; f.ent = csr_ent.p; f.rcnt = rg_rcnt.p; f.stride = rg_stride;
+    f.dt = dt; f.cap = rg_cap; f.count = rg_flags.p; f.need = rg_flags.p + 1; f.report = int_d + 4;
     f.col = rg_col.p; f.val64 = rg_val64.p; f.val32 = rg_val32.p;
-    timed(8, [&] { launch_rowgraph_fill(f, stream); });  // reports slots, entries and overflow, read after the solve's first sync
+    timed(8, [&] { launch_rowgraph_fill(f, stream); });  // reports entries and overflow, read after the solve's first sync
     rg_valid = true;
     rg_dt = dt;
 }
@@ -1223,7 +1220,7 @@ relcp_ctx::RgBufs<T> relcp_ctx::rg_bufs(const RowsT<T> &R, double tol) {
     B.C = PgdCtl{cb, cb + 2, reinterpret_cast<int *>(cb + 3), B.part, lcp_gather_blocks(m),
                  lcp_fixed > 0 ? -1.0 : tol, pst_d + 2 * pk, reinterpret_cast<int *>(pst_d + 2 * pk + 1),
                  stall_iters<T>()};
-    B.G = RowGraphT<T>{m, rg_base.p, rg_col.p, nullptr, rg_cap, rg_rcnt.p};
+    B.G = RowGraphT<T>{m, rg_stride, rg_col.p, nullptr, rg_cap, rg_rcnt.p};
     if constexpr (sizeof(T) == 8)
         B.G.val = rg_val64.p;
     else
@@ -1269,7 +1266,7 @@ void relcp_ctx::rg_start(const RowsT<T> &R, double dt, double tol, const double 
     // the last solve's count, the pass that sees convergence and headroom: a
     // short first chunk costs a wait and, in a step, the work launched behind
     // it, while a spare pass returns at once
-    st.chunk = std::max(2, std::min(64, last_iters[pk] + std::max(3, last_iters[pk] / 4) + 1));
+    st.chunk = std::max(2, std::min(64, last_iters[pk] + std::max(2, last_iters[pk] / 6) + 1));
     // a solve that last converged at its start: the pass that sees it and a
     // spare one; only the first once it has done so several times in a row.
     // The FP64 polish of a step (allow_final) then runs no pass at all: its
@@ -1322,8 +1319,14 @@ void relcp_ctx::rg_unpack(const RowsT<T> &R, const BodiesT<T> &Bd, double tol) {
 // they are re-sized and the graph is marked for re-assembly).
 bool relcp_ctx::rg_overflowed() {
     rg_entries = int_h[5];
-    if (!int_h[6] && (size_t)RELCP_WAVE * int_h[4] <= rg_cap) return false;
-    rg_reserve(2 * (size_t)RELCP_WAVE * int_h[4]);
+    if (!int_h[6]) return false;
+    // the largest count of a row that did not fit, then cleared for the next
+    // overflow; the stride takes it with half again as much headroom
+    int need = 0;
+    HIP_OK(hipMemcpyAsync(&need, rg_flags.p + 1, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipMemsetAsync(rg_flags.p + 1, 0, sizeof(int), stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    rg_stride = std::max(rg_stride + 1, need + need / 2);
     rg_valid = false;
     ++rg_restarts;
     return true;
@@ -1427,7 +1430,7 @@ int relcp_ctx::solve_rowgraph_graph(const RowsT<T> &R, const BodiesT<T> &Bd, dou
         }
         LcpDev<T> v{};
         v.m = m; v.nbg = B.C.nbg; v.cap = cap; v.tol = B.C.tol; v.stall = B.C.stall;
-        v.base = B.G.base; v.col = B.G.col; v.val = B.G.val; v.slots = B.G.cap; v.rcnt = B.G.rcnt;
+        v.stride = B.G.stride; v.col = B.G.col; v.val = B.G.val; v.slots = B.G.cap; v.rcnt = B.G.rcnt;
         v.qv = R.qv; v.dA = R.dA;
         v.z[0] = B.z0; v.z[1] = B.z1; v.g[0] = B.g0; v.g[1] = B.g1;
         v.part[0] = B.part; v.part[1] = B.part + B.stride;
@@ -1652,6 +1655,24 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
                 break;
             }
             bool again32 = false, again64 = false;
+            if (precision == 32 && lcp_fixed == 0) {
+                // an FP32 solve that has not converged within its first chunk
+                // is usually a few passes short: a short further chunk, and
+                // the polish and the tail again behind it, all waited for
+                // together (then chunks twice as long while it has not)
+                const RgBufs<float> Bf = rg_bufs<float>(R32, tol);
+                const int *done32 = reinterpret_cast<const int *>(pst_h + 1);
+                int extra = std::max(4, rgr[0].chunk / 4);
+                while (!*done32 && rgr[0].j - 1 < lcp_max_iters) {
+                    rg_passes<float>(Bf, R32, std::min(extra, lcp_max_iters - (rgr[0].j - 1)));
+                    const StartSrc src{nullptr, {Bf.z0, Bf.z1}, Bf.C.fin, Bf.C.done, (rgr[0].j - 1) & 1};
+                    rg_start<double>(R64, dt, tol, nullptr, rgam64.p, &src, true);
+                    rg_unpack<double>(R64, B64, tol);
+                    launch_tail();
+                    wait_report();
+                    extra = std::min(64, 2 * extra);
+                }
+            }
             if (precision == 32) {
                 status = rg_finish<float>(R32, B32, tol, it, res, again32);
                 if (status == RELCP_OK || status == RELCP_E_LCP_MAXITER) {

@@ -34,39 +34,49 @@ __device__ inline unsigned long long u64_min(unsigned long long a, unsigned long
 
 // Strided per-thread sums, then a fixed shuffle tree and the four waves in
 // order, so the work sum is the same on every run.  All 256 threads of the
-// workgroup call it.
-__device__ inline void tail_report(const TailReport &R) {
+// workgroup call it.  Thread t takes items t, t + 256, ... of each array in
+// that order, kTailU of each array per round with all their loads issued
+// before any use; the first round's loads can be issued early
+// (tail_preload), so that their latency overlaps other work of the caller.
+constexpr int kTailU = 4;
+struct TailRegs {
+    unsigned long long vd[kTailU], vp[kTailU], vq[kTailU];
+    double vw[kTailU];
+    int vc[kTailU];
+};
+__device__ inline void tail_load(const TailReport &R, int k0, TailRegs &v) {
+    const int ng = R.gcount ? R.ng : 0;
+#pragma unroll
+    for (int u = 0; u < kTailU; ++u) {
+        const int k = k0 + u * 256;
+        v.vd[u] = k < R.nt ? R.disp[k] : 0ull;
+        v.vp[u] = k < R.ns ? R.phi[k] : ~0ull;
+        v.vq[u] = k < R.ns ? R.marg[k] : ~0ull;
+        v.vw[u] = k < R.nw ? R.work[k] : 0.0;
+        v.vc[u] = k < ng ? R.gcount[k] : 0;
+    }
+}
+__device__ inline void tail_preload(const TailReport &R, TailRegs &v) { tail_load(R, threadIdx.x, v); }
+
+__device__ inline void tail_report(const TailReport &R, const TailRegs &first) {
     __shared__ unsigned long long s0[4], s1[4], s2[4];
     __shared__ double s3[4];
     unsigned long long d = 0ull, p = ~0ull, q = ~0ull;
     double w = 0.0;
     int c = 0;
-    // thread t takes items t, t + 256, ... of each array in that order, kU
-    // of each array per round with all their loads issued before any use
-    constexpr int kU = 4;
     const int ng = R.gcount ? R.ng : 0;
     const int nmax = max(max(R.nt, R.ns), max(R.nw, ng));
-    for (int k0 = threadIdx.x; k0 < nmax; k0 += kU * 256) {
-        unsigned long long vd[kU], vp[kU], vq[kU];
-        double vw[kU];
-        int vc[kU];
+    TailRegs v = first;
+    for (int k0 = threadIdx.x; k0 < nmax; k0 += kTailU * 256) {
+        if (k0 != (int)threadIdx.x) tail_load(R, k0, v);
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
+        for (int u = 0; u < kTailU; ++u) {
             const int k = k0 + u * 256;
-            vd[u] = k < R.nt ? R.disp[k] : 0ull;
-            vp[u] = k < R.ns ? R.phi[k] : ~0ull;
-            vq[u] = k < R.ns ? R.marg[k] : ~0ull;
-            vw[u] = k < R.nw ? R.work[k] : 0.0;
-            vc[u] = k < ng ? R.gcount[k] : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int k = k0 + u * 256;
-            d = u64_max(d, vd[u]);
-            p = u64_min(p, vp[u]);
-            q = u64_min(q, vq[u]);
-            if (k < R.nw) w += vw[u];
-            c += vc[u];
+            d = u64_max(d, v.vd[u]);
+            p = u64_min(p, v.vp[u]);
+            q = u64_min(q, v.vq[u]);
+            if (k < R.nw) w += v.vw[u];
+            c += v.vc[u];
         }
     }
     for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) {
@@ -106,6 +116,12 @@ __device__ inline void tail_report(const TailReport &R) {
             *(volatile int *)R.tok = R.seq;
         }
     }
+}
+
+__device__ inline void tail_report(const TailReport &R) {
+    TailRegs v;
+    tail_preload(R, v);
+    tail_report(R, v);
 }
 
 }  // namespace relcp

@@ -349,19 +349,9 @@ __global__ void __launch_bounds__(kThreads) k_filter_fill(int n, int nbb, const 
     const int i = b * kThreads + threadIdx.x;
     const int lane = threadIdx.x & (RELCP_WAVE - 1), w = threadIdx.x / RELCP_WAVE;
     if (rw.m > 0) {
-        // row i: the other kept entries in its two items' lists; each wave's
-        // 64 rows are one slice, whose width is their largest count
+        // row i: the other kept entries in its two items' lists
         const int m = rw.m_dev ? min(*rw.m_dev, rw.m) : rw.m;
-        int wr = 0;
-        if (i < m) {
-            wr = cnt[rw.ia[i]] + cnt[rw.ib[i]] - 2;
-            rw.rcnt[i] = wr;
-        }
-#pragma unroll
-        for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) wr = max(wr, __shfl_xor(wr, o, RELCP_WAVE));
-        const int ns = (m + RELCP_WAVE - 1) / RELCP_WAVE;
-        if (lane == 0 && i / RELCP_WAVE < ns) rw.width[i / RELCP_WAVE] = wr;
-        if (i == 0) rw.width[ns] = 0;
+        if (i < m) rw.rcnt[i] = cnt[rw.ia[i]] + cnt[rw.ib[i]] - 2;
     }
     if (b >= nbb) return;  // (a whole block: no barrier below is split)
     const int c = i < n ? cnt[i] : 0;

@@ -666,12 +666,12 @@ def test_recursion_cap_leaves_state_untouched(dev):
 
 @pytest.mark.parametrize("precision", [64, 32])
 def test_rowgraph_overflow_restart(dev, precision):
-    """The row-graph assembly sizes its entry slots from an estimate per row
-    (RELCP_RG_SLOTS_PER_ROW, read when a context is created); forced to one
-    slot per row, the first assembly overflows.  The passes of that attempt
-    read no slot past the allocation (a slice that did not fit is empty), the
-    solve re-sizes, rebuilds and restarts from the saved start, and the step
-    meets the oracle's."""
+    """The row-graph assembly stores each row's entries at a fixed stride of
+    slots per row (at first RELCP_RG_SLOTS_PER_ROW, read when a context is
+    created); forced to one slot per row, the first assembly overflows.  The
+    passes of that attempt read no entry of a row that did not fit, the solve
+    raises the stride, rebuilds and restarts from the saved start, and the
+    step meets the oracle's."""
     S = compressed_packing(0, 150, 26)
     S = dict(S, x=S["x"] * 0.99, box=S["box"] * 0.99)
     ref = O.relcp_step(S["x"], S["q"], S["kind"], S["shape"], S["rho_xi"], S["box"], tol=1e-12, lcp_mode=1, dt=5e-3,
