@@ -576,10 +576,10 @@ __global__ void k_trial(int nb, const double *__restrict__ x, int ldx, const dou
             scatter_body<double, 0>(R, Bd, i, 0.0, VRegs<double>{w});
             for (int k = 0; k < 6; ++k) {
                 Bd.vc[k * Bd.ld + i] = w[k];
-                v[k] = vfree[k * ldv + i] + w[k];
+                v[k] = (vfree ? vfree[k * ldv + i] : 0.0) + w[k];
             }
         } else {
-            for (int k = 0; k < 6; ++k) v[k] = vfree[k * ldv + i] + vc[k * ldv + i];
+            for (int k = 0; k < 6; ++k) v[k] = (vfree ? vfree[k * ldv + i] : 0.0) + vc[k * ldv + i];
         }
         if (vout)
             for (int k = 0; k < 6; ++k) vout[k * ldv + i] = v[k];

@@ -23,7 +23,10 @@ struct RowsT {
 template <typename T>
 struct BodiesT {
     int nb, ld;
+    // K: 9 comps (ld); with kiso the mobility is diag(k0 I, k3 I) (overdamped
+    // bodies in 3-D) and only comps 0 and 3 are read
     const T *K;
+    int kiso = 0;
     T *vc;
     const int *off, *ent;
 };
@@ -38,6 +41,7 @@ struct RowBuildArgs {
     int rec;             // recursion at which the rows are generated
     double dt;
     const double *K;     // 9 comps, ld = ldb
+    int kiso;            // as BodiesT::kiso
     const double *vfree; // 6 comps, or null where U_free is zero
     const double *vc;    // 6 comps (new rows: V_n - U_free) or null (iteration-0 rows)
     int ldb;
@@ -52,7 +56,7 @@ struct RowBuildArgs {
     int ldr;
     int *ia, *ib, *pair, *rec_out;
     double *n64, *ta64, *tb64, *qv64, *dA64, *gam64, *phi64;
-    float *n32, *ta32, *tb32, *qv32, *dA32, *gam32;
+    float *n32, *ta32, *tb32, *qv32, *dA32, *gam32;  // n32, ta32, tb32, gam32 may be null (not written)
 };
 
 void launch_rows_build(const RowBuildArgs &a, hipStream_t s);
@@ -128,6 +132,7 @@ struct RowGraphFill {
     const double *n, *ta, *tb;
     int ldb;
     const double *K;   // 9 comps, ld = ldb
+    int kiso;          // as BodiesT::kiso
     const int *off, *ent;
     const int *rcnt;   // entries of each row (from the count pass)
     int stride;        // entry slots per row (RowGraphT)

@@ -66,8 +66,20 @@ __device__ inline void build_row(const RowBuildArgs &A, int k, int pr) {
     // A_rr = dt (n.kt_a n + ta.Kr_a ta + n.kt_b n + tb.Kr_b tb)
     auto quad = [&](int i, d3 t) {
         const double *K = A.K;
-        double tr = n.x * n.x * K[i] + n.y * n.y * K[lb + i] + n.z * n.z * K[2 * lb + i];
-        sym3 R{K[3 * lb + i], K[4 * lb + i], K[5 * lb + i], K[6 * lb + i], K[7 * lb + i], K[8 * lb + i]};
+        double k0, k1, k2;
+        sym3 R;
+        if (A.kiso) {
+            // the same values the nine components hold
+            k0 = k1 = k2 = K[i];
+            const double kr = K[3 * lb + i];
+            R = sym3{kr, kr, kr, 0.0, 0.0, 0.0};
+        } else {
+            k0 = K[i];
+            k1 = K[lb + i];
+            k2 = K[2 * lb + i];
+            R = sym3{K[3 * lb + i], K[4 * lb + i], K[5 * lb + i], K[6 * lb + i], K[7 * lb + i], K[8 * lb + i]};
+        }
+        double tr = n.x * n.x * k0 + n.y * n.y * k1 + n.z * n.z * k2;
         return tr + dot(t, mul(R, t));
     };
     double dA = A.dt * (quad(a, ta) + quad(b, tb));
@@ -100,16 +112,20 @@ __device__ inline void build_row(const RowBuildArgs &A, int k, int pr) {
         A.n64[c * L + r] = nn[c];
         A.ta64[c * L + r] = tt[c];
         A.tb64[c * L + r] = uu[c];
-        A.n32[c * L + r] = (float)nn[c];
-        A.ta32[c * L + r] = (float)tt[c];
-        A.tb32[c * L + r] = (float)uu[c];
+    }
+    if (A.n32) {
+        for (int c = 0; c < 3; ++c) {
+            A.n32[c * L + r] = (float)nn[c];
+            A.ta32[c * L + r] = (float)tt[c];
+            A.tb32[c * L + r] = (float)uu[c];
+        }
     }
     A.qv64[r] = qv;
     A.qv32[r] = (float)qv;
     A.dA64[r] = dA;
     A.dA32[r] = (float)dA;
     A.gam64[r] = g0;
-    A.gam32[r] = (float)g0;
+    if (A.gam32) A.gam32[r] = (float)g0;
     A.phi64[r] = phi;
 }
 
@@ -809,8 +825,20 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_fill_entries(RowGraphFill
     const double *K = A.K;
     const d3 nr = mk(sr * J[0], sr * J[1], sr * J[2]);
     const d3 ur = mk(sr * J[3], sr * J[4], sr * J[5]);
-    const d3 Kn = mk(sr * K[c] * nr.x, sr * K[lb + c] * nr.y, sr * K[2 * lb + c] * nr.z);
-    const sym3 Kr{K[3 * lb + c], K[4 * lb + c], K[5 * lb + c], K[6 * lb + c], K[7 * lb + c], K[8 * lb + c]};
+    double k0, k1, k2;
+    sym3 Kr;
+    if (A.kiso) {
+        // the same values the nine components hold
+        k0 = k1 = k2 = K[c];
+        const double kr = K[3 * lb + c];
+        Kr = sym3{kr, kr, kr, 0.0, 0.0, 0.0};
+    } else {
+        k0 = K[c];
+        k1 = K[lb + c];
+        k2 = K[2 * lb + c];
+        Kr = sym3{K[3 * lb + c], K[4 * lb + c], K[5 * lb + c], K[6 * lb + c], K[7 * lb + c], K[8 * lb + c]};
+    }
+    const d3 Kn = mk(sr * k0 * nr.x, sr * k1 * nr.y, sr * k2 * nr.z);
     const d3 Ku = sr * mul(Kr, ur);
     for (int j = j0; j < j1; ++j) {
         if (j == e) continue;

@@ -306,10 +306,18 @@ struct relcp_ctx {
     size_t rg_cap = 0;     // entry slots allocated
     int rg_entries = 0;    // entries of the current graph (known after the solve's first read-back)
     bool rowgraph_mode() const { return !resident_mode() && lcp_mode != 1; }
+    // K as the body set-up forms it for overdamped bodies in 3-D:
+    // diag(k0 I, k3 I), so that kernels read components 0 and 3 only (false
+    // where the caller supplies K)
+    bool k_from_setup = true;
+    // the rows' FP32 geometry (n, ta, tb) is current (rows built for the row
+    // graph leave it out; a matrix-free FP32 solve forms it first)
+    bool rows32_ok = false;
+    bool k_iso() const { return k_from_setup && dynamics == RELCP_OVERDAMPED && !planar; }
     void build_rowgraph(double dt);
     void rg_reserve(size_t slots);
     void rg_prepare(int mcap = -1);  // buffers for mcap rows (default m)
-    bool rg_pre = false;  // the incidence build made this graph's slice widths
+    bool rg_pre = false;  // the incidence build made this graph's entry counts
     bool rg_counted = false;  // the incidence build stored this graph's entry count
     int maxpk = 0;                       // bodies of the largest packing
     DBuf<int> boff_d, roff, rlist, rlist2, rcnt, rE;
@@ -876,6 +884,7 @@ RowBuildArgs relcp_ctx::row_args(int nsel, int rec, const double *snsd, const do
     a.rec = rec;
     a.dt = dt;
     a.K = K.p;
+    a.kiso = k_iso() ? 1 : 0;
     // overdamped bodies without external forces: U_free = 0
     a.vfree = dynamics == RELCP_OVERDAMPED && !has_fext ? nullptr : vfree.p;
     a.vc = vc;
@@ -889,7 +898,13 @@ RowBuildArgs relcp_ctx::row_args(int nsel, int rec, const double *snsd, const do
     a.ia = ria.p; a.ib = rib.p; a.pair = rpair.p; a.rec_out = rrec.p;
     a.n64 = rn64.p; a.ta64 = rta64.p; a.tb64 = rtb64.p; a.qv64 = rqv64.p; a.dA64 = rdA64.p; a.gam64 = rgam64.p;
     a.phi64 = rphi64.p;
-    a.n32 = rn32.p; a.ta32 = rta32.p; a.tb32 = rtb32.p; a.qv32 = rqv32.p; a.dA32 = rdA32.p; a.gam32 = rgam32.p;
+    a.qv32 = rqv32.p; a.dA32 = rdA32.p;
+    // the FP32 geometry and start are read only by the matrix-free FP32
+    // solves (the row graph's are formed from the FP64 rows)
+    if (!rowgraph_mode()) {
+        a.n32 = rn32.p; a.ta32 = rta32.p; a.tb32 = rtb32.p; a.gam32 = rgam32.p;
+    }
+    rows32_ok = !rowgraph_mode() && (rows32_ok || rec == 0);
     return a;
 }
 
@@ -1049,7 +1064,7 @@ void relcp_ctx::build_rowgraph(double dt) {
 
     RowGraphFill f{};
     f.m = m; f.ldr = ldr; f.ia = ria.p; f.ib = rib.p; f.n = rn64.p; f.ta = rta64.p; f.tb = rtb64.p;
-    f.ldb = n; f.K = K.p; f.off = csr_off.p; f.ent = csr_ent.p; f.rcnt = rg_rcnt.p; f.stride = rg_stride;
+    f.ldb = n; f.K = K.p; f.kiso = k_iso() ? 1 : 0; f.off = csr_off.p; f.ent = csr_ent.p; f.rcnt = rg_rcnt.p; f.stride = rg_stride;
     f.dt = dt; f.cap = rg_cap; f.count = rg_flags.p; f.need = rg_flags.p + 1; f.report = int_d + 4;
     f.col = rg_col.p; f.val64 = rg_val64.p; f.val32 = rg_val32.p;
     timed(8, [&] { launch_rowgraph_fill(f, stream); });  // reports entries and overflow, read after the solve's first sync
@@ -1083,6 +1098,7 @@ BodiesT<T> relcp_ctx::bodies_of() const {
     } else {
         Bd.K = K32.p; Bd.vc = vc32.p;
     }
+    Bd.kiso = k_iso() ? 1 : 0;
     Bd.nb = n;
     Bd.ld = n;
     Bd.off = csr_off.p;
@@ -1092,6 +1108,13 @@ BodiesT<T> relcp_ctx::bodies_of() const {
 
 template <typename T>
 int relcp_ctx::solve(double dt, double tol, int &iters, double &res) {
+    if (sizeof(T) == 4 && !rowgraph_mode() && !rows32_ok) {
+        // rows built for the row graph have no FP32 geometry: from the FP64
+        launch_demote(3 * ldr, rn64.p, rn32.p, stream);
+        launch_demote(3 * ldr, rta64.p, rta32.p, stream);
+        launch_demote(3 * ldr, rtb64.p, rtb32.p, stream);
+        rows32_ok = true;
+    }
     const RowsT<T> R = rows_of<T>();
     const BodiesT<T> Bd = bodies_of<T>();
     if (resident_mode()) {
@@ -1589,7 +1612,9 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
                 const RowsT<double> Rt = rows_of<double>();
                 const BodiesT<double> Bt = bodies_of<double>();
                 const bool vrows = rowgraph_mode();
-                launch_trial(N, x.p, N, q.p, N, vfree.p, vc64.p, N, dt, kind.p, p.p, N, Rb.p, xt.p, qt.p, geot.p, N,
+                // (overdamped bodies without external forces: U_free = 0)
+                const double *vf = dynamics == RELCP_OVERDAMPED && !has_fext ? nullptr : vfree.p;
+                launch_trial(N, x.p, N, q.p, N, vf, vc64.p, N, dt, kind.p, p.p, N, Rb.p, xt.p, qt.p, geot.p, N,
                              vout.p, red.p, stream, vrows ? &Rt : nullptr, vrows ? &Bt : nullptr);
             });
             SnsdArgs sb = sa;
@@ -2635,6 +2660,7 @@ int relcp_lcp_solve_device(int32_t nb, int32_t m, const int32_t *ia, const int32
         c.alloc_host();
         c.n = nb;
         c.lcp_mode = mode == 0 ? 4 : mode;
+        c.k_from_setup = false;
         c.lcp_max_iters = max_iters > 0 ? max_iters : 100000;
         c.K.ensure(9 * (size_t)nb);
         c.K32.ensure(9 * (size_t)nb);
@@ -2652,6 +2678,7 @@ int relcp_lcp_solve_device(int32_t nb, int32_t m, const int32_t *ia, const int32
                                ia, ib, c.K.p, nb, dt, c.rn64.p, c.rta64.p, c.rtb64.p, c.rqv64.p, c.rdA64.p, c.rn32.p,
                                c.rta32.p, c.rtb32.p, c.rqv32.p, c.rdA32.p);
         }
+        c.rows32_ok = true;
         c.rebuild_csr();
         int it = 0, it64 = 0, rc;
         double res = 0, res64 = 0;

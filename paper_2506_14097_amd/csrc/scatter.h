@@ -87,11 +87,26 @@ __device__ inline void scatter_body(const RowsT<T> &R, const BodiesT<T> &B, int 
     }
     const int lb = B.ld;
     const T *K = B.K;
-    V(0, i) = K[i] * f0;
-    V(1, i) = K[lb + i] * f1;
-    V(2, i) = K[2 * lb + i] * f2;
-    T kxx = K[3 * lb + i], kyy = K[4 * lb + i], kzz = K[5 * lb + i];
-    T kxy = K[6 * lb + i], kxz = K[7 * lb + i], kyz = K[8 * lb + i];
+    T k0, k1, k2, kxx, kyy, kzz, kxy, kxz, kyz;
+    if (B.kiso) {
+        // the same values the nine components hold
+        k0 = k1 = k2 = K[i];
+        kxx = kyy = kzz = K[3 * lb + i];
+        kxy = kxz = kyz = T(0);
+    } else {
+        k0 = K[i];
+        k1 = K[lb + i];
+        k2 = K[2 * lb + i];
+        kxx = K[3 * lb + i];
+        kyy = K[4 * lb + i];
+        kzz = K[5 * lb + i];
+        kxy = K[6 * lb + i];
+        kxz = K[7 * lb + i];
+        kyz = K[8 * lb + i];
+    }
+    V(0, i) = k0 * f0;
+    V(1, i) = k1 * f1;
+    V(2, i) = k2 * f2;
     V(3, i) = kxx * t0 + kxy * t1 + kxz * t2;
     V(4, i) = kxy * t0 + kyy * t1 + kyz * t2;
     V(5, i) = kxz * t0 + kyz * t1 + kzz * t2;
