@@ -803,14 +803,12 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_fill_entries(RowGraphFill
         A.report[1] = *A.count;
         *A.count = 0;
     }
-    int k = 0;
-    if (side) {
-        const int a = A.ia[r];
-        k = A.off[a + 1] - A.off[a] - 1;  // the slots of body a's other rows
-    }
     const int j0 = A.off[c], j1 = A.off[c + 1];
     // a row that does not fit is left out by both of its entries' threads
     const int cnt = A.rcnt[r];
+    // side b: after the slots of body a's other rows (the row's count less
+    // those at b)
+    int k = side ? cnt - (j1 - j0 - 1) : 0;
     if (cnt > S || (size_t)RELCP_WAVE * (b0 + S) > A.cap) {
         atomicMax(A.need, cnt);
         A.report[2] = 1;
