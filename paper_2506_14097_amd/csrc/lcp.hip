@@ -368,6 +368,9 @@ __device__ inline void block_reduce4n(double &a, double &b, double &c, double &m
     __syncthreads();
 }
 
+// TRAIL: a barrier after thread 0's reads of sh, before sh is written
+// again; left out where a later barrier comes first or sh is not used again.
+template <bool TRAIL = true>
 __device__ inline void block_reduce4(double &a, double &b, double &c, double &mx, double (*sh)[kWaves]) {
     wave_reduce4(a, b, c, mx);
     const int lane = threadIdx.x & (RELCP_WAVE - 1), w = threadIdx.x / RELCP_WAVE;
@@ -388,7 +391,7 @@ __device__ inline void block_reduce4(double &a, double &b, double &c, double &mx
             mx = fmax(mx, sh[3][k]);
         }
     }
-    __syncthreads();
+    if (TRAIL) __syncthreads();
 }
 
 // State after one gather: iteration count, residual, convergence and the
@@ -442,7 +445,7 @@ __device__ inline void reduce_partials(const PgdCtl &C, int par, PgdState *out, 
             }
         }
     }
-    block_reduce4(ss, sy, yy, res, sh);
+    block_reduce4<false>(ss, sy, yy, res, sh);
     if (threadIdx.x == 0) *out = pgd_next(C.S[par ^ 1], ss, sy, yy, res, C.tol, C.stall);
     __syncthreads();
 }
@@ -479,7 +482,7 @@ __device__ inline void reduce_loaded(const PgdCtl &C, int par, const PartialRegs
             res = fmax(res, pr.v[u].w);
         }
     }
-    block_reduce4(ss, sy, yy, res, sh);
+    block_reduce4<false>(ss, sy, yy, res, sh);
     if (threadIdx.x == 0) *out = pgd_next(C.S[par ^ 1], ss, sy, yy, res, C.tol, C.stall);
     __syncthreads();
 }
@@ -1074,7 +1077,8 @@ __global__ void __launch_bounds__(kThreads)
     double ss = 0.0, sy = 0.0, yy = 0.0, res = 0.0;
     T gv = T(0), gn = T(0);
     if (act) row_finish<T, RM, SV>(P, al, zin, gam0, zout, gout, r, ss, sy, yy, res, &gv, &gn);
-    block_reduce4(ss, sy, yy, res, sh);
+    // (sh is used again only by the final start's work sums)
+    block_reduce4<MODE == 3>(ss, sy, yy, res, sh);
     if (threadIdx.x == 0) {
         double *p = pout + 4 * lb;
         p[0] = ss;
@@ -1092,7 +1096,7 @@ __global__ void __launch_bounds__(kThreads)
             start.g_final[r] = (double)gn;
             w = (double)gv * ((double)gn - (double)P.q);
         }
-        block_reduce4(w, z0s, z1s, z2s, sh);
+        block_reduce4<false>(w, z0s, z1s, z2s, sh);
         if (threadIdx.x == 0) start.work_final[lb] = w;
     }
 }
@@ -1196,7 +1200,7 @@ __global__ void __launch_bounds__(kThreads)
     }
     if (work) {
         // the work partials of this block, as k_work forms them
-        block_reduce4(w, z0s, z1s, z2s, sh);
+        block_reduce4<false>(w, z0s, z1s, z2s, sh);
         if (threadIdx.x == 0) work[blockIdx.x] = w;
     }
 }
@@ -1218,7 +1222,7 @@ __global__ void __launch_bounds__(kThreads) k_work(int m, const double *__restri
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     double w = 0.0, z0 = 0.0, z1 = 0.0, z2 = 0.0;
     if (c < m) w = gam[c] * (g[c] - qv[c]);
-    block_reduce4(w, z0, z1, z2, sh);
+    block_reduce4<false>(w, z0, z1, z2, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = w;
 }
 
