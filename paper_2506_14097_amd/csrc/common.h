@@ -190,21 +190,15 @@ struct TailReport;
 int flag_groups(int n);
 bool compact_flags(const int *flags, int n, const int *bcount, int *out, int *total_dev, DBuf<int> &scratch,
                    hipStream_t s, const TailReport *rep = nullptr, int *pos = nullptr);
-// scan.hip: lists of n items (off, ent: entries (j << 1) | side, as the
+// scan.hip: lists of n items (boff, bent: entries (j << 1) | side, as the
 // incidence lists) keeping the entries whose j has pos[j] >= 0, renumbered
-// (pos[j] << 1) | side, each list in its own order: cnt (n) the kept counts,
-// off (n + 1) and ent (the kept entries) the filtered lists; pairs_out (a
-// device int, or null) <- the sum over items of c (c - 1), c the kept count.
-// rows (or null): m rows, each kept once in the lists of its two items ia,
-// ib; rcnt[r] <- the other kept entries of those two lists (c_a + c_b - 2).
-// scratch grows as needed.
-struct ListRowCounts {
-    int m;               // rows, or with m_dev the rows' capacity (the grid covers it)
-    const int *ia, *ib;
-    int *rcnt;
-    const int *m_dev;    // the row count on the device (<= m), or null
-};
-void filter_lists(int n, const int *boff, const int *bent, const int *pos, int *cnt, int *off, int *ent,
-                  DBuf<int> &scratch, hipStream_t s, int *pairs_out = nullptr, const ListRowCounts *rows = nullptr);
+// (pos[j] << 1) | side, each list in its own order and in place of the
+// unfiltered one: item i's kept entries at boff[i] .. boff[i] + cnt[i] - 1 of
+// ent, then -1 up to boff[i + 1] (ent has boff[n] slots).  bsums
+// (filter_blocks(n) ints) <- per block of items the sum of c (c - 1), c the
+// kept count (summed by the row graph's assembly).
+int filter_blocks(int n);
+void filter_lists(int n, const int *boff, const int *bent, const int *pos, int *cnt, int *ent, int *bsums,
+                  hipStream_t s);
 
 }  // namespace relcp

@@ -28,7 +28,11 @@ struct BodiesT {
     const T *K;
     int kiso = 0;
     T *vc;
+    // incidence lists: body i's entries at ent[off[i]] .. before off[i + 1]
+    // (CSR), or with lcnt the first lcnt[i] of them (lists in the slots of
+    // longer ones, as filter_lists leaves them)
     const int *off, *ent;
+    const int *lcnt = nullptr;
 };
 
 struct RowBuildArgs {
@@ -134,7 +138,13 @@ struct RowGraphFill {
     const double *K;   // 9 comps, ld = ldb
     int kiso;          // as BodiesT::kiso
     const int *off, *ent;
-    const int *rcnt;   // entries of each row (from the count pass)
+    const int *lcnt;   // list lengths (as BodiesT::lcnt), or null for CSR
+    int nslots;        // incidence slots (one thread each): 2 m for CSR, off[nb] with lcnt
+    // entries of each row: read (CSR: from the count pass), or with lcnt
+    // formed here from the lists' lengths and written for the passes
+    int *rcnt;
+    const int *bsums;  // with lcnt: filter_lists' block sums of the entry count
+    int nbsums;
     int stride;        // entry slots per row (RowGraphT)
     double dt;
     size_t cap;        // entry slots allocated

@@ -781,34 +781,57 @@ __device__ inline void column_of(const RowGraphFill &A, int en, double J[6]) {
 
 __global__ void __launch_bounds__(kThreads) k_rowgraph_fill_entries(RowGraphFill A) {
     __shared__ double shJ[6][kThreads];
+    __shared__ int shs[kWaves];
     const int E0 = blockIdx.x * kThreads;
     const int e = E0 + threadIdx.x;
-    const int m2 = 2 * A.m;
-    const bool act = e < m2;
-    int en = 0, r = 0, side = 0, c = 0;
+    // a slot past a list's length holds -1 (lists with lengths)
+    const int en = e < A.nslots ? A.ent[e] : -1;
+    const bool act = en >= 0;
+    int r = 0, side = 0, c = 0, other = 0;
     double J[6] = {0, 0, 0, 0, 0, 0};
     if (act) {
-        en = A.ent[e];
         r = en >> 1;
         side = en & 1;
-        c = side ? A.ib[r] : A.ia[r];
+        const int a = A.ia[r], b = A.ib[r];
+        c = side ? b : a;
+        other = side ? a : b;
         column_of(A, en, J);
     }
 #pragma unroll
     for (int t = 0; t < 6; ++t) shJ[t][threadIdx.x] = J[t];
+    if (A.lcnt && blockIdx.x == 0) {
+        // the entry count: the list filter's block sums, added up here
+        int acc = 0;
+        for (int k = threadIdx.x; k < A.nbsums; k += kThreads) acc += A.bsums[k];
+        for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, RELCP_WAVE);
+        if ((threadIdx.x & (RELCP_WAVE - 1)) == 0) shs[threadIdx.x / RELCP_WAVE] = acc;
+    }
     __syncthreads();
+    if (A.lcnt && blockIdx.x == 0 && threadIdx.x == 0) {
+        int t = 0;
+        for (int k = 0; k < kWaves; ++k) t += shs[k];
+        A.report[1] = t;
+    }
     if (!act) return;
     const int lane = r & (RELCP_WAVE - 1), sl = r / RELCP_WAVE;
     const int S = A.stride;
     const size_t b0 = (size_t)sl * S;
-    if (r == 0 && side == 0) {
+    if (!A.lcnt && r == 0 && side == 0) {
         // the count pass is complete: report and clear its counter
         A.report[1] = *A.count;
         *A.count = 0;
     }
-    const int j0 = A.off[c], j1 = A.off[c + 1];
+    const int j0 = A.off[c], j1 = A.lcnt ? j0 + A.lcnt[c] : A.off[c + 1];
+    // the row's entries: its other rows at c and at the other body (formed
+    // here from the lists' lengths, and stored once, by the side-b entry)
+    int cnt;
+    if (A.lcnt) {
+        cnt = (j1 - j0 - 1) + (A.lcnt[other] - 1);
+        if (side) A.rcnt[r] = cnt;
+    } else {
+        cnt = A.rcnt[r];
+    }
     // a row that does not fit is left out by both of its entries' threads
-    const int cnt = A.rcnt[r];
     // side b: after the slots of body a's other rows (the row's count less
     // those at b)
     int k = side ? cnt - (j1 - j0 - 1) : 0;
@@ -1350,7 +1373,8 @@ void launch_rowgraph_counts(int m, const int *ia, const int *ib, const int *off,
 
 
 void launch_rowgraph_fill(const RowGraphFill &a, hipStream_t s) {
-    if (a.m > 0) launch_k(k_rowgraph_fill_entries, dim3(nblk(2 * (long long)a.m, kThreads)), dim3(kThreads), 0, s, a);
+    if (a.m > 0 && a.nslots > 0)
+        launch_k(k_rowgraph_fill_entries, dim3(nblk(a.nslots, kThreads)), dim3(kThreads), 0, s, a);
 }
 
 template <typename T>

@@ -29,7 +29,8 @@ struct FeatureArgs {
     int ldb;
     const int *kind;
     const double *p, *u;        // bodies (SoA, ld = ldb); u may be null
-    const int *off, *ent;       // incidence CSR of A_0 (entry = row << 1 | side)
+    const int *off, *ent;       // incidence lists of A_0 (entry = row << 1 | side)
+    const int *lcnt;            // their lengths (as BodiesT::lcnt), or null for CSR
     const int *perm;
     double dt;
     float *feat;                // [m0][8]

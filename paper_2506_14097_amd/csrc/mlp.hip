@@ -406,16 +406,18 @@ __global__ void k_features(FeatureArgs A) {
         rate = -(dot(n, mk(U[a], U[lb + a], U[2 * lb + a])) + dot(ta, mk(U[3 * lb + a], U[4 * lb + a], U[5 * lb + a]))) +
                dot(n, mk(U[b], U[lb + b], U[2 * lb + b])) + dot(tb, mk(U[3 * lb + b], U[4 * lb + b], U[5 * lb + b]));
     }
-    double ca = A.off[a + 1] - A.off[a], cb = A.off[b + 1] - A.off[b];
+    const int ea0 = A.off[a], ea1 = A.lcnt ? ea0 + A.lcnt[a] : A.off[a + 1];
+    const int eb0 = A.off[b], eb1 = A.lcnt ? eb0 + A.lcnt[b] : A.off[b + 1];
+    double ca = ea1 - ea0, cb = eb1 - eb0;
     double ra = semiaxis_ratio(ka, p[a], p[lb + a], p[2 * lb + a]);
     double rb = semiaxis_ratio(kb, p[b], p[lb + b], p[2 * lb + b]);
     // overlap load of the other rows at a and at b
     double load = 0.0;
-    for (int k = A.off[a]; k < A.off[a + 1]; ++k) {
+    for (int k = ea0; k < ea1; ++k) {
         const int o = A.ent[k] >> 1;
         if (o != r) load += fmax(0.0, -A.phi[o]);
     }
-    for (int k = A.off[b]; k < A.off[b + 1]; ++k) {
+    for (int k = eb0; k < eb1; ++k) {
         const int o = A.ent[k] >> 1;
         if (o != r) load += fmax(0.0, -A.phi[o]);
     }

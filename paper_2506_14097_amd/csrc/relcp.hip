@@ -171,7 +171,10 @@ struct relcp_ctx {
     // rows are the selected pairs in pair order, so their lists are these
     // lists filtered through prow (the pair's row, or -1), already in row
     // order: no atomics and no sort per step
-    DBuf<int> pcsr_cnt, pcsr_off, pcsr_ent, prow, fl_cnt;
+    DBuf<int> pcsr_cnt, pcsr_off, pcsr_ent, prow, fl_cnt, fl_bsums;
+    // the incidence lists are the first rows' filtered ones (in the candidate
+    // lists' slots, lengths fl_cnt) rather than rebuild_csr's CSR
+    bool lists_gapped = false;
     bool pcsr_valid = false;
     const int *pcsr_clear = nullptr;  // pcsr_cnt while its counters are known to be zero
 
@@ -318,7 +321,6 @@ struct relcp_ctx {
     void rg_reserve(size_t slots);
     void rg_prepare(int mcap = -1);  // buffers for mcap rows (default m)
     bool rg_pre = false;  // the incidence build made this graph's entry counts
-    bool rg_counted = false;  // the incidence build stored this graph's entry count
     int maxpk = 0;                       // bodies of the largest packing
     DBuf<int> boff_d, roff, rlist, rlist2, rcnt, rE;
     DBuf<PgdState> pk_state;
@@ -361,7 +363,7 @@ struct relcp_ctx {
         DBuf<int> *is[] = {&kind, &body_batch, &perm_d, &body_cell, &cell_count, &cell_start, &cell_cursor, &cell_items,
                            &pair_count, &pair_off, &pa, &pb, &pflag, &pcnt, &sel, &prev_a, &prev_b, &ria, &rib,
                            &rpair, &rrec, &csr_cnt, &csr_off, &csr_cur, &csr_ent, &scan_scratch, &dtotal,
-                           &pcsr_cnt, &pcsr_off, &pcsr_ent, &prow, &fl_cnt};
+                           &pcsr_cnt, &pcsr_off, &pcsr_ent, &prow, &fl_cnt, &fl_bsums};
         for (auto *b : is) b->release();
         grids.release();
         keys.release();
@@ -395,7 +397,7 @@ struct relcp_ctx {
     void build_rows(int nsel, int rec, const double *snsd, const double *vc, bool warm, double dt);
     RowBuildArgs row_args(int nsel, int rec, const double *snsd, const double *vc, bool warm, double dt);
     void rebuild_csr();
-    void first_rows_csr(const int *m_dev, int mcap);
+    void first_rows_csr(int mcap);
     void warm_start_rows(int m0, double dt);
     template <typename T>
     int solve(double dt, double tol, int &iters, double &res);
@@ -589,6 +591,7 @@ void relcp_ctx::upload_bodies(const relcp_bodies *B, const relcp_shapes *S) {
     csr_clear = nullptr;
     pcsr_clear = nullptr;
     pcsr_valid = false;
+    lists_gapped = false;
     log_valid = false;
     vl_valid = false;
     prev_is_list = false;
@@ -929,6 +932,7 @@ void relcp_ctx::rows_by_packing_append(int m_old, int nv) {
 
 void relcp_ctx::rebuild_csr() {
     rg_valid = false;
+    lists_gapped = false;
     csr_cnt.ensure(2 * (size_t)(n + 1));
     csr_off.ensure(n + 1);
     csr_ent.ensure(2 * (size_t)std::max(m, 1));
@@ -940,7 +944,6 @@ void relcp_ctx::rebuild_csr() {
     // entry counter: clear it)
     if (rg_pre && rg_flags.p) HIP_OK(hipMemsetAsync(rg_flags.p, 0, sizeof(int), stream));
     rg_pre = rowgraph_mode() && m > 0;
-    rg_counted = false;
     if (rg_pre) {
         rg_prepare();
         rgo = CsrRowGraphOut{rg_flags.p, rg_rcnt.p};
@@ -951,11 +954,15 @@ void relcp_ctx::rebuild_csr() {
 }
 
 // Incidence lists of the step's first rows (the selected candidate pairs,
-// row k = the k-th selected pair, prow filled by the compaction): the
+// row k = the k-th selected pair, prow filled by the selection): the
 // candidate pairs' lists (built when the candidate list changed) filtered
-// through prow.  The same lists as rebuild_csr builds, bit for bit; the
-// row graph's slice widths come from its own pass.
-void relcp_ctx::first_rows_csr(const int *m_dev, int mcap) {
+// through prow in one pass, each body's list in the slots of its candidate
+// list, with its length in fl_cnt.  Each list holds the entries rebuild_csr
+// gives it, in the same order.  The row graph's assembly forms the rows'
+// entry counts from the lengths and adds up the filter's block sums for the
+// entry count.  The filter reads no row count, so it can run before the count
+// reaches the host (mcap: the rows' capacity).
+void relcp_ctx::first_rows_csr(int mcap) {
     if (!pcsr_valid) {
         pcsr_cnt.ensure(2 * (size_t)(n + 1));
         pcsr_off.ensure(n + 1);
@@ -966,26 +973,18 @@ void relcp_ctx::first_rows_csr(const int *m_dev, int mcap) {
         pcsr_valid = true;
     }
     rg_valid = false;
-    csr_off.ensure(n + 1);
-    csr_ent.ensure(2 * (size_t)std::max(mcap, 1));
-    fl_cnt.ensure(n + 1);
-    // in the row-graph mode the filter also stores the graph's entry count
-    // (the ordered pairs of rows sharing a body) in the entry counter, so
-    // the width pass need not add it up
-    // (and the rows' entry counts and slice widths, as the width pass would)
-    // With m_dev the row count is still on its way to the host: the buffers
-    // are sized for mcap rows and the filter reads the count on the device.
-    rg_counted = rowgraph_mode() && mcap > 0;
     rg_pre = false;
-    if (rg_counted) rg_prepare(mcap);
     if (np > 0) {
-        const ListRowCounts rw{mcap, ria.p, rib.p, rg_rcnt.p, m_dev};
-        filter_lists(n, pcsr_off.p, pcsr_ent.p, prow.p, fl_cnt.p, csr_off.p, csr_ent.p, scan_scratch, stream,
-                     rg_counted ? rg_flags.p : nullptr, rg_counted ? &rw : nullptr);
-        rg_pre = rg_counted;
+        csr_ent.ensure(2 * (size_t)np);
+        fl_cnt.ensure(n + 1);
+        fl_bsums.ensure(filter_blocks(n));
+        if (rowgraph_mode() && mcap > 0) rg_prepare(mcap);
+        filter_lists(n, pcsr_off.p, pcsr_ent.p, prow.p, fl_cnt.p, csr_ent.p, fl_bsums.p, stream);
+        lists_gapped = true;
     } else {
+        csr_off.ensure(n + 1);
         HIP_OK(hipMemsetAsync(csr_off.p, 0, (n + 1) * sizeof(int), stream));
-        if (rg_counted) HIP_OK(hipMemsetAsync(rg_flags.p, 0, sizeof(int), stream));
+        lists_gapped = false;
     }
 }
 
@@ -998,7 +997,8 @@ void relcp_ctx::warm_start_rows(int m0, double dt) {
     FeatureArgs fa{};
     fa.m0 = m0; fa.ldr = ldr; fa.ia = ria.p; fa.ib = rib.p;
     fa.n = rn64.p; fa.ta = rta64.p; fa.tb = rtb64.p; fa.phi = rphi64.p; fa.lam = rgam64.p; fa.dA = rdA64.p;
-    fa.ldb = n; fa.kind = kind.p; fa.p = p.p; fa.u = u.p; fa.off = csr_off.p; fa.ent = csr_ent.p;
+    fa.ldb = n; fa.kind = kind.p; fa.p = p.p; fa.u = u.p; fa.off = lists_gapped ? pcsr_off.p : csr_off.p; fa.ent = csr_ent.p;
+    fa.lcnt = lists_gapped ? fl_cnt.p : nullptr;
     fa.perm = perm_d.p;
     fa.dt = dt; fa.feat = feat.p; fa.rowscale = rowscale.p;
     timed(6, [&] { launch_features(fa, stream); });
@@ -1051,20 +1051,23 @@ void relcp_ctx::build_rowgraph(double dt) {
     rg_prepare();
     rg_reserve(std::max<size_t>((size_t)RELCP_WAVE * ns * rg_stride, 64));
     int_h[5] = int_h[6] = 0;  // entries, overflow (written by the fill)
-    if (!rg_pre) {
-        // counts not made by the incidence build (a rebuild, or the first
-        // rows' filtered lists, which counted the entries)
+    if (!rg_pre && !lists_gapped) {
+        // counts not made by the incidence build (a rebuild; with the first
+        // rows' filtered lists the fill forms them)
         timed(8, [&] {
-            launch_rowgraph_counts(m, ria.p, rib.p, csr_off.p, rg_counted ? nullptr : rg_flags.p, rg_rcnt.p,
-                                   stream);
+            launch_rowgraph_counts(m, ria.p, rib.p, csr_off.p, rg_flags.p, rg_rcnt.p, stream);
         });
     }
     rg_pre = false;
-    rg_counted = false;
 
     RowGraphFill f{};
     f.m = m; f.ldr = ldr; f.ia = ria.p; f.ib = rib.p; f.n = rn64.p; f.ta = rta64.p; f.tb = rtb64.p;
-    f.ldb = n; f.K = K.p; f.kiso = k_iso() ? 1 : 0; f.off = csr_off.p; f.ent = csr_ent.p; f.rcnt = rg_rcnt.p; f.stride = rg_stride;
+    f.ldb = n; f.K = K.p; f.kiso = k_iso() ? 1 : 0;
+    f.off = lists_gapped ? pcsr_off.p : csr_off.p; f.ent = csr_ent.p;
+    f.lcnt = lists_gapped ? fl_cnt.p : nullptr;
+    f.nslots = lists_gapped ? 2 * np : 2 * m;
+    f.bsums = fl_bsums.p; f.nbsums = filter_blocks(n);
+    f.rcnt = rg_rcnt.p; f.stride = rg_stride;
     f.dt = dt; f.cap = rg_cap; f.count = rg_flags.p; f.need = rg_flags.p + 1; f.report = int_d + 4;
     f.col = rg_col.p; f.val64 = rg_val64.p; f.val32 = rg_val32.p;
     timed(8, [&] { launch_rowgraph_fill(f, stream); });  // reports entries and overflow, read after the solve's first sync
@@ -1101,8 +1104,9 @@ BodiesT<T> relcp_ctx::bodies_of() const {
     Bd.kiso = k_iso() ? 1 : 0;
     Bd.nb = n;
     Bd.ld = n;
-    Bd.off = csr_off.p;
+    Bd.off = lists_gapped ? pcsr_off.p : csr_off.p;
     Bd.ent = csr_ent.p;
+    Bd.lcnt = lists_gapped ? fl_cnt.p : nullptr;
     return Bd;
 }
 
@@ -1563,7 +1567,7 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         dtotal.ensure(4);
         launch_select_rows(row_args(0, 0, snsd0.p, nullptr, warm0, dt), np, pflag.p, pcnt.p, sel.p, prow.p, int_d,
                            stream, dtotal.p + 1);
-        if (early_lists) first_rows_csr(dtotal.p + 1, np);
+        if (early_lists) first_rows_csr(np);
     } else {
         compact_flags(pflag.p, np, pcnt.p, sel.p, int_d, scan_scratch, stream, nullptr, prow.p);
     }
@@ -1577,9 +1581,8 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         build_rows(m0, 0, snsd0.p, nullptr, warm0, dt);
     }
     if (early_lists) {
-        if (m0 == 0) rg_counted = rg_pre = false;
     } else if (first_lists) {
-        first_rows_csr(nullptr, m0);
+        first_rows_csr(m0);
     } else {
         rebuild_csr();
     }

@@ -287,6 +287,7 @@ bool compact_flags(const int *flags, int n, const int *bcount, int *out, int *to
 // ---------------------------------------------------------------------------
 // filtered incidence lists
 // ---------------------------------------------------------------------------
+namespace {
 // The kept entries of item i's list (pos of the entry's index >= 0), up to
 // kFiltU entries per round with all their loads in flight.
 constexpr int kFiltU = 4;
@@ -311,86 +312,37 @@ __device__ inline int filter_list(const int *__restrict__ boff, const int *__res
     return c;
 }
 
-// one item per thread: its kept count c, and per block of kThreads items
-// the sum of c (sums[b]) and of c (c - 1) (sums[nb + b]: ordered pairs of
-// kept entries of one item)
-__global__ void __launch_bounds__(kThreads) k_filter_count(int n, const int *__restrict__ boff,
-                                                           const int *__restrict__ bent, const int *__restrict__ pos,
-                                                           int *__restrict__ cnt, int *__restrict__ sums) {
+// One item per thread, in place in the unfiltered lists' slots: item i's
+// kept entries, renumbered, in its own order at boff[i] .. boff[i] + c - 1,
+// then -1 up to boff[i + 1]; cnt[i] = c, and per block of kThreads items the
+// sum of c (c - 1) (ordered pairs of kept entries of one item) in bsums.
+// No count pass and no scan: the offsets are the unfiltered lists'.
+__global__ void __launch_bounds__(kThreads) k_filter_gapped(int n, const int *__restrict__ boff,
+                                                            const int *__restrict__ bent, const int *__restrict__ pos,
+                                                            int *__restrict__ cnt, int *__restrict__ ent,
+                                                            int *__restrict__ bsums) {
     __shared__ int sh[kThreads / RELCP_WAVE];
     const int i = blockIdx.x * kThreads + threadIdx.x;
     int c = 0;
     if (i < n) {
-        c = filter_list<false>(boff, bent, pos, i, nullptr, 0);
+        const int j0 = boff[i], j1 = boff[i + 1];
+        c = filter_list<true>(boff, bent, pos, i, ent, j0);
+        for (int j = j0 + c; j < j1; ++j) ent[j] = -1;
         cnt[i] = c;
     }
-    const int t = block_total<kThreads>(c, sh);
     const int tp = block_total<kThreads>(c * (c - 1), sh);
-    if (threadIdx.x == 0) {
-        sums[blockIdx.x] = t;
-        sums[gridDim.x + blockIdx.x] = tp;
-    }
+    if (threadIdx.x == 0) bsums[blockIdx.x] = tp;
 }
 
-// offsets (the counts of the blocks before this one, then a block scan) and
-// the kept entries, renumbered; off[n] = the total.  Blocks 0 .. nbb - 1
-// cover the items; with rw.m > 0 the grid also covers the rows, and block b
-// forms the counts of rows b kThreads .. (the kept counts are complete: the
-// count pass ran before).
-__global__ void __launch_bounds__(kThreads) k_filter_fill(int n, int nbb, const int *__restrict__ boff,
-                                                          const int *__restrict__ bent, const int *__restrict__ pos,
-                                                          const int *__restrict__ cnt, const int *__restrict__ sums,
-                                                          const int *__restrict__ offs, int *__restrict__ off,
-                                                          int *__restrict__ ent, int *__restrict__ pairs_out,
-                                                          ListRowCounts rw) {
-    __shared__ int sh[kThreads / RELCP_WAVE];
-    __shared__ int wsum[kThreads / RELCP_WAVE];
-    const int b = blockIdx.x;
-    const int i = b * kThreads + threadIdx.x;
-    const int lane = threadIdx.x & (RELCP_WAVE - 1), w = threadIdx.x / RELCP_WAVE;
-    if (rw.m > 0) {
-        // row i: the other kept entries in its two items' lists
-        const int m = rw.m_dev ? min(*rw.m_dev, rw.m) : rw.m;
-        if (i < m) rw.rcnt[i] = cnt[rw.ia[i]] + cnt[rw.ib[i]] - 2;
-    }
-    if (b >= nbb) return;  // (a whole block: no barrier below is split)
-    const int c = i < n ? cnt[i] : 0;
-    if (pairs_out && b == nbb - 1) {
-        // the last block adds up the pair counts of all blocks
-        int acc = 0;
-        for (int k = threadIdx.x; k < nbb; k += kThreads) acc += sums[nbb + k];
-        const int tp = block_total<kThreads>(acc, sh);
-        if (threadIdx.x == 0) *pairs_out = tp;
-    }
-    const int toff = tile_offset(sums, offs, b, sh);
-    const int inc = wave_incl_scan(c);
-    if (lane == RELCP_WAVE - 1) wsum[w] = inc;
-    __syncthreads();
-    int woff = 0;
-#pragma unroll
-    for (int k = 0; k < kThreads / RELCP_WAVE; ++k) woff += k < w ? wsum[k] : 0;
-    const int at = toff + woff + inc - c;
-    if (i >= n) return;
-    off[i] = at;
-    if (i == n - 1) off[n] = at + c;
-    if (c) filter_list<true>(boff, bent, pos, i, ent, at);
-}
+}  // namespace
 
-void filter_lists(int n, const int *boff, const int *bent, const int *pos, int *cnt, int *off, int *ent,
-                  DBuf<int> &scratch, hipStream_t s, int *pairs_out, const ListRowCounts *rows) {
+int filter_blocks(int n) { return (n + kThreads - 1) / kThreads; }
+
+void filter_lists(int n, const int *boff, const int *bent, const int *pos, int *cnt, int *ent, int *bsums,
+                  hipStream_t s) {
     if (n <= 0) return;
-    const int nb = (n + kThreads - 1) / kThreads;
-    // past kDirect blocks the block counts are scanned first (a block would
-    // otherwise sum all the counts before it)
-    const bool scan_first = nb > kDirect;
-    scratch.ensure(2 * (size_t)nb + (scan_first ? (size_t)nb + scan_scratch_need(nb) : 0));
-    int *sums = scratch.p, *offs = scan_first ? scratch.p + 2 * (size_t)nb : nullptr;
-    hipLaunchKernelGGL(k_filter_count, dim3(nb), dim3(kThreads), 0, s, n, boff, bent, pos, cnt, sums);
-    if (scan_first) scan_into(sums, offs, nb, nullptr, offs + nb, s);
-    const ListRowCounts rw = rows ? *rows : ListRowCounts{};
-    const int nbr = rw.m > 0 ? (rw.m + kThreads - 1) / kThreads : 0;
-    hipLaunchKernelGGL(k_filter_fill, dim3(std::max(nb, nbr)), dim3(kThreads), 0, s, n, nb, boff, bent, pos, cnt, sums,
-                       offs, off, ent, pairs_out, rw);
+    hipLaunchKernelGGL(k_filter_gapped, dim3(filter_blocks(n)), dim3(kThreads), 0, s, n, boff, bent, pos, cnt, ent,
+                       bsums);
 }
 
 }  // namespace relcp

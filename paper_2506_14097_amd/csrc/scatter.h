@@ -43,7 +43,7 @@ struct VLocal {
 template <typename T, int MODE, class VS>
 __device__ inline void scatter_body(const RowsT<T> &R, const BodiesT<T> &B, int i, T al, const VS &V) {
     T f0 = 0, f1 = 0, f2 = 0, t0 = 0, t1 = 0, t2 = 0;
-    const int e0 = B.off[i], e1 = B.off[i + 1];
+    const int e0 = B.off[i], e1 = B.lcnt ? e0 + B.lcnt[i] : B.off[i + 1];
     const int L = R.ld;
     constexpr int U = 4;
     for (int e = e0; e < e1; e += U) {
