@@ -152,9 +152,16 @@ __global__ void __launch_bounds__(kThreads) k_select_rows(RowBuildArgs A, int np
     const int p = b * kThreads + threadIdx.x;
     const int lane = threadIdx.x & (RELCP_WAVE - 1), w = threadIdx.x / RELCP_WAVE;
     const int f = p < np && flags[p] ? 1 : 0;
-    // set flags of the groups before this one
+    // set flags of the groups before this one (four loads per thread in
+    // flight per round)
     int acc = 0;
-    for (int g = threadIdx.x; g < b; g += kThreads) acc += gcount[g];
+    for (int g0 = threadIdx.x; g0 < b; g0 += 4 * kThreads) {
+        int v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = g0 + u * kThreads < b ? gcount[g0 + u * kThreads] : 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += v[u];
+    }
     for (int o = RELCP_WAVE / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, RELCP_WAVE);
     if (lane == 0) sh[w] = acc;
     __syncthreads();
@@ -757,8 +764,8 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_counts(int m, const int *
 
 // Entries of the row graph, one thread per incidence entry in CSR order
 // (entry e of body c: row r, side): the thread forms its own column of D at
-// c, s (n_r, tau_r), shares it through LDS with the other entries of c in
-// its block, and writes row r's entries at c: for every other entry j of c,
+// c, s (n_r, tau_r), shares it and its entry through LDS with the other
+// entries of c in its block, and writes row r's entries at c: for every other entry j of c,
 // in incidence order, column r_j and value dt J_j . K_c J_e (so row r holds
 // its entries at body a, then those at body b).  The slots past a row's
 // entries are not written: the passes read a row's entries only (its count
@@ -781,6 +788,7 @@ __device__ inline void column_of(const RowGraphFill &A, int en, double J[6]) {
 
 __global__ void __launch_bounds__(kThreads) k_rowgraph_fill_entries(RowGraphFill A) {
     __shared__ double shJ[6][kThreads];
+    __shared__ int shE[kThreads];
     __shared__ int shs[kWaves];
     const int E0 = blockIdx.x * kThreads;
     const int e = E0 + threadIdx.x;
@@ -799,6 +807,7 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_fill_entries(RowGraphFill
     }
 #pragma unroll
     for (int t = 0; t < 6; ++t) shJ[t][threadIdx.x] = J[t];
+    shE[threadIdx.x] = en;
     if (A.lcnt && blockIdx.x == 0) {
         // the entry count: the list filter's block sums, added up here
         int acc = 0;
@@ -871,7 +880,7 @@ __global__ void __launch_bounds__(kThreads) k_rowgraph_fill_entries(RowGraphFill
         if (j >= E0 && j < E0 + kThreads) {
 #pragma unroll
             for (int t = 0; t < 6; ++t) Jj[t] = shJ[t][j - E0];
-            cj = A.ent[j] >> 1;
+            cj = shE[j - E0] >> 1;
         } else {
             const int ej = A.ent[j];
             column_of(A, ej, Jj);
