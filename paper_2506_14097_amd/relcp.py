@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+from collections.abc import Mapping
 
 import numpy as np
 
@@ -74,6 +75,38 @@ class StepStats(C.Structure):
                     t_other=self.t_other, rowgraph_entries=np.array(self.rowgraph_entries[:k]),
                     pairs_rebuilt=self.pairs_rebuilt, n_waits=self.n_waits, t_wait=self.t_wait,
                     rowgraph_restarts=self.rowgraph_restarts)
+
+
+class StepResult(Mapping):
+    """The statistics of one step, read-only: the keys of StepStats.as_dict()
+    and "status".  The C struct is converted on the first access to a key
+    other than "status", so that a caller that reads none of them (or reads
+    them later) spends no host time on it between steps."""
+    __slots__ = ("_st", "_rc", "_d")
+
+    def __init__(self, st, rc):
+        self._st, self._rc, self._d = st, rc, None
+
+    def _dict(self):
+        if self._d is None:
+            d = self._st.as_dict()
+            d["status"] = self._rc
+            self._d, self._st = d, None
+        return self._d
+
+    def __getitem__(self, key):
+        if key == "status":
+            return self._rc
+        return self._dict()[key]
+
+    def __iter__(self):
+        return iter(self._dict())
+
+    def __len__(self):
+        return len(self._dict())
+
+    def __repr__(self):
+        return repr(self._dict())
 
 
 _lib = None
@@ -210,11 +243,9 @@ class Simulation:
     def step(self, dt, overlap_tol, lcp_tol, raise_on_error=True):
         st = StepStats()
         rc = lib().relcp_step(self.ctx, dt, overlap_tol, lcp_tol, C.byref(st))
-        d = st.as_dict()
-        d["status"] = rc
         if rc != OK and raise_on_error:
             raise RelcpError(rc, self._err())
-        return d
+        return StepResult(st, rc)
 
     def get_state(self):
         n = self.n
