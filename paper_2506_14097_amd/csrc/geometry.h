@@ -77,7 +77,7 @@ int snsd_blocks(int m);
 int trial_blocks(int nb);
 // R, Bd (or null): the FP64 rows with their multipliers and the incidence
 // lists; then the contact velocities vc = K D max(0, gamma) are formed here
-// (and stored to Bd->vc, which must be vc) instead of read from vc.  vfree
+// (and stored to Bd->vc unless it is null) instead of read from vc.  vfree
 // null: U_free is zero (not read).
 void launch_trial(int nb, const double *x, int ldx, const double *q, int ldq, const double *vfree, const double *vc,
                   int ldv, double dt, const int *kind, const double *p, int ldp, const double *Rb, double *xt,

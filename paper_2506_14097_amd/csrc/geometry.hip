@@ -571,11 +571,12 @@ __global__ void k_trial(int nb, const double *__restrict__ x, int ldx, const dou
         double v[6];
         if (vc_rows) {
             // the body's contact velocity K D max(0, gamma) over its incident
-            // rows (the LCP's own scatter arithmetic), kept for later row builds
+            // rows (the LCP's own scatter arithmetic), also stored if Bd.vc
+            // is set
             double w[6];
             scatter_body<double, 0>(R, Bd, i, 0.0, VRegs<double>{w});
             for (int k = 0; k < 6; ++k) {
-                Bd.vc[k * Bd.ld + i] = w[k];
+                if (Bd.vc) Bd.vc[k * Bd.ld + i] = w[k];
                 v[k] = (vfree ? vfree[k * ldv + i] : 0.0) + w[k];
             }
         } else {

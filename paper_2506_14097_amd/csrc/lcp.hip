@@ -477,9 +477,10 @@ __device__ inline void load_partials(const PgdCtl &C, PartialRegs &pr) {
         pr.v[u] = *reinterpret_cast<const double4 *>(C.partials + 4 * k);
     }
 }
-__device__ inline void reduce_loaded(const PgdCtl &C, int par, const PartialRegs &pr, PgdState *out,
-                                     double (*sh)[kWaves]) {
-    double ss = 0.0, sy = 0.0, yy = 0.0, res = 0.0;
+// this thread's share of the loaded partial sums, in reduce_partials' order
+__device__ inline void loaded_sums(const PgdCtl &C, const PartialRegs &pr, double &ss, double &sy, double &yy,
+                                   double &res) {
+    ss = sy = yy = res = 0.0;
 #pragma unroll
     for (int u = 0; u < kPartRegs; ++u) {
         if ((int)threadIdx.x + u * kThreads < C.nbg) {
@@ -489,6 +490,11 @@ __device__ inline void reduce_loaded(const PgdCtl &C, int par, const PartialRegs
             res = fmax(res, pr.v[u].w);
         }
     }
+}
+__device__ inline void reduce_loaded(const PgdCtl &C, int par, const PartialRegs &pr, PgdState *out,
+                                     double (*sh)[kWaves]) {
+    double ss, sy, yy, res;
+    loaded_sums(C, pr, ss, sy, yy, res);
     block_reduce4<false>(ss, sy, yy, res, sh);
     if (threadIdx.x == 0) *out = pgd_next(C.S[par ^ 1], ss, sy, yy, res, C.tol, C.stall);
     __syncthreads();
@@ -1137,24 +1143,45 @@ __global__ void __launch_bounds__(kThreads)
 // (see launch_report_check).
 __global__ void __launch_bounds__(kThreads) k_report_check(TailReport R, PgdCtl C) {
     __shared__ double sh[4][kWaves];
-    __shared__ PgdState ns;
-    // the report's loads and the partial sums' go out together
+    // the report's loads, the partial sums' and the state before them go
+    // out together; the two reductions share one barrier (the partial sums'
+    // in the order reduce_loaded uses, so the state is the same bit for bit)
     TailRegs tr;
     tail_preload(R, tr);
     PartialRegs pr;
     load_partials(C, pr);
-    reduce_loaded(C, 1, pr, &ns, sh);
-    if (threadIdx.x == 0) {
-        C.S[1] = ns;
-        if (ns.conv) {
-            *C.fin = ns;
-            *C.done = 1;
-            if (C.fin_h) *C.fin_h = ns;
-            if (C.done_h) *C.done_h = 1;
-        }
-    }
-    __syncthreads();
-    tail_report(R, tr);
+    const PgdState prev = C.S[0];
+    double ss, sy, yy, res;
+    loaded_sums(C, pr, ss, sy, yy, res);
+    const int lane = threadIdx.x & (RELCP_WAVE - 1), w = threadIdx.x / RELCP_WAVE;
+    tail_report(
+        R, tr,
+        [&] {
+            wave_reduce4(ss, sy, yy, res);
+            if (lane == 0) {
+                sh[0][w] = ss;
+                sh[1][w] = sy;
+                sh[2][w] = yy;
+                sh[3][w] = res;
+            }
+        },
+        [&] {
+            double a = 0.0, b = 0.0, c = 0.0, mx = 0.0;
+            for (int k = 0; k < kWaves; ++k) {
+                a += sh[0][k];
+                b += sh[1][k];
+                c += sh[2][k];
+                mx = fmax(mx, sh[3][k]);
+            }
+            const PgdState ns = pgd_next(prev, a, b, c, mx, C.tol, C.stall);
+            C.S[1] = ns;
+            if (ns.conv) {
+                *C.fin = ns;
+                *C.done = 1;
+                if (C.fin_h) *C.fin_h = ns;
+                if (C.done_h) *C.done_h = 1;
+            }
+        });
 }
 
 // A pass whose parameters live in device memory (LcpDev), so that the

@@ -1611,9 +1611,12 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
             // (row-graph solves: the FP64 unpack has formed the work's partials)
             if (!rowgraph_mode()) launch_work(m, rgam64.p, rg64.p, rqv64.p, work_out.p, stream);
             timed(4, [&] {
-                // row-graph solves leave the contact velocities to the trial
+                // row-graph solves leave the contact velocities to the trial,
+                // which does not store them: only an augmentation needs them
+                // (formed then by the LCP's scatter from the same multipliers)
                 const RowsT<double> Rt = rows_of<double>();
-                const BodiesT<double> Bt = bodies_of<double>();
+                BodiesT<double> Bt = bodies_of<double>();
+                Bt.vc = nullptr;
                 const bool vrows = rowgraph_mode();
                 // (overdamped bodies without external forces: U_free = 0)
                 const double *vf = dynamics == RELCP_OVERDAMPED && !has_fext ? nullptr : vfree.p;
@@ -1784,6 +1787,9 @@ int relcp_ctx::step(double dt, double eps, double tol, relcp_step_stats *st) {
         {
             const int m_old = m;
             compact_flags(pflag.p, np, pcnt.p, sel.p, nullptr, scan_scratch, stream);  // the violators
+            // the contact velocities V_n - U_free of the trial (the trial's
+            // own arithmetic), which a row-graph trial did not store
+            if (rowgraph_mode()) launch_lcp_scatter<double>(0, rows_of<double>(), bodies_of<double>(), PgdCtl{}, 0, stream);
             build_rows(nv, rec + 1, snsdt.p, vc64.p, false, dt);
             rebuild_csr();
             if (resident_mode()) rows_by_packing_append(m_old, nv);

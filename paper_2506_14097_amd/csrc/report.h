@@ -58,7 +58,16 @@ __device__ inline void tail_load(const TailReport &R, int k0, TailRegs &v) {
 }
 __device__ inline void tail_preload(const TailReport &R, TailRegs &v) { tail_load(R, threadIdx.x, v); }
 
-__device__ inline void tail_report(const TailReport &R, const TailRegs &first) {
+// pre: run by every thread just before the barrier (a caller's own wave
+// results into LDS); post: run by thread 0 just after it, before the
+// report's writes (the caller's own block result), so that both share the
+// report's one barrier.
+struct NoHook {
+    __device__ void operator()() const {}
+};
+template <class Pre = NoHook, class Post = NoHook>
+__device__ inline void tail_report(const TailReport &R, const TailRegs &first, const Pre &pre = Pre{},
+                                   const Post &post = Post{}) {
     __shared__ unsigned long long s0[4], s1[4], s2[4];
     __shared__ double s3[4];
     unsigned long long d = 0ull, p = ~0ull, q = ~0ull;
@@ -95,8 +104,10 @@ __device__ inline void tail_report(const TailReport &R, const TailRegs &first) {
         s3[wv] = w;
         s4[wv] = c;
     }
+    pre();
     __syncthreads();
     if (threadIdx.x == 0) {
+        post();
         for (int k = 1; k < 4; ++k) {
             d = u64_max(d, s0[k]);
             p = u64_min(p, s1[k]);
