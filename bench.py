@@ -51,7 +51,7 @@ FP64_PEAK_TFLOPS = 78.6
 # a plain copy of known size reads), recorded in
 # profiles/lcp_rowgraph_pass_100k_hbm_traffic.md for the kernel source with
 # the given sha256 prefix (stale once it changes).
-MEASURED_TRAFFIC = {"sha256_prefix": "278c8a4945d78e3d", "lcp_rowgraph": 1.3842e7}
+MEASURED_TRAFFIC = {"sha256_prefix": "8f6f3f61ee651537", "lcp_rowgraph": 1.3852e7}
 
 
 # timing class -> kernel
@@ -64,7 +64,7 @@ KERNEL_SYMBOLS = {"lcp_rowgraph": "relcp::k_spmv<float, 1>", "lcp_rowgraph64": "
 # workload (rocprofv3 --pmc SQ_INSTS_VALU_ADD_F64, _MUL_F64, _FMA_F64,
 # _TRANS_F64: add + mul + 2 fma + trans, times 64 lanes, over the pairs of
 # the launch), for the kernel source with the given sha256 prefix.
-SNSD_FP64_OPS = {"sha256_prefix": "f1d7917c4ba4b0b2", "fp64_ops_per_pair": 1276.9,
+SNSD_FP64_OPS = {"sha256_prefix": "558655cd61167acf", "fp64_ops_per_pair": 1276.9,
                  "source": "profiles/snsd_pairs_100k_fp64_counters.md: issued FP64 operations (64 lanes per wave "
                            "instruction) per candidate pair, mean of the pass at C^k and the pass at the trial"}
 
