@@ -120,3 +120,26 @@ def test_binding_signatures_match_header():
         kinds = [] if [p.strip() for p in ps] == ["void"] else [_c_kind(p) for p in ps]
         assert [_ctypes_kind(a) for a in args] == kinds, name
         assert _ctypes_kind(res) == _c_kind(ret), name
+
+
+def test_step_result_reads_like_the_stats_dict():
+    """Simulation.step returns a read-only mapping over the C struct; it
+    converts the struct on first access and then holds exactly the keys and
+    values of StepStats.as_dict() plus "status" (no GPU: a filled struct)."""
+    st = R.StepStats()
+    st.recursions = 1
+    st.n_pairs = 7
+    st.n_contacts[0], st.n_contacts[1] = 5, 2
+    st.lcp_iters[0], st.lcp_iters[1] = 11, 3
+    st.residual_fp64 = 2.5e-7
+    res = R.StepResult(st, R.E_SKIN)
+    assert res["status"] == R.E_SKIN and res._d is None  # "status" alone converts nothing
+    ref = st.as_dict()
+    ref["status"] = R.E_SKIN
+    assert set(res) == set(ref) and len(res) == len(ref)
+    for k, v in ref.items():
+        assert np.array_equal(res[k], v), k
+    assert "lcp_iters" in res and res.get("nope") is None and dict(res).keys() == ref.keys()
+    assert list(res["n_contacts"]) == [5, 2] and res["n_pairs"] == 7
+    with pytest.raises(TypeError):
+        res["status"] = 0
